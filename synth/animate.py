@@ -1,0 +1,135 @@
+"""Seeded synthetic animations of a fixed-connectivity mesh, plus the other
+random inputs the compressor takes (anchor index sets, a Gaussian initial
+subspace).
+
+All draws come from ``numpy.random.default_rng(seed)`` in a fixed order, so the
+same seed gives the same frames on every machine.  Frames are returned as
+``[F][n][3]`` (frame-major, xyz interleaved), the layout the compressor reads.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def _unit(v):
+    return v / np.linalg.norm(v)
+
+
+def _random_axis(rng):
+    return _unit(rng.standard_normal(3))
+
+
+def _rodrigues(axis, angle):
+    """Rotation matrices for angle[...] about one unit axis: [..., 3, 3]."""
+    kx, ky, kz = axis
+    K = np.array([[0.0, -kz, ky], [kz, 0.0, -kx], [-ky, kx, 0.0]])
+    a = np.asarray(angle, dtype=np.float64)[..., None, None]
+    return np.eye(3) + np.sin(a) * K + (1.0 - np.cos(a)) * (K @ K)
+
+
+def bend_twist(rest, n_frames: int, seed: int, amplitude: float = 0.2,
+               period_range=(8.0, 32.0), noise_var: float = 1e-4,
+               dtype=np.float64):
+    """Three smooth sinusoidal deformation fields applied in order, then i.i.d.
+    Gaussian noise of variance `noise_var` on every coordinate.
+
+    Field f has a unit axis a_f, period P_f ~ U[period_range], phase
+    phi_f ~ U[0, 2pi) and strength s_f(t) = amplitude * sin(2 pi t / P_f + phi_f).
+    Fields 0 and 2 twist (rotate p about a_f by s_f(t) * (a_f . p));
+    field 1 bends (p += s_f(t) * (a_f . p)^2 * b_f, with b_f a unit vector
+    orthogonal to a_f).
+    """
+    rng = np.random.default_rng(seed)
+    fields = []
+    for f in range(3):
+        a = _random_axis(rng)
+        period = rng.uniform(*period_range)
+        phase = rng.uniform(0.0, 2.0 * np.pi)
+        bdir = None
+        if f == 1:
+            r = rng.standard_normal(3)
+            bdir = _unit(r - np.dot(r, a) * a)
+        fields.append((a, period, phase, bdir))
+    t = np.arange(n_frames, dtype=np.float64)
+    P = np.broadcast_to(rest, (n_frames,) + rest.shape).copy()
+    for f, (a, period, phase, bdir) in enumerate(fields):
+        s = amplitude * np.sin(2.0 * np.pi * t / period + phase)  # [F]
+        proj = P @ a  # [F][n]
+        if bdir is None:
+            ang = s[:, None] * proj  # [F][n]
+            # Rodrigues per point: p cos + (a x p) sin + a (a.p)(1 - cos)
+            c, sn = np.cos(ang)[..., None], np.sin(ang)[..., None]
+            cross = np.cross(np.broadcast_to(a, P.shape), P)
+            P = P * c + cross * sn + a * (proj[..., None] * (1.0 - c))
+        else:
+            P = P + (s[:, None] * proj * proj)[..., None] * bdir
+    noise = rng.standard_normal(P.shape) * np.sqrt(noise_var)
+    return (P + noise).astype(dtype)
+
+
+def rbf_skinning(rest, n_frames: int, n_bones: int, seed: int,
+                 max_angle_deg: float = 30.0, period_range=(16.0, 128.0),
+                 root_weight: float = 0.1, sigma_frac: float = 0.25,
+                 t0: int = 0, dtype=np.float32):
+    """Gaussian-RBF skinning with `n_bones` bones rotating sinusoidally.
+
+    Bone b: centre c_b = a random rest vertex, axis uniform on the sphere,
+    angle theta_b(t) = theta_max_b * sin(2 pi t / P_b + phi_b) with
+    theta_max_b ~ U(0, max_angle], P_b ~ U[period_range], phi_b ~ U[0, 2pi).
+    Weights w_b(p) = exp(-|p - c_b|^2 / (2 sigma^2)), sigma = sigma_frac times
+    the bounding-box diagonal, plus a static root weight, normalised per vertex.
+    p(t) = sum_b w_b (R_b(t)(p - c_b) + c_b) + w_root p, t = t0 + frame index.
+    """
+    rng = np.random.default_rng(seed)
+    n = rest.shape[0]
+    bones = []
+    for _ in range(n_bones):
+        centre = rest[rng.integers(0, n)].copy()
+        axis = _random_axis(rng)
+        theta_max = np.deg2rad(max_angle_deg) * (1.0 - rng.uniform(0.0, 1.0))
+        period = rng.uniform(*period_range)
+        phase = rng.uniform(0.0, 2.0 * np.pi)
+        bones.append((centre, axis, theta_max, period, phase))
+    diag = np.linalg.norm(rest.max(axis=0) - rest.min(axis=0))
+    sigma = sigma_frac * diag
+    W = np.empty((n, n_bones + 1))
+    for b, (c, *_rest) in enumerate(bones):
+        d2 = np.sum((rest - c) ** 2, axis=1)
+        W[:, b] = np.exp(-d2 / (2.0 * sigma * sigma))
+    W[:, n_bones] = root_weight
+    W /= W.sum(axis=1, keepdims=True)
+    out = np.empty((n_frames, n, 3), dtype=dtype)
+    t = t0 + np.arange(n_frames, dtype=np.float64)
+    rots = []
+    for (c, axis, theta_max, period, phase) in bones:
+        ang = theta_max * np.sin(2.0 * np.pi * t / period + phase)
+        rots.append(_rodrigues(axis, ang))  # [F][3][3]
+    for f in range(n_frames):
+        acc = W[:, n_bones:n_bones + 1] * rest
+        for b, (c, *_r) in enumerate(bones):
+            acc += W[:, b:b + 1] * ((rest - c) @ rots[b][f].T + c)
+        out[f] = acc
+    return out
+
+
+def choose_anchors(n: int, n_anchors: int, seed: int) -> np.ndarray:
+    """Seeded uniform sample of distinct vertex indices, sorted (int32)."""
+    if not 0 < n_anchors <= n:
+        raise ValueError("need 0 < n_anchors <= n")
+    rng = np.random.default_rng(seed)
+    return np.sort(rng.choice(n, n_anchors, replace=False)).astype(np.int32)
+
+
+def default_anchor_count(n: int) -> int:
+    """One per cent of the vertices, at least one."""
+    return max(1, int(round(0.01 * n)))
+
+
+def gaussian_subspace(T: int, k: int, seed: int) -> np.ndarray:
+    """A seeded Gaussian T x k block per coordinate: [3][T][k] float64.
+
+    Used as the starting block of orthogonal iterations when no previous
+    window and no exact start is wanted.
+    """
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((3, T, k))
