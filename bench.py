@@ -1,0 +1,171 @@
+"""Benchmark: vertex-frames per second of encode + decode on one MI355X.
+
+One step = the whole path over one synthetic sequence already resident in
+HBM: delta coordinates, autocorrelation, orthogonal iterations with the Ritz
+step, projection + quantisation, anchors (encode), then back-projection and the
+anchored least-squares solve by preconditioned conjugate gradients on the
+normal equations, and the transpose back to frames (decode).
+
+Workload: 128 x 128 torus (16,384 vertices), 256 frames in windows of 32,
+6-bone Gaussian-RBF skinning, k = 16, 12-bit codes, 64 anchors, float32 frames.
+
+Prints one JSON line (see the keys below).  `--gpus N` with N > 1 exits: this
+build measures one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, GB/s
+FP64_PEAK_TFLOPS = 78.6    # MI355X FP64 vector / matrix
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-kernel", default=None,
+                    help="kernel family timed with HIP events (default: the dominant one)")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures a single GPU; --gpus {args.gpus} is not supported "
+              "(multi-GPU sharding is a design note only)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2111_10105_amd import dmc
+    from synth import configs
+
+    w = configs.torus_fp32()
+    n, F, T = w.n, w.F, w.T
+    dev = torch.device("cuda:0")
+    frames = torch.from_numpy(w.frames).to(dev)
+    ctx = dmc.Context(0)
+    t0 = time.perf_counter()
+    mesh = dmc.Mesh(ctx, n, w.tris, w.anchors)
+    setup_s = time.perf_counter() - t0
+    finfo = mesh.factor_info()
+    p = dmc.make_params(w.k, coef_bits=w.bits, precision=dmc.FP32)
+    codes = torch.empty(dmc.sequence_code_bytes(n, F, T, mesh.nc, p), dtype=torch.uint8, device=dev)
+    out = torch.empty_like(frames)
+
+    def step(stats=False):
+        return dmc.compress_sequence(ctx, mesh, frames, T, p, codes=codes, out=out, stats=stats)
+
+    for _ in range(max(args.warmup, 1)):
+        step()
+    torch.cuda.synchronize()
+
+    # dominant kernel: timed live with HIP events over the timed region
+    prof_kernel = args.profile_kernel or "chol_bwd_gather"
+    dmc.profile_start(prof_kernel)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    launches, kernel_ms = dmc.profile_stop()
+
+    # encode-only and decode-only split (outside the timed region)
+    torch.cuda.synchronize()
+    te = time.perf_counter()
+    for _ in range(3):
+        dmc.compress_sequence(ctx, mesh, frames, T, p, codes=codes, decode=False, stats=False)
+    torch.cuda.synchronize()
+    enc_ms = (time.perf_counter() - te) / 3 * 1e3
+    td = time.perf_counter()
+    for _ in range(3):
+        dmc.decode_sequence(ctx, mesh, codes, F, T, p, out=out)
+    torch.cuda.synchronize()
+    dec_ms = (time.perf_counter() - td) / 3 * 1e3
+
+    _, _, stats, status = step(stats=True)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    vf = n * F
+    value = vf * args.steps / elapsed
+
+    # roofline of the profiled kernel: algorithmic bytes per launch / time
+    ncols = 3 * F
+    roof = None
+    if launches:
+        avg_s = kernel_ms / launches * 1e-3
+        if prof_kernel.startswith("chol_"):
+            # per launch: one level's share; averaged over the levels of a
+            # solve: every factor entry read once and the n x ncols float64
+            # vectors read/written once per sweep direction, spread over the
+            # launches of this family in one solve
+            fam_launches_per_solve = finfo["levels"]
+            solves = launches / fam_launches_per_solve
+            bytes_per_solve = finfo["stored"] * 8 + 2 * n * ncols * 8
+            achieved = bytes_per_solve * solves / (kernel_ms * 1e-3) / 1e9
+        else:
+            achieved = 2 * n * ncols * 8 / avg_s / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": prof_kernel, "launches": launches,
+                "avg_us": round(kernel_ms / launches * 1e3, 2)}
+
+    result = {
+        "metric": "vertex-frames/s encode+decode at fixed NMSE",
+        "value": round(value, 1),
+        "unit": "vertex-frames/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 frames, f64 solve",
+        "data": "synthetic",
+        "config": {"workload": w.name, "vertices": n, "frames": F, "window": T, "k": w.k,
+                   "bits": w.bits, "anchors": int(mesh.nc), "precond": "cholesky",
+                   "cg_tol": p.cg_tol},
+        "split_ms": {"encode": round(enc_ms, 3), "decode": round(dec_ms, 3)},
+        "cg_iters": stats[0]["cg_iters"],
+        "oi_sweeps": [s["oi_sweeps"] for s in stats],
+        "setup_s": round(setup_s, 3),
+        "factor": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in finfo.items()},
+        "status": status,
+        "roofline": roof,
+    }
+
+    import oracle as O
+    result["nmse_vs_input"] = O.nmse(got, w.frames)
+    if not args.no_cpu_baseline:
+        # the float64 oracle on the host cores, over the same whole sequence
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        tc = time.perf_counter()
+        _, ref = O.compress_sequence(n, w.tris, w.frames, w.anchors, T, w.k, w.bits,
+                                     fp32_data=True)
+        cpu_s = time.perf_counter() - tc
+        result["cpu_baseline"] = {"value": round(vf / cpu_s, 1), "unit": "vertex-frames/s",
+                                  "cores": threads, "kind": "oracle",
+                                  "sample": f"whole workload once ({n} vertices x {F} frames, "
+                                            f"{cpu_s:.1f} s)"}
+        result["nmse_vs_oracle"] = O.nmse(got, ref)
+        result["oracle_nmse_vs_input"] = O.nmse(ref, w.frames)
+        result["fixed_nmse_ok"] = bool(result["nmse_vs_oracle"] <= 1e-5 and
+                                       result["nmse_vs_input"] <= 1.01 * result["oracle_nmse_vs_input"])
+    print(json.dumps(result))
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,230 @@
+/*
+ * dmc.h -- C ABI of the MI355X (gfx950) spatio-temporal dynamic-mesh compressor.
+ *
+ * Method: Arvanitis, Lalos, Moustakas, "Fast Spatio-temporal Compression of
+ * Dynamic 3D Meshes" (arXiv 2111.10105).  Per window of T consecutive frames of
+ * a mesh with fixed connectivity (Sec. II, Sec. III-A) the encoder computes
+ *   delta coordinates     delta = L V for every frame          (Eq. 3-4, Eq. 8)
+ *   autocorrelation       R_c = A_c A_c^T, c in {x, y, z}       (Eq. 7)
+ *   eigen-trajectories    first k eigenvectors of R_c, by orthogonal
+ *                         iterations warm-started from the previous window
+ *                         (Algorithm 1) and a Rayleigh-Ritz step  (Eq. 5)
+ *   coefficients          Y_c = U_k^T delta_c^T                 (Eq. 9)
+ *   codes                 uniform quantisation of the k rows     (Eq. 10)
+ *   anchors               quantised coordinates of the vertices in N (Eq. 12)
+ * and the decoder solves the anchored least-squares system of Eq. (12) for all
+ * frames at once, by conjugate gradients on its normal equations
+ * (L^T L + I_N^T I_N) X = L^T (U Y) ^T + I_N^T A_N.
+ *
+ * Conventions (every entry point):
+ *  - Pointers named *_dev are device pointers (HIP); *_host are host pointers.
+ *    The caller owns every buffer it passes; the library never frees them.
+ *  - The context owns its kernels' scratch memory (allocated on first use,
+ *    grown when needed, kept until dmc_destroy) and the meshes made with it.
+ *  - All device work is ordered on the context's HIP stream.  Calls that fill
+ *    a stats struct synchronise that stream; others return after enqueueing.
+ *  - Errors are returned as dmc_status, never by aborting; dmc_last_error()
+ *    gives a message for the calling thread.  Arguments are validated on the
+ *    host before any launch; on error no output is written.
+ *  - Frames are float64 when params.precision == DMC_FP64, else float32, laid
+ *    out [frame][vertex][xyz] (row-major, xyz interleaved).
+ */
+#ifndef DMC_H
+#define DMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dmc_ctx_s* dmc_ctx;
+typedef struct dmc_mesh_s* dmc_mesh;
+
+typedef enum {
+  DMC_OK = 0,
+  DMC_ERR_INVALID_ARG = 1,
+  DMC_ERR_OUT_OF_MEMORY = 2,
+  DMC_ERR_DEVICE = 3,
+  DMC_ERR_NOT_CONVERGED = 4,
+  DMC_ERR_SINGULAR = 5,
+  DMC_ERR_BUFFER_TOO_SMALL = 6,
+  DMC_ERR_UNSUPPORTED = 7
+} dmc_status;
+
+/* arithmetic of the encoder's GEMMs (frames dtype follows: FP64 -> double,
+ * otherwise float) */
+enum { DMC_FP64 = 0, DMC_FP32 = 1 };
+
+/* Laplacian: Eq. (3) I - D^-1 C (default) or Eq. (1) D - C */
+enum { DMC_LAP_UNIFORM = 0, DMC_LAP_COMBINATORIAL = 1 };
+
+/* preconditioner of the decoder's conjugate gradients: none, the diagonal of
+ * the normal matrix, or its sparse Cholesky factor (computed once per mesh by
+ * dmc_mesh_create) */
+enum { DMC_PRECOND_NONE = 0, DMC_PRECOND_JACOBI = 1, DMC_PRECOND_CHOLESKY = 2 };
+
+typedef struct {
+  int32_t k;             /* kept rows k_l of Eq. (10), 1 <= k <= T            */
+  int32_t coef_bits;     /* bits of Q(.) in Eq. (10): 1..16, 0 = raw values    */
+  int32_t anchor_bits;   /* bits per anchor coordinate: 1..16, 0 = raw values  */
+  int32_t dict_bits;     /* bits per dictionary entry:  1..16, 0 = raw values  */
+  int32_t precision;     /* DMC_FP64 or DMC_FP32                               */
+  int32_t oi_max_sweeps; /* cap on orthogonal-iteration sweeps per window >= 1 */
+  double oi_tol;         /* stop when ||R Q - Q Q^T R Q||_F <= tol ||R||_F     */
+  int32_t cg_max_iters;  /* cap on conjugate-gradient iterations >= 1          */
+  int32_t precond;       /* DMC_PRECOND_*                                      */
+  double cg_tol;         /* stop a column when ||r|| <= tol ||b||              */
+} dmc_params;
+
+typedef struct {
+  int32_t T, k;             /* window length and kept rows                     */
+  int32_t oi_sweeps[3];     /* sweeps per coordinate (0 = exact start)         */
+  double oi_resid[3];       /* final ||RQ - QH||_F / ||R||_F per coordinate    */
+  int32_t chol_shifts[3];   /* CholeskyQR breakdowns repaired by a shift       */
+  int32_t cg_iters;         /* decoder iterations (0 if not decoded)           */
+  double cg_resid;          /* max over columns of ||r|| / ||b||               */
+} dmc_window_stats;
+
+/* ---- context -------------------------------------------------------------
+ * dmc_create: bind to HIP device `device`; `hip_stream` is a hipStream_t (NULL
+ * = the legacy default stream).  DMC_ERR_DEVICE if the device is not a
+ * gfx950 GPU or cannot be used. */
+dmc_status dmc_create(int32_t device, void* hip_stream, dmc_ctx* out);
+void dmc_destroy(dmc_ctx ctx);
+dmc_status dmc_set_stream(dmc_ctx ctx, void* hip_stream);
+const char* dmc_last_error(void);
+/* bytes of scratch the context holds now */
+size_t dmc_scratch_bytes(dmc_ctx ctx);
+
+/* ---- mesh (Sec. II) ------------------------------------------------------
+ * Builds, once per mesh, the binary adjacency C of Eq. (2) (edges of the
+ * triangles, duplicates merged), the degrees d_i, the Laplacian chosen by
+ * `laplacian`, and the normal matrix L^T L + I_N^T I_N of Eq. (12), and copies
+ * them to the device.  tris_host: int32 [n_tris][3]; anchors_host: int32
+ * [n_anchors], distinct vertex indices (the set N of Eq. 12; anchor values are
+ * stored in this order).  Errors: DMC_ERR_INVALID_ARG for an index out of
+ * range, a repeated anchor, or a vertex with no neighbour (Eq. 3 undefined);
+ * DMC_ERR_SINGULAR when a connected component holds no anchor. */
+dmc_status dmc_mesh_create(dmc_ctx ctx, int32_t n_verts, int32_t n_tris,
+                           const int32_t* tris_host, int32_t n_anchors,
+                           const int32_t* anchors_host, int32_t laplacian,
+                           dmc_mesh* out);
+void dmc_mesh_destroy(dmc_mesh mesh);
+int32_t dmc_mesh_nnz(dmc_mesh mesh);          /* nonzeros of C (= 2 |E|)       */
+int32_t dmc_mesh_normal_nnz(dmc_mesh mesh);   /* nonzeros of L^T L + I_N^T I_N */
+/* sizes of the normal matrix's Cholesky factor: [0] stored entries,
+ * [1] nonzeros of the exact factor, [2] supernodes, [3] tree levels,
+ * [4] factorisation flops, [5] host seconds to build it */
+void dmc_mesh_factor_info(dmc_mesh mesh, double info[6]);
+
+/* Host-only check of the ordering and factorisation (no device needed):
+ * builds L^T L + I_N^T I_N and its supernodal Cholesky factor exactly as
+ * dmc_mesh_create does, then solves (L^T L + I_N^T I_N) X = B on the host with
+ * the same blocked algorithm the device uses.  B and X are float64
+ * [n][ncols] row-major host arrays (may alias).  Same errors as
+ * dmc_mesh_create. */
+dmc_status dmc_host_normal_solve(int32_t n_verts, int32_t n_tris, const int32_t* tris_host,
+                                 int32_t n_anchors, const int32_t* anchors_host,
+                                 int32_t laplacian, int32_t ncols, const double* B_host,
+                                 double* X_host, double info[6]);
+
+/* ---- encoded window record -----------------------------------------------
+ * One window's record is a byte buffer (device memory), 256-byte aligned
+ * sections:
+ *   header      64 B  (magic "DMC1", T, k, n, n_c, coef/anchor/dict bits,
+ *                      precision)
+ *   dictionary  [3][T][k]  uint16 codes over [-1, 1], or raw values
+ *   row ranges  [3][k][2]  float32 (lo, hi) per kept row       (coef_bits > 0)
+ *   codes       [3][k][n]  uint16 codes of Eq. (10), or raw values
+ *   anchor rng  [3][2]     float32 (lo, hi) per coordinate     (anchor_bits > 0)
+ *   anchors     [3][T][n_c] uint16 codes, or raw values
+ * Raw values are float64 (DMC_FP64) or float32.  A record is self-contained
+ * given the mesh (connectivity and N are side information shared with the
+ * decoder, as in Sec. III). */
+size_t dmc_window_code_bytes(int32_t n, int32_t T, int32_t n_anchors,
+                             const dmc_params* params);
+/* sum of dmc_window_code_bytes over the windows of an F-frame sequence */
+size_t dmc_sequence_code_bytes(int32_t n, int32_t F, int32_t T, int32_t n_anchors,
+                               const dmc_params* params);
+
+/* ---- encode one window (Eq. 3-10, Eq. 12 anchors; Algorithm 1) -----------
+ * frames_dev  [T][n][3] frames of the window.
+ * q_start_dev [3][T][k] start block of orthogonal iterations per coordinate
+ *             (normally the previous window's u_out; Algorithm 1, line 3), or
+ *             NULL for the exact eigenvectors of R_c (Algorithm 1, line 1).
+ * code_dev    record buffer of dmc_window_code_bytes bytes.
+ * u_out_dev   optional [3][T][k]: the window's eigen-trajectories U_k (before
+ *             dictionary quantisation), columns ordered by eigenvalue,
+ *             largest first, sign fixed so each column's largest-magnitude
+ *             entry is positive.
+ * coef_out_dev optional [3][k][n]: the coefficients Y of Eq. (9) before
+ *             quantisation (computed with the dequantised dictionary).
+ * stats       optional; filling it synchronises the stream.
+ * DMC_ERR_NOT_CONVERGED if some coordinate hit oi_max_sweeps (outputs are
+ * still written). */
+dmc_status dmc_encode_window(dmc_ctx ctx, dmc_mesh mesh, const void* frames_dev,
+                             int32_t T, const dmc_params* params,
+                             const void* q_start_dev, void* code_dev,
+                             void* u_out_dev, void* coef_out_dev,
+                             dmc_window_stats* stats);
+
+/* ---- decode one window (Eq. 12) ------------------------------------------
+ * code_dev: a record written by dmc_encode_window for this mesh and T;
+ * frames_out_dev [T][n][3].  DMC_ERR_NOT_CONVERGED if some column did not
+ * reach cg_tol within cg_max_iters (the last iterate is still written). */
+dmc_status dmc_decode_window(dmc_ctx ctx, dmc_mesh mesh, const void* code_dev,
+                             int32_t T, const dmc_params* params,
+                             void* frames_out_dev, dmc_window_stats* stats);
+
+/* ---- whole sequence (Sec. III-A, "blocks") -------------------------------
+ * Splits F frames into windows of T (the last may be shorter), encodes them in
+ * order, each window starting its orthogonal iterations from the previous
+ * window's U_k (window 0 from q_start_dev [3][T][k], or exact if NULL; a
+ * shorter last window from its own exact eigenvectors), writing the records
+ * back to back into codes_dev (dmc_sequence_code_bytes bytes).  If
+ * frames_out_dev [F][n][3] is not NULL, then decodes every window in one
+ * solve over all 3F columns.  per_window: optional array of n_windows stats
+ * (synchronises). */
+dmc_status dmc_compress_sequence(dmc_ctx ctx, dmc_mesh mesh, const void* frames_dev,
+                                 int32_t F, int32_t T, const dmc_params* params,
+                                 const void* q_start_dev, void* codes_dev,
+                                 size_t codes_bytes, void* frames_out_dev,
+                                 dmc_window_stats* per_window);
+
+/* decode every record of a sequence written by dmc_compress_sequence */
+dmc_status dmc_decode_sequence(dmc_ctx ctx, dmc_mesh mesh, const void* codes_dev,
+                               int32_t F, int32_t T, const dmc_params* params,
+                               void* frames_out_dev, dmc_window_stats* per_window);
+
+/* ---- single steps of the path, for verification --------------------------
+ * dmc_delta: delta = L V for each of F frames (Eq. 3-4): [F][n][3] ->
+ *   [F][n][3] in the frames' dtype.
+ * dmc_autocorrelation: R_c = A_c A_c^T (Eq. 7) of one T-frame window:
+ *   frames [T][n][3] -> R_out_dev float64 [3][T][T]. */
+dmc_status dmc_delta(dmc_ctx ctx, dmc_mesh mesh, const void* frames_dev, int32_t F,
+                     int32_t precision, void* delta_out_dev);
+dmc_status dmc_autocorrelation(dmc_ctx ctx, dmc_mesh mesh, const void* frames_dev,
+                               int32_t T, int32_t precision, void* R_out_dev);
+
+/* ---- kernel timing (measurement support) ----------------------------------
+ * dmc_profile_start selects one kernel family; from then on every launch of
+ * it is bracketed by HIP events recorded on the stream it runs on.
+ * dmc_profile_stop waits for those events and returns the number of launches
+ * and their summed duration in milliseconds, then deselects.  Process-wide
+ * state: use from one thread. */
+enum {
+  DMC_KERNEL_DELTA = 0, DMC_KERNEL_AUTOCORR, DMC_KERNEL_OI, DMC_KERNEL_PROJECT,
+  DMC_KERNEL_QUANTISE, DMC_KERNEL_ANCHORS, DMC_KERNEL_BACK_PROJECT, DMC_KERNEL_RHS,
+  DMC_KERNEL_CG_SPMM, DMC_KERNEL_CG_UPDATE, DMC_KERNEL_CHOL_FWD_GATHER,
+  DMC_KERNEL_CHOL_FWD_SOLVE, DMC_KERNEL_CHOL_BWD_GATHER, DMC_KERNEL_CHOL_BWD_SOLVE,
+  DMC_KERNEL_TO_FRAMES, DMC_KERNEL_COUNT
+};
+dmc_status dmc_profile_start(int32_t kernel);
+dmc_status dmc_profile_stop(int32_t* launches, double* ms_total);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DMC_H */

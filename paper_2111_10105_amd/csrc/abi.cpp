@@ -1,0 +1,749 @@
+// C ABI entry points: argument validation, context/mesh lifetime, scratch
+// management and the order of launches for encode and decode.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "chol_host.h"
+#include "dmc_internal.h"
+#include "mesh_host.h"
+
+struct dmc_ctx_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  void* scratch = nullptr;
+  size_t scratch_bytes = 0;
+  void* pinned = nullptr;  // host staging for stats and convergence flags
+  size_t pinned_bytes = 0;
+  void* stats = nullptr;   // per-window device stats (kept apart from scratch)
+  size_t stats_bytes = 0;
+  std::vector<dmc_mesh_s*> meshes;
+};
+
+struct dmc_mesh_s {
+  dmc_ctx ctx = nullptr;
+  dmc::MeshDev dev;
+  std::vector<void*> allocations;
+  std::vector<int32_t> level_w, level_m;  // host copies of the factor's level -> task ranges
+  double factor_info[6] = {0, 0, 0, 0, 0, 0};
+};
+
+namespace {
+
+thread_local std::string g_error;
+
+dmc_status fail(dmc_status st, const std::string& msg) {
+  g_error = msg;
+  return st;
+}
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t _e = (expr);                                                             \
+    if (_e != hipSuccess)                                                               \
+      return fail(DMC_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(_e));  \
+  } while (0)
+
+dmc_status check_launch(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(DMC_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+  return DMC_OK;
+}
+
+// Scratch carving: a bump allocator over the context's scratch buffer.
+struct Carve {
+  std::vector<size_t> sizes;
+  size_t add(size_t bytes) {
+    sizes.push_back(dmc::align_up(std::max<size_t>(bytes, 1)));
+    size_t off = 0;
+    for (size_t i = 0; i + 1 < sizes.size(); ++i) off += sizes[i];
+    return off;
+  }
+  size_t total() const {
+    size_t t = 0;
+    for (size_t s : sizes) t += s;
+    return t;
+  }
+};
+
+dmc_status ensure_scratch(dmc_ctx ctx, size_t bytes) {
+  if (bytes <= ctx->scratch_bytes) return DMC_OK;
+  if (ctx->scratch) {
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    HIP_TRY(hipFree(ctx->scratch));
+    ctx->scratch = nullptr;
+    ctx->scratch_bytes = 0;
+  }
+  const size_t want = dmc::align_up(bytes, size_t(1) << 20);
+  if (hipMalloc(&ctx->scratch, want) != hipSuccess) {
+    ctx->scratch = nullptr;
+    (void)hipGetLastError();
+    return fail(DMC_ERR_OUT_OF_MEMORY, "cannot allocate " + std::to_string(want) + " scratch bytes");
+  }
+  ctx->scratch_bytes = want;
+  return DMC_OK;
+}
+
+dmc_status ensure_stats(dmc_ctx ctx, size_t bytes) {
+  if (bytes <= ctx->stats_bytes) return DMC_OK;
+  if (ctx->stats) {
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    HIP_TRY(hipFree(ctx->stats));
+  }
+  ctx->stats = nullptr;
+  ctx->stats_bytes = 0;
+  const size_t want = std::max<size_t>(bytes, 4096);
+  if (hipMalloc(&ctx->stats, want) != hipSuccess) {
+    ctx->stats = nullptr;
+    (void)hipGetLastError();
+    return fail(DMC_ERR_OUT_OF_MEMORY, "cannot allocate stats buffer");
+  }
+  ctx->stats_bytes = want;
+  return DMC_OK;
+}
+
+dmc_status ensure_pinned(dmc_ctx ctx, size_t bytes) {
+  if (bytes <= ctx->pinned_bytes) return DMC_OK;
+  if (ctx->pinned) HIP_TRY(hipHostFree(ctx->pinned));
+  ctx->pinned = nullptr;
+  ctx->pinned_bytes = 0;
+  const size_t want = std::max<size_t>(bytes, 1 << 16);
+  HIP_TRY(hipHostMalloc(&ctx->pinned, want, hipHostMallocDefault));
+  ctx->pinned_bytes = want;
+  return DMC_OK;
+}
+
+dmc_status check_params(const dmc_params* p, int32_t T, bool for_decode = false) {
+  if (!p) return fail(DMC_ERR_INVALID_ARG, "params is NULL");
+  if (T < 1 || T > 64) return fail(DMC_ERR_INVALID_ARG, "window length T must be in 1..64");
+  if (p->k < 1 || p->k > 32) return fail(DMC_ERR_INVALID_ARG, "k must be in 1..32");
+  if (p->precision != DMC_FP64 && p->precision != DMC_FP32)
+    return fail(DMC_ERR_INVALID_ARG, "precision must be DMC_FP64 or DMC_FP32");
+  for (int32_t b : {p->coef_bits, p->anchor_bits, p->dict_bits})
+    if (b < 0 || b > 16) return fail(DMC_ERR_INVALID_ARG, "bits must be in 0..16");
+  if (!for_decode) {
+    if (p->oi_max_sweeps < 1) return fail(DMC_ERR_INVALID_ARG, "oi_max_sweeps must be >= 1");
+    if (!(p->oi_tol >= 0.0)) return fail(DMC_ERR_INVALID_ARG, "oi_tol must be >= 0");
+  }
+  if (p->cg_max_iters < 1) return fail(DMC_ERR_INVALID_ARG, "cg_max_iters must be >= 1");
+  if (!(p->cg_tol >= 0.0)) return fail(DMC_ERR_INVALID_ARG, "cg_tol must be >= 0");
+  if (p->precond < DMC_PRECOND_NONE || p->precond > DMC_PRECOND_CHOLESKY)
+    return fail(DMC_ERR_INVALID_ARG, "unknown preconditioner");
+  return DMC_OK;
+}
+
+size_t real_size(int32_t precision) { return precision == DMC_FP64 ? 8 : 4; }
+
+void fill_stats(dmc_window_stats* st, const dmc::StatsDev& s, int32_t T, int32_t k) {
+  st->T = T;
+  st->k = k;
+  for (int c = 0; c < 3; ++c) {
+    st->oi_sweeps[c] = s.sweeps[c];
+    st->oi_resid[c] = s.resid[c];
+    st->chol_shifts[c] = s.shifts[c];
+  }
+}
+
+// Encode nw windows of length T starting at frames (one chain).
+dmc_status encode_chain(dmc_ctx ctx, const dmc::MeshDev& m, const void* frames, int32_t T,
+                        int32_t nw, int32_t k, const dmc_params& p, const void* q_start,
+                        uint8_t* records, const dmc::RecordLayout& lay, void* u_out,
+                        void* coef_out, const void* delta, uint8_t* ws,
+                        dmc::StatsDev* stats_dev) {
+  hipStream_t s = ctx->stream;
+  // scratch pieces (carved by the caller in this order)
+  uint8_t* cur = ws;
+  double* R = (double*)cur;
+  cur += dmc::align_up((size_t)nw * 3 * T * T * 8);
+  void* part = cur;
+  cur += dmc::align_up(dmc::autocorr_scratch_bytes(m.n, T, nw, p.precision));
+  double* u_tilde = (double*)cur;
+  cur += dmc::align_up((size_t)nw * 3 * T * k * 8);
+  void* proj = cur;
+  for (int32_t w = 0; w < nw; ++w) dmc::launch_write_header(s, records + (size_t)w * lay.bytes, lay);
+  dmc::launch_autocorr(s, frames, m.n, T, nw, p.precision, part, R);
+  dmc::OiArgs oa;
+  oa.R = R;
+  oa.nw = nw;
+  oa.T = T;
+  oa.k = k;
+  oa.precision = p.precision;
+  oa.dict_bits = p.dict_bits;
+  oa.q_start = q_start;
+  oa.u_out = u_out;
+  oa.u_tilde = u_tilde;
+  oa.records = records;
+  oa.rec_bytes = lay.bytes;
+  oa.off_dict = lay.off_dict;
+  oa.max_sweeps = p.oi_max_sweeps;
+  oa.tol = p.oi_tol;
+  oa.stats = stats_dev;
+  dmc::launch_oi(s, oa);
+  dmc::launch_project_quantise(s, delta, m.n, T, k, nw, p.precision, p.coef_bits, u_tilde, records,
+                               lay.bytes, lay, proj, coef_out);
+  dmc::launch_anchors(s, m, frames, T, nw, p.precision, p.anchor_bits, records, lay.bytes, lay);
+  return check_launch("encode kernels");
+}
+
+size_t chain_scratch_bytes(int32_t n, int32_t T, int32_t nw, int32_t k, int32_t precision) {
+  return dmc::align_up((size_t)nw * 3 * T * T * 8) +
+         dmc::align_up(dmc::autocorr_scratch_bytes(n, T, nw, precision)) +
+         dmc::align_up((size_t)nw * 3 * T * k * 8) +
+         dmc::align_up(dmc::project_scratch_bytes(n, T, k, nw, precision));
+}
+
+// Decode every window of a sequence in one solve over 3F columns.
+dmc_status decode_all(dmc_ctx ctx, const dmc::MeshDev& m, const uint8_t* records,
+                      const dmc::SeqLayout& sl, const dmc_params& p, void* frames_out,
+                      int32_t* iters_out, double* resid_out) {
+  hipStream_t s = ctx->stream;
+  const int32_t F = sl.nw_full * sl.T + sl.T_tail;
+  const int32_t ncols = 3 * F;
+  const size_t vec = (size_t)m.n * ncols * 8;
+  const size_t nrb = dmc::cg_part_rows(m.n);
+  Carve cv;
+  const size_t o_x = cv.add(vec);
+  const size_t o_r = cv.add(vec + (size_t)m.nc * ncols * 8);  // b, then r; anchor values after
+  const size_t o_p = cv.add(vec);
+  const size_t o_q = cv.add(vec);                             // back-projection, then q
+  const size_t o_part = cv.add(2 * nrb * ncols * 8);
+  const size_t o_small = cv.add((size_t)ncols * 8 * 6 + (size_t)ncols * 4);
+  const bool chol = p.precond == DMC_PRECOND_CHOLESKY;
+  const size_t o_z = chol ? cv.add(vec) : 0;
+  const size_t o_W = chol ? cv.add(vec) : 0;
+  const size_t o_Y = chol ? cv.add(vec) : 0;
+  const size_t o_X = chol ? cv.add(vec) : 0;
+  const size_t o_U = chol ? cv.add((size_t)m.chol.nslots * ncols * 8) : 0;
+  dmc_status st = ensure_scratch(ctx, cv.total());
+  if (st != DMC_OK) return st;
+  st = ensure_pinned(ctx, (size_t)ncols * 12 + 4096);
+  if (st != DMC_OK) return st;
+  uint8_t* ws = (uint8_t*)ctx->scratch;
+  dmc::CgBuffers cb;
+  cb.x = (double*)(ws + o_x);
+  cb.r = (double*)(ws + o_r);
+  cb.p = (double*)(ws + o_p);
+  cb.q = (double*)(ws + o_q);
+  cb.part = (double*)(ws + o_part);
+  cb.z = chol ? (double*)(ws + o_z) : nullptr;
+  cb.W = chol ? (double*)(ws + o_W) : nullptr;
+  cb.Y = chol ? (double*)(ws + o_Y) : nullptr;
+  cb.X = chol ? (double*)(ws + o_X) : nullptr;
+  cb.U = chol ? (double*)(ws + o_U) : nullptr;
+  double* small = (double*)(ws + o_small);
+  cb.rz = small;
+  cb.rr = small + ncols;
+  cb.bnorm2 = small + 2 * ncols;
+  cb.alpha = small + 3 * ncols;
+  cb.beta = small + 4 * ncols;
+  cb.resid = small + 5 * ncols;
+  cb.done = (int32_t*)(small + 6 * ncols);
+
+  dmc::launch_back_project(s, m, records, sl, nullptr, cb.q);
+  dmc::launch_rhs(s, m, records, sl, cb.q, cb.r);
+  dmc::launch_cg_init(s, m, ncols, cb.r, cb, p.precond);
+  st = check_launch("decode setup kernels");
+  if (st != DMC_OK) return st;
+  int32_t* h_done = (int32_t*)ctx->pinned;
+  double* h_res = (double*)((uint8_t*)ctx->pinned + dmc::align_up((size_t)ncols * 4));
+  const int check_every = chol ? 1 : 16;
+  int it = 0;
+  bool all_done = false;
+  while (it < p.cg_max_iters) {
+    dmc::launch_cg_step_a(s, m, ncols, cb, p.precond, p.cg_tol);
+    ++it;
+    if (it % check_every == 0 || it == p.cg_max_iters) {
+      st = check_launch("cg kernels");
+      if (st != DMC_OK) return st;
+      HIP_TRY(hipMemcpyAsync(h_done, cb.done, (size_t)ncols * 4, hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      all_done = true;
+      for (int j = 0; j < ncols; ++j) all_done = all_done && h_done[j];
+      if (all_done || it == p.cg_max_iters) break;
+    }
+    dmc::launch_cg_step_b(s, m, ncols, cb, p.precond);
+  }
+  dmc::launch_to_frames(s, cb.x, m.n, F, p.precision, frames_out);
+  st = check_launch("to_frames");
+  if (st != DMC_OK) return st;
+  HIP_TRY(hipMemcpyAsync(h_res, cb.resid, (size_t)ncols * 8, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  double rmax = 0.0;
+  for (int j = 0; j < ncols; ++j) rmax = std::max(rmax, h_res[j]);
+  if (iters_out) *iters_out = it;
+  if (resid_out) *resid_out = rmax;
+  if (!all_done)
+    return fail(DMC_ERR_NOT_CONVERGED, "conjugate gradients stopped at cg_max_iters with max "
+                                       "relative residual " + std::to_string(rmax));
+  return DMC_OK;
+}
+
+// Everything dmc_mesh_create computes on the host: adjacency (Eq. 2),
+// validation, the normal matrix of Eq. (12) and its Cholesky factor.
+constexpr int32_t kNdLeaf = 32;
+
+dmc_status build_mesh_host(int32_t n, int32_t n_tris, const int32_t* tris, int32_t n_anchors,
+                           const int32_t* anchors, int32_t laplacian, dmc::HostCsr& C,
+                           dmc::HostCsr& M, dmc::CholFactor& F, double info[6]) {
+  if (n < 1 || n_tris < 1 || !tris) return fail(DMC_ERR_INVALID_ARG, "need n >= 1 and triangles");
+  if (laplacian != DMC_LAP_UNIFORM && laplacian != DMC_LAP_COMBINATORIAL)
+    return fail(DMC_ERR_INVALID_ARG, "unknown Laplacian");
+  if (n_anchors < 0 || (n_anchors > 0 && !anchors))
+    return fail(DMC_ERR_INVALID_ARG, "bad anchor array");
+  std::vector<char> seen(n, 0);
+  for (int32_t a = 0; a < n_anchors; ++a) {
+    if (anchors[a] < 0 || anchors[a] >= n)
+      return fail(DMC_ERR_INVALID_ARG, "anchor index out of range");
+    if (seen[anchors[a]]) return fail(DMC_ERR_INVALID_ARG, "repeated anchor index");
+    seen[anchors[a]] = 1;
+  }
+  std::string msg;
+  if (!dmc::build_adjacency(n, n_tris, tris, C, msg)) return fail(DMC_ERR_INVALID_ARG, msg);
+  for (int32_t i = 0; i < n; ++i)
+    if (C.rowptr[i + 1] == C.rowptr[i])
+      return fail(DMC_ERR_INVALID_ARG, "vertex " + std::to_string(i) +
+                                           " has no neighbour (Eq. 3 undefined)");
+  const int32_t missing = dmc::unanchored_components(C, anchors, n_anchors);
+  if (missing > 0)
+    return fail(DMC_ERR_SINGULAR, std::to_string(missing) +
+                                      " connected component(s) without an anchor: the "
+                                      "anchored system is singular");
+  dmc::build_normal_matrix(C, laplacian, anchors, n_anchors, M);
+  const auto t0 = std::chrono::steady_clock::now();
+  if (!dmc::build_cholesky(M, kNdLeaf, F, msg)) return fail(DMC_ERR_SINGULAR, msg);
+  const double secs =
+      std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  info[0] = (double)F.val.size();
+  info[1] = (double)F.nnz_exact;
+  info[2] = F.nsuper;
+  info[3] = F.nlevels;
+  info[4] = F.flops;
+  info[5] = secs;
+  return DMC_OK;
+}
+
+}  // namespace
+
+namespace dmc {
+
+RecordLayout record_layout(int32_t n, int32_t T, int32_t k, int32_t nc, const dmc_params& p) {
+  RecordLayout l;
+  l.T = T;
+  l.k = k;
+  l.n = n;
+  l.nc = nc;
+  l.coef_bits = p.coef_bits;
+  l.anchor_bits = p.anchor_bits;
+  l.dict_bits = p.dict_bits;
+  l.precision = p.precision;
+  l.real = real_size(p.precision);
+  size_t off = align_up(64);
+  l.off_dict = off;
+  off += align_up((size_t)3 * T * k * (p.dict_bits > 0 ? 2 : l.real));
+  l.off_ranges = off;
+  off += align_up((size_t)3 * k * 2 * 4);
+  l.off_codes = off;
+  off += align_up((size_t)3 * k * n * (p.coef_bits > 0 ? 2 : l.real));
+  l.off_arange = off;
+  off += align_up((size_t)3 * 2 * 4);
+  l.off_anchors = off;
+  off += align_up((size_t)3 * T * nc * (p.anchor_bits > 0 ? 2 : l.real));
+  l.bytes = off;
+  return l;
+}
+
+}  // namespace dmc
+
+extern "C" {
+
+const char* dmc_last_error(void) { return g_error.c_str(); }
+
+dmc_status dmc_create(int32_t device, void* hip_stream, dmc_ctx* out) {
+  if (!out) return fail(DMC_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count == 0)
+    return fail(DMC_ERR_DEVICE, "no HIP device");
+  if (device < 0 || device >= count) return fail(DMC_ERR_INVALID_ARG, "device index out of range");
+  HIP_TRY(hipSetDevice(device));
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, device));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(DMC_ERR_DEVICE, std::string("built for gfx950, device is ") + prop.gcnArchName);
+  dmc_ctx c = new dmc_ctx_s();
+  c->device = device;
+  c->stream = (hipStream_t)hip_stream;
+  *out = c;
+  return DMC_OK;
+}
+
+void dmc_destroy(dmc_ctx ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  for (dmc_mesh_s* m : ctx->meshes) {
+    for (void* p : m->allocations) (void)hipFree(p);
+    delete m;
+  }
+  if (ctx->scratch) (void)hipFree(ctx->scratch);
+  if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  if (ctx->stats) (void)hipFree(ctx->stats);
+  delete ctx;
+}
+
+dmc_status dmc_set_stream(dmc_ctx ctx, void* hip_stream) {
+  if (!ctx) return fail(DMC_ERR_INVALID_ARG, "ctx is NULL");
+  ctx->stream = (hipStream_t)hip_stream;
+  return DMC_OK;
+}
+
+size_t dmc_scratch_bytes(dmc_ctx ctx) { return ctx ? ctx->scratch_bytes : 0; }
+
+dmc_status dmc_mesh_create(dmc_ctx ctx, int32_t n, int32_t n_tris, const int32_t* tris,
+                           int32_t n_anchors, const int32_t* anchors, int32_t laplacian,
+                           dmc_mesh* out) {
+  if (!ctx || !out) return fail(DMC_ERR_INVALID_ARG, "ctx or out is NULL");
+  *out = nullptr;
+  dmc::HostCsr C, M;
+  dmc::CholFactor F;
+  double info[6];
+  dmc_status st = build_mesh_host(n, n_tris, tris, n_anchors, anchors, laplacian, C, M, F, info);
+  if (st != DMC_OK) return st;
+  std::vector<double> w64(n), dinv(n, 0.0);
+  std::vector<float> w32(n);
+  std::vector<int32_t> slot(n, -1);
+  for (int32_t i = 0; i < n; ++i) {
+    const double d = C.rowptr[i + 1] - C.rowptr[i];
+    w64[i] = laplacian == DMC_LAP_UNIFORM ? 1.0 / d : d;
+    w32[i] = (float)w64[i];
+    for (int32_t e = M.rowptr[i]; e < M.rowptr[i + 1]; ++e)
+      if (M.col[e] == i) dinv[i] = 1.0 / M.val[e];
+  }
+  for (int32_t a = 0; a < n_anchors; ++a) slot[anchors[a]] = a;
+  // factor work items: (supernode, first row of a 64-row tile), by level, over
+  // the supernode's w columns and over its m rows
+  std::vector<int32_t> tw_sn, tw_r0, tm_sn, tm_r0, level_w(F.nlevels + 1, 0),
+      level_m(F.nlevels + 1, 0);
+  for (int32_t lv = 0; lv < F.nlevels; ++lv) {
+    for (int32_t sn = 0; sn < F.nsuper; ++sn) {
+      if (F.sn_level[sn] != lv) continue;
+      const int32_t w = F.sn_start[sn + 1] - F.sn_start[sn];
+      const int32_t mm = F.sn_rowptr[sn + 1] - F.sn_rowptr[sn];
+      for (int32_t r0 = 0; r0 < w; r0 += 64) {
+        tw_sn.push_back(sn);
+        tw_r0.push_back(r0);
+      }
+      for (int32_t r0 = 0; r0 < mm; r0 += 64) {
+        tm_sn.push_back(sn);
+        tm_r0.push_back(r0);
+      }
+    }
+    level_w[lv + 1] = (int32_t)tw_sn.size();
+    level_m[lv + 1] = (int32_t)tm_sn.size();
+  }
+
+  HIP_TRY(hipSetDevice(ctx->device));
+  dmc_mesh m = new dmc_mesh_s();
+  m->ctx = ctx;
+  bool ok = true;
+  auto up = [&](const void* src, size_t bytes) -> void* {
+    void* d = nullptr;
+    if (hipMalloc(&d, std::max<size_t>(bytes, 8)) != hipSuccess) {
+      ok = false;
+      return nullptr;
+    }
+    m->allocations.push_back(d);
+    if (bytes && hipMemcpy(d, src, bytes, hipMemcpyHostToDevice) != hipSuccess) ok = false;
+    return d;
+  };
+  dmc::MeshDev& dv = m->dev;
+  dv.n = n;
+  dv.nnz = (int32_t)C.col.size();
+  dv.nc = n_anchors;
+  dv.laplacian = laplacian;
+  dv.m_nnz = (int32_t)M.col.size();
+  dv.rowptr = (const int32_t*)up(C.rowptr.data(), C.rowptr.size() * 4);
+  dv.col = (const int32_t*)up(C.col.data(), C.col.size() * 4);
+  dv.w64 = (const double*)up(w64.data(), n * 8);
+  dv.w32 = (const float*)up(w32.data(), n * 4);
+  dv.anchors = (const int32_t*)up(anchors, (size_t)n_anchors * 4);
+  dv.slot = (const int32_t*)up(slot.data(), n * 4);
+  dv.m_rowptr = (const int32_t*)up(M.rowptr.data(), M.rowptr.size() * 4);
+  dv.m_col = (const int32_t*)up(M.col.data(), M.col.size() * 4);
+  dv.m_val = (const double*)up(M.val.data(), M.val.size() * 8);
+  dv.m_dinv = (const double*)up(dinv.data(), n * 8);
+  dmc::CholDev& cd = dv.chol;
+  cd.n = n;
+  cd.ns = F.nsuper;
+  cd.nlevels = F.nlevels;
+  cd.nslots = F.slot_base[F.nsuper];
+  cd.perm = (const int32_t*)up(F.perm.data(), F.perm.size() * 4);
+  cd.sn_start = (const int32_t*)up(F.sn_start.data(), F.sn_start.size() * 4);
+  cd.sn_rowptr = (const int32_t*)up(F.sn_rowptr.data(), F.sn_rowptr.size() * 4);
+  cd.rowidx = (const int32_t*)up(F.rowidx.data(), F.rowidx.size() * 4);
+  cd.sn_valptr = (const int64_t*)up(F.sn_valptr.data(), F.sn_valptr.size() * 8);
+  cd.bcol = (const double*)up(F.bcol.data(), F.bcol.size() * 8);
+  cd.brow = (const double*)up(F.brow.data(), F.brow.size() * 8);
+  cd.slot_base = (const int64_t*)up(F.slot_base.data(), F.slot_base.size() * 8);
+  cd.contrib_ptr = (const int32_t*)up(F.contrib_ptr.data(), F.contrib_ptr.size() * 4);
+  cd.contrib_slot = (const int32_t*)up(F.contrib_slot.data(), F.contrib_slot.size() * 4);
+  cd.task_w_sn = (const int32_t*)up(tw_sn.data(), tw_sn.size() * 4);
+  cd.task_w_r0 = (const int32_t*)up(tw_r0.data(), tw_r0.size() * 4);
+  cd.task_m_sn = (const int32_t*)up(tm_sn.data(), tm_sn.size() * 4);
+  cd.task_m_r0 = (const int32_t*)up(tm_r0.data(), tm_r0.size() * 4);
+  m->level_w = level_w;
+  m->level_m = level_m;
+  cd.level_w_host = m->level_w.data();
+  cd.level_m_host = m->level_m.data();
+  std::memcpy(m->factor_info, info, sizeof(info));
+  if (!ok) {
+    for (void* p : m->allocations) (void)hipFree(p);
+    delete m;
+    (void)hipGetLastError();
+    return fail(DMC_ERR_OUT_OF_MEMORY, "cannot upload mesh");
+  }
+  ctx->meshes.push_back(m);
+  *out = m;
+  return DMC_OK;
+}
+
+void dmc_mesh_factor_info(dmc_mesh mesh, double info[6]) {
+  if (!mesh || !info) return;
+  std::memcpy(info, mesh->factor_info, sizeof(mesh->factor_info));
+}
+
+dmc_status dmc_host_normal_solve(int32_t n, int32_t n_tris, const int32_t* tris, int32_t n_anchors,
+                                 const int32_t* anchors, int32_t laplacian, int32_t ncols,
+                                 const double* B, double* X, double info[6]) {
+  if (ncols < 1 || !B || !X) return fail(DMC_ERR_INVALID_ARG, "bad right-hand side");
+  dmc::HostCsr C, M;
+  dmc::CholFactor F;
+  double inf[6];
+  dmc_status st = build_mesh_host(n, n_tris, tris, n_anchors, anchors, laplacian, C, M, F, inf);
+  if (st != DMC_OK) return st;
+  dmc::chol_solve_host(F, ncols, B, X);
+  if (info) std::memcpy(info, inf, sizeof(inf));
+  return DMC_OK;
+}
+
+void dmc_mesh_destroy(dmc_mesh mesh) {
+  if (!mesh) return;
+  dmc_ctx ctx = mesh->ctx;
+  (void)hipStreamSynchronize(ctx->stream);
+  for (void* p : mesh->allocations) (void)hipFree(p);
+  ctx->meshes.erase(std::remove(ctx->meshes.begin(), ctx->meshes.end(), mesh), ctx->meshes.end());
+  delete mesh;
+}
+
+int32_t dmc_mesh_nnz(dmc_mesh mesh) { return mesh ? mesh->dev.nnz : 0; }
+int32_t dmc_mesh_normal_nnz(dmc_mesh mesh) { return mesh ? mesh->dev.m_nnz : 0; }
+
+size_t dmc_window_code_bytes(int32_t n, int32_t T, int32_t n_anchors, const dmc_params* p) {
+  if (!p || n < 1 || T < 1 || n_anchors < 0) return 0;
+  return dmc::record_layout(n, T, std::min(p->k, T), n_anchors, *p).bytes;
+}
+
+size_t dmc_sequence_code_bytes(int32_t n, int32_t F, int32_t T, int32_t n_anchors,
+                               const dmc_params* p) {
+  if (!p || F < 1 || T < 1) return 0;
+  const int32_t nw = F / T, tail = F % T;
+  size_t b = (size_t)nw * dmc_window_code_bytes(n, T, n_anchors, p);
+  if (tail) b += dmc_window_code_bytes(n, tail, n_anchors, p);
+  return b;
+}
+
+dmc_status dmc_encode_window(dmc_ctx ctx, dmc_mesh mesh, const void* frames, int32_t T,
+                             const dmc_params* params, const void* q_start, void* code,
+                             void* u_out, void* coef_out, dmc_window_stats* stats) {
+  if (!ctx || !mesh || !frames || !code) return fail(DMC_ERR_INVALID_ARG, "NULL argument");
+  dmc_status st = check_params(params, T);
+  if (st != DMC_OK) return st;
+  const dmc_params& p = *params;
+  if (p.k > T) return fail(DMC_ERR_INVALID_ARG, "k must not exceed T");
+  const dmc::MeshDev& m = mesh->dev;
+  HIP_TRY(hipSetDevice(ctx->device));
+  const dmc::RecordLayout lay = dmc::record_layout(m.n, T, p.k, m.nc, p);
+  Carve cv;
+  const size_t o_delta = cv.add((size_t)T * 3 * m.n * real_size(p.precision));
+  const size_t o_chain = cv.add(chain_scratch_bytes(m.n, T, 1, p.k, p.precision));
+  st = ensure_scratch(ctx, cv.total());
+  if (st != DMC_OK) return st;
+  st = ensure_stats(ctx, sizeof(dmc::StatsDev));
+  if (st != DMC_OK) return st;
+  uint8_t* ws = (uint8_t*)ctx->scratch;
+  void* delta = ws + o_delta;
+  dmc::StatsDev* sd = (dmc::StatsDev*)ctx->stats;
+  dmc::launch_delta(ctx->stream, m, frames, delta, T, p.precision);
+  st = encode_chain(ctx, m, frames, T, 1, p.k, p, q_start, (uint8_t*)code, lay, u_out, coef_out,
+                    delta, ws + o_chain, sd);
+  if (st != DMC_OK) return st;
+  if (stats) {
+    st = ensure_pinned(ctx, sizeof(dmc::StatsDev));
+    if (st != DMC_OK) return st;
+    HIP_TRY(hipMemcpyAsync(ctx->pinned, sd, sizeof(dmc::StatsDev), hipMemcpyDeviceToHost,
+                           ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    std::memset(stats, 0, sizeof(*stats));
+    fill_stats(stats, *(dmc::StatsDev*)ctx->pinned, T, p.k);
+    for (int c = 0; c < 3; ++c)
+      if (q_start && stats->oi_sweeps[c] >= p.oi_max_sweeps && stats->oi_resid[c] > p.oi_tol)
+        return fail(DMC_ERR_NOT_CONVERGED, "orthogonal iterations hit oi_max_sweeps");
+  }
+  return DMC_OK;
+}
+
+static dmc::SeqLayout seq_layout(int32_t n, int32_t F, int32_t T, int32_t nc, const dmc_params& p) {
+  dmc::SeqLayout sl;
+  sl.T = T;
+  sl.nw_full = F / T;
+  sl.T_tail = F % T;
+  sl.full = dmc::record_layout(n, T, std::min(p.k, T), nc, p);
+  sl.tail = dmc::record_layout(n, std::max(sl.T_tail, 1), std::min(p.k, std::max(sl.T_tail, 1)),
+                               nc, p);
+  sl.rec_bytes_full = sl.full.bytes;
+  return sl;
+}
+
+dmc_status dmc_decode_window(dmc_ctx ctx, dmc_mesh mesh, const void* code, int32_t T,
+                             const dmc_params* params, void* frames_out, dmc_window_stats* stats) {
+  if (!ctx || !mesh || !code || !frames_out) return fail(DMC_ERR_INVALID_ARG, "NULL argument");
+  dmc_status st = check_params(params, T, true);
+  if (st != DMC_OK) return st;
+  HIP_TRY(hipSetDevice(ctx->device));
+  const dmc::SeqLayout sl = seq_layout(mesh->dev.n, T, T, mesh->dev.nc, *params);
+  int32_t iters = 0;
+  double res = 0.0;
+  st = decode_all(ctx, mesh->dev, (const uint8_t*)code, sl, *params, frames_out, &iters, &res);
+  if (stats) {
+    stats->T = T;
+    stats->k = std::min(params->k, T);
+    stats->cg_iters = iters;
+    stats->cg_resid = res;
+  }
+  return st;
+}
+
+dmc_status dmc_decode_sequence(dmc_ctx ctx, dmc_mesh mesh, const void* codes, int32_t F,
+                               int32_t T, const dmc_params* params, void* frames_out,
+                               dmc_window_stats* per_window) {
+  if (!ctx || !mesh || !codes || !frames_out) return fail(DMC_ERR_INVALID_ARG, "NULL argument");
+  if (F < 1) return fail(DMC_ERR_INVALID_ARG, "F must be >= 1");
+  dmc_status st = check_params(params, T, true);
+  if (st != DMC_OK) return st;
+  HIP_TRY(hipSetDevice(ctx->device));
+  const dmc::SeqLayout sl = seq_layout(mesh->dev.n, F, T, mesh->dev.nc, *params);
+  int32_t iters = 0;
+  double res = 0.0;
+  st = decode_all(ctx, mesh->dev, (const uint8_t*)codes, sl, *params, frames_out, &iters, &res);
+  if (per_window) {
+    const int nw = sl.nw_full + (sl.T_tail ? 1 : 0);
+    for (int w = 0; w < nw; ++w) {
+      per_window[w].cg_iters = iters;
+      per_window[w].cg_resid = res;
+    }
+  }
+  return st;
+}
+
+dmc_status dmc_compress_sequence(dmc_ctx ctx, dmc_mesh mesh, const void* frames, int32_t F,
+                                 int32_t T, const dmc_params* params, const void* q_start,
+                                 void* codes, size_t codes_bytes, void* frames_out,
+                                 dmc_window_stats* per_window) {
+  if (!ctx || !mesh || !frames || !codes) return fail(DMC_ERR_INVALID_ARG, "NULL argument");
+  if (F < 1) return fail(DMC_ERR_INVALID_ARG, "F must be >= 1");
+  dmc_status st = check_params(params, T);
+  if (st != DMC_OK) return st;
+  const dmc_params& p = *params;
+  const dmc::MeshDev& m = mesh->dev;
+  const dmc::SeqLayout sl = seq_layout(m.n, F, T, m.nc, p);
+  const size_t need = dmc_sequence_code_bytes(m.n, F, T, m.nc, &p);
+  if (codes_bytes < need)
+    return fail(DMC_ERR_BUFFER_TOO_SMALL, "codes buffer needs " + std::to_string(need) + " bytes");
+  HIP_TRY(hipSetDevice(ctx->device));
+  const int32_t nw = sl.nw_full + (sl.T_tail ? 1 : 0);
+  const int32_t k_full = std::min(p.k, T);
+  Carve cv;
+  const size_t o_delta = cv.add((size_t)F * 3 * m.n * real_size(p.precision));
+  const size_t o_full = cv.add(sl.nw_full ? chain_scratch_bytes(m.n, T, sl.nw_full, k_full,
+                                                                 p.precision)
+                                          : 0);
+  const size_t o_tail = cv.add(sl.T_tail ? chain_scratch_bytes(m.n, sl.T_tail, 1, sl.tail.k,
+                                                                 p.precision)
+                                         : 0);
+  st = ensure_scratch(ctx, cv.total());
+  if (st != DMC_OK) return st;
+  st = ensure_stats(ctx, sizeof(dmc::StatsDev) * nw);
+  if (st != DMC_OK) return st;
+  uint8_t* ws = (uint8_t*)ctx->scratch;
+  void* delta = ws + o_delta;
+  dmc::StatsDev* sd = (dmc::StatsDev*)ctx->stats;
+  dmc::launch_delta(ctx->stream, m, frames, delta, F, p.precision);
+  const size_t rs = real_size(p.precision);
+  if (sl.nw_full) {
+    st = encode_chain(ctx, m, frames, T, sl.nw_full, k_full, p, q_start, (uint8_t*)codes, sl.full,
+                      nullptr, nullptr, delta, ws + o_full, sd);
+    if (st != DMC_OK) return st;
+  }
+  if (sl.T_tail) {
+    const size_t f0 = (size_t)sl.nw_full * T;
+    st = encode_chain(ctx, m, (const uint8_t*)frames + f0 * 3 * m.n * rs, sl.T_tail, 1, sl.tail.k,
+                      p, nullptr, (uint8_t*)codes + (size_t)sl.nw_full * sl.full.bytes, sl.tail,
+                      nullptr, nullptr, (const uint8_t*)delta + f0 * 3 * m.n * rs, ws + o_tail,
+                      sd + sl.nw_full);
+    if (st != DMC_OK) return st;
+  }
+  int32_t iters = 0;
+  double res = 0.0;
+  dmc_status dst = DMC_OK;
+  if (frames_out) {
+    dst = decode_all(ctx, m, (const uint8_t*)codes, sl, p, frames_out, &iters, &res);
+    if (dst != DMC_OK && dst != DMC_ERR_NOT_CONVERGED) return dst;
+  }
+  if (per_window) {
+    st = ensure_pinned(ctx, sizeof(dmc::StatsDev) * nw);
+    if (st != DMC_OK) return st;
+    HIP_TRY(hipMemcpyAsync(ctx->pinned, sd, sizeof(dmc::StatsDev) * nw, hipMemcpyDeviceToHost,
+                           ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    const dmc::StatsDev* hs = (const dmc::StatsDev*)ctx->pinned;
+    for (int w = 0; w < nw; ++w) {
+      std::memset(&per_window[w], 0, sizeof(dmc_window_stats));
+      const bool tail = w >= sl.nw_full;
+      fill_stats(&per_window[w], hs[w], tail ? sl.T_tail : T, tail ? sl.tail.k : k_full);
+      per_window[w].cg_iters = iters;
+      per_window[w].cg_resid = res;
+    }
+  }
+  return dst;
+}
+
+dmc_status dmc_delta(dmc_ctx ctx, dmc_mesh mesh, const void* frames, int32_t F, int32_t precision,
+                     void* out) {
+  if (!ctx || !mesh || !frames || !out) return fail(DMC_ERR_INVALID_ARG, "NULL argument");
+  if (F < 1) return fail(DMC_ERR_INVALID_ARG, "F must be >= 1");
+  if (precision != DMC_FP64 && precision != DMC_FP32)
+    return fail(DMC_ERR_INVALID_ARG, "bad precision");
+  HIP_TRY(hipSetDevice(ctx->device));
+  dmc::launch_delta(ctx->stream, mesh->dev, frames, out, F, precision);
+  return check_launch("delta");
+}
+
+dmc_status dmc_autocorrelation(dmc_ctx ctx, dmc_mesh mesh, const void* frames, int32_t T,
+                               int32_t precision, void* R_out) {
+  if (!ctx || !mesh || !frames || !R_out) return fail(DMC_ERR_INVALID_ARG, "NULL argument");
+  if (T < 1 || T > 64) return fail(DMC_ERR_INVALID_ARG, "T must be in 1..64");
+  if (precision != DMC_FP64 && precision != DMC_FP32)
+    return fail(DMC_ERR_INVALID_ARG, "bad precision");
+  HIP_TRY(hipSetDevice(ctx->device));
+  dmc_status st = ensure_scratch(ctx, dmc::autocorr_scratch_bytes(mesh->dev.n, T, 1, precision));
+  if (st != DMC_OK) return st;
+  dmc::launch_autocorr(ctx->stream, frames, mesh->dev.n, T, 1, precision, ctx->scratch,
+                       (double*)R_out);
+  return check_launch("autocorrelation");
+}
+
+}  // extern "C"

@@ -1,0 +1,492 @@
+// Host-side sparse Cholesky of the normal matrix of the anchored system
+// (Eq. 12): nested-dissection ordering, symbolic analysis, level-parallel
+// numeric factorisation, explicit inverses of the diagonal blocks.
+#include "chol_host.h"
+
+#include <omp.h>
+
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+namespace dmc {
+namespace {
+
+struct NdNode {
+  int32_t begin = -1, end = -1, parent = -1;
+};
+
+// Recursive bisection of the graph of M by breadth-first level sets: the
+// level that splits the vertices in half (counted from a pseudo-peripheral
+// vertex) is the separator; it is numbered after both halves.
+class Dissector {
+ public:
+  Dissector(const HostCsr& G, int32_t leaf)
+      : G_(G), leaf_(std::max(leaf, 2)), tag_(G.n, 0), seen_(G.n, 0), lev_(G.n, 0) {}
+
+  void run(std::vector<int32_t>& order, std::vector<NdNode>& nodes) {
+    std::vector<int32_t> all(G_.n);
+    std::iota(all.begin(), all.end(), 0);
+    order_.reserve(G_.n);
+    rec(all, -1);
+    order.swap(order_);
+    nodes.swap(nodes_);
+  }
+
+ private:
+  void bfs(int32_t s, int32_t member, std::vector<int32_t>& vis) {
+    const int32_t id = ++bfs_id_;
+    vis.clear();
+    vis.push_back(s);
+    seen_[s] = id;
+    lev_[s] = 0;
+    for (size_t h = 0; h < vis.size(); ++h) {
+      const int32_t u = vis[h];
+      for (int32_t e = G_.rowptr[u]; e < G_.rowptr[u + 1]; ++e) {
+        const int32_t v = G_.col[e];
+        if (v == u || tag_[v] != member || seen_[v] == id) continue;
+        seen_[v] = id;
+        lev_[v] = lev_[u] + 1;
+        vis.push_back(v);
+      }
+    }
+  }
+
+  void make_leaf(const std::vector<int32_t>& S, int32_t parent) {
+    NdNode nd;
+    nd.begin = (int32_t)order_.size();
+    order_.insert(order_.end(), S.begin(), S.end());
+    nd.end = (int32_t)order_.size();
+    nd.parent = parent;
+    nodes_.push_back(nd);
+  }
+
+  void rec(std::vector<int32_t>& S, int32_t parent) {
+    if ((int32_t)S.size() <= leaf_) {
+      make_leaf(S, parent);
+      return;
+    }
+    const int32_t member = ++stamp_;
+    for (int32_t v : S) tag_[v] = member;
+    std::vector<int32_t> vis;
+    bfs(S[0], member, vis);
+    if (vis.size() < S.size()) {  // not connected: recurse per component
+      const int32_t id = bfs_id_;
+      std::vector<int32_t> rest;
+      rest.reserve(S.size() - vis.size());
+      for (int32_t v : S)
+        if (seen_[v] != id) rest.push_back(v);
+      std::vector<int32_t> comp(vis);
+      S.clear();
+      S.shrink_to_fit();
+      rec(comp, parent);
+      rec(rest, parent);
+      return;
+    }
+    int32_t u = vis.back();
+    for (int it = 0; it < 2; ++it) {
+      bfs(u, member, vis);
+      if (vis.back() == u) break;
+      u = vis.back();
+    }
+    bfs(u, member, vis);
+    const int32_t maxl = lev_[vis.back()];
+    if (maxl < 2) {
+      make_leaf(S, parent);
+      return;
+    }
+    std::vector<int32_t> cnt(maxl + 1, 0);
+    for (int32_t v : vis) cnt[lev_[v]]++;
+    const int32_t half = (int32_t)S.size() / 2;
+    int32_t l = 0, acc = 0;
+    for (l = 0; l <= maxl; ++l) {
+      acc += cnt[l];
+      if (acc >= half) break;
+    }
+    l = std::min(std::max(l, 1), maxl - 1);
+    std::vector<int32_t> A, B, Sep;
+    for (int32_t v : vis) {
+      if (lev_[v] < l)
+        A.push_back(v);
+      else if (lev_[v] > l)
+        B.push_back(v);
+      else
+        Sep.push_back(v);
+    }
+    S.clear();
+    S.shrink_to_fit();
+    const int32_t me = (int32_t)nodes_.size();
+    nodes_.push_back(NdNode{-1, -1, parent});
+    rec(A, me);
+    rec(B, me);
+    nodes_[me].begin = (int32_t)order_.size();
+    order_.insert(order_.end(), Sep.begin(), Sep.end());
+    nodes_[me].end = (int32_t)order_.size();
+  }
+
+  const HostCsr& G_;
+  int32_t leaf_;
+  std::vector<int32_t> tag_, seen_, lev_;
+  int32_t stamp_ = 0, bfs_id_ = 0;
+  std::vector<int32_t> order_;
+  std::vector<NdNode> nodes_;
+};
+
+struct Segment {
+  int32_t d, p1, p2;  // rows [p1, p2) of supernode d fall in the target's columns
+};
+
+}  // namespace
+
+bool build_cholesky(const HostCsr& M, int32_t leaf, CholFactor& f, std::string& msg) {
+  const int32_t n = M.n;
+  f = CholFactor();
+  f.n = n;
+  std::vector<NdNode> nodes;
+  {
+    Dissector dis(M, leaf);
+    dis.run(f.perm, nodes);
+  }
+  std::vector<int32_t> iperm(n);
+  for (int32_t p = 0; p < n; ++p) iperm[f.perm[p]] = p;
+  std::sort(nodes.begin(), nodes.end(),
+            [](const NdNode& x, const NdNode& y) { return x.begin < y.begin; });
+
+  // lower triangle of P M P^T: by column (rows >= j, with values) and by row
+  std::vector<int32_t> acol_ptr(n + 1, 0), arow_ptr(n + 1, 0);
+  for (int32_t u = 0; u < n; ++u)
+    for (int32_t e = M.rowptr[u]; e < M.rowptr[u + 1]; ++e) {
+      const int32_t i = iperm[u], j = iperm[M.col[e]];
+      if (i >= j) {
+        acol_ptr[j + 1]++;
+        arow_ptr[i + 1]++;
+      }
+    }
+  for (int32_t j = 0; j < n; ++j) {
+    acol_ptr[j + 1] += acol_ptr[j];
+    arow_ptr[j + 1] += arow_ptr[j];
+  }
+  std::vector<int32_t> acol_row(acol_ptr[n]), arow_col(arow_ptr[n]);
+  std::vector<double> acol_val(acol_ptr[n]);
+  {
+    std::vector<int32_t> cf(acol_ptr.begin(), acol_ptr.end() - 1), rf(arow_ptr.begin(), arow_ptr.end() - 1);
+    for (int32_t u = 0; u < n; ++u)
+      for (int32_t e = M.rowptr[u]; e < M.rowptr[u + 1]; ++e) {
+        const int32_t i = iperm[u], j = iperm[M.col[e]];
+        if (i >= j) {
+          acol_row[cf[j]] = i;
+          acol_val[cf[j]++] = M.val[e];
+          arow_col[rf[i]++] = j;
+        }
+      }
+  }
+  // elimination tree (Liu, with path compression)
+  std::vector<int32_t> parent(n, -1), anc(n, -1);
+  for (int32_t i = 0; i < n; ++i)
+    for (int32_t e = arow_ptr[i]; e < arow_ptr[i + 1]; ++e) {
+      int32_t r = arow_col[e];
+      if (r >= i) continue;
+      while (anc[r] != -1 && anc[r] != i) {
+        const int32_t nx = anc[r];
+        anc[r] = i;
+        r = nx;
+      }
+      if (anc[r] == -1) {
+        anc[r] = i;
+        parent[r] = i;
+      }
+    }
+  // column structures of L below the diagonal, by row subtrees
+  std::vector<int32_t> lptr(n + 1, 0), mark(n, -1);
+  for (int32_t i = 0; i < n; ++i) {
+    mark[i] = i;
+    for (int32_t e = arow_ptr[i]; e < arow_ptr[i + 1]; ++e)
+      for (int32_t r = arow_col[e]; mark[r] != i; r = parent[r]) {
+        lptr[r + 1]++;
+        mark[r] = i;
+      }
+  }
+  for (int32_t j = 0; j < n; ++j) lptr[j + 1] += lptr[j];
+  std::vector<int32_t> lrow(lptr[n]);
+  {
+    std::vector<int32_t> fill(lptr.begin(), lptr.end() - 1);
+    std::fill(mark.begin(), mark.end(), -1);
+    for (int32_t i = 0; i < n; ++i) {
+      mark[i] = i;
+      for (int32_t e = arow_ptr[i]; e < arow_ptr[i + 1]; ++e)
+        for (int32_t r = arow_col[e]; mark[r] != i; r = parent[r]) {
+          lrow[fill[r]++] = i;
+          mark[r] = i;
+        }
+    }
+  }
+  f.nnz_exact = (int64_t)n + lptr[n];
+
+  // supernodes = dissection nodes; their row structures
+  const int32_t ns = (int32_t)nodes.size();
+  f.nsuper = ns;
+  f.sn_start.resize(ns + 1);
+  for (int32_t s = 0; s < ns; ++s) f.sn_start[s] = nodes[s].begin;
+  f.sn_start[ns] = n;
+  std::vector<int32_t> sn_of(n);
+  for (int32_t s = 0; s < ns; ++s)
+    for (int32_t j = f.sn_start[s]; j < f.sn_start[s + 1]; ++j) sn_of[j] = s;
+  f.sn_rowptr.assign(ns + 1, 0);
+  std::fill(mark.begin(), mark.end(), -1);
+  std::vector<int32_t> extra;
+  for (int32_t s = 0; s < ns; ++s) {
+    const int32_t a = f.sn_start[s], b = f.sn_start[s + 1];
+    extra.clear();
+    for (int32_t j = a; j < b; ++j)
+      for (int32_t e = lptr[j]; e < lptr[j + 1]; ++e) {
+        const int32_t r = lrow[e];
+        if (r >= b && mark[r] != s) {
+          mark[r] = s;
+          extra.push_back(r);
+        }
+      }
+    std::sort(extra.begin(), extra.end());
+    for (int32_t j = a; j < b; ++j) f.rowidx.push_back(j);
+    f.rowidx.insert(f.rowidx.end(), extra.begin(), extra.end());
+    f.sn_rowptr[s + 1] = (int32_t)f.rowidx.size();
+  }
+  lrow.clear();
+  lrow.shrink_to_fit();
+  // supernodal tree and levels
+  f.sn_parent.assign(ns, -1);
+  f.sn_level.assign(ns, 0);
+  for (int32_t s = 0; s < ns; ++s) {
+    const int32_t w = f.sn_start[s + 1] - f.sn_start[s];
+    const int32_t m = f.sn_rowptr[s + 1] - f.sn_rowptr[s];
+    if (m > w) f.sn_parent[s] = sn_of[f.rowidx[f.sn_rowptr[s] + w]];
+  }
+  for (int32_t s = 0; s < ns; ++s)
+    if (f.sn_parent[s] >= 0)
+      f.sn_level[f.sn_parent[s]] = std::max(f.sn_level[f.sn_parent[s]], f.sn_level[s] + 1);
+  f.nlevels = 0;
+  for (int32_t s = 0; s < ns; ++s) f.nlevels = std::max(f.nlevels, f.sn_level[s] + 1);
+
+  // contributions by row, and update segments by target supernode
+  f.contrib_ptr.assign(n + 1, 0);
+  std::vector<std::vector<Segment>> updates(ns);
+  for (int32_t s = 0; s < ns; ++s) {
+    const int32_t w = f.sn_start[s + 1] - f.sn_start[s];
+    const int32_t r0 = f.sn_rowptr[s], r1 = f.sn_rowptr[s + 1];
+    for (int32_t i = r0 + w; i < r1; ++i) f.contrib_ptr[f.rowidx[i] + 1]++;
+    int32_t i = w;
+    while (i < r1 - r0) {
+      const int32_t t = sn_of[f.rowidx[r0 + i]];
+      int32_t j = i;
+      while (j < r1 - r0 && sn_of[f.rowidx[r0 + j]] == t) ++j;
+      updates[t].push_back(Segment{s, i, j});
+      i = j;
+    }
+  }
+  for (int32_t j = 0; j < n; ++j) f.contrib_ptr[j + 1] += f.contrib_ptr[j];
+  f.contrib_sn.resize(f.contrib_ptr[n]);
+  f.contrib_pos.resize(f.contrib_ptr[n]);
+  {
+    std::vector<int32_t> fill(f.contrib_ptr.begin(), f.contrib_ptr.end() - 1);
+    for (int32_t s = 0; s < ns; ++s) {
+      const int32_t w = f.sn_start[s + 1] - f.sn_start[s];
+      const int32_t r0 = f.sn_rowptr[s], r1 = f.sn_rowptr[s + 1];
+      for (int32_t i = r0 + w; i < r1; ++i) {
+        const int32_t r = f.rowidx[i];
+        f.contrib_sn[fill[r]] = s;
+        f.contrib_pos[fill[r]++] = i - r0;
+      }
+    }
+  }
+
+  // numeric factorisation, level by level (supernodes of one level are
+  // independent: their updates come from lower levels only)
+  f.sn_valptr.assign(ns + 1, 0);
+  f.sn_invptr.assign(ns + 1, 0);
+  for (int32_t s = 0; s < ns; ++s) {
+    const int64_t w = f.sn_start[s + 1] - f.sn_start[s];
+    const int64_t m = f.sn_rowptr[s + 1] - f.sn_rowptr[s];
+    f.sn_valptr[s + 1] = f.sn_valptr[s] + m * w;
+    f.sn_invptr[s + 1] = f.sn_invptr[s] + w * w;
+  }
+  f.val.assign(f.sn_valptr[ns], 0.0);
+  f.inv.assign(f.sn_invptr[ns], 0.0);
+  std::vector<std::vector<int32_t>> by_level(f.nlevels);
+  for (int32_t s = 0; s < ns; ++s) by_level[f.sn_level[s]].push_back(s);
+  int failed = -1;
+  double flops = 0.0;
+  for (int32_t lv = 0; lv < f.nlevels && failed < 0; ++lv) {
+    const std::vector<int32_t>& list = by_level[lv];
+#pragma omp parallel reduction(+ : flops)
+    {
+      std::vector<int32_t> pos(n, -1);
+#pragma omp for schedule(dynamic, 1)
+      for (size_t li = 0; li < list.size(); ++li) {
+        const int32_t s = list[li];
+        const int32_t a = f.sn_start[s], b = f.sn_start[s + 1], w = b - a;
+        const int32_t r0 = f.sn_rowptr[s], m = f.sn_rowptr[s + 1] - r0;
+        const int32_t* R = f.rowidx.data() + r0;
+        for (int32_t t = 0; t < m; ++t) pos[R[t]] = t;
+        double* Ls = f.val.data() + f.sn_valptr[s];
+        for (int32_t j = a; j < b; ++j)
+          for (int32_t e = acol_ptr[j]; e < acol_ptr[j + 1]; ++e)
+            Ls[(size_t)pos[acol_row[e]] * w + (j - a)] = acol_val[e];
+        for (const Segment& sg : updates[s]) {
+          const int32_t d = sg.d;
+          const int32_t wd = f.sn_start[d + 1] - f.sn_start[d];
+          const int32_t rd0 = f.sn_rowptr[d], md = f.sn_rowptr[d + 1] - rd0;
+          const int32_t* Rd = f.rowidx.data() + rd0;
+          const double* Ld = f.val.data() + f.sn_valptr[d];
+          for (int32_t qi = sg.p1; qi < sg.p2; ++qi) {
+            const int32_t colx = Rd[qi] - a;
+            const double* lq = Ld + (size_t)qi * wd;
+            for (int32_t ri = qi; ri < md; ++ri) {
+              const double* lr = Ld + (size_t)ri * wd;
+              double acc = 0.0;
+              for (int32_t q = 0; q < wd; ++q) acc += lr[q] * lq[q];
+              Ls[(size_t)pos[Rd[ri]] * w + colx] -= acc;
+            }
+            flops += 2.0 * (double)(md - qi) * wd;
+          }
+        }
+        // dense left-looking Cholesky of the diagonal block fused with the
+        // triangular solve of the rows below it
+        bool ok = true;
+        for (int32_t j = 0; j < w && ok; ++j) {
+          const double* lj = Ls + (size_t)j * w;
+          for (int32_t i = j; i < m; ++i) {
+            double* li = Ls + (size_t)i * w;
+            double sum = li[j];
+            for (int32_t q = 0; q < j; ++q) sum -= li[q] * lj[q];
+            if (i == j) {
+              if (!(sum > 0.0)) {
+                ok = false;
+                break;
+              }
+              li[j] = std::sqrt(sum);
+            } else {
+              li[j] = sum / lj[j];
+            }
+          }
+          flops += 2.0 * (double)(m - j) * j;
+        }
+        if (!ok) {
+#pragma omp critical
+          failed = s;
+        } else {
+          // inverse of the lower-triangular diagonal block, row by row
+          double* Vs = f.inv.data() + f.sn_invptr[s];
+          for (int32_t i = 0; i < w; ++i) {
+            double* vi = Vs + (size_t)i * w;
+            const double* li = Ls + (size_t)i * w;
+            for (int32_t q = 0; q < i; ++q) {
+              const double lq = li[q];
+              const double* vq = Vs + (size_t)q * w;
+              for (int32_t c = 0; c <= q; ++c) vi[c] -= lq * vq[c];
+            }
+            vi[i] += 1.0;
+            const double inv_d = 1.0 / li[i];
+            for (int32_t c = 0; c <= i; ++c) vi[c] *= inv_d;
+          }
+          flops += (double)w * w * w / 3.0;
+        }
+        for (int32_t t = 0; t < m; ++t) pos[R[t]] = -1;
+      }
+    }
+  }
+  f.flops = flops;
+  if (failed >= 0) {
+    msg = "normal matrix is not numerically positive definite (supernode " +
+          std::to_string(failed) + ")";
+    return false;
+  }
+  // solve operators B_s = [inv(L_ss); L_os inv(L_ss)] and update slots
+  f.bcol.assign(f.sn_valptr[ns], 0.0);
+  f.brow.assign(f.sn_valptr[ns], 0.0);
+  f.slot_base.assign(ns + 1, 0);
+  for (int32_t s = 0; s < ns; ++s) {
+    const int64_t w = f.sn_start[s + 1] - f.sn_start[s];
+    const int64_t m = f.sn_rowptr[s + 1] - f.sn_rowptr[s];
+    f.slot_base[s + 1] = f.slot_base[s] + (m - w);
+  }
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int32_t s = 0; s < ns; ++s) {
+    const int32_t w = f.sn_start[s + 1] - f.sn_start[s];
+    const int32_t m = f.sn_rowptr[s + 1] - f.sn_rowptr[s];
+    const double* Ls = f.val.data() + f.sn_valptr[s];
+    const double* Vs = f.inv.data() + f.sn_invptr[s];
+    double* Br = f.brow.data() + f.sn_valptr[s];
+    double* Bc = f.bcol.data() + f.sn_valptr[s];
+    for (int32_t i = 0; i < w; ++i)
+      for (int32_t q = 0; q <= i; ++q) Br[(size_t)i * w + q] = Vs[(size_t)i * w + q];
+    for (int32_t i = w; i < m; ++i) {
+      const double* li = Ls + (size_t)i * w;
+      double* bi = Br + (size_t)i * w;
+      for (int32_t p = 0; p < w; ++p) {
+        const double lp = li[p];
+        const double* vp = Vs + (size_t)p * w;
+        for (int32_t q = 0; q <= p; ++q) bi[q] += lp * vp[q];
+      }
+    }
+    for (int32_t i = 0; i < m; ++i)
+      for (int32_t q = 0; q < w; ++q) Bc[(size_t)q * m + i] = Br[(size_t)i * w + q];
+  }
+  f.contrib_slot.resize(f.contrib_sn.size());
+  for (size_t e = 0; e < f.contrib_sn.size(); ++e) {
+    const int32_t d = f.contrib_sn[e];
+    const int32_t wd = f.sn_start[d + 1] - f.sn_start[d];
+    f.contrib_slot[e] = (int32_t)(f.slot_base[d] + f.contrib_pos[e] - wd);
+  }
+  return true;
+}
+
+void chol_solve_host(const CholFactor& f, int32_t ncols, const double* r, double* z) {
+  const int32_t n = f.n;
+  std::vector<double> W((size_t)n * ncols), Y((size_t)n * ncols), X((size_t)n * ncols);
+  std::vector<double> U((size_t)f.slot_base[f.nsuper] * ncols);
+  std::vector<std::vector<int32_t>> by_level(f.nlevels);
+  for (int32_t s = 0; s < f.nsuper; ++s) by_level[f.sn_level[s]].push_back(s);
+  // forward: W_s = r_s - (updates from descendants); [Y_s; U_s] = B_s W_s
+  for (int32_t lv = 0; lv < f.nlevels; ++lv)
+    for (int32_t s : by_level[lv]) {
+      const int32_t a = f.sn_start[s], w = f.sn_start[s + 1] - a;
+      const int32_t m = f.sn_rowptr[s + 1] - f.sn_rowptr[s];
+      for (int32_t j = a; j < a + w; ++j)
+        for (int32_t c = 0; c < ncols; ++c) {
+          double acc = r[(size_t)f.perm[j] * ncols + c];
+          for (int32_t e = f.contrib_ptr[j]; e < f.contrib_ptr[j + 1]; ++e)
+            acc -= U[(size_t)f.contrib_slot[e] * ncols + c];
+          W[(size_t)j * ncols + c] = acc;
+        }
+      const double* Bc = f.bcol.data() + f.sn_valptr[s];
+      for (int32_t i = 0; i < m; ++i)
+        for (int32_t c = 0; c < ncols; ++c) {
+          double acc = 0.0;
+          for (int32_t q = 0; q < w; ++q) acc += Bc[(size_t)q * m + i] * W[(size_t)(a + q) * ncols + c];
+          if (i < w)
+            Y[(size_t)(a + i) * ncols + c] = acc;
+          else
+            U[(size_t)(f.slot_base[s] + i - w) * ncols + c] = acc;
+        }
+    }
+  // backward: X_s = B_s^T [Y_s; -X_(rows of s below its diagonal block)]
+  for (int32_t lv = f.nlevels - 1; lv >= 0; --lv)
+    for (int32_t s : by_level[lv]) {
+      const int32_t a = f.sn_start[s], w = f.sn_start[s + 1] - a;
+      const int32_t rb = f.sn_rowptr[s], m = f.sn_rowptr[s + 1] - rb;
+      const double* Br = f.brow.data() + f.sn_valptr[s];
+      for (int32_t t = 0; t < w; ++t)
+        for (int32_t c = 0; c < ncols; ++c) {
+          double acc = 0.0;
+          for (int32_t i = 0; i < m; ++i) {
+            const double v = i < w ? Y[(size_t)(a + i) * ncols + c]
+                                   : -X[(size_t)f.rowidx[rb + i] * ncols + c];
+            acc += Br[(size_t)i * w + t] * v;
+          }
+          X[(size_t)(a + t) * ncols + c] = acc;
+        }
+    }
+  for (int32_t j = 0; j < n; ++j)
+    for (int32_t c = 0; c < ncols; ++c) z[(size_t)f.perm[j] * ncols + c] = X[(size_t)j * ncols + c];
+}
+
+}  // namespace dmc

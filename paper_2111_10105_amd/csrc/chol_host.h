@@ -1,0 +1,58 @@
+// Sparse Cholesky factorisation of the normal matrix L^T L + I_N^T I_N of the
+// anchored system (Eq. 12), computed once per mesh on the host and used by
+// the decoder as the preconditioner of its conjugate gradients.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "mesh_host.h"
+
+namespace dmc {
+
+struct CholFactor {
+  int32_t n = 0;
+  std::vector<int32_t> perm;       // elimination position -> vertex
+  int32_t nsuper = 0;
+  std::vector<int32_t> sn_start;   // [nsuper+1] first column of each supernode
+  std::vector<int32_t> sn_rowptr;  // [nsuper+1] into rowidx
+  std::vector<int32_t> rowidx;     // rows of each supernode: its own columns, then the rest
+  std::vector<int64_t> sn_valptr;  // [nsuper+1] into val: m_s x w_s row-major block
+  std::vector<double> val;
+  std::vector<int64_t> sn_invptr;  // [nsuper+1] into inv: w_s x w_s inverse of the diagonal block
+  std::vector<double> inv;
+  // Solve operator per supernode, B_s = [inv(L_ss); L_os inv(L_ss)] (m_s x w_s),
+  // stored column-major (bcol, for the forward solve) and row-major (brow, for
+  // the backward solve); offsets are sn_valptr.
+  std::vector<double> bcol, brow;
+  // update slots: rows w_s..m_s-1 of supernode s own slots
+  // slot_base[s] .. slot_base[s] + m_s - w_s - 1
+  std::vector<int64_t> slot_base;  // [nsuper+1]
+  std::vector<int32_t> contrib_slot;  // per contribution (same order as contrib_sn)
+  std::vector<int32_t> sn_parent;
+  std::vector<int32_t> sn_level;   // 0 for leaves, 1 + max over children otherwise
+  int32_t nlevels = 0;
+  // for every column j: the (supernode d, row position i in d) pairs with
+  // rowidx[d][i] == j and i >= width(d): the entries of row j left of the
+  // diagonal block, in increasing d
+  std::vector<int32_t> contrib_ptr;  // [n+1]
+  std::vector<int32_t> contrib_sn;
+  std::vector<int32_t> contrib_pos;
+  int64_t nnz_exact = 0;             // nonzeros of the exact factor
+  double flops = 0.0;                // numeric factorisation flops
+};
+
+// Nested-dissection ordering (recursive bisection by breadth-first level
+// sets of the graph of M; parts of at most `leaf` vertices end the recursion)
+// followed by symbolic and numeric supernodal factorisation, one supernode per
+// dissection node.  Returns false with a message if M is not numerically
+// positive definite.
+bool build_cholesky(const HostCsr& M, int32_t leaf, CholFactor& f, std::string& msg);
+
+// z = (L L^T)^{-1} r on the host, by the same blocked algorithm as the device
+// solve (gather of updates, multiplication by the inverse diagonal blocks).
+// r and z are [n][ncols] row-major in vertex order; they may alias.
+void chol_solve_host(const CholFactor& f, int32_t ncols, const double* r, double* z);
+
+}  // namespace dmc

@@ -1,0 +1,165 @@
+// Internal declarations shared by the host driver and the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/dmc.h"
+#include "profile.h"
+
+namespace dmc {
+
+constexpr int kBlock = 256;
+constexpr size_t kAlign = 256;
+
+inline size_t align_up(size_t x, size_t a = kAlign) { return (x + a - 1) / a * a; }
+
+// Byte layout of one window record (see dmc.h).
+struct RecordLayout {
+  int32_t T = 0, k = 0, n = 0, nc = 0;
+  int32_t coef_bits = 0, anchor_bits = 0, dict_bits = 0, precision = 0;
+  size_t real = 8;            // bytes per raw value
+  size_t off_dict = 0, off_ranges = 0, off_codes = 0, off_arange = 0, off_anchors = 0;
+  size_t bytes = 0;
+};
+
+RecordLayout record_layout(int32_t n, int32_t T, int32_t k, int32_t nc, const dmc_params& p);
+
+// Device-side supernodal Cholesky factor of the normal matrix (built on the
+// host by build_cholesky, see chol_host.h).
+struct CholDev {
+  int32_t n = 0, ns = 0, nlevels = 0;
+  const int32_t* perm = nullptr;        // elimination position -> vertex
+  const int32_t* sn_start = nullptr;    // [ns+1]
+  const int32_t* sn_rowptr = nullptr;   // [ns+1]
+  const int32_t* rowidx = nullptr;
+  const int64_t* sn_valptr = nullptr;   // offsets of B_s (m_s x w_s)
+  const double* bcol = nullptr;         // B_s column-major
+  const double* brow = nullptr;         // B_s row-major
+  const int64_t* slot_base = nullptr;   // [ns+1] update slots of each supernode
+  const int32_t* contrib_ptr = nullptr; // [n+1] per column: update slots aimed at it
+  const int32_t* contrib_slot = nullptr;
+  // work items (supernode, first row of a 64-row tile), grouped by level:
+  // tiles over the w_s columns of each supernode, and over its m_s rows
+  const int32_t* task_w_sn = nullptr;
+  const int32_t* task_w_r0 = nullptr;
+  const int32_t* task_m_sn = nullptr;
+  const int32_t* task_m_r0 = nullptr;
+  const int32_t* level_w_host = nullptr;  // host arrays [nlevels + 1]
+  const int32_t* level_m_host = nullptr;
+  int64_t nslots = 0;
+};
+
+// Device-side mesh data.
+struct MeshDev {
+  int32_t n = 0, nnz = 0, nc = 0, laplacian = 0;
+  int32_t m_nnz = 0;
+  const int32_t* rowptr = nullptr;   // [n+1]  CSR of the adjacency C
+  const int32_t* col = nullptr;      // [nnz]
+  const double* w64 = nullptr;       // [n] 1/d_i (uniform) or d_i (combinatorial)
+  const float* w32 = nullptr;
+  const int32_t* anchors = nullptr;  // [nc]
+  const int32_t* slot = nullptr;     // [n] anchor slot of a vertex, or -1
+  const int32_t* m_rowptr = nullptr; // [n+1] CSR of L^T L + I_N^T I_N
+  const int32_t* m_col = nullptr;
+  const double* m_val = nullptr;
+  const double* m_dinv = nullptr;    // [n] 1 / diagonal
+  CholDev chol;
+};
+
+// Per-window stats written by the kernels (device).
+struct StatsDev {
+  int32_t sweeps[3];
+  int32_t shifts[3];
+  double resid[3];
+};
+
+// ---- kernel launchers (kernels_*.hip) --------------------------------------
+
+// Delta coordinates for F frames.
+void launch_delta(hipStream_t s, const MeshDev& m, const void* in, void* out, int32_t F,
+                  int32_t precision);
+
+// Autocorrelation of nw consecutive windows of T frames each:
+// frames [nw*T][n][3] -> R [nw][3][T][T] float64.  `part` is scratch of
+// autocorr_scratch_bytes(...) bytes.
+size_t autocorr_scratch_bytes(int32_t n, int32_t T, int32_t nw, int32_t precision);
+void launch_autocorr(hipStream_t s, const void* frames, int32_t n, int32_t T, int32_t nw,
+                     int32_t precision, void* part, double* R);
+
+// Orthogonal iterations + Ritz + dictionary quantisation over a chain of nw
+// windows of T frames (window w starts from window w-1's U_k).
+struct OiArgs {
+  const double* R;       // [nw][3][T][T]
+  int32_t nw, T, k;
+  int32_t precision;
+  int32_t dict_bits;
+  const void* q_start;   // [3][T][k] real, or nullptr (exact start)
+  void* u_out;           // [nw][3][T][k] real (may be nullptr)
+  double* u_tilde;       // [nw][3][T][k] float64 dequantised dictionary
+  uint8_t* records;      // record of window w at records + w*rec_bytes
+  size_t rec_bytes;
+  size_t off_dict;
+  int32_t max_sweeps;
+  double tol;
+  StatsDev* stats;       // [nw]
+};
+void launch_oi(hipStream_t s, const OiArgs& a);
+
+// Projection (Eq. 9) + per-row ranges + quantisation (Eq. 10) for nw windows.
+size_t project_scratch_bytes(int32_t n, int32_t T, int32_t k, int32_t nw, int32_t precision);
+void launch_project_quantise(hipStream_t s, const void* delta, int32_t n, int32_t T, int32_t k,
+                             int32_t nw, int32_t precision, int32_t coef_bits,
+                             const double* u_tilde, uint8_t* records, size_t rec_bytes,
+                             const RecordLayout& lay, void* scratch, void* coef_out);
+
+// Anchor values of nw windows (Eq. 12): gather + quantisation into records.
+void launch_anchors(hipStream_t s, const MeshDev& m, const void* frames, int32_t T, int32_t nw,
+                    int32_t precision, int32_t anchor_bits, uint8_t* records, size_t rec_bytes,
+                    const RecordLayout& lay);
+
+void launch_write_header(hipStream_t s, uint8_t* rec, const RecordLayout& lay);
+
+// ---- decode ----------------------------------------------------------------
+
+// Right-hand side of the normal equations for every window of a sequence,
+// columns j = 3*t + c for global frame t.  B0 and b are [n][ncols] float64.
+struct SeqLayout {
+  int32_t nw_full, T;        // full windows
+  int32_t T_tail;            // 0 if none
+  RecordLayout full, tail;
+  size_t rec_bytes_full;
+};
+void launch_back_project(hipStream_t s, const MeshDev& m, const uint8_t* records,
+                         const SeqLayout& sl, const double* u_tilde_or_null, double* B0);
+void launch_rhs(hipStream_t s, const MeshDev& m, const uint8_t* records, const SeqLayout& sl,
+                const double* B0, double* b);
+
+struct CgBuffers {
+  double *x, *r, *p, *q;
+  double *z, *W, *Y, *X, *U;  // preconditioned residual and triangular-solve work
+  double* part;      // [nblk_rows][ncols] x 2
+  double *rz, *rr, *bnorm2, *alpha, *beta;
+  int32_t* done;     // [ncols]
+  double* resid;     // [ncols]
+};
+size_t cg_part_rows(int32_t n);
+void launch_cg_init(hipStream_t s, const MeshDev& m, int32_t ncols, const double* b,
+                    const CgBuffers& cb, int32_t precond);
+// one iteration = step_a (q = M p, alpha, x and r updates, residual check)
+// then, unless every column has converged, step_b (preconditioner, beta, p)
+void launch_cg_step_a(hipStream_t s, const MeshDev& m, int32_t ncols, const CgBuffers& cb,
+                      int32_t precond, double tol);
+void launch_cg_step_b(hipStream_t s, const MeshDev& m, int32_t ncols, const CgBuffers& cb,
+                      int32_t precond);
+void launch_chol_solve(hipStream_t s, const CholDev& f, int32_t ncols, const double* r, double* z,
+                       double* W, double* Y, double* X, double* U);
+void launch_precond_apply(hipStream_t s, const MeshDev& m, int32_t ncols, const CgBuffers& cb);
+void launch_to_frames(hipStream_t s, const double* X, int32_t n, int32_t F, int32_t precision,
+                      void* frames_out);
+
+}  // namespace dmc

@@ -1,0 +1,435 @@
+// Decoder kernels (Eq. 12): dequantisation and back-projection of every
+// window, the right-hand side of the normal equations, conjugate gradients on
+// (L^T L + I_N^T I_N) X = L^T B + I_N^T A_N for all columns at once, and the
+// final transpose to frames.
+//
+// Decoder vectors are float64 and vertex-major: row i holds the 3F values of
+// vertex i, column j = 3 t + c for global frame t and coordinate c, so every
+// sparse row gather is one contiguous read of a neighbour's row.
+#include <algorithm>
+
+#include "dmc_internal.h"
+
+namespace dmc {
+namespace {
+
+constexpr int BP_V = 32;   // vertices per back-projection block
+constexpr int CG_RB = 32;  // rows per CG block
+
+__device__ inline double dequant(uint32_t code, double lo, double hi, int bits) {
+#pragma clang fp contract(off)
+  const double levels = (double)((1u << bits) - 1u);
+  const double step = (hi - lo) / levels;
+  return lo + (double)code * step;
+}
+
+__device__ inline void window_of(const SeqLayout& sl, const uint8_t* records, int w,
+                                 const uint8_t*& rec, int& T, int& k, int& t0,
+                                 const RecordLayout*& lay) {
+  if (w < sl.nw_full) {
+    rec = records + (size_t)w * sl.rec_bytes_full;
+    T = sl.T;
+    k = sl.full.k;
+    t0 = w * sl.T;
+    lay = &sl.full;
+  } else {
+    rec = records + (size_t)sl.nw_full * sl.rec_bytes_full;
+    T = sl.T_tail;
+    k = sl.tail.k;
+    t0 = sl.nw_full * sl.T;
+    lay = &sl.tail;
+  }
+}
+
+// B0[i][3(t0+t)+c] = sum_r U~_c[t][r] Y^_c[r][i]  (Eq. 11/12 right-hand side)
+template <typename Real>
+__global__ void __launch_bounds__(kBlock)
+k_back_project(const uint8_t* __restrict__ records, SeqLayout sl, int n, int ncols,
+               double* __restrict__ B0) {
+  __shared__ double Ut[3 * 64 * 32];
+  __shared__ double Yh[BP_V * 3 * 32];
+  const int w = blockIdx.y;
+  const uint8_t* rec;
+  int T, k, t0;
+  const RecordLayout* lay;
+  window_of(sl, records, w, rec, T, k, t0, lay);
+  const int i0 = blockIdx.x * BP_V;
+  const int nv = min(BP_V, n - i0);
+  // dictionary
+  const int db = lay->dict_bits;
+  for (int e = threadIdx.x; e < 3 * T * k; e += kBlock) {
+    if (db > 0)
+      Ut[e] = dequant(((const uint16_t*)(rec + lay->off_dict))[e], -1.0, 1.0, db);
+    else
+      Ut[e] = (double)((const Real*)(rec + lay->off_dict))[e];
+  }
+  // coefficients of this block's vertices: Yh[v][c][r]
+  const int cb = lay->coef_bits;
+  for (int e = threadIdx.x; e < 3 * k * nv; e += kBlock) {
+    const int v = e % nv, cr = e / nv;  // consecutive threads -> consecutive vertices
+    const int c = cr / k, r = cr % k;
+    const size_t idx = ((size_t)c * k + r) * n + i0 + v;
+    double y;
+    if (cb > 0) {
+      const float* rg = (const float*)(rec + lay->off_ranges) + ((size_t)c * k + r) * 2;
+      y = dequant(((const uint16_t*)(rec + lay->off_codes))[idx], (double)rg[0], (double)rg[1], cb);
+    } else {
+      y = (double)((const Real*)(rec + lay->off_codes))[idx];
+    }
+    Yh[(v * 3 + c) * 32 + r] = y;
+  }
+  __syncthreads();
+  const int wcols = 3 * T;
+  for (int e = threadIdx.x; e < nv * wcols; e += kBlock) {
+    const int v = e / wcols, j = e % wcols;
+    const int t = j / 3, c = j % 3;
+    const double* u = Ut + (c * T + t) * k;
+    const double* y = Yh + (v * 3 + c) * 32;
+    double s = 0.0;
+    for (int r = 0; r < k; ++r) s = fma(u[r], y[r], s);
+    B0[(size_t)(i0 + v) * ncols + 3 * t0 + j] = s;
+  }
+}
+
+// Dense anchor values Ahat[slot][j] for every column j of the sequence.
+template <typename Real>
+__global__ void k_anchor_values(const uint8_t* __restrict__ records, SeqLayout sl, int nc,
+                                int ncols, double* __restrict__ Ah) {
+  const size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (e >= (size_t)nc * ncols) return;
+  const int s = (int)(e / ncols), j = (int)(e % ncols);
+  const int tg = j / 3, c = j % 3;
+  int w = tg / sl.T;
+  if (w > sl.nw_full) w = sl.nw_full;
+  const uint8_t* rec;
+  int T, k, t0;
+  const RecordLayout* lay;
+  window_of(sl, records, w, rec, T, k, t0, lay);
+  const int t = tg - t0;
+  const size_t idx = ((size_t)c * T + t) * nc + s;
+  double v;
+  if (lay->anchor_bits > 0) {
+    const float* rg = (const float*)(rec + lay->off_arange) + 2 * c;
+    v = dequant(((const uint16_t*)(rec + lay->off_anchors))[idx], (double)rg[0], (double)rg[1],
+                lay->anchor_bits);
+  } else {
+    v = (double)((const Real*)(rec + lay->off_anchors))[idx];
+  }
+  Ah[e] = v;
+}
+
+// b = L^T B0 + I_N^T Ahat
+//   uniform:       (L^T u)_i = u_i - sum_{j in ring(i)} u_j / d_j
+//   combinatorial: (L^T u)_i = d_i u_i - sum_{j in ring(i)} u_j
+__global__ void __launch_bounds__(kBlock)
+k_rhs(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+      const double* __restrict__ w, int uniform, const int32_t* __restrict__ slot, int n,
+      int ncols, const double* __restrict__ B0, const double* __restrict__ Ah,
+      double* __restrict__ b) {
+  const int j = blockIdx.y * kBlock + threadIdx.x;
+  if (j >= ncols) return;
+  const int r0 = blockIdx.x * CG_RB, r1 = min(n, r0 + CG_RB);
+  for (int i = r0; i < r1; ++i) {
+    const double ui = B0[(size_t)i * ncols + j];
+    double s = 0.0;
+    for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+      const int nb = col[e];
+      const double v = B0[(size_t)nb * ncols + j];
+      s += uniform ? v * w[nb] : v;
+    }
+    double out = uniform ? ui - s : w[i] * ui - s;
+    const int sl = slot[i];
+    if (sl >= 0) out += Ah[(size_t)sl * ncols + j];
+    b[(size_t)i * ncols + j] = out;
+  }
+}
+
+// ---- conjugate gradients ----------------------------------------------------
+
+__global__ void __launch_bounds__(kBlock)
+k_cg_init(const double* __restrict__ b, const double* __restrict__ dinv, int precond, int n,
+          int ncols, double* __restrict__ x, double* __restrict__ r, double* __restrict__ p,
+          double* __restrict__ part) {
+  const int j = blockIdx.y * kBlock + threadIdx.x;
+  if (j >= ncols) return;
+  const int r0 = blockIdx.x * CG_RB, r1 = min(n, r0 + CG_RB);
+  double bb = 0.0, rz = 0.0;
+  for (int i = r0; i < r1; ++i) {
+    const size_t e = (size_t)i * ncols + j;
+    const double bv = b[e];
+    const double z = precond == DMC_PRECOND_JACOBI ? dinv[i] * bv : bv;
+    x[e] = 0.0;
+    r[e] = bv;
+    p[e] = precond == DMC_PRECOND_CHOLESKY ? 0.0 : z;
+    bb += bv * bv;
+    rz += bv * z;
+  }
+  const size_t nrb = gridDim.x;
+  part[(size_t)blockIdx.x * ncols + j] = bb;
+  part[(nrb + blockIdx.x) * ncols + j] = rz;
+}
+
+__global__ void k_cg_init_reduce(const double* __restrict__ part, int nrb, int ncols,
+                                 double* __restrict__ bnorm2, double* __restrict__ rz,
+                                 int32_t* __restrict__ done, double* __restrict__ resid) {
+  const int j = blockIdx.x * kBlock + threadIdx.x;
+  if (j >= ncols) return;
+  double bb = 0.0, z = 0.0;
+  for (int q = 0; q < nrb; ++q) {
+    bb += part[(size_t)q * ncols + j];
+    z += part[((size_t)nrb + q) * ncols + j];
+  }
+  bnorm2[j] = bb;
+  rz[j] = z;
+  done[j] = bb == 0.0 ? 1 : 0;
+  resid[j] = bb == 0.0 ? 0.0 : 1.0;
+}
+
+// q = M p (CSR of L^T L + I_N^T I_N), partial p.q per column.
+__global__ void __launch_bounds__(kBlock)
+k_cg_spmm(const int32_t* __restrict__ mrow, const int32_t* __restrict__ mcol,
+          const double* __restrict__ mval, int n, int ncols, const double* __restrict__ p,
+          double* __restrict__ q, double* __restrict__ part) {
+  const int j = blockIdx.y * kBlock + threadIdx.x;
+  if (j >= ncols) return;
+  const int r0 = blockIdx.x * CG_RB, r1 = min(n, r0 + CG_RB);
+  double pq = 0.0;
+  for (int i = r0; i < r1; ++i) {
+    double acc = 0.0;
+    for (int e = mrow[i]; e < mrow[i + 1]; ++e) acc = fma(mval[e], p[(size_t)mcol[e] * ncols + j], acc);
+    q[(size_t)i * ncols + j] = acc;
+    pq = fma(p[(size_t)i * ncols + j], acc, pq);
+  }
+  part[(size_t)blockIdx.x * ncols + j] = pq;
+}
+
+__global__ void k_cg_alpha(const double* __restrict__ part, int nrb, int ncols,
+                           const double* __restrict__ rz, const int32_t* __restrict__ done,
+                           double* __restrict__ alpha) {
+  const int j = blockIdx.x * kBlock + threadIdx.x;
+  if (j >= ncols) return;
+  double pq = 0.0;
+  for (int q = 0; q < nrb; ++q) pq += part[(size_t)q * ncols + j];
+  alpha[j] = (done[j] || pq == 0.0) ? 0.0 : rz[j] / pq;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_cg_update(int n, int ncols, const double* __restrict__ alpha, const double* __restrict__ dinv,
+            int precond, double* __restrict__ x, double* __restrict__ r,
+            const double* __restrict__ p, const double* __restrict__ q, double* __restrict__ part) {
+  const int j = blockIdx.y * kBlock + threadIdx.x;
+  if (j >= ncols) return;
+  const int r0 = blockIdx.x * CG_RB, r1 = min(n, r0 + CG_RB);
+  const double a = alpha[j];
+  double rr = 0.0, rz = 0.0;
+  for (int i = r0; i < r1; ++i) {
+    const size_t e = (size_t)i * ncols + j;
+    x[e] = fma(a, p[e], x[e]);
+    const double rv = fma(-a, q[e], r[e]);
+    r[e] = rv;
+    const double z = precond == DMC_PRECOND_JACOBI ? dinv[i] * rv : rv;
+    rr = fma(rv, rv, rr);
+    rz = fma(rv, z, rz);
+  }
+  const size_t nrb = gridDim.x;
+  part[(size_t)blockIdx.x * ncols + j] = rr;
+  // with the Cholesky preconditioner r.z comes from k_cg_dot after the solve
+  if (precond != DMC_PRECOND_CHOLESKY) part[(nrb + blockIdx.x) * ncols + j] = rz;
+}
+
+// partial r.z per column into the second half of `part`
+__global__ void __launch_bounds__(kBlock)
+k_cg_dot(int n, int ncols, const double* __restrict__ r, const double* __restrict__ z,
+         double* __restrict__ part) {
+  const int j = blockIdx.y * kBlock + threadIdx.x;
+  if (j >= ncols) return;
+  const int r0 = blockIdx.x * CG_RB, r1 = min(n, r0 + CG_RB);
+  double rz = 0.0;
+  for (int i = r0; i < r1; ++i) {
+    const size_t e = (size_t)i * ncols + j;
+    rz = fma(r[e], z[e], rz);
+  }
+  part[((size_t)gridDim.x + blockIdx.x) * ncols + j] = rz;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_copy(size_t count, const double* __restrict__ src, double* __restrict__ dst) {
+  for (size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x; e < count;
+       e += (size_t)gridDim.x * kBlock)
+    dst[e] = src[e];
+}
+
+// relative residual per column from the r.r partials; marks converged columns
+__global__ void k_cg_resid(const double* __restrict__ part, int nrb, int ncols,
+                           const double* __restrict__ bnorm2, int32_t* __restrict__ done,
+                           double* __restrict__ resid, double tol) {
+  const int j = blockIdx.x * kBlock + threadIdx.x;
+  if (j >= ncols) return;
+  if (done[j]) return;
+  double rr = 0.0;
+  for (int q = 0; q < nrb; ++q) rr += part[(size_t)q * ncols + j];
+  const double res = bnorm2[j] > 0.0 ? sqrt(rr / bnorm2[j]) : 0.0;
+  resid[j] = res;
+  if (res <= tol) done[j] = 2;  // converged in this iteration
+}
+
+// beta = (r.z)_new / (r.z)_old from the r.z partials (zero for converged columns)
+__global__ void k_cg_beta(const double* __restrict__ part, int nrb, int ncols,
+                          double* __restrict__ rz, int32_t* __restrict__ done,
+                          double* __restrict__ beta) {
+  const int j = blockIdx.x * kBlock + threadIdx.x;
+  if (j >= ncols) return;
+  if (done[j]) {
+    done[j] = 1;
+    beta[j] = 0.0;
+    return;
+  }
+  double z = 0.0;
+  for (int q = 0; q < nrb; ++q) z += part[((size_t)nrb + q) * ncols + j];
+  beta[j] = rz[j] != 0.0 ? z / rz[j] : 0.0;
+  rz[j] = z;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_cg_pupdate(int n, int ncols, const double* __restrict__ beta, const double* __restrict__ dinv,
+             int precond, const double* __restrict__ r, const double* __restrict__ zarr,
+             double* __restrict__ p) {
+  const int j = blockIdx.y * kBlock + threadIdx.x;
+  if (j >= ncols) return;
+  const int r0 = blockIdx.x * CG_RB, r1 = min(n, r0 + CG_RB);
+  const double bt = beta[j];
+  for (int i = r0; i < r1; ++i) {
+    const size_t e = (size_t)i * ncols + j;
+    const double z = precond == DMC_PRECOND_CHOLESKY ? zarr[e]
+                     : precond == DMC_PRECOND_JACOBI ? dinv[i] * r[e]
+                                                     : r[e];
+    p[e] = fma(bt, p[e], z);
+  }
+}
+
+// X [n][3F] -> frames [F][n][3]
+template <typename Real>
+__global__ void __launch_bounds__(kBlock)
+k_to_frames(const double* __restrict__ X, int n, int F, Real* __restrict__ out) {
+  __shared__ double tile[32][97];
+  const int i0 = blockIdx.x * 32, t0 = blockIdx.y * 32;
+  const int ncols = 3 * F;
+  const int nv = min(32, n - i0), nt = min(32, F - t0);
+  for (int e = threadIdx.x; e < 32 * 96; e += kBlock) {
+    const int v = e / 96, j = e % 96;
+    if (v < nv && j < 3 * nt) tile[v][j] = X[(size_t)(i0 + v) * ncols + 3 * t0 + j];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 32 * 96; e += kBlock) {
+    const int t = e / 96, vc = e % 96;
+    const int v = vc / 3, c = vc % 3;
+    if (t < nt && v < nv) out[((size_t)(t0 + t) * n + i0 + v) * 3 + c] = (Real)tile[v][3 * t + c];
+  }
+}
+
+}  // namespace
+
+size_t cg_part_rows(int32_t n) { return (size_t)(n + CG_RB - 1) / CG_RB; }
+
+void launch_back_project(hipStream_t s, const MeshDev& m, const uint8_t* records,
+                         const SeqLayout& sl, const double* /*u_tilde*/, double* B0) {
+  const int nw = sl.nw_full + (sl.T_tail > 0 ? 1 : 0);
+  const int F = sl.nw_full * sl.T + sl.T_tail;
+  dim3 grid((m.n + BP_V - 1) / BP_V, nw);
+  prof::begin(s, DMC_KERNEL_BACK_PROJECT);
+  if (sl.full.precision == DMC_FP64)
+    hipLaunchKernelGGL(k_back_project<double>, grid, dim3(kBlock), 0, s, records, sl, m.n, 3 * F,
+                       B0);
+  else
+    hipLaunchKernelGGL(k_back_project<float>, grid, dim3(kBlock), 0, s, records, sl, m.n, 3 * F,
+                       B0);
+  prof::end(s, DMC_KERNEL_BACK_PROJECT);
+}
+
+void launch_rhs(hipStream_t s, const MeshDev& m, const uint8_t* records, const SeqLayout& sl,
+                const double* B0, double* b) {
+  const int F = sl.nw_full * sl.T + sl.T_tail;
+  const int ncols = 3 * F;
+  // dense anchor values live right after b (the caller sizes b for both)
+  double* Ah = b + (size_t)m.n * ncols;
+  const size_t tot = (size_t)m.nc * ncols;
+  if (sl.full.precision == DMC_FP64)
+    hipLaunchKernelGGL(k_anchor_values<double>, dim3((tot + kBlock - 1) / kBlock), dim3(kBlock),
+                       0, s, records, sl, m.nc, ncols, Ah);
+  else
+    hipLaunchKernelGGL(k_anchor_values<float>, dim3((tot + kBlock - 1) / kBlock), dim3(kBlock), 0,
+                       s, records, sl, m.nc, ncols, Ah);
+  dim3 grid(cg_part_rows(m.n), (ncols + kBlock - 1) / kBlock);
+  prof::begin(s, DMC_KERNEL_RHS);
+  hipLaunchKernelGGL(k_rhs, grid, dim3(kBlock), 0, s, m.rowptr, m.col, m.w64,
+                     m.laplacian == DMC_LAP_UNIFORM ? 1 : 0, m.slot, m.n, ncols, B0, Ah, b);
+  prof::end(s, DMC_KERNEL_RHS);
+}
+
+void launch_precond_apply(hipStream_t s, const MeshDev& m, int32_t ncols, const CgBuffers& cb) {
+  const int nrb = (int)cg_part_rows(m.n);
+  dim3 grid(nrb, (ncols + kBlock - 1) / kBlock);
+  launch_chol_solve(s, m.chol, ncols, cb.r, cb.z, cb.W, cb.Y, cb.X, cb.U);
+  hipLaunchKernelGGL(k_cg_dot, grid, dim3(kBlock), 0, s, m.n, ncols, cb.r, cb.z, cb.part);
+}
+
+void launch_cg_init(hipStream_t s, const MeshDev& m, int32_t ncols, const double* b,
+                    const CgBuffers& cb, int32_t precond) {
+  const int nrb = (int)cg_part_rows(m.n);
+  dim3 grid(nrb, (ncols + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(k_cg_init, grid, dim3(kBlock), 0, s, b, m.m_dinv, precond, m.n, ncols, cb.x,
+                     cb.r, cb.p, cb.part);
+  if (precond == DMC_PRECOND_CHOLESKY) {
+    launch_precond_apply(s, m, ncols, cb);
+    const size_t count = (size_t)m.n * ncols;
+    hipLaunchKernelGGL(k_copy, dim3(std::min<size_t>(4096, (count + kBlock - 1) / kBlock)),
+                       dim3(kBlock), 0, s, count, (const double*)cb.z, cb.p);
+  }
+  hipLaunchKernelGGL(k_cg_init_reduce, dim3((ncols + kBlock - 1) / kBlock), dim3(kBlock), 0, s,
+                     cb.part, nrb, ncols, cb.bnorm2, cb.rz, cb.done, cb.resid);
+}
+
+void launch_cg_step_a(hipStream_t s, const MeshDev& m, int32_t ncols, const CgBuffers& cb,
+                      int32_t precond, double tol) {
+  const int nrb = (int)cg_part_rows(m.n);
+  dim3 grid(nrb, (ncols + kBlock - 1) / kBlock);
+  dim3 cgrid((ncols + kBlock - 1) / kBlock);
+  prof::begin(s, DMC_KERNEL_CG_SPMM);
+  hipLaunchKernelGGL(k_cg_spmm, grid, dim3(kBlock), 0, s, m.m_rowptr, m.m_col, m.m_val, m.n,
+                     ncols, cb.p, cb.q, cb.part);
+  prof::end(s, DMC_KERNEL_CG_SPMM);
+  hipLaunchKernelGGL(k_cg_alpha, cgrid, dim3(kBlock), 0, s, cb.part, nrb, ncols, cb.rz, cb.done,
+                     cb.alpha);
+  prof::begin(s, DMC_KERNEL_CG_UPDATE);
+  hipLaunchKernelGGL(k_cg_update, grid, dim3(kBlock), 0, s, m.n, ncols, cb.alpha, m.m_dinv,
+                     precond, cb.x, cb.r, cb.p, cb.q, cb.part);
+  prof::end(s, DMC_KERNEL_CG_UPDATE);
+  hipLaunchKernelGGL(k_cg_resid, cgrid, dim3(kBlock), 0, s, cb.part, nrb, ncols, cb.bnorm2,
+                     cb.done, cb.resid, tol);
+}
+
+void launch_cg_step_b(hipStream_t s, const MeshDev& m, int32_t ncols, const CgBuffers& cb,
+                      int32_t precond) {
+  const int nrb = (int)cg_part_rows(m.n);
+  dim3 grid(nrb, (ncols + kBlock - 1) / kBlock);
+  dim3 cgrid((ncols + kBlock - 1) / kBlock);
+  if (precond == DMC_PRECOND_CHOLESKY) launch_precond_apply(s, m, ncols, cb);
+  hipLaunchKernelGGL(k_cg_beta, cgrid, dim3(kBlock), 0, s, cb.part, nrb, ncols, cb.rz, cb.done,
+                     cb.beta);
+  hipLaunchKernelGGL(k_cg_pupdate, grid, dim3(kBlock), 0, s, m.n, ncols, cb.beta, m.m_dinv,
+                     precond, cb.r, cb.z, cb.p);
+}
+
+void launch_to_frames(hipStream_t s, const double* X, int32_t n, int32_t F, int32_t precision,
+                      void* frames_out) {
+  dim3 grid((n + 31) / 32, (F + 31) / 32);
+  prof::begin(s, DMC_KERNEL_TO_FRAMES);
+  if (precision == DMC_FP64)
+    hipLaunchKernelGGL(k_to_frames<double>, grid, dim3(kBlock), 0, s, X, n, F,
+                       (double*)frames_out);
+  else
+    hipLaunchKernelGGL(k_to_frames<float>, grid, dim3(kBlock), 0, s, X, n, F, (float*)frames_out);
+  prof::end(s, DMC_KERNEL_TO_FRAMES);
+}
+
+}  // namespace dmc

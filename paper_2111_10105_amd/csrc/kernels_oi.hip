@@ -1,0 +1,537 @@
+// Orthogonal iterations (Algorithm 1) with a Rayleigh-Ritz step and the
+// dictionary quantiser, for a chain of windows, on one workgroup per
+// coordinate.  Everything lives in LDS in float64:
+//   C.Q products on the FP64 matrix cores (v_mfma_f64_16x16x4f64),
+//   thin QR by CholeskyQR2 (Gram accumulated in float64, k x k Cholesky);
+//   a pivot breakdown switches that sweep to shifted CholeskyQR3, and a second
+//   breakdown (an exactly rank-deficient block) to Gram-Schmidt run twice with
+//   completion of the missing directions from the identity;
+//   eigenvectors of the k x k Ritz matrix (and of the full T x T matrix for an
+//   exact start, Eq. 5) by parallel cyclic Jacobi.
+#include "dmc_internal.h"
+
+namespace dmc {
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int NT = 256;  // threads per workgroup (4 waves)
+
+template <int TMAX, int KMAX>
+struct OiSmem {
+  double R[TMAX * TMAX];
+  double A[TMAX * TMAX];   // Jacobi work matrix; Gram / Cholesky factor; Ritz H
+  double V[TMAX * TMAX];   // Jacobi eigenvectors
+  double Q[TMAX * KMAX];   // orthonormal block (rows >= T, cols >= k kept zero)
+  double Y[TMAX * KMAX];   // R Q, or the canonical U
+  double red[NT];
+  double rot_c[TMAX / 2 + 1], rot_s[TMAX / 2 + 1];
+  int rot_p[TMAX / 2 + 1], rot_q[TMAX / 2 + 1];
+  int perm[TMAX];
+  int flag;
+  int ok;
+};
+
+__device__ inline double block_sum(double v, double* red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = NT / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+__device__ inline double block_max(double v, double* red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = NT / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// Y = R Q (T x k) on the FP64 matrix cores.  Operand layouts of
+// v_mfma_f64_16x16x4f64: lane l holds A[l%16][l/16] and B[l/16][l%16]; result
+// element (4*r + l/16, l%16) is component r of lane l.
+template <int TMAX, int KMAX>
+__device__ void mm_RQ(OiSmem<TMAX, KMAX>& s, int T, int k) {
+  const int Tp = (T + 15) & ~15, kp = (k + 15) & ~15;
+  const int ti_n = Tp / 16, tj_n = kp / 16;
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  for (int tile = wave; tile < ti_n * tj_n; tile += NT / 64) {
+    const int ti = tile / tj_n, tj = tile % tj_n;
+    d4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int kk = 0; kk < Tp; kk += 4) {
+      const double a = s.R[(ti * 16 + lane % 16) * TMAX + kk + lane / 16];
+      const double b = s.Q[(kk + lane / 16) * KMAX + tj * 16 + lane % 16];
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    }
+    for (int r = 0; r < 4; ++r) {
+      const int row = ti * 16 + 4 * r + lane / 16, col = tj * 16 + lane % 16;
+      s.Y[row * KMAX + col] = acc[r];
+    }
+  }
+  __syncthreads();
+}
+
+// A[0:k,0:k] = X^T X for X = Q or Y (T x k).
+template <int TMAX, int KMAX>
+__device__ void gram(OiSmem<TMAX, KMAX>& s, const double* X, int T, int k) {
+  for (int e = threadIdx.x; e < k * k; e += NT) {
+    const int a = e / k, b = e % k;
+    if (b > a) continue;
+    double g = 0.0;
+    for (int t = 0; t < T; ++t) g = fma(X[t * KMAX + a], X[t * KMAX + b], g);
+    s.A[a * TMAX + b] = g;
+    s.A[b * TMAX + a] = g;
+  }
+  __syncthreads();
+}
+
+// In-place Cholesky of A[0:k,0:k] (+ shift on the diagonal); lower factor.
+// Sets s.ok = 0 on a pivot <= rel_tol * max diagonal.
+template <int TMAX, int KMAX>
+__device__ void cholesky(OiSmem<TMAX, KMAX>& s, int k, double shift) {
+  if (threadIdx.x == 0) s.ok = 1;
+  double dmax = 0.0;
+  for (int j = 0; j < k; ++j) dmax = fmax(dmax, s.A[j * TMAX + j]);
+  __syncthreads();
+  if (shift != 0.0)
+    for (int j = threadIdx.x; j < k; j += NT) s.A[j * TMAX + j] += shift;
+  __syncthreads();
+  const double thresh = 1e-15 * dmax;
+  for (int j = 0; j < k; ++j) {
+    if (threadIdx.x == 0) {
+      const double d = s.A[j * TMAX + j];
+      if (!(d > thresh)) {
+        s.ok = 0;
+        s.A[j * TMAX + j] = 1.0;
+      } else {
+        s.A[j * TMAX + j] = sqrt(d);
+      }
+    }
+    __syncthreads();
+    const double ljj = s.A[j * TMAX + j];
+    for (int i = j + 1 + threadIdx.x; i < k; i += NT) s.A[i * TMAX + j] /= ljj;
+    __syncthreads();
+    const int m = k - j - 1;
+    for (int e = threadIdx.x; e < m * m; e += NT) {
+      const int i = j + 1 + e / m, l = j + 1 + e % m;
+      if (l <= i) s.A[i * TMAX + l] -= s.A[i * TMAX + j] * s.A[l * TMAX + j];
+    }
+    __syncthreads();
+  }
+}
+
+// Q = X L^{-T} row by row (forward substitution); X may alias Q.
+template <int TMAX, int KMAX>
+__device__ void tri_solve(OiSmem<TMAX, KMAX>& s, const double* X, int T, int k) {
+  for (int t = threadIdx.x; t < T; t += NT) {
+    for (int j = 0; j < k; ++j) {
+      double v = X[t * KMAX + j];
+      for (int p = 0; p < j; ++p) v -= s.Q[t * KMAX + p] * s.A[j * TMAX + p];
+      s.Q[t * KMAX + j] = v / s.A[j * TMAX + j];
+    }
+  }
+  __syncthreads();
+}
+
+// Gram-Schmidt (each column orthogonalised twice against the previous ones) on
+// Q in place; a column with no component left is replaced by the identity
+// direction e_m with the largest part outside the span found so far.
+template <int TMAX, int KMAX>
+__device__ void gram_schmidt(OiSmem<TMAX, KMAX>& s, int T, int k) {
+  for (int j = 0; j < k; ++j) {
+    const double n0 = sqrt(block_sum(threadIdx.x < T ? s.Q[threadIdx.x * KMAX + j] *
+                                                           s.Q[threadIdx.x * KMAX + j]
+                                                     : 0.0,
+                                     s.red));
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int p = 0; p < j; ++p) {
+        const double d = block_sum(threadIdx.x < T ? s.Q[threadIdx.x * KMAX + p] *
+                                                         s.Q[threadIdx.x * KMAX + j]
+                                                   : 0.0,
+                                   s.red);
+        if (threadIdx.x < T) s.Q[threadIdx.x * KMAX + j] -= d * s.Q[threadIdx.x * KMAX + p];
+        __syncthreads();
+      }
+    }
+    double nj = sqrt(block_sum(threadIdx.x < T ? s.Q[threadIdx.x * KMAX + j] *
+                                                     s.Q[threadIdx.x * KMAX + j]
+                                               : 0.0,
+                               s.red));
+    if (!(nj > 1e-10 * n0) || n0 == 0.0) {
+      // completion: e_m maximising 1 - sum_p Q[m][p]^2
+      double best = -1.0;
+      int bm = 0;
+      for (int m = 0; m < T; ++m) {
+        double out = 1.0;
+        for (int p = 0; p < j; ++p) out -= s.Q[m * KMAX + p] * s.Q[m * KMAX + p];
+        if (out > best) {
+          best = out;
+          bm = m;
+        }
+      }
+      __syncthreads();
+      if (threadIdx.x < T) s.Q[threadIdx.x * KMAX + j] = threadIdx.x == bm ? 1.0 : 0.0;
+      __syncthreads();
+      for (int pass = 0; pass < 2; ++pass) {
+        for (int p = 0; p < j; ++p) {
+          const double d = block_sum(threadIdx.x < T ? s.Q[threadIdx.x * KMAX + p] *
+                                                           s.Q[threadIdx.x * KMAX + j]
+                                                     : 0.0,
+                                     s.red);
+          if (threadIdx.x < T) s.Q[threadIdx.x * KMAX + j] -= d * s.Q[threadIdx.x * KMAX + p];
+          __syncthreads();
+        }
+      }
+      nj = sqrt(block_sum(threadIdx.x < T ? s.Q[threadIdx.x * KMAX + j] *
+                                                s.Q[threadIdx.x * KMAX + j]
+                                          : 0.0,
+                          s.red));
+    }
+    if (threadIdx.x < T) s.Q[threadIdx.x * KMAX + j] /= nj;
+    __syncthreads();
+  }
+}
+
+// Q = orthonormal basis of span(X) (X = Y or Q, T x k).  Returns the number of
+// breakdown repairs (0: plain CholeskyQR2).
+template <int TMAX, int KMAX>
+__device__ int orthonormalise(OiSmem<TMAX, KMAX>& s, const double* X, int T, int k) {
+  int repairs = 0;
+  gram(s, X, T, k);
+  double tr = 0.0;
+  for (int j = 0; j < k; ++j) tr += s.A[j * TMAX + j];
+  __syncthreads();
+  if (tr == 0.0) {
+    // nothing to orthonormalise: complete from the identity
+    for (int e = threadIdx.x; e < T * k; e += NT) s.Q[(e / k) * KMAX + e % k] = 0.0;
+    __syncthreads();
+    gram_schmidt(s, T, k);
+    return 1;
+  }
+  cholesky(s, k, 0.0);
+  int passes = 2;
+  if (!s.ok) {
+    // shifted CholeskyQR (Fukaya et al.): shift 11 (T k + k (k + 1)) u ||X||^2
+    repairs = 1;
+    passes = 3;
+    gram(s, X, T, k);
+    const double shift = 11.0 * (double)(T * k + k * (k + 1)) * 1.1102230246251565e-16 * tr;
+    cholesky(s, k, shift);
+    if (!s.ok) {
+      if (X != s.Q)
+        for (int e = threadIdx.x; e < T * k; e += NT)
+          s.Q[(e / k) * KMAX + e % k] = X[(e / k) * KMAX + e % k];
+      __syncthreads();
+      gram_schmidt(s, T, k);
+      return 2;
+    }
+  }
+  tri_solve(s, X, T, k);
+  for (int pass = 1; pass < passes; ++pass) {
+    gram(s, s.Q, T, k);
+    cholesky(s, k, 0.0);
+    if (!s.ok) {
+      gram_schmidt(s, T, k);
+      return repairs + 2;
+    }
+    tri_solve(s, s.Q, T, k);
+  }
+  return repairs;
+}
+
+// Parallel cyclic Jacobi on the m x m symmetric matrix in A (round-robin
+// pairing, every pair zeroed once per sweep); eigenvectors accumulate in V.
+// A pair is skipped when |A_pq| <= eps sqrt(|A_pp A_qq|); stops after a sweep
+// with no rotation.
+template <int TMAX, int KMAX>
+__device__ void jacobi(OiSmem<TMAX, KMAX>& s, int m) {
+  for (int e = threadIdx.x; e < m * m; e += NT)
+    s.V[(e / m) * TMAX + e % m] = (e / m == e % m) ? 1.0 : 0.0;
+  __syncthreads();
+  if (m < 2) return;
+  const int me = m + (m & 1);
+  const int np = me / 2;
+  const double eps = 2.220446049250313e-16;
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    if (threadIdx.x == 0) s.flag = 0;
+    __syncthreads();
+    for (int round = 0; round < me - 1; ++round) {
+      if (threadIdx.x < np) {
+        const int i = threadIdx.x;
+        int a, b;
+        if (i == 0) {
+          a = me - 1;
+          b = round;
+        } else {
+          a = (round + i) % (me - 1);
+          b = (round - i + me - 1) % (me - 1);
+        }
+        const int p = a < b ? a : b, q = a < b ? b : a;
+        double c = 1.0, sn = 0.0;
+        if (q < m) {
+          const double apq = s.A[p * TMAX + q];
+          const double app = s.A[p * TMAX + p], aqq = s.A[q * TMAX + q];
+          if (fabs(apq) > fmax(eps * sqrt(fabs(app * aqq)), 2.2250738585072014e-308)) {
+            const double th = (aqq - app) / (2.0 * apq);
+            const double t = copysign(1.0, th) / (fabs(th) + sqrt(th * th + 1.0));
+            c = 1.0 / sqrt(t * t + 1.0);
+            sn = t * c;
+            s.flag = 1;
+          }
+        }
+        s.rot_p[i] = p;
+        s.rot_q[i] = q;
+        s.rot_c[i] = c;
+        s.rot_s[i] = sn;
+      }
+      __syncthreads();
+      // columns p, q of A and V
+      for (int e = threadIdx.x; e < m * np; e += NT) {
+        const int x = e / np, i = e % np;
+        const int p = s.rot_p[i], q = s.rot_q[i];
+        const double sn = s.rot_s[i];
+        if (sn == 0.0 || q >= m) continue;
+        const double c = s.rot_c[i];
+        const double ap = s.A[x * TMAX + p], aq = s.A[x * TMAX + q];
+        s.A[x * TMAX + p] = c * ap - sn * aq;
+        s.A[x * TMAX + q] = sn * ap + c * aq;
+        const double vp = s.V[x * TMAX + p], vq = s.V[x * TMAX + q];
+        s.V[x * TMAX + p] = c * vp - sn * vq;
+        s.V[x * TMAX + q] = sn * vp + c * vq;
+      }
+      __syncthreads();
+      // rows p, q of A
+      for (int e = threadIdx.x; e < np * m; e += NT) {
+        const int i = e / m, y = e % m;
+        const int p = s.rot_p[i], q = s.rot_q[i];
+        const double sn = s.rot_s[i];
+        if (sn == 0.0 || q >= m) continue;
+        const double c = s.rot_c[i];
+        const double rp = s.A[p * TMAX + y], rq = s.A[q * TMAX + y];
+        s.A[p * TMAX + y] = c * rp - sn * rq;
+        s.A[q * TMAX + y] = sn * rp + c * rq;
+      }
+      __syncthreads();
+      if (threadIdx.x < np) {
+        const int i = threadIdx.x;
+        if (s.rot_s[i] != 0.0 && s.rot_q[i] < m) {
+          s.A[s.rot_p[i] * TMAX + s.rot_q[i]] = 0.0;
+          s.A[s.rot_q[i] * TMAX + s.rot_p[i]] = 0.0;
+        }
+      }
+      __syncthreads();
+    }
+    if (s.flag == 0) break;
+    __syncthreads();
+  }
+  // order by eigenvalue, largest first (ties: lower index first)
+  for (int i = threadIdx.x; i < m; i += NT) {
+    const double li = s.A[i * TMAX + i];
+    int rank = 0;
+    for (int j = 0; j < m; ++j) {
+      const double lj = s.A[j * TMAX + j];
+      rank += (lj > li || (lj == li && j < i)) ? 1 : 0;
+    }
+    s.perm[rank] = i;
+  }
+  __syncthreads();
+}
+
+// Sign rule on the T x k columns held in Y: the entry of largest magnitude
+// (first one on a tie) becomes positive.
+template <int TMAX, int KMAX>
+__device__ void sign_fix(OiSmem<TMAX, KMAX>& s, int T, int k) {
+  for (int j = threadIdx.x; j < k; j += NT) {
+    int im = 0;
+    double vm = -1.0;
+    for (int t = 0; t < T; ++t) {
+      const double a = fabs(s.Y[t * KMAX + j]);
+      if (a > vm) {
+        vm = a;
+        im = t;
+      }
+    }
+    if (s.Y[im * KMAX + j] < 0.0)
+      for (int t = 0; t < T; ++t) s.Y[t * KMAX + j] = -s.Y[t * KMAX + j];
+  }
+  __syncthreads();
+}
+
+// ||R Q - Q (Q^T R Q)||_F / ||R||_F with Y = R Q already computed; leaves
+// H = Q^T Y (symmetrised) in A.
+template <int TMAX, int KMAX>
+__device__ double residual_and_H(OiSmem<TMAX, KMAX>& s, int T, int k, double normR) {
+  for (int e = threadIdx.x; e < k * k; e += NT) {
+    const int a = e / k, b = e % k;
+    double h = 0.0;
+    for (int t = 0; t < T; ++t) h = fma(s.Q[t * KMAX + a], s.Y[t * KMAX + b], h);
+    s.A[a * TMAX + b] = h;
+  }
+  __syncthreads();
+  double ss = 0.0;
+  for (int e = threadIdx.x; e < T * k; e += NT) {
+    const int t = e / k, b = e % k;
+    double v = s.Y[t * KMAX + b];
+    for (int a = 0; a < k; ++a) v -= s.Q[t * KMAX + a] * s.A[a * TMAX + b];
+    ss += v * v;
+  }
+  const double res = block_sum(ss, s.red);
+  for (int e = threadIdx.x; e < k * k; e += NT) {
+    const int a = e / k, b = e % k;
+    if (b > a) {
+      const double h = 0.5 * (s.A[a * TMAX + b] + s.A[b * TMAX + a]);
+      s.A[a * TMAX + b] = h;
+      s.A[b * TMAX + a] = h;
+    }
+  }
+  __syncthreads();
+  return normR > 0.0 ? sqrt(res) / normR : 0.0;
+}
+
+template <typename Real>
+__device__ inline uint16_t quant(double y, double lo, double hi, int bits) {
+#pragma clang fp contract(off)
+  const double levels = (double)((1 << bits) - 1);
+  if (hi == lo) return 0;
+  const double sc = levels / (hi - lo);
+  const double t = (y - lo) * sc;
+  double q = floor(t + 0.5);
+  q = fmin(levels, fmax(0.0, q));
+  return (uint16_t)q;
+}
+
+__device__ inline double dequant(uint16_t code, double lo, double hi, int bits) {
+#pragma clang fp contract(off)
+  const double levels = (double)((1 << bits) - 1);
+  const double step = (hi - lo) / levels;
+  return lo + (double)code * step;
+}
+
+template <int TMAX, int KMAX, typename Real>
+__global__ void __launch_bounds__(NT) k_oi(OiArgs a) {
+  __shared__ OiSmem<TMAX, KMAX> s;
+  const int c = blockIdx.x;  // coordinate
+  const int T = a.T, k = a.k;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < TMAX * KMAX; e += NT) {
+    s.Q[e] = 0.0;
+    s.Y[e] = 0.0;
+  }
+  __syncthreads();
+  for (int w = 0; w < a.nw; ++w) {
+    // ---- load R_c of window w (zero padded) ----
+    const double* Rg = a.R + ((size_t)w * 3 + c) * T * T;
+    for (int e = tid; e < TMAX * TMAX; e += NT) {
+      const int i = e / TMAX, j = e % TMAX;
+      s.R[e] = (i < T && j < T) ? Rg[i * T + j] : 0.0;
+    }
+    __syncthreads();
+    double part = 0.0;
+    for (int e = tid; e < T * T; e += NT) part += Rg[e] * Rg[e];
+    const double normR = sqrt(block_sum(part, s.red));
+
+    int sweeps = 0, repairs = 0;
+    double resid = 0.0;
+    const bool exact = (w == 0 && a.q_start == nullptr);
+    if (exact) {
+      // Algorithm 1, line 1: eigenvectors of R (Eq. 5)
+      for (int e = tid; e < TMAX * TMAX; e += NT) s.A[e] = s.R[e];
+      __syncthreads();
+      jacobi(s, T);
+      for (int e = tid; e < T * k; e += NT) {
+        const int t = e / k, j = e % k;
+        s.Y[t * KMAX + j] = s.V[t * TMAX + s.perm[j]];
+      }
+      __syncthreads();
+      sign_fix(s, T, k);
+      for (int e = tid; e < T * k; e += NT) s.Q[(e / k) * KMAX + e % k] = s.Y[(e / k) * KMAX + e % k];
+      __syncthreads();
+      mm_RQ(s, T, k);
+      resid = residual_and_H(s, T, k, normR);
+      // canonical U = Q (already sorted and sign-fixed); keep it in Y
+      for (int e = tid; e < T * k; e += NT) s.Y[(e / k) * KMAX + e % k] = s.Q[(e / k) * KMAX + e % k];
+      __syncthreads();
+    } else {
+      if (w == 0) {
+        const Real* q0 = (const Real*)a.q_start + (size_t)c * T * k;
+        for (int e = tid; e < T * k; e += NT) s.Q[(e / k) * KMAX + e % k] = (double)q0[e];
+        __syncthreads();
+      }
+      // Algorithm 1, line 3: start from the previous block (held in Q)
+      repairs += orthonormalise(s, s.Q, T, k) ? 1 : 0;
+      mm_RQ(s, T, k);
+      for (int sw = 1; sw <= a.max_sweeps; ++sw) {
+        // Algorithm 1, line 5: U^(t) = QR(R U^(t-1))
+        repairs += orthonormalise(s, s.Y, T, k) ? 1 : 0;
+        mm_RQ(s, T, k);
+        sweeps = sw;
+        resid = residual_and_H(s, T, k, normR);
+        if (resid <= a.tol) break;
+      }
+      // Rayleigh-Ritz: H = Q^T R Q = V diag(mu) V^T, U = Q V (sorted)
+      jacobi(s, k);
+      for (int e = tid; e < T * k; e += NT) {
+        const int t = e / k, j = e % k;
+        const int pj = s.perm[j];
+        double u = 0.0;
+        for (int p = 0; p < k; ++p) u = fma(s.Q[t * KMAX + p], s.V[p * TMAX + pj], u);
+        s.Y[t * KMAX + j] = u;
+      }
+      __syncthreads();
+      sign_fix(s, T, k);
+    }
+    // ---- outputs: U, dictionary codes, dequantised dictionary ----
+    Real* uo = a.u_out ? (Real*)a.u_out + ((size_t)w * 3 + c) * T * k : nullptr;
+    double* ut = a.u_tilde + ((size_t)w * 3 + c) * T * k;
+    uint8_t* rec = a.records + (size_t)w * a.rec_bytes + a.off_dict;
+    for (int e = tid; e < T * k; e += NT) {
+      const double u = s.Y[(e / k) * KMAX + e % k];
+      if (uo) uo[e] = (Real)u;
+      if (a.dict_bits > 0) {
+        const uint16_t code = quant<Real>(u, -1.0, 1.0, a.dict_bits);
+        ((uint16_t*)rec)[(size_t)c * T * k + e] = code;
+        ut[e] = dequant(code, -1.0, 1.0, a.dict_bits);
+      } else {
+        ((Real*)rec)[(size_t)c * T * k + e] = (Real)u;
+        ut[e] = (double)(Real)u;
+      }
+    }
+    // the next window starts from this window's U_k
+    for (int e = tid; e < T * k; e += NT) s.Q[(e / k) * KMAX + e % k] = s.Y[(e / k) * KMAX + e % k];
+    __syncthreads();
+    if (tid == 0 && a.stats) {
+      a.stats[w].sweeps[c] = sweeps;
+      a.stats[w].shifts[c] = repairs;
+      a.stats[w].resid[c] = resid;
+    }
+  }
+}
+
+}  // namespace
+
+void launch_oi(hipStream_t st, const OiArgs& a) {
+  prof::begin(st, DMC_KERNEL_OI);
+  if (a.T <= 32) {
+    if (a.precision == DMC_FP64)
+      hipLaunchKernelGGL((k_oi<32, 32, double>), dim3(3), dim3(NT), 0, st, a);
+    else
+      hipLaunchKernelGGL((k_oi<32, 32, float>), dim3(3), dim3(NT), 0, st, a);
+  } else {
+    if (a.precision == DMC_FP64)
+      hipLaunchKernelGGL((k_oi<64, 32, double>), dim3(3), dim3(NT), 0, st, a);
+    else
+      hipLaunchKernelGGL((k_oi<64, 32, float>), dim3(3), dim3(NT), 0, st, a);
+  }
+  prof::end(st, DMC_KERNEL_OI);
+}
+
+}  // namespace dmc

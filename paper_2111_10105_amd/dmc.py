@@ -1,0 +1,364 @@
+"""Thin ctypes binding of libdmc.so (include/dmc.h).
+
+Argument marshalling only: every step of encode and decode runs in the HIP
+library.  Device buffers are torch tensors on the GPU (torch is used for device
+memory and streams); the library receives their raw pointers and the current
+torch stream.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdmc.so")
+
+DMC_OK = 0
+STATUS = {0: "OK", 1: "INVALID_ARG", 2: "OUT_OF_MEMORY", 3: "DEVICE", 4: "NOT_CONVERGED",
+          5: "SINGULAR", 6: "BUFFER_TOO_SMALL", 7: "UNSUPPORTED"}
+FP64, FP32 = 0, 1
+LAP_UNIFORM, LAP_COMBINATORIAL = 0, 1
+PRECOND_NONE, PRECOND_JACOBI, PRECOND_CHOLESKY = 0, 1, 2
+
+EXPORTS = ["dmc_create", "dmc_destroy", "dmc_set_stream", "dmc_last_error", "dmc_scratch_bytes",
+           "dmc_mesh_create", "dmc_mesh_destroy", "dmc_mesh_nnz", "dmc_mesh_normal_nnz",
+           "dmc_mesh_factor_info", "dmc_host_normal_solve",
+           "dmc_window_code_bytes", "dmc_sequence_code_bytes", "dmc_encode_window",
+           "dmc_decode_window", "dmc_compress_sequence", "dmc_decode_sequence", "dmc_delta",
+           "dmc_autocorrelation", "dmc_profile_start", "dmc_profile_stop"]
+
+KERNELS = ["delta", "autocorr", "oi", "project", "quantise", "anchors", "back_project", "rhs",
+           "cg_spmm", "cg_update", "chol_fwd_gather", "chol_fwd_solve", "chol_bwd_gather",
+           "chol_bwd_solve", "to_frames"]
+
+
+class DmcError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"dmc error {STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int32), ("coef_bits", ctypes.c_int32),
+                ("anchor_bits", ctypes.c_int32), ("dict_bits", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("oi_max_sweeps", ctypes.c_int32),
+                ("oi_tol", ctypes.c_double), ("cg_max_iters", ctypes.c_int32),
+                ("precond", ctypes.c_int32), ("cg_tol", ctypes.c_double)]
+
+
+class WindowStats(ctypes.Structure):
+    _fields_ = [("T", ctypes.c_int32), ("k", ctypes.c_int32),
+                ("oi_sweeps", ctypes.c_int32 * 3), ("oi_resid", ctypes.c_double * 3),
+                ("chol_shifts", ctypes.c_int32 * 3), ("cg_iters", ctypes.c_int32),
+                ("cg_resid", ctypes.c_double)]
+
+    def as_dict(self):
+        return {"T": self.T, "k": self.k, "oi_sweeps": list(self.oi_sweeps),
+                "oi_resid": list(self.oi_resid), "chol_shifts": list(self.chol_shifts),
+                "cg_iters": self.cg_iters, "cg_resid": self.cg_resid}
+
+
+def make_params(k, coef_bits=12, anchor_bits=16, dict_bits=16, precision=FP32,
+                oi_max_sweeps=200, oi_tol=None, cg_max_iters=None, precond=PRECOND_CHOLESKY,
+                cg_tol=None) -> Params:
+    if oi_tol is None:
+        oi_tol = 1e-12
+    if cg_tol is None:
+        cg_tol = 1e-12
+    if cg_max_iters is None:
+        cg_max_iters = 50 if precond == PRECOND_CHOLESKY else 20000
+    return Params(k, coef_bits, anchor_bits, dict_bits, precision, oi_max_sweeps, float(oi_tol),
+                  cg_max_iters, precond, float(cg_tol))
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built (there is no
+    fallback implementation)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -c 'import __graft_entry__ as g; g.build()'`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, sz, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t, ctypes.c_double
+    P = ctypes.POINTER(Params)
+    S = ctypes.POINTER(WindowStats)
+    sig = {
+        "dmc_create": (i32, [i32, vp, ctypes.POINTER(vp)]),
+        "dmc_destroy": (None, [vp]),
+        "dmc_set_stream": (i32, [vp, vp]),
+        "dmc_last_error": (ctypes.c_char_p, []),
+        "dmc_scratch_bytes": (sz, [vp]),
+        "dmc_mesh_create": (i32, [vp, i32, i32, vp, i32, vp, i32, ctypes.POINTER(vp)]),
+        "dmc_mesh_destroy": (None, [vp]),
+        "dmc_mesh_nnz": (i32, [vp]),
+        "dmc_mesh_normal_nnz": (i32, [vp]),
+        "dmc_mesh_factor_info": (None, [vp, ctypes.POINTER(dbl)]),
+        "dmc_host_normal_solve": (i32, [i32, i32, vp, i32, vp, i32, i32, vp, vp,
+                                        ctypes.POINTER(dbl)]),
+        "dmc_window_code_bytes": (sz, [i32, i32, i32, P]),
+        "dmc_sequence_code_bytes": (sz, [i32, i32, i32, i32, P]),
+        "dmc_encode_window": (i32, [vp, vp, vp, i32, P, vp, vp, vp, vp, S]),
+        "dmc_decode_window": (i32, [vp, vp, vp, i32, P, vp, S]),
+        "dmc_compress_sequence": (i32, [vp, vp, vp, i32, i32, P, vp, vp, sz, vp, S]),
+        "dmc_decode_sequence": (i32, [vp, vp, vp, i32, i32, P, vp, S]),
+        "dmc_delta": (i32, [vp, vp, vp, i32, i32, vp]),
+        "dmc_autocorrelation": (i32, [vp, vp, vp, i32, i32, vp]),
+        "dmc_profile_start": (i32, [i32]),
+        "dmc_profile_stop": (i32, [ctypes.POINTER(i32), ctypes.POINTER(dbl)]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(status: int, allow=()):
+    if status != DMC_OK and status not in allow:
+        raise DmcError(status, lib().dmc_last_error().decode())
+    return status
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _real(precision):
+    import torch
+    return torch.float64 if precision == FP64 else torch.float32
+
+
+class Context:
+    def __init__(self, device: int = 0):
+        import torch
+        torch.cuda.set_device(device)
+        h = ctypes.c_void_p()
+        _check(lib().dmc_create(device, _stream(), ctypes.byref(h)))
+        self.h = h
+        self.device = device
+
+    def sync_stream(self):
+        _check(lib().dmc_set_stream(self.h, _stream()))
+
+    @property
+    def scratch_bytes(self) -> int:
+        return lib().dmc_scratch_bytes(self.h)
+
+    def close(self):
+        if self.h:
+            lib().dmc_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Mesh:
+    def __init__(self, ctx: Context, n: int, tris, anchors, laplacian: int = LAP_UNIFORM):
+        tris = np.ascontiguousarray(tris, dtype=np.int32)
+        anchors = np.ascontiguousarray(anchors, dtype=np.int32)
+        h = ctypes.c_void_p()
+        _check(lib().dmc_mesh_create(ctx.h, int(n), int(tris.shape[0]),
+                                     tris.ctypes.data_as(ctypes.c_void_p), int(anchors.size),
+                                     anchors.ctypes.data_as(ctypes.c_void_p), int(laplacian),
+                                     ctypes.byref(h)))
+        self.h, self.ctx, self.n, self.nc = h, ctx, int(n), int(anchors.size)
+        self.anchors = anchors
+
+    @property
+    def nnz(self):
+        return lib().dmc_mesh_nnz(self.h)
+
+    @property
+    def normal_nnz(self):
+        return lib().dmc_mesh_normal_nnz(self.h)
+
+    def factor_info(self) -> dict:
+        a = (ctypes.c_double * 6)()
+        lib().dmc_mesh_factor_info(self.h, a)
+        return dict(zip(FACTOR_INFO_KEYS, list(a)))
+
+
+FACTOR_INFO_KEYS = ("stored", "nnz_exact", "supernodes", "levels", "flops", "seconds")
+
+
+def host_normal_solve(n, tris, anchors, B, laplacian: int = LAP_UNIFORM):
+    """Solve (L^T L + I_N^T I_N) X = B on the host with the library's own
+    ordering, factorisation and blocked triangular solves (no GPU)."""
+    tris = np.ascontiguousarray(tris, dtype=np.int32)
+    anchors = np.ascontiguousarray(anchors, dtype=np.int32)
+    B = np.ascontiguousarray(B, dtype=np.float64)
+    if B.ndim == 1:
+        B = B[:, None]
+    X = np.empty_like(B)
+    info = (ctypes.c_double * 6)()
+    _check(lib().dmc_host_normal_solve(int(n), int(tris.shape[0]), tris.ctypes.data_as(ctypes.c_void_p),
+                                       int(anchors.size), anchors.ctypes.data_as(ctypes.c_void_p),
+                                       int(laplacian), int(B.shape[1]),
+                                       B.ctypes.data_as(ctypes.c_void_p),
+                                       X.ctypes.data_as(ctypes.c_void_p), info))
+    return X, dict(zip(FACTOR_INFO_KEYS, list(info)))
+
+
+def window_code_bytes(n, T, nc, params: Params) -> int:
+    return lib().dmc_window_code_bytes(n, T, nc, ctypes.byref(params))
+
+
+def sequence_code_bytes(n, F, T, nc, params: Params) -> int:
+    return lib().dmc_sequence_code_bytes(n, F, T, nc, ctypes.byref(params))
+
+
+def encode_window(ctx: Context, mesh: Mesh, frames, params: Params, q_start=None,
+                  want_u: bool = True, want_coef: bool = False, stats: bool = True):
+    """frames: CUDA tensor [T][n][3].  Returns a dict with the record (uint8
+    tensor), U_k [3][T][k], coefficients [3][k][n] (if asked) and stats."""
+    import torch
+    T = frames.shape[0]
+    dev = frames.device
+    ctx.sync_stream()
+    code = torch.empty(window_code_bytes(mesh.n, T, mesh.nc, params), dtype=torch.uint8, device=dev)
+    k = min(params.k, T)
+    u = torch.empty((3, T, k), dtype=frames.dtype, device=dev) if want_u else None
+    coef = torch.empty((3, k, mesh.n), dtype=frames.dtype, device=dev) if want_coef else None
+    st = WindowStats()
+    status = lib().dmc_encode_window(ctx.h, mesh.h, _ptr(frames), T, ctypes.byref(params),
+                                     _ptr(q_start), _ptr(code), _ptr(u), _ptr(coef),
+                                     ctypes.byref(st) if stats else None)
+    _check(status, allow=(4,))
+    return {"code": code, "u": u, "coef": coef, "stats": st.as_dict() if stats else None,
+            "status": status}
+
+
+def decode_window(ctx: Context, mesh: Mesh, code, T: int, params: Params, dtype=None):
+    import torch
+    ctx.sync_stream()
+    out = torch.empty((T, mesh.n, 3), dtype=dtype or _real(params.precision), device=code.device)
+    st = WindowStats()
+    status = lib().dmc_decode_window(ctx.h, mesh.h, _ptr(code), T, ctypes.byref(params),
+                                     _ptr(out), ctypes.byref(st))
+    _check(status, allow=(4,))
+    return out, st.as_dict(), status
+
+
+def compress_sequence(ctx: Context, mesh: Mesh, frames, T: int, params: Params, q_start=None,
+                      decode: bool = True, stats: bool = True, codes=None, out=None):
+    """Encode (and decode) a whole sequence [F][n][3].  Returns (codes, frames
+    or None, per-window stats list, status)."""
+    import torch
+    F = frames.shape[0]
+    ctx.sync_stream()
+    nbytes = sequence_code_bytes(mesh.n, F, T, mesh.nc, params)
+    if codes is None:
+        codes = torch.empty(nbytes, dtype=torch.uint8, device=frames.device)
+    if decode and out is None:
+        out = torch.empty_like(frames)
+    nw = (F + T - 1) // T
+    sts = (WindowStats * nw)() if stats else None
+    status = lib().dmc_compress_sequence(ctx.h, mesh.h, _ptr(frames), F, T, ctypes.byref(params),
+                                         _ptr(q_start), _ptr(codes), nbytes,
+                                         _ptr(out) if decode else None, sts)
+    _check(status, allow=(4,))
+    return codes, (out if decode else None), ([s.as_dict() for s in sts] if stats else None), status
+
+
+def decode_sequence(ctx: Context, mesh: Mesh, codes, F: int, T: int, params: Params, out=None):
+    import torch
+    ctx.sync_stream()
+    if out is None:
+        out = torch.empty((F, mesh.n, 3), dtype=_real(params.precision), device=codes.device)
+    nw = (F + T - 1) // T
+    sts = (WindowStats * nw)()
+    status = lib().dmc_decode_sequence(ctx.h, mesh.h, _ptr(codes), F, T, ctypes.byref(params),
+                                       _ptr(out), sts)
+    _check(status, allow=(4,))
+    return out, [s.as_dict() for s in sts], status
+
+
+def delta(ctx: Context, mesh: Mesh, frames, precision: int):
+    import torch
+    ctx.sync_stream()
+    out = torch.empty_like(frames)
+    _check(lib().dmc_delta(ctx.h, mesh.h, _ptr(frames), frames.shape[0], precision, _ptr(out)))
+    return out
+
+
+def autocorrelation(ctx: Context, mesh: Mesh, frames, precision: int):
+    import torch
+    ctx.sync_stream()
+    T = frames.shape[0]
+    R = torch.empty((3, T, T), dtype=torch.float64, device=frames.device)
+    _check(lib().dmc_autocorrelation(ctx.h, mesh.h, _ptr(frames), T, precision, _ptr(R)))
+    return R
+
+
+def profile_start(kernel: str):
+    """Time every launch of one kernel family with HIP events from now on."""
+    _check(lib().dmc_profile_start(KERNELS.index(kernel)))
+
+
+def profile_stop():
+    """(launches, total milliseconds) of the selected kernel family."""
+    n = ctypes.c_int32()
+    ms = ctypes.c_double()
+    _check(lib().dmc_profile_stop(ctypes.byref(n), ctypes.byref(ms)))
+    return n.value, ms.value
+
+
+# ---- record parsing (host side, for inspection and tests) --------------------
+
+def _align(x, a=256):
+    return (x + a - 1) // a * a
+
+
+@dataclass
+class RecordView:
+    header: np.ndarray
+    dict_codes: np.ndarray      # [3][T][k] uint16 or raw
+    ranges: np.ndarray | None   # [3][k][2] float32
+    codes: np.ndarray           # [3][k][n] uint16 or raw
+    anchor_range: np.ndarray | None  # [3][2] float32
+    anchor_codes: np.ndarray    # [3][T][nc] uint16 or raw
+
+
+def parse_record(buf: np.ndarray, n: int, T: int, nc: int, params: Params) -> RecordView:
+    """Split one record (bytes copied to the host) into its sections; mirrors
+    the layout documented in dmc.h."""
+    buf = np.asarray(buf, dtype=np.uint8)
+    k = min(params.k, T)
+    real = np.float64 if params.precision == FP64 else np.float32
+    rs = np.dtype(real).itemsize
+    off = _align(64)
+    hdr = buf[:64].view(np.int32)
+
+    def take(count, dt):
+        nonlocal off
+        nbytes = count * np.dtype(dt).itemsize
+        arr = buf[off:off + nbytes].view(dt)
+        off += _align(nbytes)
+        return arr
+
+    dct = take(3 * T * k, np.uint16 if params.dict_bits > 0 else real).reshape(3, T, k)
+    rng = take(3 * k * 2, np.float32).reshape(3, k, 2)
+    cod = take(3 * k * n, np.uint16 if params.coef_bits > 0 else real).reshape(3, k, n)
+    arg = take(3 * 2, np.float32).reshape(3, 2)
+    anc = take(3 * T * nc, np.uint16 if params.anchor_bits > 0 else real).reshape(3, T, nc)
+    del rs
+    return RecordView(hdr, dct, rng if params.coef_bits > 0 else None, cod,
+                      arg if params.anchor_bits > 0 else None, anc)
