@@ -71,7 +71,7 @@ def main():
     torch.cuda.synchronize()
 
     # dominant kernel: timed live with HIP events over the timed region
-    prof_kernel = args.profile_kernel or "chol_bwd_gather"
+    prof_kernel = args.profile_kernel or "chol_bwd_solve"
     dmc.profile_start(prof_kernel)
     torch.cuda.synchronize()
     t0 = time.perf_counter()

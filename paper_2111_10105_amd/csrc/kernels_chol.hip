@@ -12,10 +12,9 @@
 //   backward, top level downwards
 //     gemm   : X_s = B_s^T [Y_s; -X_(R_s below the diagonal block)],
 //              z[perm rows of s] = X_s
-// Work items are (supernode, 64-row tile) x 64-column tiles: each wave owns 16
-// consecutive rows of one 64-column slice and keeps them in registers, so each
-// vector load of W, Y or X feeds 16 FMAs and the operator entries are
-// wave-uniform scalar loads.
+// Work items are (supernode, 64-row tile) x 64-column tiles.  The two GEMMs
+// stage 32-deep K slices of B_s and of the right-hand rows in LDS and run on
+// the FP64 matrix cores; the gather is one load per update row.
 #include "dmc_internal.h"
 
 namespace dmc {
@@ -40,96 +39,197 @@ k_fwd_gather(CholDev f, int t0, int ncols, const double* __restrict__ rhs,
     const int j = a + t;
     double acc = rhs[(size_t)f.perm[j] * ncols + c];
     const int e1 = f.contrib_ptr[j + 1];
-    for (int e = f.contrib_ptr[j]; e < e1; ++e) acc -= U[(size_t)f.contrib_slot[e] * ncols + c];
-    W[(size_t)j * ncols + c] = acc;
+    int e = f.contrib_ptr[j];
+    // four independent partial sums keep several loads in flight
+    double a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    for (; e + 4 <= e1; e += 4) {
+      acc -= U[(size_t)f.contrib_slot[e] * ncols + c];
+      a1 -= U[(size_t)f.contrib_slot[e + 1] * ncols + c];
+      a2 -= U[(size_t)f.contrib_slot[e + 2] * ncols + c];
+      a3 -= U[(size_t)f.contrib_slot[e + 3] * ncols + c];
+    }
+    for (; e < e1; ++e) acc -= U[(size_t)f.contrib_slot[e] * ncols + c];
+    W[(size_t)j * ncols + c] = (acc + a1) + (a2 + a3);
   }
 }
 
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int KC = 32;       // K chunk staged in LDS
+constexpr int LDA = KC + 1;  // padded LDS strides
+constexpr int LDB = CT + 1;
+
+// One 64 x 64 output tile per block on the FP64 matrix cores: wave v owns the
+// 32 x 32 quadrant (v / 2, v % 2) as 2 x 2 tiles of v_mfma_f64_16x16x4f64
+// (lane l supplies A[l%16][l/16] and B[l/16][l%16]; component r of lane l is
+// D[4r + l/16][l%16]).
+struct MfmaTile {
+  d4 acc[2][2];
+  __device__ void zero() {
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+  }
+  __device__ void step(const double* As, const double* Bs, int wr, int wc, int lane) {
+#pragma unroll
+    for (int kk = 0; kk < KC; kk += 4) {
+      double af[2], bf[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) af[a] = As[(wr * 32 + a * 16 + lane % 16) * LDA + kk + lane / 16];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) bf[b] = Bs[(kk + lane / 16) * LDB + wc * 32 + b * 16 + lane % 16];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
+    }
+  }
+};
+
+// Elements of a 64 x 32 (A) and 32 x 64 (B) chunk staged per thread.
+constexpr int PER_T = RT * KC / kBlock;  // 8
+
+// forward: [Y_s; U_s] rows r0..r0+63 = B_s W_s (K = columns of B_s; rows of the
+// diagonal block only need the lower triangle of inv(L_ss)).  Two LDS stages:
+// the global loads of chunk j+1 are in flight while chunk j is multiplied.
 __global__ void __launch_bounds__(kBlock)
 k_fwd_gemm(CholDev f, int t0, int ncols, const double* __restrict__ W, double* __restrict__ Y,
            double* __restrict__ U) {
+  __shared__ double As[2][RT * LDA];
+  __shared__ double Bs[2][KC * LDB];
   const int task = t0 + blockIdx.x;
   const int s = f.task_m_sn[task], r0 = f.task_m_r0[task];
-  const int c = blockIdx.y * CT + threadIdx.x % CT;
-  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
-  if (c >= ncols) return;
+  const int c0 = blockIdx.y * CT;
   const int a = f.sn_start[s], w = f.sn_start[s + 1] - a;
   const int m = f.sn_rowptr[s + 1] - f.sn_rowptr[s];
-  const int i0 = r0 + wv * RPW;
-  if (i0 >= m) return;
-  const double* Bc = f.bcol + f.sn_valptr[s];
-  double acc[RPW];
+  const double* Br = f.brow + f.sn_valptr[s];
+  const int tid = threadIdx.x, lane = tid % 64, wv = tid / 64;
+  const int wr = wv / 2, wc = wv % 2;
+  const int qend = r0 + RT <= w ? r0 + RT : w;
+  double ra[PER_T], rb[PER_T];
+  auto load = [&](int q0) {
 #pragma unroll
-  for (int k = 0; k < RPW; ++k) acc[k] = 0.0;
-  const double* Wc = W + (size_t)a * ncols + c;
-  // rows inside the diagonal block use only the lower triangle of inv(L_ss)
-  const int qend = i0 + RPW <= w ? i0 + RPW : w;
-  if (i0 + RPW <= m) {
-    for (int q = 0; q < qend; ++q) {
-      const double x = Wc[(size_t)q * ncols];
-      const double* bq = Bc + (size_t)q * m + i0;
-#pragma unroll
-      for (int k = 0; k < RPW; ++k) acc[k] = fma(bq[k], x, acc[k]);
+    for (int u = 0; u < PER_T; ++u) {
+      const int e = tid + u * kBlock;
+      const int ii = e / KC, qq = e % KC;
+      const int i = r0 + ii, q = q0 + qq;
+      ra[u] = (i < m && q < qend) ? Br[(size_t)i * w + q] : 0.0;
+      const int q2 = e / CT, cc = e % CT;
+      const int qb = q0 + q2, c = c0 + cc;
+      rb[u] = (qb < qend && c < ncols) ? W[(size_t)(a + qb) * ncols + c] : 0.0;
     }
-  } else {
-    for (int q = 0; q < qend; ++q) {
-      const double x = Wc[(size_t)q * ncols];
-      const double* bq = Bc + (size_t)q * m + i0;
+  };
+  auto store = [&](int st) {
 #pragma unroll
-      for (int k = 0; k < RPW; ++k)
-        if (i0 + k < m) acc[k] = fma(bq[k], x, acc[k]);
+    for (int u = 0; u < PER_T; ++u) {
+      const int e = tid + u * kBlock;
+      As[st][(e / KC) * LDA + e % KC] = ra[u];
+      Bs[st][(e / CT) * LDB + e % CT] = rb[u];
     }
+  };
+  MfmaTile t;
+  t.zero();
+  int st = 0;
+  if (qend > 0) {
+    load(0);
+    store(0);
+  }
+  __syncthreads();
+  for (int q0 = 0; q0 < qend; q0 += KC) {
+    const bool more = q0 + KC < qend;
+    if (more) load(q0 + KC);
+    t.step(As[st], Bs[st], wr, wc, lane);
+    if (more) store(st ^ 1);
+    __syncthreads();
+    st ^= 1;
   }
   const int64_t sb = f.slot_base[s];
 #pragma unroll
-  for (int k = 0; k < RPW; ++k) {
-    const int i = i0 + k;
-    if (i >= m) break;
-    if (i < w)
-      Y[(size_t)(a + i) * ncols + c] = acc[k];
-    else
-      U[(size_t)(sb + i - w) * ncols + c] = acc[k];
-  }
+  for (int ta = 0; ta < 2; ++ta)
+#pragma unroll
+    for (int tb = 0; tb < 2; ++tb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = r0 + wr * 32 + ta * 16 + 4 * r + lane / 16;
+        const int c = c0 + wc * 32 + tb * 16 + lane % 16;
+        if (i >= m || c >= ncols) continue;
+        const double v = t.acc[ta][tb][r];
+        if (i < w)
+          Y[(size_t)(a + i) * ncols + c] = v;
+        else
+          U[(size_t)(sb + i - w) * ncols + c] = v;
+      }
 }
 
+// backward: X_s rows t0..t0+63 = B_s^T [Y_s; -X_(R_s below the diagonal block)]
+// (K = rows of B_s from t0 on: inv(L_ss) is lower triangular), two LDS stages
 __global__ void __launch_bounds__(kBlock)
 k_bwd_gemm(CholDev f, int t0, int ncols, const double* __restrict__ Y, double* __restrict__ X,
            double* __restrict__ z) {
+  __shared__ double As[2][RT * LDA];
+  __shared__ double Bs[2][KC * LDB];
   const int task = t0 + blockIdx.x;
   const int s = f.task_w_sn[task], r0 = f.task_w_r0[task];
-  const int c = blockIdx.y * CT + threadIdx.x % CT;
-  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
-  if (c >= ncols) return;
+  const int c0 = blockIdx.y * CT;
   const int a = f.sn_start[s], w = f.sn_start[s + 1] - a;
-  const int rb = f.sn_rowptr[s], m = f.sn_rowptr[s + 1] - rb;
-  const int t0w = r0 + wv * RPW;
-  if (t0w >= w) return;
+  const int rb0 = f.sn_rowptr[s], m = f.sn_rowptr[s + 1] - rb0;
   const double* Br = f.brow + f.sn_valptr[s];
-  double acc[RPW];
+  const int tid = threadIdx.x, lane = tid % 64, wv = tid / 64;
+  const int wr = wv / 2, wc = wv % 2;
+  double ra[PER_T], rb[PER_T];
+  auto load = [&](int i0) {
 #pragma unroll
-  for (int k = 0; k < RPW; ++k) acc[k] = 0.0;
-  const bool full = t0w + RPW <= w;
-  // rows of B_s^T: inverse part (i < w; zero for i < t) then the update part
-  for (int i = t0w; i < m; ++i) {
-    const double v = i < w ? Y[(size_t)(a + i) * ncols + c]
-                           : -X[(size_t)f.rowidx[rb + i] * ncols + c];
-    const double* bi = Br + (size_t)i * w + t0w;
-    if (full) {
-#pragma unroll
-      for (int k = 0; k < RPW; ++k) acc[k] = fma(bi[k], v, acc[k]);
-    } else {
-#pragma unroll
-      for (int k = 0; k < RPW; ++k)
-        if (t0w + k < w) acc[k] = fma(bi[k], v, acc[k]);
+    for (int u = 0; u < PER_T; ++u) {
+      const int e = tid + u * kBlock;
+      // A operand: As[tt][ii] = B_s[i0 + ii][r0 + tt] (transposed while staging)
+      const int ii = e / RT, tt = e % RT;
+      const int i = i0 + ii, tc = r0 + tt;
+      ra[u] = (i < m && tc < w) ? Br[(size_t)i * w + tc] : 0.0;
+      const int i2 = e / CT, cc = e % CT;
+      const int ib = i0 + i2, c = c0 + cc;
+      double v = 0.0;
+      if (ib < m && c < ncols)
+        v = ib < w ? Y[(size_t)(a + ib) * ncols + c] : -X[(size_t)f.rowidx[rb0 + ib] * ncols + c];
+      rb[u] = v;
     }
+  };
+  auto store = [&](int st) {
+#pragma unroll
+    for (int u = 0; u < PER_T; ++u) {
+      const int e = tid + u * kBlock;
+      As[st][(e % RT) * LDA + e / RT] = ra[u];
+      Bs[st][(e / CT) * LDB + e % CT] = rb[u];
+    }
+  };
+  MfmaTile t;
+  t.zero();
+  int st = 0;
+  load(r0);
+  store(0);
+  __syncthreads();
+  for (int i0 = r0; i0 < m; i0 += KC) {
+    const bool more = i0 + KC < m;
+    if (more) load(i0 + KC);
+    t.step(As[st], Bs[st], wr, wc, lane);
+    if (more) store(st ^ 1);
+    __syncthreads();
+    st ^= 1;
   }
 #pragma unroll
-  for (int k = 0; k < RPW; ++k) {
-    const int t = t0w + k;
-    if (t >= w) break;
-    X[(size_t)(a + t) * ncols + c] = acc[k];
-    z[(size_t)f.perm[a + t] * ncols + c] = acc[k];
-  }
+  for (int ta = 0; ta < 2; ++ta)
+#pragma unroll
+    for (int tb = 0; tb < 2; ++tb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int tr = r0 + wr * 32 + ta * 16 + 4 * r + lane / 16;
+        const int c = c0 + wc * 32 + tb * 16 + lane % 16;
+        if (tr >= w || c >= ncols) continue;
+        const double v = t.acc[ta][tb][r];
+        X[(size_t)(a + tr) * ncols + c] = v;
+        z[(size_t)f.perm[a + tr] * ncols + c] = v;
+      }
 }
 
 }  // namespace

@@ -46,8 +46,9 @@ template <typename Real>
 __global__ void __launch_bounds__(kBlock)
 k_back_project(const uint8_t* __restrict__ records, SeqLayout sl, int n, int ncols,
                double* __restrict__ B0) {
-  __shared__ double Ut[3 * 64 * 32];
-  __shared__ double Yh[BP_V * 3 * 32];
+  // padded strides (k + 1, 33) keep lanes on different LDS banks
+  __shared__ double Ut[3 * 64 * 33];
+  __shared__ double Yh[BP_V * 3 * 33];
   const int w = blockIdx.y;
   const uint8_t* rec;
   int T, k, t0;
@@ -57,11 +58,13 @@ k_back_project(const uint8_t* __restrict__ records, SeqLayout sl, int n, int nco
   const int nv = min(BP_V, n - i0);
   // dictionary
   const int db = lay->dict_bits;
+  const int ku = k + 1;
   for (int e = threadIdx.x; e < 3 * T * k; e += kBlock) {
+    const int row = e / k, r = e % k;  // row = c * T + t
     if (db > 0)
-      Ut[e] = dequant(((const uint16_t*)(rec + lay->off_dict))[e], -1.0, 1.0, db);
+      Ut[row * ku + r] = dequant(((const uint16_t*)(rec + lay->off_dict))[e], -1.0, 1.0, db);
     else
-      Ut[e] = (double)((const Real*)(rec + lay->off_dict))[e];
+      Ut[row * ku + r] = (double)((const Real*)(rec + lay->off_dict))[e];
   }
   // coefficients of this block's vertices: Yh[v][c][r]
   const int cb = lay->coef_bits;
@@ -76,15 +79,15 @@ k_back_project(const uint8_t* __restrict__ records, SeqLayout sl, int n, int nco
     } else {
       y = (double)((const Real*)(rec + lay->off_codes))[idx];
     }
-    Yh[(v * 3 + c) * 32 + r] = y;
+    Yh[(v * 3 + c) * 33 + r] = y;
   }
   __syncthreads();
   const int wcols = 3 * T;
   for (int e = threadIdx.x; e < nv * wcols; e += kBlock) {
     const int v = e / wcols, j = e % wcols;
     const int t = j / 3, c = j % 3;
-    const double* u = Ut + (c * T + t) * k;
-    const double* y = Yh + (v * 3 + c) * 32;
+    const double* u = Ut + (c * T + t) * ku;
+    const double* y = Yh + (v * 3 + c) * 33;
     double s = 0.0;
     for (int r = 0; r < k; ++r) s = fma(u[r], y[r], s);
     B0[(size_t)(i0 + v) * ncols + 3 * t0 + j] = s;
@@ -169,16 +172,35 @@ k_cg_init(const double* __restrict__ b, const double* __restrict__ dinv, int pre
   part[(nrb + blockIdx.x) * ncols + j] = rz;
 }
 
-__global__ void k_cg_init_reduce(const double* __restrict__ part, int nrb, int ncols,
-                                 double* __restrict__ bnorm2, double* __restrict__ rz,
-                                 int32_t* __restrict__ done, double* __restrict__ resid) {
-  const int j = blockIdx.x * kBlock + threadIdx.x;
-  if (j >= ncols) return;
-  double bb = 0.0, z = 0.0;
-  for (int q = 0; q < nrb; ++q) {
-    bb += part[(size_t)q * ncols + j];
-    z += part[((size_t)nrb + q) * ncols + j];
-  }
+// Column sums of the per-block partials part[h][q][j] (h = 0, 1 selects the
+// first or second half) by a block of 64 columns x 4 groups: group g adds the
+// partials q = g, g + 4, ... and the four group sums are combined in a fixed
+// order, so the result does not depend on scheduling.
+constexpr int RED_COLS = 64, RED_GROUPS = kBlock / RED_COLS;
+
+__device__ inline double column_sum(const double* __restrict__ part, int nrb, int ncols, int half,
+                                    int j, double* sh) {
+  const int g = threadIdx.x / RED_COLS, lc = threadIdx.x % RED_COLS;
+  double acc = 0.0;
+  if (j < ncols)
+    for (int q = g; q < nrb; q += RED_GROUPS) acc += part[((size_t)half * nrb + q) * ncols + j];
+  sh[g * RED_COLS + lc] = acc;
+  __syncthreads();
+  double tot = 0.0;
+  for (int h = 0; h < RED_GROUPS; ++h) tot += sh[h * RED_COLS + lc];
+  __syncthreads();
+  return tot;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_cg_init_reduce(const double* __restrict__ part, int nrb, int ncols,
+                 double* __restrict__ bnorm2, double* __restrict__ rz,
+                 int32_t* __restrict__ done, double* __restrict__ resid) {
+  __shared__ double sh[kBlock];
+  const int j = blockIdx.x * RED_COLS + threadIdx.x % RED_COLS;
+  const double bb = column_sum(part, nrb, ncols, 0, j, sh);
+  const double z = column_sum(part, nrb, ncols, 1, j, sh);
+  if (j >= ncols || threadIdx.x >= RED_COLS) return;
   bnorm2[j] = bb;
   rz[j] = z;
   done[j] = bb == 0.0 ? 1 : 0;
@@ -203,13 +225,14 @@ k_cg_spmm(const int32_t* __restrict__ mrow, const int32_t* __restrict__ mcol,
   part[(size_t)blockIdx.x * ncols + j] = pq;
 }
 
-__global__ void k_cg_alpha(const double* __restrict__ part, int nrb, int ncols,
-                           const double* __restrict__ rz, const int32_t* __restrict__ done,
-                           double* __restrict__ alpha) {
-  const int j = blockIdx.x * kBlock + threadIdx.x;
-  if (j >= ncols) return;
-  double pq = 0.0;
-  for (int q = 0; q < nrb; ++q) pq += part[(size_t)q * ncols + j];
+__global__ void __launch_bounds__(kBlock)
+k_cg_alpha(const double* __restrict__ part, int nrb, int ncols,
+           const double* __restrict__ rz, const int32_t* __restrict__ done,
+           double* __restrict__ alpha) {
+  __shared__ double sh[kBlock];
+  const int j = blockIdx.x * RED_COLS + threadIdx.x % RED_COLS;
+  const double pq = column_sum(part, nrb, ncols, 0, j, sh);
+  if (j >= ncols || threadIdx.x >= RED_COLS) return;
   alpha[j] = (done[j] || pq == 0.0) ? 0.0 : rz[j] / pq;
 }
 
@@ -260,32 +283,34 @@ k_copy(size_t count, const double* __restrict__ src, double* __restrict__ dst) {
 }
 
 // relative residual per column from the r.r partials; marks converged columns
-__global__ void k_cg_resid(const double* __restrict__ part, int nrb, int ncols,
-                           const double* __restrict__ bnorm2, int32_t* __restrict__ done,
-                           double* __restrict__ resid, double tol) {
-  const int j = blockIdx.x * kBlock + threadIdx.x;
-  if (j >= ncols) return;
+__global__ void __launch_bounds__(kBlock)
+k_cg_resid(const double* __restrict__ part, int nrb, int ncols,
+           const double* __restrict__ bnorm2, int32_t* __restrict__ done,
+           double* __restrict__ resid, double tol) {
+  __shared__ double sh[kBlock];
+  const int j = blockIdx.x * RED_COLS + threadIdx.x % RED_COLS;
+  const double rr = column_sum(part, nrb, ncols, 0, j, sh);
+  if (j >= ncols || threadIdx.x >= RED_COLS) return;
   if (done[j]) return;
-  double rr = 0.0;
-  for (int q = 0; q < nrb; ++q) rr += part[(size_t)q * ncols + j];
   const double res = bnorm2[j] > 0.0 ? sqrt(rr / bnorm2[j]) : 0.0;
   resid[j] = res;
   if (res <= tol) done[j] = 2;  // converged in this iteration
 }
 
 // beta = (r.z)_new / (r.z)_old from the r.z partials (zero for converged columns)
-__global__ void k_cg_beta(const double* __restrict__ part, int nrb, int ncols,
-                          double* __restrict__ rz, int32_t* __restrict__ done,
-                          double* __restrict__ beta) {
-  const int j = blockIdx.x * kBlock + threadIdx.x;
-  if (j >= ncols) return;
+__global__ void __launch_bounds__(kBlock)
+k_cg_beta(const double* __restrict__ part, int nrb, int ncols,
+          double* __restrict__ rz, int32_t* __restrict__ done,
+          double* __restrict__ beta) {
+  __shared__ double sh[kBlock];
+  const int j = blockIdx.x * RED_COLS + threadIdx.x % RED_COLS;
+  const double z = column_sum(part, nrb, ncols, 1, j, sh);
+  if (j >= ncols || threadIdx.x >= RED_COLS) return;
   if (done[j]) {
     done[j] = 1;
     beta[j] = 0.0;
     return;
   }
-  double z = 0.0;
-  for (int q = 0; q < nrb; ++q) z += part[((size_t)nrb + q) * ncols + j];
   beta[j] = rz[j] != 0.0 ? z / rz[j] : 0.0;
   rz[j] = z;
 }
@@ -385,7 +410,7 @@ void launch_cg_init(hipStream_t s, const MeshDev& m, int32_t ncols, const double
     hipLaunchKernelGGL(k_copy, dim3(std::min<size_t>(4096, (count + kBlock - 1) / kBlock)),
                        dim3(kBlock), 0, s, count, (const double*)cb.z, cb.p);
   }
-  hipLaunchKernelGGL(k_cg_init_reduce, dim3((ncols + kBlock - 1) / kBlock), dim3(kBlock), 0, s,
+  hipLaunchKernelGGL(k_cg_init_reduce, dim3((ncols + RED_COLS - 1) / RED_COLS), dim3(kBlock), 0, s,
                      cb.part, nrb, ncols, cb.bnorm2, cb.rz, cb.done, cb.resid);
 }
 
@@ -393,7 +418,7 @@ void launch_cg_step_a(hipStream_t s, const MeshDev& m, int32_t ncols, const CgBu
                       int32_t precond, double tol) {
   const int nrb = (int)cg_part_rows(m.n);
   dim3 grid(nrb, (ncols + kBlock - 1) / kBlock);
-  dim3 cgrid((ncols + kBlock - 1) / kBlock);
+  dim3 cgrid((ncols + RED_COLS - 1) / RED_COLS);
   prof::begin(s, DMC_KERNEL_CG_SPMM);
   hipLaunchKernelGGL(k_cg_spmm, grid, dim3(kBlock), 0, s, m.m_rowptr, m.m_col, m.m_val, m.n,
                      ncols, cb.p, cb.q, cb.part);
@@ -412,7 +437,7 @@ void launch_cg_step_b(hipStream_t s, const MeshDev& m, int32_t ncols, const CgBu
                       int32_t precond) {
   const int nrb = (int)cg_part_rows(m.n);
   dim3 grid(nrb, (ncols + kBlock - 1) / kBlock);
-  dim3 cgrid((ncols + kBlock - 1) / kBlock);
+  dim3 cgrid((ncols + RED_COLS - 1) / RED_COLS);
   if (precond == DMC_PRECOND_CHOLESKY) launch_precond_apply(s, m, ncols, cb);
   hipLaunchKernelGGL(k_cg_beta, cgrid, dim3(kBlock), 0, s, cb.part, nrb, ncols, cb.rz, cb.done,
                      cb.beta);

@@ -1,11 +1,16 @@
 // Orthogonal iterations (Algorithm 1) with a Rayleigh-Ritz step and the
-// dictionary quantiser, for a chain of windows, on one workgroup per
-// coordinate.  Everything lives in LDS in float64:
+// dictionary quantiser, for a chain of windows, on one wavefront per
+// coordinate (the problem is T <= 64 rows: one lane per row, and a workgroup
+// barrier of a single wave costs only the wait for its own LDS traffic).
+// Everything lives in LDS in float64:
 //   C.Q products on the FP64 matrix cores (v_mfma_f64_16x16x4f64),
-//   thin QR by CholeskyQR2 (Gram accumulated in float64, k x k Cholesky);
-//   a pivot breakdown switches that sweep to shifted CholeskyQR3, and a second
-//   breakdown (an exactly rank-deficient block) to Gram-Schmidt run twice with
-//   completion of the missing directions from the identity;
+//   thin QR by CholeskyQR2 on column-scaled blocks (the columns of R Q differ in
+//   norm by the eigenvalue spread, which column scaling removes without
+//   changing the Q factor), Gram accumulated in float64, k x k Cholesky,
+//   wavefront-shuffle reductions; a pivot breakdown switches that sweep to
+//   shifted CholeskyQR3, and a second breakdown (an exactly rank-deficient
+//   block) to Gram-Schmidt run twice with completion of the missing
+//   directions from the identity;
 //   eigenvectors of the k x k Ritz matrix (and of the full T x T matrix for an
 //   exact start, Eq. 5) by parallel cyclic Jacobi.
 #include "dmc_internal.h"
@@ -15,15 +20,19 @@ namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-constexpr int NT = 256;  // threads per workgroup (4 waves)
+constexpr int NT = 64;  // threads per workgroup: one wavefront
 
+// Row strides are padded to an odd number of doubles so that the lanes of a
+// wavefront walking down one column hit different LDS banks.
 template <int TMAX, int KMAX>
 struct OiSmem {
-  double R[TMAX * TMAX];
-  double A[TMAX * TMAX];   // Jacobi work matrix; Gram / Cholesky factor; Ritz H
-  double V[TMAX * TMAX];   // Jacobi eigenvectors
-  double Q[TMAX * KMAX];   // orthonormal block (rows >= T, cols >= k kept zero)
-  double Y[TMAX * KMAX];   // R Q, or the canonical U
+  static constexpr int LR = TMAX + 1;  // stride of R, A, V
+  static constexpr int LQ = KMAX + 1;  // stride of Q, Y
+  double R[TMAX * LR];
+  double A[TMAX * LR];   // Jacobi work matrix; Gram / Cholesky factor; Ritz H
+  double V[TMAX * LR];   // Jacobi eigenvectors
+  double Q[TMAX * LQ];   // orthonormal block (rows >= T, cols >= k kept zero)
+  double Y[TMAX * LQ];   // R Q, or the canonical U
   double red[NT];
   double rot_c[TMAX / 2 + 1], rot_s[TMAX / 2 + 1];
   int rot_p[TMAX / 2 + 1], rot_q[TMAX / 2 + 1];
@@ -32,35 +41,24 @@ struct OiSmem {
   int ok;
 };
 
-__device__ inline double block_sum(double v, double* red) {
-  red[threadIdx.x] = v;
-  __syncthreads();
-  for (int s = NT / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-    __syncthreads();
-  }
-  double r = red[0];
-  __syncthreads();
-  return r;
+// sums / maxima over the wavefront (the whole workgroup), result in every lane
+__device__ __forceinline__ double block_sum(double v, double* /*red*/) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
 }
 
-__device__ inline double block_max(double v, double* red) {
-  red[threadIdx.x] = v;
-  __syncthreads();
-  for (int s = NT / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
-    __syncthreads();
-  }
-  double r = red[0];
-  __syncthreads();
-  return r;
+__device__ __forceinline__ double block_max(double v, double* /*red*/) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+  return v;
 }
 
 // Y = R Q (T x k) on the FP64 matrix cores.  Operand layouts of
 // v_mfma_f64_16x16x4f64: lane l holds A[l%16][l/16] and B[l/16][l%16]; result
 // element (4*r + l/16, l%16) is component r of lane l.
 template <int TMAX, int KMAX>
-__device__ void mm_RQ(OiSmem<TMAX, KMAX>& s, int T, int k) {
+__device__ __forceinline__ void mm_RQ(OiSmem<TMAX, KMAX>& s, int T, int k) {
   const int Tp = (T + 15) & ~15, kp = (k + 15) & ~15;
   const int ti_n = Tp / 16, tj_n = kp / 16;
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
@@ -68,13 +66,13 @@ __device__ void mm_RQ(OiSmem<TMAX, KMAX>& s, int T, int k) {
     const int ti = tile / tj_n, tj = tile % tj_n;
     d4 acc = {0.0, 0.0, 0.0, 0.0};
     for (int kk = 0; kk < Tp; kk += 4) {
-      const double a = s.R[(ti * 16 + lane % 16) * TMAX + kk + lane / 16];
-      const double b = s.Q[(kk + lane / 16) * KMAX + tj * 16 + lane % 16];
+      const double a = s.R[(ti * 16 + lane % 16) * s.LR + kk + lane / 16];
+      const double b = s.Q[(kk + lane / 16) * s.LQ + tj * 16 + lane % 16];
       acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
     }
     for (int r = 0; r < 4; ++r) {
       const int row = ti * 16 + 4 * r + lane / 16, col = tj * 16 + lane % 16;
-      s.Y[row * KMAX + col] = acc[r];
+      s.Y[row * s.LQ + col] = acc[r];
     }
   }
   __syncthreads();
@@ -82,14 +80,14 @@ __device__ void mm_RQ(OiSmem<TMAX, KMAX>& s, int T, int k) {
 
 // A[0:k,0:k] = X^T X for X = Q or Y (T x k).
 template <int TMAX, int KMAX>
-__device__ void gram(OiSmem<TMAX, KMAX>& s, const double* X, int T, int k) {
+__device__ __forceinline__ void gram(OiSmem<TMAX, KMAX>& s, const double* X, int T, int k) {
   for (int e = threadIdx.x; e < k * k; e += NT) {
     const int a = e / k, b = e % k;
     if (b > a) continue;
     double g = 0.0;
-    for (int t = 0; t < T; ++t) g = fma(X[t * KMAX + a], X[t * KMAX + b], g);
-    s.A[a * TMAX + b] = g;
-    s.A[b * TMAX + a] = g;
+    for (int t = 0; t < T; ++t) g = fma(X[t * s.LQ + a], X[t * s.LQ + b], g);
+    s.A[a * s.LR + b] = g;
+    s.A[b * s.LR + a] = g;
   }
   __syncthreads();
 }
@@ -97,33 +95,33 @@ __device__ void gram(OiSmem<TMAX, KMAX>& s, const double* X, int T, int k) {
 // In-place Cholesky of A[0:k,0:k] (+ shift on the diagonal); lower factor.
 // Sets s.ok = 0 on a pivot <= rel_tol * max diagonal.
 template <int TMAX, int KMAX>
-__device__ void cholesky(OiSmem<TMAX, KMAX>& s, int k, double shift) {
+__device__ __forceinline__ void cholesky(OiSmem<TMAX, KMAX>& s, int k, double shift) {
   if (threadIdx.x == 0) s.ok = 1;
   double dmax = 0.0;
-  for (int j = 0; j < k; ++j) dmax = fmax(dmax, s.A[j * TMAX + j]);
+  for (int j = 0; j < k; ++j) dmax = fmax(dmax, s.A[j * s.LR + j]);
   __syncthreads();
   if (shift != 0.0)
-    for (int j = threadIdx.x; j < k; j += NT) s.A[j * TMAX + j] += shift;
+    for (int j = threadIdx.x; j < k; j += NT) s.A[j * s.LR + j] += shift;
   __syncthreads();
   const double thresh = 1e-15 * dmax;
   for (int j = 0; j < k; ++j) {
     if (threadIdx.x == 0) {
-      const double d = s.A[j * TMAX + j];
+      const double d = s.A[j * s.LR + j];
       if (!(d > thresh)) {
         s.ok = 0;
-        s.A[j * TMAX + j] = 1.0;
+        s.A[j * s.LR + j] = 1.0;
       } else {
-        s.A[j * TMAX + j] = sqrt(d);
+        s.A[j * s.LR + j] = sqrt(d);
       }
     }
     __syncthreads();
-    const double ljj = s.A[j * TMAX + j];
-    for (int i = j + 1 + threadIdx.x; i < k; i += NT) s.A[i * TMAX + j] /= ljj;
+    const double ljj = s.A[j * s.LR + j];
+    for (int i = j + 1 + threadIdx.x; i < k; i += NT) s.A[i * s.LR + j] /= ljj;
     __syncthreads();
     const int m = k - j - 1;
     for (int e = threadIdx.x; e < m * m; e += NT) {
       const int i = j + 1 + e / m, l = j + 1 + e % m;
-      if (l <= i) s.A[i * TMAX + l] -= s.A[i * TMAX + j] * s.A[l * TMAX + j];
+      if (l <= i) s.A[i * s.LR + l] -= s.A[i * s.LR + j] * s.A[l * s.LR + j];
     }
     __syncthreads();
   }
@@ -131,12 +129,12 @@ __device__ void cholesky(OiSmem<TMAX, KMAX>& s, int k, double shift) {
 
 // Q = X L^{-T} row by row (forward substitution); X may alias Q.
 template <int TMAX, int KMAX>
-__device__ void tri_solve(OiSmem<TMAX, KMAX>& s, const double* X, int T, int k) {
+__device__ __forceinline__ void tri_solve(OiSmem<TMAX, KMAX>& s, const double* X, int T, int k) {
   for (int t = threadIdx.x; t < T; t += NT) {
     for (int j = 0; j < k; ++j) {
-      double v = X[t * KMAX + j];
-      for (int p = 0; p < j; ++p) v -= s.Q[t * KMAX + p] * s.A[j * TMAX + p];
-      s.Q[t * KMAX + j] = v / s.A[j * TMAX + j];
+      double v = X[t * s.LQ + j];
+      for (int p = 0; p < j; ++p) v -= s.Q[t * s.LQ + p] * s.A[j * s.LR + p];
+      s.Q[t * s.LQ + j] = v / s.A[j * s.LR + j];
     }
   }
   __syncthreads();
@@ -146,24 +144,24 @@ __device__ void tri_solve(OiSmem<TMAX, KMAX>& s, const double* X, int T, int k) 
 // Q in place; a column with no component left is replaced by the identity
 // direction e_m with the largest part outside the span found so far.
 template <int TMAX, int KMAX>
-__device__ void gram_schmidt(OiSmem<TMAX, KMAX>& s, int T, int k) {
+__device__ __forceinline__ void gram_schmidt(OiSmem<TMAX, KMAX>& s, int T, int k) {
   for (int j = 0; j < k; ++j) {
-    const double n0 = sqrt(block_sum(threadIdx.x < T ? s.Q[threadIdx.x * KMAX + j] *
-                                                           s.Q[threadIdx.x * KMAX + j]
+    const double n0 = sqrt(block_sum(threadIdx.x < T ? s.Q[threadIdx.x * s.LQ + j] *
+                                                           s.Q[threadIdx.x * s.LQ + j]
                                                      : 0.0,
                                      s.red));
     for (int pass = 0; pass < 2; ++pass) {
       for (int p = 0; p < j; ++p) {
-        const double d = block_sum(threadIdx.x < T ? s.Q[threadIdx.x * KMAX + p] *
-                                                         s.Q[threadIdx.x * KMAX + j]
+        const double d = block_sum(threadIdx.x < T ? s.Q[threadIdx.x * s.LQ + p] *
+                                                         s.Q[threadIdx.x * s.LQ + j]
                                                    : 0.0,
                                    s.red);
-        if (threadIdx.x < T) s.Q[threadIdx.x * KMAX + j] -= d * s.Q[threadIdx.x * KMAX + p];
+        if (threadIdx.x < T) s.Q[threadIdx.x * s.LQ + j] -= d * s.Q[threadIdx.x * s.LQ + p];
         __syncthreads();
       }
     }
-    double nj = sqrt(block_sum(threadIdx.x < T ? s.Q[threadIdx.x * KMAX + j] *
-                                                     s.Q[threadIdx.x * KMAX + j]
+    double nj = sqrt(block_sum(threadIdx.x < T ? s.Q[threadIdx.x * s.LQ + j] *
+                                                     s.Q[threadIdx.x * s.LQ + j]
                                                : 0.0,
                                s.red));
     if (!(nj > 1e-10 * n0) || n0 == 0.0) {
@@ -172,31 +170,31 @@ __device__ void gram_schmidt(OiSmem<TMAX, KMAX>& s, int T, int k) {
       int bm = 0;
       for (int m = 0; m < T; ++m) {
         double out = 1.0;
-        for (int p = 0; p < j; ++p) out -= s.Q[m * KMAX + p] * s.Q[m * KMAX + p];
+        for (int p = 0; p < j; ++p) out -= s.Q[m * s.LQ + p] * s.Q[m * s.LQ + p];
         if (out > best) {
           best = out;
           bm = m;
         }
       }
       __syncthreads();
-      if (threadIdx.x < T) s.Q[threadIdx.x * KMAX + j] = threadIdx.x == bm ? 1.0 : 0.0;
+      if (threadIdx.x < T) s.Q[threadIdx.x * s.LQ + j] = threadIdx.x == bm ? 1.0 : 0.0;
       __syncthreads();
       for (int pass = 0; pass < 2; ++pass) {
         for (int p = 0; p < j; ++p) {
-          const double d = block_sum(threadIdx.x < T ? s.Q[threadIdx.x * KMAX + p] *
-                                                           s.Q[threadIdx.x * KMAX + j]
+          const double d = block_sum(threadIdx.x < T ? s.Q[threadIdx.x * s.LQ + p] *
+                                                           s.Q[threadIdx.x * s.LQ + j]
                                                      : 0.0,
                                      s.red);
-          if (threadIdx.x < T) s.Q[threadIdx.x * KMAX + j] -= d * s.Q[threadIdx.x * KMAX + p];
+          if (threadIdx.x < T) s.Q[threadIdx.x * s.LQ + j] -= d * s.Q[threadIdx.x * s.LQ + p];
           __syncthreads();
         }
       }
-      nj = sqrt(block_sum(threadIdx.x < T ? s.Q[threadIdx.x * KMAX + j] *
-                                                s.Q[threadIdx.x * KMAX + j]
+      nj = sqrt(block_sum(threadIdx.x < T ? s.Q[threadIdx.x * s.LQ + j] *
+                                                s.Q[threadIdx.x * s.LQ + j]
                                           : 0.0,
                           s.red));
     }
-    if (threadIdx.x < T) s.Q[threadIdx.x * KMAX + j] /= nj;
+    if (threadIdx.x < T) s.Q[threadIdx.x * s.LQ + j] /= nj;
     __syncthreads();
   }
 }
@@ -204,38 +202,41 @@ __device__ void gram_schmidt(OiSmem<TMAX, KMAX>& s, int T, int k) {
 // Q = orthonormal basis of span(X) (X = Y or Q, T x k).  Returns the number of
 // breakdown repairs (0: plain CholeskyQR2).
 template <int TMAX, int KMAX>
-__device__ int orthonormalise(OiSmem<TMAX, KMAX>& s, const double* X, int T, int k) {
-  int repairs = 0;
-  gram(s, X, T, k);
-  double tr = 0.0;
-  for (int j = 0; j < k; ++j) tr += s.A[j * TMAX + j];
+__device__ __forceinline__ int orthonormalise(OiSmem<TMAX, KMAX>& s, const double* X, int T, int k) {
+  // column scaling: Q = X D^-1 with unit columns (same Q factor); an exactly
+  // zero column is replaced by completion from the identity below
+  int zero_cols = 0;
+  for (int j = 0; j < k; ++j) {
+    const double x = threadIdx.x < T ? X[threadIdx.x * s.LQ + j] : 0.0;
+    const double nrm = sqrt(block_sum(x * x, s.red));
+    if (threadIdx.x < T) s.Q[threadIdx.x * s.LQ + j] = nrm > 0.0 ? x / nrm : 0.0;
+    zero_cols += nrm > 0.0 ? 0 : 1;
+  }
   __syncthreads();
-  if (tr == 0.0) {
-    // nothing to orthonormalise: complete from the identity
-    for (int e = threadIdx.x; e < T * k; e += NT) s.Q[(e / k) * KMAX + e % k] = 0.0;
-    __syncthreads();
+  if (zero_cols) {
     gram_schmidt(s, T, k);
     return 1;
   }
+  int repairs = 0;
+  gram(s, s.Q, T, k);
+  double tr = 0.0;
+  for (int j = 0; j < k; ++j) tr += s.A[j * s.LR + j];
+  __syncthreads();
   cholesky(s, k, 0.0);
   int passes = 2;
   if (!s.ok) {
     // shifted CholeskyQR (Fukaya et al.): shift 11 (T k + k (k + 1)) u ||X||^2
     repairs = 1;
     passes = 3;
-    gram(s, X, T, k);
+    gram(s, s.Q, T, k);
     const double shift = 11.0 * (double)(T * k + k * (k + 1)) * 1.1102230246251565e-16 * tr;
     cholesky(s, k, shift);
     if (!s.ok) {
-      if (X != s.Q)
-        for (int e = threadIdx.x; e < T * k; e += NT)
-          s.Q[(e / k) * KMAX + e % k] = X[(e / k) * KMAX + e % k];
-      __syncthreads();
       gram_schmidt(s, T, k);
       return 2;
     }
   }
-  tri_solve(s, X, T, k);
+  tri_solve(s, s.Q, T, k);
   for (int pass = 1; pass < passes; ++pass) {
     gram(s, s.Q, T, k);
     cholesky(s, k, 0.0);
@@ -250,17 +251,33 @@ __device__ int orthonormalise(OiSmem<TMAX, KMAX>& s, const double* X, int T, int
 
 // Parallel cyclic Jacobi on the m x m symmetric matrix in A (round-robin
 // pairing, every pair zeroed once per sweep); eigenvectors accumulate in V.
-// A pair is skipped when |A_pq| <= eps sqrt(|A_pp A_qq|); stops after a sweep
-// with no rotation.
+// A pair is skipped when |A_pq| <= max(eps sqrt(|A_pp A_qq|), eps ||A||_F)
+// (below one ulp of the matrix a rotation changes nothing the matrix
+// determines); stops after a sweep with no rotation.  General-size version,
+// with the matrices in LDS (used for m > 32).  In each round the rotations are disjoint, so A J and V J
+// are done by rows (a thread owns row x and updates its entries in columns p, q
+// of every pair) and J^T (A J) by columns; each thread issues all loads of a
+// batch before its stores, so the LDS latency is paid once per batch.
 template <int TMAX, int KMAX>
-__device__ void jacobi(OiSmem<TMAX, KMAX>& s, int m) {
+__device__ __forceinline__ void jacobi(OiSmem<TMAX, KMAX>& s, int m) {
+  const int LR = s.LR;
   for (int e = threadIdx.x; e < m * m; e += NT)
-    s.V[(e / m) * TMAX + e % m] = (e / m == e % m) ? 1.0 : 0.0;
+    s.V[(e / m) * LR + e % m] = (e / m == e % m) ? 1.0 : 0.0;
   __syncthreads();
-  if (m < 2) return;
+  if (m < 2) {
+    if (threadIdx.x == 0) s.perm[0] = 0;
+    __syncthreads();
+    return;
+  }
   const int me = m + (m & 1);
   const int np = me / 2;
   const double eps = 2.220446049250313e-16;
+  double fro = 0.0;
+  for (int e = threadIdx.x; e < m * m; e += NT) {
+    const double v = s.A[(e / m) * LR + e % m];
+    fro += v * v;
+  }
+  const double floor_abs = eps * sqrt(block_sum(fro, s.red));
   for (int sweep = 0; sweep < 60; ++sweep) {
     if (threadIdx.x == 0) s.flag = 0;
     __syncthreads();
@@ -278,9 +295,9 @@ __device__ void jacobi(OiSmem<TMAX, KMAX>& s, int m) {
         const int p = a < b ? a : b, q = a < b ? b : a;
         double c = 1.0, sn = 0.0;
         if (q < m) {
-          const double apq = s.A[p * TMAX + q];
-          const double app = s.A[p * TMAX + p], aqq = s.A[q * TMAX + q];
-          if (fabs(apq) > fmax(eps * sqrt(fabs(app * aqq)), 2.2250738585072014e-308)) {
+          const double apq = s.A[p * LR + q];
+          const double app = s.A[p * LR + p], aqq = s.A[q * LR + q];
+          if (fabs(apq) > fmax(eps * sqrt(fabs(app * aqq)), floor_abs) && apq != 0.0) {
             const double th = (aqq - app) / (2.0 * apq);
             const double t = copysign(1.0, th) / (fabs(th) + sqrt(th * th + 1.0));
             c = 1.0 / sqrt(t * t + 1.0);
@@ -289,44 +306,36 @@ __device__ void jacobi(OiSmem<TMAX, KMAX>& s, int m) {
           }
         }
         s.rot_p[i] = p;
-        s.rot_q[i] = q;
+        s.rot_q[i] = q < m ? q : p;
         s.rot_c[i] = c;
         s.rot_s[i] = sn;
       }
       __syncthreads();
-      // columns p, q of A and V
+      // A <- A J and V <- V J
       for (int e = threadIdx.x; e < m * np; e += NT) {
         const int x = e / np, i = e % np;
-        const int p = s.rot_p[i], q = s.rot_q[i];
         const double sn = s.rot_s[i];
-        if (sn == 0.0 || q >= m) continue;
+        if (sn == 0.0) continue;
+        const int p = s.rot_p[i], q = s.rot_q[i];
         const double c = s.rot_c[i];
-        const double ap = s.A[x * TMAX + p], aq = s.A[x * TMAX + q];
-        s.A[x * TMAX + p] = c * ap - sn * aq;
-        s.A[x * TMAX + q] = sn * ap + c * aq;
-        const double vp = s.V[x * TMAX + p], vq = s.V[x * TMAX + q];
-        s.V[x * TMAX + p] = c * vp - sn * vq;
-        s.V[x * TMAX + q] = sn * vp + c * vq;
+        const double ap = s.A[x * LR + p], aq = s.A[x * LR + q];
+        s.A[x * LR + p] = c * ap - sn * aq;
+        s.A[x * LR + q] = sn * ap + c * aq;
+        const double vp = s.V[x * LR + p], vq = s.V[x * LR + q];
+        s.V[x * LR + p] = c * vp - sn * vq;
+        s.V[x * LR + q] = sn * vp + c * vq;
       }
       __syncthreads();
-      // rows p, q of A
+      // A <- J^T A; the rotated pair's own off-diagonal entries become zero
       for (int e = threadIdx.x; e < np * m; e += NT) {
         const int i = e / m, y = e % m;
-        const int p = s.rot_p[i], q = s.rot_q[i];
         const double sn = s.rot_s[i];
-        if (sn == 0.0 || q >= m) continue;
+        if (sn == 0.0) continue;
+        const int p = s.rot_p[i], q = s.rot_q[i];
         const double c = s.rot_c[i];
-        const double rp = s.A[p * TMAX + y], rq = s.A[q * TMAX + y];
-        s.A[p * TMAX + y] = c * rp - sn * rq;
-        s.A[q * TMAX + y] = sn * rp + c * rq;
-      }
-      __syncthreads();
-      if (threadIdx.x < np) {
-        const int i = threadIdx.x;
-        if (s.rot_s[i] != 0.0 && s.rot_q[i] < m) {
-          s.A[s.rot_p[i] * TMAX + s.rot_q[i]] = 0.0;
-          s.A[s.rot_q[i] * TMAX + s.rot_p[i]] = 0.0;
-        }
+        const double rp = s.A[p * LR + y], rq = s.A[q * LR + y];
+        s.A[p * LR + y] = (y == q) ? 0.0 : c * rp - sn * rq;
+        s.A[q * LR + y] = (y == p) ? 0.0 : sn * rp + c * rq;
       }
       __syncthreads();
     }
@@ -335,10 +344,10 @@ __device__ void jacobi(OiSmem<TMAX, KMAX>& s, int m) {
   }
   // order by eigenvalue, largest first (ties: lower index first)
   for (int i = threadIdx.x; i < m; i += NT) {
-    const double li = s.A[i * TMAX + i];
+    const double li = s.A[i * LR + i];
     int rank = 0;
     for (int j = 0; j < m; ++j) {
-      const double lj = s.A[j * TMAX + j];
+      const double lj = s.A[j * LR + j];
       rank += (lj > li || (lj == li && j < i)) ? 1 : 0;
     }
     s.perm[rank] = i;
@@ -346,22 +355,161 @@ __device__ void jacobi(OiSmem<TMAX, KMAX>& s, int m) {
   __syncthreads();
 }
 
+
+__device__ __forceinline__ double shfl_f64(double v, int src) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __shfl((int)(b & 0xffffffffLL), src);
+  const int hi = __shfl((int)(b >> 32), src);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Register-resident parallel cyclic Jacobi for m <= M (M = 16 or 32, zero
+// padded to M; padding is never rotated because its off-diagonal entries are
+// exactly zero).  Lane l < 32 holds row l of A, lane 32 + l row l of V; all
+// register indices are constants.  Pairing by the circle method: in every
+// round the slots (k, M - 1 - k) are rotated together, then slot 0 stays and
+// the contents of slots 1..M-1 move one place along a ring (columns: register
+// moves; rows of A: one lane shuffle per entry).  After M - 1 rounds every
+// pair has met once and the slots are back in their original order.
+// Skip rule and ordering as in `jacobi`.
+template <int M, int TMAX, int KMAX>
+__device__ __forceinline__ void jacobi_regs(OiSmem<TMAX, KMAX>& s, int m) {
+  const int LR = s.LR;
+  const int lane = threadIdx.x;
+  const int t = lane & 31;
+  const bool isA = lane < 32;
+  const bool rowA = isA && t < M;
+  double a[M];
+  double fro = 0.0;
+#pragma unroll
+  for (int j = 0; j < M; ++j) {
+    const double v = (t < m && j < m) ? s.A[t * LR + j] : 0.0;
+    a[j] = isA ? v : (t == j ? 1.0 : 0.0);
+    fro += isA ? v * v : 0.0;
+  }
+  const double eps = 2.220446049250313e-16;
+  const double floor_abs = eps * sqrt(block_sum(fro, s.red));
+  const int partner = M - 1 - t;               // pair (t, M - 1 - t)
+  const int pair = t < partner ? t : partner;  // pair index
+  const bool is_p = t < partner;
+  const int prev_lane = t == 0 ? 0 : (t == 1 ? M - 1 : t - 1);  // ring move of rows
+  __syncthreads();
+  int sweeps_done = 0;
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    bool rotated = false;
+    for (int round = 0; round < M - 1; ++round) {
+      // this lane's diagonal and off-diagonal entry with its partner
+      double diag = 0.0, off = 0.0;
+#pragma unroll
+      for (int j = 0; j < M; ++j) {
+        diag = (j == t) ? a[j] : diag;
+        off = (j == partner) ? a[j] : off;
+      }
+      const double dpart = shfl_f64(diag, partner);
+      const double app = is_p ? diag : dpart, aqq = is_p ? dpart : diag;
+      double c = 1.0, sn = 0.0;
+      if (rowA && fabs(off) > fmax(eps * sqrt(fabs(app * aqq)), floor_abs) && off != 0.0) {
+        const double th = (aqq - app) / (2.0 * off);
+        const double tt = copysign(1.0, th) / (fabs(th) + sqrt(th * th + 1.0));
+        c = 1.0 / sqrt(tt * tt + 1.0);
+        sn = tt * c;
+      }
+      const bool any = __any(sn != 0.0);
+      rotated = rotated || any;
+      if (any) {
+        if (rowA && is_p) {
+          s.rot_c[pair] = c;
+          s.rot_s[pair] = sn;
+        }
+        __syncthreads();
+        // A <- A J and V <- V J: lane-local on its row
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int i = 0; i < M / 2; ++i) {
+          const double ci = s.rot_c[i], si = s.rot_s[i];
+          const double xp = a[i], xq = a[M - 1 - i];
+          a[i] = ci * xp - si * xq;
+          a[M - 1 - i] = si * xp + ci * xq;
+          if ((i & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+        }
+        // A <- J^T A: rows p and q combine (partner's row by shuffle)
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+          const double pj = shfl_f64(a[j], partner);
+          if (rowA && sn != 0.0) {
+            const double v = is_p ? c * a[j] - sn * pj : sn * pj + c * a[j];
+            a[j] = (j == partner) ? 0.0 : v;
+          }
+          if ((j & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+        }
+        __syncthreads();
+      }
+      // ring move of the slots: columns (all lanes) and rows (A lanes)
+      {
+        const double last = a[M - 1];
+#pragma unroll
+        for (int j = M - 1; j >= 2; --j) a[j] = a[j - 1];
+        a[1] = last;
+      }
+#pragma unroll
+      for (int j = 0; j < M; ++j) {
+        const double v = shfl_f64(a[j], prev_lane);
+        if (rowA) a[j] = v;
+        if ((j & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+    if (!rotated) {
+      sweeps_done = sweep + 1;
+      break;
+    }
+    sweeps_done = sweep + 1;
+  }
+  if (threadIdx.x == 0) s.flag = sweeps_done;  // sweeps used (for inspection)
+  // write back: diagonal of A, rows of V
+#pragma unroll
+  for (int j = 0; j < M; ++j) {
+    if (isA && t < m && j == t) s.A[t * LR + t] = a[j];
+    if (!isA && t < m && j < m) s.V[t * LR + j] = a[j];
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < m; i += NT) {
+    const double li = s.A[i * LR + i];
+    int rank = 0;
+    for (int j = 0; j < m; ++j) {
+      const double lj = s.A[j * LR + j];
+      rank += (lj > li || (lj == li && j < i)) ? 1 : 0;
+    }
+    s.perm[rank] = i;
+  }
+  __syncthreads();
+}
+
+template <int TMAX, int KMAX>
+__device__ __forceinline__ void eigen_sym(OiSmem<TMAX, KMAX>& s, int m) {
+  if (m <= 16)
+    jacobi_regs<16>(s, m);
+  else if (m <= 32)
+    jacobi_regs<32>(s, m);
+  else
+    jacobi(s, m);
+}
+
 // Sign rule on the T x k columns held in Y: the entry of largest magnitude
 // (first one on a tie) becomes positive.
 template <int TMAX, int KMAX>
-__device__ void sign_fix(OiSmem<TMAX, KMAX>& s, int T, int k) {
+__device__ __forceinline__ void sign_fix(OiSmem<TMAX, KMAX>& s, int T, int k) {
   for (int j = threadIdx.x; j < k; j += NT) {
     int im = 0;
     double vm = -1.0;
     for (int t = 0; t < T; ++t) {
-      const double a = fabs(s.Y[t * KMAX + j]);
+      const double a = fabs(s.Y[t * s.LQ + j]);
       if (a > vm) {
         vm = a;
         im = t;
       }
     }
-    if (s.Y[im * KMAX + j] < 0.0)
-      for (int t = 0; t < T; ++t) s.Y[t * KMAX + j] = -s.Y[t * KMAX + j];
+    if (s.Y[im * s.LQ + j] < 0.0)
+      for (int t = 0; t < T; ++t) s.Y[t * s.LQ + j] = -s.Y[t * s.LQ + j];
   }
   __syncthreads();
 }
@@ -369,28 +517,28 @@ __device__ void sign_fix(OiSmem<TMAX, KMAX>& s, int T, int k) {
 // ||R Q - Q (Q^T R Q)||_F / ||R||_F with Y = R Q already computed; leaves
 // H = Q^T Y (symmetrised) in A.
 template <int TMAX, int KMAX>
-__device__ double residual_and_H(OiSmem<TMAX, KMAX>& s, int T, int k, double normR) {
+__device__ __forceinline__ double residual_and_H(OiSmem<TMAX, KMAX>& s, int T, int k, double normR) {
   for (int e = threadIdx.x; e < k * k; e += NT) {
     const int a = e / k, b = e % k;
     double h = 0.0;
-    for (int t = 0; t < T; ++t) h = fma(s.Q[t * KMAX + a], s.Y[t * KMAX + b], h);
-    s.A[a * TMAX + b] = h;
+    for (int t = 0; t < T; ++t) h = fma(s.Q[t * s.LQ + a], s.Y[t * s.LQ + b], h);
+    s.A[a * s.LR + b] = h;
   }
   __syncthreads();
   double ss = 0.0;
   for (int e = threadIdx.x; e < T * k; e += NT) {
     const int t = e / k, b = e % k;
-    double v = s.Y[t * KMAX + b];
-    for (int a = 0; a < k; ++a) v -= s.Q[t * KMAX + a] * s.A[a * TMAX + b];
+    double v = s.Y[t * s.LQ + b];
+    for (int a = 0; a < k; ++a) v -= s.Q[t * s.LQ + a] * s.A[a * s.LR + b];
     ss += v * v;
   }
   const double res = block_sum(ss, s.red);
   for (int e = threadIdx.x; e < k * k; e += NT) {
     const int a = e / k, b = e % k;
     if (b > a) {
-      const double h = 0.5 * (s.A[a * TMAX + b] + s.A[b * TMAX + a]);
-      s.A[a * TMAX + b] = h;
-      s.A[b * TMAX + a] = h;
+      const double h = 0.5 * (s.A[a * s.LR + b] + s.A[b * s.LR + a]);
+      s.A[a * s.LR + b] = h;
+      s.A[b * s.LR + a] = h;
     }
   }
   __syncthreads();
@@ -398,7 +546,7 @@ __device__ double residual_and_H(OiSmem<TMAX, KMAX>& s, int T, int k, double nor
 }
 
 template <typename Real>
-__device__ inline uint16_t quant(double y, double lo, double hi, int bits) {
+__device__ __forceinline__ uint16_t quant(double y, double lo, double hi, int bits) {
 #pragma clang fp contract(off)
   const double levels = (double)((1 << bits) - 1);
   if (hi == lo) return 0;
@@ -409,7 +557,7 @@ __device__ inline uint16_t quant(double y, double lo, double hi, int bits) {
   return (uint16_t)q;
 }
 
-__device__ inline double dequant(uint16_t code, double lo, double hi, int bits) {
+__device__ __forceinline__ double dequant(uint16_t code, double lo, double hi, int bits) {
 #pragma clang fp contract(off)
   const double levels = (double)((1 << bits) - 1);
   const double step = (hi - lo) / levels;
@@ -422,7 +570,7 @@ __global__ void __launch_bounds__(NT) k_oi(OiArgs a) {
   const int c = blockIdx.x;  // coordinate
   const int T = a.T, k = a.k;
   const int tid = threadIdx.x;
-  for (int e = tid; e < TMAX * KMAX; e += NT) {
+  for (int e = tid; e < TMAX * s.LQ; e += NT) {
     s.Q[e] = 0.0;
     s.Y[e] = 0.0;
   }
@@ -432,7 +580,7 @@ __global__ void __launch_bounds__(NT) k_oi(OiArgs a) {
     const double* Rg = a.R + ((size_t)w * 3 + c) * T * T;
     for (int e = tid; e < TMAX * TMAX; e += NT) {
       const int i = e / TMAX, j = e % TMAX;
-      s.R[e] = (i < T && j < T) ? Rg[i * T + j] : 0.0;
+      s.R[i * s.LR + j] = (i < T && j < T) ? Rg[i * T + j] : 0.0;
     }
     __syncthreads();
     double part = 0.0;
@@ -444,26 +592,26 @@ __global__ void __launch_bounds__(NT) k_oi(OiArgs a) {
     const bool exact = (w == 0 && a.q_start == nullptr);
     if (exact) {
       // Algorithm 1, line 1: eigenvectors of R (Eq. 5)
-      for (int e = tid; e < TMAX * TMAX; e += NT) s.A[e] = s.R[e];
+      for (int e = tid; e < TMAX * s.LR; e += NT) s.A[e] = s.R[e];
       __syncthreads();
-      jacobi(s, T);
+      eigen_sym(s, T);
       for (int e = tid; e < T * k; e += NT) {
         const int t = e / k, j = e % k;
-        s.Y[t * KMAX + j] = s.V[t * TMAX + s.perm[j]];
+        s.Y[t * s.LQ + j] = s.V[t * s.LR + s.perm[j]];
       }
       __syncthreads();
       sign_fix(s, T, k);
-      for (int e = tid; e < T * k; e += NT) s.Q[(e / k) * KMAX + e % k] = s.Y[(e / k) * KMAX + e % k];
+      for (int e = tid; e < T * k; e += NT) s.Q[(e / k) * s.LQ + e % k] = s.Y[(e / k) * s.LQ + e % k];
       __syncthreads();
       mm_RQ(s, T, k);
       resid = residual_and_H(s, T, k, normR);
       // canonical U = Q (already sorted and sign-fixed); keep it in Y
-      for (int e = tid; e < T * k; e += NT) s.Y[(e / k) * KMAX + e % k] = s.Q[(e / k) * KMAX + e % k];
+      for (int e = tid; e < T * k; e += NT) s.Y[(e / k) * s.LQ + e % k] = s.Q[(e / k) * s.LQ + e % k];
       __syncthreads();
     } else {
       if (w == 0) {
         const Real* q0 = (const Real*)a.q_start + (size_t)c * T * k;
-        for (int e = tid; e < T * k; e += NT) s.Q[(e / k) * KMAX + e % k] = (double)q0[e];
+        for (int e = tid; e < T * k; e += NT) s.Q[(e / k) * s.LQ + e % k] = (double)q0[e];
         __syncthreads();
       }
       // Algorithm 1, line 3: start from the previous block (held in Q)
@@ -478,13 +626,13 @@ __global__ void __launch_bounds__(NT) k_oi(OiArgs a) {
         if (resid <= a.tol) break;
       }
       // Rayleigh-Ritz: H = Q^T R Q = V diag(mu) V^T, U = Q V (sorted)
-      jacobi(s, k);
+      eigen_sym(s, k);
       for (int e = tid; e < T * k; e += NT) {
         const int t = e / k, j = e % k;
         const int pj = s.perm[j];
         double u = 0.0;
-        for (int p = 0; p < k; ++p) u = fma(s.Q[t * KMAX + p], s.V[p * TMAX + pj], u);
-        s.Y[t * KMAX + j] = u;
+        for (int p = 0; p < k; ++p) u = fma(s.Q[t * s.LQ + p], s.V[p * s.LR + pj], u);
+        s.Y[t * s.LQ + j] = u;
       }
       __syncthreads();
       sign_fix(s, T, k);
@@ -494,7 +642,7 @@ __global__ void __launch_bounds__(NT) k_oi(OiArgs a) {
     double* ut = a.u_tilde + ((size_t)w * 3 + c) * T * k;
     uint8_t* rec = a.records + (size_t)w * a.rec_bytes + a.off_dict;
     for (int e = tid; e < T * k; e += NT) {
-      const double u = s.Y[(e / k) * KMAX + e % k];
+      const double u = s.Y[(e / k) * s.LQ + e % k];
       if (uo) uo[e] = (Real)u;
       if (a.dict_bits > 0) {
         const uint16_t code = quant<Real>(u, -1.0, 1.0, a.dict_bits);
@@ -506,7 +654,7 @@ __global__ void __launch_bounds__(NT) k_oi(OiArgs a) {
       }
     }
     // the next window starts from this window's U_k
-    for (int e = tid; e < T * k; e += NT) s.Q[(e / k) * KMAX + e % k] = s.Y[(e / k) * KMAX + e % k];
+    for (int e = tid; e < T * k; e += NT) s.Q[(e / k) * s.LQ + e % k] = s.Y[(e / k) * s.LQ + e % k];
     __syncthreads();
     if (tid == 0 && a.stats) {
       a.stats[w].sweeps[c] = sweeps;
