@@ -356,6 +356,26 @@ __device__ __forceinline__ void jacobi(OiSmem<TMAX, KMAX>& s, int m) {
 }
 
 
+// DPP lane moves of a double (both halves): DPP_ROW_MIRROR (0x140) gives lane t
+// of each 16-lane row the value of lane 15 - t; DPP_WAVE_ROR1 (0x13C) gives
+// lane t the value of lane t - 1 (mod 64).
+constexpr int kDppRowMirror = 0x140, kDppWaveRor1 = 0x13C;
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffLL), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 __device__ __forceinline__ double shfl_f64(double v, int src) {
   const long long b = __double_as_longlong(v);
   const int lo = __shfl((int)(b & 0xffffffffLL), src);
@@ -392,7 +412,6 @@ __device__ __forceinline__ void jacobi_regs(OiSmem<TMAX, KMAX>& s, int m) {
   const int partner = M - 1 - t;               // pair (t, M - 1 - t)
   const int pair = t < partner ? t : partner;  // pair index
   const bool is_p = t < partner;
-  const int prev_lane = t == 0 ? 0 : (t == 1 ? M - 1 : t - 1);  // ring move of rows
   __syncthreads();
   int sweeps_done = 0;
   for (int sweep = 0; sweep < 60; ++sweep) {
@@ -405,7 +424,7 @@ __device__ __forceinline__ void jacobi_regs(OiSmem<TMAX, KMAX>& s, int m) {
         diag = (j == t) ? a[j] : diag;
         off = (j == partner) ? a[j] : off;
       }
-      const double dpart = shfl_f64(diag, partner);
+      const double dpart = M == 16 ? dpp_f64<kDppRowMirror>(diag) : shfl_f64(diag, partner);
       const double app = is_p ? diag : dpart, aqq = is_p ? dpart : diag;
       double c = 1.0, sn = 0.0;
       if (rowA && fabs(off) > fmax(eps * sqrt(fabs(app * aqq)), floor_abs) && off != 0.0) {
@@ -423,24 +442,20 @@ __device__ __forceinline__ void jacobi_regs(OiSmem<TMAX, KMAX>& s, int m) {
         }
         __syncthreads();
         // A <- A J and V <- V J: lane-local on its row
-        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int i = 0; i < M / 2; ++i) {
           const double ci = s.rot_c[i], si = s.rot_s[i];
           const double xp = a[i], xq = a[M - 1 - i];
           a[i] = ci * xp - si * xq;
           a[M - 1 - i] = si * xp + ci * xq;
-          if ((i & 3) == 3) __builtin_amdgcn_sched_barrier(0);
         }
-        // A <- J^T A: rows p and q combine (partner's row by shuffle)
+        // A <- J^T A: rows p and q combine (partner's row by lane exchange)
+        const bool upd = rowA && sn != 0.0;
 #pragma unroll
         for (int j = 0; j < M; ++j) {
-          const double pj = shfl_f64(a[j], partner);
-          if (rowA && sn != 0.0) {
-            const double v = is_p ? c * a[j] - sn * pj : sn * pj + c * a[j];
-            a[j] = (j == partner) ? 0.0 : v;
-          }
-          if ((j & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+          const double pj = M == 16 ? dpp_f64<kDppRowMirror>(a[j]) : shfl_f64(a[j], partner);
+          const double v = is_p ? c * a[j] - sn * pj : sn * pj + c * a[j];
+          a[j] = upd ? ((j == partner) ? 0.0 : v) : a[j];
         }
         __syncthreads();
       }
@@ -451,11 +466,13 @@ __device__ __forceinline__ void jacobi_regs(OiSmem<TMAX, KMAX>& s, int m) {
         for (int j = M - 1; j >= 2; --j) a[j] = a[j - 1];
         a[1] = last;
       }
+      // rows: lane t takes lane t - 1's row (t >= 2), lane 1 takes lane
+      // M - 1's, lane 0 keeps its own
 #pragma unroll
       for (int j = 0; j < M; ++j) {
-        const double v = shfl_f64(a[j], prev_lane);
-        if (rowA) a[j] = v;
-        if ((j & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+        const double sh = dpp_f64<kDppWaveRor1>(a[j]);
+        const double last = readlane_f64(a[j], M - 1);
+        a[j] = rowA ? (t == 0 ? a[j] : (t == 1 ? last : sh)) : a[j];
       }
     }
     if (!rotated) {
