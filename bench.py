@@ -8,15 +8,25 @@ normal equations, and the transpose back to frames (decode).
 
 Workload: 128 x 128 torus (16,384 vertices), 256 frames in windows of 32,
 6-bone Gaussian-RBF skinning, k = 16, 12-bit codes, 64 anchors, float32 frames.
+The first window's orthogonal iterations start from a seeded Gaussian block,
+every later window from the previous window's subspace (Algorithm 1).
 
-Prints one JSON line (see the keys below).  `--gpus N` with N > 1 exits: this
-build measures one GPU.
+Prints one JSON line.  Besides the required keys it carries the per-family
+kernel breakdown (HIP events per launch, outside the timed region) and the
+roofline of the dominant family, timed live over the timed region.
+
+`--gpus N` with N > 1 exits: this program measures one GPU.
+`--copy-calibration MB` only runs a plain device-to-device copy of MB
+megabytes (five times) and exits: the reference reading for the HBM byte
+counters of the dominant kernel.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -24,7 +34,23 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, GB/s
-FP64_PEAK_TFLOPS = 78.6    # MI355X FP64 vector / matrix
+FP64_PEAK_TFLOPS = 78.6    # MI355X FP64 matrix / vector, TFLOP/s
+FIRST_START_SEED = 909     # seeded Gaussian start block of window 0
+
+# source file of each kernel family (the byte counters of a family are valid
+# only while its source is unchanged)
+FAMILY_SOURCE = {
+    "delta": "kernels_encode.hip", "autocorr": "kernels_encode.hip", "oi": "kernels_oi.hip",
+    "project": "kernels_encode.hip", "quantise": "kernels_encode.hip",
+    "anchors": "kernels_encode.hip", "back_project": "kernels_decode.hip",
+    "rhs": "kernels_decode.hip", "cg_spmm": "kernels_decode.hip",
+    "cg_update": "kernels_decode.hip", "chol_fwd_gather": "kernels_chol.hip",
+    "chol_fwd_solve": "kernels_chol.hip", "chol_bwd_solve": "kernels_chol.hip",
+    "to_frames": "kernels_decode.hip",
+}
+FAMILY_KERNEL = {"chol_bwd_solve": "k_bwd_gemm", "chol_fwd_solve": "k_fwd_gemm",
+                 "chol_fwd_gather": "k_fwd_gather", "oi": "k_oi", "cg_spmm": "k_cg_spmm",
+                 "delta": "k_delta", "back_project": "k_back_project"}
 
 
 def parse():
@@ -34,8 +60,89 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-kernel", default=None,
-                    help="kernel family timed with HIP events (default: the dominant one)")
+                    help="kernel family timed live (default: the dominant one)")
+    ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="MB")
     return ap.parse_args()
+
+
+def source_hash(family: str) -> str:
+    path = os.path.join(ROOT, "paper_2111_10105_amd", "csrc", FAMILY_SOURCE[family])
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(family: str):
+    """HBM bytes per launch of `family` from the committed counter summary
+    (profiles/<kernel>_torus128_pmc.txt), or None when there is none or the
+    kernel source changed since the counters were taken."""
+    kern = FAMILY_KERNEL.get(family)
+    if kern is None:
+        return None
+    path = os.path.join(ROOT, "profiles", f"{kern}_torus128_pmc.txt")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m_hash = re.search(r"^source_sha256_16:\s*(\S+)", text, re.M)
+    m_bytes = re.search(r"^hbm_bytes_per_launch:\s*(\S+)", text, re.M)
+    if not m_hash or not m_bytes or m_hash.group(1) != source_hash(family):
+        return None
+    return float(m_bytes.group(1))
+
+
+def work_model(fam, *, n, F, T, k, nw, rs, ncols, nnz, m_nnz, finfo, sweeps_total):
+    """Algorithmic work of one step for a kernel family: (bound, amount, unit)
+    with amount in bytes (hbm) or flops (mfma).  Bytes count each input read
+    once and each output written once; flops count 2 per multiply-add of the
+    operation's definition."""
+    vec = 8.0 * n * ncols                     # one float64 n x 3F block
+    fr = float(rs) * 3 * n * F                # the frames (or deltas) in their type
+    coef = 3.0 * k * n * nw
+    if fam == "delta":
+        return "hbm", 2 * fr + 4.0 * (nnz + n + 1), "B"
+    if fam == "autocorr":
+        return "hbm", fr, "B"
+    if fam == "oi":
+        per = 2.0 * T * T * k + 2.0 * T * k * k + k ** 3 / 3.0
+        return "mfma", per * sweeps_total, "flop"
+    if fam == "project":
+        return "hbm", fr + rs * coef, "B"
+    if fam == "quantise":
+        return "hbm", rs * coef + 2.0 * coef, "B"
+    if fam == "back_project":
+        return "hbm", 2.0 * coef + vec, "B"
+    if fam == "rhs":
+        return "hbm", 2 * vec, "B"
+    if fam == "cg_spmm":
+        return "hbm", 2 * vec + 12.0 * m_nnz, "B"
+    if fam == "cg_update":
+        return "hbm", 6 * vec, "B"
+    if fam == "chol_fwd_gather":
+        return "hbm", 2 * vec + 8.0 * finfo["update_rows"] * ncols, "B"
+    if fam in ("chol_fwd_solve", "chol_bwd_solve"):
+        return "mfma", 2.0 * finfo["solve_entries"] * ncols, "flop"
+    if fam == "to_frames":
+        return "hbm", vec + fr, "B"
+    return None, None, None
+
+
+def nmse(x, y) -> float:
+    """sum (x - y)^2 / sum y^2 over every vertex, frame and coordinate."""
+    import numpy as np
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    return float(np.sum((x - y) ** 2) / np.sum(y ** 2))
+
+
+def copy_calibration(mb: float):
+    import torch
+    nbytes = int(mb * 1e6) // 8 * 8
+    x = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
+    y = torch.empty_like(x)
+    for _ in range(5):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_read": nbytes, "bytes_written": nbytes,
+                      "launches": 5}))
 
 
 def main():
@@ -44,16 +151,21 @@ def main():
         print(f"bench.py measures a single GPU; --gpus {args.gpus} is not supported "
               "(multi-GPU sharding is a design note only)", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration > 0:
+        copy_calibration(args.copy_calibration)
+        return
     import numpy as np
     import torch
 
     from paper_2111_10105_amd import dmc
-    from synth import configs
+    from synth import animate, configs
 
     w = configs.torus_fp32()
     n, F, T = w.n, w.F, w.T
     dev = torch.device("cuda:0")
     frames = torch.from_numpy(w.frames).to(dev)
+    q0_host = animate.gaussian_subspace(T, w.k, FIRST_START_SEED).astype(np.float32)
+    q0 = torch.from_numpy(q0_host).to(dev)
     ctx = dmc.Context(0)
     t0 = time.perf_counter()
     mesh = dmc.Mesh(ctx, n, w.tris, w.anchors)
@@ -64,15 +176,31 @@ def main():
     out = torch.empty_like(frames)
 
     def step(stats=False):
-        return dmc.compress_sequence(ctx, mesh, frames, T, p, codes=codes, out=out, stats=stats)
+        return dmc.compress_sequence(ctx, mesh, frames, T, p, q_start=q0, codes=codes, out=out,
+                                     stats=stats)
 
     for _ in range(max(args.warmup, 1)):
         step()
     torch.cuda.synchronize()
+    _, _, stats, status = step(stats=True)
+    sweeps_total = sum(sum(s["oi_sweeps"]) for s in stats)
+    nw = len(stats)
 
-    # dominant kernel: timed live with HIP events over the timed region
-    prof_kernel = args.profile_kernel or "chol_bwd_solve"
-    dmc.profile_start(prof_kernel)
+    # per-family breakdown (HIP events around every launch; outside the timed region)
+    fam_steps = 2
+    breakdown = {}
+    for fam in dmc.KERNELS:
+        dmc.profile_start(fam)
+        for _ in range(fam_steps):
+            step()
+        launches, ms = dmc.profile_stop()
+        if launches:
+            breakdown[fam] = {"ms_per_step": ms / fam_steps, "launches_per_step": launches // fam_steps}
+    dominant = max(breakdown, key=lambda f: breakdown[f]["ms_per_step"])
+    prof_family = args.profile_kernel or dominant
+
+    # timed region; the profiled family is timed live on the library's stream
+    dmc.profile_start(prof_family)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -85,7 +213,8 @@ def main():
     torch.cuda.synchronize()
     te = time.perf_counter()
     for _ in range(3):
-        dmc.compress_sequence(ctx, mesh, frames, T, p, codes=codes, decode=False, stats=False)
+        dmc.compress_sequence(ctx, mesh, frames, T, p, q_start=q0, codes=codes, decode=False,
+                              stats=False)
     torch.cuda.synchronize()
     enc_ms = (time.perf_counter() - te) / 3 * 1e3
     td = time.perf_counter()
@@ -94,32 +223,80 @@ def main():
     torch.cuda.synchronize()
     dec_ms = (time.perf_counter() - td) / 3 * 1e3
 
-    _, _, stats, status = step(stats=True)
+    step()
     torch.cuda.synchronize()
     got = out.cpu().numpy()
     vf = n * F
     value = vf * args.steps / elapsed
 
-    # roofline of the profiled kernel: algorithmic bytes per launch / time
-    ncols = 3 * F
+    # the other starts of the orthogonal iterations (outside the timed region):
+    # per-window Gaussian blocks and the sketch R_c Omega run every window
+    # concurrently; exact = per-window eigen-decomposition (Eq. 5)
+    nwf = F // T
+    variants = {
+        "random": (dmc.INIT_RANDOM, torch.from_numpy(np.stack(
+            [animate.gaussian_subspace(T, w.k, FIRST_START_SEED + 1 + i) for i in range(nwf)]
+        ).astype(np.float32)).to(dev)),
+        "sketch": (dmc.INIT_SKETCH, torch.from_numpy(
+            animate.gaussian_subspace(T, w.k, FIRST_START_SEED)[0].astype(np.float32)).to(dev)),
+        "exact": (dmc.INIT_EXACT, None),
+    }
+    by_init = {}
+    for name, (mode, qs) in variants.items():
+        pv = dmc.make_params(w.k, coef_bits=w.bits, precision=dmc.FP32, init=mode)
+        outv = torch.empty_like(frames)
+        for _ in range(2):
+            dmc.compress_sequence(ctx, mesh, frames, T, pv, q_start=qs, codes=codes, out=outv,
+                                  stats=False)
+        torch.cuda.synchronize()
+        tv = time.perf_counter()
+        nrep = max(3, args.steps // 2)
+        for _ in range(nrep):
+            dmc.compress_sequence(ctx, mesh, frames, T, pv, q_start=qs, codes=codes, out=outv,
+                                  stats=False)
+        torch.cuda.synchronize()
+        msv = (time.perf_counter() - tv) / nrep * 1e3
+        _, _, stv, _ = dmc.compress_sequence(ctx, mesh, frames, T, pv, q_start=qs, codes=codes,
+                                             out=outv, stats=True)
+        torch.cuda.synchronize()
+        by_init[name] = {"ms_per_step": round(msv, 4), "value": round(vf / (msv * 1e-3), 1),
+                         "oi_sweeps_total": int(sum(sum(x["oi_sweeps"]) for x in stv)),
+                         "nmse_vs_input": nmse(outv.cpu().numpy(), w.frames)}
+
+    model = dict(n=n, F=F, T=T, k=min(w.k, T), nw=nw, rs=4, ncols=3 * F, nnz=mesh.nnz,
+                 m_nnz=mesh.normal_nnz, finfo=finfo, sweeps_total=sweeps_total)
+    kernels = {}
+    for fam, b in breakdown.items():
+        bound, amount, unit = work_model(fam, **model)
+        e = {"ms_per_step": round(b["ms_per_step"], 4), "launches_per_step": b["launches_per_step"]}
+        if bound:
+            if unit == "B":
+                ach = amount / (b["ms_per_step"] * 1e-3) / 1e9
+                e.update(bound="hbm", achieved_GBs=round(ach, 1), frac=round(ach / HBM_PEAK_GBS, 4))
+            else:
+                ach = amount / (b["ms_per_step"] * 1e-3) / 1e12
+                e.update(bound="mfma", achieved_TFLOPs=round(ach, 3),
+                         frac=round(ach / FP64_PEAK_TFLOPS, 5))
+        kernels[fam] = e
+
     roof = None
     if launches:
+        bound, amount, unit = work_model(prof_family, **model)
+        per_launch = amount / breakdown[prof_family]["launches_per_step"] if amount else None
         avg_s = kernel_ms / launches * 1e-3
-        if prof_kernel.startswith("chol_"):
-            # per launch: one level's share; averaged over the levels of a
-            # solve: every factor entry read once and the n x ncols float64
-            # vectors read/written once per sweep direction, spread over the
-            # launches of this family in one solve
-            fam_launches_per_solve = finfo["levels"]
-            solves = launches / fam_launches_per_solve
-            bytes_per_solve = finfo["stored"] * 8 + 2 * n * ncols * 8
-            achieved = bytes_per_solve * solves / (kernel_ms * 1e-3) / 1e9
-        else:
-            achieved = 2 * n * ncols * 8 / avg_s / 1e9
-        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": prof_kernel, "launches": launches,
-                "avg_us": round(kernel_ms / launches * 1e3, 2)}
+        traffic = measured_traffic(prof_family)
+        if bound == "hbm":
+            ach = per_launch / avg_s / 1e9
+            roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(ach / HBM_PEAK_GBS, 4)}
+        elif bound == "mfma":
+            ach = per_launch / avg_s / 1e12
+            roof = {"bound": "mfma", "achieved": round(ach, 3), "peak": FP64_PEAK_TFLOPS,
+                    "unit": "TFLOP/s", "frac": round(ach / FP64_PEAK_TFLOPS, 5)}
+        if roof is not None:
+            roof.update(traffic=traffic, kernel=prof_family, launches=launches,
+                        avg_us=round(kernel_ms / launches * 1e3, 2),
+                        algorithmic_per_launch=per_launch, dtype="f64")
 
     result = {
         "metric": "vertex-frames/s encode+decode at fixed NMSE",
@@ -132,37 +309,43 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 frames, f64 solve",
+        "dtype": "f32/f64",
         "data": "synthetic",
         "config": {"workload": w.name, "vertices": n, "frames": F, "window": T, "k": w.k,
-                   "bits": w.bits, "anchors": int(mesh.nc), "precond": "cholesky",
-                   "cg_tol": p.cg_tol},
+                   "bits": w.bits, "anchors": int(mesh.nc), "first_start": "gaussian",
+                   "oi_tol": p.oi_tol, "precond": "cholesky", "cg_tol": p.cg_tol},
         "split_ms": {"encode": round(enc_ms, 3), "decode": round(dec_ms, 3)},
         "cg_iters": stats[0]["cg_iters"],
         "oi_sweeps": [s["oi_sweeps"] for s in stats],
         "setup_s": round(setup_s, 3),
-        "factor": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in finfo.items()},
+        "factor": {kk: (round(v, 4) if isinstance(v, float) else v) for kk, v in finfo.items()},
         "status": status,
         "roofline": roof,
+        "kernels": kernels,
+        "by_init": by_init,
     }
 
-    import oracle as O
-    result["nmse_vs_input"] = O.nmse(got, w.frames)
+    result["nmse_vs_input"] = nmse(got, w.frames)
     if not args.no_cpu_baseline:
+        import oracle as O
         # the float64 oracle on the host cores, over the same whole sequence
+        # (same first start block, as float64 of the float32 values)
         threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
         tc = time.perf_counter()
         _, ref = O.compress_sequence(n, w.tris, w.frames, w.anchors, T, w.k, w.bits,
-                                     fp32_data=True)
+                                     first_start=q0_host.astype(np.float64), fp32_data=True)
         cpu_s = time.perf_counter() - tc
         result["cpu_baseline"] = {"value": round(vf / cpu_s, 1), "unit": "vertex-frames/s",
                                   "cores": threads, "kind": "oracle",
                                   "sample": f"whole workload once ({n} vertices x {F} frames, "
                                             f"{cpu_s:.1f} s)"}
-        result["nmse_vs_oracle"] = O.nmse(got, ref)
-        result["oracle_nmse_vs_input"] = O.nmse(ref, w.frames)
+        result["nmse_vs_oracle"] = nmse(got, ref)
+        result["oracle_nmse_vs_input"] = nmse(ref, w.frames)
         result["fixed_nmse_ok"] = bool(result["nmse_vs_oracle"] <= 1e-5 and
                                        result["nmse_vs_input"] <= 1.01 * result["oracle_nmse_vs_input"])
+        for v in by_init.values():
+            v["within_1pct_of_oracle_nmse"] = bool(
+                v["nmse_vs_input"] <= 1.01 * result["oracle_nmse_vs_input"])
     print(json.dumps(result))
     ctx.close()
 

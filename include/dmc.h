@@ -65,6 +65,21 @@ enum { DMC_LAP_UNIFORM = 0, DMC_LAP_COMBINATORIAL = 1 };
  * dmc_mesh_create) */
 enum { DMC_PRECOND_NONE = 0, DMC_PRECOND_JACOBI = 1, DMC_PRECOND_CHOLESKY = 2 };
 
+/* start block of each window's orthogonal iterations (Algorithm 1):
+ * DMC_INIT_PREV   the previous window's U_k (Algorithm 1's warm start); window 0
+ *                 from q_start [3][T][k], or its exact eigenvectors (Eq. 5)
+ *                 if q_start is NULL.  Windows run in order.
+ * DMC_INIT_RANDOM a caller-given block per window, q_start [nw][3][T][k]
+ *                 (e.g. seeded Gaussian); windows run concurrently.
+ * DMC_INIT_SKETCH the sketch R_c Omega of each window with one caller-given
+ *                 q_start = Omega [T][k] for all windows and coordinates;
+ *                 windows run concurrently.
+ * DMC_INIT_EXACT  every window from its exact eigenvectors (Eq. 5, the
+ *                 per-block SVD); q_start is ignored; windows run concurrently.
+ * Start blocks are in the frames' type.  A shorter last window of a sequence
+ * always starts from its exact eigenvectors. */
+enum { DMC_INIT_PREV = 0, DMC_INIT_RANDOM = 1, DMC_INIT_SKETCH = 2, DMC_INIT_EXACT = 3 };
+
 typedef struct {
   int32_t k;             /* kept rows k_l of Eq. (10), 1 <= k <= T            */
   int32_t coef_bits;     /* bits of Q(.) in Eq. (10): 1..16, 0 = raw values    */
@@ -76,6 +91,7 @@ typedef struct {
   int32_t cg_max_iters;  /* cap on conjugate-gradient iterations >= 1          */
   int32_t precond;       /* DMC_PRECOND_*                                      */
   double cg_tol;         /* stop a column when ||r|| <= tol ||b||              */
+  int32_t init;          /* DMC_INIT_* (0 = DMC_INIT_PREV, Algorithm 1)        */
 } dmc_params;
 
 typedef struct {
@@ -116,8 +132,11 @@ int32_t dmc_mesh_nnz(dmc_mesh mesh);          /* nonzeros of C (= 2 |E|)       *
 int32_t dmc_mesh_normal_nnz(dmc_mesh mesh);   /* nonzeros of L^T L + I_N^T I_N */
 /* sizes of the normal matrix's Cholesky factor: [0] stored entries,
  * [1] nonzeros of the exact factor, [2] supernodes, [3] tree levels,
- * [4] factorisation flops, [5] host seconds to build it */
-void dmc_mesh_factor_info(dmc_mesh mesh, double info[6]);
+ * [4] factorisation flops, [5] host seconds to build it, [6] entries of the
+ * solve operators one triangular solve reads (per right-hand side: 2 flops
+ * each), [7] update rows (entries of the factor left of a diagonal block,
+ * counted by row of the supernode that produces them) */
+void dmc_mesh_factor_info(dmc_mesh mesh, double info[8]);
 
 /* Host-only check of the ordering and factorisation (no device needed):
  * builds L^T L + I_N^T I_N and its supernodal Cholesky factor exactly as
@@ -128,7 +147,7 @@ void dmc_mesh_factor_info(dmc_mesh mesh, double info[6]);
 dmc_status dmc_host_normal_solve(int32_t n_verts, int32_t n_tris, const int32_t* tris_host,
                                  int32_t n_anchors, const int32_t* anchors_host,
                                  int32_t laplacian, int32_t ncols, const double* B_host,
-                                 double* X_host, double info[6]);
+                                 double* X_host, double info[8]);
 
 /* ---- encoded window record -----------------------------------------------
  * One window's record is a byte buffer (device memory), 256-byte aligned
@@ -151,9 +170,12 @@ size_t dmc_sequence_code_bytes(int32_t n, int32_t F, int32_t T, int32_t n_anchor
 
 /* ---- encode one window (Eq. 3-10, Eq. 12 anchors; Algorithm 1) -----------
  * frames_dev  [T][n][3] frames of the window.
- * q_start_dev [3][T][k] start block of orthogonal iterations per coordinate
- *             (normally the previous window's u_out; Algorithm 1, line 3), or
- *             NULL for the exact eigenvectors of R_c (Algorithm 1, line 1).
+ * q_start_dev start of the orthogonal iterations: with DMC_INIT_PREV or
+ *             DMC_INIT_RANDOM a [3][T][k] block per coordinate (normally the
+ *             previous window's u_out, the warm start of Algorithm 1), or NULL
+ *             for the exact eigenvectors of R_c (Eq. 5); with
+ *             DMC_INIT_SKETCH Omega [T][k] (start R_c Omega); ignored with
+ *             DMC_INIT_EXACT.
  * code_dev    record buffer of dmc_window_code_bytes bytes.
  * u_out_dev   optional [3][T][k]: the window's eigen-trajectories U_k (before
  *             dictionary quantisation), columns ordered by eigenvalue,
@@ -179,11 +201,13 @@ dmc_status dmc_decode_window(dmc_ctx ctx, dmc_mesh mesh, const void* code_dev,
                              void* frames_out_dev, dmc_window_stats* stats);
 
 /* ---- whole sequence (Sec. III-A, "blocks") -------------------------------
- * Splits F frames into windows of T (the last may be shorter), encodes them in
- * order, each window starting its orthogonal iterations from the previous
- * window's U_k (window 0 from q_start_dev [3][T][k], or exact if NULL; a
- * shorter last window from its own exact eigenvectors), writing the records
- * back to back into codes_dev (dmc_sequence_code_bytes bytes).  If
+ * Splits F frames into windows of T (the last may be shorter) and encodes
+ * them, each window's orthogonal iterations starting as params->init says
+ * (DMC_INIT_PREV: in order, from the previous window's U_k, window 0 from
+ * q_start_dev [3][T][k] or exact if NULL; DMC_INIT_RANDOM: q_start_dev
+ * [nw][3][T][k] for the nw = F / T full windows; DMC_INIT_SKETCH: Omega
+ * [T][k]), writing the records back to back into codes_dev
+ * (dmc_sequence_code_bytes bytes).  If
  * frames_out_dev [F][n][3] is not NULL, then decodes every window in one
  * solve over all 3F columns.  per_window: optional array of n_windows stats
  * (synchronises). */

@@ -359,12 +359,13 @@ def anchor_values(frames_w: np.ndarray, anchors: np.ndarray, c: int) -> np.ndarr
 
 
 def encode_window(L, frames_w, anchors, k, bits, *, dict_bits=16, anchor_bits=16,
-                  q_start=None, oi_tol=1e-12, oi_max_sweeps=200, fp32_data=False):
+                  q_start=None, omega=None, oi_tol=1e-12, oi_max_sweeps=200, fp32_data=False):
     """One window of the encoder.
 
     q_start None -> exact eigenvectors of each R_c (Algorithm 1, first block);
     otherwise a [3][T][k] start block for orthogonal iterations followed by the
-    Ritz step.  Returns a dict with the dictionary, coefficients, codes,
+    Ritz step.  omega ([T][k]) instead starts every coordinate from the sketch
+    R_c omega.  Returns a dict with the dictionary, coefficients, codes,
     anchor codes and per-coordinate iteration counts.
     """
     frames_w = np.asarray(frames_w)
@@ -378,7 +379,10 @@ def encode_window(L, frames_w, anchors, k, bits, *, dict_bits=16, anchor_bits=16
     for c in range(3):
         A_c = coordinate_matrix(frames_w, c)
         R = autocorrelation(A_c)
-        if q_start is None:
+        if omega is not None:
+            Q, sweeps, resid = orthogonal_iterations(R, R @ omega[:, :kw], oi_tol, oi_max_sweeps)
+            lam, U = ritz(R, Q)
+        elif q_start is None:
             lam, U = exact_subspace(R, kw)
             sweeps, resid = 0, oi_residual(R, U)
         else:
@@ -471,22 +475,34 @@ def decode_window(solver: AnchoredSolver, rec) -> np.ndarray:
 # ---------------------------------------------------------------------------
 
 def compress_sequence(n, tris, frames, anchors, T, k, bits, *, laplacian_kind=LAP_UNIFORM,
-                      dict_bits=16, anchor_bits=16, first_start=None, oi_tol=1e-12,
-                      oi_max_sweeps=200, decode=True, fp32_data=False):
-    """Encode (and decode) every window; window w > 0 starts its orthogonal
-    iterations from window w-1's U_k (Algorithm 1); window 0 starts from
-    `first_start` ([3][T][k]) or, if None, from its exact eigenvectors.  A short
-    last window starts from its own exact eigenvectors.
+                      dict_bits=16, anchor_bits=16, first_start=None, init="prev",
+                      starts=None, omega=None, oi_tol=1e-12, oi_max_sweeps=200, decode=True,
+                      fp32_data=False):
+    """Encode (and decode) every window.  Start of each full window's
+    orthogonal iterations, by `init`:
+      "prev"   window w > 0 from window w-1's U_k (Algorithm 1); window 0 from
+               `first_start` ([3][T][k]) or, if None, its exact eigenvectors;
+      "random" window w from starts[w] ([nw][3][T][k]);
+      "sketch" every window from R_c omega (omega [T][k]);
+      "exact"  every window from its exact eigenvectors (Eq. 5).
+    A short last window starts from its own exact eigenvectors.
     Returns (records, reconstruction or None)."""
     L = laplacian(n, tris, laplacian_kind)
     frames = np.asarray(frames)
     recs = []
     prev = first_start
-    for (s, e) in windows(frames.shape[0], T):
+    for wi, (s, e) in enumerate(windows(frames.shape[0], T)):
         fw = frames[s:e]
-        start = prev if (e - s) == T else None
+        full = (e - s) == T
+        start, om = None, None
+        if full and init == "prev":
+            start = prev
+        elif full and init == "random":
+            start = starts[wi]
+        elif full and init == "sketch":
+            om = omega
         rec = encode_window(L, fw, anchors, k, bits, dict_bits=dict_bits,
-                            anchor_bits=anchor_bits, q_start=start, oi_tol=oi_tol,
+                            anchor_bits=anchor_bits, q_start=start, omega=om, oi_tol=oi_tol,
                             oi_max_sweeps=oi_max_sweeps, fp32_data=fp32_data)
         rec["start"] = s
         recs.append(rec)

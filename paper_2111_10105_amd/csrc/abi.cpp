@@ -29,7 +29,7 @@ struct dmc_mesh_s {
   dmc::MeshDev dev;
   std::vector<void*> allocations;
   std::vector<int32_t> level_w, level_m;  // host copies of the factor's level -> task ranges
-  double factor_info[6] = {0, 0, 0, 0, 0, 0};
+  double factor_info[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 };
 
 namespace {
@@ -126,6 +126,8 @@ dmc_status check_params(const dmc_params* p, int32_t T, bool for_decode = false)
   for (int32_t b : {p->coef_bits, p->anchor_bits, p->dict_bits})
     if (b < 0 || b > 16) return fail(DMC_ERR_INVALID_ARG, "bits must be in 0..16");
   if (!for_decode) {
+    if (p->init < DMC_INIT_PREV || p->init > DMC_INIT_EXACT)
+      return fail(DMC_ERR_INVALID_ARG, "unknown init");
     if (p->oi_max_sweeps < 1) return fail(DMC_ERR_INVALID_ARG, "oi_max_sweeps must be >= 1");
     if (!(p->oi_tol >= 0.0)) return fail(DMC_ERR_INVALID_ARG, "oi_tol must be >= 0");
   }
@@ -173,7 +175,8 @@ dmc_status encode_chain(dmc_ctx ctx, const dmc::MeshDev& m, const void* frames, 
   oa.k = k;
   oa.precision = p.precision;
   oa.dict_bits = p.dict_bits;
-  oa.q_start = q_start;
+  oa.init = p.init;
+  oa.q_start = p.init == DMC_INIT_EXACT ? nullptr : q_start;
   oa.u_out = u_out;
   oa.u_tilde = u_tilde;
   oa.records = records;
@@ -288,7 +291,7 @@ constexpr int32_t kNdLeaf = 32;
 
 dmc_status build_mesh_host(int32_t n, int32_t n_tris, const int32_t* tris, int32_t n_anchors,
                            const int32_t* anchors, int32_t laplacian, dmc::HostCsr& C,
-                           dmc::HostCsr& M, dmc::CholFactor& F, double info[6]) {
+                           dmc::HostCsr& M, dmc::CholFactor& F, double info[8]) {
   if (n < 1 || n_tris < 1 || !tris) return fail(DMC_ERR_INVALID_ARG, "need n >= 1 and triangles");
   if (laplacian != DMC_LAP_UNIFORM && laplacian != DMC_LAP_COMBINATORIAL)
     return fail(DMC_ERR_INVALID_ARG, "unknown Laplacian");
@@ -323,6 +326,17 @@ dmc_status build_mesh_host(int32_t n, int32_t n_tris, const int32_t* tris, int32
   info[3] = F.nlevels;
   info[4] = F.flops;
   info[5] = secs;
+  // entries of the solve operators one triangular solve reads (lower
+  // triangle of inv(L_ss) plus the dense L_os inv(L_ss)), and update rows
+  double entries = 0.0, updates = 0.0;
+  for (int32_t s = 0; s < F.nsuper; ++s) {
+    const double w = F.sn_start[s + 1] - F.sn_start[s];
+    const double m = F.sn_rowptr[s + 1] - F.sn_rowptr[s];
+    entries += w * (w + 1) / 2 + (m - w) * w;
+    updates += m - w;
+  }
+  info[6] = entries;
+  info[7] = updates;
   return DMC_OK;
 }
 
@@ -410,7 +424,7 @@ dmc_status dmc_mesh_create(dmc_ctx ctx, int32_t n, int32_t n_tris, const int32_t
   *out = nullptr;
   dmc::HostCsr C, M;
   dmc::CholFactor F;
-  double info[6];
+  double info[8];
   dmc_status st = build_mesh_host(n, n_tris, tris, n_anchors, anchors, laplacian, C, M, F, info);
   if (st != DMC_OK) return st;
   std::vector<double> w64(n), dinv(n, 0.0);
@@ -511,18 +525,18 @@ dmc_status dmc_mesh_create(dmc_ctx ctx, int32_t n, int32_t n_tris, const int32_t
   return DMC_OK;
 }
 
-void dmc_mesh_factor_info(dmc_mesh mesh, double info[6]) {
+void dmc_mesh_factor_info(dmc_mesh mesh, double info[8]) {
   if (!mesh || !info) return;
   std::memcpy(info, mesh->factor_info, sizeof(mesh->factor_info));
 }
 
 dmc_status dmc_host_normal_solve(int32_t n, int32_t n_tris, const int32_t* tris, int32_t n_anchors,
                                  const int32_t* anchors, int32_t laplacian, int32_t ncols,
-                                 const double* B, double* X, double info[6]) {
+                                 const double* B, double* X, double info[8]) {
   if (ncols < 1 || !B || !X) return fail(DMC_ERR_INVALID_ARG, "bad right-hand side");
   dmc::HostCsr C, M;
   dmc::CholFactor F;
-  double inf[6];
+  double inf[8];
   dmc_status st = build_mesh_host(n, n_tris, tris, n_anchors, anchors, laplacian, C, M, F, inf);
   if (st != DMC_OK) return st;
   dmc::chol_solve_host(F, ncols, B, X);
@@ -658,6 +672,8 @@ dmc_status dmc_compress_sequence(dmc_ctx ctx, dmc_mesh mesh, const void* frames,
   dmc_status st = check_params(params, T);
   if (st != DMC_OK) return st;
   const dmc_params& p = *params;
+  if ((p.init == DMC_INIT_RANDOM || p.init == DMC_INIT_SKETCH) && !q_start && F >= T)
+    return fail(DMC_ERR_INVALID_ARG, "DMC_INIT_RANDOM and DMC_INIT_SKETCH need q_start");
   const dmc::MeshDev& m = mesh->dev;
   const dmc::SeqLayout sl = seq_layout(m.n, F, T, m.nc, p);
   const size_t need = dmc_sequence_code_bytes(m.n, F, T, m.nc, &p);

@@ -98,7 +98,8 @@ struct OiArgs {
   int32_t nw, T, k;
   int32_t precision;
   int32_t dict_bits;
-  const void* q_start;   // [3][T][k] real, or nullptr (exact start)
+  int32_t init;          // DMC_INIT_*
+  const void* q_start;   // per init: [3][T][k], [nw][3][T][k] or Omega [T][k] (real)
   void* u_out;           // [nw][3][T][k] real (may be nullptr)
   double* u_tilde;       // [nw][3][T][k] float64 dequantised dictionary
   uint8_t* records;      // record of window w at records + w*rec_bytes

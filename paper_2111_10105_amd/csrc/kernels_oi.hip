@@ -54,90 +54,161 @@ __device__ __forceinline__ double block_max(double v, double* /*red*/) {
   return v;
 }
 
-// Y = R Q (T x k) on the FP64 matrix cores.  Operand layouts of
-// v_mfma_f64_16x16x4f64: lane l holds A[l%16][l/16] and B[l/16][l%16]; result
-// element (4*r + l/16, l%16) is component r of lane l.
-template <int TMAX, int KMAX>
-__device__ __forceinline__ void mm_RQ(OiSmem<TMAX, KMAX>& s, int T, int k) {
-  const int Tp = (T + 15) & ~15, kp = (k + 15) & ~15;
-  const int ti_n = Tp / 16, tj_n = kp / 16;
-  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-  for (int tile = wave; tile < ti_n * tj_n; tile += NT / 64) {
-    const int ti = tile / tj_n, tj = tile % tj_n;
-    d4 acc = {0.0, 0.0, 0.0, 0.0};
-    for (int kk = 0; kk < Tp; kk += 4) {
-      const double a = s.R[(ti * 16 + lane % 16) * s.LR + kk + lane / 16];
-      const double b = s.Q[(kk + lane / 16) * s.LQ + tj * 16 + lane % 16];
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
-    }
-    for (int r = 0; r < 4; ++r) {
-      const int row = ti * 16 + 4 * r + lane / 16, col = tj * 16 + lane % 16;
-      s.Y[row * s.LQ + col] = acc[r];
+// DPP lane moves of a double (both halves): DPP_ROW_MIRROR (0x140) gives lane t
+// of each 16-lane row the value of lane 15 - t; DPP_WAVE_ROR1 (0x13C) gives
+// lane t the value of lane t - 1 (mod 64).
+constexpr int kDppRowMirror = 0x140, kDppWaveRor1 = 0x13C;
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffLL), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ __forceinline__ double shfl_f64(double v, int src) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __shfl((int)(b & 0xffffffffLL), src);
+  const int hi = __shfl((int)(b >> 32), src);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Products on the FP64 matrix cores (v_mfma_f64_16x16x4f64).  Operand
+// layouts: lane l holds A[l%16][l/16] and B[l/16][l%16]; result element
+// (4*r + l/16, l%16) is component r of lane l.  Every product below runs its
+// whole contraction unrolled (operands zero padded to TMAX rows / KR columns),
+// with one accumulator per output tile so that consecutive MFMAs are
+// independent.
+__device__ __forceinline__ d4 mfma64(double a, double b, d4 acc) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+}
+
+// Y = R Q (T x k; rows >= T and columns >= k come out zero).
+template <int KR, int TMAX, int KMAX>
+__device__ __forceinline__ void mm_RQ(OiSmem<TMAX, KMAX>& s) {
+  constexpr int TI = TMAX / 16, TJ = KR / 16;
+  const int lane = threadIdx.x, r16 = lane % 16, q4 = lane / 16;
+  d4 acc[TI][TJ];
+#pragma unroll
+  for (int i = 0; i < TI; ++i)
+#pragma unroll
+    for (int j = 0; j < TJ; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int kk = 0; kk < TMAX; kk += 4) {
+    double b[TJ];
+#pragma unroll
+    for (int j = 0; j < TJ; ++j) b[j] = s.Q[(kk + q4) * s.LQ + j * 16 + r16];
+#pragma unroll
+    for (int i = 0; i < TI; ++i) {
+      const double a = s.R[(i * 16 + r16) * s.LR + kk + q4];
+#pragma unroll
+      for (int j = 0; j < TJ; ++j) acc[i][j] = mfma64(a, b[j], acc[i][j]);
     }
   }
+#pragma unroll
+  for (int i = 0; i < TI; ++i)
+#pragma unroll
+    for (int j = 0; j < TJ; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) s.Y[(i * 16 + 4 * r + q4) * s.LQ + j * 16 + r16] = acc[i][j][r];
   __syncthreads();
 }
 
-// A[0:k,0:k] = X^T X for X = Q or Y (T x k).
-template <int TMAX, int KMAX>
-__device__ __forceinline__ void gram(OiSmem<TMAX, KMAX>& s, const double* X, int T, int k) {
-  for (int e = threadIdx.x; e < k * k; e += NT) {
-    const int a = e / k, b = e % k;
-    if (b > a) continue;
-    double g = 0.0;
-    for (int t = 0; t < T; ++t) g = fma(X[t * s.LQ + a], X[t * s.LQ + b], g);
-    s.A[a * s.LR + b] = g;
-    s.A[b * s.LR + a] = g;
+// A[0:KR, 0:KR] = X^T Z for T x KR blocks X, Z in LDS (stride LQ, rows >= T
+// zero).  X == Z gives the Gram matrix.
+template <int KR, int TMAX, int KMAX>
+__device__ __forceinline__ void mm_XtZ(OiSmem<TMAX, KMAX>& s, const double* X, const double* Z) {
+  constexpr int TN = KR / 16;
+  const int lane = threadIdx.x, r16 = lane % 16, q4 = lane / 16;
+  d4 acc[TN][TN];
+#pragma unroll
+  for (int i = 0; i < TN; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int kk = 0; kk < TMAX; kk += 4) {
+    double a[TN], b[TN];
+#pragma unroll
+    for (int i = 0; i < TN; ++i) {
+      a[i] = X[(kk + q4) * s.LQ + i * 16 + r16];
+      b[i] = Z[(kk + q4) * s.LQ + i * 16 + r16];
+    }
+#pragma unroll
+    for (int i = 0; i < TN; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j) acc[i][j] = mfma64(a[i], b[j], acc[i][j]);
   }
+#pragma unroll
+  for (int i = 0; i < TN; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) s.A[(i * 16 + 4 * r + q4) * s.LR + j * 16 + r16] = acc[i][j][r];
   __syncthreads();
 }
 
-// In-place Cholesky of A[0:k,0:k] (+ shift on the diagonal); lower factor.
-// Sets s.ok = 0 on a pivot <= rel_tol * max diagonal.
-template <int TMAX, int KMAX>
-__device__ __forceinline__ void cholesky(OiSmem<TMAX, KMAX>& s, int k, double shift) {
-  if (threadIdx.x == 0) s.ok = 1;
-  double dmax = 0.0;
-  for (int j = 0; j < k; ++j) dmax = fmax(dmax, s.A[j * s.LR + j]);
-  __syncthreads();
-  if (shift != 0.0)
-    for (int j = threadIdx.x; j < k; j += NT) s.A[j * s.LR + j] += shift;
-  __syncthreads();
-  const double thresh = 1e-15 * dmax;
-  for (int j = 0; j < k; ++j) {
-    if (threadIdx.x == 0) {
-      const double d = s.A[j * s.LR + j];
-      if (!(d > thresh)) {
-        s.ok = 0;
-        s.A[j * s.LR + j] = 1.0;
-      } else {
-        s.A[j * s.LR + j] = sqrt(d);
-      }
+// One pass of Cholesky QR in registers.  Lane i < KR holds row i of the KR x
+// KR Gram matrix in g (identity rows/columns beyond k), lane t holds row t of
+// the block in x (zero beyond column k and beyond row T).  Column j of the
+// Cholesky factor L is formed at step j and broadcast by lane reads; it serves
+// both the trailing update of g and the forward substitution x <- x L^-T,
+// which proceed column by column together.  A pivot <= thresh fails the pass
+// (returned false; the results are then discarded).
+template <int KR>
+__device__ __forceinline__ bool chol_qr_regs(double (&g)[KR], double (&x)[KR], double thresh) {
+  const int lane = threadIdx.x;
+  bool ok = true;
+#pragma unroll
+  for (int j = 0; j < KR; ++j) {
+    const double d = readlane_f64(g[j], j);
+    const bool good = d > thresh;
+    ok = ok && good;
+    const double ljj = good ? sqrt(d) : 1.0;
+    const double inv = 1.0 / ljj;
+    const double lij = lane > j ? g[j] * inv : (lane == j ? ljj : 0.0);
+    g[j] = lij;
+    const double qj = x[j] * inv;
+    x[j] = qj;
+#pragma unroll
+    for (int l = j + 1; l < KR; ++l) {
+      const double c = readlane_f64(lij, l);  // L[l][j]
+      g[l] = fma(-lij, c, g[l]);
+      x[l] = fma(-qj, c, x[l]);
     }
-    __syncthreads();
-    const double ljj = s.A[j * s.LR + j];
-    for (int i = j + 1 + threadIdx.x; i < k; i += NT) s.A[i * s.LR + j] /= ljj;
-    __syncthreads();
-    const int m = k - j - 1;
-    for (int e = threadIdx.x; e < m * m; e += NT) {
-      const int i = j + 1 + e / m, l = j + 1 + e % m;
-      if (l <= i) s.A[i * s.LR + l] -= s.A[i * s.LR + j] * s.A[l * s.LR + j];
-    }
-    __syncthreads();
   }
+  return ok;
 }
 
-// Q = X L^{-T} row by row (forward substitution); X may alias Q.
-template <int TMAX, int KMAX>
-__device__ __forceinline__ void tri_solve(OiSmem<TMAX, KMAX>& s, const double* X, int T, int k) {
-  for (int t = threadIdx.x; t < T; t += NT) {
-    for (int j = 0; j < k; ++j) {
-      double v = X[t * s.LQ + j];
-      for (int p = 0; p < j; ++p) v -= s.Q[t * s.LQ + p] * s.A[j * s.LR + p];
-      s.Q[t * s.LQ + j] = v / s.A[j * s.LR + j];
-    }
+// The same pass for T <= 32 with both operands in one array: lanes 0..31 hold
+// the rows of the block, lane 32 + i row i of the Gram matrix.  One FMA per
+// entry and step serves both the trailing update and the substitution.
+template <int KR>
+__device__ __forceinline__ bool chol_qr_packed(double (&v)[KR], double thresh) {
+  const int lane = threadIdx.x;
+  const bool isG = lane >= 32;
+  const int i = lane - 32;
+  bool ok = true;
+#pragma unroll
+  for (int j = 0; j < KR; ++j) {
+    const double d = readlane_f64(v[j], 32 + j);
+    const bool good = d > thresh;
+    ok = ok && good;
+    const double ljj = good ? sqrt(d) : 1.0;
+    const double inv = 1.0 / ljj;
+    const double own = isG ? (i > j ? v[j] * inv : (i == j ? ljj : 0.0)) : v[j] * inv;
+    v[j] = own;
+#pragma unroll
+    for (int l = j + 1; l < KR; ++l) v[l] = fma(-own, readlane_f64(own, 32 + l), v[l]);
   }
-  __syncthreads();
+  return ok;
 }
 
 // Gram-Schmidt (each column orthogonalised twice against the previous ones) on
@@ -199,53 +270,97 @@ __device__ __forceinline__ void gram_schmidt(OiSmem<TMAX, KMAX>& s, int T, int k
   }
 }
 
-// Q = orthonormal basis of span(X) (X = Y or Q, T x k).  Returns the number of
-// breakdown repairs (0: plain CholeskyQR2).
-template <int TMAX, int KMAX>
+// Q = orthonormal basis of span(X) (X = Y or Q, T x k), left in s.Q.
+// Cholesky QR2 on the column-scaled block (columns of R Q differ in norm by
+// the eigenvalue spread; scaling by the Gram diagonal removes that without
+// changing the Q factor).  A pivot breakdown switches to shifted Cholesky QR3
+// (Fukaya et al.: shift 11 (T k + k (k + 1)) u ||X||_F^2), a second one, or an
+// exactly zero column, to Gram-Schmidt with completion.  Returns the number
+// of repairs (0: plain Cholesky QR2).
+template <int KR, int TMAX, int KMAX>
 __device__ __forceinline__ int orthonormalise(OiSmem<TMAX, KMAX>& s, const double* X, int T, int k) {
-  // column scaling: Q = X D^-1 with unit columns (same Q factor); an exactly
-  // zero column is replaced by completion from the identity below
-  int zero_cols = 0;
-  for (int j = 0; j < k; ++j) {
-    const double x = threadIdx.x < T ? X[threadIdx.x * s.LQ + j] : 0.0;
-    const double nrm = sqrt(block_sum(x * x, s.red));
-    if (threadIdx.x < T) s.Q[threadIdx.x * s.LQ + j] = nrm > 0.0 ? x / nrm : 0.0;
-    zero_cols += nrm > 0.0 ? 0 : 1;
-  }
-  __syncthreads();
-  if (zero_cols) {
+  const int lane = threadIdx.x;
+  constexpr double thresh = 1e-15;  // pivots relative to the unit diagonal
+  constexpr bool packed = TMAX <= 32;
+  mm_XtZ<KR>(s, X, X);
+  // column scales: lane r < k holds 1 / ||x_r|| (packed: lanes 32 + r too)
+  const int r = packed ? (lane & 31) : lane;
+  const double grr = r < k ? s.A[r * s.LR + r] : 1.0;
+  const bool zero_col = __any(r < k && !(grr > 0.0));
+  const double dinv = (r < k && grr > 0.0) ? 1.0 / sqrt(grr) : 1.0;
+  double x[KR];
+  double g[packed ? 1 : KR];
+  // rows of the block (lanes < T; packed: lanes < 32) and of the Gram matrix
+  // in A (packed: lane 32 + i holds row i; else lane i in g), both scaled
+  // by the column scales when `scaled`; the block rows are reloaded from X
+  // unless `gram_only`
+  auto load = [&](bool scaled, bool gram_only) {
+#pragma unroll
+    for (int j = 0; j < KR; ++j) {
+      const double dj = scaled ? readlane_f64(dinv, j) : 1.0;
+      const double di = scaled ? dinv : 1.0;
+      const int gi = packed ? lane - 32 : lane;
+      const double gv = (gi >= 0 && gi < k) ? s.A[gi * s.LR + j] * di * dj
+                                            : ((gi >= k && gi == j) ? 1.0 : 0.0);
+      const double xv = lane < T ? X[lane * s.LQ + j] * dj : 0.0;
+      if constexpr (packed) {
+        x[j] = lane >= 32 ? gv : (gram_only ? x[j] : xv);
+      } else {
+        g[j] = gv;
+        if (!gram_only) x[j] = xv;
+      }
+    }
+  };
+  auto pass = [&]() -> bool {
+    if constexpr (packed)
+      return chol_qr_packed<KR>(x, thresh);
+    else
+      return chol_qr_regs<KR>(g, x, thresh);
+  };
+  auto to_Q = [&]() {  // block rows back to s.Q (X may alias it)
+    __syncthreads();
+    if (lane < T && (!packed || lane < 32)) {
+#pragma unroll
+      for (int j = 0; j < KR; ++j) s.Q[lane * s.LQ + j] = x[j];
+    }
+    __syncthreads();
+  };
+  load(true, false);
+  if (zero_col) {
+    to_Q();
     gram_schmidt(s, T, k);
     return 1;
   }
-  int repairs = 0;
-  gram(s, s.Q, T, k);
-  double tr = 0.0;
-  for (int j = 0; j < k; ++j) tr += s.A[j * s.LR + j];
-  __syncthreads();
-  cholesky(s, k, 0.0);
-  int passes = 2;
-  if (!s.ok) {
-    // shifted CholeskyQR (Fukaya et al.): shift 11 (T k + k (k + 1)) u ||X||^2
+  int repairs = 0, passes = 2;
+  if (!pass()) {
     repairs = 1;
     passes = 3;
-    gram(s, s.Q, T, k);
-    const double shift = 11.0 * (double)(T * k + k * (k + 1)) * 1.1102230246251565e-16 * tr;
-    cholesky(s, k, shift);
-    if (!s.ok) {
+    load(true, false);
+    const double shift = 11.0 * (double)(T * k + k * (k + 1)) * 1.1102230246251565e-16 * (double)k;
+#pragma unroll
+    for (int j = 0; j < KR; ++j) {
+      if constexpr (packed)
+        x[j] += (lane - 32 == j && j < k) ? shift : 0.0;
+      else
+        g[j] += (lane == j && j < k) ? shift : 0.0;
+    }
+    if (!pass()) {
+      load(true, false);
+      to_Q();
       gram_schmidt(s, T, k);
       return 2;
     }
   }
-  tri_solve(s, s.Q, T, k);
-  for (int pass = 1; pass < passes; ++pass) {
-    gram(s, s.Q, T, k);
-    cholesky(s, k, 0.0);
-    if (!s.ok) {
+  for (int p = 1; p < passes; ++p) {
+    to_Q();
+    mm_XtZ<KR>(s, s.Q, s.Q);
+    load(false, true);
+    if (!pass()) {  // s.Q still holds the last block
       gram_schmidt(s, T, k);
       return repairs + 2;
     }
-    tri_solve(s, s.Q, T, k);
   }
+  to_Q();
   return repairs;
 }
 
@@ -356,33 +471,6 @@ __device__ __forceinline__ void jacobi(OiSmem<TMAX, KMAX>& s, int m) {
 }
 
 
-// DPP lane moves of a double (both halves): DPP_ROW_MIRROR (0x140) gives lane t
-// of each 16-lane row the value of lane 15 - t; DPP_WAVE_ROR1 (0x13C) gives
-// lane t the value of lane t - 1 (mod 64).
-constexpr int kDppRowMirror = 0x140, kDppWaveRor1 = 0x13C;
-
-template <int CTRL>
-__device__ __forceinline__ double dpp_f64(double v) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffLL), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, false);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
-__device__ __forceinline__ double readlane_f64(double v, int lane) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), lane);
-  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
-__device__ __forceinline__ double shfl_f64(double v, int src) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __shfl((int)(b & 0xffffffffLL), src);
-  const int hi = __shfl((int)(b >> 32), src);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
 // Register-resident parallel cyclic Jacobi for m <= M (M = 16 or 32, zero
 // padded to M; padding is never rotated because its off-diagonal entries are
 // exactly zero).  Lane l < 32 holds row l of A, lane 32 + l row l of V; all
@@ -426,8 +514,9 @@ __device__ __forceinline__ void jacobi_regs(OiSmem<TMAX, KMAX>& s, int m) {
       }
       const double dpart = M == 16 ? dpp_f64<kDppRowMirror>(diag) : shfl_f64(diag, partner);
       const double app = is_p ? diag : dpart, aqq = is_p ? dpart : diag;
+      // the rotation of each pair is decided and computed by its p row only
       double c = 1.0, sn = 0.0;
-      if (rowA && fabs(off) > fmax(eps * sqrt(fabs(app * aqq)), floor_abs) && off != 0.0) {
+      if (rowA && is_p && fabs(off) > fmax(eps * sqrt(fabs(app * aqq)), floor_abs) && off != 0.0) {
         const double th = (aqq - app) / (2.0 * off);
         const double tt = copysign(1.0, th) / (fabs(th) + sqrt(th * th + 1.0));
         c = 1.0 / sqrt(tt * tt + 1.0);
@@ -449,7 +538,12 @@ __device__ __forceinline__ void jacobi_regs(OiSmem<TMAX, KMAX>& s, int m) {
           a[i] = ci * xp - si * xq;
           a[M - 1 - i] = si * xp + ci * xq;
         }
-        // A <- J^T A: rows p and q combine (partner's row by lane exchange)
+        // A <- J^T A: rows p and q combine (partner's row by lane exchange),
+        // both with the rotation of their pair
+        if (rowA) {
+          c = s.rot_c[pair];
+          sn = s.rot_s[pair];
+        }
         const bool upd = rowA && sn != 0.0;
 #pragma unroll
         for (int j = 0; j < M; ++j) {
@@ -475,11 +569,23 @@ __device__ __forceinline__ void jacobi_regs(OiSmem<TMAX, KMAX>& s, int m) {
         a[j] = rowA ? (t == 0 ? a[j] : (t == 1 ? last : sh)) : a[j];
       }
     }
-    if (!rotated) {
-      sweeps_done = sweep + 1;
-      break;
-    }
     sweeps_done = sweep + 1;
+    if (!rotated) break;
+    // The slots are back in their original order.  If every pair already
+    // passes the skip test (checked from both rows, so never looser than the
+    // test of a round), the next sweep would rotate nothing: stop here.
+    bool pending = false;
+    double dtt = 0.0;
+#pragma unroll
+    for (int i = 0; i < M; ++i) dtt = (i == t) ? a[i] : dtt;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      const double djj = readlane_f64(a[j], j);
+      const double x = a[j];
+      pending = pending || (rowA && j != t && x != 0.0 &&
+                            fabs(x) > fmax(eps * sqrt(fabs(dtt * djj)), floor_abs));
+    }
+    if (!__any(pending)) break;
   }
   if (threadIdx.x == 0) s.flag = sweeps_done;  // sweeps used (for inspection)
   // write back: diagonal of A, rows of V
@@ -532,24 +638,41 @@ __device__ __forceinline__ void sign_fix(OiSmem<TMAX, KMAX>& s, int T, int k) {
 }
 
 // ||R Q - Q (Q^T R Q)||_F / ||R||_F with Y = R Q already computed; leaves
-// H = Q^T Y (symmetrised) in A.
-template <int TMAX, int KMAX>
-__device__ __forceinline__ double residual_and_H(OiSmem<TMAX, KMAX>& s, int T, int k, double normR) {
-  for (int e = threadIdx.x; e < k * k; e += NT) {
-    const int a = e / k, b = e % k;
-    double h = 0.0;
-    for (int t = 0; t < T; ++t) h = fma(s.Q[t * s.LQ + a], s.Y[t * s.LQ + b], h);
-    s.A[a * s.LR + b] = h;
+// H = Q^T Y (symmetrised) in A.  Both products on the matrix cores.
+template <int KR, int TMAX, int KMAX>
+__device__ __forceinline__ double residual_and_H(OiSmem<TMAX, KMAX>& s, int k, double normR) {
+  mm_XtZ<KR>(s, s.Q, s.Y);
+  constexpr int TI = TMAX / 16, TJ = KR / 16;
+  const int lane = threadIdx.x, r16 = lane % 16, q4 = lane / 16;
+  d4 acc[TI][TJ];
+#pragma unroll
+  for (int i = 0; i < TI; ++i)
+#pragma unroll
+    for (int j = 0; j < TJ; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int kk = 0; kk < KR; kk += 4) {
+    double b[TJ];
+#pragma unroll
+    for (int j = 0; j < TJ; ++j) b[j] = s.A[(kk + q4) * s.LR + j * 16 + r16];
+#pragma unroll
+    for (int i = 0; i < TI; ++i) {
+      const double a = s.Q[(i * 16 + r16) * s.LQ + kk + q4];
+#pragma unroll
+      for (int j = 0; j < TJ; ++j) acc[i][j] = mfma64(a, b[j], acc[i][j]);
+    }
   }
-  __syncthreads();
   double ss = 0.0;
-  for (int e = threadIdx.x; e < T * k; e += NT) {
-    const int t = e / k, b = e % k;
-    double v = s.Y[t * s.LQ + b];
-    for (int a = 0; a < k; ++a) v -= s.Q[t * s.LQ + a] * s.A[a * s.LR + b];
-    ss += v * v;
-  }
+#pragma unroll
+  for (int i = 0; i < TI; ++i)
+#pragma unroll
+    for (int j = 0; j < TJ; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const double e = s.Y[(i * 16 + 4 * r + q4) * s.LQ + j * 16 + r16] - acc[i][j][r];
+        ss = fma(e, e, ss);
+      }
   const double res = block_sum(ss, s.red);
+  __syncthreads();
   for (int e = threadIdx.x; e < k * k; e += NT) {
     const int a = e / k, b = e % k;
     if (b > a) {
@@ -560,6 +683,41 @@ __device__ __forceinline__ double residual_and_H(OiSmem<TMAX, KMAX>& s, int T, i
   }
   __syncthreads();
   return normR > 0.0 ? sqrt(res) / normR : 0.0;
+}
+
+// Ritz vectors Y = Q V(:, perm) (columns in decreasing eigenvalue order).
+template <int KR, int TMAX, int KMAX>
+__device__ __forceinline__ void ritz_vectors(OiSmem<TMAX, KMAX>& s, int k) {
+  constexpr int TI = TMAX / 16, TJ = KR / 16;
+  const int lane = threadIdx.x, r16 = lane % 16, q4 = lane / 16;
+  d4 acc[TI][TJ];
+#pragma unroll
+  for (int i = 0; i < TI; ++i)
+#pragma unroll
+    for (int j = 0; j < TJ; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int kk = 0; kk < KR; kk += 4) {
+    double b[TJ];
+#pragma unroll
+    for (int j = 0; j < TJ; ++j) {
+      const int col = j * 16 + r16, row = kk + q4;
+      b[j] = (col < k && row < k) ? s.V[row * s.LR + s.perm[col]] : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < TI; ++i) {
+      const double a = s.Q[(i * 16 + r16) * s.LQ + kk + q4];
+#pragma unroll
+      for (int j = 0; j < TJ; ++j) acc[i][j] = mfma64(a, b[j], acc[i][j]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < TI; ++i)
+#pragma unroll
+    for (int j = 0; j < TJ; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) s.Y[(i * 16 + 4 * r + q4) * s.LQ + j * 16 + r16] = acc[i][j][r];
+  __syncthreads();
 }
 
 template <typename Real>
@@ -581,7 +739,29 @@ __device__ __forceinline__ double dequant(uint16_t code, double lo, double hi, i
   return lo + (double)code * step;
 }
 
-template <int TMAX, int KMAX, typename Real>
+// Algorithm 1's iterations and the Ritz step: start block in Q (the previous
+// window's U, or a caller-given block), sweeps Y = R Q, Q = QR(Y) until the
+// residual test passes or the sweep cap, then U = Q V from H = Q^T R Q = V
+// diag(mu) V^T; U is left in Y (not yet sign-fixed).
+template <int KR, int TMAX, int KMAX>
+__device__ __forceinline__ void oi_sweeps(OiSmem<TMAX, KMAX>& s, int T, int k, int max_sweeps, double tol,
+                                          double normR, int& sweeps, int& repairs, double& resid) {
+  repairs += orthonormalise<KR>(s, s.Q, T, k) ? 1 : 0;
+  mm_RQ<KR>(s);
+  for (int sw = 1; sw <= max_sweeps; ++sw) {
+    repairs += orthonormalise<KR>(s, s.Y, T, k) ? 1 : 0;
+    mm_RQ<KR>(s);
+    sweeps = sw;
+    resid = residual_and_H<KR>(s, k, normR);
+    if (resid <= tol) break;
+  }
+  eigen_sym(s, k);
+  ritz_vectors<KR>(s, k);
+}
+
+// One workgroup (one wavefront) per coordinate; KR = k rounded up to the
+// 16-column tile of the matrix-core products (16 or 32).
+template <int TMAX, int KMAX, int KR, typename Real>
 __global__ void __launch_bounds__(NT) k_oi(OiArgs a) {
   __shared__ OiSmem<TMAX, KMAX> s;
   const int c = blockIdx.x;  // coordinate
@@ -592,23 +772,38 @@ __global__ void __launch_bounds__(NT) k_oi(OiArgs a) {
     s.Y[e] = 0.0;
   }
   __syncthreads();
-  for (int w = 0; w < a.nw; ++w) {
-    // ---- load R_c of window w (zero padded) ----
+  // DMC_INIT_PREV chains the windows in one workgroup per coordinate; the
+  // other starts give every (window, coordinate) its own workgroup
+  const bool chain = a.init == DMC_INIT_PREV;
+  const int w_begin = chain ? 0 : (int)blockIdx.y;
+  const int w_end = chain ? a.nw : w_begin + 1;
+  for (int w = w_begin; w < w_end; ++w) {
+    // ---- load R_c of window w (zero padded), every load in flight at once ----
     const double* Rg = a.R + ((size_t)w * 3 + c) * T * T;
-    for (int e = tid; e < TMAX * TMAX; e += NT) {
-      const int i = e / TMAX, j = e % TMAX;
-      s.R[i * s.LR + j] = (i < T && j < T) ? Rg[i * T + j] : 0.0;
+    constexpr int PER = TMAX * TMAX / NT;
+    double rv[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = tid + u * NT, i = e / TMAX, j = e % TMAX;
+      rv[u] = (i < T && j < T) ? Rg[i * T + j] : 0.0;
+    }
+    double part = 0.0;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = tid + u * NT, i = e / TMAX, j = e % TMAX;
+      s.R[i * s.LR + j] = rv[u];
+      part = fma(rv[u], rv[u], part);
     }
     __syncthreads();
-    double part = 0.0;
-    for (int e = tid; e < T * T; e += NT) part += Rg[e] * Rg[e];
     const double normR = sqrt(block_sum(part, s.red));
 
     int sweeps = 0, repairs = 0;
     double resid = 0.0;
-    const bool exact = (w == 0 && a.q_start == nullptr);
+    // exact start: always with DMC_INIT_EXACT, else for a missing start block
+    // (window 0 of the chain; any window otherwise)
+    const bool exact = a.init == DMC_INIT_EXACT || (a.q_start == nullptr && (w == 0 || !chain));
     if (exact) {
-      // Algorithm 1, line 1: eigenvectors of R (Eq. 5)
+      // exact start of Algorithm 1: eigenvectors of R (Eq. 5)
       for (int e = tid; e < TMAX * s.LR; e += NT) s.A[e] = s.R[e];
       __syncthreads();
       eigen_sym(s, T);
@@ -620,38 +815,38 @@ __global__ void __launch_bounds__(NT) k_oi(OiArgs a) {
       sign_fix(s, T, k);
       for (int e = tid; e < T * k; e += NT) s.Q[(e / k) * s.LQ + e % k] = s.Y[(e / k) * s.LQ + e % k];
       __syncthreads();
-      mm_RQ(s, T, k);
-      resid = residual_and_H(s, T, k, normR);
+      mm_RQ<KR>(s);
+      resid = residual_and_H<KR>(s, k, normR);
       // canonical U = Q (already sorted and sign-fixed); keep it in Y
       for (int e = tid; e < T * k; e += NT) s.Y[(e / k) * s.LQ + e % k] = s.Q[(e / k) * s.LQ + e % k];
       __syncthreads();
     } else {
-      if (w == 0) {
-        const Real* q0 = (const Real*)a.q_start + (size_t)c * T * k;
-        for (int e = tid; e < T * k; e += NT) s.Q[(e / k) * s.LQ + e % k] = (double)q0[e];
+      if (!chain || w == 0) {
+        // caller-given start (window 0 of the chain, or this window's own
+        // block), or Omega for the sketch start R_c Omega
+        const Real* q0 = (const Real*)a.q_start;
+        if (a.init == DMC_INIT_RANDOM) q0 += ((size_t)w * 3 + c) * T * k;
+        else if (a.init != DMC_INIT_SKETCH) q0 += (size_t)c * T * k;
+        constexpr int PQ = TMAX * KR / NT;
+        double qv[PQ];
+#pragma unroll
+        for (int u = 0; u < PQ; ++u) {
+          const int e = tid + u * NT;
+          qv[u] = e < T * k ? (double)q0[e] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < PQ; ++u) {
+          const int e = tid + u * NT;
+          if (e < T * k) s.Q[(e / k) * s.LQ + e % k] = qv[u];
+        }
         __syncthreads();
+        if (a.init == DMC_INIT_SKETCH) {
+          mm_RQ<KR>(s);  // Y = R_c Omega
+          for (int e = tid; e < T * k; e += NT) s.Q[(e / k) * s.LQ + e % k] = s.Y[(e / k) * s.LQ + e % k];
+          __syncthreads();
+        }
       }
-      // Algorithm 1, line 3: start from the previous block (held in Q)
-      repairs += orthonormalise(s, s.Q, T, k) ? 1 : 0;
-      mm_RQ(s, T, k);
-      for (int sw = 1; sw <= a.max_sweeps; ++sw) {
-        // Algorithm 1, line 5: U^(t) = QR(R U^(t-1))
-        repairs += orthonormalise(s, s.Y, T, k) ? 1 : 0;
-        mm_RQ(s, T, k);
-        sweeps = sw;
-        resid = residual_and_H(s, T, k, normR);
-        if (resid <= a.tol) break;
-      }
-      // Rayleigh-Ritz: H = Q^T R Q = V diag(mu) V^T, U = Q V (sorted)
-      eigen_sym(s, k);
-      for (int e = tid; e < T * k; e += NT) {
-        const int t = e / k, j = e % k;
-        const int pj = s.perm[j];
-        double u = 0.0;
-        for (int p = 0; p < k; ++p) u = fma(s.Q[t * s.LQ + p], s.V[p * s.LR + pj], u);
-        s.Y[t * s.LQ + j] = u;
-      }
-      __syncthreads();
+      oi_sweeps<KR>(s, T, k, a.max_sweeps, a.tol, normR, sweeps, repairs, resid);
       sign_fix(s, T, k);
     }
     // ---- outputs: U, dictionary codes, dequantised dictionary ----
@@ -683,19 +878,22 @@ __global__ void __launch_bounds__(NT) k_oi(OiArgs a) {
 
 }  // namespace
 
+template <int TMAX, int KR>
+void launch_oi_t(hipStream_t st, const OiArgs& a) {
+  const dim3 grid(3, a.init == DMC_INIT_PREV ? 1 : a.nw);
+  if (a.precision == DMC_FP64)
+    hipLaunchKernelGGL((k_oi<TMAX, 32, KR, double>), grid, dim3(NT), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_oi<TMAX, 32, KR, float>), grid, dim3(NT), 0, st, a);
+}
+
 void launch_oi(hipStream_t st, const OiArgs& a) {
   prof::begin(st, DMC_KERNEL_OI);
-  if (a.T <= 32) {
-    if (a.precision == DMC_FP64)
-      hipLaunchKernelGGL((k_oi<32, 32, double>), dim3(3), dim3(NT), 0, st, a);
-    else
-      hipLaunchKernelGGL((k_oi<32, 32, float>), dim3(3), dim3(NT), 0, st, a);
-  } else {
-    if (a.precision == DMC_FP64)
-      hipLaunchKernelGGL((k_oi<64, 32, double>), dim3(3), dim3(NT), 0, st, a);
-    else
-      hipLaunchKernelGGL((k_oi<64, 32, float>), dim3(3), dim3(NT), 0, st, a);
-  }
+  const int kt = a.k <= 16 ? 16 : 32;
+  if (a.T <= 32)
+    kt == 16 ? launch_oi_t<32, 16>(st, a) : launch_oi_t<32, 32>(st, a);
+  else
+    kt == 16 ? launch_oi_t<64, 16>(st, a) : launch_oi_t<64, 32>(st, a);
   prof::end(st, DMC_KERNEL_OI);
 }
 

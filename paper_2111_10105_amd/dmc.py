@@ -22,6 +22,7 @@ STATUS = {0: "OK", 1: "INVALID_ARG", 2: "OUT_OF_MEMORY", 3: "DEVICE", 4: "NOT_CO
 FP64, FP32 = 0, 1
 LAP_UNIFORM, LAP_COMBINATORIAL = 0, 1
 PRECOND_NONE, PRECOND_JACOBI, PRECOND_CHOLESKY = 0, 1, 2
+INIT_PREV, INIT_RANDOM, INIT_SKETCH, INIT_EXACT = 0, 1, 2, 3
 
 EXPORTS = ["dmc_create", "dmc_destroy", "dmc_set_stream", "dmc_last_error", "dmc_scratch_bytes",
            "dmc_mesh_create", "dmc_mesh_destroy", "dmc_mesh_nnz", "dmc_mesh_normal_nnz",
@@ -46,7 +47,8 @@ class Params(ctypes.Structure):
                 ("anchor_bits", ctypes.c_int32), ("dict_bits", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("oi_max_sweeps", ctypes.c_int32),
                 ("oi_tol", ctypes.c_double), ("cg_max_iters", ctypes.c_int32),
-                ("precond", ctypes.c_int32), ("cg_tol", ctypes.c_double)]
+                ("precond", ctypes.c_int32), ("cg_tol", ctypes.c_double),
+                ("init", ctypes.c_int32)]
 
 
 class WindowStats(ctypes.Structure):
@@ -63,7 +65,7 @@ class WindowStats(ctypes.Structure):
 
 def make_params(k, coef_bits=12, anchor_bits=16, dict_bits=16, precision=FP32,
                 oi_max_sweeps=200, oi_tol=None, cg_max_iters=None, precond=PRECOND_CHOLESKY,
-                cg_tol=None) -> Params:
+                cg_tol=None, init=INIT_PREV) -> Params:
     if oi_tol is None:
         oi_tol = 1e-12
     if cg_tol is None:
@@ -71,7 +73,7 @@ def make_params(k, coef_bits=12, anchor_bits=16, dict_bits=16, precision=FP32,
     if cg_max_iters is None:
         cg_max_iters = 50 if precond == PRECOND_CHOLESKY else 20000
     return Params(k, coef_bits, anchor_bits, dict_bits, precision, oi_max_sweeps, float(oi_tol),
-                  cg_max_iters, precond, float(cg_tol))
+                  cg_max_iters, precond, float(cg_tol), init)
 
 
 _lib = None
@@ -126,6 +128,28 @@ def _check(status: int, allow=()):
     if status != DMC_OK and status not in allow:
         raise DmcError(status, lib().dmc_last_error().decode())
     return status
+
+
+def _check_start(q_start, frames, T: int, params: "Params", nw: int = 0):
+    """Shape, dtype and device of a start block (the library reads it as raw
+    memory): [3][T][k] (DMC_INIT_PREV; DMC_INIT_RANDOM for one window),
+    [nw][3][T][k] (DMC_INIT_RANDOM over nw full windows), Omega [T][k]
+    (DMC_INIT_SKETCH); k = min(params.k, T)."""
+    if q_start is None or params.init == INIT_EXACT:
+        return
+    k = min(params.k, T)
+    if params.init == INIT_SKETCH:
+        want = (T, k)
+    elif params.init == INIT_RANDOM and nw:
+        want = (nw, 3, T, k)
+    else:
+        want = (3, T, k)
+    if tuple(q_start.shape) != want:
+        raise ValueError(f"q_start must have shape {want}, got {tuple(q_start.shape)}")
+    if q_start.dtype != frames.dtype or q_start.device != frames.device:
+        raise ValueError("q_start must match the frames' dtype and device")
+    if not q_start.is_contiguous():
+        raise ValueError("q_start must be contiguous")
 
 
 def _ptr(t):
@@ -191,12 +215,13 @@ class Mesh:
         return lib().dmc_mesh_normal_nnz(self.h)
 
     def factor_info(self) -> dict:
-        a = (ctypes.c_double * 6)()
+        a = (ctypes.c_double * 8)()
         lib().dmc_mesh_factor_info(self.h, a)
         return dict(zip(FACTOR_INFO_KEYS, list(a)))
 
 
-FACTOR_INFO_KEYS = ("stored", "nnz_exact", "supernodes", "levels", "flops", "seconds")
+FACTOR_INFO_KEYS = ("stored", "nnz_exact", "supernodes", "levels", "flops", "seconds",
+                    "solve_entries", "update_rows")
 
 
 def host_normal_solve(n, tris, anchors, B, laplacian: int = LAP_UNIFORM):
@@ -208,7 +233,7 @@ def host_normal_solve(n, tris, anchors, B, laplacian: int = LAP_UNIFORM):
     if B.ndim == 1:
         B = B[:, None]
     X = np.empty_like(B)
-    info = (ctypes.c_double * 6)()
+    info = (ctypes.c_double * 8)()
     _check(lib().dmc_host_normal_solve(int(n), int(tris.shape[0]), tris.ctypes.data_as(ctypes.c_void_p),
                                        int(anchors.size), anchors.ctypes.data_as(ctypes.c_void_p),
                                        int(laplacian), int(B.shape[1]),
@@ -232,6 +257,7 @@ def encode_window(ctx: Context, mesh: Mesh, frames, params: Params, q_start=None
     import torch
     T = frames.shape[0]
     dev = frames.device
+    _check_start(q_start, frames, T, params)
     ctx.sync_stream()
     code = torch.empty(window_code_bytes(mesh.n, T, mesh.nc, params), dtype=torch.uint8, device=dev)
     k = min(params.k, T)
@@ -263,6 +289,7 @@ def compress_sequence(ctx: Context, mesh: Mesh, frames, T: int, params: Params, 
     or None, per-window stats list, status)."""
     import torch
     F = frames.shape[0]
+    _check_start(q_start, frames, T, params, nw=F // T)
     ctx.sync_stream()
     nbytes = sequence_code_bytes(mesh.n, F, T, mesh.nc, params)
     if codes is None:

@@ -124,7 +124,8 @@ def test_encode_window_codes_bit_exact(ctx, prec, bits):
 
 @pytest.mark.parametrize("prec", [dmc.FP64, dmc.FP32])
 def test_encode_window_exact_start_matches_jacobi(ctx, prec):
-    """Algorithm 1, line 1: the GPU's Jacobi eigenvectors match the oracle's."""
+    """Exact start of Algorithm 1 (first block, Eq. 5): the GPU's Jacobi
+    eigenvectors match the oracle's."""
     T, k = 32, 4
     v, t, fr, anchors = _window_case(prec, T, k, seed=13)
     n = v.shape[0]
@@ -249,6 +250,44 @@ def test_ragged_sequence_with_warm_start(ctx, prec):
     # round-off, yet carry delta-coordinate energy: an independent float64
     # implementation agrees with the oracle to well below the method's own
     # error, not to round-off
+    assert e_or <= 0.5 * r_in
+    assert e_in <= 1.1 * r_in
+
+
+@pytest.mark.parametrize("init", [dmc.INIT_RANDOM, dmc.INIT_SKETCH, dmc.INIT_EXACT, dmc.INIT_PREV])
+@pytest.mark.parametrize("prec", [dmc.FP64, dmc.FP32])
+def test_sequence_start_modes(ctx, init, prec):
+    """56 frames in windows of 16 (three full windows run concurrently unless
+    chained, plus a short tail) for every start of the orthogonal iterations,
+    against the oracle given the same start blocks."""
+    w = configs.small_torus(frames=56, T=16, k=10, precision="fp64" if prec == dmc.FP64 else "fp32")
+    m = dmc.Mesh(ctx, w.n, w.tris, w.anchors)
+    p = dmc.make_params(w.k, coef_bits=w.bits, precision=prec, cg_tol=1e-13, init=init)
+    nw = w.F // w.T
+    rdt = np.float64 if prec == dmc.FP64 else np.float32
+    starts = np.stack([animate.gaussian_subspace(w.T, w.k, seed=70 + i) for i in range(nw)]).astype(rdt)
+    omega = animate.gaussian_subspace(w.T, w.k, seed=80)[0].astype(rdt)
+    q = {dmc.INIT_RANDOM: starts, dmc.INIT_SKETCH: omega, dmc.INIT_PREV: starts[0],
+         dmc.INIT_EXACT: None}[init]
+    codes, out, stats, status = dmc.compress_sequence(ctx, m, to_dev(w.frames), w.T, p,
+                                                      q_start=None if q is None else to_dev(q))
+    assert status == 0
+    assert [s["T"] for s in stats] == [16, 16, 16, 8]
+    sweeps = [s["oi_sweeps"] for s in stats]
+    if init == dmc.INIT_EXACT:
+        assert all(sw == [0, 0, 0] for sw in sweeps)
+    else:
+        assert all(min(sw) >= 1 for sw in sweeps[:nw]) and sweeps[nw] == [0, 0, 0]
+    name = {dmc.INIT_RANDOM: "random", dmc.INIT_SKETCH: "sketch", dmc.INIT_EXACT: "exact",
+            dmc.INIT_PREV: "prev"}[init]
+    recs, ref = O.compress_sequence(w.n, w.tris, w.frames, w.anchors, w.T, w.k, w.bits, init=name,
+                                    first_start=starts[0].astype(np.float64),
+                                    starts=starts.astype(np.float64),
+                                    omega=omega.astype(np.float64), fp32_data=(prec == dmc.FP32))
+    got = _np(out)
+    e_or, e_in, r_in = O.nmse(got, ref), O.nmse(got, w.frames), O.nmse(ref, w.frames)
+    print(f"init {name} prec {prec}: sweeps gpu {sweeps} oracle {[r['sweeps'] for r in recs]} "
+          f"NMSE(gpu,oracle)={e_or:.3e} NMSE(gpu,input)={e_in:.3e} NMSE(oracle,input)={r_in:.3e}")
     assert e_or <= 0.5 * r_in
     assert e_in <= 1.1 * r_in
 

@@ -404,3 +404,34 @@ def test_dictionary_quantiser_range():
     for (i, j) in itertools.islice(itertools.product(range(16), range(5)), 20):
         assert codes[i, j] == _exact_code(U[i, j], -1.0, 1.0, 16) or \
             abs(int(codes[i, j]) - _exact_code(U[i, j], -1.0, 1.0, 16)) <= 1
+
+
+@pytest.mark.parametrize("level,F,T,k", [(1, 16, 8, 2), (2, 32, 16, 1), (3, 64, 32, 4)])
+def test_sequence_start_modes_reach_the_exact_subspace(level, F, T, k):
+    """Every start of the orthogonal iterations (previous window, per-window
+    Gaussian block, sketch R_c Omega) converges on gapped windows to the
+    window's exact eigenvectors (Jacobi, itself pinned to LAPACK), so the
+    records of all modes carry the same dictionary."""
+    v, t = meshes.icosphere(level)
+    fr = animate.bend_twist(v, F, seed=10 + level, noise_var=1e-6)
+    anchors = np.arange(0, v.shape[0], max(1, v.shape[0] // 6))
+    nw = F // T
+    starts = np.stack([animate.gaussian_subspace(T, k, seed=50 + i) for i in range(nw)])
+    omega = animate.gaussian_subspace(T, k, seed=60)[0]
+    runs = {}
+    for init in ("exact", "prev", "random", "sketch"):
+        recs, _ = O.compress_sequence(v.shape[0], t, fr, anchors, T, k, 12, init=init,
+                                      first_start=starts[0], starts=starts, omega=omega,
+                                      oi_tol=1e-14, decode=False)
+        runs[init] = recs
+    for w in range(nw):
+        for c in range(3):
+            U_ex = runs["exact"][w]["U"][c]
+            lam, Uj = O.jacobi_eigh(O.autocorrelation(O.coordinate_matrix(fr[w * T:(w + 1) * T], c)))
+            assert np.max(np.abs(U_ex - Uj[:, :k] * np.sign(Uj[np.argmax(np.abs(Uj[:, :k]), axis=0),
+                                                              range(k)]))) < 1e-12
+            for init in ("prev", "random", "sketch"):
+                assert runs[init][w]["sweeps"][c] >= 1
+                assert _sin_angle(U_ex, runs[init][w]["U"][c]) < 1e-10
+                assert np.max(np.abs(runs[init][w]["U"][c] - U_ex)) < 1e-8
+    assert all(s == [0, 0, 0] for s in (r["sweeps"] for r in runs["exact"]))
