@@ -3,4 +3,4 @@
 Shared by the oracle's tests, the HIP library's tests and the benchmark.  It
 holds none of the compression method's arithmetic.
 """
-from . import animate, configs, meshes  # noqa: F401
+from . import animate, configs, learned, meshes  # noqa: F401
