@@ -76,9 +76,13 @@ enum { DMC_PRECOND_NONE = 0, DMC_PRECOND_JACOBI = 1, DMC_PRECOND_CHOLESKY = 2 };
  *                 windows run concurrently.
  * DMC_INIT_EXACT  every window from its exact eigenvectors (Eq. 5, the
  *                 per-block SVD); q_start is ignored; windows run concurrently.
+ * DMC_INIT_LEARNED the network registered with dmc_learned_start predicts
+ *                 each window's start from its sketch R_c Omega; windows run
+ *                 concurrently; q_start is ignored.
  * Start blocks are in the frames' type.  A shorter last window of a sequence
  * always starts from its exact eigenvectors. */
-enum { DMC_INIT_PREV = 0, DMC_INIT_RANDOM = 1, DMC_INIT_SKETCH = 2, DMC_INIT_EXACT = 3 };
+enum { DMC_INIT_PREV = 0, DMC_INIT_RANDOM = 1, DMC_INIT_SKETCH = 2, DMC_INIT_EXACT = 3,
+       DMC_INIT_LEARNED = 4 };
 
 typedef struct {
   int32_t k;             /* kept rows k_l of Eq. (10), 1 <= k <= T            */
@@ -231,6 +235,66 @@ dmc_status dmc_delta(dmc_ctx ctx, dmc_mesh mesh, const void* frames_dev, int32_t
                      int32_t precision, void* delta_out_dev);
 dmc_status dmc_autocorrelation(dmc_ctx ctx, dmc_mesh mesh, const void* frames_dev,
                                int32_t T, int32_t precision, void* R_out_dev);
+
+/* ---- orthogonal iterations on independent covariance blocks --------------
+ * Algorithm 1's iterations and the Ritz step (as in dmc_encode_window) on nb
+ * independent symmetric blocks R_dev float64 [nb][T][T], all concurrently:
+ * U_out_dev float64 [nb][T][k] (k = params->k <= T), columns ordered by
+ * eigenvalue, sign fixed.  params->init: DMC_INIT_RANDOM (q_start_dev
+ * float64 [nb][T][k]), DMC_INIT_SKETCH (Omega float64 [T][k]),
+ * DMC_INIT_EXACT, or DMC_INIT_LEARNED (registered network).  sweeps_host
+ * [nb] and resid_host [nb] (optional; filling them synchronises) receive the
+ * sweeps used and the final residual ||R Q - Q Q^T R Q||_F / ||R||_F. */
+dmc_status dmc_oi_blocks(dmc_ctx ctx, const double* R_dev, int32_t nb, int32_t T,
+                         const dmc_params* params, const void* q_start_dev,
+                         double* U_out_dev, int32_t* sweeps_host, double* resid_host);
+
+/* ---- learned start (not in the paper; the plain starts remain) ------------
+ * A row-wise perceptron maps each row of the sketch features S (the columns
+ * of R_c Omega, Omega [T][32], orthonormalised by Gram-Schmidt run twice, a
+ * column keeping less than 1e-10 of its norm after the projections set to
+ * zero, then scaled by sqrt(T)) to a row of the start block:
+ * h1 = gelu(S W1 + b1) (32 -> 128), h2 = gelu(h1 W2 + b2) (128 -> 128),
+ * Q = h2 W3 + b3 (128 -> k), gelu(x) = x Phi(x).  theta: float32
+ * [dmc_mlp_param_count(k)] = W1 [32][128], b1 [128], W2 [128][128], b2 [128],
+ * W3 [128][k], b3 [k], row-major.  Products take bfloat16 operands with
+ * float32 accumulation (matrix cores); the backward pass uses the
+ * bfloat16-rounded weights in float32.  All pointers are device memory;
+ * every call is ordered on the context's stream.
+ *
+ * dmc_learned_start  registers (omega float64 [T][32], theta) for
+ *                    DMC_INIT_LEARNED with this T and k; the buffers stay
+ *                    owned by the caller and must outlive their use; NULL
+ *                    pointers unregister.
+ * dmc_mlp_sketch     S_out float32 [nb][T][32] from R float64 [nb][T][T].
+ * dmc_mlp_forward    Q_out float32 [N][k] from S float32 [N][32]; cache
+ *                    (optional, float32 [N][256]) keeps the pre-activations
+ *                    for dmc_mlp_backward.
+ * dmc_mlp_loss_grad  per block b of nb: loss_dev[b] (float64, optional) =
+ *                    ||(I - U U^T) Q||^2 / ||Q||^2
+ *                    + mu ||Q^T Q / (||Q||^2 / k) - I||^2 with Q float32 and
+ *                    the orthonormal targets U float64, both [nb][T][k];
+ *                    dQ_out float32 = gradient of the mean over blocks.
+ * dmc_mlp_backward   grad_out float32 [count] = gradient of sum(dQ * Q) with
+ *                    respect to theta (uses the context's scratch).
+ * dmc_mlp_adam       one bias-corrected Adam step (step >= 1) on theta with
+ *                    moments m, v (float32 [count], zero at step 1). */
+int32_t dmc_mlp_param_count(int32_t k);
+dmc_status dmc_learned_start(dmc_ctx ctx, int32_t T, int32_t k, const double* omega_dev,
+                             const float* theta_dev);
+dmc_status dmc_mlp_sketch(dmc_ctx ctx, const double* R_dev, int32_t nb, int32_t T,
+                          const double* omega_dev, float* S_out_dev);
+dmc_status dmc_mlp_forward(dmc_ctx ctx, const float* theta_dev, int32_t k, const float* S_dev,
+                           int32_t N, float* Q_out_dev, float* cache_dev);
+dmc_status dmc_mlp_loss_grad(dmc_ctx ctx, const float* Q_dev, const double* U_dev, int32_t nb,
+                             int32_t T, int32_t k, double mu, float* dQ_out_dev,
+                             double* loss_dev);
+dmc_status dmc_mlp_backward(dmc_ctx ctx, const float* theta_dev, int32_t k, const float* S_dev,
+                            int32_t N, const float* cache_dev, const float* dQ_dev,
+                            float* grad_out_dev);
+dmc_status dmc_mlp_adam(dmc_ctx ctx, float* theta_dev, const float* grad_dev, float* m_dev,
+                        float* v_dev, int32_t count, int32_t step, double lr, double beta1,
+                        double beta2, double eps);
 
 /* ---- kernel timing (measurement support) ----------------------------------
  * dmc_profile_start selects one kernel family; from then on every launch of

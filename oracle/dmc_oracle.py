@@ -359,13 +359,15 @@ def anchor_values(frames_w: np.ndarray, anchors: np.ndarray, c: int) -> np.ndarr
 
 
 def encode_window(L, frames_w, anchors, k, bits, *, dict_bits=16, anchor_bits=16,
-                  q_start=None, omega=None, oi_tol=1e-12, oi_max_sweeps=200, fp32_data=False):
+                  q_start=None, omega=None, learned=None, oi_tol=1e-12, oi_max_sweeps=200,
+                  fp32_data=False):
     """One window of the encoder.
 
     q_start None -> exact eigenvectors of each R_c (Algorithm 1, first block);
     otherwise a [3][T][k] start block for orthogonal iterations followed by the
     Ritz step.  omega ([T][k]) instead starts every coordinate from the sketch
-    R_c omega.  Returns a dict with the dictionary, coefficients, codes,
+    R_c omega; learned = (Omega [T][32], theta) from the row-wise perceptron's
+    prediction on the sketch (oracle.mlp_oracle.predict_start).  Returns a dict with the dictionary, coefficients, codes,
     anchor codes and per-coordinate iteration counts.
     """
     frames_w = np.asarray(frames_w)
@@ -379,7 +381,12 @@ def encode_window(L, frames_w, anchors, k, bits, *, dict_bits=16, anchor_bits=16
     for c in range(3):
         A_c = coordinate_matrix(frames_w, c)
         R = autocorrelation(A_c)
-        if omega is not None:
+        if learned is not None:
+            from .mlp_oracle import predict_start
+            Q0 = predict_start(R, learned[0], learned[1], kw)
+            Q, sweeps, resid = orthogonal_iterations(R, Q0, oi_tol, oi_max_sweeps)
+            lam, U = ritz(R, Q)
+        elif omega is not None:
             Q, sweeps, resid = orthogonal_iterations(R, R @ omega[:, :kw], oi_tol, oi_max_sweeps)
             lam, U = ritz(R, Q)
         elif q_start is None:
@@ -476,15 +483,17 @@ def decode_window(solver: AnchoredSolver, rec) -> np.ndarray:
 
 def compress_sequence(n, tris, frames, anchors, T, k, bits, *, laplacian_kind=LAP_UNIFORM,
                       dict_bits=16, anchor_bits=16, first_start=None, init="prev",
-                      starts=None, omega=None, oi_tol=1e-12, oi_max_sweeps=200, decode=True,
-                      fp32_data=False):
+                      starts=None, omega=None, learned=None, oi_tol=1e-12, oi_max_sweeps=200,
+                      decode=True, fp32_data=False):
     """Encode (and decode) every window.  Start of each full window's
     orthogonal iterations, by `init`:
       "prev"   window w > 0 from window w-1's U_k (Algorithm 1); window 0 from
                `first_start` ([3][T][k]) or, if None, its exact eigenvectors;
       "random" window w from starts[w] ([nw][3][T][k]);
       "sketch" every window from R_c omega (omega [T][k]);
-      "exact"  every window from its exact eigenvectors (Eq. 5).
+      "exact"  every window from its exact eigenvectors (Eq. 5);
+      "learned" every window from the perceptron's prediction, learned =
+               (Omega [T][32], theta).
     A short last window starts from its own exact eigenvectors.
     Returns (records, reconstruction or None)."""
     L = laplacian(n, tris, laplacian_kind)
@@ -501,8 +510,10 @@ def compress_sequence(n, tris, frames, anchors, T, k, bits, *, laplacian_kind=LA
             start = starts[wi]
         elif full and init == "sketch":
             om = omega
+        lrn = learned if (full and init == "learned") else None
         rec = encode_window(L, fw, anchors, k, bits, dict_bits=dict_bits,
-                            anchor_bits=anchor_bits, q_start=start, omega=om, oi_tol=oi_tol,
+                            anchor_bits=anchor_bits, q_start=start, omega=om, learned=lrn,
+                            oi_tol=oi_tol,
                             oi_max_sweeps=oi_max_sweeps, fp32_data=fp32_data)
         rec["start"] = s
         recs.append(rec)

@@ -5,8 +5,9 @@ bench.py's CPU-baseline leg, never by the library.
 
 The start block of a window's orthogonal iterations (Algorithm 1 takes any
 orthonormal start) is predicted from a sketch of the window's autocorrelation
-(Eq. 7): S = R Omega (Omega a fixed seeded Gaussian T x 32 block), scaled to
-||S||_F = sqrt(T), mapped row by row by a three-layer perceptron
+(Eq. 7): R Omega (Omega a fixed seeded Gaussian T x 32 block) with its
+columns orthonormalised and scaled by sqrt(T), mapped row by row by a
+three-layer perceptron
     h1 = gelu(S W1 + b1)      32 -> 128
     h2 = gelu(h1 W2 + b2)    128 -> 128
     Q  = h2 W3 + b3          128 -> k
@@ -66,13 +67,30 @@ def bf16_round(x: np.ndarray) -> np.ndarray:
     return out
 
 
+SKETCH_DROP = 1e-10  # a sketch column with less than this fraction of its norm
+                     # left after projection carries no direction: zeroed
+
+
 def sketch(R: np.ndarray, omega: np.ndarray) -> np.ndarray:
-    """S = R Omega scaled to Frobenius norm sqrt(T) (the subspace of S, which
-    is what the start is predicted from, does not depend on the scale)."""
+    """Input rows of the network: the sketch R Omega with orthonormalised
+    columns, scaled by sqrt(T) (entries of order one).  The columns of R Omega
+    differ in size by the eigenvalue spread of R; orthonormalising exposes the
+    smaller directions.  Classical Gram-Schmidt run twice per column, in
+    column order; a column keeping less than SKETCH_DROP of its norm after the
+    projections is set to zero (and projects nothing out of later columns)."""
     S = np.asarray(R, dtype=np.float64) @ np.asarray(omega, dtype=np.float64)
-    nrm = np.linalg.norm(S)
-    T = S.shape[0]
-    return S * (math.sqrt(T) / nrm) if nrm > 0 else S
+    T, m = S.shape
+    Q = np.zeros_like(S)
+    for j in range(m):
+        v = S[:, j].copy()
+        n0 = math.sqrt(float(v @ v))
+        for _ in range(2):
+            d = Q[:, :j].T @ v
+            v = v - Q[:, :j] @ d
+        nj = math.sqrt(float(v @ v))
+        if n0 > 0.0 and nj > SKETCH_DROP * n0:
+            Q[:, j] = v / nj
+    return Q * math.sqrt(T)
 
 
 def _Phi(x: np.ndarray) -> np.ndarray:

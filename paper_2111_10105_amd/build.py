@@ -14,7 +14,7 @@ OUT = os.path.join(HERE, "libdmc.so")
 OBJ = os.path.join(HERE, "_build")
 
 SOURCES = ["abi.cpp", "mesh_host.cpp", "chol_host.cpp", "profile.cpp", "kernels_encode.hip",
-           "kernels_oi.hip", "kernels_decode.hip", "kernels_chol.hip"]
+           "kernels_oi.hip", "kernels_decode.hip", "kernels_chol.hip", "kernels_mlp.hip"]
 
 # packed FP32 instructions are disabled (the compiler would otherwise form them
 # from ordinary float code)

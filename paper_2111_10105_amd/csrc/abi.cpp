@@ -22,6 +22,10 @@ struct dmc_ctx_s {
   void* stats = nullptr;   // per-window device stats (kept apart from scratch)
   size_t stats_bytes = 0;
   std::vector<dmc_mesh_s*> meshes;
+  // learned start registered by dmc_learned_start (caller-owned device memory)
+  int32_t learned_T = 0, learned_k = 0;
+  const double* learned_omega = nullptr;
+  const float* learned_theta = nullptr;
 };
 
 struct dmc_mesh_s {
@@ -126,7 +130,7 @@ dmc_status check_params(const dmc_params* p, int32_t T, bool for_decode = false)
   for (int32_t b : {p->coef_bits, p->anchor_bits, p->dict_bits})
     if (b < 0 || b > 16) return fail(DMC_ERR_INVALID_ARG, "bits must be in 0..16");
   if (!for_decode) {
-    if (p->init < DMC_INIT_PREV || p->init > DMC_INIT_EXACT)
+    if (p->init < DMC_INIT_PREV || p->init > DMC_INIT_LEARNED)
       return fail(DMC_ERR_INVALID_ARG, "unknown init");
     if (p->oi_max_sweeps < 1) return fail(DMC_ERR_INVALID_ARG, "oi_max_sweeps must be >= 1");
     if (!(p->oi_tol >= 0.0)) return fail(DMC_ERR_INVALID_ARG, "oi_tol must be >= 0");
@@ -165,9 +169,21 @@ dmc_status encode_chain(dmc_ctx ctx, const dmc::MeshDev& m, const void* frames, 
   cur += dmc::align_up(dmc::autocorr_scratch_bytes(m.n, T, nw, p.precision));
   double* u_tilde = (double*)cur;
   cur += dmc::align_up((size_t)nw * 3 * T * k * 8);
+  float* sk = nullptr;
+  float* ql = nullptr;
+  if (p.init == DMC_INIT_LEARNED) {
+    sk = (float*)cur;
+    cur += dmc::align_up((size_t)nw * 3 * T * 32 * 4);
+    ql = (float*)cur;
+    cur += dmc::align_up((size_t)nw * 3 * T * k * 4);
+  }
   void* proj = cur;
   for (int32_t w = 0; w < nw; ++w) dmc::launch_write_header(s, records + (size_t)w * lay.bytes, lay);
   dmc::launch_autocorr(s, frames, m.n, T, nw, p.precision, part, R);
+  if (p.init == DMC_INIT_LEARNED) {
+    dmc::launch_mlp_sketch(s, R, nw * 3, T, ctx->learned_omega, sk);
+    dmc::launch_mlp_forward(s, ctx->learned_theta, k, sk, nw * 3 * T, ql, nullptr);
+  }
   dmc::OiArgs oa;
   oa.R = R;
   oa.nw = nw;
@@ -176,7 +192,9 @@ dmc_status encode_chain(dmc_ctx ctx, const dmc::MeshDev& m, const void* frames, 
   oa.precision = p.precision;
   oa.dict_bits = p.dict_bits;
   oa.init = p.init;
+  oa.ncoord = 3;
   oa.q_start = p.init == DMC_INIT_EXACT ? nullptr : q_start;
+  oa.q_learned = ql;
   oa.u_out = u_out;
   oa.u_tilde = u_tilde;
   oa.records = records;
@@ -192,11 +210,26 @@ dmc_status encode_chain(dmc_ctx ctx, const dmc::MeshDev& m, const void* frames, 
   return check_launch("encode kernels");
 }
 
-size_t chain_scratch_bytes(int32_t n, int32_t T, int32_t nw, int32_t k, int32_t precision) {
+size_t chain_scratch_bytes(int32_t n, int32_t T, int32_t nw, int32_t k, int32_t precision,
+                           int32_t init) {
+  const size_t learned = init == DMC_INIT_LEARNED
+                             ? dmc::align_up((size_t)nw * 3 * T * 32 * 4) +
+                                   dmc::align_up((size_t)nw * 3 * T * k * 4)
+                             : 0;
   return dmc::align_up((size_t)nw * 3 * T * T * 8) +
          dmc::align_up(dmc::autocorr_scratch_bytes(n, T, nw, precision)) +
-         dmc::align_up((size_t)nw * 3 * T * k * 8) +
+         dmc::align_up((size_t)nw * 3 * T * k * 8) + learned +
          dmc::align_up(dmc::project_scratch_bytes(n, T, k, nw, precision));
+}
+
+// The learned start needs a network registered for this window length and k.
+dmc_status check_learned(dmc_ctx ctx, const dmc_params& p, int32_t T) {
+  if (p.init != DMC_INIT_LEARNED) return DMC_OK;
+  if (!ctx->learned_theta || !ctx->learned_omega)
+    return fail(DMC_ERR_INVALID_ARG, "DMC_INIT_LEARNED needs dmc_learned_start first");
+  if (ctx->learned_T != T || ctx->learned_k != std::min(p.k, T))
+    return fail(DMC_ERR_INVALID_ARG, "the registered learned start is for another T or k");
+  return DMC_OK;
 }
 
 // Decode every window of a sequence in one solve over 3F columns.
@@ -583,7 +616,9 @@ dmc_status dmc_encode_window(dmc_ctx ctx, dmc_mesh mesh, const void* frames, int
   const dmc::RecordLayout lay = dmc::record_layout(m.n, T, p.k, m.nc, p);
   Carve cv;
   const size_t o_delta = cv.add((size_t)T * 3 * m.n * real_size(p.precision));
-  const size_t o_chain = cv.add(chain_scratch_bytes(m.n, T, 1, p.k, p.precision));
+  st = check_learned(ctx, p, T);
+  if (st != DMC_OK) return st;
+  const size_t o_chain = cv.add(chain_scratch_bytes(m.n, T, 1, p.k, p.precision, p.init));
   st = ensure_scratch(ctx, cv.total());
   if (st != DMC_OK) return st;
   st = ensure_stats(ctx, sizeof(dmc::StatsDev));
@@ -684,11 +719,17 @@ dmc_status dmc_compress_sequence(dmc_ctx ctx, dmc_mesh mesh, const void* frames,
   const int32_t k_full = std::min(p.k, T);
   Carve cv;
   const size_t o_delta = cv.add((size_t)F * 3 * m.n * real_size(p.precision));
+  if (sl.nw_full) {
+    st = check_learned(ctx, p, T);
+    if (st != DMC_OK) return st;
+  }
+  dmc_params p_tail = p;  // a shorter last window starts from its exact eigenvectors
+  p_tail.init = DMC_INIT_EXACT;
   const size_t o_full = cv.add(sl.nw_full ? chain_scratch_bytes(m.n, T, sl.nw_full, k_full,
-                                                                 p.precision)
+                                                                 p.precision, p.init)
                                           : 0);
   const size_t o_tail = cv.add(sl.T_tail ? chain_scratch_bytes(m.n, sl.T_tail, 1, sl.tail.k,
-                                                                 p.precision)
+                                                                 p.precision, p_tail.init)
                                          : 0);
   st = ensure_scratch(ctx, cv.total());
   if (st != DMC_OK) return st;
@@ -707,7 +748,7 @@ dmc_status dmc_compress_sequence(dmc_ctx ctx, dmc_mesh mesh, const void* frames,
   if (sl.T_tail) {
     const size_t f0 = (size_t)sl.nw_full * T;
     st = encode_chain(ctx, m, (const uint8_t*)frames + f0 * 3 * m.n * rs, sl.T_tail, 1, sl.tail.k,
-                      p, nullptr, (uint8_t*)codes + (size_t)sl.nw_full * sl.full.bytes, sl.tail,
+                      p_tail, nullptr, (uint8_t*)codes + (size_t)sl.nw_full * sl.full.bytes, sl.tail,
                       nullptr, nullptr, (const uint8_t*)delta + f0 * 3 * m.n * rs, ws + o_tail,
                       sd + sl.nw_full);
     if (st != DMC_OK) return st;
@@ -763,3 +804,153 @@ dmc_status dmc_autocorrelation(dmc_ctx ctx, dmc_mesh mesh, const void* frames, i
 }
 
 }  // extern "C"
+
+// ---- learned start ---------------------------------------------------------
+
+int32_t dmc_mlp_param_count(int32_t k) { return (k < 1 || k > 32) ? 0 : dmc::mlp_param_count(k); }
+
+dmc_status dmc_learned_start(dmc_ctx ctx, int32_t T, int32_t k, const double* omega,
+                             const float* theta) {
+  if (!ctx) return fail(DMC_ERR_INVALID_ARG, "NULL context");
+  if (!omega || !theta) {
+    ctx->learned_omega = nullptr;
+    ctx->learned_theta = nullptr;
+    ctx->learned_T = ctx->learned_k = 0;
+    return DMC_OK;
+  }
+  if (T < 1 || T > 64 || k < 1 || k > 32 || k > T)
+    return fail(DMC_ERR_INVALID_ARG, "need 1 <= k <= min(T, 32) and T <= 64");
+  ctx->learned_T = T;
+  ctx->learned_k = k;
+  ctx->learned_omega = omega;
+  ctx->learned_theta = theta;
+  return DMC_OK;
+}
+
+dmc_status dmc_mlp_sketch(dmc_ctx ctx, const double* R, int32_t nb, int32_t T, const double* omega,
+                          float* S) {
+  if (!ctx || !R || !omega || !S) return fail(DMC_ERR_INVALID_ARG, "NULL argument");
+  if (nb < 0 || T < 1 || T > 64) return fail(DMC_ERR_INVALID_ARG, "need nb >= 0 and T in 1..64");
+  if (nb == 0) return DMC_OK;
+  HIP_TRY(hipSetDevice(ctx->device));
+  dmc::launch_mlp_sketch(ctx->stream, R, nb, T, omega, S);
+  return check_launch("mlp sketch");
+}
+
+dmc_status dmc_mlp_forward(dmc_ctx ctx, const float* theta, int32_t k, const float* S, int32_t N,
+                           float* Q, float* cache) {
+  if (!ctx || !theta || !S || !Q) return fail(DMC_ERR_INVALID_ARG, "NULL argument");
+  if (k < 1 || k > 32 || N < 0) return fail(DMC_ERR_INVALID_ARG, "need k in 1..32 and N >= 0");
+  if (N == 0) return DMC_OK;
+  HIP_TRY(hipSetDevice(ctx->device));
+  dmc::launch_mlp_forward(ctx->stream, theta, k, S, N, Q, cache);
+  return check_launch("mlp forward");
+}
+
+dmc_status dmc_mlp_loss_grad(dmc_ctx ctx, const float* Q, const double* U, int32_t nb, int32_t T,
+                             int32_t k, double mu, float* dQ, double* loss) {
+  if (!ctx || !Q || !U || !dQ) return fail(DMC_ERR_INVALID_ARG, "NULL argument");
+  if (nb < 1 || T < 1 || T > 64 || k < 1 || k > 32 || k > T)
+    return fail(DMC_ERR_INVALID_ARG, "need nb >= 1, T in 1..64, 1 <= k <= min(T, 32)");
+  if (!(mu >= 0.0)) return fail(DMC_ERR_INVALID_ARG, "mu must be >= 0");
+  HIP_TRY(hipSetDevice(ctx->device));
+  dmc::launch_mlp_loss(ctx->stream, Q, U, T, k, nb, mu, dQ, loss);
+  return check_launch("mlp loss");
+}
+
+dmc_status dmc_mlp_backward(dmc_ctx ctx, const float* theta, int32_t k, const float* S, int32_t N,
+                            const float* cache, const float* dQ, float* grad) {
+  if (!ctx || !theta || !S || !cache || !dQ || !grad)
+    return fail(DMC_ERR_INVALID_ARG, "NULL argument");
+  if (k < 1 || k > 32 || N < 1) return fail(DMC_ERR_INVALID_ARG, "need k in 1..32 and N >= 1");
+  HIP_TRY(hipSetDevice(ctx->device));
+  Carve cv;
+  const size_t o_part = cv.add((size_t)dmc::mlp_bwd_parts() * dmc::mlp_param_count(k) * sizeof(float));
+  const size_t o_dz = cv.add((size_t)N * 256 * sizeof(float));
+  dmc_status st = ensure_scratch(ctx, cv.total());
+  if (st != DMC_OK) return st;
+  uint8_t* ws = (uint8_t*)ctx->scratch;
+  dmc::launch_mlp_backward(ctx->stream, theta, k, S, N, cache, dQ, (float*)(ws + o_dz),
+                           (float*)(ws + o_part), grad);
+  return check_launch("mlp backward");
+}
+
+dmc_status dmc_mlp_adam(dmc_ctx ctx, float* theta, const float* grad, float* m, float* v,
+                        int32_t count, int32_t step, double lr, double beta1, double beta2,
+                        double eps) {
+  if (!ctx || !theta || !grad || !m || !v) return fail(DMC_ERR_INVALID_ARG, "NULL argument");
+  if (count < 1 || step < 1 || !(lr > 0.0) || !(beta1 >= 0.0 && beta1 < 1.0) ||
+      !(beta2 >= 0.0 && beta2 < 1.0) || !(eps >= 0.0))
+    return fail(DMC_ERR_INVALID_ARG, "bad Adam arguments");
+  HIP_TRY(hipSetDevice(ctx->device));
+  dmc::launch_mlp_adam(ctx->stream, theta, grad, m, v, count, step, lr, beta1, beta2, eps);
+  return check_launch("mlp adam");
+}
+
+// ---- orthogonal iterations on independent covariance blocks ----------------
+
+dmc_status dmc_oi_blocks(dmc_ctx ctx, const double* R, int32_t nb, int32_t T,
+                         const dmc_params* params, const void* q_start, double* U_out,
+                         int32_t* sweeps, double* resid) {
+  if (!ctx || !R || !U_out) return fail(DMC_ERR_INVALID_ARG, "NULL argument");
+  if (nb < 1) return fail(DMC_ERR_INVALID_ARG, "nb must be >= 1");
+  dmc_status st = check_params(params, T);
+  if (st != DMC_OK) return st;
+  const dmc_params& p = *params;
+  if (p.k > T) return fail(DMC_ERR_INVALID_ARG, "k must not exceed T");
+  if (p.init == DMC_INIT_PREV)
+    return fail(DMC_ERR_INVALID_ARG, "independent blocks take DMC_INIT_RANDOM, _SKETCH, _EXACT "
+                                     "or _LEARNED");
+  if ((p.init == DMC_INIT_RANDOM || p.init == DMC_INIT_SKETCH) && !q_start)
+    return fail(DMC_ERR_INVALID_ARG, "DMC_INIT_RANDOM and DMC_INIT_SKETCH need q_start");
+  st = check_learned(ctx, p, T);
+  if (st != DMC_OK) return st;
+  HIP_TRY(hipSetDevice(ctx->device));
+  Carve cv;
+  const bool learned = p.init == DMC_INIT_LEARNED;
+  const size_t o_s = cv.add(learned ? (size_t)nb * T * 32 * 4 : 0);
+  const size_t o_q = cv.add(learned ? (size_t)nb * T * p.k * 4 : 0);
+  st = ensure_scratch(ctx, cv.total());
+  if (st != DMC_OK) return st;
+  st = ensure_stats(ctx, sizeof(dmc::StatsDev) * nb);
+  if (st != DMC_OK) return st;
+  uint8_t* ws = (uint8_t*)ctx->scratch;
+  if (learned) {
+    dmc::launch_mlp_sketch(ctx->stream, R, nb, T, ctx->learned_omega, (float*)(ws + o_s));
+    dmc::launch_mlp_forward(ctx->stream, ctx->learned_theta, p.k, (const float*)(ws + o_s), nb * T,
+                            (float*)(ws + o_q), nullptr);
+  }
+  dmc::OiArgs oa{};
+  oa.R = R;
+  oa.nw = nb;
+  oa.T = T;
+  oa.k = p.k;
+  oa.precision = DMC_FP64;  // blocks and outputs are float64
+  oa.dict_bits = 0;
+  oa.init = p.init;
+  oa.ncoord = 1;
+  oa.q_start = p.init == DMC_INIT_EXACT ? nullptr : q_start;
+  oa.q_learned = learned ? (const float*)(ws + o_q) : nullptr;
+  oa.u_out = U_out;
+  oa.u_tilde = nullptr;
+  oa.records = nullptr;
+  oa.max_sweeps = p.oi_max_sweeps;
+  oa.tol = p.oi_tol;
+  oa.stats = (dmc::StatsDev*)ctx->stats;
+  dmc::launch_oi(ctx->stream, oa);
+  st = check_launch("oi blocks");
+  if (st != DMC_OK) return st;
+  if (sweeps || resid) {
+    st = ensure_pinned(ctx, sizeof(dmc::StatsDev) * nb);
+    if (st != DMC_OK) return st;
+    HIP_TRY(hipMemcpyAsync(ctx->pinned, ctx->stats, sizeof(dmc::StatsDev) * nb,
+                           hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    const dmc::StatsDev* hs = (const dmc::StatsDev*)ctx->pinned;
+    for (int32_t b = 0; b < nb; ++b) {
+      if (sweeps) sweeps[b] = hs[b].sweeps[0];
+      if (resid) resid[b] = hs[b].resid[0];
+    }
+  }
+  return DMC_OK;
+}

@@ -99,10 +99,12 @@ struct OiArgs {
   int32_t precision;
   int32_t dict_bits;
   int32_t init;          // DMC_INIT_*
+  int32_t ncoord;        // blocks per window: 3 (x, y, z), or 1 for independent blocks
   const void* q_start;   // per init: [3][T][k], [nw][3][T][k] or Omega [T][k] (real)
-  void* u_out;           // [nw][3][T][k] real (may be nullptr)
-  double* u_tilde;       // [nw][3][T][k] float64 dequantised dictionary
-  uint8_t* records;      // record of window w at records + w*rec_bytes
+  const float* q_learned;  // DMC_INIT_LEARNED: [nw][ncoord][T][k] predicted starts
+  void* u_out;           // [nw][ncoord][T][k] real (may be nullptr)
+  double* u_tilde;       // [nw][ncoord][T][k] float64 dequantised dictionary (or nullptr)
+  uint8_t* records;      // record of window w at records + w*rec_bytes (or nullptr)
   size_t rec_bytes;
   size_t off_dict;
   int32_t max_sweeps;
@@ -110,6 +112,20 @@ struct OiArgs {
   StatsDev* stats;       // [nw]
 };
 void launch_oi(hipStream_t s, const OiArgs& a);
+
+// Learned start (row-wise perceptron on the sketch R Omega).
+int mlp_param_count(int k);
+int mlp_bwd_parts();
+void launch_mlp_sketch(hipStream_t s, const double* R, int nb, int T, const double* omega, float* S);
+void launch_mlp_forward(hipStream_t s, const float* theta, int k, const float* S, int N, float* Q,
+                        float* cache);
+void launch_mlp_loss(hipStream_t s, const float* Q, const double* U, int T, int k, int nb, double mu,
+                     float* dQ, double* loss);
+void launch_mlp_backward(hipStream_t s, const float* theta, int k, const float* S, int N,
+                         const float* cache, const float* dQ, float* dZ, float* partial,
+                         float* grad);
+void launch_mlp_adam(hipStream_t s, float* theta, const float* grad, float* m, float* v, int count,
+                     int step, double lr, double b1, double b2, double eps);
 
 // Projection (Eq. 9) + per-row ranges + quantisation (Eq. 10) for nw windows.
 size_t project_scratch_bytes(int32_t n, int32_t T, int32_t k, int32_t nw, int32_t precision);

@@ -779,7 +779,7 @@ __global__ void __launch_bounds__(NT) k_oi(OiArgs a) {
   const int w_end = chain ? a.nw : w_begin + 1;
   for (int w = w_begin; w < w_end; ++w) {
     // ---- load R_c of window w (zero padded), every load in flight at once ----
-    const double* Rg = a.R + ((size_t)w * 3 + c) * T * T;
+    const double* Rg = a.R + ((size_t)w * a.ncoord + c) * T * T;
     constexpr int PER = TMAX * TMAX / NT;
     double rv[PER];
 #pragma unroll
@@ -801,7 +801,8 @@ __global__ void __launch_bounds__(NT) k_oi(OiArgs a) {
     double resid = 0.0;
     // exact start: always with DMC_INIT_EXACT, else for a missing start block
     // (window 0 of the chain; any window otherwise)
-    const bool exact = a.init == DMC_INIT_EXACT || (a.q_start == nullptr && (w == 0 || !chain));
+    const bool exact = a.init == DMC_INIT_EXACT ||
+                       (a.init != DMC_INIT_LEARNED && a.q_start == nullptr && (w == 0 || !chain));
     if (exact) {
       // exact start of Algorithm 1: eigenvectors of R (Eq. 5)
       for (int e = tid; e < TMAX * s.LR; e += NT) s.A[e] = s.R[e];
@@ -824,15 +825,25 @@ __global__ void __launch_bounds__(NT) k_oi(OiArgs a) {
       if (!chain || w == 0) {
         // caller-given start (window 0 of the chain, or this window's own
         // block), or Omega for the sketch start R_c Omega
-        const Real* q0 = (const Real*)a.q_start;
-        if (a.init == DMC_INIT_RANDOM) q0 += ((size_t)w * 3 + c) * T * k;
-        else if (a.init != DMC_INIT_SKETCH) q0 += (size_t)c * T * k;
         constexpr int PQ = TMAX * KR / NT;
         double qv[PQ];
+        if (a.init == DMC_INIT_LEARNED) {
+          // the network's prediction for this (window, coordinate)
+          const float* ql = a.q_learned + ((size_t)w * a.ncoord + c) * T * k;
 #pragma unroll
-        for (int u = 0; u < PQ; ++u) {
-          const int e = tid + u * NT;
-          qv[u] = e < T * k ? (double)q0[e] : 0.0;
+          for (int u = 0; u < PQ; ++u) {
+            const int e = tid + u * NT;
+            qv[u] = e < T * k ? (double)ql[e] : 0.0;
+          }
+        } else {
+          const Real* q0 = (const Real*)a.q_start;
+          if (a.init == DMC_INIT_RANDOM) q0 += ((size_t)w * a.ncoord + c) * T * k;
+          else if (a.init != DMC_INIT_SKETCH) q0 += (size_t)c * T * k;
+#pragma unroll
+          for (int u = 0; u < PQ; ++u) {
+            const int e = tid + u * NT;
+            qv[u] = e < T * k ? (double)q0[e] : 0.0;
+          }
         }
 #pragma unroll
         for (int u = 0; u < PQ; ++u) {
@@ -850,12 +861,13 @@ __global__ void __launch_bounds__(NT) k_oi(OiArgs a) {
       sign_fix(s, T, k);
     }
     // ---- outputs: U, dictionary codes, dequantised dictionary ----
-    Real* uo = a.u_out ? (Real*)a.u_out + ((size_t)w * 3 + c) * T * k : nullptr;
-    double* ut = a.u_tilde + ((size_t)w * 3 + c) * T * k;
-    uint8_t* rec = a.records + (size_t)w * a.rec_bytes + a.off_dict;
+    Real* uo = a.u_out ? (Real*)a.u_out + ((size_t)w * a.ncoord + c) * T * k : nullptr;
+    double* ut = a.u_tilde ? a.u_tilde + ((size_t)w * a.ncoord + c) * T * k : nullptr;
+    uint8_t* rec = a.records ? a.records + (size_t)w * a.rec_bytes + a.off_dict : nullptr;
     for (int e = tid; e < T * k; e += NT) {
       const double u = s.Y[(e / k) * s.LQ + e % k];
       if (uo) uo[e] = (Real)u;
+      if (!rec) continue;  // subspace only (no record)
       if (a.dict_bits > 0) {
         const uint16_t code = quant<Real>(u, -1.0, 1.0, a.dict_bits);
         ((uint16_t*)rec)[(size_t)c * T * k + e] = code;
@@ -880,7 +892,7 @@ __global__ void __launch_bounds__(NT) k_oi(OiArgs a) {
 
 template <int TMAX, int KR>
 void launch_oi_t(hipStream_t st, const OiArgs& a) {
-  const dim3 grid(3, a.init == DMC_INIT_PREV ? 1 : a.nw);
+  const dim3 grid(a.ncoord, a.init == DMC_INIT_PREV ? 1 : a.nw);
   if (a.precision == DMC_FP64)
     hipLaunchKernelGGL((k_oi<TMAX, 32, KR, double>), grid, dim3(NT), 0, st, a);
   else

@@ -22,14 +22,16 @@ STATUS = {0: "OK", 1: "INVALID_ARG", 2: "OUT_OF_MEMORY", 3: "DEVICE", 4: "NOT_CO
 FP64, FP32 = 0, 1
 LAP_UNIFORM, LAP_COMBINATORIAL = 0, 1
 PRECOND_NONE, PRECOND_JACOBI, PRECOND_CHOLESKY = 0, 1, 2
-INIT_PREV, INIT_RANDOM, INIT_SKETCH, INIT_EXACT = 0, 1, 2, 3
+INIT_PREV, INIT_RANDOM, INIT_SKETCH, INIT_EXACT, INIT_LEARNED = 0, 1, 2, 3, 4
 
 EXPORTS = ["dmc_create", "dmc_destroy", "dmc_set_stream", "dmc_last_error", "dmc_scratch_bytes",
            "dmc_mesh_create", "dmc_mesh_destroy", "dmc_mesh_nnz", "dmc_mesh_normal_nnz",
            "dmc_mesh_factor_info", "dmc_host_normal_solve",
            "dmc_window_code_bytes", "dmc_sequence_code_bytes", "dmc_encode_window",
            "dmc_decode_window", "dmc_compress_sequence", "dmc_decode_sequence", "dmc_delta",
-           "dmc_autocorrelation", "dmc_profile_start", "dmc_profile_stop"]
+           "dmc_autocorrelation", "dmc_profile_start", "dmc_profile_stop", "dmc_oi_blocks",
+           "dmc_mlp_param_count", "dmc_learned_start", "dmc_mlp_sketch", "dmc_mlp_forward",
+           "dmc_mlp_loss_grad", "dmc_mlp_backward", "dmc_mlp_adam"]
 
 KERNELS = ["delta", "autocorr", "oi", "project", "quantise", "anchors", "back_project", "rhs",
            "cg_spmm", "cg_update", "chol_fwd_gather", "chol_fwd_solve", "chol_bwd_gather",
@@ -115,6 +117,14 @@ def lib():
         "dmc_autocorrelation": (i32, [vp, vp, vp, i32, i32, vp]),
         "dmc_profile_start": (i32, [i32]),
         "dmc_profile_stop": (i32, [ctypes.POINTER(i32), ctypes.POINTER(dbl)]),
+        "dmc_oi_blocks": (i32, [vp, vp, i32, i32, P, vp, vp, vp, vp]),
+        "dmc_mlp_param_count": (i32, [i32]),
+        "dmc_learned_start": (i32, [vp, i32, i32, vp, vp]),
+        "dmc_mlp_sketch": (i32, [vp, vp, i32, i32, vp, vp]),
+        "dmc_mlp_forward": (i32, [vp, vp, i32, vp, i32, vp, vp]),
+        "dmc_mlp_loss_grad": (i32, [vp, vp, vp, i32, i32, i32, dbl, vp, vp]),
+        "dmc_mlp_backward": (i32, [vp, vp, i32, vp, i32, vp, vp, vp]),
+        "dmc_mlp_adam": (i32, [vp, vp, vp, vp, vp, i32, i32, dbl, dbl, dbl, dbl]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -389,3 +399,113 @@ def parse_record(buf: np.ndarray, n: int, T: int, nc: int, params: Params) -> Re
     del rs
     return RecordView(hdr, dct, rng if params.coef_bits > 0 else None, cod,
                       arg if params.anchor_bits > 0 else None, anc)
+
+
+# ---- orthogonal iterations on independent blocks, learned start ------------
+
+def _need(t, dtype, shape, name):
+    import torch
+    if t.dtype != dtype or tuple(t.shape) != tuple(shape) or not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous CUDA {dtype} tensor of shape {tuple(shape)}, "
+                         f"got {t.dtype} {tuple(t.shape)}")
+
+
+def oi_blocks(ctx: Context, R, params: Params, q_start=None):
+    """Orthogonal iterations + Ritz step on independent blocks R float64
+    [nb][T][T]; returns (U float64 [nb][T][k], sweeps, residuals) as
+    (tensor, numpy int32, numpy float64)."""
+    import torch
+    nb, T = R.shape[0], R.shape[1]
+    _need(R, torch.float64, (nb, T, T), "R")
+    k = params.k
+    if q_start is not None:
+        want = (T, k) if params.init == INIT_SKETCH else (nb, T, k)
+        _need(q_start, torch.float64, want, "q_start")
+    ctx.sync_stream()
+    U = torch.empty((nb, T, k), dtype=torch.float64, device=R.device)
+    sweeps = np.zeros(nb, dtype=np.int32)
+    resid = np.zeros(nb, dtype=np.float64)
+    _check(lib().dmc_oi_blocks(ctx.h, _ptr(R), nb, T, ctypes.byref(params), _ptr(q_start), _ptr(U),
+                               sweeps.ctypes.data_as(ctypes.c_void_p),
+                               resid.ctypes.data_as(ctypes.c_void_p)))
+    return U, sweeps, resid
+
+
+def mlp_param_count(k: int) -> int:
+    return int(lib().dmc_mlp_param_count(int(k)))
+
+
+def learned_start(ctx: Context, T: int, k: int, omega, theta):
+    """Register (omega float64 [T][32], theta float32) for INIT_LEARNED; the
+    context keeps references to both tensors.  None unregisters."""
+    import torch
+    if omega is None or theta is None:
+        _check(lib().dmc_learned_start(ctx.h, 0, 0, None, None))
+        ctx._learned = None
+        return
+    _need(omega, torch.float64, (T, 32), "omega")
+    _need(theta, torch.float32, (mlp_param_count(k),), "theta")
+    _check(lib().dmc_learned_start(ctx.h, int(T), int(k), _ptr(omega), _ptr(theta)))
+    ctx._learned = (omega, theta)
+
+
+def mlp_sketch(ctx: Context, R, omega):
+    import torch
+    nb, T = R.shape[0], R.shape[1]
+    _need(R, torch.float64, (nb, T, T), "R")
+    _need(omega, torch.float64, (T, 32), "omega")
+    ctx.sync_stream()
+    S = torch.empty((nb, T, 32), dtype=torch.float32, device=R.device)
+    _check(lib().dmc_mlp_sketch(ctx.h, _ptr(R), nb, T, _ptr(omega), _ptr(S)))
+    return S
+
+
+def mlp_forward(ctx: Context, theta, k: int, S, cache: bool = False):
+    """Rows of S float32 [N][32] (any leading shape) -> Q float32 [N][k];
+    with cache=True also the pre-activations [N][256] for mlp_backward."""
+    import torch
+    N = S.numel() // 32
+    _need(theta, torch.float32, (mlp_param_count(k),), "theta")
+    if S.dtype != torch.float32 or not S.is_contiguous() or S.shape[-1] != 32:
+        raise ValueError("S must be contiguous float32 with 32 columns")
+    ctx.sync_stream()
+    Q = torch.empty((N, k), dtype=torch.float32, device=S.device)
+    C = torch.empty((N, 256), dtype=torch.float32, device=S.device) if cache else None
+    _check(lib().dmc_mlp_forward(ctx.h, _ptr(theta), int(k), _ptr(S), N, _ptr(Q), _ptr(C)))
+    return (Q, C) if cache else Q
+
+
+def mlp_loss_grad(ctx: Context, Q, U, mu: float = 0.1):
+    """Q float32 and U float64, both [nb][T][k] -> (dQ float32 [nb][T][k],
+    per-block losses float64 [nb])."""
+    import torch
+    nb, T, k = U.shape
+    _need(U, torch.float64, (nb, T, k), "U")
+    _need(Q, torch.float32, (nb, T, k), "Q")
+    ctx.sync_stream()
+    dQ = torch.empty_like(Q)
+    loss = torch.empty(nb, dtype=torch.float64, device=Q.device)
+    _check(lib().dmc_mlp_loss_grad(ctx.h, _ptr(Q), _ptr(U), nb, T, k, float(mu), _ptr(dQ), _ptr(loss)))
+    return dQ, loss
+
+
+def mlp_backward(ctx: Context, theta, k: int, S, cache, dQ):
+    import torch
+    N = S.numel() // 32
+    _need(cache, torch.float32, (N, 256), "cache")
+    if dQ.numel() != N * k or dQ.dtype != torch.float32 or not dQ.is_contiguous():
+        raise ValueError("dQ must be contiguous float32 with N x k entries")
+    ctx.sync_stream()
+    g = torch.empty_like(theta)
+    _check(lib().dmc_mlp_backward(ctx.h, _ptr(theta), int(k), _ptr(S), N, _ptr(cache), _ptr(dQ),
+                                  _ptr(g)))
+    return g
+
+
+def mlp_adam(ctx: Context, theta, grad, m, v, step: int, lr: float, beta1: float = 0.9,
+             beta2: float = 0.999, eps: float = 1e-8):
+    """One Adam step in place on theta, m, v (float32 tensors of one size)."""
+    ctx.sync_stream()
+    _check(lib().dmc_mlp_adam(ctx.h, _ptr(theta), _ptr(grad), _ptr(m), _ptr(v), theta.numel(),
+                              int(step), float(lr), float(beta1), float(beta2), float(eps)))
+

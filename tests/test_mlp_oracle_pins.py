@@ -36,14 +36,30 @@ def test_bf16_round_matches_torch():
     assert M.bf16_round(np.array([1.0 + 3 * 2 ** -8]))[0] == 1.0 + 2 ** -6
 
 
-def test_sketch_scale_and_invariance():
+def test_sketch_is_scaled_q_factor_of_r_omega():
+    """On a well-conditioned sketch the features are sqrt(T) times LAPACK's Q
+    factor of R Omega (positive diagonal); scaling R changes nothing."""
     rng = np.random.default_rng(1)
-    A = rng.standard_normal((20, 300))
+    A = rng.standard_normal((40, 300))
     R = A @ A.T
-    om = rng.standard_normal((20, M.SKETCH))
+    om = rng.standard_normal((40, M.SKETCH))
     S = M.sketch(R, om)
-    assert abs(np.linalg.norm(S) - math.sqrt(20)) < 1e-12
-    np.testing.assert_allclose(M.sketch(7.5 * R, om), S, rtol=1e-13, atol=1e-14)
+    Qr, Rr = np.linalg.qr(R @ om)
+    Qr = Qr * np.sign(np.diag(Rr))
+    np.testing.assert_allclose(S, math.sqrt(40) * Qr, atol=1e-10)
+    np.testing.assert_allclose(S.T @ S / 40, np.eye(M.SKETCH), atol=1e-12)
+    np.testing.assert_allclose(M.sketch(7.5 * R, om), S, atol=1e-12)
+
+
+def test_sketch_drops_directions_without_content():
+    """A rank-5 R: the first five columns span range(R), the others are zero."""
+    rng = np.random.default_rng(2)
+    B = rng.standard_normal((24, 5))
+    R = B @ B.T
+    S = M.sketch(R, rng.standard_normal((24, M.SKETCH)))
+    assert np.all(np.linalg.norm(S[:, 5:], axis=0) == 0.0)
+    P = B @ np.linalg.pinv(B)
+    np.testing.assert_allclose(P @ S[:, :5], S[:, :5], atol=1e-10)
 
 
 @pytest.mark.parametrize("k", [4, 16, 32])
