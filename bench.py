@@ -125,6 +125,35 @@ def work_model(fam, *, n, F, T, k, nw, rs, ncols, nnz, m_nnz, finfo, sweeps_tota
     return None, None, None
 
 
+def train_learned_start(ctx, dmc, w, dev, mesh):
+    """Train the learned start on the GPU (outside the timed region) on windows
+    of other seeded RBF animations of the same torus, and register it."""
+    import numpy as np
+    import torch
+    from paper_2111_10105_amd import learned as L
+    from synth import animate, learned
+    t0 = time.perf_counter()
+    blocks = []
+    for seed in range(5000, 5006):
+        fr = torch.from_numpy(animate.rbf_skinning(w.verts, w.F, 6 + seed % 7, seed=seed,
+                                                   dtype=np.float32)).to(dev)
+        for w0 in range(0, w.F, w.T):
+            blocks.append(dmc.autocorrelation(ctx, mesh, fr[w0:w0 + w.T].contiguous(),
+                                              dmc.FP32).cpu().numpy())
+    R = np.concatenate(blocks)
+    R = R[np.random.default_rng(0).permutation(R.shape[0])]
+    omega = learned.sketch_omega(w.T, FIRST_START_SEED + 100)
+    k = min(w.k, w.T)
+    data = L.Dataset(ctx, R, omega, k)
+    theta, hist = L.train(ctx, data, learned.mlp_init(k, FIRST_START_SEED + 200), steps=400,
+                          batch=24, lr=2e-3)
+    dmc.learned_start(ctx, w.T, k, data.omega, theta)
+    ctx._bench_learned = (data, theta)
+    return {"blocks": int(R.shape[0]), "steps": 400, "loss_first": round(hist[0][1], 4),
+            "loss_last": round(hist[-1][1], 4), "seconds": round(time.perf_counter() - t0, 2),
+            "data": "seeded RBF animations 5000-5005 of the same torus"}
+
+
 def nmse(x, y) -> float:
     """sum (x - y)^2 / sum y^2 over every vertex, frame and coordinate."""
     import numpy as np
@@ -240,7 +269,9 @@ def main():
         "sketch": (dmc.INIT_SKETCH, torch.from_numpy(
             animate.gaussian_subspace(T, w.k, FIRST_START_SEED)[0].astype(np.float32)).to(dev)),
         "exact": (dmc.INIT_EXACT, None),
+        "learned": (dmc.INIT_LEARNED, None),
     }
+    train_info = train_learned_start(ctx, dmc, w, dev, mesh)
     by_init = {}
     for name, (mode, qs) in variants.items():
         pv = dmc.make_params(w.k, coef_bits=w.bits, precision=dmc.FP32, init=mode)
@@ -262,6 +293,8 @@ def main():
         by_init[name] = {"ms_per_step": round(msv, 4), "value": round(vf / (msv * 1e-3), 1),
                          "oi_sweeps_total": int(sum(sum(x["oi_sweeps"]) for x in stv)),
                          "nmse_vs_input": nmse(outv.cpu().numpy(), w.frames)}
+    by_init["learned"]["training"] = train_info
+    dmc.learned_start(ctx, 0, 0, None, None)
 
     model = dict(n=n, F=F, T=T, k=min(w.k, T), nw=nw, rs=4, ncols=3 * F, nnz=mesh.nnz,
                  m_nnz=mesh.normal_nnz, finfo=finfo, sweeps_total=sweeps_total)

@@ -54,8 +54,18 @@ typedef enum {
 } dmc_status;
 
 /* arithmetic of the encoder's GEMMs (frames dtype follows: FP64 -> double,
- * otherwise float) */
-enum { DMC_FP64 = 0, DMC_FP32 = 1 };
+ * otherwise float).  DMC_BF16 is the precision form: float32 frames; the
+ * covariance (Eq. 7) and the C.Q products of the orthogonal iterations take
+ * bfloat16 operands with float32 accumulation on the matrix cores; the
+ * iterations run with those products to a stage tolerance
+ * (DMC_BF16_STAGE_TOL, or oi_tol if larger), then refine with
+ * full-precision products (at least one sweep) until oi_tol, or until a
+ * sweep reduces the residual by less than a tenth (the bfloat16 covariance
+ * fixes its small eigen-directions only to its own rounding, and there the
+ * iterations stall); the k x k Cholesky factors and the Ritz eigen-solve
+ * stay float64; everything else is as DMC_FP32. */
+enum { DMC_FP64 = 0, DMC_FP32 = 1, DMC_BF16 = 2 };
+#define DMC_BF16_STAGE_TOL 3e-2
 
 /* Laplacian: Eq. (3) I - D^-1 C (default) or Eq. (1) D - C */
 enum { DMC_LAP_UNIFORM = 0, DMC_LAP_COMBINATORIAL = 1 };

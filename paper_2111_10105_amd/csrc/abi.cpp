@@ -125,8 +125,8 @@ dmc_status check_params(const dmc_params* p, int32_t T, bool for_decode = false)
   if (!p) return fail(DMC_ERR_INVALID_ARG, "params is NULL");
   if (T < 1 || T > 64) return fail(DMC_ERR_INVALID_ARG, "window length T must be in 1..64");
   if (p->k < 1 || p->k > 32) return fail(DMC_ERR_INVALID_ARG, "k must be in 1..32");
-  if (p->precision != DMC_FP64 && p->precision != DMC_FP32)
-    return fail(DMC_ERR_INVALID_ARG, "precision must be DMC_FP64 or DMC_FP32");
+  if (p->precision != DMC_FP64 && p->precision != DMC_FP32 && p->precision != DMC_BF16)
+    return fail(DMC_ERR_INVALID_ARG, "precision must be DMC_FP64, DMC_FP32 or DMC_BF16");
   for (int32_t b : {p->coef_bits, p->anchor_bits, p->dict_bits})
     if (b < 0 || b > 16) return fail(DMC_ERR_INVALID_ARG, "bits must be in 0..16");
   if (!for_decode) {
@@ -782,7 +782,7 @@ dmc_status dmc_delta(dmc_ctx ctx, dmc_mesh mesh, const void* frames, int32_t F, 
                      void* out) {
   if (!ctx || !mesh || !frames || !out) return fail(DMC_ERR_INVALID_ARG, "NULL argument");
   if (F < 1) return fail(DMC_ERR_INVALID_ARG, "F must be >= 1");
-  if (precision != DMC_FP64 && precision != DMC_FP32)
+  if (precision != DMC_FP64 && precision != DMC_FP32 && precision != DMC_BF16)
     return fail(DMC_ERR_INVALID_ARG, "bad precision");
   HIP_TRY(hipSetDevice(ctx->device));
   dmc::launch_delta(ctx->stream, mesh->dev, frames, out, F, precision);
@@ -793,7 +793,7 @@ dmc_status dmc_autocorrelation(dmc_ctx ctx, dmc_mesh mesh, const void* frames, i
                                int32_t precision, void* R_out) {
   if (!ctx || !mesh || !frames || !R_out) return fail(DMC_ERR_INVALID_ARG, "NULL argument");
   if (T < 1 || T > 64) return fail(DMC_ERR_INVALID_ARG, "T must be in 1..64");
-  if (precision != DMC_FP64 && precision != DMC_FP32)
+  if (precision != DMC_FP64 && precision != DMC_FP32 && precision != DMC_BF16)
     return fail(DMC_ERR_INVALID_ARG, "bad precision");
   HIP_TRY(hipSetDevice(ctx->device));
   dmc_status st = ensure_scratch(ctx, dmc::autocorr_scratch_bytes(mesh->dev.n, T, 1, precision));

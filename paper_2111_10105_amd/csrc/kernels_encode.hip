@@ -177,6 +177,83 @@ __global__ void k_autocorr_reduce(const Real* __restrict__ part, int T, int nw, 
   R[e] = s;
 }
 
+// Precision form: bfloat16 operands, float32 accumulation
+// (v_mfma_f32_16x16x32_bf16: lane l supplies A[l%16][8(l/16) .. 8(l/16)+7] and
+// B[8(l/16) .. +7][l%16]; component r of lane l is D[4(l/16) + r][l%16]).  The
+// staged tile is [c][t][v] in bfloat16 (vertices contiguous), so both operands
+// are one 16-byte LDS read per lane.  64 vertices per tile (two MFMA K steps).
+constexpr int BF_VT = 64;
+constexpr int BF_LD = BF_VT + 8;  // 16-byte aligned rows
+
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+template <int TP>
+__global__ void __launch_bounds__(AC_WAVES * 64)
+k_autocorr_bf16(const float* __restrict__ frames, int n, int T, int nw, int P,
+                float* __restrict__ part) {
+  constexpr int NT = TP / 16;
+  constexpr int JOBS = 3 * NT * (NT + 1) / 2;
+  constexpr int JPW = (JOBS + AC_WAVES - 1) / AC_WAVES;
+  __shared__ __attribute__((aligned(16))) __bf16 tile[3 * TP * BF_LD];
+  const int p = blockIdx.x, w = blockIdx.y;
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int per = (n + P - 1) / P;
+  const int v_begin = p * per, v_end = min(n, v_begin + per);
+  const float* base = frames + (size_t)w * T * 3 * n;
+  f4v acc[JPW];
+  int jc[JPW], ji[JPW], jj[JPW];
+  for (int q = 0; q < JPW; ++q) {
+    acc[q] = f4v{0.f, 0.f, 0.f, 0.f};
+    const int job = wave + q * AC_WAVES;
+    jc[q] = -1;
+    if (job < JOBS) {
+      const int per_c = NT * (NT + 1) / 2;
+      jc[q] = job / per_c;
+      int rem = job % per_c, bi = 0;
+      while (rem >= NT - bi) {
+        rem -= NT - bi;
+        ++bi;
+      }
+      ji[q] = bi;
+      jj[q] = bi + rem;
+    }
+  }
+  for (int v0 = v_begin; v0 < v_end; v0 += BF_VT) {
+    const int nv = min(BF_VT, v_end - v0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < TP * 3 * BF_VT; e += AC_WAVES * 64) {
+      const int t = e / (3 * BF_VT), rem = e % (3 * BF_VT);
+      const int v = rem / 3, c = rem % 3;
+      float val = 0.f;
+      if (t < T && v < nv) val = base[(size_t)t * 3 * n + (size_t)(v0 + v) * 3 + c];
+      tile[(c * TP + t) * BF_LD + v] = (__bf16)val;
+    }
+    __syncthreads();
+    for (int q = 0; q < JPW; ++q) {
+      if (jc[q] < 0) continue;
+      const __bf16* tc = tile + jc[q] * TP * BF_LD;
+      const int ra = ji[q] * 16 + lane % 16, rb = jj[q] * 16 + lane % 16;
+#pragma unroll
+      for (int kk = 0; kk < BF_VT; kk += 32) {
+        const bf8v a = *(const bf8v*)&tc[ra * BF_LD + kk + 8 * (lane / 16)];
+        const bf8v b = *(const bf8v*)&tc[rb * BF_LD + kk + 8 * (lane / 16)];
+        acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[q], 0, 0, 0);
+      }
+    }
+  }
+  float* out = part + ((size_t)w * P + p) * 3 * TP * TP;
+  for (int q = 0; q < JPW; ++q) {
+    if (jc[q] < 0) continue;
+    float* oc = out + (size_t)jc[q] * TP * TP;
+    for (int r = 0; r < 4; ++r) {
+      const int gi = ji[q] * 16 + 4 * (lane / 16) + r, gj = jj[q] * 16 + lane % 16;
+      oc[gi * TP + gj] = acc[q][r];
+      oc[gj * TP + gi] = acc[q][r];
+    }
+  }
+}
+
 int pad_T(int T) { return T <= 32 ? 32 : 64; }
 
 int autocorr_blocks(int n, int nw) {
@@ -385,10 +462,33 @@ void launch_delta(hipStream_t s, const MeshDev& m, const void* in, void* out, in
 // largest one still carry delta-coordinate energy, so float32 accumulation would
 // change the reconstruction measurably.
 size_t autocorr_scratch_bytes(int32_t n, int32_t T, int32_t nw, int32_t precision) {
-  (void)precision;
   const int P = autocorr_blocks(n, nw);
   const int TP = pad_T(T);
-  return (size_t)nw * P * 3 * TP * TP * 8;
+  return (size_t)nw * P * 3 * TP * TP * (precision == DMC_BF16 ? 4 : 8);
+}
+
+// precision form: bfloat16 products accumulated in float32, partials added in
+// float64 in a fixed order
+static void autocorr_bf16(hipStream_t s, const float* frames, int32_t n, int32_t T, int32_t nw,
+                          float* part, double* R) {
+  const int P = autocorr_blocks(n, nw);
+  dim3 grid(P, nw);
+  const int tot = nw * 3 * T * T;
+  dim3 rgrid((tot + kBlock - 1) / kBlock);
+  prof::begin(s, DMC_KERNEL_AUTOCORR);
+  if (T <= 32)
+    hipLaunchKernelGGL((k_autocorr_bf16<32>), grid, dim3(AC_WAVES * 64), 0, s, frames, n, T, nw, P,
+                       part);
+  else
+    hipLaunchKernelGGL((k_autocorr_bf16<64>), grid, dim3(AC_WAVES * 64), 0, s, frames, n, T, nw, P,
+                       part);
+  prof::end(s, DMC_KERNEL_AUTOCORR);
+  if (T <= 32)
+    hipLaunchKernelGGL((k_autocorr_reduce<float, 32>), rgrid, dim3(kBlock), 0, s,
+                       (const float*)part, T, nw, P, R);
+  else
+    hipLaunchKernelGGL((k_autocorr_reduce<float, 64>), rgrid, dim3(kBlock), 0, s,
+                       (const float*)part, T, nw, P, R);
 }
 
 template <typename In>
@@ -418,6 +518,8 @@ void launch_autocorr(hipStream_t s, const void* frames, int32_t n, int32_t T, in
                      int32_t precision, void* part, double* R) {
   if (precision == DMC_FP64)
     autocorr_impl(s, (const double*)frames, n, T, nw, (double*)part, R);
+  else if (precision == DMC_BF16)
+    autocorr_bf16(s, (const float*)frames, n, T, nw, (float*)part, R);
   else
     autocorr_impl(s, (const float*)frames, n, T, nw, (double*)part, R);
 }

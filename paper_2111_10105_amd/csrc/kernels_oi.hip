@@ -122,6 +122,46 @@ __device__ __forceinline__ void mm_RQ(OiSmem<TMAX, KMAX>& s) {
   __syncthreads();
 }
 
+// Y = R Q with bfloat16 operands and float32 accumulation (precision form):
+// v_mfma_f32_16x16x32_bf16, lane l supplies A[l%16][8(l/16) .. +7] and
+// B[8(l/16) .. +7][l%16]; component r of lane l is D[4(l/16) + r][l%16].
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+template <int KR, int TMAX, int KMAX>
+__device__ __forceinline__ void mm_RQ_bf16(OiSmem<TMAX, KMAX>& s) {
+  constexpr int TI = TMAX / 16, TJ = KR / 16;
+  const int lane = threadIdx.x, r16 = lane % 16, q4 = lane / 16;
+  f4 acc[TI][TJ];
+#pragma unroll
+  for (int i = 0; i < TI; ++i)
+#pragma unroll
+    for (int j = 0; j < TJ; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int kk = 0; kk < TMAX; kk += 32) {
+    bf8 b[TJ];
+#pragma unroll
+    for (int j = 0; j < TJ; ++j)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) b[j][e] = (__bf16)s.Q[(kk + 8 * q4 + e) * s.LQ + j * 16 + r16];
+#pragma unroll
+    for (int i = 0; i < TI; ++i) {
+      bf8 a;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) a[e] = (__bf16)s.R[(i * 16 + r16) * s.LR + kk + 8 * q4 + e];
+#pragma unroll
+      for (int j = 0; j < TJ; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[j], acc[i][j], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < TI; ++i)
+#pragma unroll
+    for (int j = 0; j < TJ; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) s.Y[(i * 16 + 4 * q4 + r) * s.LQ + j * 16 + r16] = (double)acc[i][j][r];
+  __syncthreads();
+}
+
 // A[0:KR, 0:KR] = X^T Z for T x KR blocks X, Z in LDS (stride LQ, rows >= T
 // zero).  X == Z gives the Gram matrix.
 template <int KR, int TMAX, int KMAX>
@@ -745,15 +785,41 @@ __device__ __forceinline__ double dequant(uint16_t code, double lo, double hi, i
 // diag(mu) V^T; U is left in Y (not yet sign-fixed).
 template <int KR, int TMAX, int KMAX>
 __device__ __forceinline__ void oi_sweeps(OiSmem<TMAX, KMAX>& s, int T, int k, int max_sweeps, double tol,
-                                          double normR, int& sweeps, int& repairs, double& resid) {
+                                          double normR, bool bf16, int& sweeps, int& repairs, double& resid) {
+  // precision form: bfloat16 products until the stage tolerance (or one sweep
+  // before the cap), then full-precision refinement sweeps (at least one)
+  // until tol, or until a sweep no longer reduces the residual by a tenth
+  // (the subspace has reached what the bfloat16 covariance determines)
+  const double stage_tol = tol > DMC_BF16_STAGE_TOL ? tol : DMC_BF16_STAGE_TOL;
+  bool refining = false;
+  double prev = 0.0;
   repairs += orthonormalise<KR>(s, s.Q, T, k) ? 1 : 0;
-  mm_RQ<KR>(s);
+  if (bf16)
+    mm_RQ_bf16<KR>(s);
+  else
+    mm_RQ<KR>(s);
   for (int sw = 1; sw <= max_sweeps; ++sw) {
     repairs += orthonormalise<KR>(s, s.Y, T, k) ? 1 : 0;
-    mm_RQ<KR>(s);
+    if (bf16)
+      mm_RQ_bf16<KR>(s);
+    else
+      mm_RQ<KR>(s);
     sweeps = sw;
     resid = residual_and_H<KR>(s, k, normR);
+    if (bf16) {
+      if (resid <= stage_tol || sw + 1 >= max_sweeps) {
+        bf16 = false;
+        refining = true;
+        prev = -1.0;
+        mm_RQ<KR>(s);  // full-precision product for the refinement sweeps
+      }
+      continue;
+    }
     if (resid <= tol) break;
+    if (refining) {
+      if (prev > 0.0 && resid > 0.9 * prev) break;
+      prev = resid;
+    }
   }
   eigen_sym(s, k);
   ritz_vectors<KR>(s, k);
@@ -780,19 +846,21 @@ __global__ void __launch_bounds__(NT) k_oi(OiArgs a) {
   for (int w = w_begin; w < w_end; ++w) {
     // ---- load R_c of window w (zero padded), every load in flight at once ----
     const double* Rg = a.R + ((size_t)w * a.ncoord + c) * T * T;
-    constexpr int PER = TMAX * TMAX / NT;
-    double rv[PER];
-#pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      const int e = tid + u * NT, i = e / TMAX, j = e % TMAX;
-      rv[u] = (i < T && j < T) ? Rg[i * T + j] : 0.0;
-    }
+    constexpr int PER = TMAX * TMAX / NT, CH = 16;  // 16 loads in flight per lane
     double part = 0.0;
+    for (int u0 = 0; u0 < PER; u0 += CH) {
+      double rv[CH];
 #pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      const int e = tid + u * NT, i = e / TMAX, j = e % TMAX;
-      s.R[i * s.LR + j] = rv[u];
-      part = fma(rv[u], rv[u], part);
+      for (int u = 0; u < CH; ++u) {
+        const int e = tid + (u0 + u) * NT, i = e / TMAX, j = e % TMAX;
+        rv[u] = (i < T && j < T) ? Rg[i * T + j] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < CH; ++u) {
+        const int e = tid + (u0 + u) * NT, i = e / TMAX, j = e % TMAX;
+        s.R[i * s.LR + j] = rv[u];
+        part = fma(rv[u], rv[u], part);
+      }
     }
     __syncthreads();
     const double normR = sqrt(block_sum(part, s.red));
@@ -825,30 +893,29 @@ __global__ void __launch_bounds__(NT) k_oi(OiArgs a) {
       if (!chain || w == 0) {
         // caller-given start (window 0 of the chain, or this window's own
         // block), or Omega for the sketch start R_c Omega
-        constexpr int PQ = TMAX * KR / NT;
-        double qv[PQ];
-        if (a.init == DMC_INIT_LEARNED) {
-          // the network's prediction for this (window, coordinate)
-          const float* ql = a.q_learned + ((size_t)w * a.ncoord + c) * T * k;
-#pragma unroll
-          for (int u = 0; u < PQ; ++u) {
-            const int e = tid + u * NT;
-            qv[u] = e < T * k ? (double)ql[e] : 0.0;
-          }
-        } else {
-          const Real* q0 = (const Real*)a.q_start;
+        constexpr int PQ = TMAX * KR / NT, CQ = PQ < 16 ? PQ : 16;
+        // the network's prediction for this (window, coordinate), or the
+        // caller's block
+        const float* ql = a.init == DMC_INIT_LEARNED
+                              ? a.q_learned + ((size_t)w * a.ncoord + c) * T * k
+                              : nullptr;
+        const Real* q0 = (const Real*)a.q_start;
+        if (!ql) {
           if (a.init == DMC_INIT_RANDOM) q0 += ((size_t)w * a.ncoord + c) * T * k;
           else if (a.init != DMC_INIT_SKETCH) q0 += (size_t)c * T * k;
-#pragma unroll
-          for (int u = 0; u < PQ; ++u) {
-            const int e = tid + u * NT;
-            qv[u] = e < T * k ? (double)q0[e] : 0.0;
-          }
         }
+        for (int u0 = 0; u0 < PQ; u0 += CQ) {
+          double qv[CQ];
 #pragma unroll
-        for (int u = 0; u < PQ; ++u) {
-          const int e = tid + u * NT;
-          if (e < T * k) s.Q[(e / k) * s.LQ + e % k] = qv[u];
+          for (int u = 0; u < CQ; ++u) {
+            const int e = tid + (u0 + u) * NT;
+            qv[u] = e < T * k ? (ql ? (double)ql[e] : (double)q0[e]) : 0.0;
+          }
+#pragma unroll
+          for (int u = 0; u < CQ; ++u) {
+            const int e = tid + (u0 + u) * NT;
+            if (e < T * k) s.Q[(e / k) * s.LQ + e % k] = qv[u];
+          }
         }
         __syncthreads();
         if (a.init == DMC_INIT_SKETCH) {
@@ -857,7 +924,8 @@ __global__ void __launch_bounds__(NT) k_oi(OiArgs a) {
           __syncthreads();
         }
       }
-      oi_sweeps<KR>(s, T, k, a.max_sweeps, a.tol, normR, sweeps, repairs, resid);
+      oi_sweeps<KR>(s, T, k, a.max_sweeps, a.tol, normR, a.precision == DMC_BF16, sweeps, repairs,
+                    resid);
       sign_fix(s, T, k);
     }
     // ---- outputs: U, dictionary codes, dequantised dictionary ----

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libdmc.so")
 DMC_OK = 0
 STATUS = {0: "OK", 1: "INVALID_ARG", 2: "OUT_OF_MEMORY", 3: "DEVICE", 4: "NOT_CONVERGED",
           5: "SINGULAR", 6: "BUFFER_TOO_SMALL", 7: "UNSUPPORTED"}
-FP64, FP32 = 0, 1
+FP64, FP32, BF16 = 0, 1, 2
 LAP_UNIFORM, LAP_COMBINATORIAL = 0, 1
 PRECOND_NONE, PRECOND_JACOBI, PRECOND_CHOLESKY = 0, 1, 2
 INIT_PREV, INIT_RANDOM, INIT_SKETCH, INIT_EXACT, INIT_LEARNED = 0, 1, 2, 3, 4
