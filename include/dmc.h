@@ -306,6 +306,42 @@ dmc_status dmc_mlp_adam(dmc_ctx ctx, float* theta_dev, const float* grad_dev, fl
                         float* v_dev, int32_t count, int32_t step, double lr, double beta1,
                         double beta2, double eps);
 
+/* ---- batched form: many independent sequences, one captured graph --------
+ * dmc_batch_create plans nseq sequences: sequence i is frames_dev[i]
+ * [F[i]][n_i][3] on meshes[i] (meshes of this context), windows of T[i],
+ * params[i] (one precision for the whole batch; init DMC_INIT_PREV, _RANDOM,
+ * _SKETCH or _EXACT with q_start_dev[i] as for dmc_compress_sequence),
+ * records into codes_dev[i] (dmc_sequence_code_bytes bytes) and, when
+ * frames_out_dev[i] is not NULL, the decoded frames.  Addresses are fixed at
+ * creation: the first dmc_batch_run records the whole batch as a HIP graph
+ * and later runs replay it.  In it the orthogonal iterations of every window
+ * of every sequence run in one launch per class (T <= 32 or <= 64, k <= 16
+ * or <= 32), the bandwidth-bound kernels per sequence, and each decode with
+ * exactly params[i].cg_max_iters conjugate-gradient iterations and no host
+ * synchronisation.  At creation a small autotuner times candidate vertex
+ * splits of the covariance kernel and frames per workgroup of the delta
+ * kernel on each sequence's own frames and keeps the fastest.  The batch owns
+ * its device scratch (allocated at creation); meshes and caller buffers must
+ * outlive it.
+ * dmc_batch_run: ordered on the context's stream, does not synchronise.
+ * dmc_batch_stats: synchronises; fills per_window (one entry per window of
+ * sequence seq) like dmc_compress_sequence (cg_iters = the fixed count,
+ * cg_resid = largest relative residual) and returns DMC_ERR_NOT_CONVERGED if
+ * some column of the sequence did not reach cg_tol.
+ * dmc_batch_tuning: the autotuner's choices for sequence seq:
+ * tuning[0] = covariance vertex blocks per window, tuning[1] = delta frames
+ * per workgroup. */
+typedef struct dmc_batch_s* dmc_batch;
+dmc_status dmc_batch_create(dmc_ctx ctx, int32_t nseq, const dmc_mesh* meshes,
+                            const void* const* frames_dev, const int32_t* F, const int32_t* T,
+                            const dmc_params* params, const void* const* q_start_dev,
+                            void* const* codes_dev, void* const* frames_out_dev,
+                            dmc_batch* out);
+dmc_status dmc_batch_run(dmc_batch batch);
+dmc_status dmc_batch_stats(dmc_batch batch, int32_t seq, dmc_window_stats* per_window);
+dmc_status dmc_batch_tuning(dmc_batch batch, int32_t seq, int32_t tuning[2]);
+void dmc_batch_destroy(dmc_batch batch);
+
 /* ---- kernel timing (measurement support) ----------------------------------
  * dmc_profile_start selects one kernel family; from then on every launch of
  * it is bracketed by HIP events recorded on the stream it runs on.

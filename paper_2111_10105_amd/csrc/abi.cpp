@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cstring>
 #include <string>
@@ -232,45 +233,46 @@ dmc_status check_learned(dmc_ctx ctx, const dmc_params& p, int32_t T) {
   return DMC_OK;
 }
 
-// Decode every window of a sequence in one solve over 3F columns.
-dmc_status decode_all(dmc_ctx ctx, const dmc::MeshDev& m, const uint8_t* records,
-                      const dmc::SeqLayout& sl, const dmc_params& p, void* frames_out,
-                      int32_t* iters_out, double* resid_out) {
-  hipStream_t s = ctx->stream;
-  const int32_t F = sl.nw_full * sl.T + sl.T_tail;
-  const int32_t ncols = 3 * F;
+// Decoder buffers for ncols right-hand sides, carved from one region.
+struct DecodeLayout {
+  size_t o_x, o_r, o_p, o_q, o_part, o_small, o_z, o_W, o_Y, o_X, o_U, total;
+};
+
+DecodeLayout decode_layout(const dmc::MeshDev& m, int32_t ncols, bool chol) {
   const size_t vec = (size_t)m.n * ncols * 8;
   const size_t nrb = dmc::cg_part_rows(m.n);
   Carve cv;
-  const size_t o_x = cv.add(vec);
-  const size_t o_r = cv.add(vec + (size_t)m.nc * ncols * 8);  // b, then r; anchor values after
-  const size_t o_p = cv.add(vec);
-  const size_t o_q = cv.add(vec);                             // back-projection, then q
-  const size_t o_part = cv.add(2 * nrb * ncols * 8);
-  const size_t o_small = cv.add((size_t)ncols * 8 * 6 + (size_t)ncols * 4);
-  const bool chol = p.precond == DMC_PRECOND_CHOLESKY;
-  const size_t o_z = chol ? cv.add(vec) : 0;
-  const size_t o_W = chol ? cv.add(vec) : 0;
-  const size_t o_Y = chol ? cv.add(vec) : 0;
-  const size_t o_X = chol ? cv.add(vec) : 0;
-  const size_t o_U = chol ? cv.add((size_t)m.chol.nslots * ncols * 8) : 0;
-  dmc_status st = ensure_scratch(ctx, cv.total());
-  if (st != DMC_OK) return st;
-  st = ensure_pinned(ctx, (size_t)ncols * 12 + 4096);
-  if (st != DMC_OK) return st;
-  uint8_t* ws = (uint8_t*)ctx->scratch;
+  DecodeLayout d{};
+  d.o_x = cv.add(vec);
+  d.o_r = cv.add(vec + (size_t)m.nc * ncols * 8);  // b, then r; anchor values after
+  d.o_p = cv.add(vec);
+  d.o_q = cv.add(vec);                             // back-projection, then q
+  d.o_part = cv.add(2 * nrb * ncols * 8);
+  d.o_small = cv.add((size_t)ncols * 8 * 6 + (size_t)ncols * 4);
+  if (chol) {
+    d.o_z = cv.add(vec);
+    d.o_W = cv.add(vec);
+    d.o_Y = cv.add(vec);
+    d.o_X = cv.add(vec);
+    d.o_U = cv.add((size_t)m.chol.nslots * ncols * 8);
+  }
+  d.total = cv.total();
+  return d;
+}
+
+dmc::CgBuffers decode_buffers(uint8_t* ws, const DecodeLayout& d, int32_t ncols, bool chol) {
   dmc::CgBuffers cb;
-  cb.x = (double*)(ws + o_x);
-  cb.r = (double*)(ws + o_r);
-  cb.p = (double*)(ws + o_p);
-  cb.q = (double*)(ws + o_q);
-  cb.part = (double*)(ws + o_part);
-  cb.z = chol ? (double*)(ws + o_z) : nullptr;
-  cb.W = chol ? (double*)(ws + o_W) : nullptr;
-  cb.Y = chol ? (double*)(ws + o_Y) : nullptr;
-  cb.X = chol ? (double*)(ws + o_X) : nullptr;
-  cb.U = chol ? (double*)(ws + o_U) : nullptr;
-  double* small = (double*)(ws + o_small);
+  cb.x = (double*)(ws + d.o_x);
+  cb.r = (double*)(ws + d.o_r);
+  cb.p = (double*)(ws + d.o_p);
+  cb.q = (double*)(ws + d.o_q);
+  cb.part = (double*)(ws + d.o_part);
+  cb.z = chol ? (double*)(ws + d.o_z) : nullptr;
+  cb.W = chol ? (double*)(ws + d.o_W) : nullptr;
+  cb.Y = chol ? (double*)(ws + d.o_Y) : nullptr;
+  cb.X = chol ? (double*)(ws + d.o_X) : nullptr;
+  cb.U = chol ? (double*)(ws + d.o_U) : nullptr;
+  double* small = (double*)(ws + d.o_small);
   cb.rz = small;
   cb.rr = small + ncols;
   cb.bnorm2 = small + 2 * ncols;
@@ -278,6 +280,42 @@ dmc_status decode_all(dmc_ctx ctx, const dmc::MeshDev& m, const uint8_t* records
   cb.beta = small + 4 * ncols;
   cb.resid = small + 5 * ncols;
   cb.done = (int32_t*)(small + 6 * ncols);
+  return cb;
+}
+
+// Decode with a fixed number of conjugate-gradient iterations and no host
+// synchronisation (capturable); summary[0..1] receives the largest relative
+// residual and whether every column converged.
+void decode_enqueue_fixed(hipStream_t s, const dmc::MeshDev& m, const uint8_t* records,
+                          const dmc::SeqLayout& sl, const dmc_params& p, void* frames_out,
+                          const dmc::CgBuffers& cb, int iters, double* summary) {
+  const int32_t F = sl.nw_full * sl.T + sl.T_tail;
+  const int32_t ncols = 3 * F;
+  dmc::launch_back_project(s, m, records, sl, nullptr, cb.q);
+  dmc::launch_rhs(s, m, records, sl, cb.q, cb.r);
+  dmc::launch_cg_init(s, m, ncols, cb.r, cb, p.precond);
+  for (int it = 1; it <= iters; ++it) {
+    dmc::launch_cg_step_a(s, m, ncols, cb, p.precond, p.cg_tol);
+    if (it < iters) dmc::launch_cg_step_b(s, m, ncols, cb, p.precond);
+  }
+  dmc::launch_cg_summary(s, cb, ncols, summary);
+  dmc::launch_to_frames(s, cb.x, m.n, F, p.precision, frames_out);
+}
+
+// Decode every window of a sequence in one solve over 3F columns.
+dmc_status decode_all(dmc_ctx ctx, const dmc::MeshDev& m, const uint8_t* records,
+                      const dmc::SeqLayout& sl, const dmc_params& p, void* frames_out,
+                      int32_t* iters_out, double* resid_out) {
+  hipStream_t s = ctx->stream;
+  const int32_t F = sl.nw_full * sl.T + sl.T_tail;
+  const int32_t ncols = 3 * F;
+  const bool chol = p.precond == DMC_PRECOND_CHOLESKY;
+  const DecodeLayout dl = decode_layout(m, ncols, chol);
+  dmc_status st = ensure_scratch(ctx, dl.total);
+  if (st != DMC_OK) return st;
+  st = ensure_pinned(ctx, (size_t)ncols * 12 + 4096);
+  if (st != DMC_OK) return st;
+  const dmc::CgBuffers cb = decode_buffers((uint8_t*)ctx->scratch, dl, ncols, chol);
 
   dmc::launch_back_project(s, m, records, sl, nullptr, cb.q);
   dmc::launch_rhs(s, m, records, sl, cb.q, cb.r);
@@ -953,4 +991,380 @@ dmc_status dmc_oi_blocks(dmc_ctx ctx, const double* R, int32_t nb, int32_t T,
     }
   }
   return DMC_OK;
+}
+
+// ---- batched form -----------------------------------------------------------
+
+struct BatchSeq {
+  dmc_mesh mesh = nullptr;
+  const uint8_t* frames = nullptr;
+  int32_t F = 0, T = 0, k_full = 0, k_tail = 0;
+  dmc_params p{};
+  const void* q_start = nullptr;
+  uint8_t* codes = nullptr;
+  void* out = nullptr;
+  dmc::SeqLayout sl{};
+  size_t o_delta = 0, o_R = 0, o_Rt = 0, o_ut = 0, o_utt = 0;
+  int32_t stats_off = 0;  // first window in the batch's stats array
+  int P = 0, fpb = 8;     // tuned launch shapes
+};
+
+struct dmc_batch_s {
+  dmc_ctx ctx = nullptr;
+  int32_t precision = DMC_FP32;
+  std::vector<BatchSeq> seq;
+  uint8_t* buf = nullptr;
+  size_t o_shared = 0, o_args = 0, o_jobs = 0, o_summary = 0, o_stats = 0;
+  std::vector<int> cls_tmax, cls_kr, cls_off, cls_n;  // OI launch classes
+  hipStream_t stream = nullptr;  // private stream the graph is captured on and replayed on
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+// The whole batch on stream s, with no host synchronisation.
+void batch_enqueue(dmc_batch b, hipStream_t s) {
+  uint8_t* shared = b->buf + b->o_shared;
+  const size_t rs = real_size(b->precision);
+  for (BatchSeq& q : b->seq)
+    dmc::launch_delta(s, q.mesh->dev, q.frames, b->buf + q.o_delta, q.F, b->precision, q.fpb);
+  for (BatchSeq& q : b->seq) {
+    const dmc::MeshDev& m = q.mesh->dev;
+    for (int32_t w = 0; w < q.sl.nw_full; ++w)
+      dmc::launch_write_header(s, q.codes + (size_t)w * q.sl.full.bytes, q.sl.full);
+    if (q.sl.T_tail)
+      dmc::launch_write_header(s, q.codes + (size_t)q.sl.nw_full * q.sl.full.bytes, q.sl.tail);
+    if (q.sl.nw_full)
+      dmc::launch_autocorr(s, q.frames, m.n, q.T, q.sl.nw_full, b->precision, shared,
+                           (double*)(b->buf + q.o_R), q.P);
+    if (q.sl.T_tail)
+      dmc::launch_autocorr(s, q.frames + (size_t)q.sl.nw_full * q.T * 3 * m.n * rs, m.n,
+                           q.sl.T_tail, 1, b->precision, shared, (double*)(b->buf + q.o_Rt));
+  }
+  for (size_t c = 0; c < b->cls_n.size(); ++c)
+    dmc::launch_oi_batch(s, b->cls_tmax[c], b->cls_kr[c], b->precision,
+                         (const dmc::OiArgs*)(b->buf + b->o_args),
+                         (const int4*)(b->buf + b->o_jobs) + b->cls_off[c], b->cls_n[c]);
+  for (BatchSeq& q : b->seq) {
+    const dmc::MeshDev& m = q.mesh->dev;
+    const uint8_t* delta = b->buf + q.o_delta;
+    if (q.sl.nw_full) {
+      dmc::launch_project_quantise(s, delta, m.n, q.T, q.k_full, q.sl.nw_full, b->precision,
+                                   q.p.coef_bits, (const double*)(b->buf + q.o_ut), q.codes,
+                                   q.sl.full.bytes, q.sl.full, shared, nullptr);
+      dmc::launch_anchors(s, m, q.frames, q.T, q.sl.nw_full, b->precision, q.p.anchor_bits,
+                          q.codes, q.sl.full.bytes, q.sl.full);
+    }
+    if (q.sl.T_tail) {
+      const size_t f0 = (size_t)q.sl.nw_full * q.T;
+      uint8_t* rec = q.codes + (size_t)q.sl.nw_full * q.sl.full.bytes;
+      dmc::launch_project_quantise(s, delta + f0 * 3 * m.n * rs, m.n, q.sl.T_tail, q.k_tail, 1,
+                                   b->precision, q.p.coef_bits, (const double*)(b->buf + q.o_utt),
+                                   rec, q.sl.tail.bytes, q.sl.tail, shared, nullptr);
+      dmc::launch_anchors(s, m, q.frames + f0 * 3 * m.n * rs, q.sl.T_tail, 1, b->precision,
+                          q.p.anchor_bits, rec, q.sl.tail.bytes, q.sl.tail);
+    }
+  }
+  double* summary = (double*)(b->buf + b->o_summary);
+  for (size_t i = 0; i < b->seq.size(); ++i) {
+    BatchSeq& q = b->seq[i];
+    if (!q.out) continue;
+    const int32_t ncols = 3 * q.F;
+    const bool chol = q.p.precond == DMC_PRECOND_CHOLESKY;
+    const DecodeLayout dl = decode_layout(q.mesh->dev, ncols, chol);
+    const dmc::CgBuffers cb = decode_buffers(shared, dl, ncols, chol);
+    decode_enqueue_fixed(s, q.mesh->dev, q.codes, q.sl, q.p, q.out, cb, q.p.cg_max_iters,
+                         summary + 2 * i);
+  }
+}
+
+// Times `launch` (three runs after one warm-up) with events on stream s.
+template <typename F>
+float time_launch(hipStream_t s, F launch) {
+  hipEvent_t a, z;
+  if (hipEventCreate(&a) != hipSuccess) return 1e30f;
+  if (hipEventCreate(&z) != hipSuccess) {
+    (void)hipEventDestroy(a);
+    return 1e30f;
+  }
+  launch();
+  (void)hipEventRecord(a, s);
+  for (int r = 0; r < 3; ++r) launch();
+  (void)hipEventRecord(z, s);
+  float ms = 1e30f;
+  if (hipEventSynchronize(z) != hipSuccess || hipEventElapsedTime(&ms, a, z) != hipSuccess)
+    ms = 1e30f;
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(z);
+  return ms;
+}
+
+}  // namespace
+
+dmc_status dmc_batch_create(dmc_ctx ctx, int32_t nseq, const dmc_mesh* meshes,
+                            const void* const* frames, const int32_t* F, const int32_t* T,
+                            const dmc_params* params, const void* const* q_start,
+                            void* const* codes, void* const* frames_out, dmc_batch* out) {
+  if (!ctx || !meshes || !frames || !F || !T || !params || !codes || !out)
+    return fail(DMC_ERR_INVALID_ARG, "NULL argument");
+  *out = nullptr;
+  if (nseq < 1) return fail(DMC_ERR_INVALID_ARG, "nseq must be >= 1");
+  HIP_TRY(hipSetDevice(ctx->device));
+  auto b = new dmc_batch_s();
+  b->ctx = ctx;
+  b->precision = params[0].precision;
+  auto bail = [&](dmc_status st) {
+    delete b;
+    return st;
+  };
+  Carve cv;
+  size_t shared = 0, nargs = 0, njobs = 0, nwin = 0;
+  b->seq.resize(nseq);
+  for (int32_t i = 0; i < nseq; ++i) {
+    BatchSeq& q = b->seq[i];
+    const dmc_params& p = params[i];
+    dmc_status st = check_params(&p, T[i]);
+    if (st != DMC_OK) return bail(st);
+    if (!meshes[i] || meshes[i]->ctx != ctx || !frames[i] || !codes[i] || F[i] < 1)
+      return bail(fail(DMC_ERR_INVALID_ARG, "sequence " + std::to_string(i) + ": bad argument"));
+    if (p.precision != b->precision)
+      return bail(fail(DMC_ERR_INVALID_ARG, "one precision per batch"));
+    if (p.init == DMC_INIT_LEARNED)
+      return bail(fail(DMC_ERR_UNSUPPORTED, "the learned start is not available in a batch"));
+    const bool need_start = p.init == DMC_INIT_RANDOM || p.init == DMC_INIT_SKETCH;
+    if (need_start && F[i] >= T[i] && (!q_start || !q_start[i]))
+      return bail(fail(DMC_ERR_INVALID_ARG, "sequence " + std::to_string(i) + " needs q_start"));
+    q.mesh = meshes[i];
+    q.frames = (const uint8_t*)frames[i];
+    q.F = F[i];
+    q.T = T[i];
+    q.p = p;
+    q.q_start = q_start ? q_start[i] : nullptr;
+    q.codes = (uint8_t*)codes[i];
+    q.out = frames_out ? frames_out[i] : nullptr;
+    const dmc::MeshDev& m = q.mesh->dev;
+    q.sl = seq_layout(m.n, q.F, q.T, m.nc, p);
+    q.k_full = std::min(p.k, q.T);
+    q.k_tail = q.sl.T_tail ? std::min(p.k, q.sl.T_tail) : 0;
+    const size_t rs = real_size(b->precision);
+    q.o_delta = cv.add((size_t)q.F * 3 * m.n * rs);
+    q.o_R = cv.add((size_t)q.sl.nw_full * 3 * q.T * q.T * 8);
+    q.o_ut = cv.add((size_t)q.sl.nw_full * 3 * q.T * q.k_full * 8);
+    q.o_Rt = cv.add((size_t)3 * q.sl.T_tail * q.sl.T_tail * 8);
+    q.o_utt = cv.add((size_t)3 * q.sl.T_tail * q.k_tail * 8);
+    q.stats_off = (int32_t)nwin;
+    nwin += q.sl.nw_full + (q.sl.T_tail ? 1 : 0);
+    // shared region: the largest autocorrelation partials (any tuned split),
+    // projection scratch and decoder buffers of any one sequence
+    const int P0 = dmc::autocorr_blocks(m.n, std::max(1, q.sl.nw_full));
+    const int Pmax = std::max(1, std::min(4 * P0, std::max(1, m.n)));
+    shared = std::max(shared, dmc::autocorr_scratch_bytes(m.n, q.T, std::max(1, q.sl.nw_full),
+                                                          b->precision, Pmax));
+    shared = std::max(shared, dmc::project_scratch_bytes(m.n, q.T, q.k_full,
+                                                         std::max(1, q.sl.nw_full), b->precision));
+    if (q.out)
+      shared = std::max(shared, decode_layout(m, 3 * q.F, p.precond == DMC_PRECOND_CHOLESKY).total);
+    if (q.sl.nw_full) {
+      ++nargs;
+      njobs += p.init == DMC_INIT_PREV ? 3 : 3 * (size_t)q.sl.nw_full;
+    }
+    if (q.sl.T_tail) {
+      ++nargs;
+      njobs += 3;
+    }
+  }
+  b->o_shared = cv.add(shared);
+  b->o_args = cv.add(nargs * sizeof(dmc::OiArgs));
+  b->o_jobs = cv.add(njobs * sizeof(int4));
+  b->o_summary = cv.add((size_t)nseq * 2 * sizeof(double));
+  b->o_stats = cv.add(nwin * sizeof(dmc::StatsDev));
+  if (hipMalloc(&b->buf, cv.total()) != hipSuccess) {
+    (void)hipGetLastError();
+    return bail(fail(DMC_ERR_OUT_OF_MEMORY, "cannot allocate the batch's scratch"));
+  }
+  // orthogonal-iteration arguments and jobs, grouped into launch classes
+  std::vector<dmc::OiArgs> args;
+  std::vector<std::array<int, 6>> jobs;  // tmax, kr, args index, w0, w1, c
+  dmc::StatsDev* stats = (dmc::StatsDev*)(b->buf + b->o_stats);
+  for (BatchSeq& q : b->seq) {
+    for (int part = 0; part < 2; ++part) {
+      const bool tail = part == 1;
+      const int32_t nw = tail ? (q.sl.T_tail ? 1 : 0) : q.sl.nw_full;
+      if (!nw) continue;
+      dmc::OiArgs a{};
+      a.R = (const double*)(b->buf + (tail ? q.o_Rt : q.o_R));
+      a.nw = nw;
+      a.T = tail ? q.sl.T_tail : q.T;
+      a.k = tail ? q.k_tail : q.k_full;
+      a.precision = b->precision;
+      a.dict_bits = q.p.dict_bits;
+      a.init = tail ? DMC_INIT_EXACT : q.p.init;
+      a.ncoord = 3;
+      a.q_start = (tail || q.p.init == DMC_INIT_EXACT) ? nullptr : q.q_start;
+      a.q_learned = nullptr;
+      a.u_out = nullptr;
+      a.u_tilde = (double*)(b->buf + (tail ? q.o_utt : q.o_ut));
+      a.records = q.codes + (tail ? (size_t)q.sl.nw_full * q.sl.full.bytes : 0);
+      a.rec_bytes = tail ? q.sl.tail.bytes : q.sl.full.bytes;
+      a.off_dict = tail ? q.sl.tail.off_dict : q.sl.full.off_dict;
+      a.max_sweeps = q.p.oi_max_sweeps;
+      a.tol = q.p.oi_tol;
+      a.stats = stats + q.stats_off + (tail ? q.sl.nw_full : 0);
+      const int ai = (int)args.size();
+      args.push_back(a);
+      const int tmax = a.T <= 32 ? 32 : 64, kr = a.k <= 16 ? 16 : 32;
+      for (int c = 0; c < 3; ++c) {
+        if (a.init == DMC_INIT_PREV)
+          jobs.push_back({tmax, kr, ai, 0, nw, c});
+        else
+          for (int w = 0; w < nw; ++w) jobs.push_back({tmax, kr, ai, w, w + 1, c});
+      }
+    }
+  }
+  std::stable_sort(jobs.begin(), jobs.end(), [](const std::array<int, 6>& x,
+                                                const std::array<int, 6>& y) {
+    return x[0] != y[0] ? x[0] < y[0] : x[1] < y[1];
+  });
+  std::vector<int4> dj(jobs.size());
+  for (size_t j = 0; j < jobs.size(); ++j) {
+    dj[j] = make_int4(jobs[j][2], jobs[j][3], jobs[j][4], jobs[j][5]);
+    if (j == 0 || jobs[j][0] != jobs[j - 1][0] || jobs[j][1] != jobs[j - 1][1]) {
+      b->cls_tmax.push_back(jobs[j][0]);
+      b->cls_kr.push_back(jobs[j][1]);
+      b->cls_off.push_back((int)j);
+      b->cls_n.push_back(0);
+    }
+    ++b->cls_n.back();
+  }
+  if (hipMemcpy(b->buf + b->o_args, args.data(), args.size() * sizeof(dmc::OiArgs),
+                hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(b->buf + b->o_jobs, dj.data(), dj.size() * sizeof(int4),
+                hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipFree(b->buf);
+    return bail(fail(DMC_ERR_DEVICE, "cannot upload the batch's job table"));
+  }
+  // autotuner: vertex split of the covariance kernel, frames per workgroup of
+  // the delta kernel, timed on each sequence's own frames
+  hipStream_t s = ctx->stream;
+  uint8_t* sh = b->buf + b->o_shared;
+  for (BatchSeq& q : b->seq) {
+    const dmc::MeshDev& m = q.mesh->dev;
+    float best = 1e30f;
+    for (int fpb : {4, 8, 16}) {
+      const float t = time_launch(s, [&] {
+        dmc::launch_delta(s, m, q.frames, b->buf + q.o_delta, q.F, b->precision, fpb);
+      });
+      if (t < best) {
+        best = t;
+        q.fpb = fpb;
+      }
+    }
+    if (!q.sl.nw_full) continue;
+    const int P0 = dmc::autocorr_blocks(m.n, q.sl.nw_full);
+    best = 1e30f;
+    for (int P : {P0 / 4, P0 / 2, P0, 2 * P0, 4 * P0}) {
+      if (P < 1 || P > std::max(1, m.n)) continue;
+      const float t = time_launch(s, [&] {
+        dmc::launch_autocorr(s, q.frames, m.n, q.T, q.sl.nw_full, b->precision, sh,
+                             (double*)(b->buf + q.o_R), P);
+      });
+      if (t < best) {
+        best = t;
+        q.P = P;
+      }
+    }
+  }
+  dmc_status st = check_launch("batch autotuner");
+  if (st == DMC_OK &&
+      (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess ||
+       hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) != hipSuccess ||
+       hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) != hipSuccess)) {
+    (void)hipGetLastError();
+    st = fail(DMC_ERR_DEVICE, "cannot create the batch's stream");
+  }
+  if (st != DMC_OK) {
+    dmc_batch_destroy(b);
+    return st;
+  }
+  *out = b;
+  return DMC_OK;
+}
+
+dmc_status dmc_batch_run(dmc_batch b) {
+  if (!b) return fail(DMC_ERR_INVALID_ARG, "NULL batch");
+  HIP_TRY(hipSetDevice(b->ctx->device));
+  hipStream_t s = b->stream;
+  if (!b->exec) {
+    dmc::prof::pause(true);
+    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      batch_enqueue(b, s);
+      e = hipStreamEndCapture(s, &b->graph);
+    }
+    dmc::prof::pause(false);
+    if (e != hipSuccess)
+      return fail(DMC_ERR_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    HIP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+  }
+  // ordered after earlier work on the context's stream, and before later work
+  HIP_TRY(hipEventRecord(b->ev_in, b->ctx->stream));
+  HIP_TRY(hipStreamWaitEvent(s, b->ev_in, 0));
+  HIP_TRY(hipGraphLaunch(b->exec, s));
+  HIP_TRY(hipEventRecord(b->ev_out, s));
+  HIP_TRY(hipStreamWaitEvent(b->ctx->stream, b->ev_out, 0));
+  return check_launch("batch graph");
+}
+
+dmc_status dmc_batch_stats(dmc_batch b, int32_t i, dmc_window_stats* per_window) {
+  if (!b || !per_window) return fail(DMC_ERR_INVALID_ARG, "NULL argument");
+  if (i < 0 || i >= (int32_t)b->seq.size()) return fail(DMC_ERR_INVALID_ARG, "bad sequence index");
+  const BatchSeq& q = b->seq[i];
+  const int32_t nw = q.sl.nw_full + (q.sl.T_tail ? 1 : 0);
+  HIP_TRY(hipSetDevice(b->ctx->device));
+  dmc_status st = ensure_pinned(b->ctx, sizeof(dmc::StatsDev) * nw + 64);
+  if (st != DMC_OK) return st;
+  uint8_t* h = (uint8_t*)b->ctx->pinned;
+  HIP_TRY(hipMemcpyAsync(h, b->buf + b->o_stats + q.stats_off * sizeof(dmc::StatsDev),
+                         sizeof(dmc::StatsDev) * nw, hipMemcpyDeviceToHost, b->ctx->stream));
+  HIP_TRY(hipMemcpyAsync(h + sizeof(dmc::StatsDev) * nw, b->buf + b->o_summary + 16 * i, 16,
+                         hipMemcpyDeviceToHost, b->ctx->stream));
+  HIP_TRY(hipStreamSynchronize(b->ctx->stream));
+  const dmc::StatsDev* hs = (const dmc::StatsDev*)h;
+  const double* sum = (const double*)(h + sizeof(dmc::StatsDev) * nw);
+  for (int32_t w = 0; w < nw; ++w) {
+    std::memset(&per_window[w], 0, sizeof(dmc_window_stats));
+    const bool tail = w >= q.sl.nw_full;
+    fill_stats(&per_window[w], hs[w], tail ? q.sl.T_tail : q.T, tail ? q.k_tail : q.k_full);
+    per_window[w].cg_iters = q.out ? q.p.cg_max_iters : 0;
+    per_window[w].cg_resid = q.out ? sum[0] : 0.0;
+  }
+  if (q.out && sum[1] == 0.0)
+    return fail(DMC_ERR_NOT_CONVERGED, "sequence " + std::to_string(i) +
+                                           ": some column did not reach cg_tol");
+  return DMC_OK;
+}
+
+dmc_status dmc_batch_tuning(dmc_batch b, int32_t i, int32_t tuning[2]) {
+  if (!b || !tuning) return fail(DMC_ERR_INVALID_ARG, "NULL argument");
+  if (i < 0 || i >= (int32_t)b->seq.size()) return fail(DMC_ERR_INVALID_ARG, "bad sequence index");
+  tuning[0] = b->seq[i].P;
+  tuning[1] = b->seq[i].fpb;
+  return DMC_OK;
+}
+
+void dmc_batch_destroy(dmc_batch b) {
+  if (!b) return;
+  (void)hipSetDevice(b->ctx->device);
+  (void)hipStreamSynchronize(b->ctx->stream);
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->ev_in) (void)hipEventDestroy(b->ev_in);
+  if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+  if (b->stream) (void)hipStreamDestroy(b->stream);
+  if (b->buf) (void)hipFree(b->buf);
+  delete b;
 }

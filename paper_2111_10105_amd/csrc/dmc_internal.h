@@ -80,16 +80,18 @@ struct StatsDev {
 
 // ---- kernel launchers (kernels_*.hip) --------------------------------------
 
-// Delta coordinates for F frames.
+// Delta coordinates for F frames; fpb frames per workgroup (a tuning knob).
 void launch_delta(hipStream_t s, const MeshDev& m, const void* in, void* out, int32_t F,
-                  int32_t precision);
+                  int32_t precision, int fpb = 8);
 
 // Autocorrelation of nw consecutive windows of T frames each:
 // frames [nw*T][n][3] -> R [nw][3][T][T] float64.  `part` is scratch of
-// autocorr_scratch_bytes(...) bytes.
-size_t autocorr_scratch_bytes(int32_t n, int32_t T, int32_t nw, int32_t precision);
+// autocorr_scratch_bytes(...) bytes.  P = vertex blocks per window (a tuning
+// knob; 0 = the default for n and nw).
+size_t autocorr_scratch_bytes(int32_t n, int32_t T, int32_t nw, int32_t precision, int P = 0);
 void launch_autocorr(hipStream_t s, const void* frames, int32_t n, int32_t T, int32_t nw,
-                     int32_t precision, void* part, double* R);
+                     int32_t precision, void* part, double* R, int P = 0);
+int autocorr_blocks(int n, int nw);
 
 // Orthogonal iterations + Ritz + dictionary quantisation over a chain of nw
 // windows of T frames (window w starts from window w-1's U_k).
@@ -112,6 +114,11 @@ struct OiArgs {
   StatsDev* stats;       // [nw]
 };
 void launch_oi(hipStream_t s, const OiArgs& a);
+// jobs[b] = (index into args, first window, end window, coordinate); the
+// (TMAX, KR) class is the largest T (<= 32 or <= 64) and k (<= 16 or <= 32)
+// of the jobs
+void launch_oi_batch(hipStream_t s, int tmax, int kr, int precision, const OiArgs* args,
+                     const int4* jobs, int njobs);
 
 // Learned start (row-wise perceptron on the sketch R Omega).
 int mlp_param_count(int k);
@@ -173,6 +180,9 @@ void launch_cg_step_a(hipStream_t s, const MeshDev& m, int32_t ncols, const CgBu
                       int32_t precond, double tol);
 void launch_cg_step_b(hipStream_t s, const MeshDev& m, int32_t ncols, const CgBuffers& cb,
                       int32_t precond);
+// summary of a solve on the device: out[0] = max relative residual, out[1] =
+// 1.0 if every column converged
+void launch_cg_summary(hipStream_t s, const CgBuffers& cb, int32_t ncols, double* out);
 void launch_chol_solve(hipStream_t s, const CholDev& f, int32_t ncols, const double* r, double* z,
                        double* W, double* Y, double* X, double* U);
 void launch_precond_apply(hipStream_t s, const MeshDev& m, int32_t ncols, const CgBuffers& cb);

@@ -433,6 +433,41 @@ void launch_cg_step_a(hipStream_t s, const MeshDev& m, int32_t ncols, const CgBu
                      cb.done, cb.resid, tol);
 }
 
+namespace {
+// out[0] = largest relative residual over the columns, out[1] = 1 if every
+// column has converged (else 0)
+__global__ void __launch_bounds__(kBlock)
+k_cg_summary(const double* __restrict__ resid, const int32_t* __restrict__ done, int ncols,
+             double* __restrict__ out) {
+  __shared__ double smax[kBlock];
+  __shared__ int sdone[kBlock];
+  double m = 0.0;
+  int d = 1;
+  for (int j = threadIdx.x; j < ncols; j += kBlock) {
+    m = fmax(m, resid[j]);
+    d = d && (done[j] != 0);
+  }
+  smax[threadIdx.x] = m;
+  sdone[threadIdx.x] = d;
+  __syncthreads();
+  for (int st = kBlock / 2; st > 0; st >>= 1) {
+    if (threadIdx.x < st) {
+      smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + st]);
+      sdone[threadIdx.x] = sdone[threadIdx.x] && sdone[threadIdx.x + st];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = smax[0];
+    out[1] = sdone[0] ? 1.0 : 0.0;
+  }
+}
+}  // namespace
+
+void launch_cg_summary(hipStream_t s, const CgBuffers& cb, int32_t ncols, double* out) {
+  hipLaunchKernelGGL(k_cg_summary, dim3(1), dim3(kBlock), 0, s, cb.resid, cb.done, ncols, out);
+}
+
 void launch_cg_step_b(hipStream_t s, const MeshDev& m, int32_t ncols, const CgBuffers& cb,
                       int32_t precond) {
   const int nrb = (int)cg_part_rows(m.n);

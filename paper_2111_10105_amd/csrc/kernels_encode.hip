@@ -256,11 +256,6 @@ k_autocorr_bf16(const float* __restrict__ frames, int n, int T, int nw, int P,
 
 int pad_T(int T) { return T <= 32 ? 32 : 64; }
 
-int autocorr_blocks(int n, int nw) {
-  int P = (1024 + nw - 1) / nw;
-  P = std::max(1, std::min(P, (n + AC_VT - 1) / AC_VT));
-  return P;
-}
 
 // ---------------------------------------------------------------------------
 // Projection (Eq. 9): Y_c[r][i] = sum_t U~_c[t][r] delta[t][i][c] for the k
@@ -441,9 +436,15 @@ __global__ void k_header(int32_t* h, int32_t T, int32_t k, int32_t n, int32_t nc
 
 }  // namespace
 
+int autocorr_blocks(int n, int nw) {
+  int P = (1024 + nw - 1) / nw;
+  P = std::max(1, std::min(P, (n + AC_VT - 1) / AC_VT));
+  return P;
+}
+
 void launch_delta(hipStream_t s, const MeshDev& m, const void* in, void* out, int32_t F,
-                  int32_t precision) {
-  const int fpb = 8;
+                  int32_t precision, int fpb) {
+  if (fpb < 1) fpb = 8;
   dim3 grid((3 * m.n + kBlock - 1) / kBlock, (F + fpb - 1) / fpb);
   const int uni = m.laplacian == DMC_LAP_UNIFORM;
   prof::begin(s, DMC_KERNEL_DELTA);
@@ -461,8 +462,8 @@ void launch_delta(hipStream_t s, const MeshDev& m, const void* in, void* out, in
 // magnitude (the mean shape dominates), and eigen-trajectories far below the
 // largest one still carry delta-coordinate energy, so float32 accumulation would
 // change the reconstruction measurably.
-size_t autocorr_scratch_bytes(int32_t n, int32_t T, int32_t nw, int32_t precision) {
-  const int P = autocorr_blocks(n, nw);
+size_t autocorr_scratch_bytes(int32_t n, int32_t T, int32_t nw, int32_t precision, int P) {
+  if (P < 1) P = autocorr_blocks(n, nw);
   const int TP = pad_T(T);
   return (size_t)nw * P * 3 * TP * TP * (precision == DMC_BF16 ? 4 : 8);
 }
@@ -470,8 +471,7 @@ size_t autocorr_scratch_bytes(int32_t n, int32_t T, int32_t nw, int32_t precisio
 // precision form: bfloat16 products accumulated in float32, partials added in
 // float64 in a fixed order
 static void autocorr_bf16(hipStream_t s, const float* frames, int32_t n, int32_t T, int32_t nw,
-                          float* part, double* R) {
-  const int P = autocorr_blocks(n, nw);
+                          float* part, double* R, int P) {
   dim3 grid(P, nw);
   const int tot = nw * 3 * T * T;
   dim3 rgrid((tot + kBlock - 1) / kBlock);
@@ -493,8 +493,7 @@ static void autocorr_bf16(hipStream_t s, const float* frames, int32_t n, int32_t
 
 template <typename In>
 static void autocorr_impl(hipStream_t s, const In* frames, int32_t n, int32_t T, int32_t nw,
-                          double* part, double* R) {
-  const int P = autocorr_blocks(n, nw);
+                          double* part, double* R, int P) {
   dim3 grid(P, nw);
   const int tot = nw * 3 * T * T;
   dim3 rgrid((tot + kBlock - 1) / kBlock);
@@ -515,13 +514,15 @@ static void autocorr_impl(hipStream_t s, const In* frames, int32_t n, int32_t T,
 }
 
 void launch_autocorr(hipStream_t s, const void* frames, int32_t n, int32_t T, int32_t nw,
-                     int32_t precision, void* part, double* R) {
+                     int32_t precision, void* part, double* R, int P) {
+  if (P < 1) P = autocorr_blocks(n, nw);
+  P = std::min(P, std::max(1, n));
   if (precision == DMC_FP64)
-    autocorr_impl(s, (const double*)frames, n, T, nw, (double*)part, R);
+    autocorr_impl(s, (const double*)frames, n, T, nw, (double*)part, R, P);
   else if (precision == DMC_BF16)
-    autocorr_bf16(s, (const float*)frames, n, T, nw, (float*)part, R);
+    autocorr_bf16(s, (const float*)frames, n, T, nw, (float*)part, R, P);
   else
-    autocorr_impl(s, (const float*)frames, n, T, nw, (double*)part, R);
+    autocorr_impl(s, (const float*)frames, n, T, nw, (double*)part, R, P);
 }
 
 size_t project_scratch_bytes(int32_t n, int32_t T, int32_t k, int32_t nw, int32_t precision) {

@@ -827,22 +827,19 @@ __device__ __forceinline__ void oi_sweeps(OiSmem<TMAX, KMAX>& s, int T, int k, i
 
 // One workgroup (one wavefront) per coordinate; KR = k rounded up to the
 // 16-column tile of the matrix-core products (16 or 32).
+// The work of one workgroup: coordinate c of windows w_begin..w_end-1 (the
+// whole chain for DMC_INIT_PREV, one window otherwise).
 template <int TMAX, int KMAX, int KR, typename Real>
-__global__ void __launch_bounds__(NT) k_oi(OiArgs a) {
-  __shared__ OiSmem<TMAX, KMAX> s;
-  const int c = blockIdx.x;  // coordinate
+__device__ __forceinline__ void oi_run(OiSmem<TMAX, KMAX>& s, const OiArgs& a, int c, int w_begin,
+                                       int w_end) {
   const int T = a.T, k = a.k;
   const int tid = threadIdx.x;
+  const bool chain = a.init == DMC_INIT_PREV;
   for (int e = tid; e < TMAX * s.LQ; e += NT) {
     s.Q[e] = 0.0;
     s.Y[e] = 0.0;
   }
   __syncthreads();
-  // DMC_INIT_PREV chains the windows in one workgroup per coordinate; the
-  // other starts give every (window, coordinate) its own workgroup
-  const bool chain = a.init == DMC_INIT_PREV;
-  const int w_begin = chain ? 0 : (int)blockIdx.y;
-  const int w_end = chain ? a.nw : w_begin + 1;
   for (int w = w_begin; w < w_end; ++w) {
     // ---- load R_c of window w (zero padded), every load in flight at once ----
     const double* Rg = a.R + ((size_t)w * a.ncoord + c) * T * T;
@@ -956,6 +953,27 @@ __global__ void __launch_bounds__(NT) k_oi(OiArgs a) {
   }
 }
 
+// DMC_INIT_PREV chains the windows in one workgroup per coordinate; the other
+// starts give every (window, coordinate) its own workgroup.
+template <int TMAX, int KMAX, int KR, typename Real>
+__global__ void __launch_bounds__(NT) k_oi(OiArgs a) {
+  __shared__ OiSmem<TMAX, KMAX> s;
+  const bool chain = a.init == DMC_INIT_PREV;
+  const int w_begin = chain ? 0 : (int)blockIdx.y;
+  oi_run<TMAX, KMAX, KR, Real>(s, a, blockIdx.x, w_begin, chain ? a.nw : w_begin + 1);
+}
+
+// Many sequences in one launch: workgroup b runs job jobs[b] = (sequence,
+// first window, end window, coordinate) of args[sequence].
+template <int TMAX, int KMAX, int KR, typename Real>
+__global__ void __launch_bounds__(NT) k_oi_batch(const OiArgs* __restrict__ args,
+                                                 const int4* __restrict__ jobs) {
+  __shared__ OiSmem<TMAX, KMAX> s;
+  const int4 j = jobs[blockIdx.x];
+  const OiArgs a = args[j.x];
+  oi_run<TMAX, KMAX, KR, Real>(s, a, j.w, j.y, j.z);
+}
+
 }  // namespace
 
 template <int TMAX, int KR>
@@ -965,6 +983,28 @@ void launch_oi_t(hipStream_t st, const OiArgs& a) {
     hipLaunchKernelGGL((k_oi<TMAX, 32, KR, double>), grid, dim3(NT), 0, st, a);
   else
     hipLaunchKernelGGL((k_oi<TMAX, 32, KR, float>), grid, dim3(NT), 0, st, a);
+}
+
+template <int TMAX, int KR>
+void launch_oi_batch_t(hipStream_t st, int precision, const OiArgs* args, const int4* jobs,
+                       int njobs) {
+  if (precision == DMC_FP64)
+    hipLaunchKernelGGL((k_oi_batch<TMAX, 32, KR, double>), dim3(njobs), dim3(NT), 0, st, args, jobs);
+  else
+    hipLaunchKernelGGL((k_oi_batch<TMAX, 32, KR, float>), dim3(njobs), dim3(NT), 0, st, args, jobs);
+}
+
+void launch_oi_batch(hipStream_t st, int tmax, int kr, int precision, const OiArgs* args,
+                     const int4* jobs, int njobs) {
+  if (njobs <= 0) return;
+  prof::begin(st, DMC_KERNEL_OI);
+  if (tmax <= 32)
+    kr <= 16 ? launch_oi_batch_t<32, 16>(st, precision, args, jobs, njobs)
+             : launch_oi_batch_t<32, 32>(st, precision, args, jobs, njobs);
+  else
+    kr <= 16 ? launch_oi_batch_t<64, 16>(st, precision, args, jobs, njobs)
+             : launch_oi_batch_t<64, 32>(st, precision, args, jobs, njobs);
+  prof::end(st, DMC_KERNEL_OI);
 }
 
 void launch_oi(hipStream_t st, const OiArgs& a) {

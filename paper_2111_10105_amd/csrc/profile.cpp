@@ -9,6 +9,7 @@ namespace prof {
 namespace {
 
 int g_selected = -1;
+bool g_paused = false;  // no events while a stream is being captured into a graph
 std::vector<hipEvent_t> g_pool;  // begin/end pairs, reused between sessions
 size_t g_used = 0;
 
@@ -24,12 +25,14 @@ hipEvent_t next_event() {
 }  // namespace
 
 void begin(hipStream_t s, int kernel) {
-  if (kernel != g_selected) return;
+  if (kernel != g_selected || g_paused) return;
   hipEvent_t e = next_event();
   if (e) (void)hipEventRecord(e, s);
 }
 
 void end(hipStream_t s, int kernel) { begin(s, kernel); }
+
+void pause(bool on) { g_paused = on; }
 
 }  // namespace prof
 }  // namespace dmc

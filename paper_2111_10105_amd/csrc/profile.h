@@ -10,6 +10,8 @@ namespace prof {
 
 void begin(hipStream_t s, int kernel);
 void end(hipStream_t s, int kernel);
+// suspend event recording (while a stream is captured into a graph)
+void pause(bool on);
 
 }  // namespace prof
 }  // namespace dmc

@@ -31,7 +31,8 @@ EXPORTS = ["dmc_create", "dmc_destroy", "dmc_set_stream", "dmc_last_error", "dmc
            "dmc_decode_window", "dmc_compress_sequence", "dmc_decode_sequence", "dmc_delta",
            "dmc_autocorrelation", "dmc_profile_start", "dmc_profile_stop", "dmc_oi_blocks",
            "dmc_mlp_param_count", "dmc_learned_start", "dmc_mlp_sketch", "dmc_mlp_forward",
-           "dmc_mlp_loss_grad", "dmc_mlp_backward", "dmc_mlp_adam"]
+           "dmc_mlp_loss_grad", "dmc_mlp_backward", "dmc_mlp_adam", "dmc_batch_create",
+           "dmc_batch_run", "dmc_batch_stats", "dmc_batch_tuning", "dmc_batch_destroy"]
 
 KERNELS = ["delta", "autocorr", "oi", "project", "quantise", "anchors", "back_project", "rhs",
            "cg_spmm", "cg_update", "chol_fwd_gather", "chol_fwd_solve", "chol_bwd_gather",
@@ -125,6 +126,13 @@ def lib():
         "dmc_mlp_loss_grad": (i32, [vp, vp, vp, i32, i32, i32, dbl, vp, vp]),
         "dmc_mlp_backward": (i32, [vp, vp, i32, vp, i32, vp, vp, vp]),
         "dmc_mlp_adam": (i32, [vp, vp, vp, vp, vp, i32, i32, dbl, dbl, dbl, dbl]),
+        "dmc_batch_create": (i32, [vp, i32, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                   ctypes.POINTER(i32), ctypes.POINTER(i32), P, ctypes.POINTER(vp),
+                                   ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp)]),
+        "dmc_batch_run": (i32, [vp]),
+        "dmc_batch_stats": (i32, [vp, i32, S]),
+        "dmc_batch_tuning": (i32, [vp, i32, ctypes.POINTER(i32)]),
+        "dmc_batch_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -508,4 +516,73 @@ def mlp_adam(ctx: Context, theta, grad, m, v, step: int, lr: float, beta1: float
     ctx.sync_stream()
     _check(lib().dmc_mlp_adam(ctx.h, _ptr(theta), _ptr(grad), _ptr(m), _ptr(v), theta.numel(),
                               int(step), float(lr), float(beta1), float(beta2), float(eps)))
+
+
+# ---- batched form ------------------------------------------------------------
+
+class Batch:
+    """Many independent sequences encoded and decoded by one replayed HIP
+    graph.  frames: list of CUDA tensors [F_i][n_i][3] (one dtype), meshes:
+    list of Mesh, Ts: window lengths, params: list of Params (one precision),
+    q_starts: optional list of start blocks (as for compress_sequence).  The
+    batch allocates each sequence's record buffer and (with decode=True) its
+    output frames; their addresses stay fixed for the life of the batch."""
+
+    def __init__(self, ctx: Context, meshes, frames, Ts, params, q_starts=None, decode=True):
+        import torch
+        nseq = len(frames)
+        if not (len(meshes) == len(Ts) == len(params) == nseq) or nseq < 1:
+            raise ValueError("meshes, frames, Ts and params must have one entry per sequence")
+        ctx.sync_stream()
+        self.ctx = ctx
+        self.frames = frames
+        self.meshes = meshes
+        self.Ts = [int(t) for t in Ts]
+        self.params = list(params)
+        self.q_starts = list(q_starts) if q_starts is not None else [None] * nseq
+        for f, T, p, q in zip(frames, self.Ts, self.params, self.q_starts):
+            if not f.is_cuda or not f.is_contiguous():
+                raise ValueError("frames must be contiguous CUDA tensors")
+            _check_start(q, f, T, p, nw=f.shape[0] // T)
+        self.codes = [torch.empty(sequence_code_bytes(m.n, f.shape[0], T, m.nc, p), dtype=torch.uint8,
+                                  device=f.device)
+                      for m, f, T, p in zip(meshes, frames, self.Ts, self.params)]
+        self.out = [torch.empty_like(f) for f in frames] if decode else None
+        vpa = ctypes.c_void_p * nseq
+        P = (Params * nseq)(*self.params)
+        h = ctypes.c_void_p()
+        _check(lib().dmc_batch_create(
+            ctx.h, nseq, vpa(*[m.h for m in meshes]), vpa(*[f.data_ptr() for f in frames]),
+            (ctypes.c_int32 * nseq)(*[f.shape[0] for f in frames]), (ctypes.c_int32 * nseq)(*self.Ts),
+            P, vpa(*[q.data_ptr() if q is not None else None for q in self.q_starts]),
+            vpa(*[c.data_ptr() for c in self.codes]),
+            vpa(*[o.data_ptr() for o in self.out]) if decode else None, ctypes.byref(h)))
+        self.h = h
+
+    def run(self):
+        self.ctx.sync_stream()
+        _check(lib().dmc_batch_run(self.h))
+
+    def stats(self, i: int):
+        nw = (self.frames[i].shape[0] + self.Ts[i] - 1) // self.Ts[i]
+        sts = (WindowStats * nw)()
+        status = lib().dmc_batch_stats(self.h, int(i), sts)
+        _check(status, allow=(4,))
+        return [s.as_dict() for s in sts], status
+
+    def tuning(self, i: int):
+        t = (ctypes.c_int32 * 2)()
+        _check(lib().dmc_batch_tuning(self.h, int(i), t))
+        return {"autocorr_blocks": t[0], "delta_frames_per_block": t[1]}
+
+    def close(self):
+        if self.h:
+            lib().dmc_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 

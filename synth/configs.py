@@ -80,6 +80,37 @@ def small_torus(a: int = 24, b: int = 20, frames: int = 40, T: int = 16, k: int 
                     T=T, k=k, bits=bits, precision=precision)
 
 
+def batched(count: int = 64, n_range=(2000, 60000), f_range=(16, 128), ks=(8, 16, 32),
+            seed: int = 4000, bones: int = 6):
+    """Independent sequences of uneven size for the batched form: mesh type
+    torus or icosphere (the icosphere level whose size is nearest the drawn
+    n, from levels 2..6), torus a = round(sqrt(n)), b = round(n / a); frame
+    count uniform in f_range, k drawn from ks, window T = 2k, 1% anchors (at
+    least 4), RBF skinning seeded per sequence, float32."""
+    rng = np.random.default_rng(seed)
+    out = []
+    levels = {L: 10 * 4 ** L + 2 for L in range(2, 7)}
+    for i in range(count):
+        n_target = int(rng.integers(n_range[0], n_range[1] + 1))
+        if rng.random() < 0.5:
+            a = max(3, int(round(np.sqrt(n_target))))
+            b = max(3, int(round(n_target / a)))
+            v, t = meshes.torus(a, b)
+            name = f"torus{a}x{b}"
+        else:
+            L = min(levels, key=lambda x: abs(levels[x] - n_target))
+            v, t = meshes.icosphere(L)
+            name = f"icosphere{L}"
+        F = int(rng.integers(f_range[0], f_range[1] + 1))
+        k = int(ks[int(rng.integers(0, len(ks)))])
+        fr = animate.rbf_skinning(v, F, bones, seed=seed + 1 + i, dtype=np.float32)
+        nc = max(4, int(round(0.01 * v.shape[0])))
+        anc = animate.choose_anchors(v.shape[0], nc, seed=seed + 1001 + i)
+        out.append(Workload(f"{name}-{F}f-T{2 * k}-k{k}", v, t, fr, anc, T=2 * k, k=k, bits=12,
+                            precision="fp32"))
+    return out
+
+
 REGISTRY = {
     "plain_fp64": plain_fp64,
     "torus_fp32": torus_fp32,
