@@ -62,6 +62,9 @@ def parse():
     ap.add_argument("--profile-kernel", default=None,
                     help="kernel family timed live (default: the dominant one)")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="MB")
+    ap.add_argument("--workload", default="torus", choices=["torus", "icosphere7", "batched"],
+                    help="torus: the headline workload; icosphere7: the precision form's "
+                         "size; batched: 64 sequences in one graph")
     return ap.parse_args()
 
 
@@ -154,6 +157,99 @@ def train_learned_start(ctx, dmc, w, dev, mesh):
             "data": "seeded RBF animations 5000-5005 of the same torus"}
 
 
+def _timed(fn, steps, warmup):
+    import torch
+    for _ in range(max(1, warmup)):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def bench_icosphere7(args):
+    """Icosphere level 7 (163,842 vertices), 512 frames in windows of 64,
+    k = 32, 10-bit codes, 1,638 anchors: the float32 form and the precision
+    form (bfloat16 covariance and C.Q) with the chained start."""
+    import numpy as np
+    import torch
+    from paper_2111_10105_amd import dmc
+    from synth import animate, configs
+    t0 = time.perf_counter()
+    w = configs.icosphere7()
+    gen_s = time.perf_counter() - t0
+    n, F, T = w.n, w.F, w.T
+    dev = torch.device("cuda:0")
+    frames = torch.from_numpy(w.frames).to(dev)
+    q0 = torch.from_numpy(animate.gaussian_subspace(T, w.k, FIRST_START_SEED).astype(np.float32)).to(dev)
+    ctx = dmc.Context(0)
+    t0 = time.perf_counter()
+    mesh = dmc.Mesh(ctx, n, w.tris, w.anchors)
+    setup_s = time.perf_counter() - t0
+    out = {}
+    steps = max(1, min(args.steps, 5))
+    for name, prec in (("fp32", dmc.FP32), ("bf16", dmc.BF16)):
+        p = dmc.make_params(w.k, coef_bits=w.bits, precision=prec)
+        codes = torch.empty(dmc.sequence_code_bytes(n, F, T, mesh.nc, p), dtype=torch.uint8,
+                            device=dev)
+        o = torch.empty_like(frames)
+        sec = _timed(lambda: dmc.compress_sequence(ctx, mesh, frames, T, p, q_start=q0, codes=codes,
+                                                   out=o, stats=False), steps, 1)
+        _, _, st, status = dmc.compress_sequence(ctx, mesh, frames, T, p, q_start=q0, codes=codes,
+                                                 out=o, stats=True)
+        torch.cuda.synchronize()
+        enc = _timed(lambda: dmc.compress_sequence(ctx, mesh, frames, T, p, q_start=q0, codes=codes,
+                                                   decode=False, stats=False), steps, 1)
+        out[name] = {"ms_per_step": round(sec * 1e3, 3), "value": round(n * F / sec, 1),
+                     "encode_ms": round(enc * 1e3, 3),
+                     "oi_sweeps_total": int(sum(sum(x["oi_sweeps"]) for x in st)),
+                     "cg_resid": st[0]["cg_resid"], "status": status,
+                     "nmse_vs_input": nmse(o.cpu().numpy(), w.frames)}
+    print(json.dumps({"workload": w.name, "vertices": n, "frames": F, "window": T, "k": w.k,
+                      "bits": w.bits, "anchors": int(mesh.nc), "generate_s": round(gen_s, 1),
+                      "setup_s": round(setup_s, 2), "factor": mesh.factor_info(), "steps": steps,
+                      "forms": out, "unit": "vertex-frames/s", "data": "synthetic"}))
+    ctx.close()
+
+
+def bench_batched(args):
+    """64 independent sequences (tori and icospheres of 2k-60k vertices,
+    16-128 frames, k in {8, 16, 32}, T = 2k, 1% anchors, float32) encoded and
+    decoded by one replayed HIP graph."""
+    import torch
+    from paper_2111_10105_amd import dmc
+    from synth import configs
+    t0 = time.perf_counter()
+    ws = configs.batched()
+    gen_s = time.perf_counter() - t0
+    ctx = dmc.Context(0)
+    t0 = time.perf_counter()
+    meshes = [dmc.Mesh(ctx, w.n, w.tris, w.anchors) for w in ws]
+    setup_s = time.perf_counter() - t0
+    frames = [torch.from_numpy(w.frames).cuda() for w in ws]
+    params = [dmc.make_params(w.k, coef_bits=w.bits, precision=dmc.FP32, init=dmc.INIT_EXACT,
+                              cg_max_iters=1) for w in ws]
+    t0 = time.perf_counter()
+    b = dmc.Batch(ctx, meshes, frames, [w.T for w in ws], params)
+    plan_s = time.perf_counter() - t0
+    b.run()
+    torch.cuda.synchronize()
+    sec = _timed(b.run, max(1, min(args.steps, 10)), 1)
+    vf = sum(w.n * w.F for w in ws)
+    conv = [b.stats(i)[1] == 0 for i in range(len(ws))]
+    err = [nmse(b.out[i].cpu().numpy(), ws[i].frames) for i in range(len(ws))]
+    print(json.dumps({"workload": "batched-64", "sequences": len(ws), "vertex_frames": vf,
+                      "ms_per_run": round(sec * 1e3, 3), "value": round(vf / sec, 1),
+                      "unit": "vertex-frames/s", "generate_s": round(gen_s, 1),
+                      "setup_s": round(setup_s, 2), "plan_s": round(plan_s, 2),
+                      "all_converged": bool(all(conv)), "nmse_vs_input_max": max(err),
+                      "tuning": [b.tuning(i) for i in range(len(ws))][:8], "data": "synthetic"}))
+    b.close()
+    ctx.close()
+
+
 def nmse(x, y) -> float:
     """sum (x - y)^2 / sum y^2 over every vertex, frame and coordinate."""
     import numpy as np
@@ -182,6 +278,12 @@ def main():
         sys.exit(2)
     if args.copy_calibration > 0:
         copy_calibration(args.copy_calibration)
+        return
+    if args.workload == "icosphere7":
+        bench_icosphere7(args)
+        return
+    if args.workload == "batched":
+        bench_batched(args)
         return
     import numpy as np
     import torch
