@@ -235,7 +235,7 @@ dmc_status check_learned(dmc_ctx ctx, const dmc_params& p, int32_t T) {
 
 // Decoder buffers for ncols right-hand sides, carved from one region.
 struct DecodeLayout {
-  size_t o_x, o_r, o_p, o_q, o_part, o_small, o_z, o_W, o_Y, o_X, o_U, total;
+  size_t o_x, o_r, o_p, o_q, o_part, o_small, o_z, o_W, o_Y, o_X, o_U, o_S, total;
 };
 
 DecodeLayout decode_layout(const dmc::MeshDev& m, int32_t ncols, bool chol) {
@@ -255,6 +255,7 @@ DecodeLayout decode_layout(const dmc::MeshDev& m, int32_t ncols, bool chol) {
     d.o_Y = cv.add(vec);
     d.o_X = cv.add(vec);
     d.o_U = cv.add((size_t)m.chol.nslots * ncols * 8);
+    d.o_S = cv.add(dmc::chol_split_bytes(m.chol, ncols));
   }
   d.total = cv.total();
   return d;
@@ -272,6 +273,7 @@ dmc::CgBuffers decode_buffers(uint8_t* ws, const DecodeLayout& d, int32_t ncols,
   cb.Y = chol ? (double*)(ws + d.o_Y) : nullptr;
   cb.X = chol ? (double*)(ws + d.o_X) : nullptr;
   cb.U = chol ? (double*)(ws + d.o_U) : nullptr;
+  cb.S = chol ? (double*)(ws + d.o_S) : nullptr;
   double* small = (double*)(ws + d.o_small);
   cb.rz = small;
   cb.rr = small + ncols;

@@ -166,6 +166,7 @@ void launch_rhs(hipStream_t s, const MeshDev& m, const uint8_t* records, const S
 struct CgBuffers {
   double *x, *r, *p, *q;
   double *z, *W, *Y, *X, *U;  // preconditioned residual and triangular-solve work
+  double* S;                    // split-K partials of the backward solve
   double* part;      // [nblk_rows][ncols] x 2
   double *rz, *rr, *bnorm2, *alpha, *beta;
   int32_t* done;     // [ncols]
@@ -183,8 +184,10 @@ void launch_cg_step_b(hipStream_t s, const MeshDev& m, int32_t ncols, const CgBu
 // summary of a solve on the device: out[0] = max relative residual, out[1] =
 // 1.0 if every column converged
 void launch_cg_summary(hipStream_t s, const CgBuffers& cb, int32_t ncols, double* out);
+// part: split-K scratch of chol_split_bytes(f, ncols) bytes (nullptr: no split)
+size_t chol_split_bytes(const CholDev& f, int32_t ncols);
 void launch_chol_solve(hipStream_t s, const CholDev& f, int32_t ncols, const double* r, double* z,
-                       double* W, double* Y, double* X, double* U);
+                       double* W, double* Y, double* X, double* U, double* part);
 void launch_precond_apply(hipStream_t s, const MeshDev& m, int32_t ncols, const CgBuffers& cb);
 void launch_to_frames(hipStream_t s, const double* X, int32_t n, int32_t F, int32_t precision,
                       void* frames_out);

@@ -12,7 +12,10 @@
 //   backward, top level downwards
 //     gemm   : X_s = B_s^T [Y_s; -X_(R_s below the diagonal block)],
 //              z[perm rows of s] = X_s
-// Work items are (supernode, 64-row tile) x 64-column tiles.  The two GEMMs
+// Work items are (supernode, 64-row tile) x 64-column tiles (the gather splits
+// each tile into four blocks of 16 rows; the backward GEMM splits its K range
+// over several blocks on levels with few tiles, and a second kernel adds the
+// partial sums in a fixed order).  The two GEMMs
 // stage 32-deep K slices of B_s and of the right-hand rows in LDS and run on
 // the FP64 matrix cores; the gather is one load per update row.
 #include "dmc_internal.h"
@@ -21,8 +24,9 @@ namespace dmc {
 namespace {
 
 constexpr int CT = 64;   // columns per block (one per lane)
-constexpr int RT = 64;   // rows per block
-constexpr int RPW = 16;  // rows per wave
+constexpr int RT = 64;   // rows per task
+constexpr int GQ = 4;    // gather: blocks per task (16 rows each, 4 per wave)
+constexpr int RPW = RT / GQ / (kBlock / 64);  // gather rows per wave
 
 __global__ void __launch_bounds__(kBlock)
 k_fwd_gather(CholDev f, int t0, int ncols, const double* __restrict__ rhs,
@@ -34,7 +38,7 @@ k_fwd_gather(CholDev f, int t0, int ncols, const double* __restrict__ rhs,
   if (c >= ncols) return;
   const int a = f.sn_start[s], w = f.sn_start[s + 1] - a;
   for (int k = 0; k < RPW; ++k) {
-    const int t = r0 + wv * RPW + k;
+    const int t = r0 + blockIdx.z * (RT / GQ) + wv * RPW + k;
     if (t >= w) break;
     const int j = a + t;
     double acc = rhs[(size_t)f.perm[j] * ncols + c];
@@ -56,6 +60,7 @@ k_fwd_gather(CholDev f, int t0, int ncols, const double* __restrict__ rhs,
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 constexpr int KC = 32;       // K chunk staged in LDS
+constexpr int RIDX = 2048;   // ancestor row indices cached per block
 constexpr int LDA = KC + 1;  // padded LDS strides
 constexpr int LDB = CT + 1;
 
@@ -167,9 +172,10 @@ k_fwd_gemm(CholDev f, int t0, int ncols, const double* __restrict__ W, double* _
 // (K = rows of B_s from t0 on: inv(L_ss) is lower triangular), two LDS stages
 __global__ void __launch_bounds__(kBlock)
 k_bwd_gemm(CholDev f, int t0, int ncols, const double* __restrict__ Y, double* __restrict__ X,
-           double* __restrict__ z) {
+           double* __restrict__ z, int nsplit, double* __restrict__ part) {
   __shared__ double As[2][RT * LDA];
   __shared__ double Bs[2][KC * LDB];
+  __shared__ int rows[RIDX];  // ancestor row indices of this block's K range
   const int task = t0 + blockIdx.x;
   const int s = f.task_w_sn[task], r0 = f.task_w_r0[task];
   const int c0 = blockIdx.y * CT;
@@ -179,6 +185,11 @@ k_bwd_gemm(CholDev f, int t0, int ncols, const double* __restrict__ Y, double* _
   const int tid = threadIdx.x, lane = tid % 64, wv = tid / 64;
   const int wr = wv / 2, wc = wv % 2;
   double ra[PER_T], rb[PER_T];
+  // split-K: this block's share of the K chunks (all of them when nsplit == 1)
+  const int nch = (m - r0 + KC - 1) / KC;
+  const int per = (nch + nsplit - 1) / nsplit;
+  const int kb = r0 + blockIdx.z * per * KC;
+  const int ke = min(m, kb + per * KC);
   auto load = [&](int i0) {
 #pragma unroll
     for (int u = 0; u < PER_T; ++u) {
@@ -190,8 +201,14 @@ k_bwd_gemm(CholDev f, int t0, int ncols, const double* __restrict__ Y, double* _
       const int i2 = e / CT, cc = e % CT;
       const int ib = i0 + i2, c = c0 + cc;
       double v = 0.0;
-      if (ib < m && c < ncols)
-        v = ib < w ? Y[(size_t)(a + ib) * ncols + c] : -X[(size_t)f.rowidx[rb0 + ib] * ncols + c];
+      if (ib < m && c < ncols) {
+        if (ib < w) {
+          v = Y[(size_t)(a + ib) * ncols + c];
+        } else {
+          const int ri = ib - kb < RIDX ? rows[ib - kb] : f.rowidx[rb0 + ib];
+          v = -X[(size_t)ri * ncols + c];
+        }
+      }
       rb[u] = v;
     }
   };
@@ -205,12 +222,16 @@ k_bwd_gemm(CholDev f, int t0, int ncols, const double* __restrict__ Y, double* _
   };
   MfmaTile t;
   t.zero();
-  int st = 0;
-  load(r0);
-  store(0);
+  for (int i = kb + threadIdx.x; i < min(ke, kb + RIDX); i += kBlock) rows[i - kb] = f.rowidx[rb0 + i];
   __syncthreads();
-  for (int i0 = r0; i0 < m; i0 += KC) {
-    const bool more = i0 + KC < m;
+  int st = 0;
+  if (kb < ke) {
+    load(kb);
+    store(0);
+  }
+  __syncthreads();
+  for (int i0 = kb; i0 < ke; i0 += KC) {
+    const bool more = i0 + KC < ke;
     if (more) load(i0 + KC);
     t.step(As[st], Bs[st], wr, wc, lane);
     if (more) store(st ^ 1);
@@ -223,26 +244,72 @@ k_bwd_gemm(CholDev f, int t0, int ncols, const double* __restrict__ Y, double* _
     for (int tb = 0; tb < 2; ++tb)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int tr = r0 + wr * 32 + ta * 16 + 4 * r + lane / 16;
+        const int lr = wr * 32 + ta * 16 + 4 * r + lane / 16;  // row within the tile
+        const int tr = r0 + lr;
         const int c = c0 + wc * 32 + tb * 16 + lane % 16;
         if (tr >= w || c >= ncols) continue;
         const double v = t.acc[ta][tb][r];
-        X[(size_t)(a + tr) * ncols + c] = v;
-        z[(size_t)f.perm[a + tr] * ncols + c] = v;
+        if (nsplit == 1) {
+          X[(size_t)(a + tr) * ncols + c] = v;
+          z[(size_t)f.perm[a + tr] * ncols + c] = v;
+        } else {
+          part[(((size_t)blockIdx.z * gridDim.x + blockIdx.x) * RT + lr) * ncols + c] = v;
+        }
       }
+}
+
+// sums the split-K partials of one level in split order (deterministic)
+__global__ void __launch_bounds__(kBlock)
+k_bwd_reduce(CholDev f, int t0, int ntasks, int ncols, int nsplit, const double* __restrict__ part,
+             double* __restrict__ X, double* __restrict__ z) {
+  const int task = t0 + blockIdx.x;
+  const int s = f.task_w_sn[task], r0 = f.task_w_r0[task];
+  const int a = f.sn_start[s], w = f.sn_start[s + 1] - a;
+  const int c0 = blockIdx.y * CT;
+  constexpr int RQ = RT / 4;  // rows per block (blockIdx.z picks the quarter)
+#pragma unroll
+  for (int u = 0; u < RQ * CT / kBlock; ++u) {
+    const int e = threadIdx.x + u * kBlock;
+    const int lr = blockIdx.z * RQ + e / CT, c = c0 + e % CT;
+    const int tr = r0 + lr;
+    if (tr >= w || c >= ncols) continue;
+    double v = 0.0;
+    for (int q = 0; q < nsplit; ++q)
+      v += part[(((size_t)q * ntasks + blockIdx.x) * RT + lr) * ncols + c];
+    X[(size_t)(a + tr) * ncols + c] = v;
+    z[(size_t)f.perm[a + tr] * ncols + c] = v;
+  }
+}
+
+// split factor of a backward level: enough blocks to occupy the chip
+int bwd_split(int ntw, int cb) {
+  const int blocks = ntw * cb;
+  if (blocks >= 512) return 1;
+  return std::min(8, (512 + blocks - 1) / blocks);
 }
 
 }  // namespace
 
+size_t chol_split_bytes(const CholDev& f, int32_t ncols) {
+  const int cb = (ncols + CT - 1) / CT;
+  size_t need = 0;
+  for (int lv = 0; lv < f.nlevels; ++lv) {
+    const int ntw = f.level_w_host[lv + 1] - f.level_w_host[lv];
+    const int ns = bwd_split(ntw, cb);
+    if (ns > 1) need = std::max(need, (size_t)ns * ntw * RT * ncols * sizeof(double));
+  }
+  return need;
+}
+
 void launch_chol_solve(hipStream_t s, const CholDev& f, int32_t ncols, const double* r, double* z,
-                       double* W, double* Y, double* X, double* U) {
+                       double* W, double* Y, double* X, double* U, double* part) {
   dim3 blk(kBlock);
   const int cb = (ncols + CT - 1) / CT;
   for (int lv = 0; lv < f.nlevels; ++lv) {
     const int tw0 = f.level_w_host[lv], ntw = f.level_w_host[lv + 1] - tw0;
     const int tm0 = f.level_m_host[lv], ntm = f.level_m_host[lv + 1] - tm0;
     prof::begin(s, DMC_KERNEL_CHOL_FWD_GATHER);
-    hipLaunchKernelGGL(k_fwd_gather, dim3(ntw, cb), blk, 0, s, f, tw0, ncols, r, U, W);
+    hipLaunchKernelGGL(k_fwd_gather, dim3(ntw, cb, GQ), blk, 0, s, f, tw0, ncols, r, U, W);
     prof::end(s, DMC_KERNEL_CHOL_FWD_GATHER);
     prof::begin(s, DMC_KERNEL_CHOL_FWD_SOLVE);
     hipLaunchKernelGGL(k_fwd_gemm, dim3(ntm, cb), blk, 0, s, f, tm0, ncols, W, Y, U);
@@ -250,8 +317,11 @@ void launch_chol_solve(hipStream_t s, const CholDev& f, int32_t ncols, const dou
   }
   for (int lv = f.nlevels - 1; lv >= 0; --lv) {
     const int tw0 = f.level_w_host[lv], ntw = f.level_w_host[lv + 1] - tw0;
+    const int ns = part ? bwd_split(ntw, cb) : 1;
     prof::begin(s, DMC_KERNEL_CHOL_BWD_SOLVE);
-    hipLaunchKernelGGL(k_bwd_gemm, dim3(ntw, cb), blk, 0, s, f, tw0, ncols, Y, X, z);
+    hipLaunchKernelGGL(k_bwd_gemm, dim3(ntw, cb, ns), blk, 0, s, f, tw0, ncols, Y, X, z, ns, part);
+    if (ns > 1)
+      hipLaunchKernelGGL(k_bwd_reduce, dim3(ntw, cb, 4), blk, 0, s, f, tw0, ntw, ncols, ns, part, X, z);
     prof::end(s, DMC_KERNEL_CHOL_BWD_SOLVE);
   }
 }

@@ -394,7 +394,7 @@ void launch_rhs(hipStream_t s, const MeshDev& m, const uint8_t* records, const S
 void launch_precond_apply(hipStream_t s, const MeshDev& m, int32_t ncols, const CgBuffers& cb) {
   const int nrb = (int)cg_part_rows(m.n);
   dim3 grid(nrb, (ncols + kBlock - 1) / kBlock);
-  launch_chol_solve(s, m.chol, ncols, cb.r, cb.z, cb.W, cb.Y, cb.X, cb.U);
+  launch_chol_solve(s, m.chol, ncols, cb.r, cb.z, cb.W, cb.Y, cb.X, cb.U, cb.S);
   hipLaunchKernelGGL(k_cg_dot, grid, dim3(kBlock), 0, s, m.n, ncols, cb.r, cb.z, cb.part);
 }
 

@@ -251,62 +251,48 @@ __device__ __forceinline__ bool chol_qr_packed(double (&v)[KR], double thresh) {
   return ok;
 }
 
-// Gram-Schmidt (each column orthogonalised twice against the previous ones) on
-// Q in place; a column with no component left is replaced by the identity
-// direction e_m with the largest part outside the span found so far.
-template <int TMAX, int KMAX>
-__device__ __forceinline__ void gram_schmidt(OiSmem<TMAX, KMAX>& s, int T, int k) {
-  for (int j = 0; j < k; ++j) {
-    const double n0 = sqrt(block_sum(threadIdx.x < T ? s.Q[threadIdx.x * s.LQ + j] *
-                                                           s.Q[threadIdx.x * s.LQ + j]
-                                                     : 0.0,
-                                     s.red));
-    for (int pass = 0; pass < 2; ++pass) {
-      for (int p = 0; p < j; ++p) {
-        const double d = block_sum(threadIdx.x < T ? s.Q[threadIdx.x * s.LQ + p] *
-                                                         s.Q[threadIdx.x * s.LQ + j]
-                                                   : 0.0,
-                                   s.red);
-        if (threadIdx.x < T) s.Q[threadIdx.x * s.LQ + j] -= d * s.Q[threadIdx.x * s.LQ + p];
-        __syncthreads();
-      }
+// Gram-Schmidt on the rows held in registers (lane t < T holds row t of the
+// block): each column orthogonalised twice against the previous ones, one
+// projection after the other (modified Gram-Schmidt); a column with no
+// component left (below
+// 1e-10 of its norm) is replaced by the identity direction e_m with the
+// largest part outside the span found so far (first such m), then
+// orthogonalised the same way.  Columns >= k are set to zero.
+template <int KR>
+__device__ __forceinline__ void cgs2_regs(double (&x)[KR], int T, int k) {
+  const int lane = threadIdx.x;
+  const bool row = lane < T;
+#pragma unroll
+  for (int j = 0; j < KR; ++j) {
+    if (j >= k) {
+      x[j] = 0.0;
+      continue;
     }
-    double nj = sqrt(block_sum(threadIdx.x < T ? s.Q[threadIdx.x * s.LQ + j] *
-                                                     s.Q[threadIdx.x * s.LQ + j]
-                                               : 0.0,
-                               s.red));
+    double v = row ? x[j] : 0.0;
+    const double n0 = sqrt(block_sum(v * v, nullptr));
+    auto project_out = [&]() {
+#pragma unroll
+      for (int pass = 0; pass < 2; ++pass)
+#pragma unroll
+        for (int l = 0; l < j; ++l) {
+          const double d = block_sum(row ? x[l] * v : 0.0, nullptr);
+          v = row ? v - d * x[l] : 0.0;
+        }
+    };
+    project_out();
+    double nj = sqrt(block_sum(v * v, nullptr));
     if (!(nj > 1e-10 * n0) || n0 == 0.0) {
-      // completion: e_m maximising 1 - sum_p Q[m][p]^2
-      double best = -1.0;
-      int bm = 0;
-      for (int m = 0; m < T; ++m) {
-        double out = 1.0;
-        for (int p = 0; p < j; ++p) out -= s.Q[m * s.LQ + p] * s.Q[m * s.LQ + p];
-        if (out > best) {
-          best = out;
-          bm = m;
-        }
-      }
-      __syncthreads();
-      if (threadIdx.x < T) s.Q[threadIdx.x * s.LQ + j] = threadIdx.x == bm ? 1.0 : 0.0;
-      __syncthreads();
-      for (int pass = 0; pass < 2; ++pass) {
-        for (int p = 0; p < j; ++p) {
-          const double d = block_sum(threadIdx.x < T ? s.Q[threadIdx.x * s.LQ + p] *
-                                                           s.Q[threadIdx.x * s.LQ + j]
-                                                     : 0.0,
-                                     s.red);
-          if (threadIdx.x < T) s.Q[threadIdx.x * s.LQ + j] -= d * s.Q[threadIdx.x * s.LQ + p];
-          __syncthreads();
-        }
-      }
-      nj = sqrt(block_sum(threadIdx.x < T ? s.Q[threadIdx.x * s.LQ + j] *
-                                                s.Q[threadIdx.x * s.LQ + j]
-                                          : 0.0,
-                          s.red));
+      double out = 1.0;
+#pragma unroll
+      for (int l = 0; l < j; ++l) out -= row ? x[l] * x[l] : 0.0;
+      const double best = block_max(row ? out : -1.0, nullptr);
+      const unsigned long long hit = __ballot(row && out == best);
+      const int bm = hit ? __ffsll(hit) - 1 : 0;
+      v = lane == bm ? 1.0 : 0.0;
+      project_out();
+      nj = sqrt(block_sum(v * v, nullptr));
     }
-    if (threadIdx.x < T) s.Q[threadIdx.x * s.LQ + j] /= nj;
-    __syncthreads();
+    x[j] = row ? v / nj : 0.0;
   }
 }
 
@@ -314,11 +300,14 @@ __device__ __forceinline__ void gram_schmidt(OiSmem<TMAX, KMAX>& s, int T, int k
 // Cholesky QR2 on the column-scaled block (columns of R Q differ in norm by
 // the eigenvalue spread; scaling by the Gram diagonal removes that without
 // changing the Q factor).  A pivot breakdown switches to shifted Cholesky QR3
-// (Fukaya et al.: shift 11 (T k + k (k + 1)) u ||X||_F^2), a second one, or an
-// exactly zero column, to Gram-Schmidt with completion.  Returns the number
-// of repairs (0: plain Cholesky QR2).
+// (Fukaya et al.: shift 11 (T k + k (k + 1)) u ||X||_F^2); `shifted` starts
+// with the shifted pass directly (blocks R Q whose columns are known to be
+// nearly dependent).  A breakdown after that, or an exactly zero column,
+// switches to Gram-Schmidt with completion.  Returns the number of repairs
+// (0: plain Cholesky QR2).
 template <int KR, int TMAX, int KMAX>
-__device__ __forceinline__ int orthonormalise(OiSmem<TMAX, KMAX>& s, const double* X, int T, int k) {
+__device__ __forceinline__ int orthonormalise(OiSmem<TMAX, KMAX>& s, const double* X, int T, int k,
+                                              bool shifted = false) {
   const int lane = threadIdx.x;
   constexpr double thresh = 1e-15;  // pivots relative to the unit diagonal
   constexpr bool packed = TMAX <= 32;
@@ -365,17 +354,7 @@ __device__ __forceinline__ int orthonormalise(OiSmem<TMAX, KMAX>& s, const doubl
     }
     __syncthreads();
   };
-  load(true, false);
-  if (zero_col) {
-    to_Q();
-    gram_schmidt(s, T, k);
-    return 1;
-  }
-  int repairs = 0, passes = 2;
-  if (!pass()) {
-    repairs = 1;
-    passes = 3;
-    load(true, false);
+  auto add_shift = [&]() {
     const double shift = 11.0 * (double)(T * k + k * (k + 1)) * 1.1102230246251565e-16 * (double)k;
 #pragma unroll
     for (int j = 0; j < KR; ++j) {
@@ -384,19 +363,45 @@ __device__ __forceinline__ int orthonormalise(OiSmem<TMAX, KMAX>& s, const doubl
       else
         g[j] += (lane == j && j < k) ? shift : 0.0;
     }
-    if (!pass()) {
+  };
+  load(true, false);
+  if (zero_col) {
+    cgs2_regs<KR>(x, T, k);
+    to_Q();
+    return 1;
+  }
+  int repairs = 0, passes = 2;
+  bool ok;
+  if (shifted) {
+    add_shift();
+    ok = pass();
+    repairs = 1;
+    passes = 3;
+  } else {
+    ok = pass();
+    if (!ok) {
+      repairs = 1;
+      passes = 3;
       load(true, false);
-      to_Q();
-      gram_schmidt(s, T, k);
-      return 2;
+      add_shift();
+      ok = pass();
     }
+  }
+  if (!ok) {
+    load(true, false);
+    cgs2_regs<KR>(x, T, k);
+    to_Q();
+    return 2;
   }
   for (int p = 1; p < passes; ++p) {
     to_Q();
     mm_XtZ<KR>(s, s.Q, s.Q);
     load(false, true);
     if (!pass()) {  // s.Q still holds the last block
-      gram_schmidt(s, T, k);
+#pragma unroll
+      for (int j = 0; j < KR; ++j) x[j] = lane < T ? s.Q[lane * s.LQ + j] : 0.0;
+      cgs2_regs<KR>(x, T, k);
+      to_Q();
       return repairs + 2;
     }
   }
@@ -785,7 +790,8 @@ __device__ __forceinline__ double dequant(uint16_t code, double lo, double hi, i
 // diag(mu) V^T; U is left in Y (not yet sign-fixed).
 template <int KR, int TMAX, int KMAX>
 __device__ __forceinline__ void oi_sweeps(OiSmem<TMAX, KMAX>& s, int T, int k, int max_sweeps, double tol,
-                                          double normR, bool bf16, int& sweeps, int& repairs, double& resid) {
+                                          double normR, bool bf16, bool q_orthonormal, int& sweeps,
+                                          int& repairs, double& resid) {
   // precision form: bfloat16 products until the stage tolerance (or one sweep
   // before the cap), then full-precision refinement sweeps (at least one)
   // until tol, or until a sweep no longer reduces the residual by a tenth
@@ -793,13 +799,16 @@ __device__ __forceinline__ void oi_sweeps(OiSmem<TMAX, KMAX>& s, int T, int k, i
   const double stage_tol = tol > DMC_BF16_STAGE_TOL ? tol : DMC_BF16_STAGE_TOL;
   bool refining = false;
   double prev = 0.0;
-  repairs += orthonormalise<KR>(s, s.Q, T, k) ? 1 : 0;
+  // a start that is already orthonormal (the previous window's U) is kept
+  if (!q_orthonormal) repairs += orthonormalise<KR>(s, s.Q, T, k) ? 1 : 0;
   if (bf16)
     mm_RQ_bf16<KR>(s);
   else
     mm_RQ<KR>(s);
   for (int sw = 1; sw <= max_sweeps; ++sw) {
-    repairs += orthonormalise<KR>(s, s.Y, T, k) ? 1 : 0;
+    // from the previous window's subspace, R Q spreads its columns by the
+    // eigenvalue spread (nearly dependent after scaling): start shifted
+    repairs += orthonormalise<KR>(s, s.Y, T, k, q_orthonormal) ? 1 : 0;
     if (bf16)
       mm_RQ_bf16<KR>(s);
     else
@@ -921,8 +930,8 @@ __device__ __forceinline__ void oi_run(OiSmem<TMAX, KMAX>& s, const OiArgs& a, i
           __syncthreads();
         }
       }
-      oi_sweeps<KR>(s, T, k, a.max_sweeps, a.tol, normR, a.precision == DMC_BF16, sweeps, repairs,
-                    resid);
+      oi_sweeps<KR>(s, T, k, a.max_sweeps, a.tol, normR, a.precision == DMC_BF16, chain && w > 0,
+                    sweeps, repairs, resid);
       sign_fix(s, T, k);
     }
     // ---- outputs: U, dictionary codes, dequantised dictionary ----
