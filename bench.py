@@ -40,7 +40,7 @@ FIRST_START_SEED = 909     # seeded Gaussian start block of window 0
 # source file of each kernel family (the byte counters of a family are valid
 # only while its source is unchanged)
 FAMILY_SOURCE = {
-    "delta": "kernels_encode.hip", "autocorr": "kernels_encode.hip", "oi": "kernels_oi.hip",
+    "delta": "kernels_encode.hip", "autocorr": "kernels_encode.hip", "oi": "oi_device.h",
     "project": "kernels_encode.hip", "quantise": "kernels_encode.hip",
     "anchors": "kernels_encode.hip", "back_project": "kernels_decode.hip",
     "rhs": "kernels_decode.hip", "cg_spmm": "kernels_decode.hip",

@@ -119,6 +119,13 @@ void launch_oi(hipStream_t s, const OiArgs& a);
 // of the jobs
 void launch_oi_batch(hipStream_t s, int tmax, int kr, int precision, const OiArgs* args,
                      const int4* jobs, int njobs);
+// the launchers of one (TMAX, KR) class (TMAX 32 or 64, KR 16 or 32), each
+// instantiated in a unit of its own
+template <int TMAX, int KR>
+void launch_oi_t(hipStream_t st, const OiArgs& a);
+template <int TMAX, int KR>
+void launch_oi_batch_t(hipStream_t st, int precision, const OiArgs* args, const int4* jobs,
+                       int njobs);
 
 // Learned start (row-wise perceptron on the sketch R Omega).
 int mlp_param_count(int k);
