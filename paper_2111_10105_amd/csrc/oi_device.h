@@ -44,19 +44,6 @@ struct OiSmem {
   int ok;
 };
 
-// sums / maxima over the wavefront (the whole workgroup), result in every lane
-__device__ __forceinline__ double block_sum(double v, double* /*red*/) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-  return v;
-}
-
-__device__ __forceinline__ double block_max(double v, double* /*red*/) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
-  return v;
-}
-
 // DPP lane moves of a double (both halves): DPP_ROW_MIRROR (0x140) gives lane t
 // of each 16-lane row the value of lane 15 - t; DPP_WAVE_ROR1 (0x13C) gives
 // lane t the value of lane t - 1 (mod 64).
@@ -82,6 +69,38 @@ __device__ __forceinline__ double shfl_f64(double v, int src) {
   const int lo = __shfl((int)(b & 0xffffffffLL), src);
   const int hi = __shfl((int)(b >> 32), src);
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Value of v held by lane (l ^ 16) for lane l (swizzle within 32 lanes).
+__device__ __forceinline__ double swap16_f64(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_ds_swizzle((int)(b & 0xffffffffLL), 0x401F);
+  const int hi = __builtin_amdgcn_ds_swizzle((int)(b >> 32), 0x401F);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sums / maxima over the wavefront (the whole workgroup), the same value in
+// every lane: within each 16-lane row by DPP (quad_perm [1,0,3,2] and
+// [2,3,0,1], row_half_mirror, row_mirror: each step pairs a lane with one
+// holding the other half of its group), the two rows of each 32-lane half by
+// a swizzle, the halves by lane reads.  Each step adds a value and its
+// partner's in the same order on both lanes, so every lane gets the same bits.
+template <typename Op>
+__device__ __forceinline__ double wave_reduce(double v, Op op) {
+  v = op(v, dpp_f64<0xB1>(v));
+  v = op(v, dpp_f64<0x4E>(v));
+  v = op(v, dpp_f64<0x141>(v));
+  v = op(v, dpp_f64<kDppRowMirror>(v));
+  v = op(v, swap16_f64(v));
+  return op(readlane_f64(v, 0), readlane_f64(v, 32));
+}
+
+__device__ __forceinline__ double block_sum(double v, double* /*red*/) {
+  return wave_reduce(v, [](double a, double b) { return a + b; });
+}
+
+__device__ __forceinline__ double block_max(double v, double* /*red*/) {
+  return wave_reduce(v, [](double a, double b) { return fmax(a, b); });
 }
 
 // Products on the FP64 matrix cores (v_mfma_f64_16x16x4f64).  Operand
@@ -254,49 +273,56 @@ __device__ __forceinline__ bool chol_qr_packed(double (&v)[KR], double thresh) {
   return ok;
 }
 
-// Gram-Schmidt on the rows held in registers (lane t < T holds row t of the
-// block): each column orthogonalised twice against the previous ones, one
-// projection after the other (modified Gram-Schmidt); a column with no
-// component left (below
-// 1e-10 of its norm) is replaced by the identity direction e_m with the
-// largest part outside the span found so far (first such m), then
-// orthogonalised the same way.  Columns >= k are set to zero.
-template <int KR>
-__device__ __forceinline__ void cgs2_regs(double (&x)[KR], int T, int k) {
+// Gram-Schmidt in place on the block in s.Q (lane t < T works on row t):
+// each column orthogonalised twice against the previous ones, one projection
+// after the other (modified Gram-Schmidt); a column with no component left
+// (below 1e-10 of its norm) is replaced by the identity direction e_m with
+// the largest part outside the span found so far (first such m), then
+// orthogonalised the same way.  Columns k..KMAX-1 are set to zero.  The
+// fallback of `orthonormalise` for exactly rank-deficient blocks: it runs
+// rarely, so its loops stay rolled (short code).
+template <int TMAX, int KMAX>
+__device__ __forceinline__ void mgs_lds(OiSmem<TMAX, KMAX>& s, int T, int k) {
   const int lane = threadIdx.x;
   const bool row = lane < T;
-#pragma unroll
-  for (int j = 0; j < KR; ++j) {
-    if (j >= k) {
-      x[j] = 0.0;
-      continue;
-    }
-    double v = row ? x[j] : 0.0;
+  double* q = s.Q + (row ? lane : 0) * s.LQ;
+  __syncthreads();
+#pragma unroll 1
+  for (int j = 0; j < k; ++j) {
+    double v = row ? q[j] : 0.0;
     const double n0 = sqrt(block_sum(v * v, nullptr));
-    auto project_out = [&]() {
-#pragma unroll
-      for (int pass = 0; pass < 2; ++pass)
-#pragma unroll
+    double nj = 0.0;
+#pragma unroll 1
+    for (int attempt = 0; attempt < 2; ++attempt) {
+      if (attempt == 1) {
+        // completion: the identity direction with the largest part left
+        double out = 1.0;
+#pragma unroll 1
+        for (int l = 0; l < j; ++l) out -= row ? q[l] * q[l] : 0.0;
+        const double best = block_max(row ? out : -1.0, nullptr);
+        const unsigned long long hit = __ballot(row && out == best);
+        const int bm = hit ? __ffsll(hit) - 1 : 0;
+        v = lane == bm ? 1.0 : 0.0;
+      }
+#pragma unroll 1
+      for (int pass = 0; pass < 2; ++pass) {
+        double ql = row ? q[0] : 0.0;
+#pragma unroll 1
         for (int l = 0; l < j; ++l) {
-          const double d = block_sum(row ? x[l] * v : 0.0, nullptr);
-          v = row ? v - d * x[l] : 0.0;
+          const double qn = (row && l + 1 < j) ? q[l + 1] : 0.0;  // next column, in flight
+          const double d = block_sum(row ? ql * v : 0.0, nullptr);
+          v = row ? v - d * ql : 0.0;
+          ql = qn;
         }
-    };
-    project_out();
-    double nj = sqrt(block_sum(v * v, nullptr));
-    if (!(nj > 1e-10 * n0) || n0 == 0.0) {
-      double out = 1.0;
-#pragma unroll
-      for (int l = 0; l < j; ++l) out -= row ? x[l] * x[l] : 0.0;
-      const double best = block_max(row ? out : -1.0, nullptr);
-      const unsigned long long hit = __ballot(row && out == best);
-      const int bm = hit ? __ffsll(hit) - 1 : 0;
-      v = lane == bm ? 1.0 : 0.0;
-      project_out();
+      }
       nj = sqrt(block_sum(v * v, nullptr));
+      if (attempt == 0 && (nj > 1e-10 * n0) && n0 != 0.0) break;
     }
-    x[j] = row ? v / nj : 0.0;
+    if (row) q[j] = v / nj;
   }
+  if (row)
+    for (int j = k; j < KMAX; ++j) q[j] = 0.0;
+  __syncthreads();
 }
 
 // Q = orthonormal basis of span(X) (X = Y or Q, T x k), left in s.Q.
@@ -367,44 +393,40 @@ __device__ __forceinline__ int orthonormalise(OiSmem<TMAX, KMAX>& s, const doubl
         g[j] += (lane == j && j < k) ? shift : 0.0;
     }
   };
-  load(true, false);
   if (zero_col) {
-    cgs2_regs<KR>(x, T, k);
+    load(true, false);
     to_Q();
+    mgs_lds(s, T, k);
     return 1;
   }
-  int repairs = 0, passes = 2;
-  bool ok;
-  if (shifted) {
-    add_shift();
-    ok = pass();
-    repairs = 1;
-    passes = 3;
-  } else {
-    ok = pass();
-    if (!ok) {
-      repairs = 1;
-      passes = 3;
-      load(true, false);
-      add_shift();
-      ok = pass();
-    }
-  }
-  if (!ok) {
-    load(true, false);
-    cgs2_regs<KR>(x, T, k);
-    to_Q();
-    return 2;
-  }
-  for (int p = 1; p < passes; ++p) {
-    to_Q();
-    mm_XtZ<KR>(s, s.Q, s.Q);
-    load(false, true);
-    if (!pass()) {  // s.Q still holds the last block
-#pragma unroll
-      for (int j = 0; j < KR; ++j) x[j] = lane < T ? s.Q[lane * s.LQ + j] : 0.0;
-      cgs2_regs<KR>(x, T, k);
+  // pass 0 factors the scaled X (shifted: with the shift, and three passes in
+  // all); a breakdown of an unshifted pass 0 restarts it shifted; passes >= 1
+  // factor the Gram matrix of the previous pass's Q
+  int repairs = shifted ? 1 : 0, passes = shifted ? 3 : 2;
+  bool shift = shifted;
+#pragma unroll 1
+  for (int p = 0; p < passes; ++p) {
+    if (p > 0) {
       to_Q();
+      mm_XtZ<KR>(s, s.Q, s.Q);
+    }
+    load(p == 0, p > 0);
+    if (p == 0 && shift) add_shift();
+    if (!pass()) {
+      if (p == 0 && !shift) {  // restart shifted
+        shift = true;
+        repairs = 1;
+        passes = 3;
+        p = -1;
+        continue;
+      }
+      if (p == 0) {  // the scaled X to s.Q for Gram-Schmidt
+        load(true, false);
+        to_Q();
+        mgs_lds(s, T, k);
+        return 2;
+      }
+      mgs_lds(s, T, k);  // s.Q still holds the last block
       return repairs + 2;
     }
   }
@@ -673,14 +695,6 @@ __device__ __forceinline__ double xor16(double v) {
   else return xor16<15>(xor16<(R ^ 15)>(v));
 }
 
-// Value of v held by lane (l ^ 16) for lane l (swizzle within 32 lanes).
-__device__ __forceinline__ double swap16_f64(double v) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_ds_swizzle((int)(b & 0xffffffffLL), 0x401F);
-  const int hi = __builtin_amdgcn_ds_swizzle((int)(b >> 32), 0x401F);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
 // One round of `jacobi_xor16`: every pair (t, t ^ R) is rotated together.
 // Registers hold rows XOR-permuted (b[j] = row entry at column t ^ j), so the
 // diagonal is b[0] and the pair's off-diagonal entry is b[R] on every lane.
@@ -858,17 +872,22 @@ __device__ __forceinline__ void jacobi_xor16(OiSmem<TMAX, KMAX>& s, int m) {
 }
 
 // Eigenvectors of the m x m symmetric matrix in A: register Jacobi up to
-// m = 32, the LDS version above.  FAST16 (set in the kernels for k <= 16,
-// where the Ritz matrix always fits) selects the in-place XOR-schedule
-// version for m <= 16; it is instantiated only there, as it is long code.
+// m = 32, the LDS version above.  FAST16 (set for the Ritz step of the
+// kernels for k <= 16, where the Ritz matrix always fits) selects the in-place
+// XOR-schedule version; it is instantiated only there, as it is long code.
 template <bool FAST16 = false, int TMAX, int KMAX>
 __device__ __forceinline__ void eigen_sym(OiSmem<TMAX, KMAX>& s, int m) {
-  if (FAST16 && m <= 16)
-    jacobi_xor16(s, m);
-  else if (m <= 32)
-    jacobi_regs<32>(s, m);
-  else
-    jacobi(s, m);
+  if constexpr (FAST16) {
+    if (m <= 16)
+      jacobi_xor16(s, m);
+    else
+      jacobi(s, m);  // not reached from the k <= 16 kernels; short code
+  } else {
+    if (m <= 32)
+      jacobi_regs<32>(s, m);
+    else
+      jacobi(s, m);
+  }
 }
 
 // Sign rule on the T x k columns held in Y: the entry of largest magnitude
@@ -1008,20 +1027,20 @@ __device__ __forceinline__ void oi_sweeps(OiSmem<TMAX, KMAX>& s, int T, int k, i
   const double stage_tol = tol > DMC_BF16_STAGE_TOL ? tol : DMC_BF16_STAGE_TOL;
   bool refining = false;
   double prev = 0.0;
-  // a start that is already orthonormal (the previous window's U) is kept
-  if (!q_orthonormal) repairs += orthonormalise<KR>(s, s.Q, T, k) ? 1 : 0;
-  if (bf16)
-    mm_RQ_bf16<KR>(s);
-  else
-    mm_RQ<KR>(s);
-  for (int sw = 1; sw <= max_sweeps; ++sw) {
+  // sweep 0 only orthonormalises the start (a start that is already
+  // orthonormal, the previous window's U, is kept) and forms R Q; one code
+  // path serves it and the sweeps, so the long orthonormalisation is
+  // instantiated once
+  for (int sw = 0; sw <= max_sweeps; ++sw) {
     // from the previous window's subspace, R Q spreads its columns by the
     // eigenvalue spread (nearly dependent after scaling): start shifted
-    repairs += orthonormalise<KR>(s, s.Y, T, k, q_orthonormal) ? 1 : 0;
+    if (sw > 0 || !q_orthonormal)
+      repairs += orthonormalise<KR>(s, sw == 0 ? s.Q : s.Y, T, k, sw > 0 && q_orthonormal) ? 1 : 0;
     if (bf16)
       mm_RQ_bf16<KR>(s);
     else
       mm_RQ<KR>(s);
+    if (sw == 0) continue;
     sweeps = sw;
     resid = residual_and_H<KR>(s, k, normR);
     if (bf16) {
