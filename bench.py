@@ -341,18 +341,18 @@ def main():
     launches, kernel_ms = dmc.profile_stop()
 
     # encode-only and decode-only split (outside the timed region)
-    torch.cuda.synchronize()
-    te = time.perf_counter()
-    for _ in range(3):
-        dmc.compress_sequence(ctx, mesh, frames, T, p, q_start=q0, codes=codes, decode=False,
-                              stats=False)
-    torch.cuda.synchronize()
-    enc_ms = (time.perf_counter() - te) / 3 * 1e3
-    td = time.perf_counter()
-    for _ in range(3):
-        dmc.decode_sequence(ctx, mesh, codes, F, T, p, out=out)
-    torch.cuda.synchronize()
-    dec_ms = (time.perf_counter() - td) / 3 * 1e3
+    def split_time(fn, reps=10):
+        fn()  # warm
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / reps * 1e3
+
+    enc_ms = split_time(lambda: dmc.compress_sequence(ctx, mesh, frames, T, p, q_start=q0,
+                                                      codes=codes, decode=False, stats=False))
+    dec_ms = split_time(lambda: dmc.decode_sequence(ctx, mesh, codes, F, T, p, out=out))
 
     step()
     torch.cuda.synchronize()

@@ -42,12 +42,16 @@ __device__ inline void window_of(const SeqLayout& sl, const uint8_t* records, in
 }
 
 // B0[i][3(t0+t)+c] = sum_r U~_c[t][r] Y^_c[r][i]  (Eq. 11/12 right-hand side)
+// Thread (j, g) owns column j = 3 t + c of the window: its dictionary row
+// U~_c[t][.] stays in registers while it runs over the block's vertices
+// g, g + G, ... (G = 256 / 3T groups), reading each vertex's coefficients from
+// LDS (one address per coordinate across the wave); consecutive lanes write
+// consecutive columns of a vertex row.
 template <typename Real>
 __global__ void __launch_bounds__(kBlock)
 k_back_project(const uint8_t* __restrict__ records, SeqLayout sl, int n, int ncols,
                double* __restrict__ B0) {
-  // padded strides (k + 1, 33) keep lanes on different LDS banks
-  __shared__ double Ut[3 * 64 * 33];
+  // padded stride 33 keeps the coordinates of a vertex on different LDS banks
   __shared__ double Yh[BP_V * 3 * 33];
   const int w = blockIdx.y;
   const uint8_t* rec;
@@ -56,16 +60,6 @@ k_back_project(const uint8_t* __restrict__ records, SeqLayout sl, int n, int nco
   window_of(sl, records, w, rec, T, k, t0, lay);
   const int i0 = blockIdx.x * BP_V;
   const int nv = min(BP_V, n - i0);
-  // dictionary
-  const int db = lay->dict_bits;
-  const int ku = k + 1;
-  for (int e = threadIdx.x; e < 3 * T * k; e += kBlock) {
-    const int row = e / k, r = e % k;  // row = c * T + t
-    if (db > 0)
-      Ut[row * ku + r] = dequant(((const uint16_t*)(rec + lay->off_dict))[e], -1.0, 1.0, db);
-    else
-      Ut[row * ku + r] = (double)((const Real*)(rec + lay->off_dict))[e];
-  }
   // coefficients of this block's vertices: Yh[v][c][r]
   const int cb = lay->coef_bits;
   for (int e = threadIdx.x; e < 3 * k * nv; e += kBlock) {
@@ -82,14 +76,27 @@ k_back_project(const uint8_t* __restrict__ records, SeqLayout sl, int n, int nco
     Yh[(v * 3 + c) * 33 + r] = y;
   }
   __syncthreads();
-  const int wcols = 3 * T;
-  for (int e = threadIdx.x; e < nv * wcols; e += kBlock) {
-    const int v = e / wcols, j = e % wcols;
-    const int t = j / 3, c = j % 3;
-    const double* u = Ut + (c * T + t) * ku;
+  const int wcols = 3 * T;  // <= 192
+  const int groups = kBlock / wcols;
+  const int j = threadIdx.x % wcols, g = threadIdx.x / wcols;
+  if (g >= groups) return;
+  const int t = j / 3, c = j % 3;
+  // dictionary row (k <= 32)
+  const int db = lay->dict_bits;
+  double u[32];
+#pragma unroll
+  for (int r = 0; r < 32; ++r) {
+    const int e = (c * T + t) * k + r;
+    u[r] = r >= k ? 0.0
+           : db > 0 ? dequant(((const uint16_t*)(rec + lay->off_dict))[e], -1.0, 1.0, db)
+                    : (double)((const Real*)(rec + lay->off_dict))[e];
+  }
+  for (int v = g; v < nv; v += groups) {
     const double* y = Yh + (v * 3 + c) * 33;
     double s = 0.0;
-    for (int r = 0; r < k; ++r) s = fma(u[r], y[r], s);
+#pragma unroll
+    for (int r = 0; r < 32; ++r)
+      if (r < k) s = fma(u[r], y[r], s);
     B0[(size_t)(i0 + v) * ncols + 3 * t0 + j] = s;
   }
 }
@@ -132,14 +139,28 @@ k_rhs(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
   const int j = blockIdx.y * kBlock + threadIdx.x;
   if (j >= ncols) return;
   const int r0 = blockIdx.x * CG_RB, r1 = min(n, r0 + CG_RB);
+  const double* Bj = B0 + j;
   for (int i = r0; i < r1; ++i) {
-    const double ui = B0[(size_t)i * ncols + j];
-    double s = 0.0;
-    for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) {
-      const int nb = col[e];
-      const double v = B0[(size_t)nb * ncols + j];
-      s += uniform ? v * w[nb] : v;
+    const double ui = Bj[(size_t)i * ncols];
+    const int e1 = rowptr[i + 1];
+    int e = rowptr[i];
+    // four independent partial sums keep several row loads in flight
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    for (; e + 4 <= e1; e += 4) {
+      const int n0 = col[e], n1 = col[e + 1], n2 = col[e + 2], n3 = col[e + 3];
+      const double v0 = Bj[(size_t)n0 * ncols], v1 = Bj[(size_t)n1 * ncols];
+      const double v2 = Bj[(size_t)n2 * ncols], v3 = Bj[(size_t)n3 * ncols];
+      s0 += uniform ? v0 * w[n0] : v0;
+      s1 += uniform ? v1 * w[n1] : v1;
+      s2 += uniform ? v2 * w[n2] : v2;
+      s3 += uniform ? v3 * w[n3] : v3;
     }
+    for (; e < e1; ++e) {
+      const int nb = col[e];
+      const double v = Bj[(size_t)nb * ncols];
+      s0 += uniform ? v * w[nb] : v;
+    }
+    const double s = (s0 + s1) + (s2 + s3);
     double out = uniform ? ui - s : w[i] * ui - s;
     const int sl = slot[i];
     if (sl >= 0) out += Ah[(size_t)sl * ncols + j];
@@ -215,12 +236,23 @@ k_cg_spmm(const int32_t* __restrict__ mrow, const int32_t* __restrict__ mcol,
   const int j = blockIdx.y * kBlock + threadIdx.x;
   if (j >= ncols) return;
   const int r0 = blockIdx.x * CG_RB, r1 = min(n, r0 + CG_RB);
+  const double* pj = p + j;
   double pq = 0.0;
   for (int i = r0; i < r1; ++i) {
-    double acc = 0.0;
-    for (int e = mrow[i]; e < mrow[i + 1]; ++e) acc = fma(mval[e], p[(size_t)mcol[e] * ncols + j], acc);
+    const int e1 = mrow[i + 1];
+    int e = mrow[i];
+    // four independent partial sums keep several row loads in flight
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    for (; e + 4 <= e1; e += 4) {
+      a0 = fma(mval[e], pj[(size_t)mcol[e] * ncols], a0);
+      a1 = fma(mval[e + 1], pj[(size_t)mcol[e + 1] * ncols], a1);
+      a2 = fma(mval[e + 2], pj[(size_t)mcol[e + 2] * ncols], a2);
+      a3 = fma(mval[e + 3], pj[(size_t)mcol[e + 3] * ncols], a3);
+    }
+    for (; e < e1; ++e) a0 = fma(mval[e], pj[(size_t)mcol[e] * ncols], a0);
+    const double acc = (a0 + a1) + (a2 + a3);
     q[(size_t)i * ncols + j] = acc;
-    pq = fma(p[(size_t)i * ncols + j], acc, pq);
+    pq = fma(pj[(size_t)i * ncols], acc, pq);
   }
   part[(size_t)blockIdx.x * ncols + j] = pq;
 }

@@ -2,6 +2,7 @@
 // projection (Eq. 9) with per-row ranges and uniform quantisation (Eq. 10),
 // anchor values (Eq. 12).
 #include "dmc_internal.h"
+#include "wave_ops.h"
 
 namespace dmc {
 namespace {
@@ -20,6 +21,8 @@ typedef float f16v __attribute__((ext_vector_type(16)));
 // absolute error of the size of one ulp of the coordinates in it.  The kernel
 // is bound by memory traffic, so this costs nothing measurable.
 // ---------------------------------------------------------------------------
+constexpr int DMAX = 8;  // ring members held in registers by k_delta
+
 template <typename Real>
 __global__ void __launch_bounds__(kBlock)
 k_delta(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
@@ -29,16 +32,29 @@ k_delta(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
   if (g >= 3 * n) return;
   const int i = g / 3, c = g - 3 * i;
   const int e0 = rowptr[i], e1 = rowptr[i + 1];
+  const int deg = e1 - e0;
   const double wi = w[i];
   const int t0 = blockIdx.y * fpb;
   const int t1 = min(F, t0 + fpb);
   const size_t fs = (size_t)3 * n;
+  // the first DMAX ring members' offsets stay in registers, so the loads of
+  // a frame are all issued at once (a longer ring reads the rest in a loop)
+  int off[DMAX];
+#pragma unroll
+  for (int d = 0; d < DMAX; ++d) off[d] = d < deg ? 3 * col[e0 + d] + c : g;
+#pragma unroll 2
   for (int t = t0; t < t1; ++t) {
     const Real* fr = in + (size_t)t * fs;
+    double v[DMAX];
+#pragma unroll
+    for (int d = 0; d < DMAX; ++d) v[d] = (double)fr[off[d]];
     double sum = 0.0;
-    for (int e = e0; e < e1; ++e) sum += (double)fr[3 * col[e] + c];
-    const double v = (double)fr[g];
-    out[(size_t)t * fs + g] = (Real)(uniform ? v - wi * sum : wi * v - sum);
+#pragma unroll
+    for (int d = 0; d < DMAX; ++d)
+      if (d < deg) sum += v[d];
+    for (int e = e0 + DMAX; e < e1; ++e) sum += (double)fr[3 * col[e] + c];
+    const double x = (double)fr[g];
+    out[(size_t)t * fs + g] = (Real)(uniform ? x - wi * sum : wi * x - sum);
   }
 }
 
@@ -282,6 +298,8 @@ k_project(const Real* __restrict__ delta, int n, int T, int k, const double* __r
   for (int r = 0; r < KMAX; ++r) acc[r] = 0;
   const Real* dw = delta + (size_t)w * T * 3 * n;
   const Real* uc = Ut + c * T * k;
+  // eight frames' loads in flight at a time
+#pragma unroll 8
   for (int t = 0; t < T; ++t) {
     const Real d = valid ? dw[(size_t)t * 3 * n + 3 * (size_t)i + c] : (Real)0;
 #pragma unroll
@@ -292,11 +310,8 @@ k_project(const Real* __restrict__ delta, int n, int T, int k, const double* __r
   const int nblk = gridDim.x;
   for (int r = 0; r < k; ++r) {
     if (valid) yw[(size_t)r * n + i] = acc[r];
-    double lo = valid ? (double)acc[r] : 1e300, hi = valid ? (double)acc[r] : -1e300;
-    for (int off = 32; off > 0; off >>= 1) {
-      lo = fmin(lo, __shfl_xor(lo, off));
-      hi = fmax(hi, __shfl_xor(hi, off));
-    }
+    const double lo = wave_min(valid ? (double)acc[r] : 1e300);
+    const double hi = wave_max(valid ? (double)acc[r] : -1e300);
     if (lane == 0) {
       double* o = mm + ((((size_t)w * 3 + c) * k + r) * nblk + blk) * 2;
       o[0] = lo;
