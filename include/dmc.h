@@ -151,6 +151,19 @@ int32_t dmc_mesh_normal_nnz(dmc_mesh mesh);   /* nonzeros of L^T L + I_N^T I_N *
  * each), [7] update rows (entries of the factor left of a diagonal block,
  * counted by row of the supernode that produces them) */
 void dmc_mesh_factor_info(dmc_mesh mesh, double info[8]);
+/* Whether the mesh holds its anchor response G = (L^T L + I_N^T I_N)^{-1}
+ * I_N^T (n x n_c, float64 on the device), built by dmc_mesh_create when it
+ * takes at most 2 GiB: the right-hand side of Eq. (12) is linear in the
+ * decoded delta coordinates and anchor values, so with G the decoder solves
+ * the 3k columns L^T Y^^T of each window instead of its 3T frames' columns and
+ * forms X = Z U~^T + G A^ (same solution up to rounding).  The decoder's
+ * convergence test then bounds the relative residual of every frame's full
+ * system of Eq. (12) by cg_tol, counting G's own residual.  Returns 1 if built
+ * and writes, where the pointers are not NULL, the conjugate-gradient
+ * iterations of its solve and the largest relative residual of its columns;
+ * 0 if not built (the decoder then solves 3T columns per window) or for a
+ * NULL mesh. */
+int32_t dmc_mesh_anchor_response(dmc_mesh mesh, int32_t* cg_iters, double* resid);
 
 /* Host-only check of the ordering and factorisation (no device needed):
  * builds L^T L + I_N^T I_N and its supernodal Cholesky factor exactly as

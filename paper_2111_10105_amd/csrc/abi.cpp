@@ -35,6 +35,7 @@ struct dmc_mesh_s {
   std::vector<void*> allocations;
   std::vector<int32_t> level_w, level_m;  // host copies of the factor's level -> task ranges
   double factor_info[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int32_t g_iters = 0;  // CG iterations of the anchor response (0: not built)
 };
 
 namespace {
@@ -235,10 +236,14 @@ dmc_status check_learned(dmc_ctx ctx, const dmc_params& p, int32_t T) {
 
 // Decoder buffers for ncols right-hand sides, carved from one region.
 struct DecodeLayout {
-  size_t o_x, o_r, o_p, o_q, o_part, o_small, o_z, o_W, o_Y, o_X, o_U, o_S, total;
+  size_t o_x, o_r, o_p, o_q, o_part, o_small, o_z, o_W, o_Y, o_X, o_U, o_S, o_Ah, o_gram, total;
 };
 
-DecodeLayout decode_layout(const dmc::MeshDev& m, int32_t ncols, bool chol) {
+// ah_values, gram_values: doubles of the dense anchor values [nc][3F] and of
+// the partial Gram matrices of the reduced decode (0 for the full decode,
+// whose anchor values follow b)
+DecodeLayout decode_layout(const dmc::MeshDev& m, int32_t ncols, bool chol,
+                           size_t ah_values = 0, size_t gram_values = 0) {
   const size_t vec = (size_t)m.n * ncols * 8;
   const size_t nrb = dmc::cg_part_rows(m.n);
   Carve cv;
@@ -257,7 +262,30 @@ DecodeLayout decode_layout(const dmc::MeshDev& m, int32_t ncols, bool chol) {
     d.o_U = cv.add((size_t)m.chol.nslots * ncols * 8);
     d.o_S = cv.add(dmc::chol_split_bytes(m.chol, ncols));
   }
+  d.o_Ah = cv.add(ah_values * 8);
+  d.o_gram = cv.add(gram_values * 8);
   d.total = cv.total();
+  return d;
+}
+
+// How a sequence is decoded: the temporal-subspace form (solve the 3k columns
+// L^T Y^^T of each window, then X = Z U~^T + G A^) whenever the mesh holds
+// its anchor response and that is fewer columns than the 3T of the direct form.
+struct DecodePlan {
+  bool reduced = false;
+  int32_t F = 0, ncols = 0;  // frames; columns of the solve
+  DecodeLayout lay{};
+};
+
+DecodePlan decode_plan(const dmc::MeshDev& m, const dmc::SeqLayout& sl, const dmc_params& p) {
+  DecodePlan d;
+  d.F = sl.nw_full * sl.T + sl.T_tail;
+  const int32_t nz = dmc::reduced_cols(sl);
+  d.reduced = m.G != nullptr && nz < 3 * d.F;
+  d.ncols = d.reduced ? nz : 3 * d.F;
+  d.lay = decode_layout(m, d.ncols, p.precond == DMC_PRECOND_CHOLESKY,
+                        d.reduced ? (size_t)m.nc * 3 * d.F : 0,
+                        d.reduced ? dmc::group_gram_doubles(m.n, sl) : 0);
   return d;
 }
 
@@ -288,20 +316,80 @@ dmc::CgBuffers decode_buffers(uint8_t* ws, const DecodeLayout& d, int32_t ncols,
 // Decode with a fixed number of conjugate-gradient iterations and no host
 // synchronisation (capturable); summary[0..1] receives the largest relative
 // residual and whether every column converged.
-void decode_enqueue_fixed(hipStream_t s, const dmc::MeshDev& m, const uint8_t* records,
-                          const dmc::SeqLayout& sl, const dmc_params& p, void* frames_out,
-                          const dmc::CgBuffers& cb, int iters, double* summary) {
-  const int32_t F = sl.nw_full * sl.T + sl.T_tail;
-  const int32_t ncols = 3 * F;
-  dmc::launch_back_project(s, m, records, sl, nullptr, cb.q);
-  dmc::launch_rhs(s, m, records, sl, cb.q, cb.r);
-  dmc::launch_cg_init(s, m, ncols, cb.r, cb, p.precond);
-  for (int it = 1; it <= iters; ++it) {
-    dmc::launch_cg_step_a(s, m, ncols, cb, p.precond, p.cg_tol);
-    if (it < iters) dmc::launch_cg_step_b(s, m, ncols, cb, p.precond);
+void decode_enqueue_setup(hipStream_t s, const dmc::MeshDev& m, const uint8_t* records,
+                          const dmc::SeqLayout& sl, const dmc_params& p, const DecodePlan& d,
+                          const dmc::CgBuffers& cb, uint8_t* ws) {
+  double* Ah = (double*)(ws + d.lay.o_Ah);
+  if (d.reduced) {
+    dmc::launch_coef_rows(s, m, records, sl, cb.q);
+    dmc::launch_rhs_reduced(s, m, d.ncols, cb.q, cb.r);
+    dmc::launch_anchor_values(s, m, records, sl, Ah);
+  } else {
+    dmc::launch_back_project(s, m, records, sl, nullptr, cb.q);
+    dmc::launch_rhs(s, m, records, sl, cb.q, cb.r);
   }
-  dmc::launch_cg_summary(s, cb, ncols, summary);
-  dmc::launch_to_frames(s, cb.x, m.n, F, p.precision, frames_out);
+  dmc::launch_cg_init(s, m, d.ncols, cb.r, cb, p.precond);
+  // the test on the reduced columns bounds every frame's full-system residual
+  // (r still holds b here)
+  if (d.reduced)
+    dmc::launch_group_ref(s, m, records, sl, cb.r, Ah, p.cg_tol, (double*)(ws + d.lay.o_gram),
+                          cb.bnorm2);
+}
+
+void decode_enqueue_finish(hipStream_t s, const dmc::MeshDev& m, const uint8_t* records,
+                           const dmc::SeqLayout& sl, const dmc_params& p, const DecodePlan& d,
+                           const dmc::CgBuffers& cb, const double* Ah, void* frames_out) {
+  if (d.reduced)
+    dmc::launch_compose(s, m, records, sl, cb.x, Ah, p.precision, frames_out);
+  else
+    dmc::launch_to_frames(s, cb.x, m.n, d.F, p.precision, frames_out);
+}
+
+void decode_enqueue_fixed(hipStream_t s, const dmc::MeshDev& m, const uint8_t* records,
+                          const dmc::SeqLayout& sl, const dmc_params& p, const DecodePlan& d,
+                          uint8_t* ws, void* frames_out, int iters, double* summary) {
+  const bool chol = p.precond == DMC_PRECOND_CHOLESKY;
+  const dmc::CgBuffers cb = decode_buffers(ws, d.lay, d.ncols, chol);
+  double* Ah = (double*)(ws + d.lay.o_Ah);
+  decode_enqueue_setup(s, m, records, sl, p, d, cb, ws);
+  for (int it = 1; it <= iters; ++it) {
+    dmc::launch_cg_step_a(s, m, d.ncols, cb, p.precond, p.cg_tol);
+    if (it < iters) dmc::launch_cg_step_b(s, m, d.ncols, cb, p.precond);
+  }
+  dmc::launch_cg_summary(s, cb, d.ncols, summary);
+  decode_enqueue_finish(s, m, records, sl, p, d, cb, Ah, frames_out);
+}
+
+// Conjugate-gradient iterations on the system launch_cg_init set up, with a
+// host check of convergence every check_every iterations (every iteration
+// with the Cholesky preconditioner, which converges in one or two).
+dmc_status cg_iterate(dmc_ctx ctx, const dmc::MeshDev& m, int32_t ncols,
+                      const dmc::CgBuffers& cb, int32_t precond, double tol, int32_t max_iters,
+                      int32_t* iters_out, bool* all_done_out) {
+  hipStream_t s = ctx->stream;
+  dmc_status st = ensure_pinned(ctx, (size_t)ncols * 12 + 4096);
+  if (st != DMC_OK) return st;
+  int32_t* h_done = (int32_t*)ctx->pinned;
+  const int check_every = precond == DMC_PRECOND_CHOLESKY ? 1 : 16;
+  int it = 0;
+  bool all_done = false;
+  while (it < max_iters) {
+    dmc::launch_cg_step_a(s, m, ncols, cb, precond, tol);
+    ++it;
+    if (it % check_every == 0 || it == max_iters) {
+      st = check_launch("cg kernels");
+      if (st != DMC_OK) return st;
+      HIP_TRY(hipMemcpyAsync(h_done, cb.done, (size_t)ncols * 4, hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      all_done = true;
+      for (int j = 0; j < ncols; ++j) all_done = all_done && h_done[j];
+      if (all_done || it == max_iters) break;
+    }
+    dmc::launch_cg_step_b(s, m, ncols, cb, precond);
+  }
+  *iters_out = it;
+  *all_done_out = all_done;
+  return DMC_OK;
 }
 
 // Decode every window of a sequence in one solve over 3F columns.
@@ -309,42 +397,27 @@ dmc_status decode_all(dmc_ctx ctx, const dmc::MeshDev& m, const uint8_t* records
                       const dmc::SeqLayout& sl, const dmc_params& p, void* frames_out,
                       int32_t* iters_out, double* resid_out) {
   hipStream_t s = ctx->stream;
-  const int32_t F = sl.nw_full * sl.T + sl.T_tail;
-  const int32_t ncols = 3 * F;
+  const DecodePlan d = decode_plan(m, sl, p);
+  const int32_t ncols = d.ncols;
   const bool chol = p.precond == DMC_PRECOND_CHOLESKY;
-  const DecodeLayout dl = decode_layout(m, ncols, chol);
-  dmc_status st = ensure_scratch(ctx, dl.total);
+  dmc_status st = ensure_scratch(ctx, d.lay.total);
   if (st != DMC_OK) return st;
   st = ensure_pinned(ctx, (size_t)ncols * 12 + 4096);
   if (st != DMC_OK) return st;
-  const dmc::CgBuffers cb = decode_buffers((uint8_t*)ctx->scratch, dl, ncols, chol);
+  uint8_t* ws = (uint8_t*)ctx->scratch;
+  const dmc::CgBuffers cb = decode_buffers(ws, d.lay, ncols, chol);
+  double* Ah = (double*)(ws + d.lay.o_Ah);
 
-  dmc::launch_back_project(s, m, records, sl, nullptr, cb.q);
-  dmc::launch_rhs(s, m, records, sl, cb.q, cb.r);
-  dmc::launch_cg_init(s, m, ncols, cb.r, cb, p.precond);
+  decode_enqueue_setup(s, m, records, sl, p, d, cb, ws);
   st = check_launch("decode setup kernels");
   if (st != DMC_OK) return st;
-  int32_t* h_done = (int32_t*)ctx->pinned;
   double* h_res = (double*)((uint8_t*)ctx->pinned + dmc::align_up((size_t)ncols * 4));
-  const int check_every = chol ? 1 : 16;
-  int it = 0;
+  int32_t it = 0;
   bool all_done = false;
-  while (it < p.cg_max_iters) {
-    dmc::launch_cg_step_a(s, m, ncols, cb, p.precond, p.cg_tol);
-    ++it;
-    if (it % check_every == 0 || it == p.cg_max_iters) {
-      st = check_launch("cg kernels");
-      if (st != DMC_OK) return st;
-      HIP_TRY(hipMemcpyAsync(h_done, cb.done, (size_t)ncols * 4, hipMemcpyDeviceToHost, s));
-      HIP_TRY(hipStreamSynchronize(s));
-      all_done = true;
-      for (int j = 0; j < ncols; ++j) all_done = all_done && h_done[j];
-      if (all_done || it == p.cg_max_iters) break;
-    }
-    dmc::launch_cg_step_b(s, m, ncols, cb, p.precond);
-  }
-  dmc::launch_to_frames(s, cb.x, m.n, F, p.precision, frames_out);
-  st = check_launch("to_frames");
+  st = cg_iterate(ctx, m, ncols, cb, p.precond, p.cg_tol, p.cg_max_iters, &it, &all_done);
+  if (st != DMC_OK) return st;
+  decode_enqueue_finish(s, m, records, sl, p, d, cb, Ah, frames_out);
+  st = check_launch("frames");
   if (st != DMC_OK) return st;
   HIP_TRY(hipMemcpyAsync(h_res, cb.resid, (size_t)ncols * 8, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
@@ -444,6 +517,59 @@ RecordLayout record_layout(int32_t n, int32_t T, int32_t k, int32_t nc, const dm
 }
 
 }  // namespace dmc
+
+// The anchor response G = (L^T L + I_N^T I_N)^{-1} I_N^T of a mesh (one column
+// per anchor), solved on the device by conjugate gradients with the Cholesky
+// preconditioner, aiming at a relative residual of kAnchorResponseTol in at
+// most kAnchorResponseIters iterations.  It lets the decoder solve 3k instead
+// of 3T columns per window (its residual enters the decoder's test).  It is
+// left unbuilt (the direct decode is used) when it would take more than
+// kAnchorResponseBytes, when its allocation fails or when its largest
+// residual is above kAnchorResponseAccept.
+constexpr double kAnchorResponseTol = 1e-14;
+constexpr double kAnchorResponseAccept = 1e-12;
+constexpr int32_t kAnchorResponseIters = 8;
+constexpr size_t kAnchorResponseBytes = size_t(2) << 30;
+
+dmc_status build_anchor_response(dmc_ctx ctx, dmc_mesh m) {
+  dmc::MeshDev& dv = m->dev;
+  const int32_t nc = dv.nc;
+  const size_t bytes = (size_t)dv.n * nc * 8;
+  if (nc < 1 || bytes > kAnchorResponseBytes) return DMC_OK;
+  const DecodeLayout dl = decode_layout(dv, nc, true);
+  dmc_status st = ensure_scratch(ctx, dl.total);
+  if (st != DMC_OK) return st;
+  uint8_t* ws = (uint8_t*)ctx->scratch;
+  const dmc::CgBuffers cb = decode_buffers(ws, dl, nc, true);
+  hipStream_t s = ctx->stream;
+  dmc::launch_anchor_unit_rhs(s, dv, cb.r);
+  dmc::launch_cg_init(s, dv, nc, cb.r, cb, DMC_PRECOND_CHOLESKY);
+  st = check_launch("anchor response setup");
+  if (st != DMC_OK) return st;
+  int32_t it = 0;
+  bool done = false;  // below kAnchorResponseTol everywhere (not required)
+  st = cg_iterate(ctx, dv, nc, cb, DMC_PRECOND_CHOLESKY, kAnchorResponseTol, kAnchorResponseIters,
+                  &it, &done);
+  if (st != DMC_OK) return st;
+  double* h_res = (double*)((uint8_t*)ctx->pinned + dmc::align_up((size_t)nc * 4));
+  HIP_TRY(hipMemcpyAsync(h_res, cb.resid, (size_t)nc * 8, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  double rmax = 0.0;
+  for (int32_t j = 0; j < nc; ++j) rmax = std::max(rmax, h_res[j]);
+  if (!(rmax <= kAnchorResponseAccept)) return DMC_OK;
+  void* G = nullptr;
+  if (hipMalloc(&G, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return DMC_OK;
+  }
+  m->allocations.push_back(G);
+  HIP_TRY(hipMemcpyAsync(G, cb.x, bytes, hipMemcpyDeviceToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  dv.G = (const double*)G;
+  dv.G_resid = rmax;
+  m->g_iters = it;
+  return DMC_OK;
+}
 
 extern "C" {
 
@@ -593,9 +719,23 @@ dmc_status dmc_mesh_create(dmc_ctx ctx, int32_t n, int32_t n_tris, const int32_t
     (void)hipGetLastError();
     return fail(DMC_ERR_OUT_OF_MEMORY, "cannot upload mesh");
   }
+  st = build_anchor_response(ctx, m);
+  if (st != DMC_OK) {
+    (void)hipStreamSynchronize(ctx->stream);
+    for (void* p : m->allocations) (void)hipFree(p);
+    delete m;
+    return st;
+  }
   ctx->meshes.push_back(m);
   *out = m;
   return DMC_OK;
+}
+
+int32_t dmc_mesh_anchor_response(dmc_mesh mesh, int32_t* cg_iters, double* resid) {
+  if (!mesh) return 0;
+  if (cg_iters) *cg_iters = mesh->g_iters;
+  if (resid) *resid = mesh->dev.G_resid;
+  return mesh->dev.G ? 1 : 0;
 }
 
 void dmc_mesh_factor_info(dmc_mesh mesh, double info[8]) {
@@ -1073,11 +1213,8 @@ void batch_enqueue(dmc_batch b, hipStream_t s) {
   for (size_t i = 0; i < b->seq.size(); ++i) {
     BatchSeq& q = b->seq[i];
     if (!q.out) continue;
-    const int32_t ncols = 3 * q.F;
-    const bool chol = q.p.precond == DMC_PRECOND_CHOLESKY;
-    const DecodeLayout dl = decode_layout(q.mesh->dev, ncols, chol);
-    const dmc::CgBuffers cb = decode_buffers(shared, dl, ncols, chol);
-    decode_enqueue_fixed(s, q.mesh->dev, q.codes, q.sl, q.p, q.out, cb, q.p.cg_max_iters,
+    const DecodePlan d = decode_plan(q.mesh->dev, q.sl, q.p);
+    decode_enqueue_fixed(s, q.mesh->dev, q.codes, q.sl, q.p, d, shared, q.out, q.p.cg_max_iters,
                          summary + 2 * i);
   }
 }
@@ -1166,8 +1303,7 @@ dmc_status dmc_batch_create(dmc_ctx ctx, int32_t nseq, const dmc_mesh* meshes,
                                                           b->precision, Pmax));
     shared = std::max(shared, dmc::project_scratch_bytes(m.n, q.T, q.k_full,
                                                          std::max(1, q.sl.nw_full), b->precision));
-    if (q.out)
-      shared = std::max(shared, decode_layout(m, 3 * q.F, p.precond == DMC_PRECOND_CHOLESKY).total);
+    if (q.out) shared = std::max(shared, decode_plan(m, q.sl, p).lay.total);
     if (q.sl.nw_full) {
       ++nargs;
       njobs += p.init == DMC_INIT_PREV ? 3 : 3 * (size_t)q.sl.nw_full;

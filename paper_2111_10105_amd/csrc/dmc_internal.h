@@ -69,6 +69,10 @@ struct MeshDev {
   const double* m_val = nullptr;
   const double* m_dinv = nullptr;    // [n] 1 / diagonal
   CholDev chol;
+  // anchor response G = (L^T L + I_N^T I_N)^{-1} I_N^T, [n][nc] vertex-major
+  // (nullptr when not built: the decoder then solves 3T columns per window)
+  const double* G = nullptr;
+  double G_resid = 0.0;  // largest relative residual of G's columns
 };
 
 // Per-window stats written by the kernels (device).
@@ -169,6 +173,27 @@ void launch_back_project(hipStream_t s, const MeshDev& m, const uint8_t* records
                          const SeqLayout& sl, const double* u_tilde_or_null, double* B0);
 void launch_rhs(hipStream_t s, const MeshDev& m, const uint8_t* records, const SeqLayout& sl,
                 const double* B0, double* b);
+// Temporal-subspace decode (X_wc = Z_wc U~_wc^T + G A^_wc, Eq. 12 by linearity):
+// columns of the reduced system (3k per window), dequantised coefficients
+// Yd [n][nz], its right-hand side L^T Yd (no anchor term), the dense anchor
+// values [nc][3F], the anchor response's right-hand sides I_N^T [n][nc], and
+// the product that writes the frames [F][n][3] from Z [n][nz], G and A^.
+int32_t reduced_cols(const SeqLayout& sl);
+void launch_coef_rows(hipStream_t s, const MeshDev& m, const uint8_t* records,
+                      const SeqLayout& sl, double* Yd);
+void launch_rhs_reduced(hipStream_t s, const MeshDev& m, int32_t nz, const double* Yd, double* b);
+void launch_anchor_values(hipStream_t s, const MeshDev& m, const uint8_t* records,
+                          const SeqLayout& sl, double* Ah);
+void launch_anchor_unit_rhs(hipStream_t s, const MeshDev& m, double* b);
+// Reference norms of the reduced columns (after launch_cg_init, with b the
+// reduced right-hand side): the test on them bounds every frame's full-system
+// relative residual by tol.  gram_part: group_gram_doubles(n, sl) doubles.
+size_t group_gram_doubles(int32_t n, const SeqLayout& sl);
+void launch_group_ref(hipStream_t s, const MeshDev& m, const uint8_t* records, const SeqLayout& sl,
+                      const double* b, const double* Ah, double tol, double* gram_part,
+                      double* bnorm2);
+void launch_compose(hipStream_t s, const MeshDev& m, const uint8_t* records, const SeqLayout& sl,
+                    const double* Z, const double* Ah, int32_t precision, void* frames_out);
 
 struct CgBuffers {
   double *x, *r, *p, *q;

@@ -9,9 +9,12 @@
 #include <algorithm>
 
 #include "dmc_internal.h"
+#include "wave_ops.h"
 
 namespace dmc {
 namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
 
 constexpr int BP_V = 32;   // vertices per back-projection block
 constexpr int CG_RB = 32;  // rows per CG block
@@ -23,21 +26,24 @@ __device__ inline double dequant(uint32_t code, double lo, double hi, int bits) 
   return lo + (double)code * step;
 }
 
+// The record of window w.  The layout is returned by value: taking the
+// address of a member of the by-value kernel argument would place the whole
+// argument in scratch memory and turn every field read into a scratch load.
 __device__ inline void window_of(const SeqLayout& sl, const uint8_t* records, int w,
                                  const uint8_t*& rec, int& T, int& k, int& t0,
-                                 const RecordLayout*& lay) {
+                                 RecordLayout& lay) {
   if (w < sl.nw_full) {
     rec = records + (size_t)w * sl.rec_bytes_full;
     T = sl.T;
     k = sl.full.k;
     t0 = w * sl.T;
-    lay = &sl.full;
+    lay = sl.full;
   } else {
     rec = records + (size_t)sl.nw_full * sl.rec_bytes_full;
     T = sl.T_tail;
     k = sl.tail.k;
     t0 = sl.nw_full * sl.T;
-    lay = &sl.tail;
+    lay = sl.tail;
   }
 }
 
@@ -56,22 +62,22 @@ k_back_project(const uint8_t* __restrict__ records, SeqLayout sl, int n, int nco
   const int w = blockIdx.y;
   const uint8_t* rec;
   int T, k, t0;
-  const RecordLayout* lay;
+  RecordLayout lay;
   window_of(sl, records, w, rec, T, k, t0, lay);
   const int i0 = blockIdx.x * BP_V;
   const int nv = min(BP_V, n - i0);
   // coefficients of this block's vertices: Yh[v][c][r]
-  const int cb = lay->coef_bits;
+  const int cb = lay.coef_bits;
   for (int e = threadIdx.x; e < 3 * k * nv; e += kBlock) {
     const int v = e % nv, cr = e / nv;  // consecutive threads -> consecutive vertices
     const int c = cr / k, r = cr % k;
     const size_t idx = ((size_t)c * k + r) * n + i0 + v;
     double y;
     if (cb > 0) {
-      const float* rg = (const float*)(rec + lay->off_ranges) + ((size_t)c * k + r) * 2;
-      y = dequant(((const uint16_t*)(rec + lay->off_codes))[idx], (double)rg[0], (double)rg[1], cb);
+      const float* rg = (const float*)(rec + lay.off_ranges) + ((size_t)c * k + r) * 2;
+      y = dequant(((const uint16_t*)(rec + lay.off_codes))[idx], (double)rg[0], (double)rg[1], cb);
     } else {
-      y = (double)((const Real*)(rec + lay->off_codes))[idx];
+      y = (double)((const Real*)(rec + lay.off_codes))[idx];
     }
     Yh[(v * 3 + c) * 33 + r] = y;
   }
@@ -82,14 +88,14 @@ k_back_project(const uint8_t* __restrict__ records, SeqLayout sl, int n, int nco
   if (g >= groups) return;
   const int t = j / 3, c = j % 3;
   // dictionary row (k <= 32)
-  const int db = lay->dict_bits;
+  const int db = lay.dict_bits;
   double u[32];
 #pragma unroll
   for (int r = 0; r < 32; ++r) {
     const int e = (c * T + t) * k + r;
     u[r] = r >= k ? 0.0
-           : db > 0 ? dequant(((const uint16_t*)(rec + lay->off_dict))[e], -1.0, 1.0, db)
-                    : (double)((const Real*)(rec + lay->off_dict))[e];
+           : db > 0 ? dequant(((const uint16_t*)(rec + lay.off_dict))[e], -1.0, 1.0, db)
+                    : (double)((const Real*)(rec + lay.off_dict))[e];
   }
   for (int v = g; v < nv; v += groups) {
     const double* y = Yh + (v * 3 + c) * 33;
@@ -113,22 +119,22 @@ __global__ void k_anchor_values(const uint8_t* __restrict__ records, SeqLayout s
   if (w > sl.nw_full) w = sl.nw_full;
   const uint8_t* rec;
   int T, k, t0;
-  const RecordLayout* lay;
+  RecordLayout lay;
   window_of(sl, records, w, rec, T, k, t0, lay);
   const int t = tg - t0;
   const size_t idx = ((size_t)c * T + t) * nc + s;
   double v;
-  if (lay->anchor_bits > 0) {
-    const float* rg = (const float*)(rec + lay->off_arange) + 2 * c;
-    v = dequant(((const uint16_t*)(rec + lay->off_anchors))[idx], (double)rg[0], (double)rg[1],
-                lay->anchor_bits);
+  if (lay.anchor_bits > 0) {
+    const float* rg = (const float*)(rec + lay.off_arange) + 2 * c;
+    v = dequant(((const uint16_t*)(rec + lay.off_anchors))[idx], (double)rg[0], (double)rg[1],
+                lay.anchor_bits);
   } else {
-    v = (double)((const Real*)(rec + lay->off_anchors))[idx];
+    v = (double)((const Real*)(rec + lay.off_anchors))[idx];
   }
   Ah[e] = v;
 }
 
-// b = L^T B0 + I_N^T Ahat
+// b = L^T B0 + I_N^T Ahat (the anchor term only when Ah is given)
 //   uniform:       (L^T u)_i = u_i - sum_{j in ring(i)} u_j / d_j
 //   combinatorial: (L^T u)_i = d_i u_i - sum_{j in ring(i)} u_j
 __global__ void __launch_bounds__(kBlock)
@@ -163,7 +169,7 @@ k_rhs(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
     const double s = (s0 + s1) + (s2 + s3);
     double out = uniform ? ui - s : w[i] * ui - s;
     const int sl = slot[i];
-    if (sl >= 0) out += Ah[(size_t)sl * ncols + j];
+    if (Ah && sl >= 0) out += Ah[(size_t)sl * ncols + j];
     b[(size_t)i * ncols + j] = out;
   }
 }
@@ -384,6 +390,268 @@ k_to_frames(const double* __restrict__ X, int n, int F, Real* __restrict__ out) 
   }
 }
 
+// ---- temporal-subspace decode ------------------------------------------------
+// Eq. (12) is linear in its right-hand side, and the right-hand side of window
+// w and coordinate c is L^T Y^_wc^T U~_wc^T + I_N^T A^_wc.  So
+//   X_wc = Z_wc U~_wc^T + G A^_wc,
+// where Z_wc (n x k) solves the normal equations for the k columns L^T Y^_wc^T
+// and G = (L^T L + I_N^T I_N)^{-1} I_N^T (n x nc) is the anchor response of
+// the mesh, solved once.  The reduced system has 3k columns per window
+// instead of 3T.  Column of coefficient r of coordinate c of window w:
+// zoff(w) + c k_w + r.
+__device__ inline int zoff(const SeqLayout& sl, int w) {
+  return 3 * sl.full.k * (w < sl.nw_full ? w : sl.nw_full);
+}
+
+constexpr int CR_V = 32;  // vertices per block of k_coef_rows
+
+// Yd[i][zoff(w) + c k + r] = Y^_wc[r][i] (dequantised coefficients, vertex-major)
+template <typename Real>
+__global__ void __launch_bounds__(kBlock)
+k_coef_rows(const uint8_t* __restrict__ records, SeqLayout sl, int n, int nz,
+            double* __restrict__ Yd) {
+  __shared__ double tile[CR_V * 97];  // [v][c k + r], 3k <= 96
+  const int w = blockIdx.y;
+  const uint8_t* rec;
+  int T, k, t0;
+  RecordLayout lay;
+  window_of(sl, records, w, rec, T, k, t0, lay);
+  const int i0 = blockIdx.x * CR_V;
+  const int nv = min(CR_V, n - i0);
+  const int ck = 3 * k;
+  const int cb = lay.coef_bits;
+  for (int e = threadIdx.x; e < ck * CR_V; e += kBlock) {
+    const int cr = e / CR_V, v = e % CR_V;  // consecutive threads -> consecutive vertices
+    if (v >= nv) continue;
+    const size_t idx = (size_t)cr * n + i0 + v;
+    double y;
+    if (cb > 0) {
+      const float* rg = (const float*)(rec + lay.off_ranges) + (size_t)cr * 2;
+      y = dequant(((const uint16_t*)(rec + lay.off_codes))[idx], (double)rg[0], (double)rg[1], cb);
+    } else {
+      y = (double)((const Real*)(rec + lay.off_codes))[idx];
+    }
+    tile[v * 97 + cr] = y;
+  }
+  __syncthreads();
+  const int z0 = zoff(sl, w);
+  for (int e = threadIdx.x; e < nv * ck; e += kBlock) {
+    const int v = e / ck, cr = e % ck;
+    Yd[(size_t)(i0 + v) * nz + z0 + cr] = tile[v * 97 + cr];
+  }
+}
+
+// right-hand sides of the anchor response: b[i][a] = 1 if vertex i is anchor a
+__global__ void __launch_bounds__(kBlock)
+k_anchor_unit_rhs(const int32_t* __restrict__ slot, int n, int nc, double* __restrict__ b) {
+  const size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (e >= (size_t)n * nc) return;
+  const int i = (int)(e / nc), a = (int)(e % nc);
+  b[e] = slot[i] == a ? 1.0 : 0.0;
+}
+
+constexpr int GR_ROWS = 512;  // rows per partial Gram block
+
+// Partial Gram matrices b_g^T b_g of the groups g = 3 w + c of the reduced
+// right-hand side b [n][nz] (the k columns of window w, coordinate c).  Block
+// (g, chunk) adds rows chunk*GR_ROWS.. in order; part[g][chunk][k*k] (stride kk2).
+__global__ void __launch_bounds__(kBlock)
+k_group_gram(SeqLayout sl, int n, int nz, int kk2, const double* __restrict__ b,
+             double* __restrict__ part) {
+  __shared__ double rows[64 * 33];
+  const int g = blockIdx.x, chunk = blockIdx.y;
+  const int w = g / 3, c = g % 3;
+  const int k = w < sl.nw_full ? sl.full.k : sl.tail.k;
+  const int col0 = zoff(sl, w) + c * k;
+  const int r0 = chunk * GR_ROWS, r1 = min(n, r0 + GR_ROWS);
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};  // entries threadIdx.x + q * kBlock (k*k <= 1024)
+  for (int i0 = r0; i0 < r1; i0 += 64) {
+    const int nv = min(64, r1 - i0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < 64 * k; e += kBlock) {
+      const int v = e / k, r = e % k;
+      rows[v * 33 + r] = v < nv ? b[(size_t)(i0 + v) * nz + col0 + r] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = threadIdx.x + q * kBlock;
+      if (e < k * k) {
+        const int r = e / k, s = e % k;
+        double a = acc[q];
+        for (int v = 0; v < nv; ++v) a = fma(rows[v * 33 + r], rows[v * 33 + s], a);
+        acc[q] = a;
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int e = threadIdx.x + q * kBlock;
+    if (e < k * k) part[((size_t)g * gridDim.y + chunk) * kk2 + e] = acc[q];
+  }
+}
+
+// Reference norms of the reduced columns, so that the conjugate-gradient test
+// on them bounds the residual of every frame's full system: frame t of group
+// g = (w, c) has right-hand side B_t = sum_r b_r U~[t][r] + I_N^T A^_t and
+// residual sum_r rho_r U~[t][r] + rho_G A^_t, with
+//   ||B_t||^2 = u^T Gram u + 2 u . s + ||A^_t||^2   (u = U~[t], s_r = sum_a
+//   b_r[anchor a] A^[a][t]),  ||rho_G A^_t|| <= g_resid ||A^_t||_1.
+// With allowance_t = tol ||B_t|| - g_resid ||A^_t||_1, the test
+// sum_r ||rho_r||^2 <= min_t allowance_t^2 (rows of U~ have norm <= 1) gives
+// ||residual_t|| <= tol ||B_t||.  bnorm2 of the group's k columns becomes
+// min_t allowance_t^2 / (k tol^2) over frames with B_t != 0, since the test
+// on column j is ||rho_j||^2 <= tol^2 bnorm2[j] (unchanged if there is none).
+__global__ void __launch_bounds__(64)
+k_group_ref(const uint8_t* __restrict__ records, SeqLayout sl, int nc, int nz, int ncols,
+            int nchunks, int kk2, const int32_t* __restrict__ anchors,
+            const double* __restrict__ b, const double* __restrict__ Ah,
+            const double* __restrict__ part, double g_resid, double tol,
+            double* __restrict__ bnorm2) {
+  __shared__ double gram[1024];
+  const int g = blockIdx.x, w = g / 3, c = g % 3;
+  const uint8_t* rec;
+  int T, k, t0;
+  RecordLayout lay;
+  window_of(sl, records, w, rec, T, k, t0, lay);
+  const int col0 = zoff(sl, w) + c * k;
+  for (int e = threadIdx.x; e < k * k; e += 64) {
+    double s = 0.0;
+    for (int q = 0; q < nchunks; ++q) s += part[((size_t)g * nchunks + q) * kk2 + e];
+    gram[e] = s;
+  }
+  __syncthreads();
+  const int t = threadIdx.x;
+  double allow2 = -1.0;  // < 0: frame without content
+  if (t < T) {
+    const int j = 3 * (t0 + t) + c;
+    const int db = lay.dict_bits;
+    const bool raw64 = lay.precision == DMC_FP64;
+    double u[32], sv[32];
+#pragma unroll
+    for (int r = 0; r < 32; ++r) {
+      const int d = (c * T + t) * k + r;
+      u[r] = r >= k    ? 0.0
+             : db > 0  ? dequant(((const uint16_t*)(rec + lay.off_dict))[d], -1.0, 1.0, db)
+             : raw64   ? ((const double*)(rec + lay.off_dict))[d]
+                       : (double)((const float*)(rec + lay.off_dict))[d];
+      sv[r] = 0.0;
+    }
+    double an2 = 0.0, an1 = 0.0;
+    for (int a = 0; a < nc; ++a) {
+      const double av = Ah[(size_t)a * ncols + j];
+      an2 = fma(av, av, an2);
+      an1 += fabs(av);
+      const double* br = b + (size_t)anchors[a] * nz + col0;
+#pragma unroll
+      for (int r = 0; r < 32; ++r)
+        if (r < k) sv[r] = fma(br[r], av, sv[r]);
+    }
+    double q = an2;
+#pragma unroll
+    for (int r = 0; r < 32; ++r) {
+      if (r >= k) continue;
+      double gu = 0.0;
+      for (int s = 0; s < k; ++s) gu = fma(gram[r * k + s], u[s], gu);
+      q += u[r] * gu + 2.0 * u[r] * sv[r];
+    }
+    const double bn = sqrt(fmax(q, 0.0));
+    if (bn > 0.0) {
+      const double allow = tol * bn - g_resid * an1;
+      allow2 = allow > 0.0 ? allow * allow : 0.0;
+    }
+  }
+  // smallest allowance over the frames with content
+  double m = allow2 >= 0.0 ? allow2 : 1e308;
+  m = wave_min(m);
+  if (m < 1e308 && threadIdx.x < k)
+    bnorm2[col0 + threadIdx.x] = fmax(m, 1e-300) / ((double)k * tol * tol);
+}
+
+constexpr int CP_V = 64;      // vertices per compose block (16 per wave)
+constexpr int CP_KC = 16;     // K rows staged in LDS per step
+constexpr int CP_JT = 12;     // 16-column output tiles (3T <= 192)
+
+// frames of window w for 64 vertices:
+//   X^T (3T x 64) = [A^_w ; U~_w block] ^T-product with [G | Z_w]^T,
+// i.e. X[i][3t + c] = sum_a G[i][a] A^[a][3(t0 + t) + c] + sum_r Z[i][zoff + c k + r] U~_wc[t][r],
+// as one product with K = nc + 3k on the FP64 matrix cores.  The B rows of the
+// Z part are block-diagonal in c (zero where the column's coordinate differs).
+// v_mfma_f64_16x16x4f64: lane l supplies A[l%16][l/16] and B[l/16][l%16];
+// component r of lane l is D[4r + l/16][l%16].  D rows are output columns j,
+// D columns are vertices, so a store covers 16 consecutive vertices.
+template <typename Real>
+__global__ void __launch_bounds__(kBlock)
+k_compose(const uint8_t* __restrict__ records, SeqLayout sl, int n, int nc, int nz, int ncols,
+          const double* __restrict__ G, const double* __restrict__ Z,
+          const double* __restrict__ Ah, Real* __restrict__ out) {
+  __shared__ double As[CP_V * (CP_KC + 1)];          // [vertex][kk]
+  __shared__ double Bs[CP_KC * (16 * CP_JT + 1)];    // [kk][j]
+  constexpr int LB = 16 * CP_JT + 1;
+  const int w = blockIdx.y;
+  const uint8_t* rec;
+  int T, k, t0;
+  RecordLayout lay;
+  window_of(sl, records, w, rec, T, k, t0, lay);
+  const int i0 = blockIdx.x * CP_V;
+  const int J = 3 * T;
+  const int njt = (J + 15) / 16;
+  const int K = nc + 3 * k;
+  const int z0 = zoff(sl, w);
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int db = lay.dict_bits;
+  d4 acc[CP_JT];
+#pragma unroll
+  for (int jt = 0; jt < CP_JT; ++jt) acc[jt] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < K; k0 += CP_KC) {
+    __syncthreads();
+    for (int e = tid; e < CP_V * CP_KC; e += kBlock) {
+      const int i = e / CP_KC, kk = e % CP_KC;
+      const int gi = i0 + i, q = k0 + kk;
+      double v = 0.0;
+      if (gi < n && q < K)
+        v = q < nc ? G[(size_t)gi * nc + q] : Z[(size_t)gi * nz + z0 + (q - nc)];
+      As[i * (CP_KC + 1) + kk] = v;
+    }
+    for (int e = tid; e < CP_KC * J; e += kBlock) {
+      const int kk = e / J, j = e % J;
+      const int q = k0 + kk;
+      double v = 0.0;
+      if (q < nc) {
+        v = Ah[(size_t)q * ncols + 3 * t0 + j];
+      } else if (q < K) {
+        const int cr = q - nc, c = cr / k, r = cr % k;
+        if (j % 3 == c) {
+          const int d = (c * T + j / 3) * k + r;
+          v = db > 0 ? dequant(((const uint16_t*)(rec + lay.off_dict))[d], -1.0, 1.0, db)
+                     : (double)((const Real*)(rec + lay.off_dict))[d];
+        }
+      }
+      Bs[kk * LB + j] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < CP_KC; ks += 4) {
+      const double vb = As[(16 * wv + lane % 16) * (CP_KC + 1) + ks + lane / 16];
+#pragma unroll
+      for (int jt = 0; jt < CP_JT; ++jt)
+        if (jt < njt) {
+          const double va = Bs[(ks + lane / 16) * LB + 16 * jt + lane % 16];
+          acc[jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(va, vb, acc[jt], 0, 0, 0);
+        }
+    }
+  }
+  const int i = i0 + 16 * wv + lane % 16;
+  if (i >= n) return;
+#pragma unroll
+  for (int jt = 0; jt < CP_JT; ++jt)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int j = 16 * jt + 4 * r + lane / 16;
+      if (jt < njt && j < J) out[((size_t)(t0 + j / 3) * n + i) * 3 + j % 3] = (Real)acc[jt][r];
+    }
+}
+
 }  // namespace
 
 size_t cg_part_rows(int32_t n) { return (size_t)(n + CG_RB - 1) / CG_RB; }
@@ -521,6 +789,91 @@ void launch_to_frames(hipStream_t s, const double* X, int32_t n, int32_t F, int3
                        (double*)frames_out);
   else
     hipLaunchKernelGGL(k_to_frames<float>, grid, dim3(kBlock), 0, s, X, n, F, (float*)frames_out);
+  prof::end(s, DMC_KERNEL_TO_FRAMES);
+}
+
+
+int32_t reduced_cols(const SeqLayout& sl) {
+  return 3 * (sl.full.k * sl.nw_full + (sl.T_tail > 0 ? sl.tail.k : 0));
+}
+
+void launch_coef_rows(hipStream_t s, const MeshDev& m, const uint8_t* records,
+                      const SeqLayout& sl, double* Yd) {
+  const int nw = sl.nw_full + (sl.T_tail > 0 ? 1 : 0);
+  dim3 grid((m.n + CR_V - 1) / CR_V, nw);
+  const int nz = reduced_cols(sl);
+  prof::begin(s, DMC_KERNEL_BACK_PROJECT);
+  if (sl.full.precision == DMC_FP64)
+    hipLaunchKernelGGL(k_coef_rows<double>, grid, dim3(kBlock), 0, s, records, sl, m.n, nz, Yd);
+  else
+    hipLaunchKernelGGL(k_coef_rows<float>, grid, dim3(kBlock), 0, s, records, sl, m.n, nz, Yd);
+  prof::end(s, DMC_KERNEL_BACK_PROJECT);
+}
+
+void launch_rhs_reduced(hipStream_t s, const MeshDev& m, int32_t nz, const double* Yd, double* b) {
+  dim3 grid(cg_part_rows(m.n), (nz + kBlock - 1) / kBlock);
+  prof::begin(s, DMC_KERNEL_RHS);
+  hipLaunchKernelGGL(k_rhs, grid, dim3(kBlock), 0, s, m.rowptr, m.col, m.w64,
+                     m.laplacian == DMC_LAP_UNIFORM ? 1 : 0, m.slot, m.n, nz, Yd,
+                     (const double*)nullptr, b);
+  prof::end(s, DMC_KERNEL_RHS);
+}
+
+void launch_anchor_values(hipStream_t s, const MeshDev& m, const uint8_t* records,
+                          const SeqLayout& sl, double* Ah) {
+  const int F = sl.nw_full * sl.T + sl.T_tail;
+  const int ncols = 3 * F;
+  const size_t tot = (size_t)m.nc * ncols;
+  if (tot == 0) return;
+  if (sl.full.precision == DMC_FP64)
+    hipLaunchKernelGGL(k_anchor_values<double>, dim3((tot + kBlock - 1) / kBlock), dim3(kBlock),
+                       0, s, records, sl, m.nc, ncols, Ah);
+  else
+    hipLaunchKernelGGL(k_anchor_values<float>, dim3((tot + kBlock - 1) / kBlock), dim3(kBlock), 0,
+                       s, records, sl, m.nc, ncols, Ah);
+}
+
+size_t group_gram_doubles(int32_t n, const SeqLayout& sl) {
+  const int nw = sl.nw_full + (sl.T_tail > 0 ? 1 : 0);
+  const int nchunks = (n + GR_ROWS - 1) / GR_ROWS;
+  return (size_t)3 * nw * nchunks * sl.full.k * sl.full.k;
+}
+
+void launch_group_ref(hipStream_t s, const MeshDev& m, const uint8_t* records, const SeqLayout& sl,
+                      const double* b, const double* Ah, double tol, double* gram_part,
+                      double* bnorm2) {
+  if (!(tol > 0.0)) return;
+  const int nw = sl.nw_full + (sl.T_tail > 0 ? 1 : 0);
+  const int nchunks = (m.n + GR_ROWS - 1) / GR_ROWS;
+  const int nz = reduced_cols(sl);
+  const int F = sl.nw_full * sl.T + sl.T_tail;
+  const int kk2 = sl.full.k * sl.full.k;
+  hipLaunchKernelGGL(k_group_gram, dim3(3 * nw, nchunks), dim3(kBlock), 0, s, sl, m.n, nz, kk2, b,
+                     gram_part);
+  hipLaunchKernelGGL(k_group_ref, dim3(3 * nw), dim3(64), 0, s, records, sl, m.nc, nz, 3 * F,
+                     nchunks, kk2, m.anchors, b, Ah, (const double*)gram_part, m.G_resid, tol,
+                     bnorm2);
+}
+
+void launch_anchor_unit_rhs(hipStream_t s, const MeshDev& m, double* b) {
+  const size_t tot = (size_t)m.n * m.nc;
+  hipLaunchKernelGGL(k_anchor_unit_rhs, dim3((tot + kBlock - 1) / kBlock), dim3(kBlock), 0, s,
+                     m.slot, m.n, m.nc, b);
+}
+
+void launch_compose(hipStream_t s, const MeshDev& m, const uint8_t* records, const SeqLayout& sl,
+                    const double* Z, const double* Ah, int32_t precision, void* frames_out) {
+  const int nw = sl.nw_full + (sl.T_tail > 0 ? 1 : 0);
+  const int F = sl.nw_full * sl.T + sl.T_tail;
+  dim3 grid((m.n + CP_V - 1) / CP_V, nw);
+  const int nz = reduced_cols(sl);
+  prof::begin(s, DMC_KERNEL_TO_FRAMES);
+  if (precision == DMC_FP64)
+    hipLaunchKernelGGL(k_compose<double>, grid, dim3(kBlock), 0, s, records, sl, m.n, m.nc, nz,
+                       3 * F, m.G, Z, Ah, (double*)frames_out);
+  else
+    hipLaunchKernelGGL(k_compose<float>, grid, dim3(kBlock), 0, s, records, sl, m.n, m.nc, nz,
+                       3 * F, m.G, Z, Ah, (float*)frames_out);
   prof::end(s, DMC_KERNEL_TO_FRAMES);
 }
 

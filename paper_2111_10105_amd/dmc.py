@@ -26,7 +26,7 @@ INIT_PREV, INIT_RANDOM, INIT_SKETCH, INIT_EXACT, INIT_LEARNED = 0, 1, 2, 3, 4
 
 EXPORTS = ["dmc_create", "dmc_destroy", "dmc_set_stream", "dmc_last_error", "dmc_scratch_bytes",
            "dmc_mesh_create", "dmc_mesh_destroy", "dmc_mesh_nnz", "dmc_mesh_normal_nnz",
-           "dmc_mesh_factor_info", "dmc_host_normal_solve",
+           "dmc_mesh_factor_info", "dmc_mesh_anchor_response", "dmc_host_normal_solve",
            "dmc_window_code_bytes", "dmc_sequence_code_bytes", "dmc_encode_window",
            "dmc_decode_window", "dmc_compress_sequence", "dmc_decode_sequence", "dmc_delta",
            "dmc_autocorrelation", "dmc_profile_start", "dmc_profile_stop", "dmc_oi_blocks",
@@ -106,6 +106,7 @@ def lib():
         "dmc_mesh_nnz": (i32, [vp]),
         "dmc_mesh_normal_nnz": (i32, [vp]),
         "dmc_mesh_factor_info": (None, [vp, ctypes.POINTER(dbl)]),
+        "dmc_mesh_anchor_response": (i32, [vp, ctypes.POINTER(i32), ctypes.POINTER(dbl)]),
         "dmc_host_normal_solve": (i32, [i32, i32, vp, i32, vp, i32, i32, vp, vp,
                                         ctypes.POINTER(dbl)]),
         "dmc_window_code_bytes": (sz, [i32, i32, i32, P]),
@@ -236,6 +237,15 @@ class Mesh:
         a = (ctypes.c_double * 8)()
         lib().dmc_mesh_factor_info(self.h, a)
         return dict(zip(FACTOR_INFO_KEYS, list(a)))
+
+    def anchor_response(self):
+        """(built, CG iterations, largest relative residual) of the mesh's
+        anchor response (see dmc_mesh_anchor_response): with it the decoder
+        solves 3k columns per window instead of 3T."""
+        it = ctypes.c_int32(0)
+        res = ctypes.c_double(0.0)
+        built = lib().dmc_mesh_anchor_response(self.h, ctypes.byref(it), ctypes.byref(res))
+        return bool(built), int(it.value), float(res.value)
 
 
 FACTOR_INFO_KEYS = ("stored", "nnz_exact", "supernodes", "levels", "flops", "seconds",
