@@ -23,22 +23,22 @@
 namespace dmc {
 namespace {
 
-constexpr int CT = 64;   // columns per block (one per lane)
-constexpr int RT = 64;   // rows per task
+constexpr int CTG = 64;  // columns per gather / reduce block (one per lane)
+constexpr int RTK = 64;  // rows per task of the task lists
 constexpr int GQ = 4;    // gather: blocks per task (16 rows each, 4 per wave)
-constexpr int RPW = RT / GQ / (kBlock / 64);  // gather rows per wave
+constexpr int RPW = RTK / GQ / (kBlock / 64);  // gather rows per wave
 
 __global__ void __launch_bounds__(kBlock)
 k_fwd_gather(CholDev f, int t0, int ncols, const double* __restrict__ rhs,
              const double* __restrict__ U, double* __restrict__ W) {
   const int task = t0 + blockIdx.x;
   const int s = f.task_w_sn[task], r0 = f.task_w_r0[task];
-  const int c = blockIdx.y * CT + threadIdx.x % CT;
+  const int c = blockIdx.y * CTG + threadIdx.x % CTG;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
   if (c >= ncols) return;
   const int a = f.sn_start[s], w = f.sn_start[s + 1] - a;
   for (int k = 0; k < RPW; ++k) {
-    const int t = r0 + blockIdx.z * (RT / GQ) + wv * RPW + k;
+    const int t = r0 + blockIdx.z * (RTK / GQ) + wv * RPW + k;
     if (t >= w) break;
     const int j = a + t;
     double acc = rhs[(size_t)f.perm[j] * ncols + c];
@@ -59,56 +59,75 @@ k_fwd_gather(CholDev f, int t0, int ncols, const double* __restrict__ rhs,
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-constexpr int KC = 32;       // K chunk staged in LDS
 constexpr int RIDX = 2048;   // ancestor row indices cached per block
-constexpr int LDA = KC + 1;  // padded LDS strides
-constexpr int LDB = CT + 1;
 
-// One 64 x 64 output tile per block on the FP64 matrix cores: wave v owns the
-// 32 x 32 quadrant (v / 2, v % 2) as 2 x 2 tiles of v_mfma_f64_16x16x4f64
-// (lane l supplies A[l%16][l/16] and B[l/16][l%16]; component r of lane l is
-// D[4r + l/16][l%16]).
+// One RT x RT output tile per block on the FP64 matrix cores (RT = 64 or 32):
+// wave v owns the quadrant (v / 2, v % 2) as NQ x NQ tiles of
+// v_mfma_f64_16x16x4f64 (NQ = RT / 32; lane l supplies A[l%16][l/16] and
+// B[l/16][l%16]; component r of lane l is D[4r + l/16][l%16]).  The 32 x 32
+// tiles serve forward levels with few tasks: four times the blocks, a quarter
+// of the matrix-core work on each block's critical path.  K chunks are 32 deep.
+template <int RT>
 struct MfmaTile {
-  d4 acc[2][2];
+  static constexpr int NQ = RT / 32, LDB = RT + 1;
+  static constexpr int KC = 32, LDA = KC + 1;
+  d4 acc[NQ][NQ];
   __device__ void zero() {
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < NQ; ++a)
 #pragma unroll
-      for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+      for (int b = 0; b < NQ; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
   }
   __device__ void step(const double* As, const double* Bs, int wr, int wc, int lane) {
 #pragma unroll
     for (int kk = 0; kk < KC; kk += 4) {
-      double af[2], bf[2];
+      double af[NQ], bf[NQ];
 #pragma unroll
-      for (int a = 0; a < 2; ++a) af[a] = As[(wr * 32 + a * 16 + lane % 16) * LDA + kk + lane / 16];
+      for (int a = 0; a < NQ; ++a)
+        af[a] = As[(wr * 16 * NQ + a * 16 + lane % 16) * LDA + kk + lane / 16];
 #pragma unroll
-      for (int b = 0; b < 2; ++b) bf[b] = Bs[(kk + lane / 16) * LDB + wc * 32 + b * 16 + lane % 16];
+      for (int b = 0; b < NQ; ++b)
+        bf[b] = Bs[(kk + lane / 16) * LDB + wc * 16 * NQ + b * 16 + lane % 16];
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
+      for (int a = 0; a < NQ; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
+        for (int b = 0; b < NQ; ++b)
           acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
     }
   }
 };
 
-// Elements of a 64 x 32 (A) and 32 x 64 (B) chunk staged per thread.
-constexpr int PER_T = RT * KC / kBlock;  // 8
+// The task of a block: the 64-row task lists are shared by both tile sizes;
+// with RT = 32 block x takes half x % 2 of task x / 2 (rows r0 + 32 (x % 2)).
+template <int RT>
+__device__ inline int tile_task(int t0, int& half) {
+  if (RT == 64) {
+    half = 0;
+    return t0 + blockIdx.x;
+  }
+  half = blockIdx.x & 1;
+  return t0 + (blockIdx.x >> 1);
+}
 
-// forward: [Y_s; U_s] rows r0..r0+63 = B_s W_s (K = columns of B_s; rows of the
+// forward: [Y_s; U_s] rows r0..r0+RT-1 = B_s W_s (K = columns of B_s; rows of the
 // diagonal block only need the lower triangle of inv(L_ss)).  Two LDS stages:
 // the global loads of chunk j+1 are in flight while chunk j is multiplied.
+template <int RT>
 __global__ void __launch_bounds__(kBlock)
 k_fwd_gemm(CholDev f, int t0, int ncols, const double* __restrict__ W, double* __restrict__ Y,
            double* __restrict__ U) {
+  constexpr int CT = RT, LDB = MfmaTile<RT>::LDB;
+  constexpr int KC = MfmaTile<RT>::KC, LDA = MfmaTile<RT>::LDA;
+  constexpr int PER_T = RT * KC / kBlock;  // elements of a chunk staged per thread
   __shared__ double As[2][RT * LDA];
   __shared__ double Bs[2][KC * LDB];
-  const int task = t0 + blockIdx.x;
-  const int s = f.task_m_sn[task], r0 = f.task_m_r0[task];
-  const int c0 = blockIdx.y * CT;
+  int half;
+  const int task = tile_task<RT>(t0, half);
+  const int s = f.task_m_sn[task], r0 = f.task_m_r0[task] + RT * half;
   const int a = f.sn_start[s], w = f.sn_start[s + 1] - a;
   const int m = f.sn_rowptr[s + 1] - f.sn_rowptr[s];
+  if (r0 >= m) return;  // whole block
+  const int c0 = blockIdx.y * CT;
   const double* Br = f.brow + f.sn_valptr[s];
   const int tid = threadIdx.x, lane = tid % 64, wv = tid / 64;
   const int wr = wv / 2, wc = wv % 2;
@@ -134,7 +153,7 @@ k_fwd_gemm(CholDev f, int t0, int ncols, const double* __restrict__ W, double* _
       Bs[st][(e / CT) * LDB + e % CT] = rb[u];
     }
   };
-  MfmaTile t;
+  MfmaTile<RT> t;
   t.zero();
   int st = 0;
   if (qend > 0) {
@@ -150,15 +169,16 @@ k_fwd_gemm(CholDev f, int t0, int ncols, const double* __restrict__ W, double* _
     __syncthreads();
     st ^= 1;
   }
+  constexpr int NQ = MfmaTile<RT>::NQ;
   const int64_t sb = f.slot_base[s];
 #pragma unroll
-  for (int ta = 0; ta < 2; ++ta)
+  for (int ta = 0; ta < NQ; ++ta)
 #pragma unroll
-    for (int tb = 0; tb < 2; ++tb)
+    for (int tb = 0; tb < NQ; ++tb)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int i = r0 + wr * 32 + ta * 16 + 4 * r + lane / 16;
-        const int c = c0 + wc * 32 + tb * 16 + lane % 16;
+        const int i = r0 + wr * 16 * NQ + ta * 16 + 4 * r + lane / 16;
+        const int c = c0 + wc * 16 * NQ + tb * 16 + lane % 16;
         if (i >= m || c >= ncols) continue;
         const double v = t.acc[ta][tb][r];
         if (i < w)
@@ -168,18 +188,26 @@ k_fwd_gemm(CholDev f, int t0, int ncols, const double* __restrict__ W, double* _
       }
 }
 
-// backward: X_s rows t0..t0+63 = B_s^T [Y_s; -X_(R_s below the diagonal block)]
-// (K = rows of B_s from t0 on: inv(L_ss) is lower triangular), two LDS stages
+// backward: X_s rows r0..r0+RT-1 = B_s^T [Y_s; -X_(R_s below the diagonal block)]
+// (K = rows of B_s from r0 on: inv(L_ss) is lower triangular), two LDS stages.
+// With nsplit > 1 block z takes a share of the K chunks and writes its
+// partial tile to `part` (summed by k_bwd_reduce); launched with RT = 64.
+template <int RT>
 __global__ void __launch_bounds__(kBlock)
 k_bwd_gemm(CholDev f, int t0, int ncols, const double* __restrict__ Y, double* __restrict__ X,
            double* __restrict__ z, int nsplit, double* __restrict__ part) {
+  constexpr int CT = RT, LDB = MfmaTile<RT>::LDB;
+  constexpr int KC = MfmaTile<RT>::KC, LDA = MfmaTile<RT>::LDA;
+  constexpr int PER_T = RT * KC / kBlock;
   __shared__ double As[2][RT * LDA];
   __shared__ double Bs[2][KC * LDB];
   __shared__ int rows[RIDX];  // ancestor row indices of this block's K range
-  const int task = t0 + blockIdx.x;
-  const int s = f.task_w_sn[task], r0 = f.task_w_r0[task];
-  const int c0 = blockIdx.y * CT;
+  int half;
+  const int task = tile_task<RT>(t0, half);
+  const int s = f.task_w_sn[task], r0 = f.task_w_r0[task] + RT * half;
   const int a = f.sn_start[s], w = f.sn_start[s + 1] - a;
+  if (r0 >= w) return;  // whole block
+  const int c0 = blockIdx.y * CT;
   const int rb0 = f.sn_rowptr[s], m = f.sn_rowptr[s + 1] - rb0;
   const double* Br = f.brow + f.sn_valptr[s];
   const int tid = threadIdx.x, lane = tid % 64, wv = tid / 64;
@@ -220,7 +248,7 @@ k_bwd_gemm(CholDev f, int t0, int ncols, const double* __restrict__ Y, double* _
       Bs[st][(e / CT) * LDB + e % CT] = rb[u];
     }
   };
-  MfmaTile t;
+  MfmaTile<RT> t;
   t.zero();
   for (int i = kb + threadIdx.x; i < min(ke, kb + RIDX); i += kBlock) rows[i - kb] = f.rowidx[rb0 + i];
   __syncthreads();
@@ -238,15 +266,16 @@ k_bwd_gemm(CholDev f, int t0, int ncols, const double* __restrict__ Y, double* _
     __syncthreads();
     st ^= 1;
   }
+  constexpr int NQ = MfmaTile<RT>::NQ;
 #pragma unroll
-  for (int ta = 0; ta < 2; ++ta)
+  for (int ta = 0; ta < NQ; ++ta)
 #pragma unroll
-    for (int tb = 0; tb < 2; ++tb)
+    for (int tb = 0; tb < NQ; ++tb)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int lr = wr * 32 + ta * 16 + 4 * r + lane / 16;  // row within the tile
+        const int lr = wr * 16 * NQ + ta * 16 + 4 * r + lane / 16;  // row within the tile
         const int tr = r0 + lr;
-        const int c = c0 + wc * 32 + tb * 16 + lane % 16;
+        const int c = c0 + wc * 16 * NQ + tb * 16 + lane % 16;
         if (tr >= w || c >= ncols) continue;
         const double v = t.acc[ta][tb][r];
         if (nsplit == 1) {
@@ -265,17 +294,17 @@ k_bwd_reduce(CholDev f, int t0, int ntasks, int ncols, int nsplit, const double*
   const int task = t0 + blockIdx.x;
   const int s = f.task_w_sn[task], r0 = f.task_w_r0[task];
   const int a = f.sn_start[s], w = f.sn_start[s + 1] - a;
-  const int c0 = blockIdx.y * CT;
-  constexpr int RQ = RT / 4;  // rows per block (blockIdx.z picks the quarter)
+  const int c0 = blockIdx.y * CTG;
+  constexpr int RQ = RTK / 4;  // rows per block (blockIdx.z picks the quarter)
 #pragma unroll
-  for (int u = 0; u < RQ * CT / kBlock; ++u) {
+  for (int u = 0; u < RQ * CTG / kBlock; ++u) {
     const int e = threadIdx.x + u * kBlock;
-    const int lr = blockIdx.z * RQ + e / CT, c = c0 + e % CT;
+    const int lr = blockIdx.z * RQ + e / CTG, c = c0 + e % CTG;
     const int tr = r0 + lr;
     if (tr >= w || c >= ncols) continue;
     double v = 0.0;
     for (int q = 0; q < nsplit; ++q)
-      v += part[(((size_t)q * ntasks + blockIdx.x) * RT + lr) * ncols + c];
+      v += part[(((size_t)q * ntasks + blockIdx.x) * RTK + lr) * ncols + c];
     X[(size_t)(a + tr) * ncols + c] = v;
     z[(size_t)f.perm[a + tr] * ncols + c] = v;
   }
@@ -291,20 +320,29 @@ int bwd_split(int ntw, int cb) {
 }  // namespace
 
 size_t chol_split_bytes(const CholDev& f, int32_t ncols) {
-  const int cb = (ncols + CT - 1) / CT;
+  const int cb = (ncols + CTG - 1) / CTG;
   size_t need = 0;
   for (int lv = 0; lv < f.nlevels; ++lv) {
     const int ntw = f.level_w_host[lv + 1] - f.level_w_host[lv];
     const int ns = bwd_split(ntw, cb);
-    if (ns > 1) need = std::max(need, (size_t)ns * ntw * RT * ncols * sizeof(double));
+    if (ns > 1) need = std::max(need, (size_t)ns * ntw * RTK * ncols * sizeof(double));
   }
   return need;
 }
 
+// Tile size of a forward level: 64 x 64 output tiles, or 32 x 32 (four times
+// the blocks, each with a quarter of the critical-path work) when the
+// 64-tiles would not fill 512 blocks.  The backward levels keep 64 x 64 tiles
+// and split their longer K ranges (all rows of B_s) over blocks instead:
+// measured on the torus 128 x 128 factor, 32 x 32 tiles there leave each
+// block a long chain of load-bound chunks.
+constexpr int kSmallLevelBlocks = 512;
+
 void launch_chol_solve(hipStream_t s, const CholDev& f, int32_t ncols, const double* r, double* z,
                        double* W, double* Y, double* X, double* U, double* part) {
   dim3 blk(kBlock);
-  const int cb = (ncols + CT - 1) / CT;
+  const int cb = (ncols + CTG - 1) / CTG;
+  const int cb32 = (ncols + 31) / 32;
   for (int lv = 0; lv < f.nlevels; ++lv) {
     const int tw0 = f.level_w_host[lv], ntw = f.level_w_host[lv + 1] - tw0;
     const int tm0 = f.level_m_host[lv], ntm = f.level_m_host[lv + 1] - tm0;
@@ -312,16 +350,21 @@ void launch_chol_solve(hipStream_t s, const CholDev& f, int32_t ncols, const dou
     hipLaunchKernelGGL(k_fwd_gather, dim3(ntw, cb, GQ), blk, 0, s, f, tw0, ncols, r, U, W);
     prof::end(s, DMC_KERNEL_CHOL_FWD_GATHER);
     prof::begin(s, DMC_KERNEL_CHOL_FWD_SOLVE);
-    hipLaunchKernelGGL(k_fwd_gemm, dim3(ntm, cb), blk, 0, s, f, tm0, ncols, W, Y, U);
+    if (ntm * cb < kSmallLevelBlocks)
+      hipLaunchKernelGGL(k_fwd_gemm<32>, dim3(2 * ntm, cb32), blk, 0, s, f, tm0, ncols, W, Y, U);
+    else
+      hipLaunchKernelGGL(k_fwd_gemm<64>, dim3(ntm, cb), blk, 0, s, f, tm0, ncols, W, Y, U);
     prof::end(s, DMC_KERNEL_CHOL_FWD_SOLVE);
   }
   for (int lv = f.nlevels - 1; lv >= 0; --lv) {
     const int tw0 = f.level_w_host[lv], ntw = f.level_w_host[lv + 1] - tw0;
-    const int ns = part ? bwd_split(ntw, cb) : 1;
     prof::begin(s, DMC_KERNEL_CHOL_BWD_SOLVE);
-    hipLaunchKernelGGL(k_bwd_gemm, dim3(ntw, cb, ns), blk, 0, s, f, tw0, ncols, Y, X, z, ns, part);
+    const int ns = part ? bwd_split(ntw, cb) : 1;
+    hipLaunchKernelGGL(k_bwd_gemm<64>, dim3(ntw, cb, ns), blk, 0, s, f, tw0, ncols, Y, X, z, ns,
+                       part);
     if (ns > 1)
-      hipLaunchKernelGGL(k_bwd_reduce, dim3(ntw, cb, 4), blk, 0, s, f, tw0, ntw, ncols, ns, part, X, z);
+      hipLaunchKernelGGL(k_bwd_reduce, dim3(ntw, cb, 4), blk, 0, s, f, tw0, ntw, ncols, ns, part, X,
+                         z);
     prof::end(s, DMC_KERNEL_CHOL_BWD_SOLVE);
   }
 }

@@ -200,17 +200,29 @@ k_cg_init(const double* __restrict__ b, const double* __restrict__ dinv, int pre
 }
 
 // Column sums of the per-block partials part[h][q][j] (h = 0, 1 selects the
-// first or second half) by a block of 64 columns x 4 groups: group g adds the
-// partials q = g, g + 4, ... and the four group sums are combined in a fixed
-// order, so the result does not depend on scheduling.
-constexpr int RED_COLS = 64, RED_GROUPS = kBlock / RED_COLS;
+// first or second half) by a block of 16 columns x 16 groups: group g adds the
+// partials q = g, g + 16, ... into four independent sums (several loads in
+// flight), and the sums and then the sixteen group sums are combined in a
+// fixed order, so the result does not depend on scheduling.
+constexpr int RED_COLS = 16, RED_GROUPS = kBlock / RED_COLS;
 
 __device__ inline double column_sum(const double* __restrict__ part, int nrb, int ncols, int half,
                                     int j, double* sh) {
   const int g = threadIdx.x / RED_COLS, lc = threadIdx.x % RED_COLS;
   double acc = 0.0;
-  if (j < ncols)
-    for (int q = g; q < nrb; q += RED_GROUPS) acc += part[((size_t)half * nrb + q) * ncols + j];
+  if (j < ncols) {
+    const double* pj = part + (size_t)half * nrb * ncols + j;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int q = g;
+    for (; q + 3 * RED_GROUPS < nrb; q += 4 * RED_GROUPS) {
+      a0 += pj[(size_t)q * ncols];
+      a1 += pj[(size_t)(q + RED_GROUPS) * ncols];
+      a2 += pj[(size_t)(q + 2 * RED_GROUPS) * ncols];
+      a3 += pj[(size_t)(q + 3 * RED_GROUPS) * ncols];
+    }
+    for (; q < nrb; q += RED_GROUPS) a0 += pj[(size_t)q * ncols];
+    acc = (a0 + a1) + (a2 + a3);
+  }
   sh[g * RED_COLS + lc] = acc;
   __syncthreads();
   double tot = 0.0;
@@ -502,32 +514,83 @@ k_group_gram(SeqLayout sl, int n, int nz, int kk2, const double* __restrict__ b,
 // ||residual_t|| <= tol ||B_t||.  bnorm2 of the group's k columns becomes
 // min_t allowance_t^2 / (k tol^2) over frames with B_t != 0, since the test
 // on column j is ||rho_j||^2 <= tol^2 bnorm2[j] (unchanged if there is none).
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(kBlock)
 k_group_ref(const uint8_t* __restrict__ records, SeqLayout sl, int nc, int nz, int ncols,
             int nchunks, int kk2, const int32_t* __restrict__ anchors,
             const double* __restrict__ b, const double* __restrict__ Ah,
             const double* __restrict__ part, double g_resid, double tol,
             double* __restrict__ bnorm2) {
   __shared__ double gram[1024];
+  __shared__ double sbA[64 * 33];   // anchor rows of b: [anchor of the chunk][r]
+  __shared__ double sAh[64 * 65];   // A^ of the chunk: [anchor][t]; then s_t[r] at [t][r] (33)
   const int g = blockIdx.x, w = g / 3, c = g % 3;
   const uint8_t* rec;
   int T, k, t0;
   RecordLayout lay;
   window_of(sl, records, w, rec, T, k, t0, lay);
   const int col0 = zoff(sl, w) + c * k;
-  for (int e = threadIdx.x; e < k * k; e += 64) {
-    double s = 0.0;
-    for (int q = 0; q < nchunks; ++q) s += part[((size_t)g * nchunks + q) * kk2 + e];
-    gram[e] = s;
+  const int tid = threadIdx.x;
+  // Gram matrix: the partials in order, four independent sums
+  for (int e = tid; e < k * k; e += kBlock) {
+    const double* pe = part + (size_t)g * nchunks * kk2 + e;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int q = 0;
+    for (; q + 3 < nchunks; q += 4) {
+      a0 += pe[(size_t)q * kk2];
+      a1 += pe[(size_t)(q + 1) * kk2];
+      a2 += pe[(size_t)(q + 2) * kk2];
+      a3 += pe[(size_t)(q + 3) * kk2];
+    }
+    for (; q < nchunks; ++q) a0 += pe[(size_t)q * kk2];
+    gram[e] = (a0 + a1) + (a2 + a3);
+  }
+  // s_t[r] = sum_a b[anchor_a][col0 + r] A^[a][t] (thread owns entries tid + 256 u of
+  // the T x k block, T k <= 2048), ||A^_t||^2 and ||A^_t||_1 (threads t < T)
+  double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  double an2 = 0.0, an1 = 0.0;
+  for (int a0 = 0; a0 < nc; a0 += 64) {
+    const int na = min(64, nc - a0);
+    __syncthreads();
+    for (int e = tid; e < na * k; e += kBlock) {
+      const int a = e / k, r = e % k;
+      sbA[a * 33 + r] = b[(size_t)anchors[a0 + a] * nz + col0 + r];
+    }
+    for (int e = tid; e < na * T; e += kBlock) {
+      const int a = e / T, t = e % T;
+      sAh[a * 65 + t] = Ah[(size_t)(a0 + a) * ncols + 3 * (t0 + t) + c];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = tid + u * kBlock;
+      if (e < T * k) {
+        const int t = e / k, r = e % k;
+        double s = acc[u];
+        for (int a = 0; a < na; ++a) s = fma(sbA[a * 33 + r], sAh[a * 65 + t], s);
+        acc[u] = s;
+      }
+    }
+    if (tid < T)
+      for (int a = 0; a < na; ++a) {
+        const double v = sAh[a * 65 + tid];
+        an2 = fma(v, v, an2);
+        an1 += fabs(v);
+      }
   }
   __syncthreads();
-  const int t = threadIdx.x;
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int e = tid + u * kBlock;
+    if (e < T * k) sAh[(e / k) * 33 + e % k] = acc[u];
+  }
+  __syncthreads();
+  if (tid >= 64) return;  // T <= 64: the frames are in the first wavefront
+  const int t = tid;
   double allow2 = -1.0;  // < 0: frame without content
   if (t < T) {
-    const int j = 3 * (t0 + t) + c;
     const int db = lay.dict_bits;
     const bool raw64 = lay.precision == DMC_FP64;
-    double u[32], sv[32];
+    double u[32];
 #pragma unroll
     for (int r = 0; r < 32; ++r) {
       const int d = (c * T + t) * k + r;
@@ -535,25 +598,16 @@ k_group_ref(const uint8_t* __restrict__ records, SeqLayout sl, int nc, int nz, i
              : db > 0  ? dequant(((const uint16_t*)(rec + lay.off_dict))[d], -1.0, 1.0, db)
              : raw64   ? ((const double*)(rec + lay.off_dict))[d]
                        : (double)((const float*)(rec + lay.off_dict))[d];
-      sv[r] = 0.0;
-    }
-    double an2 = 0.0, an1 = 0.0;
-    for (int a = 0; a < nc; ++a) {
-      const double av = Ah[(size_t)a * ncols + j];
-      an2 = fma(av, av, an2);
-      an1 += fabs(av);
-      const double* br = b + (size_t)anchors[a] * nz + col0;
-#pragma unroll
-      for (int r = 0; r < 32; ++r)
-        if (r < k) sv[r] = fma(br[r], av, sv[r]);
     }
     double q = an2;
 #pragma unroll
     for (int r = 0; r < 32; ++r) {
       if (r >= k) continue;
       double gu = 0.0;
-      for (int s = 0; s < k; ++s) gu = fma(gram[r * k + s], u[s], gu);
-      q += u[r] * gu + 2.0 * u[r] * sv[r];
+#pragma unroll
+      for (int s = 0; s < 32; ++s)
+        if (s < k) gu = fma(gram[r * k + s], u[s], gu);
+      q += u[r] * gu + 2.0 * u[r] * sAh[t * 33 + r];
     }
     const double bn = sqrt(fmax(q, 0.0));
     if (bn > 0.0) {
@@ -562,94 +616,94 @@ k_group_ref(const uint8_t* __restrict__ records, SeqLayout sl, int nc, int nz, i
     }
   }
   // smallest allowance over the frames with content
-  double m = allow2 >= 0.0 ? allow2 : 1e308;
-  m = wave_min(m);
-  if (m < 1e308 && threadIdx.x < k)
-    bnorm2[col0 + threadIdx.x] = fmax(m, 1e-300) / ((double)k * tol * tol);
+  const double m = wave_min(allow2 >= 0.0 ? allow2 : 1e308);
+  if (m < 1e308 && t < k) bnorm2[col0 + t] = fmax(m, 1e-300) / ((double)k * tol * tol);
 }
 
-constexpr int CP_V = 64;      // vertices per compose block (16 per wave)
-constexpr int CP_KC = 16;     // K rows staged in LDS per step
-constexpr int CP_JT = 12;     // 16-column output tiles (3T <= 192)
+constexpr int CP_V = 64;  // vertices per compose block (16 per wavefront)
 
-// frames of window w for 64 vertices:
-//   X^T (3T x 64) = [A^_w ; U~_w block] ^T-product with [G | Z_w]^T,
-// i.e. X[i][3t + c] = sum_a G[i][a] A^[a][3(t0 + t) + c] + sum_r Z[i][zoff + c k + r] U~_wc[t][r],
-// as one product with K = nc + 3k on the FP64 matrix cores.  The B rows of the
-// Z part are block-diagonal in c (zero where the column's coordinate differs).
-// v_mfma_f64_16x16x4f64: lane l supplies A[l%16][l/16] and B[l/16][l%16];
-// component r of lane l is D[4r + l/16][l%16].  D rows are output columns j,
-// D columns are vertices, so a store covers 16 consecutive vertices.
-template <typename Real>
+// frames of window w for 64 vertices, coordinate by coordinate:
+//   X_c^T (T x 16 vertices) = A^_c^T G^T + U~_c Z_c^T,
+// i.e. X[i][t][c] = sum_a A^[a][3(t0 + t) + c] G[i][a] + sum_r U~_c[t][r] Z[i][zoff + c k + r],
+// on the FP64 matrix cores.  Each wavefront owns 16 vertices and reads its
+// operand fragments straight from memory (G, Z rows of its vertices; A^ and
+// the dictionary, shared by every wavefront, from the caches): no LDS, no
+// barriers.  v_mfma_f64_16x16x4f64: lane l supplies A[l%16][l/16] (frame,
+// K index) and B[l/16][l%16] (K index, vertex); component r of lane l is
+// D[4r + l/16][l%16], so a store covers 16 consecutive vertices.
+// TTM: 16-frame tiles held (2 for T <= 32, 4 for T <= 64).
+template <typename Real, int TTM>
 __global__ void __launch_bounds__(kBlock)
 k_compose(const uint8_t* __restrict__ records, SeqLayout sl, int n, int nc, int nz, int ncols,
           const double* __restrict__ G, const double* __restrict__ Z,
           const double* __restrict__ Ah, Real* __restrict__ out) {
-  __shared__ double As[CP_V * (CP_KC + 1)];          // [vertex][kk]
-  __shared__ double Bs[CP_KC * (16 * CP_JT + 1)];    // [kk][j]
-  constexpr int LB = 16 * CP_JT + 1;
   const int w = blockIdx.y;
   const uint8_t* rec;
   int T, k, t0;
   RecordLayout lay;
   window_of(sl, records, w, rec, T, k, t0, lay);
-  const int i0 = blockIdx.x * CP_V;
-  const int J = 3 * T;
-  const int njt = (J + 15) / 16;
-  const int K = nc + 3 * k;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int i = blockIdx.x * CP_V + 16 * wv + lane % 16;  // this lane's vertex (B column)
+  const bool iv = i < n;
+  const int kq = lane / 16;  // K index within a step of four
+  const int tl = lane % 16;  // frame within a 16-frame tile (A row)
+  const int tt_n = (T + 15) / 16;
   const int z0 = zoff(sl, w);
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int db = lay.dict_bits;
-  d4 acc[CP_JT];
+  const bool raw64 = lay.precision == DMC_FP64;
+  d4 acc[3][TTM];
 #pragma unroll
-  for (int jt = 0; jt < CP_JT; ++jt) acc[jt] = d4{0.0, 0.0, 0.0, 0.0};
-  for (int k0 = 0; k0 < K; k0 += CP_KC) {
-    __syncthreads();
-    for (int e = tid; e < CP_V * CP_KC; e += kBlock) {
-      const int i = e / CP_KC, kk = e % CP_KC;
-      const int gi = i0 + i, q = k0 + kk;
-      double v = 0.0;
-      if (gi < n && q < K)
-        v = q < nc ? G[(size_t)gi * nc + q] : Z[(size_t)gi * nz + z0 + (q - nc)];
-      As[i * (CP_KC + 1) + kk] = v;
-    }
-    for (int e = tid; e < CP_KC * J; e += kBlock) {
-      const int kk = e / J, j = e % J;
-      const int q = k0 + kk;
-      double v = 0.0;
-      if (q < nc) {
-        v = Ah[(size_t)q * ncols + 3 * t0 + j];
-      } else if (q < K) {
-        const int cr = q - nc, c = cr / k, r = cr % k;
-        if (j % 3 == c) {
-          const int d = (c * T + j / 3) * k + r;
-          v = db > 0 ? dequant(((const uint16_t*)(rec + lay.off_dict))[d], -1.0, 1.0, db)
-                     : (double)((const Real*)(rec + lay.off_dict))[d];
-        }
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int tt = 0; tt < TTM; ++tt) acc[c][tt] = d4{0.0, 0.0, 0.0, 0.0};
+  // anchor part: K = anchors, four per step
+#pragma unroll 2
+  for (int a0 = 0; a0 < nc; a0 += 4) {
+    const int a = a0 + kq;
+    const bool av = a < nc;
+    const double vb = (iv && av) ? G[(size_t)i * nc + a] : 0.0;
+    const double* ar = Ah + (size_t)(av ? a : 0) * ncols + 3 * t0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int tt = 0; tt < TTM; ++tt) {
+        if (tt >= tt_n) continue;
+        const int t = 16 * tt + tl;
+        const double va = (av && t < T) ? ar[3 * t + c] : 0.0;
+        acc[c][tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(va, vb, acc[c][tt], 0, 0, 0);
       }
-      Bs[kk * LB + j] = v;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int ks = 0; ks < CP_KC; ks += 4) {
-      const double vb = As[(16 * wv + lane % 16) * (CP_KC + 1) + ks + lane / 16];
-#pragma unroll
-      for (int jt = 0; jt < CP_JT; ++jt)
-        if (jt < njt) {
-          const double va = Bs[(ks + lane / 16) * LB + 16 * jt + lane % 16];
-          acc[jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(va, vb, acc[jt], 0, 0, 0);
-        }
-    }
   }
-  const int i = i0 + 16 * wv + lane % 16;
-  if (i >= n) return;
+  // subspace part: K = the k coefficients of each coordinate
 #pragma unroll
-  for (int jt = 0; jt < CP_JT; ++jt)
+  for (int c = 0; c < 3; ++c)
+    for (int r0 = 0; r0 < k; r0 += 4) {
+      const int r = r0 + kq;
+      const bool rv = r < k;
+      const double vb = (iv && rv) ? Z[(size_t)i * nz + z0 + c * k + r] : 0.0;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int j = 16 * jt + 4 * r + lane / 16;
-      if (jt < njt && j < J) out[((size_t)(t0 + j / 3) * n + i) * 3 + j % 3] = (Real)acc[jt][r];
+      for (int tt = 0; tt < TTM; ++tt) {
+        if (tt >= tt_n) continue;
+        const int t = 16 * tt + tl;
+        double va = 0.0;
+        if (rv && t < T) {
+          const int d = (c * T + t) * k + r;
+          va = db > 0 ? dequant(((const uint16_t*)(rec + lay.off_dict))[d], -1.0, 1.0, db)
+               : raw64 ? ((const double*)(rec + lay.off_dict))[d]
+                       : (double)((const float*)(rec + lay.off_dict))[d];
+        }
+        acc[c][tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(va, vb, acc[c][tt], 0, 0, 0);
+      }
     }
+  if (!iv) return;
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int tt = 0; tt < TTM; ++tt)
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        const int t = 16 * tt + 4 * rr + kq;
+        if (tt < tt_n && t < T) out[((size_t)(t0 + t) * n + i) * 3 + c] = (Real)acc[c][tt][rr];
+      }
 }
 
 }  // namespace
@@ -850,7 +904,7 @@ void launch_group_ref(hipStream_t s, const MeshDev& m, const uint8_t* records, c
   const int kk2 = sl.full.k * sl.full.k;
   hipLaunchKernelGGL(k_group_gram, dim3(3 * nw, nchunks), dim3(kBlock), 0, s, sl, m.n, nz, kk2, b,
                      gram_part);
-  hipLaunchKernelGGL(k_group_ref, dim3(3 * nw), dim3(64), 0, s, records, sl, m.nc, nz, 3 * F,
+  hipLaunchKernelGGL(k_group_ref, dim3(3 * nw), dim3(kBlock), 0, s, records, sl, m.nc, nz, 3 * F,
                      nchunks, kk2, m.anchors, b, Ah, (const double*)gram_part, m.G_resid, tol,
                      bnorm2);
 }
@@ -868,12 +922,16 @@ void launch_compose(hipStream_t s, const MeshDev& m, const uint8_t* records, con
   dim3 grid((m.n + CP_V - 1) / CP_V, nw);
   const int nz = reduced_cols(sl);
   prof::begin(s, DMC_KERNEL_TO_FRAMES);
-  if (precision == DMC_FP64)
-    hipLaunchKernelGGL(k_compose<double>, grid, dim3(kBlock), 0, s, records, sl, m.n, m.nc, nz,
-                       3 * F, m.G, Z, Ah, (double*)frames_out);
-  else
-    hipLaunchKernelGGL(k_compose<float>, grid, dim3(kBlock), 0, s, records, sl, m.n, m.nc, nz,
-                       3 * F, m.G, Z, Ah, (float*)frames_out);
+  const bool t32 = sl.T <= 32;  // the tail window is never longer
+  if (precision == DMC_FP64) {
+    auto kern = t32 ? k_compose<double, 2> : k_compose<double, 4>;
+    hipLaunchKernelGGL(kern, grid, dim3(kBlock), 0, s, records, sl, m.n, m.nc, nz, 3 * F, m.G, Z,
+                       Ah, (double*)frames_out);
+  } else {
+    auto kern = t32 ? k_compose<float, 2> : k_compose<float, 4>;
+    hipLaunchKernelGGL(kern, grid, dim3(kBlock), 0, s, records, sl, m.n, m.nc, nz, 3 * F, m.G, Z,
+                       Ah, (float*)frames_out);
+  }
   prof::end(s, DMC_KERNEL_TO_FRAMES);
 }
 
