@@ -60,6 +60,11 @@ k_fwd_gather(CholDev f, int t0, int ncols, const double* __restrict__ rhs,
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 constexpr int RIDX = 2048;   // ancestor row indices cached per block
+// LDS stages of the solve GEMMs: one stage (the next chunk waits in registers
+// while the current one is multiplied, then replaces it after a barrier)
+// halves the LDS of a block, so twice the blocks share a CU and cover each
+// other's load latency.
+constexpr int kStages = 1;
 
 // One RT x RT output tile per block on the FP64 matrix cores (RT = 64 or 32):
 // wave v owns the quadrant (v / 2, v % 2) as NQ x NQ tiles of
@@ -119,8 +124,8 @@ k_fwd_gemm(CholDev f, int t0, int ncols, const double* __restrict__ W, double* _
   constexpr int CT = RT, LDB = MfmaTile<RT>::LDB;
   constexpr int KC = MfmaTile<RT>::KC, LDA = MfmaTile<RT>::LDA;
   constexpr int PER_T = RT * KC / kBlock;  // elements of a chunk staged per thread
-  __shared__ double As[2][RT * LDA];
-  __shared__ double Bs[2][KC * LDB];
+  __shared__ double As[kStages][RT * LDA];
+  __shared__ double Bs[kStages][KC * LDB];
   int half;
   const int task = tile_task<RT>(t0, half);
   const int s = f.task_m_sn[task], r0 = f.task_m_r0[task] + RT * half;
@@ -165,9 +170,12 @@ k_fwd_gemm(CholDev f, int t0, int ncols, const double* __restrict__ W, double* _
     const bool more = q0 + KC < qend;
     if (more) load(q0 + KC);
     t.step(As[st], Bs[st], wr, wc, lane);
-    if (more) store(st ^ 1);
+    if (more) {
+      if (kStages == 1) __syncthreads();  // every wave has read the stage
+      store(kStages == 1 ? 0 : st ^ 1);
+    }
     __syncthreads();
-    st ^= 1;
+    if (kStages == 2) st ^= 1;
   }
   constexpr int NQ = MfmaTile<RT>::NQ;
   const int64_t sb = f.slot_base[s];
@@ -199,8 +207,8 @@ k_bwd_gemm(CholDev f, int t0, int ncols, const double* __restrict__ Y, double* _
   constexpr int CT = RT, LDB = MfmaTile<RT>::LDB;
   constexpr int KC = MfmaTile<RT>::KC, LDA = MfmaTile<RT>::LDA;
   constexpr int PER_T = RT * KC / kBlock;
-  __shared__ double As[2][RT * LDA];
-  __shared__ double Bs[2][KC * LDB];
+  __shared__ double As[kStages][RT * LDA];
+  __shared__ double Bs[kStages][KC * LDB];
   __shared__ int rows[RIDX];  // ancestor row indices of this block's K range
   int half;
   const int task = tile_task<RT>(t0, half);
@@ -262,9 +270,12 @@ k_bwd_gemm(CholDev f, int t0, int ncols, const double* __restrict__ Y, double* _
     const bool more = i0 + KC < ke;
     if (more) load(i0 + KC);
     t.step(As[st], Bs[st], wr, wc, lane);
-    if (more) store(st ^ 1);
+    if (more) {
+      if (kStages == 1) __syncthreads();  // every wave has read the stage
+      store(kStages == 1 ? 0 : st ^ 1);
+    }
     __syncthreads();
-    st ^= 1;
+    if (kStages == 2) st ^= 1;
   }
   constexpr int NQ = MfmaTile<RT>::NQ;
 #pragma unroll
