@@ -25,7 +25,7 @@ namespace {
 
 constexpr int CTG = 64;  // columns per gather / reduce block (one per lane)
 constexpr int RTK = 64;  // rows per task of the task lists
-constexpr int GQ = 4;    // gather: blocks per task (16 rows each, 4 per wave)
+constexpr int GQ = 16;   // gather: blocks per task (4 rows each, one per wave)
 constexpr int RPW = RTK / GQ / (kBlock / 64);  // gather rows per wave
 
 __global__ void __launch_bounds__(kBlock)
@@ -44,16 +44,13 @@ k_fwd_gather(CholDev f, int t0, int ncols, const double* __restrict__ rhs,
     double acc = rhs[(size_t)f.perm[j] * ncols + c];
     const int e1 = f.contrib_ptr[j + 1];
     int e = f.contrib_ptr[j];
-    // four independent partial sums keep several loads in flight
-    double a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    for (; e + 4 <= e1; e += 4) {
-      acc -= U[(size_t)f.contrib_slot[e] * ncols + c];
-      a1 -= U[(size_t)f.contrib_slot[e + 1] * ncols + c];
-      a2 -= U[(size_t)f.contrib_slot[e + 2] * ncols + c];
-      a3 -= U[(size_t)f.contrib_slot[e + 3] * ncols + c];
-    }
+    // eight independent partial sums keep several loads in flight
+    double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (; e + 8 <= e1; e += 8)
+#pragma unroll
+      for (int q = 0; q < 8; ++q) a[q] -= U[(size_t)f.contrib_slot[e + q] * ncols + c];
     for (; e < e1; ++e) acc -= U[(size_t)f.contrib_slot[e] * ncols + c];
-    W[(size_t)j * ncols + c] = (acc + a1) + (a2 + a3);
+    W[(size_t)j * ncols + c] = acc + (((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7])));
   }
 }
 
