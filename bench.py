@@ -92,12 +92,14 @@ def measured_traffic(family: str):
     return float(m_bytes.group(1))
 
 
-def work_model(fam, *, n, F, T, k, nw, rs, ncols, nnz, m_nnz, finfo, sweeps_total):
+def work_model(fam, *, n, F, T, k, nw, rs, ncols, nnz, m_nnz, finfo, sweeps_total, reduced=False,
+               nc=0):
     """Algorithmic work of one step for a kernel family: (bound, amount, unit)
     with amount in bytes (hbm) or flops (mfma).  Bytes count each input read
     once and each output written once; flops count 2 per multiply-add of the
-    operation's definition."""
-    vec = 8.0 * n * ncols                     # one float64 n x 3F block
+    operation's definition.  ncols: columns of the decoder's solve (3k per
+    window with the mesh's anchor response, `reduced`, else 3F); nc anchors."""
+    vec = 8.0 * n * ncols                     # one float64 n x ncols block
     fr = float(rs) * 3 * n * F                # the frames (or deltas) in their type
     coef = 3.0 * k * n * nw
     if fam == "delta":
@@ -111,7 +113,7 @@ def work_model(fam, *, n, F, T, k, nw, rs, ncols, nnz, m_nnz, finfo, sweeps_tota
         return "hbm", fr + rs * coef, "B"
     if fam == "quantise":
         return "hbm", rs * coef + 2.0 * coef, "B"
-    if fam == "back_project":
+    if fam == "back_project":  # reduced: the dequantised coefficient rows
         return "hbm", 2.0 * coef + vec, "B"
     if fam == "rhs":
         return "hbm", 2 * vec, "B"
@@ -124,6 +126,8 @@ def work_model(fam, *, n, F, T, k, nw, rs, ncols, nnz, m_nnz, finfo, sweeps_tota
     if fam in ("chol_fwd_solve", "chol_bwd_solve"):
         return "mfma", 2.0 * finfo["solve_entries"] * ncols, "flop"
     if fam == "to_frames":
+        if reduced:  # X = Z U~^T + G A^ per window and coordinate, written as frames
+            return "mfma", 2.0 * n * 3 * F * (nc + k), "flop"
         return "hbm", vec + fr, "B"
     return None, None, None
 
@@ -421,8 +425,14 @@ def main():
                              "oi_sweeps_total": int(sum(sum(x["oi_sweeps"]) for x in stb)),
                              "nmse_vs_input": nmse(got_bf16, w.frames)}}
 
-    model = dict(n=n, F=F, T=T, k=min(w.k, T), nw=nw, rs=4, ncols=3 * F, nnz=mesh.nnz,
-                 m_nnz=mesh.normal_nnz, finfo=finfo, sweeps_total=sweeps_total)
+    # the decode form the library takes (its cost rule, include/dmc.h)
+    nz = 3 * min(w.k, T) * nw
+    S, A = 16.0 * finfo["solve_entries"], 2.0 * n * mesh.nc
+    reduced = mesh.anchor_response()[0] and nz * S + 3 * F * A < 3 * F * S
+    model = dict(n=n, F=F, T=T, k=min(w.k, T), nw=nw, rs=4,
+                 ncols=nz if reduced else 3 * F, nnz=mesh.nnz,
+                 m_nnz=mesh.normal_nnz, finfo=finfo, sweeps_total=sweeps_total, reduced=reduced,
+                 nc=int(mesh.nc))
     kernels = {}
     for fam, b in breakdown.items():
         bound, amount, unit = work_model(fam, **model)

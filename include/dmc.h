@@ -152,13 +152,16 @@ int32_t dmc_mesh_normal_nnz(dmc_mesh mesh);   /* nonzeros of L^T L + I_N^T I_N *
  * counted by row of the supernode that produces them) */
 void dmc_mesh_factor_info(dmc_mesh mesh, double info[8]);
 /* Whether the mesh holds its anchor response G = (L^T L + I_N^T I_N)^{-1}
- * I_N^T (n x n_c, float64 on the device), built by dmc_mesh_create when it
- * takes at most 2 GiB: the right-hand side of Eq. (12) is linear in the
- * decoded delta coordinates and anchor values, so with G the decoder solves
- * the 3k columns L^T Y^^T of each window instead of its 3T frames' columns and
- * forms X = Z U~^T + G A^ (same solution up to rounding).  The decoder's
- * convergence test then bounds the relative residual of every frame's full
- * system of Eq. (12) by cg_tol, counting G's own residual.  Returns 1 if built
+ * I_N^T (n x n_c, float64 on the device).  The right-hand side of Eq. (12) is
+ * linear in the decoded delta coordinates and anchor values, so with G the
+ * decoder can solve the 3k columns L^T Y^^T of each window instead of its 3T
+ * frames' columns and form X = Z U~^T + G A^ (same solution up to rounding).
+ * Cost model: a solved column costs S = 16 x (entries of the solve operators,
+ * dmc_mesh_factor_info [6]), the product A = 2 n n_c per output column.
+ * dmc_mesh_create builds G when 2 A <= S and it takes at most 2 GiB; a decode
+ * uses it when nz S + 3F A < 3F S (nz the reduced columns).  The convergence
+ * test then bounds the relative residual of every frame's full system of
+ * Eq. (12) by cg_tol, counting G's own residual.  Returns 1 if built
  * and writes, where the pointers are not NULL, the conjugate-gradient
  * iterations of its solve and the largest relative residual of its columns;
  * 0 if not built (the decoder then solves 3T columns per window) or for a

@@ -268,9 +268,18 @@ DecodeLayout decode_layout(const dmc::MeshDev& m, int32_t ncols, bool chol,
   return d;
 }
 
+// Cost weights of the decode forms, per column of the solve and per output
+// column: a solved column costs about 4 flops per solve-operator entry (the
+// forward and backward solves), weighted 4x because the level-scheduled solve
+// runs at about a quarter of the efficiency of the dense anchor product, which
+// costs 2 n n_c flops per output column.
+inline double solve_cost_per_column(const dmc::MeshDev& m) { return 16.0 * m.solve_entries; }
+inline double anchor_cost_per_column(const dmc::MeshDev& m) { return 2.0 * m.n * (double)m.nc; }
+
 // How a sequence is decoded: the temporal-subspace form (solve the 3k columns
-// L^T Y^^T of each window, then X = Z U~^T + G A^) whenever the mesh holds
-// its anchor response and that is fewer columns than the 3T of the direct form.
+// L^T Y^^T of each window, then X = Z U~^T + G A^) when the mesh holds its
+// anchor response and nz S + 3F A < 3F S (S, A the costs above, nz the
+// reduced columns); otherwise the direct form (3T columns per window).
 struct DecodePlan {
   bool reduced = false;
   int32_t F = 0, ncols = 0;  // frames; columns of the solve
@@ -281,7 +290,9 @@ DecodePlan decode_plan(const dmc::MeshDev& m, const dmc::SeqLayout& sl, const dm
   DecodePlan d;
   d.F = sl.nw_full * sl.T + sl.T_tail;
   const int32_t nz = dmc::reduced_cols(sl);
-  d.reduced = m.G != nullptr && nz < 3 * d.F;
+  const double S = solve_cost_per_column(m), A = anchor_cost_per_column(m);
+  d.reduced = m.G != nullptr && nz < 3 * d.F &&
+              (double)nz * S + 3.0 * d.F * A < 3.0 * d.F * S;
   d.ncols = d.reduced ? nz : 3 * d.F;
   d.lay = decode_layout(m, d.ncols, p.precond == DMC_PRECOND_CHOLESKY,
                         d.reduced ? (size_t)m.nc * 3 * d.F : 0,
@@ -523,8 +534,9 @@ RecordLayout record_layout(int32_t n, int32_t T, int32_t k, int32_t nc, const dm
 // preconditioner, aiming at a relative residual of kAnchorResponseTol in at
 // most kAnchorResponseIters iterations.  It lets the decoder solve 3k instead
 // of 3T columns per window (its residual enters the decoder's test).  It is
-// left unbuilt (the direct decode is used) when it would take more than
-// kAnchorResponseBytes, when its allocation fails or when its largest
+// left unbuilt (the direct decode is used) when its product costs more than
+// half a solved column even at k = T / 2 (2 A > S), when it would take more
+// than kAnchorResponseBytes, when its allocation fails or when its largest
 // residual is above kAnchorResponseAccept.
 constexpr double kAnchorResponseTol = 1e-14;
 constexpr double kAnchorResponseAccept = 1e-12;
@@ -536,6 +548,7 @@ dmc_status build_anchor_response(dmc_ctx ctx, dmc_mesh m) {
   const int32_t nc = dv.nc;
   const size_t bytes = (size_t)dv.n * nc * 8;
   if (nc < 1 || bytes > kAnchorResponseBytes) return DMC_OK;
+  if (2.0 * anchor_cost_per_column(dv) > solve_cost_per_column(dv)) return DMC_OK;
   const DecodeLayout dl = decode_layout(dv, nc, true);
   dmc_status st = ensure_scratch(ctx, dl.total);
   if (st != DMC_OK) return st;
@@ -690,6 +703,7 @@ dmc_status dmc_mesh_create(dmc_ctx ctx, int32_t n, int32_t n_tris, const int32_t
   dv.m_val = (const double*)up(M.val.data(), M.val.size() * 8);
   dv.m_dinv = (const double*)up(dinv.data(), n * 8);
   dmc::CholDev& cd = dv.chol;
+  dv.solve_entries = info[6];
   cd.n = n;
   cd.ns = F.nsuper;
   cd.nlevels = F.nlevels;

@@ -73,6 +73,7 @@ struct MeshDev {
   // (nullptr when not built: the decoder then solves 3T columns per window)
   const double* G = nullptr;
   double G_resid = 0.0;  // largest relative residual of G's columns
+  double solve_entries = 0.0;  // entries of the solve operators (one triangular solve)
 };
 
 // Per-window stats written by the kernels (device).
