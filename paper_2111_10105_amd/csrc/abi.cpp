@@ -179,6 +179,15 @@ dmc_status encode_chain(dmc_ctx ctx, const dmc::MeshDev& m, const void* frames, 
     ql = (float*)cur;
     cur += dmc::align_up((size_t)nw * 3 * T * k * 4);
   }
+  // the chained start defers each window's Ritz step to one parallel pass
+  double* ritz_qh = nullptr;
+  int32_t* ritz_flag = nullptr;
+  if (p.init == DMC_INIT_PREV) {
+    ritz_qh = (double*)cur;
+    cur += dmc::align_up((size_t)nw * 3 * (T * k + k * k) * 8);
+    ritz_flag = (int32_t*)cur;
+    cur += dmc::align_up((size_t)nw * 3 * 4);
+  }
   void* proj = cur;
   for (int32_t w = 0; w < nw; ++w) dmc::launch_write_header(s, records + (size_t)w * lay.bytes, lay);
   dmc::launch_autocorr(s, frames, m.n, T, nw, p.precision, part, R);
@@ -186,7 +195,7 @@ dmc_status encode_chain(dmc_ctx ctx, const dmc::MeshDev& m, const void* frames, 
     dmc::launch_mlp_sketch(s, R, nw * 3, T, ctx->learned_omega, sk);
     dmc::launch_mlp_forward(s, ctx->learned_theta, k, sk, nw * 3 * T, ql, nullptr);
   }
-  dmc::OiArgs oa;
+  dmc::OiArgs oa{};
   oa.R = R;
   oa.nw = nw;
   oa.T = T;
@@ -205,6 +214,8 @@ dmc_status encode_chain(dmc_ctx ctx, const dmc::MeshDev& m, const void* frames, 
   oa.max_sweeps = p.oi_max_sweeps;
   oa.tol = p.oi_tol;
   oa.stats = stats_dev;
+  oa.ritz_qh = ritz_qh;
+  oa.ritz_flag = ritz_flag;
   dmc::launch_oi(s, oa);
   dmc::launch_project_quantise(s, delta, m.n, T, k, nw, p.precision, p.coef_bits, u_tilde, records,
                                lay.bytes, lay, proj, coef_out);
@@ -218,9 +229,13 @@ size_t chain_scratch_bytes(int32_t n, int32_t T, int32_t nw, int32_t k, int32_t 
                              ? dmc::align_up((size_t)nw * 3 * T * 32 * 4) +
                                    dmc::align_up((size_t)nw * 3 * T * k * 4)
                              : 0;
+  const size_t ritz = init == DMC_INIT_PREV
+                          ? dmc::align_up((size_t)nw * 3 * (T * k + k * k) * 8) +
+                                dmc::align_up((size_t)nw * 3 * 4)
+                          : 0;
   return dmc::align_up((size_t)nw * 3 * T * T * 8) +
          dmc::align_up(dmc::autocorr_scratch_bytes(n, T, nw, precision)) +
-         dmc::align_up((size_t)nw * 3 * T * k * 8) + learned +
+         dmc::align_up((size_t)nw * 3 * T * k * 8) + learned + ritz +
          dmc::align_up(dmc::project_scratch_bytes(n, T, k, nw, precision));
 }
 

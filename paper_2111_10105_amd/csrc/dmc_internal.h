@@ -117,6 +117,11 @@ struct OiArgs {
   int32_t max_sweeps;
   double tol;
   StatsDev* stats;       // [nw]
+  // chained path (DMC_INIT_PREV): scratch for the deferred Ritz step,
+  // [nw][ncoord][T*k + k*k] float64 (Q, then H = Q^T R Q) and [nw][ncoord]
+  // flags, or nullptr (the Ritz step then runs inside the chain)
+  double* ritz_qh;
+  int32_t* ritz_flag;
 };
 void launch_oi(hipStream_t s, const OiArgs& a);
 // jobs[b] = (index into args, first window, end window, coordinate); the

@@ -969,7 +969,7 @@ __device__ __forceinline__ double dequant(uint16_t code, double lo, double hi, i
 template <int KR, int TMAX, int KMAX>
 __device__ __forceinline__ void oi_sweeps(OiSmem<TMAX, KMAX>& s, int T, int k, int max_sweeps, double tol,
                                           double normR, bool bf16, bool q_orthonormal, int& sweeps,
-                                          int& repairs, double& resid) {
+                                          int& repairs, double& resid, bool ritz = true) {
   // precision form: bfloat16 products until the stage tolerance (or one sweep
   // before the cap), then full-precision refinement sweeps (at least one)
   // until tol, or until a sweep no longer reduces the residual by a tenth
@@ -1008,8 +1008,34 @@ __device__ __forceinline__ void oi_sweeps(OiSmem<TMAX, KMAX>& s, int T, int k, i
       prev = resid;
     }
   }
-  eigen_sym<KR == 16>(s, k);
-  ritz_vectors<KR>(s, k);
+  if (ritz) {
+    eigen_sym<KR == 16>(s, k);
+    ritz_vectors<KR>(s, k);
+  }
+}
+
+// Outputs of window w, coordinate c from the canonical U in s.Y: U, the
+// dictionary codes (Sec. IV: 16-bit uniform over [-1, 1]) and the dequantised
+// dictionary.
+template <int TMAX, int KMAX, typename Real>
+__device__ __forceinline__ void oi_outputs(OiSmem<TMAX, KMAX>& s, const OiArgs& a, int w, int c) {
+  const int T = a.T, k = a.k;
+  Real* uo = a.u_out ? (Real*)a.u_out + ((size_t)w * a.ncoord + c) * T * k : nullptr;
+  double* ut = a.u_tilde ? a.u_tilde + ((size_t)w * a.ncoord + c) * T * k : nullptr;
+  uint8_t* rec = a.records ? a.records + (size_t)w * a.rec_bytes + a.off_dict : nullptr;
+  for (int e = threadIdx.x; e < T * k; e += NT) {
+    const double u = s.Y[(e / k) * s.LQ + e % k];
+    if (uo) uo[e] = (Real)u;
+    if (!rec) continue;  // subspace only (no record)
+    if (a.dict_bits > 0) {
+      const uint16_t code = quant<Real>(u, -1.0, 1.0, a.dict_bits);
+      ((uint16_t*)rec)[(size_t)c * T * k + e] = code;
+      ut[e] = dequant(code, -1.0, 1.0, a.dict_bits);
+    } else {
+      ((Real*)rec)[(size_t)c * T * k + e] = (Real)u;
+      ut[e] = (double)(Real)u;
+    }
+  }
 }
 
 // One workgroup (one wavefront) per coordinate; KR = k rounded up to the
@@ -1051,6 +1077,7 @@ __device__ __forceinline__ void oi_run(OiSmem<TMAX, KMAX>& s, const OiArgs& a, i
 
     int sweeps = 0, repairs = 0;
     double resid = 0.0;
+    bool defer = false;
     // exact start: always with DMC_INIT_EXACT, else for a missing start block
     // (window 0 of the chain; any window otherwise)
     const bool exact = a.init == DMC_INIT_EXACT ||
@@ -1108,29 +1135,28 @@ __device__ __forceinline__ void oi_run(OiSmem<TMAX, KMAX>& s, const OiArgs& a, i
           __syncthreads();
         }
       }
+      // chained windows with deferral: the Ritz step and the outputs run
+      // afterwards for every window at once (k_oi_ritz), and the next window
+      // starts from Q, which spans the same subspace as this window's U_k
+      // (the sweeps, their residual test and the Ritz step depend on the
+      // start's span only)
+      defer = chain && a.ritz_qh != nullptr;
       oi_sweeps<KR>(s, T, k, a.max_sweeps, a.tol, normR, a.precision == DMC_BF16, chain && w > 0,
-                    sweeps, repairs, resid);
-      sign_fix(s, T, k);
-    }
-    // ---- outputs: U, dictionary codes, dequantised dictionary ----
-    Real* uo = a.u_out ? (Real*)a.u_out + ((size_t)w * a.ncoord + c) * T * k : nullptr;
-    double* ut = a.u_tilde ? a.u_tilde + ((size_t)w * a.ncoord + c) * T * k : nullptr;
-    uint8_t* rec = a.records ? a.records + (size_t)w * a.rec_bytes + a.off_dict : nullptr;
-    for (int e = tid; e < T * k; e += NT) {
-      const double u = s.Y[(e / k) * s.LQ + e % k];
-      if (uo) uo[e] = (Real)u;
-      if (!rec) continue;  // subspace only (no record)
-      if (a.dict_bits > 0) {
-        const uint16_t code = quant<Real>(u, -1.0, 1.0, a.dict_bits);
-        ((uint16_t*)rec)[(size_t)c * T * k + e] = code;
-        ut[e] = dequant(code, -1.0, 1.0, a.dict_bits);
+                    sweeps, repairs, resid, !defer);
+      if (defer) {
+        double* dst = a.ritz_qh + ((size_t)w * a.ncoord + c) * (T * k + k * k);
+        for (int e = tid; e < T * k; e += NT) dst[e] = s.Q[(e / k) * s.LQ + e % k];
+        for (int e = tid; e < k * k; e += NT) dst[T * k + e] = s.A[(e / k) * s.LR + e % k];
       } else {
-        ((Real*)rec)[(size_t)c * T * k + e] = (Real)u;
-        ut[e] = (double)(Real)u;
+        sign_fix(s, T, k);
       }
     }
-    // the next window starts from this window's U_k
-    for (int e = tid; e < T * k; e += NT) s.Q[(e / k) * s.LQ + e % k] = s.Y[(e / k) * s.LQ + e % k];
+    if (chain && a.ritz_flag && tid == 0) a.ritz_flag[w * a.ncoord + c] = defer ? 1 : 0;
+    if (!defer) {
+      oi_outputs<TMAX, KMAX, Real>(s, a, w, c);
+      // the next window starts from this window's U_k
+      for (int e = tid; e < T * k; e += NT) s.Q[(e / k) * s.LQ + e % k] = s.Y[(e / k) * s.LQ + e % k];
+    }
     __syncthreads();
     if (tid == 0 && a.stats) {
       a.stats[w].sweeps[c] = sweeps;
@@ -1150,6 +1176,28 @@ __global__ void __launch_bounds__(NT) k_oi(OiArgs a) {
   oi_run<TMAX, KMAX, KR, Real>(s, a, blockIdx.x, w_begin, chain ? a.nw : w_begin + 1);
 }
 
+// The deferred Ritz step of the chained path (Algorithm 1 followed by Eq. 5 on
+// the converged block): workgroup (c, w) takes window w's Q and H = Q^T R Q,
+// forms the canonical U = Q V (eigenvectors of H, largest first, sign rule)
+// and writes the window's outputs.  All windows run at once.
+template <int TMAX, int KMAX, int KR, typename Real>
+__global__ void __launch_bounds__(NT) k_oi_ritz(OiArgs a) {
+  __shared__ OiSmem<TMAX, KMAX> s;
+  const int c = blockIdx.x, w = blockIdx.y;
+  if (a.ritz_flag[w * a.ncoord + c] == 0) return;  // whole workgroup: handled by k_oi
+  const int T = a.T, k = a.k, tid = threadIdx.x;
+  const double* src = a.ritz_qh + ((size_t)w * a.ncoord + c) * (T * k + k * k);
+  for (int e = tid; e < TMAX * s.LQ; e += NT) s.Q[e] = 0.0;
+  __syncthreads();
+  for (int e = tid; e < T * k; e += NT) s.Q[(e / k) * s.LQ + e % k] = src[e];
+  for (int e = tid; e < k * k; e += NT) s.A[(e / k) * s.LR + e % k] = src[T * k + e];
+  __syncthreads();
+  eigen_sym<KR == 16>(s, k);
+  ritz_vectors<KR>(s, k);
+  sign_fix(s, T, k);
+  oi_outputs<TMAX, KMAX, Real>(s, a, w, c);
+}
+
 // Many sequences in one launch: workgroup b runs job jobs[b] = (sequence,
 // first window, end window, coordinate) of args[sequence].
 template <int TMAX, int KMAX, int KR, typename Real>
@@ -1166,10 +1214,16 @@ __global__ void __launch_bounds__(NT) k_oi_batch(const OiArgs* __restrict__ args
 template <int TMAX, int KR>
 void launch_oi_t(hipStream_t st, const OiArgs& a) {
   const dim3 grid(a.ncoord, a.init == DMC_INIT_PREV ? 1 : a.nw);
-  if (a.precision == DMC_FP64)
+  const bool deferred = a.init == DMC_INIT_PREV && a.ritz_qh != nullptr;
+  if (a.precision == DMC_FP64) {
     hipLaunchKernelGGL((k_oi<TMAX, 32, KR, double>), grid, dim3(NT), 0, st, a);
-  else
+    if (deferred)
+      hipLaunchKernelGGL((k_oi_ritz<TMAX, 32, KR, double>), dim3(a.ncoord, a.nw), dim3(NT), 0, st, a);
+  } else {
     hipLaunchKernelGGL((k_oi<TMAX, 32, KR, float>), grid, dim3(NT), 0, st, a);
+    if (deferred)
+      hipLaunchKernelGGL((k_oi_ritz<TMAX, 32, KR, float>), dim3(a.ncoord, a.nw), dim3(NT), 0, st, a);
+  }
 }
 
 template <int TMAX, int KR>
