@@ -34,6 +34,7 @@ struct dmc_mesh_s {
   dmc::MeshDev dev;
   std::vector<void*> allocations;
   std::vector<int32_t> level_w, level_m;  // host copies of the factor's level -> task ranges
+  std::vector<int32_t> level_maxw;        // widest supernode of each level
   double factor_info[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   int32_t g_iters = 0;  // CG iterations of the anchor response (0: not built)
 };
@@ -668,12 +669,13 @@ dmc_status dmc_mesh_create(dmc_ctx ctx, int32_t n, int32_t n_tris, const int32_t
   // factor work items: (supernode, first row of a 64-row tile), by level, over
   // the supernode's w columns and over its m rows
   std::vector<int32_t> tw_sn, tw_r0, tm_sn, tm_r0, level_w(F.nlevels + 1, 0),
-      level_m(F.nlevels + 1, 0);
+      level_m(F.nlevels + 1, 0), level_maxw(F.nlevels, 0);
   for (int32_t lv = 0; lv < F.nlevels; ++lv) {
     for (int32_t sn = 0; sn < F.nsuper; ++sn) {
       if (F.sn_level[sn] != lv) continue;
       const int32_t w = F.sn_start[sn + 1] - F.sn_start[sn];
       const int32_t mm = F.sn_rowptr[sn + 1] - F.sn_rowptr[sn];
+      level_maxw[lv] = std::max(level_maxw[lv], w);
       for (int32_t r0 = 0; r0 < w; r0 += 64) {
         tw_sn.push_back(sn);
         tw_r0.push_back(r0);
@@ -739,8 +741,10 @@ dmc_status dmc_mesh_create(dmc_ctx ctx, int32_t n, int32_t n_tris, const int32_t
   cd.task_m_r0 = (const int32_t*)up(tm_r0.data(), tm_r0.size() * 4);
   m->level_w = level_w;
   m->level_m = level_m;
+  m->level_maxw = level_maxw;
   cd.level_w_host = m->level_w.data();
   cd.level_m_host = m->level_m.data();
+  cd.level_maxw_host = m->level_maxw.data();
   std::memcpy(m->factor_info, info, sizeof(info));
   if (!ok) {
     for (void* p : m->allocations) (void)hipFree(p);

@@ -51,6 +51,7 @@ struct CholDev {
   const int32_t* task_m_r0 = nullptr;
   const int32_t* level_w_host = nullptr;  // host arrays [nlevels + 1]
   const int32_t* level_m_host = nullptr;
+  const int32_t* level_maxw_host = nullptr;  // host [nlevels]: widest supernode of a level
   int64_t nslots = 0;
 };
 
@@ -226,7 +227,8 @@ void launch_cg_summary(hipStream_t s, const CgBuffers& cb, int32_t ncols, double
 size_t chol_split_bytes(const CholDev& f, int32_t ncols);
 void launch_chol_solve(hipStream_t s, const CholDev& f, int32_t ncols, const double* r, double* z,
                        double* W, double* Y, double* X, double* U, double* part);
-void launch_precond_apply(hipStream_t s, const MeshDev& m, int32_t ncols, const CgBuffers& cb);
+void launch_precond_apply(hipStream_t s, const MeshDev& m, int32_t ncols, const CgBuffers& cb,
+                          double* p_out);
 void launch_to_frames(hipStream_t s, const double* X, int32_t n, int32_t F, int32_t precision,
                       void* frames_out);
 

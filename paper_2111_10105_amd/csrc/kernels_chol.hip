@@ -340,10 +340,11 @@ size_t chol_split_bytes(const CholDev& f, int32_t ncols) {
 
 // Tile size of a forward level: 64 x 64 output tiles, or 32 x 32 (four times
 // the blocks, each with a quarter of the critical-path work) when the
-// 64-tiles would not fill 512 blocks.  The backward levels keep 64 x 64 tiles
-// and split their longer K ranges (all rows of B_s) over blocks instead:
-// measured on the torus 128 x 128 factor, 32 x 32 tiles there leave each
-// block a long chain of load-bound chunks.
+// 64-tiles would not fill 512 blocks.  A backward level uses 32 x 32 tiles
+// when none of its supernodes is wider than 32 (64-row tiles would be half
+// padding); the others keep 64 x 64 tiles and split their longer K ranges
+// (all rows of B_s) over blocks: measured on the torus 128 x 128 factor, 32 x
+// 32 tiles there leave each block a long chain of load-bound chunks.
 constexpr int kSmallLevelBlocks = 512;
 
 void launch_chol_solve(hipStream_t s, const CholDev& f, int32_t ncols, const double* r, double* z,
@@ -367,12 +368,19 @@ void launch_chol_solve(hipStream_t s, const CholDev& f, int32_t ncols, const dou
   for (int lv = f.nlevels - 1; lv >= 0; --lv) {
     const int tw0 = f.level_w_host[lv], ntw = f.level_w_host[lv + 1] - tw0;
     prof::begin(s, DMC_KERNEL_CHOL_BWD_SOLVE);
-    const int ns = part ? bwd_split(ntw, cb) : 1;
-    hipLaunchKernelGGL(k_bwd_gemm<64>, dim3(ntw, cb, ns), blk, 0, s, f, tw0, ncols, Y, X, z, ns,
-                       part);
-    if (ns > 1)
-      hipLaunchKernelGGL(k_bwd_reduce, dim3(ntw, cb, 4), blk, 0, s, f, tw0, ntw, ncols, ns, part, X,
-                         z);
+    if (f.level_maxw_host[lv] <= 32) {
+      // every supernode of the level is at most 32 wide (the dissection's
+      // leaves and the lowest separators): 64-row tiles would be half padding
+      hipLaunchKernelGGL(k_bwd_gemm<32>, dim3(2 * ntw, cb32, 1), blk, 0, s, f, tw0, ncols, Y, X,
+                         z, 1, (double*)nullptr);
+    } else {
+      const int ns = part ? bwd_split(ntw, cb) : 1;
+      hipLaunchKernelGGL(k_bwd_gemm<64>, dim3(ntw, cb, ns), blk, 0, s, f, tw0, ncols, Y, X, z, ns,
+                         part);
+      if (ns > 1)
+        hipLaunchKernelGGL(k_bwd_reduce, dim3(ntw, cb, 4), blk, 0, s, f, tw0, ntw, ncols, ns, part,
+                           X, z);
+    }
     prof::end(s, DMC_KERNEL_CHOL_BWD_SOLVE);
   }
 }

@@ -176,21 +176,25 @@ k_rhs(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
 
 // ---- conjugate gradients ----------------------------------------------------
 
+// x = 0, r = b (b may be r itself: the right-hand side is built in place),
+// p = M^-1 r for the diagonal preconditioners (the Cholesky one sets p from
+// its solve); partial b.b and r.z per column.
 __global__ void __launch_bounds__(kBlock)
-k_cg_init(const double* __restrict__ b, const double* __restrict__ dinv, int precond, int n,
-          int ncols, double* __restrict__ x, double* __restrict__ r, double* __restrict__ p,
-          double* __restrict__ part) {
+k_cg_init(const double* b, const double* __restrict__ dinv, int precond, int n, int ncols,
+          double* __restrict__ x, double* r, double* __restrict__ p, double* __restrict__ part) {
   const int j = blockIdx.y * kBlock + threadIdx.x;
   if (j >= ncols) return;
   const int r0 = blockIdx.x * CG_RB, r1 = min(n, r0 + CG_RB);
+  const bool copy_r = r != b;
+  const bool set_p = precond != DMC_PRECOND_CHOLESKY;
   double bb = 0.0, rz = 0.0;
   for (int i = r0; i < r1; ++i) {
     const size_t e = (size_t)i * ncols + j;
     const double bv = b[e];
     const double z = precond == DMC_PRECOND_JACOBI ? dinv[i] * bv : bv;
     x[e] = 0.0;
-    r[e] = bv;
-    p[e] = precond == DMC_PRECOND_CHOLESKY ? 0.0 : z;
+    if (copy_r) r[e] = bv;
+    if (set_p) p[e] = z;
     bb += bv * bv;
     rz += bv * z;
   }
@@ -310,26 +314,22 @@ k_cg_update(int n, int ncols, const double* __restrict__ alpha, const double* __
   if (precond != DMC_PRECOND_CHOLESKY) part[(nrb + blockIdx.x) * ncols + j] = rz;
 }
 
-// partial r.z per column into the second half of `part`
+// partial r.z per column into the second half of `part`; with p given, also
+// p = z (the first search direction)
 __global__ void __launch_bounds__(kBlock)
 k_cg_dot(int n, int ncols, const double* __restrict__ r, const double* __restrict__ z,
-         double* __restrict__ part) {
+         double* __restrict__ p, double* __restrict__ part) {
   const int j = blockIdx.y * kBlock + threadIdx.x;
   if (j >= ncols) return;
   const int r0 = blockIdx.x * CG_RB, r1 = min(n, r0 + CG_RB);
   double rz = 0.0;
   for (int i = r0; i < r1; ++i) {
     const size_t e = (size_t)i * ncols + j;
-    rz = fma(r[e], z[e], rz);
+    const double zv = z[e];
+    rz = fma(r[e], zv, rz);
+    if (p) p[e] = zv;
   }
   part[((size_t)gridDim.x + blockIdx.x) * ncols + j] = rz;
-}
-
-__global__ void __launch_bounds__(kBlock)
-k_copy(size_t count, const double* __restrict__ src, double* __restrict__ dst) {
-  for (size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x; e < count;
-       e += (size_t)gridDim.x * kBlock)
-    dst[e] = src[e];
 }
 
 // relative residual per column from the r.r partials; marks converged columns
@@ -745,11 +745,13 @@ void launch_rhs(hipStream_t s, const MeshDev& m, const uint8_t* records, const S
   prof::end(s, DMC_KERNEL_RHS);
 }
 
-void launch_precond_apply(hipStream_t s, const MeshDev& m, int32_t ncols, const CgBuffers& cb) {
+// z = M^-1 r by the Cholesky factor, the r.z partials and, with p_out, p = z
+void launch_precond_apply(hipStream_t s, const MeshDev& m, int32_t ncols, const CgBuffers& cb,
+                          double* p_out) {
   const int nrb = (int)cg_part_rows(m.n);
   dim3 grid(nrb, (ncols + kBlock - 1) / kBlock);
   launch_chol_solve(s, m.chol, ncols, cb.r, cb.z, cb.W, cb.Y, cb.X, cb.U, cb.S);
-  hipLaunchKernelGGL(k_cg_dot, grid, dim3(kBlock), 0, s, m.n, ncols, cb.r, cb.z, cb.part);
+  hipLaunchKernelGGL(k_cg_dot, grid, dim3(kBlock), 0, s, m.n, ncols, cb.r, cb.z, p_out, cb.part);
 }
 
 void launch_cg_init(hipStream_t s, const MeshDev& m, int32_t ncols, const double* b,
@@ -758,12 +760,7 @@ void launch_cg_init(hipStream_t s, const MeshDev& m, int32_t ncols, const double
   dim3 grid(nrb, (ncols + kBlock - 1) / kBlock);
   hipLaunchKernelGGL(k_cg_init, grid, dim3(kBlock), 0, s, b, m.m_dinv, precond, m.n, ncols, cb.x,
                      cb.r, cb.p, cb.part);
-  if (precond == DMC_PRECOND_CHOLESKY) {
-    launch_precond_apply(s, m, ncols, cb);
-    const size_t count = (size_t)m.n * ncols;
-    hipLaunchKernelGGL(k_copy, dim3(std::min<size_t>(4096, (count + kBlock - 1) / kBlock)),
-                       dim3(kBlock), 0, s, count, (const double*)cb.z, cb.p);
-  }
+  if (precond == DMC_PRECOND_CHOLESKY) launch_precond_apply(s, m, ncols, cb, cb.p);
   hipLaunchKernelGGL(k_cg_init_reduce, dim3((ncols + RED_COLS - 1) / RED_COLS), dim3(kBlock), 0, s,
                      cb.part, nrb, ncols, cb.bnorm2, cb.rz, cb.done, cb.resid);
 }
@@ -827,7 +824,7 @@ void launch_cg_step_b(hipStream_t s, const MeshDev& m, int32_t ncols, const CgBu
   const int nrb = (int)cg_part_rows(m.n);
   dim3 grid(nrb, (ncols + kBlock - 1) / kBlock);
   dim3 cgrid((ncols + RED_COLS - 1) / RED_COLS);
-  if (precond == DMC_PRECOND_CHOLESKY) launch_precond_apply(s, m, ncols, cb);
+  if (precond == DMC_PRECOND_CHOLESKY) launch_precond_apply(s, m, ncols, cb, nullptr);
   hipLaunchKernelGGL(k_cg_beta, cgrid, dim3(kBlock), 0, s, cb.part, nrb, ncols, cb.rz, cb.done,
                      cb.beta);
   hipLaunchKernelGGL(k_cg_pupdate, grid, dim3(kBlock), 0, s, m.n, ncols, cb.beta, m.m_dinv,
