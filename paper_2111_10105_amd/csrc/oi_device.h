@@ -167,6 +167,19 @@ __device__ __forceinline__ void mm_XtZ(OiSmem<TMAX, KMAX>& s, const double* X, c
   __syncthreads();
 }
 
+// 1 / sqrt(d) for a normal d > 0: the hardware estimate refined by two
+// Newton steps r <- r + r (1 - d r^2) / 2 (each roughly squares the relative
+// error), a short dependent chain beside a rounded square root and division.
+__device__ __forceinline__ double rsqrt_f64(double d) {
+  double r = __builtin_amdgcn_rsq(d);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const double e = fma(-d * r, r, 1.0);
+    r = fma(0.5 * e, r, r);
+  }
+  return r;
+}
+
 // One pass of Cholesky QR in registers.  Lane i < KR holds row i of the KR x
 // KR Gram matrix in g (identity rows/columns beyond k), lane t holds row t of
 // the block in x (zero beyond column k and beyond row T).  Column j of the
@@ -183,8 +196,8 @@ __device__ __forceinline__ bool chol_qr_regs(double (&g)[KR], double (&x)[KR], d
     const double d = readlane_f64(g[j], j);
     const bool good = d > thresh;
     ok = ok && good;
-    const double ljj = good ? sqrt(d) : 1.0;
-    const double inv = 1.0 / ljj;
+    const double inv = good ? rsqrt_f64(d) : 1.0;
+    const double ljj = good ? d * inv : 1.0;
     const double lij = lane > j ? g[j] * inv : (lane == j ? ljj : 0.0);
     g[j] = lij;
     const double qj = x[j] * inv;
@@ -213,8 +226,8 @@ __device__ __forceinline__ bool chol_qr_packed(double (&v)[KR], double thresh) {
     const double d = readlane_f64(v[j], 32 + j);
     const bool good = d > thresh;
     ok = ok && good;
-    const double ljj = good ? sqrt(d) : 1.0;
-    const double inv = 1.0 / ljj;
+    const double inv = good ? rsqrt_f64(d) : 1.0;
+    const double ljj = good ? d * inv : 1.0;
     const double own = isG ? (i > j ? v[j] * inv : (i == j ? ljj : 0.0)) : v[j] * inv;
     v[j] = own;
 #pragma unroll
@@ -224,15 +237,19 @@ __device__ __forceinline__ bool chol_qr_packed(double (&v)[KR], double thresh) {
 }
 
 // Gram-Schmidt in place on the block in s.Q (lane t < T works on row t):
-// each column orthogonalised twice against the previous ones, one projection
-// after the other (modified Gram-Schmidt); a column with no component left
-// (below 1e-10 of its norm) is replaced by the identity direction e_m with
-// the largest part outside the span found so far (first such m), then
-// orthogonalised the same way.  Columns k..KMAX-1 are set to zero.  The
-// fallback of `orthonormalise` for exactly rank-deficient blocks: it runs
-// rarely, so its loops stay rolled (short code).
+// each column orthogonalised twice against the previous ones, four at a time
+// (the four projections of a group are taken from the same vector, so their
+// wavefront sums are in flight together; the groups follow one another, as
+// in modified Gram-Schmidt); a column with no component left (below 1e-10 of
+// its norm) is replaced by the identity direction e_m with the largest part
+// outside the span found so far (first such m), then orthogonalised the same
+// way.  Columns k..KMAX-1 are set to zero.  The fallback of `orthonormalise`
+// for numerically rank-deficient blocks; its loops over columns stay rolled
+// (short code).
 template <int TMAX, int KMAX>
 __device__ __forceinline__ void mgs_lds(OiSmem<TMAX, KMAX>& s, int T, int k) {
+  constexpr int G = 4;  // projections per group
+  static_assert(KMAX % G == 0, "column groups must not run past the block");
   const int lane = threadIdx.x;
   const bool row = lane < T;
   double* q = s.Q + (row ? lane : 0) * s.LQ;
@@ -256,13 +273,18 @@ __device__ __forceinline__ void mgs_lds(OiSmem<TMAX, KMAX>& s, int T, int k) {
       }
 #pragma unroll 1
       for (int pass = 0; pass < 2; ++pass) {
-        double ql = row ? q[0] : 0.0;
 #pragma unroll 1
-        for (int l = 0; l < j; ++l) {
-          const double qn = (row && l + 1 < j) ? q[l + 1] : 0.0;  // next column, in flight
-          const double d = block_sum(row ? ql * v : 0.0, nullptr);
-          v = row ? v - d * ql : 0.0;
-          ql = qn;
+        for (int l0 = 0; l0 < j; l0 += G) {
+          double ql[G], d[G];
+#pragma unroll
+          for (int u = 0; u < G; ++u) {
+            const double x = q[l0 + u];  // inside the row (KMAX % G == 0)
+            ql[u] = (row && l0 + u < j) ? x : 0.0;
+            d[u] = ql[u] * v;
+          }
+          wave_sum_n<G>(d);
+#pragma unroll
+          for (int u = 0; u < G; ++u) v = fma(-d[u], ql[u], v);
         }
       }
       nj = sqrt(block_sum(v * v, nullptr));

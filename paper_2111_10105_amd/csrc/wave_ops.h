@@ -59,6 +59,36 @@ __device__ __forceinline__ double wave_reduce(double v, Op op) {
 __device__ __forceinline__ double wave_sum(double v) {
   return wave_reduce(v, [](double a, double b) { return a + b; });
 }
+
+// N independent sums over the wavefront, stage by stage (the N lane moves of
+// a stage are issued together, and the N swizzles share one wait); each sum
+// takes the same steps in the same order as wave_sum, so it has its bits.
+template <int N>
+__device__ __forceinline__ void wave_sum_n(double (&v)[N]) {
+  double t[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) t[i] = dpp_f64<0xB1>(v[i]);
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] += t[i];
+#pragma unroll
+  for (int i = 0; i < N; ++i) t[i] = dpp_f64<0x4E>(v[i]);
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] += t[i];
+#pragma unroll
+  for (int i = 0; i < N; ++i) t[i] = dpp_f64<0x141>(v[i]);
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] += t[i];
+#pragma unroll
+  for (int i = 0; i < N; ++i) t[i] = dpp_f64<kDppRowMirror>(v[i]);
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] += t[i];
+#pragma unroll
+  for (int i = 0; i < N; ++i) t[i] = swap16_f64(v[i]);
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] += t[i];
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] = readlane_f64(v[i], 0) + readlane_f64(v[i], 32);
+}
 __device__ __forceinline__ double wave_min(double v) {
   return wave_reduce(v, [](double a, double b) { return fmin(a, b); });
 }
