@@ -620,7 +620,7 @@ k_group_ref(const uint8_t* __restrict__ records, SeqLayout sl, int nc, int nz, i
   if (m < 1e308 && t < k) bnorm2[col0 + t] = fmax(m, 1e-300) / ((double)k * tol * tol);
 }
 
-constexpr int CP_V = 64;  // vertices per compose block (16 per wavefront)
+constexpr int CP_V = 64;  // vertices per compose block and vertex tile (16 per wavefront)
 
 // frames of window w for 64 vertices, coordinate by coordinate:
 //   X_c^T (T x 16 vertices) = A^_c^T G^T + U~_c Z_c^T,
@@ -632,7 +632,7 @@ constexpr int CP_V = 64;  // vertices per compose block (16 per wavefront)
 // K index) and B[l/16][l%16] (K index, vertex); component r of lane l is
 // D[4r + l/16][l%16], so a store covers 16 consecutive vertices.
 // TTM: 16-frame tiles held (2 for T <= 32, 4 for T <= 64).
-template <typename Real, int TTM>
+template <typename Real, int TTM, int NV>
 __global__ void __launch_bounds__(kBlock)
 k_compose(const uint8_t* __restrict__ records, SeqLayout sl, int n, int nc, int nz, int ncols,
           const double* __restrict__ G, const double* __restrict__ Z,
@@ -643,25 +643,35 @@ k_compose(const uint8_t* __restrict__ records, SeqLayout sl, int n, int nc, int 
   RecordLayout lay;
   window_of(sl, records, w, rec, T, k, t0, lay);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int i = blockIdx.x * CP_V + 16 * wv + lane % 16;  // this lane's vertex (B column)
-  const bool iv = i < n;
+  // this lane's vertices (B columns), one per 16-vertex tile of the wavefront
+  int iv_[NV];
+  bool ok_[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    iv_[v] = (blockIdx.x * 4 + wv) * 16 * NV + 16 * v + lane % 16;
+    ok_[v] = iv_[v] < n;
+  }
   const int kq = lane / 16;  // K index within a step of four
   const int tl = lane % 16;  // frame within a 16-frame tile (A row)
   const int tt_n = (T + 15) / 16;
   const int z0 = zoff(sl, w);
   const int db = lay.dict_bits;
   const bool raw64 = lay.precision == DMC_FP64;
-  d4 acc[3][TTM];
+  d4 acc[3][TTM][NV];
 #pragma unroll
   for (int c = 0; c < 3; ++c)
 #pragma unroll
-    for (int tt = 0; tt < TTM; ++tt) acc[c][tt] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int tt = 0; tt < TTM; ++tt)
+#pragma unroll
+      for (int v = 0; v < NV; ++v) acc[c][tt][v] = d4{0.0, 0.0, 0.0, 0.0};
   // anchor part: K = anchors, four per step
 #pragma unroll 2
   for (int a0 = 0; a0 < nc; a0 += 4) {
     const int a = a0 + kq;
     const bool av = a < nc;
-    const double vb = (iv && av) ? G[(size_t)i * nc + a] : 0.0;
+    double vb[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) vb[v] = (ok_[v] && av) ? G[(size_t)iv_[v] * nc + a] : 0.0;
     const double* ar = Ah + (size_t)(av ? a : 0) * ncols + 3 * t0;
 #pragma unroll
     for (int c = 0; c < 3; ++c)
@@ -670,7 +680,9 @@ k_compose(const uint8_t* __restrict__ records, SeqLayout sl, int n, int nc, int 
         if (tt >= tt_n) continue;
         const int t = 16 * tt + tl;
         const double va = (av && t < T) ? ar[3 * t + c] : 0.0;
-        acc[c][tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(va, vb, acc[c][tt], 0, 0, 0);
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+          acc[c][tt][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(va, vb[v], acc[c][tt][v], 0, 0, 0);
       }
   }
   // subspace part: K = the k coefficients of each coordinate
@@ -679,7 +691,10 @@ k_compose(const uint8_t* __restrict__ records, SeqLayout sl, int n, int nc, int 
     for (int r0 = 0; r0 < k; r0 += 4) {
       const int r = r0 + kq;
       const bool rv = r < k;
-      const double vb = (iv && rv) ? Z[(size_t)i * nz + z0 + c * k + r] : 0.0;
+      double vb[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+        vb[v] = (ok_[v] && rv) ? Z[(size_t)iv_[v] * nz + z0 + c * k + r] : 0.0;
 #pragma unroll
       for (int tt = 0; tt < TTM; ++tt) {
         if (tt >= tt_n) continue;
@@ -691,19 +706,25 @@ k_compose(const uint8_t* __restrict__ records, SeqLayout sl, int n, int nc, int 
                : raw64 ? ((const double*)(rec + lay.off_dict))[d]
                        : (double)((const float*)(rec + lay.off_dict))[d];
         }
-        acc[c][tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(va, vb, acc[c][tt], 0, 0, 0);
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+          acc[c][tt][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(va, vb[v], acc[c][tt][v], 0, 0, 0);
       }
     }
-  if (!iv) return;
 #pragma unroll
-  for (int c = 0; c < 3; ++c)
+  for (int v = 0; v < NV; ++v) {
+    if (!ok_[v]) continue;
 #pragma unroll
-    for (int tt = 0; tt < TTM; ++tt)
+    for (int c = 0; c < 3; ++c)
 #pragma unroll
-      for (int rr = 0; rr < 4; ++rr) {
-        const int t = 16 * tt + 4 * rr + kq;
-        if (tt < tt_n && t < T) out[((size_t)(t0 + t) * n + i) * 3 + c] = (Real)acc[c][tt][rr];
-      }
+      for (int tt = 0; tt < TTM; ++tt)
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+          const int t = 16 * tt + 4 * rr + kq;
+          if (tt < tt_n && t < T)
+            out[((size_t)(t0 + t) * n + iv_[v]) * 3 + c] = (Real)acc[c][tt][v][rr];
+        }
+  }
 }
 
 }  // namespace
@@ -916,16 +937,20 @@ void launch_compose(hipStream_t s, const MeshDev& m, const uint8_t* records, con
                     const double* Z, const double* Ah, int32_t precision, void* frames_out) {
   const int nw = sl.nw_full + (sl.T_tail > 0 ? 1 : 0);
   const int F = sl.nw_full * sl.T + sl.T_tail;
-  dim3 grid((m.n + CP_V - 1) / CP_V, nw);
   const int nz = reduced_cols(sl);
   prof::begin(s, DMC_KERNEL_TO_FRAMES);
+  // T <= 32: two 16-vertex tiles per wavefront, so each anchor-value and
+  // dictionary operand serves two products (the same accumulator count as
+  // T <= 64 with one tile)
   const bool t32 = sl.T <= 32;  // the tail window is never longer
+  const int nv = t32 ? 2 : 1;
+  dim3 grid((m.n + CP_V * nv - 1) / (CP_V * nv), nw);
   if (precision == DMC_FP64) {
-    auto kern = t32 ? k_compose<double, 2> : k_compose<double, 4>;
+    auto kern = t32 ? k_compose<double, 2, 2> : k_compose<double, 4, 1>;
     hipLaunchKernelGGL(kern, grid, dim3(kBlock), 0, s, records, sl, m.n, m.nc, nz, 3 * F, m.G, Z,
                        Ah, (double*)frames_out);
   } else {
-    auto kern = t32 ? k_compose<float, 2> : k_compose<float, 4>;
+    auto kern = t32 ? k_compose<float, 2, 2> : k_compose<float, 4, 1>;
     hipLaunchKernelGGL(kern, grid, dim3(kBlock), 0, s, records, sl, m.n, m.nc, nz, 3 * F, m.G, Z,
                        Ah, (float*)frames_out);
   }
