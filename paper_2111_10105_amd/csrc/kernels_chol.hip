@@ -295,6 +295,8 @@ k_bwd_gemm(CholDev f, int t0, int ncols, const double* __restrict__ Y, double* _
       }
 }
 
+constexpr int kMaxSplit = 8;  // split-K blocks per backward tile at most
+
 // sums the split-K partials of one level in split order (deterministic)
 __global__ void __launch_bounds__(kBlock)
 k_bwd_reduce(CholDev f, int t0, int ntasks, int ncols, int nsplit, const double* __restrict__ part,
@@ -310,9 +312,15 @@ k_bwd_reduce(CholDev f, int t0, int ntasks, int ncols, int nsplit, const double*
     const int lr = blockIdx.z * RQ + e / CTG, c = c0 + e % CTG;
     const int tr = r0 + lr;
     if (tr >= w || c >= ncols) continue;
+    // every partial in flight at once, then added in split order (the
+    // zeros beyond nsplit leave the sum unchanged)
+    double pv[kMaxSplit];
+#pragma unroll
+    for (int q = 0; q < kMaxSplit; ++q)
+      pv[q] = q < nsplit ? part[(((size_t)q * ntasks + blockIdx.x) * RTK + lr) * ncols + c] : 0.0;
     double v = 0.0;
-    for (int q = 0; q < nsplit; ++q)
-      v += part[(((size_t)q * ntasks + blockIdx.x) * RTK + lr) * ncols + c];
+#pragma unroll
+    for (int q = 0; q < kMaxSplit; ++q) v += pv[q];
     X[(size_t)(a + tr) * ncols + c] = v;
     z[(size_t)f.perm[a + tr] * ncols + c] = v;
   }
@@ -322,7 +330,7 @@ k_bwd_reduce(CholDev f, int t0, int ntasks, int ncols, int nsplit, const double*
 int bwd_split(int ntw, int cb) {
   const int blocks = ntw * cb;
   if (blocks >= 512) return 1;
-  return std::min(8, (512 + blocks - 1) / blocks);
+  return std::min(kMaxSplit, (512 + blocks - 1) / blocks);
 }
 
 }  // namespace
