@@ -295,7 +295,7 @@ k_bwd_gemm(CholDev f, int t0, int ncols, const double* __restrict__ Y, double* _
       }
 }
 
-constexpr int kMaxSplit = 8;  // split-K blocks per backward tile at most
+constexpr int kMaxSplit = 16;  // split-K blocks per backward tile at most
 
 // sums the split-K partials of one level in split order (deterministic)
 __global__ void __launch_bounds__(kBlock)
@@ -329,8 +329,8 @@ k_bwd_reduce(CholDev f, int t0, int ntasks, int ncols, int nsplit, const double*
 // split factor of a backward level: enough blocks to occupy the chip
 int bwd_split(int ntw, int cb) {
   const int blocks = ntw * cb;
-  if (blocks >= 512) return 1;
-  return std::min(kMaxSplit, (512 + blocks - 1) / blocks);
+  if (blocks >= 1024) return 1;
+  return std::min(kMaxSplit, (1024 + blocks - 1) / blocks);
 }
 
 }  // namespace
