@@ -433,20 +433,35 @@ k_anchors(const Real* __restrict__ frames, int n, int T, const int32_t* __restri
   }
 }
 
-__global__ void k_header(int32_t* h, int32_t T, int32_t k, int32_t n, int32_t nc, int32_t cb,
-                         int32_t ab, int32_t db, int32_t prec) {
+// The record header (the problem sizes and formats), and zeros in the
+// alignment gaps after the header and after each section, so that every byte
+// of a record is defined.
+__global__ void k_header(uint8_t* rec, RecordLayout l) {
+  int32_t* h = (int32_t*)rec;
   if (threadIdx.x == 0) {
     h[0] = 0x31434d44;  // "DMC1"
-    h[1] = T;
-    h[2] = k;
-    h[3] = n;
-    h[4] = nc;
-    h[5] = cb;
-    h[6] = ab;
-    h[7] = db;
-    h[8] = prec;
+    h[1] = l.T;
+    h[2] = l.k;
+    h[3] = l.n;
+    h[4] = l.nc;
+    h[5] = l.coef_bits;
+    h[6] = l.anchor_bits;
+    h[7] = l.dict_bits;
+    h[8] = l.precision;
     for (int i = 9; i < 16; ++i) h[i] = 0;
   }
+  const size_t dict = (size_t)3 * l.T * l.k * (l.dict_bits > 0 ? 2 : l.real);
+  const size_t codes = (size_t)3 * l.k * l.n * (l.coef_bits > 0 ? 2 : l.real);
+  const size_t anchors = (size_t)3 * l.T * l.nc * (l.anchor_bits > 0 ? 2 : l.real);
+  // (end of a section's data, start of the next section)
+  const size_t gap[6][2] = {{64, l.off_dict},
+                            {l.off_dict + dict, l.off_ranges},
+                            {l.off_ranges + (size_t)3 * l.k * 2 * 4, l.off_codes},
+                            {l.off_codes + codes, l.off_arange},
+                            {l.off_arange + (size_t)3 * 2 * 4, l.off_anchors},
+                            {l.off_anchors + anchors, l.bytes}};
+  for (int g = 0; g < 6; ++g)
+    for (size_t b = gap[g][0] + threadIdx.x; b < gap[g][1]; b += blockDim.x) rec[b] = 0;
 }
 
 }  // namespace
@@ -607,8 +622,7 @@ void launch_anchors(hipStream_t s, const MeshDev& m, const void* frames, int32_t
 }
 
 void launch_write_header(hipStream_t s, uint8_t* rec, const RecordLayout& l) {
-  hipLaunchKernelGGL(k_header, dim3(1), dim3(64), 0, s, (int32_t*)rec, l.T, l.k, l.n, l.nc,
-                     l.coef_bits, l.anchor_bits, l.dict_bits, l.precision);
+  hipLaunchKernelGGL(k_header, dim3(1), dim3(64), 0, s, rec, l);
 }
 
 }  // namespace dmc
