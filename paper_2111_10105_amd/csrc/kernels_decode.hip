@@ -250,17 +250,27 @@ k_cg_init_reduce(const double* __restrict__ part, int nrb, int ncols,
   resid[j] = bb == 0.0 ? 0.0 : 1.0;
 }
 
-// q = M p (CSR of L^T L + I_N^T I_N), partial p.q per column.
+// q = M p (CSR of L^T L + I_N^T I_N), partial p.q per column.  A block
+// takes CG_RB rows and 64 columns (one per lane); its four wavefronts take
+// every fourth row, so each lane has a short chain of rows, and their p.q
+// partials are added in wavefront order (deterministic).  The row's pattern
+// and values are the same for the whole wavefront (scalar loads).
+constexpr int SP_COLS = 64;
+
 __global__ void __launch_bounds__(kBlock)
 k_cg_spmm(const int32_t* __restrict__ mrow, const int32_t* __restrict__ mcol,
           const double* __restrict__ mval, int n, int ncols, const double* __restrict__ p,
           double* __restrict__ q, double* __restrict__ part) {
-  const int j = blockIdx.y * kBlock + threadIdx.x;
-  if (j >= ncols) return;
+  constexpr int NW = kBlock / 64;
+  __shared__ double sh[NW][SP_COLS];
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int j = blockIdx.y * SP_COLS + lane;
+  const bool jv = j < ncols;
+  const double* pj = p + (jv ? j : 0);
   const int r0 = blockIdx.x * CG_RB, r1 = min(n, r0 + CG_RB);
-  const double* pj = p + j;
   double pq = 0.0;
-  for (int i = r0; i < r1; ++i) {
+  for (int i = r0 + wv; i < r1; i += NW) {
     const int e1 = mrow[i + 1];
     int e = mrow[i];
     // four independent partial sums keep several row loads in flight
@@ -273,10 +283,17 @@ k_cg_spmm(const int32_t* __restrict__ mrow, const int32_t* __restrict__ mcol,
     }
     for (; e < e1; ++e) a0 = fma(mval[e], pj[(size_t)mcol[e] * ncols], a0);
     const double acc = (a0 + a1) + (a2 + a3);
-    q[(size_t)i * ncols + j] = acc;
+    if (jv) q[(size_t)i * ncols + j] = acc;
     pq = fma(pj[(size_t)i * ncols], acc, pq);
   }
-  part[(size_t)blockIdx.x * ncols + j] = pq;
+  sh[wv][lane] = pq;
+  __syncthreads();
+  if (threadIdx.x < SP_COLS && jv) {
+    double v = sh[0][lane];
+#pragma unroll
+    for (int u = 1; u < NW; ++u) v += sh[u][lane];
+    part[(size_t)blockIdx.x * ncols + j] = v;
+  }
 }
 
 __global__ void __launch_bounds__(kBlock)
@@ -790,9 +807,10 @@ void launch_cg_step_a(hipStream_t s, const MeshDev& m, int32_t ncols, const CgBu
                       int32_t precond, double tol) {
   const int nrb = (int)cg_part_rows(m.n);
   dim3 grid(nrb, (ncols + kBlock - 1) / kBlock);
+  dim3 sgrid(nrb, (ncols + SP_COLS - 1) / SP_COLS);
   dim3 cgrid((ncols + RED_COLS - 1) / RED_COLS);
   prof::begin(s, DMC_KERNEL_CG_SPMM);
-  hipLaunchKernelGGL(k_cg_spmm, grid, dim3(kBlock), 0, s, m.m_rowptr, m.m_col, m.m_val, m.n,
+  hipLaunchKernelGGL(k_cg_spmm, sgrid, dim3(kBlock), 0, s, m.m_rowptr, m.m_col, m.m_val, m.n,
                      ncols, cb.p, cb.q, cb.part);
   prof::end(s, DMC_KERNEL_CG_SPMM);
   hipLaunchKernelGGL(k_cg_alpha, cgrid, dim3(kBlock), 0, s, cb.part, nrb, ncols, cb.rz, cb.done,
