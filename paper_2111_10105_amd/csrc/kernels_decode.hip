@@ -137,16 +137,21 @@ __global__ void k_anchor_values(const uint8_t* __restrict__ records, SeqLayout s
 // b = L^T B0 + I_N^T Ahat (the anchor term only when Ah is given)
 //   uniform:       (L^T u)_i = u_i - sum_{j in ring(i)} u_j / d_j
 //   combinatorial: (L^T u)_i = d_i u_i - sum_{j in ring(i)} u_j
+// A block takes CG_RB rows and 64 columns (one per lane); its four
+// wavefronts take every fourth row, with the row's pattern in scalar loads.
+constexpr int RHS_COLS = 64;
+
 __global__ void __launch_bounds__(kBlock)
 k_rhs(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
       const double* __restrict__ w, int uniform, const int32_t* __restrict__ slot, int n,
       int ncols, const double* __restrict__ B0, const double* __restrict__ Ah,
       double* __restrict__ b) {
-  const int j = blockIdx.y * kBlock + threadIdx.x;
+  const int j = blockIdx.y * RHS_COLS + (threadIdx.x & 63);
   if (j >= ncols) return;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int r0 = blockIdx.x * CG_RB, r1 = min(n, r0 + CG_RB);
   const double* Bj = B0 + j;
-  for (int i = r0; i < r1; ++i) {
+  for (int i = r0 + wv; i < r1; i += kBlock / 64) {
     const double ui = Bj[(size_t)i * ncols];
     const int e1 = rowptr[i + 1];
     int e = rowptr[i];
@@ -776,7 +781,7 @@ void launch_rhs(hipStream_t s, const MeshDev& m, const uint8_t* records, const S
   else
     hipLaunchKernelGGL(k_anchor_values<float>, dim3((tot + kBlock - 1) / kBlock), dim3(kBlock), 0,
                        s, records, sl, m.nc, ncols, Ah);
-  dim3 grid(cg_part_rows(m.n), (ncols + kBlock - 1) / kBlock);
+  dim3 grid(cg_part_rows(m.n), (ncols + RHS_COLS - 1) / RHS_COLS);
   prof::begin(s, DMC_KERNEL_RHS);
   hipLaunchKernelGGL(k_rhs, grid, dim3(kBlock), 0, s, m.rowptr, m.col, m.w64,
                      m.laplacian == DMC_LAP_UNIFORM ? 1 : 0, m.slot, m.n, ncols, B0, Ah, b);
@@ -901,7 +906,7 @@ void launch_coef_rows(hipStream_t s, const MeshDev& m, const uint8_t* records,
 }
 
 void launch_rhs_reduced(hipStream_t s, const MeshDev& m, int32_t nz, const double* Yd, double* b) {
-  dim3 grid(cg_part_rows(m.n), (nz + kBlock - 1) / kBlock);
+  dim3 grid(cg_part_rows(m.n), (nz + RHS_COLS - 1) / RHS_COLS);
   prof::begin(s, DMC_KERNEL_RHS);
   hipLaunchKernelGGL(k_rhs, grid, dim3(kBlock), 0, s, m.rowptr, m.col, m.w64,
                      m.laplacian == DMC_LAP_UNIFORM ? 1 : 0, m.slot, m.n, nz, Yd,
