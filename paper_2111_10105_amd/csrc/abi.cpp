@@ -438,16 +438,54 @@ dmc_status decode_all(dmc_ctx ctx, const dmc::MeshDev& m, const uint8_t* records
   decode_enqueue_setup(s, m, records, sl, p, d, cb, ws);
   st = check_launch("decode setup kernels");
   if (st != DMC_OK) return st;
+  int32_t* h_done = (int32_t*)ctx->pinned;
   double* h_res = (double*)((uint8_t*)ctx->pinned + dmc::align_up((size_t)ncols * 4));
   int32_t it = 0;
   bool all_done = false;
-  st = cg_iterate(ctx, m, ncols, cb, p.precond, p.cg_tol, p.cg_max_iters, &it, &all_done);
-  if (st != DMC_OK) return st;
-  decode_enqueue_finish(s, m, records, sl, p, d, cb, Ah, frames_out);
-  st = check_launch("frames");
-  if (st != DMC_OK) return st;
-  HIP_TRY(hipMemcpyAsync(h_res, cb.resid, (size_t)ncols * 8, hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
+  if (chol && p.cg_max_iters >= 1) {
+    // The Cholesky preconditioner converges in one iteration, so the frames
+    // are formed right after it and the host reads the convergence flags
+    // once, at the end; columns that have not converged get more iterations
+    // and the frames are formed again.
+    auto read_flags = [&]() -> dmc_status {
+      HIP_TRY(hipMemcpyAsync(h_done, cb.done, (size_t)ncols * 4, hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipMemcpyAsync(h_res, cb.resid, (size_t)ncols * 8, hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      all_done = true;
+      for (int j = 0; j < ncols; ++j) all_done = all_done && h_done[j];
+      return DMC_OK;
+    };
+    dmc::launch_cg_step_a(s, m, ncols, cb, p.precond, p.cg_tol);
+    it = 1;
+    decode_enqueue_finish(s, m, records, sl, p, d, cb, Ah, frames_out);
+    st = check_launch("cg kernels and frames");
+    if (st != DMC_OK) return st;
+    st = read_flags();
+    if (st != DMC_OK) return st;
+    if (!all_done && it < p.cg_max_iters) {
+      while (!all_done && it < p.cg_max_iters) {
+        dmc::launch_cg_step_b(s, m, ncols, cb, p.precond);
+        dmc::launch_cg_step_a(s, m, ncols, cb, p.precond, p.cg_tol);
+        ++it;
+        st = check_launch("cg kernels");
+        if (st != DMC_OK) return st;
+        st = read_flags();
+        if (st != DMC_OK) return st;
+      }
+      decode_enqueue_finish(s, m, records, sl, p, d, cb, Ah, frames_out);
+      st = check_launch("frames");
+      if (st != DMC_OK) return st;
+      HIP_TRY(hipStreamSynchronize(s));
+    }
+  } else {
+    st = cg_iterate(ctx, m, ncols, cb, p.precond, p.cg_tol, p.cg_max_iters, &it, &all_done);
+    if (st != DMC_OK) return st;
+    decode_enqueue_finish(s, m, records, sl, p, d, cb, Ah, frames_out);
+    st = check_launch("frames");
+    if (st != DMC_OK) return st;
+    HIP_TRY(hipMemcpyAsync(h_res, cb.resid, (size_t)ncols * 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  }
   double rmax = 0.0;
   for (int j = 0; j < ncols; ++j) rmax = std::max(rmax, h_res[j]);
   if (iters_out) *iters_out = it;
