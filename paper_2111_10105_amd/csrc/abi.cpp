@@ -497,8 +497,11 @@ dmc_status decode_all(dmc_ctx ctx, const dmc::MeshDev& m, const uint8_t* records
 }
 
 // Everything dmc_mesh_create computes on the host: adjacency (Eq. 2),
-// validation, the normal matrix of Eq. (12) and its Cholesky factor.
-constexpr int32_t kNdLeaf = 32;
+// validation, the normal matrix of Eq. (12) and its Cholesky factor.  Parts
+// of at most kNdLeaf vertices end the nested dissection: larger leaves mean
+// fewer tree levels (each level is a few dependent launches of the solve)
+// for somewhat more operator entries in the dense leaf blocks.
+constexpr int32_t kNdLeaf = 128;
 
 dmc_status build_mesh_host(int32_t n, int32_t n_tris, const int32_t* tris, int32_t n_anchors,
                            const int32_t* anchors, int32_t laplacian, dmc::HostCsr& C,
