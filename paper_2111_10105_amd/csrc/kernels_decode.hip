@@ -654,6 +654,33 @@ constexpr int CP_V = 64;  // vertices per compose block and vertex tile (16 per 
 // K index) and B[l/16][l%16] (K index, vertex); component r of lane l is
 // D[4r + l/16][l%16], so a store covers 16 consecutive vertices.
 // TTM: 16-frame tiles held (2 for T <= 32, 4 for T <= 64).
+// The compose products in the output's type: float64 frames on the FP64
+// matrix cores; float32 frames on the FP32 ones (v_mfma_f32_16x16x4f32, the
+// same operand layout, twice the rate; the products' rounding, ~1e-7
+// relative, is that of the float32 output itself).
+typedef float cf4 __attribute__((ext_vector_type(4)));
+template <typename Real>
+struct ComposeMfma;
+// Component r of lane l holds result row row(r, l / 16), column l % 16: the
+// FP64 instruction interleaves the rows (4 r + l / 16), the FP32 one gives
+// each group of 16 lanes four consecutive rows (4 (l / 16) + r).
+template <>
+struct ComposeMfma<double> {
+  using Acc = d4;
+  __device__ static Acc step(double a, double b, Acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static int row(int r, int q) { return 4 * r + q; }
+};
+template <>
+struct ComposeMfma<float> {
+  using Acc = cf4;
+  __device__ static Acc step(double a, double b, Acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32((float)a, (float)b, c, 0, 0, 0);
+  }
+  __device__ static int row(int r, int q) { return 4 * q + r; }
+};
+
 template <typename Real, int TTM, int NV>
 __global__ void __launch_bounds__(kBlock)
 k_compose(const uint8_t* __restrict__ records, SeqLayout sl, int n, int nc, int nz, int ncols,
@@ -679,13 +706,14 @@ k_compose(const uint8_t* __restrict__ records, SeqLayout sl, int n, int nc, int 
   const int z0 = zoff(sl, w);
   const int db = lay.dict_bits;
   const bool raw64 = lay.precision == DMC_FP64;
-  d4 acc[3][TTM][NV];
+  using Acc = typename ComposeMfma<Real>::Acc;
+  Acc acc[3][TTM][NV];
 #pragma unroll
   for (int c = 0; c < 3; ++c)
 #pragma unroll
     for (int tt = 0; tt < TTM; ++tt)
 #pragma unroll
-      for (int v = 0; v < NV; ++v) acc[c][tt][v] = d4{0.0, 0.0, 0.0, 0.0};
+      for (int v = 0; v < NV; ++v) acc[c][tt][v] = Acc{0, 0, 0, 0};
   // anchor part: K = anchors, four per step
 #pragma unroll 2
   for (int a0 = 0; a0 < nc; a0 += 4) {
@@ -704,7 +732,7 @@ k_compose(const uint8_t* __restrict__ records, SeqLayout sl, int n, int nc, int 
         const double va = (av && t < T) ? ar[3 * t + c] : 0.0;
 #pragma unroll
         for (int v = 0; v < NV; ++v)
-          acc[c][tt][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(va, vb[v], acc[c][tt][v], 0, 0, 0);
+          acc[c][tt][v] = ComposeMfma<Real>::step(va, vb[v], acc[c][tt][v]);
       }
   }
   // subspace part: K = the k coefficients of each coordinate
@@ -730,7 +758,7 @@ k_compose(const uint8_t* __restrict__ records, SeqLayout sl, int n, int nc, int 
         }
 #pragma unroll
         for (int v = 0; v < NV; ++v)
-          acc[c][tt][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(va, vb[v], acc[c][tt][v], 0, 0, 0);
+          acc[c][tt][v] = ComposeMfma<Real>::step(va, vb[v], acc[c][tt][v]);
       }
     }
 #pragma unroll
@@ -742,7 +770,7 @@ k_compose(const uint8_t* __restrict__ records, SeqLayout sl, int n, int nc, int 
       for (int tt = 0; tt < TTM; ++tt)
 #pragma unroll
         for (int rr = 0; rr < 4; ++rr) {
-          const int t = 16 * tt + 4 * rr + kq;
+          const int t = 16 * tt + ComposeMfma<Real>::row(rr, kq);
           if (tt < tt_n && t < T)
             out[((size_t)(t0 + t) * n + iv_[v]) * 3 + c] = (Real)acc[c][tt][v][rr];
         }
