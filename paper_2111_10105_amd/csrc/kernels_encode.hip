@@ -11,50 +11,69 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f16v __attribute__((ext_vector_type(16)));
 
 // ---------------------------------------------------------------------------
-// Delta coordinates: one thread per (vertex, coordinate), frames in a loop so
-// the CSR row is read once per frame group.  Adjacent lanes read adjacent
-// xyz-interleaved values; neighbour rows are gathered through the caches.
+// Delta coordinates: one thread per vertex, frames in a loop so the CSR row is
+// read once per frame group.  Each ring member's xyz is one 12-byte (float32)
+// or 24-byte (float64) load: a wavefront's gather instruction serves three
+// coordinates, and the kernel is bound by the number of such instructions
+// the texture addressers process, not by HBM bytes.
 // uniform:       delta_i = v_i - (1/d_i) sum_{j in ring(i)} v_j    (Eq. 3)
 // combinatorial: delta_i = d_i v_i - sum_{j in ring(i)} v_j         (Eq. 1, 4)
 // The stencil is evaluated in float64 for both storage types: delta is a small
 // difference of nearly equal coordinates, and float32 arithmetic would leave an
-// absolute error of the size of one ulp of the coordinates in it.  The kernel
-// is bound by memory traffic, so this costs nothing measurable.
+// absolute error of the size of one ulp of the coordinates in it.  Each
+// coordinate's ring sum is taken in ring order.
 // ---------------------------------------------------------------------------
 constexpr int DMAX = 8;  // ring members held in registers by k_delta
+
+template <typename Real>
+struct Xyz {
+  Real x, y, z;
+};
 
 template <typename Real>
 __global__ void __launch_bounds__(kBlock)
 k_delta(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
         const double* __restrict__ w, int uniform, int n, int F, int fpb,
         const Real* __restrict__ in, Real* __restrict__ out) {
-  const int g = blockIdx.x * kBlock + threadIdx.x;
-  if (g >= 3 * n) return;
-  const int i = g / 3, c = g - 3 * i;
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
   const int e0 = rowptr[i], e1 = rowptr[i + 1];
   const int deg = e1 - e0;
   const double wi = w[i];
   const int t0 = blockIdx.y * fpb;
   const int t1 = min(F, t0 + fpb);
   const size_t fs = (size_t)3 * n;
-  // the first DMAX ring members' offsets stay in registers, so the loads of
-  // a frame are all issued at once (a longer ring reads the rest in a loop)
-  int off[DMAX];
+  // the first DMAX ring members stay in registers, so the loads of a frame
+  // are all issued at once (a longer ring reads the rest in a loop)
+  int nb[DMAX];
 #pragma unroll
-  for (int d = 0; d < DMAX; ++d) off[d] = d < deg ? 3 * col[e0 + d] + c : g;
+  for (int d = 0; d < DMAX; ++d) nb[d] = d < deg ? col[e0 + d] : i;
 #pragma unroll 2
   for (int t = t0; t < t1; ++t) {
-    const Real* fr = in + (size_t)t * fs;
-    double v[DMAX];
+    const Xyz<Real>* fr = (const Xyz<Real>*)(in + (size_t)t * fs);
+    Xyz<Real> v[DMAX];
 #pragma unroll
-    for (int d = 0; d < DMAX; ++d) v[d] = (double)fr[off[d]];
-    double sum = 0.0;
+    for (int d = 0; d < DMAX; ++d) v[d] = fr[nb[d]];
+    double sx = 0.0, sy = 0.0, sz = 0.0;
 #pragma unroll
     for (int d = 0; d < DMAX; ++d)
-      if (d < deg) sum += v[d];
-    for (int e = e0 + DMAX; e < e1; ++e) sum += (double)fr[3 * col[e] + c];
-    const double x = (double)fr[g];
-    out[(size_t)t * fs + g] = (Real)(uniform ? x - wi * sum : wi * x - sum);
+      if (d < deg) {
+        sx += (double)v[d].x;
+        sy += (double)v[d].y;
+        sz += (double)v[d].z;
+      }
+    for (int e = e0 + DMAX; e < e1; ++e) {
+      const Xyz<Real> u = fr[col[e]];
+      sx += (double)u.x;
+      sy += (double)u.y;
+      sz += (double)u.z;
+    }
+    const Xyz<Real> own = fr[i];
+    Xyz<Real> o;
+    o.x = (Real)(uniform ? (double)own.x - wi * sx : wi * (double)own.x - sx);
+    o.y = (Real)(uniform ? (double)own.y - wi * sy : wi * (double)own.y - sy);
+    o.z = (Real)(uniform ? (double)own.z - wi * sz : wi * (double)own.z - sz);
+    ((Xyz<Real>*)(out + (size_t)t * fs))[i] = o;
   }
 }
 
@@ -475,7 +494,7 @@ int autocorr_blocks(int n, int nw) {
 void launch_delta(hipStream_t s, const MeshDev& m, const void* in, void* out, int32_t F,
                   int32_t precision, int fpb) {
   if (fpb < 1) fpb = 8;
-  dim3 grid((3 * m.n + kBlock - 1) / kBlock, (F + fpb - 1) / fpb);
+  dim3 grid((m.n + kBlock - 1) / kBlock, (F + fpb - 1) / fpb);
   const int uni = m.laplacian == DMC_LAP_UNIFORM;
   prof::begin(s, DMC_KERNEL_DELTA);
   if (precision == DMC_FP64)
