@@ -189,8 +189,10 @@ dmc_status dmc_host_normal_solve(int32_t n_verts, int32_t n_tris, const int32_t*
  *   codes       [3][k][n]  uint16 codes of Eq. (10), or raw values
  *   anchor rng  [3][2]     float32 (lo, hi) per coordinate     (anchor_bits > 0)
  *   anchors     [3][T][n_c] uint16 codes, or raw values
- * Raw values are float64 (DMC_FP64) or float32.  A record is self-contained
- * given the mesh (connectivity and N are side information shared with the
+ * Raw values are float64 (DMC_FP64) or float32.  The bytes between a
+ * section's data and the next 256-byte boundary are written as zeros, so
+ * every byte of a record is defined.  A record is self-contained given the
+ * mesh (connectivity and N are side information shared with the
  * decoder, as in Sec. III). */
 size_t dmc_window_code_bytes(int32_t n, int32_t T, int32_t n_anchors,
                              const dmc_params* params);

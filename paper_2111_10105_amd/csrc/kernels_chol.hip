@@ -112,8 +112,9 @@ __device__ inline int tile_task(int t0, int& half) {
 }
 
 // forward: [Y_s; U_s] rows r0..r0+RT-1 = B_s W_s (K = columns of B_s; rows of the
-// diagonal block only need the lower triangle of inv(L_ss)).  Two LDS stages:
-// the global loads of chunk j+1 are in flight while chunk j is multiplied.
+// diagonal block only need the lower triangle of inv(L_ss)).  The global
+// loads of chunk j+1 are in flight (in registers) while chunk j is multiplied
+// out of the LDS stage (kStages).
 template <int RT>
 __global__ void __launch_bounds__(kBlock)
 k_fwd_gemm(CholDev f, int t0, int ncols, const double* __restrict__ W, double* __restrict__ Y,
@@ -194,7 +195,8 @@ k_fwd_gemm(CholDev f, int t0, int ncols, const double* __restrict__ W, double* _
 }
 
 // backward: X_s rows r0..r0+RT-1 = B_s^T [Y_s; -X_(R_s below the diagonal block)]
-// (K = rows of B_s from r0 on: inv(L_ss) is lower triangular), two LDS stages.
+// (K = rows of B_s from r0 on: inv(L_ss) is lower triangular), staged as in
+// the forward kernel.
 // With nsplit > 1 block z takes a share of the K chunks and writes its
 // partial tile to `part` (summed by k_bwd_reduce); launched with RT = 64.
 template <int RT>
