@@ -345,7 +345,7 @@ dmc::CgBuffers decode_buffers(uint8_t* ws, const DecodeLayout& d, int32_t ncols,
 // residual and whether every column converged.
 void decode_enqueue_setup(hipStream_t s, const dmc::MeshDev& m, const uint8_t* records,
                           const dmc::SeqLayout& sl, const dmc_params& p, const DecodePlan& d,
-                          const dmc::CgBuffers& cb, uint8_t* ws) {
+                          const dmc::CgBuffers& cb, uint8_t* ws, bool zero_x) {
   double* Ah = (double*)(ws + d.lay.o_Ah);
   if (d.reduced) {
     dmc::launch_coef_rows(s, m, records, sl, cb.q);
@@ -355,7 +355,7 @@ void decode_enqueue_setup(hipStream_t s, const dmc::MeshDev& m, const uint8_t* r
     dmc::launch_back_project(s, m, records, sl, nullptr, cb.q);
     dmc::launch_rhs(s, m, records, sl, cb.q, cb.r);
   }
-  dmc::launch_cg_init(s, m, d.ncols, cb.r, cb, p.precond);
+  dmc::launch_cg_init(s, m, d.ncols, cb.r, cb, p.precond, zero_x);
   // the test on the reduced columns bounds every frame's full-system residual
   // (r still holds b here)
   if (d.reduced)
@@ -378,9 +378,9 @@ void decode_enqueue_fixed(hipStream_t s, const dmc::MeshDev& m, const uint8_t* r
   const bool chol = p.precond == DMC_PRECOND_CHOLESKY;
   const dmc::CgBuffers cb = decode_buffers(ws, d.lay, d.ncols, chol);
   double* Ah = (double*)(ws + d.lay.o_Ah);
-  decode_enqueue_setup(s, m, records, sl, p, d, cb, ws);
+  decode_enqueue_setup(s, m, records, sl, p, d, cb, ws, iters < 1);
   for (int it = 1; it <= iters; ++it) {
-    dmc::launch_cg_step_a(s, m, d.ncols, cb, p.precond, p.cg_tol);
+    dmc::launch_cg_step_a(s, m, d.ncols, cb, p.precond, p.cg_tol, it == 1);
     if (it < iters) dmc::launch_cg_step_b(s, m, d.ncols, cb, p.precond);
   }
   dmc::launch_cg_summary(s, cb, d.ncols, summary);
@@ -401,7 +401,7 @@ dmc_status cg_iterate(dmc_ctx ctx, const dmc::MeshDev& m, int32_t ncols,
   int it = 0;
   bool all_done = false;
   while (it < max_iters) {
-    dmc::launch_cg_step_a(s, m, ncols, cb, precond, tol);
+    dmc::launch_cg_step_a(s, m, ncols, cb, precond, tol, it == 0);
     ++it;
     if (it % check_every == 0 || it == max_iters) {
       st = check_launch("cg kernels");
@@ -435,7 +435,7 @@ dmc_status decode_all(dmc_ctx ctx, const dmc::MeshDev& m, const uint8_t* records
   const dmc::CgBuffers cb = decode_buffers(ws, d.lay, ncols, chol);
   double* Ah = (double*)(ws + d.lay.o_Ah);
 
-  decode_enqueue_setup(s, m, records, sl, p, d, cb, ws);
+  decode_enqueue_setup(s, m, records, sl, p, d, cb, ws, p.cg_max_iters < 1);
   st = check_launch("decode setup kernels");
   if (st != DMC_OK) return st;
   int32_t* h_done = (int32_t*)ctx->pinned;
@@ -455,7 +455,7 @@ dmc_status decode_all(dmc_ctx ctx, const dmc::MeshDev& m, const uint8_t* records
       for (int j = 0; j < ncols; ++j) all_done = all_done && h_done[j];
       return DMC_OK;
     };
-    dmc::launch_cg_step_a(s, m, ncols, cb, p.precond, p.cg_tol);
+    dmc::launch_cg_step_a(s, m, ncols, cb, p.precond, p.cg_tol, true);
     it = 1;
     decode_enqueue_finish(s, m, records, sl, p, d, cb, Ah, frames_out);
     st = check_launch("cg kernels and frames");
@@ -465,7 +465,7 @@ dmc_status decode_all(dmc_ctx ctx, const dmc::MeshDev& m, const uint8_t* records
     if (!all_done && it < p.cg_max_iters) {
       while (!all_done && it < p.cg_max_iters) {
         dmc::launch_cg_step_b(s, m, ncols, cb, p.precond);
-        dmc::launch_cg_step_a(s, m, ncols, cb, p.precond, p.cg_tol);
+        dmc::launch_cg_step_a(s, m, ncols, cb, p.precond, p.cg_tol, false);
         ++it;
         st = check_launch("cg kernels");
         if (st != DMC_OK) return st;
@@ -613,7 +613,7 @@ dmc_status build_anchor_response(dmc_ctx ctx, dmc_mesh m) {
   const dmc::CgBuffers cb = decode_buffers(ws, dl, nc, true);
   hipStream_t s = ctx->stream;
   dmc::launch_anchor_unit_rhs(s, dv, cb.r);
-  dmc::launch_cg_init(s, dv, nc, cb.r, cb, DMC_PRECOND_CHOLESKY);
+  dmc::launch_cg_init(s, dv, nc, cb.r, cb, DMC_PRECOND_CHOLESKY, kAnchorResponseIters < 1);
   st = check_launch("anchor response setup");
   if (st != DMC_OK) return st;
   int32_t it = 0;

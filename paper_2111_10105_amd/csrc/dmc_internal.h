@@ -212,12 +212,15 @@ struct CgBuffers {
   double* resid;     // [ncols]
 };
 size_t cg_part_rows(int32_t n);
+// zero_x: set x = 0 (needed only when no iteration will run: the first
+// step_a, with first set, writes x = alpha p)
 void launch_cg_init(hipStream_t s, const MeshDev& m, int32_t ncols, const double* b,
-                    const CgBuffers& cb, int32_t precond);
+                    const CgBuffers& cb, int32_t precond, bool zero_x);
 // one iteration = step_a (q = M p, alpha, x and r updates, residual check)
-// then, unless every column has converged, step_b (preconditioner, beta, p)
+// then, unless every column has converged, step_b (preconditioner, beta, p);
+// first: the first iteration after launch_cg_init (x taken as zero)
 void launch_cg_step_a(hipStream_t s, const MeshDev& m, int32_t ncols, const CgBuffers& cb,
-                      int32_t precond, double tol);
+                      int32_t precond, double tol, bool first);
 void launch_cg_step_b(hipStream_t s, const MeshDev& m, int32_t ncols, const CgBuffers& cb,
                       int32_t precond);
 // summary of a solve on the device: out[0] = max relative residual, out[1] =

@@ -181,12 +181,14 @@ k_rhs(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
 
 // ---- conjugate gradients ----------------------------------------------------
 
-// x = 0, r = b (b may be r itself: the right-hand side is built in place),
-// p = M^-1 r for the diagonal preconditioners (the Cholesky one sets p from
-// its solve); partial b.b and r.z per column.
+// x = 0 (only with zero_x: the first update writes x = alpha p), r = b (b may
+// be r itself: the right-hand side is built in place), p = M^-1 r for the
+// diagonal preconditioners (the Cholesky one sets p from its solve); partial
+// b.b and r.z per column.
 __global__ void __launch_bounds__(kBlock)
-k_cg_init(const double* b, const double* __restrict__ dinv, int precond, int n, int ncols,
-          double* __restrict__ x, double* r, double* __restrict__ p, double* __restrict__ part) {
+k_cg_init(const double* b, const double* __restrict__ dinv, int precond, int zero_x, int n,
+          int ncols, double* __restrict__ x, double* r, double* __restrict__ p,
+          double* __restrict__ part) {
   const int j = blockIdx.y * kBlock + threadIdx.x;
   if (j >= ncols) return;
   const int r0 = blockIdx.x * CG_RB, r1 = min(n, r0 + CG_RB);
@@ -197,7 +199,7 @@ k_cg_init(const double* b, const double* __restrict__ dinv, int precond, int n, 
     const size_t e = (size_t)i * ncols + j;
     const double bv = b[e];
     const double z = precond == DMC_PRECOND_JACOBI ? dinv[i] * bv : bv;
-    x[e] = 0.0;
+    if (zero_x) x[e] = 0.0;
     if (copy_r) r[e] = bv;
     if (set_p) p[e] = z;
     bb += bv * bv;
@@ -314,7 +316,7 @@ k_cg_alpha(const double* __restrict__ part, int nrb, int ncols,
 
 __global__ void __launch_bounds__(kBlock)
 k_cg_update(int n, int ncols, const double* __restrict__ alpha, const double* __restrict__ dinv,
-            int precond, double* __restrict__ x, double* __restrict__ r,
+            int precond, int first, double* __restrict__ x, double* __restrict__ r,
             const double* __restrict__ p, const double* __restrict__ q, double* __restrict__ part) {
   const int j = blockIdx.y * kBlock + threadIdx.x;
   if (j >= ncols) return;
@@ -323,7 +325,8 @@ k_cg_update(int n, int ncols, const double* __restrict__ alpha, const double* __
   double rr = 0.0, rz = 0.0;
   for (int i = r0; i < r1; ++i) {
     const size_t e = (size_t)i * ncols + j;
-    x[e] = fma(a, p[e], x[e]);
+    // from x = 0 the first update is alpha p (fma(a, p, 0) = a p exactly)
+    x[e] = first ? a * p[e] : fma(a, p[e], x[e]);
     const double rv = fma(-a, q[e], r[e]);
     r[e] = rv;
     const double z = precond == DMC_PRECOND_JACOBI ? dinv[i] * rv : rv;
@@ -826,18 +829,18 @@ void launch_precond_apply(hipStream_t s, const MeshDev& m, int32_t ncols, const 
 }
 
 void launch_cg_init(hipStream_t s, const MeshDev& m, int32_t ncols, const double* b,
-                    const CgBuffers& cb, int32_t precond) {
+                    const CgBuffers& cb, int32_t precond, bool zero_x) {
   const int nrb = (int)cg_part_rows(m.n);
   dim3 grid(nrb, (ncols + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL(k_cg_init, grid, dim3(kBlock), 0, s, b, m.m_dinv, precond, m.n, ncols, cb.x,
-                     cb.r, cb.p, cb.part);
+  hipLaunchKernelGGL(k_cg_init, grid, dim3(kBlock), 0, s, b, m.m_dinv, precond, zero_x ? 1 : 0,
+                     m.n, ncols, cb.x, cb.r, cb.p, cb.part);
   if (precond == DMC_PRECOND_CHOLESKY) launch_precond_apply(s, m, ncols, cb, cb.p);
   hipLaunchKernelGGL(k_cg_init_reduce, dim3((ncols + RED_COLS - 1) / RED_COLS), dim3(kBlock), 0, s,
                      cb.part, nrb, ncols, cb.bnorm2, cb.rz, cb.done, cb.resid);
 }
 
 void launch_cg_step_a(hipStream_t s, const MeshDev& m, int32_t ncols, const CgBuffers& cb,
-                      int32_t precond, double tol) {
+                      int32_t precond, double tol, bool first) {
   const int nrb = (int)cg_part_rows(m.n);
   dim3 grid(nrb, (ncols + kBlock - 1) / kBlock);
   dim3 sgrid(nrb, (ncols + SP_COLS - 1) / SP_COLS);
@@ -850,7 +853,7 @@ void launch_cg_step_a(hipStream_t s, const MeshDev& m, int32_t ncols, const CgBu
                      cb.alpha);
   prof::begin(s, DMC_KERNEL_CG_UPDATE);
   hipLaunchKernelGGL(k_cg_update, grid, dim3(kBlock), 0, s, m.n, ncols, cb.alpha, m.m_dinv,
-                     precond, cb.x, cb.r, cb.p, cb.q, cb.part);
+                     precond, first ? 1 : 0, cb.x, cb.r, cb.p, cb.q, cb.part);
   prof::end(s, DMC_KERNEL_CG_UPDATE);
   hipLaunchKernelGGL(k_cg_resid, cgrid, dim3(kBlock), 0, s, cb.part, nrb, ncols, cb.bnorm2,
                      cb.done, cb.resid, tol);
