@@ -819,13 +819,17 @@ void launch_rhs(hipStream_t s, const MeshDev& m, const uint8_t* records, const S
   prof::end(s, DMC_KERNEL_RHS);
 }
 
-// z = M^-1 r by the Cholesky factor, the r.z partials and, with p_out, p = z
+// z = M^-1 r by the Cholesky factor and the r.z partials; with p_out the
+// solve writes straight into p_out (the first search direction p = z; z
+// itself is rewritten by every later application before it is read)
 void launch_precond_apply(hipStream_t s, const MeshDev& m, int32_t ncols, const CgBuffers& cb,
                           double* p_out) {
   const int nrb = (int)cg_part_rows(m.n);
   dim3 grid(nrb, (ncols + kBlock - 1) / kBlock);
-  launch_chol_solve(s, m.chol, ncols, cb.r, cb.z, cb.W, cb.Y, cb.X, cb.U, cb.S);
-  hipLaunchKernelGGL(k_cg_dot, grid, dim3(kBlock), 0, s, m.n, ncols, cb.r, cb.z, p_out, cb.part);
+  double* z = p_out ? p_out : cb.z;
+  launch_chol_solve(s, m.chol, ncols, cb.r, z, cb.W, cb.Y, cb.X, cb.U, cb.S);
+  hipLaunchKernelGGL(k_cg_dot, grid, dim3(kBlock), 0, s, m.n, ncols, cb.r, z, (double*)nullptr,
+                     cb.part);
 }
 
 void launch_cg_init(hipStream_t s, const MeshDev& m, int32_t ncols, const double* b,
