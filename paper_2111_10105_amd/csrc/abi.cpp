@@ -347,15 +347,18 @@ void decode_enqueue_setup(hipStream_t s, const dmc::MeshDev& m, const uint8_t* r
                           const dmc::SeqLayout& sl, const dmc_params& p, const DecodePlan& d,
                           const dmc::CgBuffers& cb, uint8_t* ws, bool zero_x) {
   double* Ah = (double*)(ws + d.lay.o_Ah);
+  // the right-hand side kernel also forms the b.b partials the Cholesky
+  // start needs (the init kernel then has nothing left to do)
+  double* bb = p.precond == DMC_PRECOND_CHOLESKY ? cb.part : nullptr;
   if (d.reduced) {
     dmc::launch_coef_rows(s, m, records, sl, cb.q);
-    dmc::launch_rhs_reduced(s, m, d.ncols, cb.q, cb.r);
+    dmc::launch_rhs_reduced(s, m, d.ncols, cb.q, cb.r, bb);
     dmc::launch_anchor_values(s, m, records, sl, Ah);
   } else {
     dmc::launch_back_project(s, m, records, sl, nullptr, cb.q);
-    dmc::launch_rhs(s, m, records, sl, cb.q, cb.r);
+    dmc::launch_rhs(s, m, records, sl, cb.q, cb.r, bb);
   }
-  dmc::launch_cg_init(s, m, d.ncols, cb.r, cb, p.precond, zero_x);
+  dmc::launch_cg_init(s, m, d.ncols, cb.r, cb, p.precond, zero_x, bb != nullptr);
   // the test on the reduced columns bounds every frame's full-system residual
   // (r still holds b here)
   if (d.reduced)

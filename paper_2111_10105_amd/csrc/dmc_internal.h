@@ -178,8 +178,10 @@ struct SeqLayout {
 };
 void launch_back_project(hipStream_t s, const MeshDev& m, const uint8_t* records,
                          const SeqLayout& sl, const double* u_tilde_or_null, double* B0);
+// bb (optional): per-block partial b.b per column (the first half of the CG
+// partials, [cg_part_rows(n)][ncols])
 void launch_rhs(hipStream_t s, const MeshDev& m, const uint8_t* records, const SeqLayout& sl,
-                const double* B0, double* b);
+                const double* B0, double* b, double* bb);
 // Temporal-subspace decode (X_wc = Z_wc U~_wc^T + G A^_wc, Eq. 12 by linearity):
 // columns of the reduced system (3k per window), dequantised coefficients
 // Yd [n][nz], its right-hand side L^T Yd (no anchor term), the dense anchor
@@ -188,7 +190,8 @@ void launch_rhs(hipStream_t s, const MeshDev& m, const uint8_t* records, const S
 int32_t reduced_cols(const SeqLayout& sl);
 void launch_coef_rows(hipStream_t s, const MeshDev& m, const uint8_t* records,
                       const SeqLayout& sl, double* Yd);
-void launch_rhs_reduced(hipStream_t s, const MeshDev& m, int32_t nz, const double* Yd, double* b);
+void launch_rhs_reduced(hipStream_t s, const MeshDev& m, int32_t nz, const double* Yd, double* b,
+                        double* bb);
 void launch_anchor_values(hipStream_t s, const MeshDev& m, const uint8_t* records,
                           const SeqLayout& sl, double* Ah);
 void launch_anchor_unit_rhs(hipStream_t s, const MeshDev& m, double* b);
@@ -214,8 +217,9 @@ struct CgBuffers {
 size_t cg_part_rows(int32_t n);
 // zero_x: set x = 0 (needed only when no iteration will run: the first
 // step_a, with first set, writes x = alpha p)
+// bb_done: the right-hand side's b.b partials are already in cb.part
 void launch_cg_init(hipStream_t s, const MeshDev& m, int32_t ncols, const double* b,
-                    const CgBuffers& cb, int32_t precond, bool zero_x);
+                    const CgBuffers& cb, int32_t precond, bool zero_x, bool bb_done = false);
 // one iteration = step_a (q = M p, alpha, x and r updates, residual check)
 // then, unless every column has converged, step_b (preconditioner, beta, p);
 // first: the first iteration after launch_cg_init (x taken as zero)

@@ -139,19 +139,26 @@ __global__ void k_anchor_values(const uint8_t* __restrict__ records, SeqLayout s
 //   combinatorial: (L^T u)_i = d_i u_i - sum_{j in ring(i)} u_j
 // A block takes CG_RB rows and 64 columns (one per lane); its four
 // wavefronts take every fourth row, with the row's pattern in scalar loads.
+// With bb given, also the block's partial b.b per column (the four
+// wavefronts' sums added in wavefront order), the first half of the CG
+// partials.
 constexpr int RHS_COLS = 64;
 
 __global__ void __launch_bounds__(kBlock)
 k_rhs(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
       const double* __restrict__ w, int uniform, const int32_t* __restrict__ slot, int n,
       int ncols, const double* __restrict__ B0, const double* __restrict__ Ah,
-      double* __restrict__ b) {
-  const int j = blockIdx.y * RHS_COLS + (threadIdx.x & 63);
-  if (j >= ncols) return;
+      double* __restrict__ b, double* __restrict__ bb) {
+  constexpr int NW = kBlock / 64;
+  __shared__ double sh[NW][RHS_COLS];
+  const int lane = threadIdx.x & 63;
+  const int j = blockIdx.y * RHS_COLS + lane;
+  const bool jv = j < ncols;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int r0 = blockIdx.x * CG_RB, r1 = min(n, r0 + CG_RB);
-  const double* Bj = B0 + j;
-  for (int i = r0 + wv; i < r1; i += kBlock / 64) {
+  const double* Bj = B0 + (jv ? j : 0);
+  double b2 = 0.0;
+  for (int i = r0 + wv; i < r1; i += NW) {
     const double ui = Bj[(size_t)i * ncols];
     const int e1 = rowptr[i + 1];
     int e = rowptr[i];
@@ -174,8 +181,18 @@ k_rhs(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
     const double s = (s0 + s1) + (s2 + s3);
     double out = uniform ? ui - s : w[i] * ui - s;
     const int sl = slot[i];
-    if (Ah && sl >= 0) out += Ah[(size_t)sl * ncols + j];
-    b[(size_t)i * ncols + j] = out;
+    if (Ah && sl >= 0 && jv) out += Ah[(size_t)sl * ncols + j];
+    if (jv) b[(size_t)i * ncols + j] = out;
+    b2 = fma(out, out, b2);
+  }
+  if (!bb) return;  // uniform over the block
+  sh[wv][lane] = b2;
+  __syncthreads();
+  if (threadIdx.x < RHS_COLS && jv) {
+    double v = sh[0][lane];
+#pragma unroll
+    for (int u = 1; u < NW; ++u) v += sh[u][lane];
+    bb[(size_t)blockIdx.x * ncols + j] = v;
   }
 }
 
@@ -800,7 +817,7 @@ void launch_back_project(hipStream_t s, const MeshDev& m, const uint8_t* records
 }
 
 void launch_rhs(hipStream_t s, const MeshDev& m, const uint8_t* records, const SeqLayout& sl,
-                const double* B0, double* b) {
+                const double* B0, double* b, double* bb) {
   const int F = sl.nw_full * sl.T + sl.T_tail;
   const int ncols = 3 * F;
   // dense anchor values live right after b (the caller sizes b for both)
@@ -815,7 +832,7 @@ void launch_rhs(hipStream_t s, const MeshDev& m, const uint8_t* records, const S
   dim3 grid(cg_part_rows(m.n), (ncols + RHS_COLS - 1) / RHS_COLS);
   prof::begin(s, DMC_KERNEL_RHS);
   hipLaunchKernelGGL(k_rhs, grid, dim3(kBlock), 0, s, m.rowptr, m.col, m.w64,
-                     m.laplacian == DMC_LAP_UNIFORM ? 1 : 0, m.slot, m.n, ncols, B0, Ah, b);
+                     m.laplacian == DMC_LAP_UNIFORM ? 1 : 0, m.slot, m.n, ncols, B0, Ah, b, bb);
   prof::end(s, DMC_KERNEL_RHS);
 }
 
@@ -833,11 +850,16 @@ void launch_precond_apply(hipStream_t s, const MeshDev& m, int32_t ncols, const 
 }
 
 void launch_cg_init(hipStream_t s, const MeshDev& m, int32_t ncols, const double* b,
-                    const CgBuffers& cb, int32_t precond, bool zero_x) {
+                    const CgBuffers& cb, int32_t precond, bool zero_x, bool bb_done) {
   const int nrb = (int)cg_part_rows(m.n);
   dim3 grid(nrb, (ncols + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL(k_cg_init, grid, dim3(kBlock), 0, s, b, m.m_dinv, precond, zero_x ? 1 : 0,
-                     m.n, ncols, cb.x, cb.r, cb.p, cb.part);
+  // with the Cholesky preconditioner, b built in place in r and x left to
+  // the first update, the init kernel's only remaining output is the b.b
+  // partials, which the right-hand-side kernel has already written
+  const bool skip = bb_done && precond == DMC_PRECOND_CHOLESKY && !zero_x && b == cb.r;
+  if (!skip)
+    hipLaunchKernelGGL(k_cg_init, grid, dim3(kBlock), 0, s, b, m.m_dinv, precond, zero_x ? 1 : 0,
+                       m.n, ncols, cb.x, cb.r, cb.p, cb.part);
   if (precond == DMC_PRECOND_CHOLESKY) launch_precond_apply(s, m, ncols, cb, cb.p);
   hipLaunchKernelGGL(k_cg_init_reduce, dim3((ncols + RED_COLS - 1) / RED_COLS), dim3(kBlock), 0, s,
                      cb.part, nrb, ncols, cb.bnorm2, cb.rz, cb.done, cb.resid);
@@ -940,12 +962,13 @@ void launch_coef_rows(hipStream_t s, const MeshDev& m, const uint8_t* records,
   prof::end(s, DMC_KERNEL_BACK_PROJECT);
 }
 
-void launch_rhs_reduced(hipStream_t s, const MeshDev& m, int32_t nz, const double* Yd, double* b) {
+void launch_rhs_reduced(hipStream_t s, const MeshDev& m, int32_t nz, const double* Yd, double* b,
+                        double* bb) {
   dim3 grid(cg_part_rows(m.n), (nz + RHS_COLS - 1) / RHS_COLS);
   prof::begin(s, DMC_KERNEL_RHS);
   hipLaunchKernelGGL(k_rhs, grid, dim3(kBlock), 0, s, m.rowptr, m.col, m.w64,
                      m.laplacian == DMC_LAP_UNIFORM ? 1 : 0, m.slot, m.n, nz, Yd,
-                     (const double*)nullptr, b);
+                     (const double*)nullptr, b, bb);
   prof::end(s, DMC_KERNEL_RHS);
 }
 
