@@ -335,12 +335,18 @@ __global__ void __launch_bounds__(kBlock)
 k_cg_update(int n, int ncols, const double* __restrict__ alpha, const double* __restrict__ dinv,
             int precond, int first, double* __restrict__ x, double* __restrict__ r,
             const double* __restrict__ p, const double* __restrict__ q, double* __restrict__ part) {
-  const int j = blockIdx.y * kBlock + threadIdx.x;
-  if (j >= ncols) return;
-  const int r0 = blockIdx.x * CG_RB, r1 = min(n, r0 + CG_RB);
-  const double a = alpha[j];
+  // 64 columns per block, its four wavefronts on every fourth row; the
+  // partials are added in wavefront order
+  constexpr int NW = kBlock / 64;
+  __shared__ double sh[2][NW][SP_COLS];
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int j = blockIdx.y * SP_COLS + lane;
+  const bool jv = j < ncols;
+  const int r0 = blockIdx.x * CG_RB, r1 = jv ? min(n, r0 + CG_RB) : r0;
+  const double a = jv ? alpha[j] : 0.0;
   double rr = 0.0, rz = 0.0;
-  for (int i = r0; i < r1; ++i) {
+  for (int i = r0 + wv; i < r1; i += NW) {
     const size_t e = (size_t)i * ncols + j;
     // from x = 0 the first update is alpha p (fma(a, p, 0) = a p exactly)
     x[e] = first ? a * p[e] : fma(a, p[e], x[e]);
@@ -350,10 +356,20 @@ k_cg_update(int n, int ncols, const double* __restrict__ alpha, const double* __
     rr = fma(rv, rv, rr);
     rz = fma(rv, z, rz);
   }
+  sh[0][wv][lane] = rr;
+  sh[1][wv][lane] = rz;
+  __syncthreads();
+  if (threadIdx.x >= SP_COLS || !jv) return;
+  double vrr = sh[0][0][lane], vrz = sh[1][0][lane];
+#pragma unroll
+  for (int u = 1; u < NW; ++u) {
+    vrr += sh[0][u][lane];
+    vrz += sh[1][u][lane];
+  }
   const size_t nrb = gridDim.x;
-  part[(size_t)blockIdx.x * ncols + j] = rr;
+  part[(size_t)blockIdx.x * ncols + j] = vrr;
   // with the Cholesky preconditioner r.z comes from k_cg_dot after the solve
-  if (precond != DMC_PRECOND_CHOLESKY) part[(nrb + blockIdx.x) * ncols + j] = rz;
+  if (precond != DMC_PRECOND_CHOLESKY) part[(nrb + blockIdx.x) * ncols + j] = vrz;
 }
 
 // partial r.z per column into the second half of `part`; with p given, also
@@ -361,17 +377,29 @@ k_cg_update(int n, int ncols, const double* __restrict__ alpha, const double* __
 __global__ void __launch_bounds__(kBlock)
 k_cg_dot(int n, int ncols, const double* __restrict__ r, const double* __restrict__ z,
          double* __restrict__ p, double* __restrict__ part) {
-  const int j = blockIdx.y * kBlock + threadIdx.x;
-  if (j >= ncols) return;
-  const int r0 = blockIdx.x * CG_RB, r1 = min(n, r0 + CG_RB);
+  // 64 columns per block, its four wavefronts on every fourth row; the
+  // partials are added in wavefront order
+  constexpr int NW = kBlock / 64;
+  __shared__ double sh[NW][SP_COLS];
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int j = blockIdx.y * SP_COLS + lane;
+  const bool jv = j < ncols;
+  const int r0 = blockIdx.x * CG_RB, r1 = jv ? min(n, r0 + CG_RB) : r0;
   double rz = 0.0;
-  for (int i = r0; i < r1; ++i) {
+  for (int i = r0 + wv; i < r1; i += NW) {
     const size_t e = (size_t)i * ncols + j;
     const double zv = z[e];
     rz = fma(r[e], zv, rz);
     if (p) p[e] = zv;
   }
-  part[((size_t)gridDim.x + blockIdx.x) * ncols + j] = rz;
+  sh[wv][lane] = rz;
+  __syncthreads();
+  if (threadIdx.x >= SP_COLS || !jv) return;
+  double v = sh[0][lane];
+#pragma unroll
+  for (int u = 1; u < NW; ++u) v += sh[u][lane];
+  part[((size_t)gridDim.x + blockIdx.x) * ncols + j] = v;
 }
 
 // relative residual per column from the r.r partials; marks converged columns
@@ -842,7 +870,7 @@ void launch_rhs(hipStream_t s, const MeshDev& m, const uint8_t* records, const S
 void launch_precond_apply(hipStream_t s, const MeshDev& m, int32_t ncols, const CgBuffers& cb,
                           double* p_out) {
   const int nrb = (int)cg_part_rows(m.n);
-  dim3 grid(nrb, (ncols + kBlock - 1) / kBlock);
+  dim3 grid(nrb, (ncols + SP_COLS - 1) / SP_COLS);
   double* z = p_out ? p_out : cb.z;
   launch_chol_solve(s, m.chol, ncols, cb.r, z, cb.W, cb.Y, cb.X, cb.U, cb.S);
   hipLaunchKernelGGL(k_cg_dot, grid, dim3(kBlock), 0, s, m.n, ncols, cb.r, z, (double*)nullptr,
@@ -868,7 +896,6 @@ void launch_cg_init(hipStream_t s, const MeshDev& m, int32_t ncols, const double
 void launch_cg_step_a(hipStream_t s, const MeshDev& m, int32_t ncols, const CgBuffers& cb,
                       int32_t precond, double tol, bool first) {
   const int nrb = (int)cg_part_rows(m.n);
-  dim3 grid(nrb, (ncols + kBlock - 1) / kBlock);
   dim3 sgrid(nrb, (ncols + SP_COLS - 1) / SP_COLS);
   dim3 cgrid((ncols + RED_COLS - 1) / RED_COLS);
   prof::begin(s, DMC_KERNEL_CG_SPMM);
@@ -878,7 +905,7 @@ void launch_cg_step_a(hipStream_t s, const MeshDev& m, int32_t ncols, const CgBu
   hipLaunchKernelGGL(k_cg_alpha, cgrid, dim3(kBlock), 0, s, cb.part, nrb, ncols, cb.rz, cb.done,
                      cb.alpha);
   prof::begin(s, DMC_KERNEL_CG_UPDATE);
-  hipLaunchKernelGGL(k_cg_update, grid, dim3(kBlock), 0, s, m.n, ncols, cb.alpha, m.m_dinv,
+  hipLaunchKernelGGL(k_cg_update, sgrid, dim3(kBlock), 0, s, m.n, ncols, cb.alpha, m.m_dinv,
                      precond, first ? 1 : 0, cb.x, cb.r, cb.p, cb.q, cb.part);
   prof::end(s, DMC_KERNEL_CG_UPDATE);
   hipLaunchKernelGGL(k_cg_resid, cgrid, dim3(kBlock), 0, s, cb.part, nrb, ncols, cb.bnorm2,
