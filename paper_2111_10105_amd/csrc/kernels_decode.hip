@@ -242,6 +242,9 @@ __device__ inline double column_sum(const double* __restrict__ part, int nrb, in
     const double* pj = part + (size_t)half * nrb * ncols + j;
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
     int q = g;
+    // unrolled so that four rounds' loads are in flight together (the
+    // accumulators and their order are unchanged)
+#pragma unroll 4
     for (; q + 3 * RED_GROUPS < nrb; q += 4 * RED_GROUPS) {
       a0 += pj[(size_t)q * ncols];
       a1 += pj[(size_t)(q + RED_GROUPS) * ncols];
