@@ -266,15 +266,20 @@ __global__ void __launch_bounds__(kBlock)
 k_cg_init_reduce(const double* __restrict__ part, int nrb, int ncols,
                  double* __restrict__ bnorm2, double* __restrict__ rz,
                  int32_t* __restrict__ done, double* __restrict__ resid) {
+  // blockIdx.y = 0: the b.b half (and the flags that follow from it);
+  // blockIdx.y = 1: the r.z half, in parallel
   __shared__ double sh[kBlock];
   const int j = blockIdx.x * RED_COLS + threadIdx.x % RED_COLS;
-  const double bb = column_sum(part, nrb, ncols, 0, j, sh);
-  const double z = column_sum(part, nrb, ncols, 1, j, sh);
+  const int half = blockIdx.y;
+  const double v = column_sum(part, nrb, ncols, half, j, sh);
   if (j >= ncols || threadIdx.x >= RED_COLS) return;
-  bnorm2[j] = bb;
-  rz[j] = z;
-  done[j] = bb == 0.0 ? 1 : 0;
-  resid[j] = bb == 0.0 ? 0.0 : 1.0;
+  if (half == 1) {
+    rz[j] = v;
+    return;
+  }
+  bnorm2[j] = v;
+  done[j] = v == 0.0 ? 1 : 0;
+  resid[j] = v == 0.0 ? 0.0 : 1.0;
 }
 
 // q = M p (CSR of L^T L + I_N^T I_N), partial p.q per column.  A block
@@ -892,7 +897,7 @@ void launch_cg_init(hipStream_t s, const MeshDev& m, int32_t ncols, const double
     hipLaunchKernelGGL(k_cg_init, grid, dim3(kBlock), 0, s, b, m.m_dinv, precond, zero_x ? 1 : 0,
                        m.n, ncols, cb.x, cb.r, cb.p, cb.part);
   if (precond == DMC_PRECOND_CHOLESKY) launch_precond_apply(s, m, ncols, cb, cb.p);
-  hipLaunchKernelGGL(k_cg_init_reduce, dim3((ncols + RED_COLS - 1) / RED_COLS), dim3(kBlock), 0, s,
+  hipLaunchKernelGGL(k_cg_init_reduce, dim3((ncols + RED_COLS - 1) / RED_COLS, 2), dim3(kBlock), 0, s,
                      cb.part, nrb, ncols, cb.bnorm2, cb.rz, cb.done, cb.resid);
 }
 
