@@ -555,14 +555,29 @@ k_group_gram(SeqLayout sl, int n, int nz, int kk2, const double* __restrict__ b,
   const int col0 = zoff(sl, w) + c * k;
   const int r0 = chunk * GR_ROWS, r1 = min(n, r0 + GR_ROWS);
   double acc[4] = {0.0, 0.0, 0.0, 0.0};  // entries threadIdx.x + q * kBlock (k*k <= 1024)
+  // the next 64-row tile is loaded into registers (every load in flight)
+  // while the current one is multiplied
+  constexpr int PT = 64 * 32 / kBlock;  // tile elements per thread (k <= 32)
+  double pre[PT];
+  auto load = [&](int i0) {
+    const int nv = min(64, r1 - i0);
+#pragma unroll
+    for (int u = 0; u < PT; ++u) {
+      const int e = threadIdx.x + u * kBlock, v = e / k, r = e % k;
+      pre[u] = (e < 64 * k && v < nv) ? b[(size_t)(i0 + v) * nz + col0 + r] : 0.0;
+    }
+  };
+  if (r0 < r1) load(r0);
   for (int i0 = r0; i0 < r1; i0 += 64) {
     const int nv = min(64, r1 - i0);
     __syncthreads();
-    for (int e = threadIdx.x; e < 64 * k; e += kBlock) {
-      const int v = e / k, r = e % k;
-      rows[v * 33 + r] = v < nv ? b[(size_t)(i0 + v) * nz + col0 + r] : 0.0;
+#pragma unroll
+    for (int u = 0; u < PT; ++u) {
+      const int e = threadIdx.x + u * kBlock;
+      if (e < 64 * k) rows[(e / k) * 33 + e % k] = pre[u];
     }
     __syncthreads();
+    if (i0 + 64 < r1) load(i0 + 64);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int e = threadIdx.x + q * kBlock;
