@@ -19,10 +19,17 @@
  * Conventions (every entry point):
  *  - Pointers named *_dev are device pointers (HIP); *_host are host pointers.
  *    The caller owns every buffer it passes; the library never frees them.
- *  - The context owns its kernels' scratch memory (allocated on first use,
- *    grown when needed, kept until dmc_destroy) and the meshes made with it.
- *  - All device work is ordered on the context's HIP stream.  Calls that fill
- *    a stats struct synchronise that stream; others return after enqueueing.
+ *  - Scratch memory: by default the context allocates its kernels' scratch on
+ *    first use, grows it when a call needs more and keeps it until
+ *    dmc_destroy.  A caller that must not allocate gives a workspace instead
+ *    (dmc_set_workspace, sized by dmc_workspace_bytes): then encode and
+ *    decode calls allocate nothing and fail with DMC_ERR_BUFFER_TOO_SMALL
+ *    when the workspace is short.  The context also owns small stats and
+ *    staging buffers made by dmc_create, and the meshes made with it.
+ *  - All device work is ordered on the context's HIP stream.  The encode,
+ *    decode and sequence calls synchronise it once at their end (they read
+ *    convergence flags there); the single-step and learned-start calls
+ *    return after enqueueing.
  *  - Errors are returned as dmc_status, never by aborting; dmc_last_error()
  *    gives a message for the calling thread.  Arguments are validated on the
  *    host before any launch; on error no output is written.
@@ -99,8 +106,9 @@ typedef struct {
   int32_t coef_bits;     /* bits of Q(.) in Eq. (10): 1..16, 0 = raw values    */
   int32_t anchor_bits;   /* bits per anchor coordinate: 1..16, 0 = raw values  */
   int32_t dict_bits;     /* bits per dictionary entry:  1..16, 0 = raw values  */
-  int32_t precision;     /* DMC_FP64 or DMC_FP32                               */
-  int32_t oi_max_sweeps; /* cap on orthogonal-iteration sweeps per window >= 1 */
+  int32_t precision;     /* DMC_FP64, DMC_FP32 or DMC_BF16                     */
+  int32_t oi_max_sweeps; /* cap on orthogonal-iteration sweeps per window >= 1
+                            (>= 2 for DMC_BF16)                                */
   double oi_tol;         /* stop when ||R Q - Q Q^T R Q||_F <= tol ||R||_F     */
   int32_t cg_max_iters;  /* cap on conjugate-gradient iterations >= 1          */
   int32_t precond;       /* DMC_PRECOND_*                                      */
@@ -108,6 +116,12 @@ typedef struct {
   int32_t init;          /* DMC_INIT_* (0 = DMC_INIT_PREV, Algorithm 1)        */
 } dmc_params;
 
+/* Per-window statistics.  The bit rates follow Eq. (13) read per coordinate:
+ * bits of the window's record part divided by 3 n T (vertices x frames x
+ * coordinates): q the coefficient codes of Eq. (10) with their row ranges,
+ * q_a the anchor codes with their range, q_d the dictionary, q_s = q + q_a +
+ * q_d.  ms_encode and ms_decode are the stream times of the whole call's
+ * encode and decode (the same in every window's entry of a sequence call). */
 typedef struct {
   int32_t T, k;             /* window length and kept rows                     */
   int32_t oi_sweeps[3];     /* sweeps per coordinate (0 = exact start)         */
@@ -115,6 +129,8 @@ typedef struct {
   int32_t chol_shifts[3];   /* CholeskyQR breakdowns repaired by a shift       */
   int32_t cg_iters;         /* decoder iterations (0 if not decoded)           */
   double cg_resid;          /* max over columns of ||r|| / ||b||               */
+  double q, q_a, q_d, q_s;  /* bits per vertex per frame and coordinate        */
+  float ms_encode, ms_decode;
 } dmc_window_stats;
 
 /* ---- context -------------------------------------------------------------
@@ -125,8 +141,21 @@ dmc_status dmc_create(int32_t device, void* hip_stream, dmc_ctx* out);
 void dmc_destroy(dmc_ctx ctx);
 dmc_status dmc_set_stream(dmc_ctx ctx, void* hip_stream);
 const char* dmc_last_error(void);
-/* bytes of scratch the context holds now */
+/* bytes of scratch the context has allocated itself (0 while a caller's
+ * workspace is in use) */
 size_t dmc_scratch_bytes(dmc_ctx ctx);
+/* dmc_workspace_bytes: device bytes of scratch that dmc_compress_sequence
+ * (with or without decoding) and dmc_decode_sequence need for F frames in
+ * windows of T on this mesh with these params; with F = T, the same for
+ * dmc_encode_window and dmc_decode_window.  0 for invalid arguments.
+ * dmc_set_workspace: the context uses dev_ptr [bytes] (device memory owned
+ * by the caller, 256-byte aligned, kept alive and unused by the caller until
+ * it is replaced or the context destroyed) as its scratch and frees any
+ * scratch it allocated itself; NULL and 0 return to library-allocated
+ * scratch.  Synchronises the context's stream.  With a workspace set, a call
+ * that needs more returns DMC_ERR_BUFFER_TOO_SMALL before launching. */
+size_t dmc_workspace_bytes(dmc_mesh mesh, int32_t F, int32_t T, const dmc_params* params);
+dmc_status dmc_set_workspace(dmc_ctx ctx, void* dev_ptr, size_t bytes);
 
 /* ---- mesh (Sec. II) ------------------------------------------------------
  * Builds, once per mesh, the binary adjacency C of Eq. (2) (edges of the
@@ -215,9 +244,12 @@ size_t dmc_sequence_code_bytes(int32_t n, int32_t F, int32_t T, int32_t n_anchor
  *             entry is positive.
  * coef_out_dev optional [3][k][n]: the coefficients Y of Eq. (9) before
  *             quantisation (computed with the dequantised dictionary).
- * stats       optional; filling it synchronises the stream.
- * DMC_ERR_NOT_CONVERGED if some coordinate hit oi_max_sweeps (outputs are
- * still written). */
+ * stats       optional.
+ * Synchronises the stream at its end and returns DMC_ERR_NOT_CONVERGED
+ * (outputs still written) if the orthogonal iterations of some coordinate
+ * ended with a residual above oi_tol, at oi_max_sweeps or where the precision
+ * form's refinement stopped improving; an exact start is not iterated and
+ * never reports it. */
 dmc_status dmc_encode_window(dmc_ctx ctx, dmc_mesh mesh, const void* frames_dev,
                              int32_t T, const dmc_params* params,
                              const void* q_start_dev, void* code_dev,
@@ -226,8 +258,11 @@ dmc_status dmc_encode_window(dmc_ctx ctx, dmc_mesh mesh, const void* frames_dev,
 
 /* ---- decode one window (Eq. 12) ------------------------------------------
  * code_dev: a record written by dmc_encode_window for this mesh and T;
- * frames_out_dev [T][n][3].  DMC_ERR_NOT_CONVERGED if some column did not
- * reach cg_tol within cg_max_iters (the last iterate is still written). */
+ * frames_out_dev [T][n][3].  The record's header is read back first: a
+ * magic, T, k, n, n_c, bit widths or precision that differ from the call's
+ * give DMC_ERR_INVALID_ARG before any kernel runs.  DMC_ERR_NOT_CONVERGED if
+ * some column did not reach cg_tol within cg_max_iters (the last iterate is
+ * still written). */
 dmc_status dmc_decode_window(dmc_ctx ctx, dmc_mesh mesh, const void* code_dev,
                              int32_t T, const dmc_params* params,
                              void* frames_out_dev, dmc_window_stats* stats);
@@ -239,17 +274,22 @@ dmc_status dmc_decode_window(dmc_ctx ctx, dmc_mesh mesh, const void* code_dev,
  * q_start_dev [3][T][k] or exact if NULL; DMC_INIT_RANDOM: q_start_dev
  * [nw][3][T][k] for the nw = F / T full windows; DMC_INIT_SKETCH: Omega
  * [T][k]), writing the records back to back into codes_dev
- * (dmc_sequence_code_bytes bytes).  If
- * frames_out_dev [F][n][3] is not NULL, then decodes every window in one
- * solve over all 3F columns.  per_window: optional array of n_windows stats
- * (synchronises). */
+ * (dmc_sequence_code_bytes bytes).  If frames_out_dev [F][n][3] is not NULL,
+ * then decodes every window in one solve: over the 3k columns L^T Y^^T of
+ * each window when the mesh holds its anchor response and the cost rule of
+ * dmc_mesh_anchor_response picks that form, else over all 3F frame columns.
+ * per_window: optional array of n_windows stats.  Synchronises once at the
+ * end; DMC_ERR_NOT_CONVERGED (outputs still written) if the decoder's
+ * conjugate gradients or some window's orthogonal iterations did not reach
+ * their tolerance (as for dmc_encode_window). */
 dmc_status dmc_compress_sequence(dmc_ctx ctx, dmc_mesh mesh, const void* frames_dev,
                                  int32_t F, int32_t T, const dmc_params* params,
                                  const void* q_start_dev, void* codes_dev,
                                  size_t codes_bytes, void* frames_out_dev,
                                  dmc_window_stats* per_window);
 
-/* decode every record of a sequence written by dmc_compress_sequence */
+/* decode every record of a sequence written by dmc_compress_sequence; the
+ * headers are checked as in dmc_decode_window */
 dmc_status dmc_decode_sequence(dmc_ctx ctx, dmc_mesh mesh, const void* codes_dev,
                                int32_t F, int32_t T, const dmc_params* params,
                                void* frames_out_dev, dmc_window_stats* per_window);

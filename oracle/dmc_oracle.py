@@ -536,7 +536,7 @@ def nmse(X: np.ndarray, Y: np.ndarray) -> float:
 
 
 def bpvf(n: int, F: int, n_anchors: int, window_shapes, bits: int,
-         anchor_bits: int = 16, dict_bits: int = 16) -> dict:
+         anchor_bits: int = 16, dict_bits: int = 16, raw_bits: int = 64) -> dict:
     """Bits per vertex per frame for one coordinate (Eq. 13 and its
     discussion), for what this encoder actually sends:
       q   : coefficient codes, bits * k_w * n per window
@@ -544,13 +544,14 @@ def bpvf(n: int, F: int, n_anchors: int, window_shapes, bits: int,
       q_a : anchor codes, anchor_bits * n_c per frame (+ 2 float32 per window)
       q_d : dictionary, dict_bits * T_w * k_w per window
       q_s : the sum.
-    window_shapes: iterable of (T_w, k_w)."""
+    A part whose bit count is 0 is sent as raw values of raw_bits each and
+    has no range.  window_shapes: iterable of (T_w, k_w)."""
     vf = float(n * F)
     shapes = list(window_shapes)
-    q = sum(bits * kw * n for (_tw, kw) in shapes) / vf
+    q = sum((bits or raw_bits) * kw * n for (_tw, kw) in shapes) / vf
     q_r = sum(64 * kw for (_tw, kw) in shapes) / vf if bits else 0.0
-    q_a = (anchor_bits * n_anchors * F + 64 * len(shapes)) / vf
-    q_d = sum(dict_bits * tw * kw for (tw, kw) in shapes) / vf
+    q_a = ((anchor_bits or raw_bits) * n_anchors * F + (64 * len(shapes) if anchor_bits else 0)) / vf
+    q_d = sum((dict_bits or raw_bits) * tw * kw for (tw, kw) in shapes) / vf
     return {"q": q, "q_r": q_r, "q_a": q_a, "q_d": q_d, "q_s": q + q_r + q_a + q_d}
 
 

@@ -18,10 +18,12 @@ struct dmc_ctx_s {
   hipStream_t stream = nullptr;
   void* scratch = nullptr;
   size_t scratch_bytes = 0;
+  bool scratch_external = false;  // caller's workspace (dmc_set_workspace): never freed or grown
   void* pinned = nullptr;  // host staging for stats and convergence flags
   size_t pinned_bytes = 0;
   void* stats = nullptr;   // per-window device stats (kept apart from scratch)
   size_t stats_bytes = 0;
+  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};  // encode / decode timers of the stats
   std::vector<dmc_mesh_s*> meshes;
   // learned start registered by dmc_learned_start (caller-owned device memory)
   int32_t learned_T = 0, learned_k = 0;
@@ -79,6 +81,10 @@ struct Carve {
 
 dmc_status ensure_scratch(dmc_ctx ctx, size_t bytes) {
   if (bytes <= ctx->scratch_bytes) return DMC_OK;
+  if (ctx->scratch_external)
+    return fail(DMC_ERR_BUFFER_TOO_SMALL, "the workspace holds " +
+                                              std::to_string(ctx->scratch_bytes) + " bytes, the call needs " +
+                                              std::to_string(bytes) + " (dmc_workspace_bytes)");
   if (ctx->scratch) {
     HIP_TRY(hipStreamSynchronize(ctx->stream));
     HIP_TRY(hipFree(ctx->scratch));
@@ -95,8 +101,16 @@ dmc_status ensure_scratch(dmc_ctx ctx, size_t bytes) {
   return DMC_OK;
 }
 
+// The stats and staging buffers are allocated with the context at sizes that
+// cover thousands of windows; they grow only beyond that, and never while the
+// caller's workspace is in use (those calls must not allocate).
+constexpr size_t kStatsBytes = size_t(256) << 10;
+constexpr size_t kPinnedBytes = size_t(1) << 20;
+
 dmc_status ensure_stats(dmc_ctx ctx, size_t bytes) {
   if (bytes <= ctx->stats_bytes) return DMC_OK;
+  if (ctx->scratch_external)
+    return fail(DMC_ERR_BUFFER_TOO_SMALL, "too many windows for the context's stats buffer");
   if (ctx->stats) {
     HIP_TRY(hipStreamSynchronize(ctx->stream));
     HIP_TRY(hipFree(ctx->stats));
@@ -115,7 +129,12 @@ dmc_status ensure_stats(dmc_ctx ctx, size_t bytes) {
 
 dmc_status ensure_pinned(dmc_ctx ctx, size_t bytes) {
   if (bytes <= ctx->pinned_bytes) return DMC_OK;
-  if (ctx->pinned) HIP_TRY(hipHostFree(ctx->pinned));
+  if (ctx->scratch_external)
+    return fail(DMC_ERR_BUFFER_TOO_SMALL, "too many columns for the context's staging buffer");
+  if (ctx->pinned) {
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    HIP_TRY(hipHostFree(ctx->pinned));
+  }
   ctx->pinned = nullptr;
   ctx->pinned_bytes = 0;
   const size_t want = std::max<size_t>(bytes, 1 << 16);
@@ -136,6 +155,10 @@ dmc_status check_params(const dmc_params* p, int32_t T, bool for_decode = false)
     if (p->init < DMC_INIT_PREV || p->init > DMC_INIT_LEARNED)
       return fail(DMC_ERR_INVALID_ARG, "unknown init");
     if (p->oi_max_sweeps < 1) return fail(DMC_ERR_INVALID_ARG, "oi_max_sweeps must be >= 1");
+    // the precision form needs a sweep with bfloat16 products and at least
+    // one full-precision refinement sweep before the Ritz step
+    if (p->precision == DMC_BF16 && p->oi_max_sweeps < 2)
+      return fail(DMC_ERR_INVALID_ARG, "DMC_BF16 needs oi_max_sweeps >= 2");
     if (!(p->oi_tol >= 0.0)) return fail(DMC_ERR_INVALID_ARG, "oi_tol must be >= 0");
   }
   if (p->cg_max_iters < 1) return fail(DMC_ERR_INVALID_ARG, "cg_max_iters must be >= 1");
@@ -147,14 +170,55 @@ dmc_status check_params(const dmc_params* p, int32_t T, bool for_decode = false)
 
 size_t real_size(int32_t precision) { return precision == DMC_FP64 ? 8 : 4; }
 
-void fill_stats(dmc_window_stats* st, const dmc::StatsDev& s, int32_t T, int32_t k) {
-  st->T = T;
-  st->k = k;
+// Bits per vertex per frame and coordinate of one window's record (Eq. 13
+// read per coordinate): q counts the coefficient codes and their row ranges,
+// q_a the anchor codes and their range, q_d the dictionary.
+void record_bpvf(const dmc::RecordLayout& l, double out[4]) {
+  const double vf = 3.0 * l.n * l.T;
+  const double real_bits = 8.0 * l.real;
+  double q = 0.0, qa = 0.0, qd = 0.0;
+  for (int c = 0; c < 3; ++c) {
+    q += l.coef_bits > 0 ? (double)l.coef_bits * l.k * l.n + 64.0 * l.k : real_bits * l.k * l.n;
+    qa += l.anchor_bits > 0 ? (double)l.anchor_bits * l.T * l.nc + 64.0 : real_bits * l.T * l.nc;
+    qd += (l.dict_bits > 0 ? (double)l.dict_bits : real_bits) * l.T * l.k;
+  }
+  out[0] = q / vf;
+  out[1] = qa / vf;
+  out[2] = qd / vf;
+  out[3] = out[0] + out[1] + out[2];
+}
+
+void fill_stats(dmc_window_stats* st, const dmc::StatsDev& s, const dmc::RecordLayout& l) {
+  st->T = l.T;
+  st->k = l.k;
   for (int c = 0; c < 3; ++c) {
     st->oi_sweeps[c] = s.sweeps[c];
     st->oi_resid[c] = s.resid[c];
     st->chol_shifts[c] = s.shifts[c];
   }
+  double b[4];
+  record_bpvf(l, b);
+  st->q = b[0];
+  st->q_a = b[1];
+  st->q_d = b[2];
+  st->q_s = b[3];
+}
+
+// Algorithm 1 did not reach oi_tol for some coordinate of some window (its
+// iterations ran and ended above the tolerance, at the sweep cap or where
+// the precision form's refinement stopped improving); an exact start (no
+// sweeps) is not an iteration.
+bool oi_not_converged(const dmc::StatsDev* s, int32_t nw, double tol) {
+  for (int32_t w = 0; w < nw; ++w)
+    for (int c = 0; c < 3; ++c)
+      if (s[w].sweeps[c] > 0 && !(s[w].resid[c] <= tol)) return true;
+  return false;
+}
+
+float elapsed_ms(hipEvent_t a, hipEvent_t b) {
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return 0.f;
+  return ms;
 }
 
 // Encode nw windows of length T starting at frames (one chain).
@@ -610,9 +674,22 @@ dmc_status build_anchor_response(dmc_ctx ctx, dmc_mesh m) {
   if (nc < 1 || bytes > kAnchorResponseBytes) return DMC_OK;
   if (2.0 * anchor_cost_per_column(dv) > solve_cost_per_column(dv)) return DMC_OK;
   const DecodeLayout dl = decode_layout(dv, nc, true);
-  dmc_status st = ensure_scratch(ctx, dl.total);
-  if (st != DMC_OK) return st;
-  uint8_t* ws = (uint8_t*)ctx->scratch;
+  // mesh set-up solves in a temporary buffer of its own (the context's
+  // scratch may be a caller's workspace sized for encode and decode)
+  uint8_t* ws = nullptr;
+  if (hipMalloc(&ws, dl.total) != hipSuccess) {
+    (void)hipGetLastError();
+    return DMC_OK;  // no anchor response: the decoder uses the direct form
+  }
+  struct Release {
+    uint8_t* p;
+    hipStream_t s;
+    ~Release() {
+      (void)hipStreamSynchronize(s);
+      (void)hipFree(p);
+    }
+  } release{ws, ctx->stream};
+  dmc_status st = DMC_OK;
   const dmc::CgBuffers cb = decode_buffers(ws, dl, nc, true);
   hipStream_t s = ctx->stream;
   dmc::launch_anchor_unit_rhs(s, dv, cb.r);
@@ -663,6 +740,18 @@ dmc_status dmc_create(int32_t device, void* hip_stream, dmc_ctx* out) {
   dmc_ctx c = new dmc_ctx_s();
   c->device = device;
   c->stream = (hipStream_t)hip_stream;
+  // the stats and staging buffers and the timers are made here, so that the
+  // encode and decode calls themselves need no allocation
+  bool ok = hipMalloc(&c->stats, kStatsBytes) == hipSuccess;
+  if (ok) c->stats_bytes = kStatsBytes;
+  ok = ok && hipHostMalloc(&c->pinned, kPinnedBytes, hipHostMallocDefault) == hipSuccess;
+  if (ok) c->pinned_bytes = kPinnedBytes;
+  for (int e = 0; e < 3 && ok; ++e) ok = hipEventCreate(&c->ev[e]) == hipSuccess;
+  if (!ok) {
+    (void)hipGetLastError();
+    dmc_destroy(c);
+    return fail(DMC_ERR_OUT_OF_MEMORY, "cannot allocate the context's stats and staging buffers");
+  }
   *out = c;
   return DMC_OK;
 }
@@ -675,9 +764,11 @@ void dmc_destroy(dmc_ctx ctx) {
     for (void* p : m->allocations) (void)hipFree(p);
     delete m;
   }
-  if (ctx->scratch) (void)hipFree(ctx->scratch);
+  if (ctx->scratch && !ctx->scratch_external) (void)hipFree(ctx->scratch);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   if (ctx->stats) (void)hipFree(ctx->stats);
+  for (hipEvent_t e : ctx->ev)
+    if (e) (void)hipEventDestroy(e);
   delete ctx;
 }
 
@@ -687,7 +778,24 @@ dmc_status dmc_set_stream(dmc_ctx ctx, void* hip_stream) {
   return DMC_OK;
 }
 
-size_t dmc_scratch_bytes(dmc_ctx ctx) { return ctx ? ctx->scratch_bytes : 0; }
+size_t dmc_scratch_bytes(dmc_ctx ctx) {
+  return ctx && !ctx->scratch_external ? ctx->scratch_bytes : 0;
+}
+
+dmc_status dmc_set_workspace(dmc_ctx ctx, void* dev_ptr, size_t bytes) {
+  if (!ctx) return fail(DMC_ERR_INVALID_ARG, "ctx is NULL");
+  if ((dev_ptr == nullptr) != (bytes == 0))
+    return fail(DMC_ERR_INVALID_ARG, "give both a workspace and its size, or neither");
+  if (dev_ptr && (uintptr_t)dev_ptr % dmc::kAlign != 0)
+    return fail(DMC_ERR_INVALID_ARG, "the workspace must be 256-byte aligned");
+  HIP_TRY(hipSetDevice(ctx->device));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  if (ctx->scratch && !ctx->scratch_external) HIP_TRY(hipFree(ctx->scratch));
+  ctx->scratch = dev_ptr;
+  ctx->scratch_bytes = bytes;
+  ctx->scratch_external = dev_ptr != nullptr;
+  return DMC_OK;
+}
 
 dmc_status dmc_mesh_create(dmc_ctx ctx, int32_t n, int32_t n_tris, const int32_t* tris,
                            int32_t n_anchors, const int32_t* anchors, int32_t laplacian,
@@ -860,46 +968,76 @@ size_t dmc_sequence_code_bytes(int32_t n, int32_t F, int32_t T, int32_t n_anchor
   return b;
 }
 
-dmc_status dmc_encode_window(dmc_ctx ctx, dmc_mesh mesh, const void* frames, int32_t T,
-                             const dmc_params* params, const void* q_start, void* code,
-                             void* u_out, void* coef_out, dmc_window_stats* stats) {
+// Scratch of one window's encode: the delta coordinates, then the chain's
+// pieces (autocorrelation partials, R, dictionary, projection), and the
+// window's stats when the caller's array holds them too (stats_off).
+struct WindowScratch {
+  size_t o_delta = 0, o_chain = 0, o_stats = 0, total = 0;
+};
+
+WindowScratch window_scratch(const dmc::MeshDev& m, int32_t T, const dmc_params& p,
+                             bool with_stats) {
+  Carve cv;
+  WindowScratch w;
+  w.o_delta = cv.add((size_t)T * 3 * m.n * real_size(p.precision));
+  w.o_chain = cv.add(chain_scratch_bytes(m.n, T, 1, std::min(p.k, T), p.precision, p.init));
+  if (with_stats) w.o_stats = cv.add(sizeof(dmc::StatsDev));
+  w.total = cv.total();
+  return w;
+}
+
+// dmc_encode_window on a given scratch area and stats slot (checked
+// arguments; ws holds window_scratch(...).total bytes).
+dmc_status encode_window_on(dmc_ctx ctx, const dmc::MeshDev& m, const void* frames, int32_t T,
+                            const dmc_params& p, const void* q_start, void* code, void* u_out,
+                            void* coef_out, dmc_window_stats* stats, uint8_t* ws,
+                            const WindowScratch& wl, dmc::StatsDev* sd) {
+  const dmc::RecordLayout lay = dmc::record_layout(m.n, T, p.k, m.nc, p);
+  void* delta = ws + wl.o_delta;
+  if (stats) HIP_TRY(hipEventRecord(ctx->ev[0], ctx->stream));
+  dmc::launch_delta(ctx->stream, m, frames, delta, T, p.precision);
+  dmc_status st = encode_chain(ctx, m, frames, T, 1, p.k, p, q_start, (uint8_t*)code, lay, u_out,
+                               coef_out, delta, ws + wl.o_chain, sd);
+  if (st != DMC_OK) return st;
+  if (stats) HIP_TRY(hipEventRecord(ctx->ev[1], ctx->stream));
+  // the convergence of the orthogonal iterations is read back at this one
+  // synchronisation point, whether or not stats are requested
+  HIP_TRY(hipMemcpyAsync(ctx->pinned, sd, sizeof(dmc::StatsDev), hipMemcpyDeviceToHost,
+                         ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  const dmc::StatsDev* hs = (const dmc::StatsDev*)ctx->pinned;
+  if (stats) {
+    std::memset(stats, 0, sizeof(*stats));
+    fill_stats(stats, *hs, lay);
+    stats->ms_encode = elapsed_ms(ctx->ev[0], ctx->ev[1]);
+  }
+  if (oi_not_converged(hs, 1, p.oi_tol))
+    return fail(DMC_ERR_NOT_CONVERGED, "orthogonal iterations ended above oi_tol");
+  return DMC_OK;
+}
+
+dmc_status check_encode_window(dmc_ctx ctx, dmc_mesh mesh, const void* frames, int32_t T,
+                               const dmc_params* params, void* code) {
   if (!ctx || !mesh || !frames || !code) return fail(DMC_ERR_INVALID_ARG, "NULL argument");
   dmc_status st = check_params(params, T);
   if (st != DMC_OK) return st;
-  const dmc_params& p = *params;
-  if (p.k > T) return fail(DMC_ERR_INVALID_ARG, "k must not exceed T");
-  const dmc::MeshDev& m = mesh->dev;
-  HIP_TRY(hipSetDevice(ctx->device));
-  const dmc::RecordLayout lay = dmc::record_layout(m.n, T, p.k, m.nc, p);
-  Carve cv;
-  const size_t o_delta = cv.add((size_t)T * 3 * m.n * real_size(p.precision));
-  st = check_learned(ctx, p, T);
+  if (params->k > T) return fail(DMC_ERR_INVALID_ARG, "k must not exceed T");
+  return check_learned(ctx, *params, T);
+}
+
+dmc_status dmc_encode_window(dmc_ctx ctx, dmc_mesh mesh, const void* frames, int32_t T,
+                             const dmc_params* params, const void* q_start, void* code,
+                             void* u_out, void* coef_out, dmc_window_stats* stats) {
+  dmc_status st = check_encode_window(ctx, mesh, frames, T, params, code);
   if (st != DMC_OK) return st;
-  const size_t o_chain = cv.add(chain_scratch_bytes(m.n, T, 1, p.k, p.precision, p.init));
-  st = ensure_scratch(ctx, cv.total());
+  HIP_TRY(hipSetDevice(ctx->device));
+  const WindowScratch wl = window_scratch(mesh->dev, T, *params, false);
+  st = ensure_scratch(ctx, wl.total);
   if (st != DMC_OK) return st;
   st = ensure_stats(ctx, sizeof(dmc::StatsDev));
   if (st != DMC_OK) return st;
-  uint8_t* ws = (uint8_t*)ctx->scratch;
-  void* delta = ws + o_delta;
-  dmc::StatsDev* sd = (dmc::StatsDev*)ctx->stats;
-  dmc::launch_delta(ctx->stream, m, frames, delta, T, p.precision);
-  st = encode_chain(ctx, m, frames, T, 1, p.k, p, q_start, (uint8_t*)code, lay, u_out, coef_out,
-                    delta, ws + o_chain, sd);
-  if (st != DMC_OK) return st;
-  if (stats) {
-    st = ensure_pinned(ctx, sizeof(dmc::StatsDev));
-    if (st != DMC_OK) return st;
-    HIP_TRY(hipMemcpyAsync(ctx->pinned, sd, sizeof(dmc::StatsDev), hipMemcpyDeviceToHost,
-                           ctx->stream));
-    HIP_TRY(hipStreamSynchronize(ctx->stream));
-    std::memset(stats, 0, sizeof(*stats));
-    fill_stats(stats, *(dmc::StatsDev*)ctx->pinned, T, p.k);
-    for (int c = 0; c < 3; ++c)
-      if (q_start && stats->oi_sweeps[c] >= p.oi_max_sweeps && stats->oi_resid[c] > p.oi_tol)
-        return fail(DMC_ERR_NOT_CONVERGED, "orthogonal iterations hit oi_max_sweeps");
-  }
-  return DMC_OK;
+  return encode_window_on(ctx, mesh->dev, frames, T, *params, q_start, code, u_out, coef_out,
+                          stats, (uint8_t*)ctx->scratch, wl, (dmc::StatsDev*)ctx->stats);
 }
 
 static dmc::SeqLayout seq_layout(int32_t n, int32_t F, int32_t T, int32_t nc, const dmc_params& p) {
@@ -914,6 +1052,40 @@ static dmc::SeqLayout seq_layout(int32_t n, int32_t F, int32_t T, int32_t nc, co
   return sl;
 }
 
+// The decoder indexes a record by the sizes and formats of the call, so every
+// window's header (written by k_header) is read back and compared with them
+// before any decode kernel runs.
+dmc_status check_headers(dmc_ctx ctx, const dmc::MeshDev& m, const uint8_t* records,
+                         const dmc::SeqLayout& sl) {
+  const int32_t nw = sl.nw_full + (sl.T_tail ? 1 : 0);
+  dmc_status st = ensure_pinned(ctx, (size_t)nw * 64);
+  if (st != DMC_OK) return st;
+  uint8_t* h = (uint8_t*)ctx->pinned;
+  if (sl.nw_full)
+    HIP_TRY(hipMemcpy2DAsync(h, 64, records, sl.rec_bytes_full, 64, sl.nw_full,
+                             hipMemcpyDeviceToHost, ctx->stream));
+  if (sl.T_tail)
+    HIP_TRY(hipMemcpyAsync(h + (size_t)sl.nw_full * 64,
+                           records + (size_t)sl.nw_full * sl.rec_bytes_full, 64,
+                           hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  for (int32_t w = 0; w < nw; ++w) {
+    const dmc::RecordLayout& l = w < sl.nw_full ? sl.full : sl.tail;
+    int32_t hd[9];
+    std::memcpy(hd, h + (size_t)w * 64, sizeof(hd));
+    const int32_t want[9] = {dmc::kRecordMagic, l.T,         l.k,        m.n,        m.nc,
+                             l.coef_bits,       l.anchor_bits, l.dict_bits, l.precision};
+    static const char* what[9] = {"magic", "T", "k", "n", "n_c", "coef_bits", "anchor_bits",
+                                  "dict_bits", "precision"};
+    for (int f = 0; f < 9; ++f)
+      if (hd[f] != want[f])
+        return fail(DMC_ERR_INVALID_ARG, "record of window " + std::to_string(w) + ": header " +
+                                             what[f] + " = " + std::to_string(hd[f]) +
+                                             ", the call expects " + std::to_string(want[f]));
+  }
+  return DMC_OK;
+}
+
 dmc_status dmc_decode_window(dmc_ctx ctx, dmc_mesh mesh, const void* code, int32_t T,
                              const dmc_params* params, void* frames_out, dmc_window_stats* stats) {
   if (!ctx || !mesh || !code || !frames_out) return fail(DMC_ERR_INVALID_ARG, "NULL argument");
@@ -921,14 +1093,28 @@ dmc_status dmc_decode_window(dmc_ctx ctx, dmc_mesh mesh, const void* code, int32
   if (st != DMC_OK) return st;
   HIP_TRY(hipSetDevice(ctx->device));
   const dmc::SeqLayout sl = seq_layout(mesh->dev.n, T, T, mesh->dev.nc, *params);
+  st = check_headers(ctx, mesh->dev, (const uint8_t*)code, sl);
+  if (st != DMC_OK) return st;
   int32_t iters = 0;
   double res = 0.0;
+  if (stats) HIP_TRY(hipEventRecord(ctx->ev[1], ctx->stream));
   st = decode_all(ctx, mesh->dev, (const uint8_t*)code, sl, *params, frames_out, &iters, &res);
+  if (st != DMC_OK && st != DMC_ERR_NOT_CONVERGED) return st;
   if (stats) {
+    HIP_TRY(hipEventRecord(ctx->ev[2], ctx->stream));
+    HIP_TRY(hipEventSynchronize(ctx->ev[2]));
+    std::memset(stats, 0, sizeof(*stats));
     stats->T = T;
     stats->k = std::min(params->k, T);
+    double b[4];
+    record_bpvf(sl.full, b);
+    stats->q = b[0];
+    stats->q_a = b[1];
+    stats->q_d = b[2];
+    stats->q_s = b[3];
     stats->cg_iters = iters;
     stats->cg_resid = res;
+    stats->ms_decode = elapsed_ms(ctx->ev[1], ctx->ev[2]);
   }
   return st;
 }
@@ -942,17 +1128,54 @@ dmc_status dmc_decode_sequence(dmc_ctx ctx, dmc_mesh mesh, const void* codes, in
   if (st != DMC_OK) return st;
   HIP_TRY(hipSetDevice(ctx->device));
   const dmc::SeqLayout sl = seq_layout(mesh->dev.n, F, T, mesh->dev.nc, *params);
+  st = check_headers(ctx, mesh->dev, (const uint8_t*)codes, sl);
+  if (st != DMC_OK) return st;
   int32_t iters = 0;
   double res = 0.0;
+  if (per_window) HIP_TRY(hipEventRecord(ctx->ev[1], ctx->stream));
   st = decode_all(ctx, mesh->dev, (const uint8_t*)codes, sl, *params, frames_out, &iters, &res);
+  if (st != DMC_OK && st != DMC_ERR_NOT_CONVERGED) return st;
   if (per_window) {
+    HIP_TRY(hipEventRecord(ctx->ev[2], ctx->stream));
+    HIP_TRY(hipEventSynchronize(ctx->ev[2]));
+    const float ms = elapsed_ms(ctx->ev[1], ctx->ev[2]);
     const int nw = sl.nw_full + (sl.T_tail ? 1 : 0);
     for (int w = 0; w < nw; ++w) {
+      const dmc::RecordLayout& l = w < sl.nw_full ? sl.full : sl.tail;
+      std::memset(&per_window[w], 0, sizeof(dmc_window_stats));
+      per_window[w].T = l.T;
+      per_window[w].k = l.k;
+      double b[4];
+      record_bpvf(l, b);
+      per_window[w].q = b[0];
+      per_window[w].q_a = b[1];
+      per_window[w].q_d = b[2];
+      per_window[w].q_s = b[3];
       per_window[w].cg_iters = iters;
       per_window[w].cg_resid = res;
+      per_window[w].ms_decode = ms;
     }
   }
   return st;
+}
+
+// Scratch bytes of the encoder (delta coordinates of every frame, then the
+// chains of full windows and the short last window) and of the decoder (the
+// solve's vectors), for an F-frame sequence; the two never live together.
+size_t encode_scratch_bytes(const dmc::MeshDev& m, const dmc::SeqLayout& sl, const dmc_params& p,
+                            size_t* o_full = nullptr, size_t* o_tail = nullptr) {
+  const int32_t F = sl.nw_full * sl.T + sl.T_tail;
+  Carve cv;
+  cv.add((size_t)F * 3 * m.n * real_size(p.precision));
+  const size_t of = cv.add(sl.nw_full ? chain_scratch_bytes(m.n, sl.T, sl.nw_full, sl.full.k,
+                                                              p.precision, p.init)
+                                      : 0);
+  const size_t ot = cv.add(sl.T_tail ? chain_scratch_bytes(m.n, sl.T_tail, 1, sl.tail.k,
+                                                             p.precision, DMC_INIT_EXACT)
+                                     : 0);
+  if (o_full) *o_full = of;
+  if (o_tail) *o_tail = ot;
+  return cv.total();
 }
 
 dmc_status dmc_compress_sequence(dmc_ctx ctx, dmc_mesh mesh, const void* frames, int32_t F,
@@ -974,27 +1197,29 @@ dmc_status dmc_compress_sequence(dmc_ctx ctx, dmc_mesh mesh, const void* frames,
   HIP_TRY(hipSetDevice(ctx->device));
   const int32_t nw = sl.nw_full + (sl.T_tail ? 1 : 0);
   const int32_t k_full = std::min(p.k, T);
-  Carve cv;
-  const size_t o_delta = cv.add((size_t)F * 3 * m.n * real_size(p.precision));
   if (sl.nw_full) {
     st = check_learned(ctx, p, T);
     if (st != DMC_OK) return st;
   }
   dmc_params p_tail = p;  // a shorter last window starts from its exact eigenvectors
   p_tail.init = DMC_INIT_EXACT;
-  const size_t o_full = cv.add(sl.nw_full ? chain_scratch_bytes(m.n, T, sl.nw_full, k_full,
-                                                                 p.precision, p.init)
-                                          : 0);
-  const size_t o_tail = cv.add(sl.T_tail ? chain_scratch_bytes(m.n, sl.T_tail, 1, sl.tail.k,
-                                                                 p.precision, p_tail.init)
-                                         : 0);
-  st = ensure_scratch(ctx, cv.total());
+  size_t o_full = 0, o_tail = 0;
+  st = ensure_scratch(ctx, encode_scratch_bytes(m, sl, p, &o_full, &o_tail));
   if (st != DMC_OK) return st;
   st = ensure_stats(ctx, sizeof(dmc::StatsDev) * nw);
   if (st != DMC_OK) return st;
+  // the stats are staged in the upper half of the staging buffer, apart from
+  // the decoder's convergence flags in the lower half
+  const size_t stats_at =
+      frames_out ? std::max(kPinnedBytes / 2,
+                            dmc::align_up((size_t)decode_plan(m, sl, p).ncols * 12 + 4096))
+                 : 0;
+  st = ensure_pinned(ctx, stats_at + sizeof(dmc::StatsDev) * nw);
+  if (st != DMC_OK) return st;
   uint8_t* ws = (uint8_t*)ctx->scratch;
-  void* delta = ws + o_delta;
+  void* delta = ws;
   dmc::StatsDev* sd = (dmc::StatsDev*)ctx->stats;
+  if (per_window) HIP_TRY(hipEventRecord(ctx->ev[0], ctx->stream));
   dmc::launch_delta(ctx->stream, m, frames, delta, F, p.precision);
   const size_t rs = real_size(p.precision);
   if (sl.nw_full) {
@@ -1010,6 +1235,12 @@ dmc_status dmc_compress_sequence(dmc_ctx ctx, dmc_mesh mesh, const void* frames,
                       sd + sl.nw_full);
     if (st != DMC_OK) return st;
   }
+  if (per_window) HIP_TRY(hipEventRecord(ctx->ev[1], ctx->stream));
+  // the windows' convergence is staged now and read at the one
+  // synchronisation point at the end
+  uint8_t* staged = (uint8_t*)ctx->pinned + stats_at;
+  HIP_TRY(hipMemcpyAsync(staged, sd, sizeof(dmc::StatsDev) * nw, hipMemcpyDeviceToHost,
+                         ctx->stream));
   int32_t iters = 0;
   double res = 0.0;
   dmc_status dst = DMC_OK;
@@ -1017,22 +1248,36 @@ dmc_status dmc_compress_sequence(dmc_ctx ctx, dmc_mesh mesh, const void* frames,
     dst = decode_all(ctx, m, (const uint8_t*)codes, sl, p, frames_out, &iters, &res);
     if (dst != DMC_OK && dst != DMC_ERR_NOT_CONVERGED) return dst;
   }
+  if (per_window) HIP_TRY(hipEventRecord(ctx->ev[2], ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  std::vector<dmc::StatsDev> hs(nw);
+  std::memcpy(hs.data(), staged, sizeof(dmc::StatsDev) * nw);
   if (per_window) {
-    st = ensure_pinned(ctx, sizeof(dmc::StatsDev) * nw);
-    if (st != DMC_OK) return st;
-    HIP_TRY(hipMemcpyAsync(ctx->pinned, sd, sizeof(dmc::StatsDev) * nw, hipMemcpyDeviceToHost,
-                           ctx->stream));
-    HIP_TRY(hipStreamSynchronize(ctx->stream));
-    const dmc::StatsDev* hs = (const dmc::StatsDev*)ctx->pinned;
+    const float ms_enc = elapsed_ms(ctx->ev[0], ctx->ev[1]);
+    const float ms_dec = frames_out ? elapsed_ms(ctx->ev[1], ctx->ev[2]) : 0.f;
     for (int w = 0; w < nw; ++w) {
       std::memset(&per_window[w], 0, sizeof(dmc_window_stats));
       const bool tail = w >= sl.nw_full;
-      fill_stats(&per_window[w], hs[w], tail ? sl.T_tail : T, tail ? sl.tail.k : k_full);
+      fill_stats(&per_window[w], hs[w], tail ? sl.tail : sl.full);
       per_window[w].cg_iters = iters;
       per_window[w].cg_resid = res;
+      per_window[w].ms_encode = ms_enc;
+      per_window[w].ms_decode = ms_dec;
     }
   }
-  return dst;
+  if (dst != DMC_OK) return dst;
+  if (oi_not_converged(hs.data(), nw, p.oi_tol))
+    return fail(DMC_ERR_NOT_CONVERGED, "orthogonal iterations ended above oi_tol");
+  return DMC_OK;
+}
+
+size_t dmc_workspace_bytes(dmc_mesh mesh, int32_t F, int32_t T, const dmc_params* params) {
+  if (!mesh || !params || F < 1 || T < 1 || T > 64 || params->k < 1) return 0;
+  const dmc::MeshDev& m = mesh->dev;
+  const dmc::SeqLayout sl = seq_layout(m.n, F, T, m.nc, *params);
+  const size_t enc = encode_scratch_bytes(m, sl, *params);
+  const size_t dec = decode_plan(m, sl, *params).lay.total;
+  return std::max(enc, dec);
 }
 
 dmc_status dmc_delta(dmc_ctx ctx, dmc_mesh mesh, const void* frames, int32_t F, int32_t precision,
@@ -1552,13 +1797,16 @@ dmc_status dmc_batch_stats(dmc_batch b, int32_t i, dmc_window_stats* per_window)
   for (int32_t w = 0; w < nw; ++w) {
     std::memset(&per_window[w], 0, sizeof(dmc_window_stats));
     const bool tail = w >= q.sl.nw_full;
-    fill_stats(&per_window[w], hs[w], tail ? q.sl.T_tail : q.T, tail ? q.k_tail : q.k_full);
+    fill_stats(&per_window[w], hs[w], tail ? q.sl.tail : q.sl.full);
     per_window[w].cg_iters = q.out ? q.p.cg_max_iters : 0;
     per_window[w].cg_resid = q.out ? sum[0] : 0.0;
   }
   if (q.out && sum[1] == 0.0)
     return fail(DMC_ERR_NOT_CONVERGED, "sequence " + std::to_string(i) +
                                            ": some column did not reach cg_tol");
+  if (oi_not_converged(hs, nw, q.p.oi_tol))
+    return fail(DMC_ERR_NOT_CONVERGED, "sequence " + std::to_string(i) +
+                                           ": orthogonal iterations ended above oi_tol");
   return DMC_OK;
 }
 

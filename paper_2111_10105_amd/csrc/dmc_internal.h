@@ -18,6 +18,9 @@ constexpr size_t kAlign = 256;
 
 inline size_t align_up(size_t x, size_t a = kAlign) { return (x + a - 1) / a * a; }
 
+// First word of every window record ("DMC1" in memory order).
+constexpr int32_t kRecordMagic = 0x31434d44;
+
 // Byte layout of one window record (see dmc.h).
 struct RecordLayout {
   int32_t T = 0, k = 0, n = 0, nc = 0;

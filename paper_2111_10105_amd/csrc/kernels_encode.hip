@@ -458,7 +458,7 @@ k_anchors(const Real* __restrict__ frames, int n, int T, const int32_t* __restri
 __global__ void k_header(uint8_t* rec, RecordLayout l) {
   int32_t* h = (int32_t*)rec;
   if (threadIdx.x == 0) {
-    h[0] = 0x31434d44;  // "DMC1"
+    h[0] = kRecordMagic;
     h[1] = l.T;
     h[2] = l.k;
     h[3] = l.n;

@@ -25,6 +25,7 @@ PRECOND_NONE, PRECOND_JACOBI, PRECOND_CHOLESKY = 0, 1, 2
 INIT_PREV, INIT_RANDOM, INIT_SKETCH, INIT_EXACT, INIT_LEARNED = 0, 1, 2, 3, 4
 
 EXPORTS = ["dmc_create", "dmc_destroy", "dmc_set_stream", "dmc_last_error", "dmc_scratch_bytes",
+           "dmc_workspace_bytes", "dmc_set_workspace",
            "dmc_mesh_create", "dmc_mesh_destroy", "dmc_mesh_nnz", "dmc_mesh_normal_nnz",
            "dmc_mesh_factor_info", "dmc_mesh_anchor_response", "dmc_host_normal_solve",
            "dmc_window_code_bytes", "dmc_sequence_code_bytes", "dmc_encode_window",
@@ -58,19 +59,26 @@ class WindowStats(ctypes.Structure):
     _fields_ = [("T", ctypes.c_int32), ("k", ctypes.c_int32),
                 ("oi_sweeps", ctypes.c_int32 * 3), ("oi_resid", ctypes.c_double * 3),
                 ("chol_shifts", ctypes.c_int32 * 3), ("cg_iters", ctypes.c_int32),
-                ("cg_resid", ctypes.c_double)]
+                ("cg_resid", ctypes.c_double), ("q", ctypes.c_double), ("q_a", ctypes.c_double),
+                ("q_d", ctypes.c_double), ("q_s", ctypes.c_double),
+                ("ms_encode", ctypes.c_float), ("ms_decode", ctypes.c_float)]
 
     def as_dict(self):
         return {"T": self.T, "k": self.k, "oi_sweeps": list(self.oi_sweeps),
                 "oi_resid": list(self.oi_resid), "chol_shifts": list(self.chol_shifts),
-                "cg_iters": self.cg_iters, "cg_resid": self.cg_resid}
+                "cg_iters": self.cg_iters, "cg_resid": self.cg_resid, "q": self.q,
+                "q_a": self.q_a, "q_d": self.q_d, "q_s": self.q_s,
+                "ms_encode": self.ms_encode, "ms_decode": self.ms_decode}
 
 
 def make_params(k, coef_bits=12, anchor_bits=16, dict_bits=16, precision=FP32,
                 oi_max_sweeps=200, oi_tol=None, cg_max_iters=None, precond=PRECOND_CHOLESKY,
                 cg_tol=None, init=INIT_PREV) -> Params:
     if oi_tol is None:
-        oi_tol = 1e-12
+        # the precision form's bfloat16 covariance fixes the trailing
+        # eigen-directions only to its rounding: without a gap there the
+        # residual stalls near 1e-8, so its default tolerance sits above that
+        oi_tol = 1e-6 if precision == BF16 else 1e-12
     if cg_tol is None:
         cg_tol = 1e-12
     if cg_max_iters is None:
@@ -101,6 +109,8 @@ def lib():
         "dmc_set_stream": (i32, [vp, vp]),
         "dmc_last_error": (ctypes.c_char_p, []),
         "dmc_scratch_bytes": (sz, [vp]),
+        "dmc_workspace_bytes": (sz, [vp, i32, i32, P]),
+        "dmc_set_workspace": (i32, [vp, vp, sz]),
         "dmc_mesh_create": (i32, [vp, i32, i32, vp, i32, vp, i32, ctypes.POINTER(vp)]),
         "dmc_mesh_destroy": (None, [vp]),
         "dmc_mesh_nnz": (i32, [vp]),
@@ -201,6 +211,17 @@ class Context:
     def scratch_bytes(self) -> int:
         return lib().dmc_scratch_bytes(self.h)
 
+    def set_workspace(self, buf):
+        """Use a caller-owned device buffer (a uint8 CUDA tensor, or None to
+        return to library-allocated scratch) as the context's scratch; the
+        context keeps a reference to the tensor."""
+        self.sync_stream()
+        if buf is None:
+            _check(lib().dmc_set_workspace(self.h, None, 0))
+        else:
+            _check(lib().dmc_set_workspace(self.h, _ptr(buf), buf.numel() * buf.element_size()))
+        self._workspace = buf
+
     def close(self):
         if self.h:
             lib().dmc_destroy(self.h)
@@ -268,6 +289,10 @@ def host_normal_solve(n, tris, anchors, B, laplacian: int = LAP_UNIFORM):
                                        B.ctypes.data_as(ctypes.c_void_p),
                                        X.ctypes.data_as(ctypes.c_void_p), info))
     return X, dict(zip(FACTOR_INFO_KEYS, list(info)))
+
+
+def workspace_bytes(mesh: "Mesh", F: int, T: int, params: Params) -> int:
+    return lib().dmc_workspace_bytes(mesh.h, int(F), int(T), ctypes.byref(params))
 
 
 def window_code_bytes(n, T, nc, params: Params) -> int:

@@ -133,3 +133,42 @@ def gaussian_subspace(T: int, k: int, seed: int) -> np.ndarray:
     """
     rng = np.random.default_rng(seed)
     return rng.standard_normal((3, T, k))
+
+
+def gapped_windows(rest, n_frames: int, T: int, k: int, seed: int, gap: float = 4.0,
+                   decay: float = 0.1, scale: float = 0.1, dtype=np.float64):
+    """Frames whose every window of T frames has, per coordinate, an
+    autocorrelation with a clean eigenvalue gap after its k-th eigenvalue.
+
+    The T x n matrix of a window's coordinate c is A_c = U (S V^T + sqrt(T)
+    e_0 r_c^T), with r_c the rest pose's coordinate c, U (T x T) a seeded
+    orthonormal block whose first column is constant (1/sqrt(T)), V (n x T)
+    seeded orthonormal columns orthogonal to r_c, and S = diag(s) scaled by
+    scale sqrt(n): s_j = 2^(-decay j) for j < k and
+    s_(k-1) 2^(-decay (j - k + 1)) / gap beyond.  Then A_c A_c^T =
+    U diag(s_0^2 + T |r_c|^2, s_1^2, ...) U^T exactly: frame t is the rest
+    pose plus a deformation, lambda_k / lambda_(k+1) is about gap^2, and the
+    trailing eigenvalues stay far above round-off.  A shorter last window uses
+    its own length T_w and k_w = min(k, T_w)."""
+    rng = np.random.default_rng(seed)
+    n = rest.shape[0]
+    out = np.empty((n_frames, n, 3), dtype=np.float64)
+    for s0 in range(0, n_frames, T):
+        tw = min(T, n_frames - s0)
+        kw = min(k, tw)
+        j = np.arange(tw, dtype=np.float64)
+        s = np.where(j < kw, 2.0 ** (-decay * j),
+                     2.0 ** (-decay * (kw - 1)) * 2.0 ** (-decay * (j - kw + 1)) / gap)
+        s = s * scale * np.sqrt(n)
+        for c in range(3):
+            G = rng.standard_normal((tw, tw))
+            G[:, 0] = 1.0
+            U, _ = np.linalg.qr(G)
+            U[:, 0] = np.abs(U[:, 0])  # the constant column, positive
+            r = rest[:, c].astype(np.float64)
+            B = rng.standard_normal((n, tw + 1))
+            B[:, 0] = r
+            Qb, _ = np.linalg.qr(B)
+            V = Qb[:, 1:]  # orthonormal, orthogonal to r
+            out[s0:s0 + tw, :, c] = (U * s) @ V.T + np.outer(U[:, 0] * np.sqrt(tw), r)
+    return out.astype(dtype)

@@ -81,12 +81,14 @@ def small_torus(a: int = 24, b: int = 20, frames: int = 40, T: int = 16, k: int 
 
 
 def batched(count: int = 64, n_range=(2000, 60000), f_range=(16, 128), ks=(8, 16, 32),
-            seed: int = 4000, bones: int = 6):
+            seed: int = 4000, bones: int = 6, only=None):
     """Independent sequences of uneven size for the batched form: mesh type
     torus or icosphere (the icosphere level whose size is nearest the drawn
     n, from levels 2..6), torus a = round(sqrt(n)), b = round(n / a); frame
     count uniform in f_range, k drawn from ks, window T = 2k, 1% anchors (at
-    least 4), RBF skinning seeded per sequence, float32."""
+    least 4), RBF skinning seeded per sequence, float32.  `only`: indices of
+    the sequences to build (the draws of the others are still made, so each
+    sequence is the same as in the full batch)."""
     rng = np.random.default_rng(seed)
     out = []
     levels = {L: 10 * 4 ** L + 2 for L in range(2, 7)}
@@ -103,6 +105,8 @@ def batched(count: int = 64, n_range=(2000, 60000), f_range=(16, 128), ks=(8, 16
             name = f"icosphere{L}"
         F = int(rng.integers(f_range[0], f_range[1] + 1))
         k = int(ks[int(rng.integers(0, len(ks)))])
+        if only is not None and i not in only:
+            continue
         fr = animate.rbf_skinning(v, F, bones, seed=seed + 1 + i, dtype=np.float32)
         nc = max(4, int(round(0.01 * v.shape[0])))
         anc = animate.choose_anchors(v.shape[0], nc, seed=seed + 1001 + i)

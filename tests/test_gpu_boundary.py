@@ -1,0 +1,176 @@
+"""The C ABI's contract beyond the arithmetic: convergence reporting of the
+orthogonal iterations (Algorithm 1) without stats, the record header check
+before decoding, the caller-provided workspace, and the per-window bit rates
+of Eq. (13) against the oracle's accounting.  Needs an MI355X."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2111_10105_amd import dmc
+from synth import animate, configs, meshes
+
+from gpu_helpers import to_dev
+
+pytestmark = pytest.mark.gpu
+
+INVALID_ARG, NOT_CONVERGED, BUFFER_TOO_SMALL = 1, 4, 6
+
+
+@pytest.fixture(scope="module")
+def ctx(gpu):
+    c = dmc.Context(0)
+    yield c
+    c.close()
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def test_oi_not_converged_without_stats(ctx):
+    """One sweep against a zero tolerance cannot converge: the sequence call
+    reports it with stats NULL and with or without decoding, and so does the
+    single-window call."""
+    w = configs.small_torus(frames=40, T=16, k=6, precision="fp32")
+    m = dmc.Mesh(ctx, w.n, w.tris, w.anchors)
+    q0 = to_dev(animate.gaussian_subspace(w.T, w.k, 5).astype(np.float32))
+    p = dmc.make_params(w.k, precision=dmc.FP32, oi_max_sweeps=1, oi_tol=0.0)
+    fr = to_dev(w.frames)
+    for decode in (True, False):
+        _, _, _, status = dmc.compress_sequence(ctx, m, fr, w.T, p, q_start=q0, decode=decode,
+                                                stats=False)
+        assert status == NOT_CONVERGED
+    r = dmc.encode_window(ctx, m, fr[:w.T].contiguous(), p, q_start=q0, stats=False)
+    assert r["status"] == NOT_CONVERGED
+    # the same calls with a reachable tolerance converge
+    p_ok = dmc.make_params(w.k, precision=dmc.FP32)
+    _, _, st, status = dmc.compress_sequence(ctx, m, fr, w.T, p_ok, q_start=q0, stats=False)
+    assert status == 0
+    # the exact start is not iterated: never reported
+    p_ex = dmc.make_params(w.k, precision=dmc.FP32, init=dmc.INIT_EXACT, oi_max_sweeps=1,
+                           oi_tol=0.0)
+    _, _, _, status = dmc.compress_sequence(ctx, m, fr, w.T, p_ex, stats=False)
+    assert status == 0
+
+
+def test_bf16_needs_a_refinement_sweep(ctx):
+    w = configs.small_torus(frames=16, T=16, k=4, precision="fp32")
+    m = dmc.Mesh(ctx, w.n, w.tris, w.anchors)
+    p = dmc.make_params(w.k, precision=dmc.BF16, oi_max_sweeps=1)
+    with pytest.raises(dmc.DmcError) as e:
+        dmc.compress_sequence(ctx, m, to_dev(w.frames), w.T, p)
+    assert e.value.status == INVALID_ARG
+
+
+def test_decode_rejects_foreign_records(ctx):
+    """A record decoded with other sizes or formats than it was written with,
+    or a buffer that holds no record, is refused by the host check of the
+    headers before any kernel runs."""
+    w = configs.small_torus(frames=40, T=16, k=6, precision="fp32")
+    m = dmc.Mesh(ctx, w.n, w.tris, w.anchors)
+    p = dmc.make_params(w.k, precision=dmc.FP32)
+    codes, out, _, status = dmc.compress_sequence(ctx, m, to_dev(w.frames), w.T, p)
+    assert status == 0
+    good, _, st = dmc.decode_sequence(ctx, m, codes, w.F, w.T, p)
+    assert st == 0
+    assert np.array_equal(_np(good), _np(out))
+    import torch
+    for bad in (dmc.make_params(w.k - 2, precision=dmc.FP32),
+                dmc.make_params(w.k, coef_bits=10, precision=dmc.FP32),
+                dmc.make_params(w.k, anchor_bits=12, precision=dmc.FP32)):
+        with pytest.raises(dmc.DmcError) as e:
+            dmc.decode_sequence(ctx, m, codes, w.F, w.T, bad)
+        assert e.value.status == INVALID_ARG
+    with pytest.raises(dmc.DmcError) as e:
+        dmc.decode_sequence(ctx, m, codes, w.F, w.T, dmc.make_params(w.k, precision=dmc.FP64))
+    assert e.value.status == INVALID_ARG
+    # another mesh with the same vertex count but other anchors
+    m2 = dmc.Mesh(ctx, w.n, w.tris, w.anchors[:-1])
+    with pytest.raises(dmc.DmcError) as e:
+        dmc.decode_sequence(ctx, m2, codes, w.F, w.T, p)
+    assert e.value.status == INVALID_ARG
+    # a window record decoded with the wrong window length, and zeros
+    r = dmc.encode_window(ctx, m, to_dev(w.frames[:w.T]), p)
+    with pytest.raises(dmc.DmcError) as e:
+        dmc.decode_window(ctx, m, r["code"], w.T - 1, p)
+    assert e.value.status == INVALID_ARG
+    with pytest.raises(dmc.DmcError) as e:
+        dmc.decode_window(ctx, m, torch.zeros_like(r["code"]), w.T, p)
+    assert e.value.status == INVALID_ARG
+
+
+@pytest.mark.parametrize("precond", [dmc.PRECOND_CHOLESKY, dmc.PRECOND_JACOBI])
+def test_workspace_no_library_scratch(ctx, precond):
+    """A whole sequence (encode, decode, decode_sequence) runs on a torch-
+    allocated workspace of dmc_workspace_bytes: the context allocates no
+    scratch of its own, the results equal those of library scratch bit for
+    bit, and a workspace one byte short is refused."""
+    import torch
+    w = configs.small_torus(frames=40, T=16, k=6, precision="fp32")
+    c2 = dmc.Context(0)
+    try:
+        m = dmc.Mesh(c2, w.n, w.tris, w.anchors)
+        p = dmc.make_params(w.k, coef_bits=w.bits, precision=dmc.FP32, precond=precond,
+                            cg_tol=1e-10)
+        fr = to_dev(w.frames)
+        q0 = to_dev(animate.gaussian_subspace(w.T, w.k, 8).astype(np.float32))
+        ref_codes, ref_out, _, st = dmc.compress_sequence(c2, m, fr, w.T, p, q_start=q0)
+        assert st == 0
+        need = dmc.workspace_bytes(m, w.F, w.T, p)
+        assert need > 0
+        c3 = dmc.Context(0)
+        try:
+            m3 = dmc.Mesh(c3, w.n, w.tris, w.anchors)
+            buf = torch.empty(need, dtype=torch.uint8, device="cuda:0")
+            c3.set_workspace(buf)
+            codes, out, stats, st = dmc.compress_sequence(c3, m3, fr, w.T, p, q_start=q0)
+            assert st == 0
+            dec, _, st2 = dmc.decode_sequence(c3, m3, codes, w.F, w.T, p)
+            assert st2 == 0
+            assert c3.scratch_bytes == 0
+            assert torch.equal(codes, ref_codes)
+            assert torch.equal(out, ref_out)
+            assert torch.equal(dec, ref_out)
+            # window calls fit the workspace of their own size
+            need_w = dmc.workspace_bytes(m3, w.T, w.T, p)
+            assert 0 < need_w <= need
+            r = dmc.encode_window(c3, m3, fr[:w.T].contiguous(), p, q_start=q0)
+            assert r["status"] == 0
+            dmc.decode_window(c3, m3, r["code"], w.T, p)
+            assert c3.scratch_bytes == 0
+            small = torch.empty(need - 256, dtype=torch.uint8, device="cuda:0")
+            c3.set_workspace(small)
+            with pytest.raises(dmc.DmcError) as e:
+                dmc.compress_sequence(c3, m3, fr, w.T, p, q_start=q0)
+            assert e.value.status == BUFFER_TOO_SMALL
+            c3.set_workspace(None)
+            _, out4, _, st = dmc.compress_sequence(c3, m3, fr, w.T, p, q_start=q0)
+            assert st == 0 and torch.equal(out4, ref_out)
+            assert c3.scratch_bytes > 0
+        finally:
+            c3.close()
+    finally:
+        c2.close()
+
+
+@pytest.mark.parametrize("bits", [(12, 16, 16), (8, 12, 10), (0, 0, 0)])
+def test_stats_bit_rates_match_oracle_accounting(ctx, bits):
+    """The bits per vertex per frame and coordinate that each window's stats
+    report (Eq. 13) add up to the oracle's accounting of the same sequence,
+    ragged last window included; the stage timers are filled."""
+    cb, ab, db = bits
+    w = configs.small_torus(frames=40, T=16, k=6, precision="fp32")
+    m = dmc.Mesh(ctx, w.n, w.tris, w.anchors)
+    p = dmc.make_params(w.k, coef_bits=cb, anchor_bits=ab, dict_bits=db, precision=dmc.FP32)
+    _, _, stats, status = dmc.compress_sequence(ctx, m, to_dev(w.frames), w.T, p)
+    assert status == 0
+    shapes = [(e - s, min(w.k, e - s)) for s, e in O.windows(w.F, w.T)]
+    ref = O.bpvf(w.n, w.F, w.anchors.size, shapes, cb, anchor_bits=ab, dict_bits=db,
+                 raw_bits=32)
+    agg = {key: sum(s[key] * s["T"] for s in stats) / w.F for key in ("q", "q_a", "q_d", "q_s")}
+    print(bits, agg, ref)
+    assert agg["q"] == pytest.approx(ref["q"] + ref["q_r"], rel=1e-12)
+    assert agg["q_a"] == pytest.approx(ref["q_a"], rel=1e-12)
+    assert agg["q_d"] == pytest.approx(ref["q_d"], rel=1e-12)
+    assert agg["q_s"] == pytest.approx(ref["q_s"], rel=1e-12)
+    assert all(s["ms_encode"] > 0 and s["ms_decode"] > 0 for s in stats)

@@ -380,12 +380,46 @@ def test_table1_side_information():
             assert abs(e["q"] + e["q_a"] + e["q_d"] - e["q_s"]) <= 1e-3
 
 
-def test_bpvf_accounting_counts():
-    b = O.bpvf(1000, 20, 10, [(8, 4), (8, 4), (4, 4)], bits=12)
-    assert b["q"] == pytest.approx(12 * 12 * 1000 / 20000)
-    assert b["q_d"] == pytest.approx(16 * (32 + 32 + 16) / 20000)
-    assert b["q_a"] == pytest.approx((16 * 10 * 20 + 64 * 3) / 20000)
-    assert b["q_s"] == pytest.approx(b["q"] + b["q_r"] + b["q_a"] + b["q_d"])
+def test_bpvf_reproduces_table1_side_information():
+    """bpvf() on the shape of Table I's PCA+qs/qp column (one window spanning
+    all F = T = 175 frames, every frame's eigen-trajectory kept, 1% anchors,
+    16-bit anchors and dictionary, Sec. IV) gives the printed q_a and q_d to
+    the table's four digits; our range side information (two float32 per
+    window and coordinate) is the only extra and stays below the printed
+    rounding."""
+    g = json.load(open(os.path.join(GOLDEN, "table1_bpvf.json")))
+    hs = g["models"]["Handstand"]
+    n, F, nc = hs["n"], hs["k"], hs["n_c"]
+    b = O.bpvf(n, F, nc, [(F, F)], bits=12)
+    assert round(b["q_a"], 4) == hs["pca_qp"]["q_a"]
+    assert round(b["q_d"], 4) == hs["pca_qp"]["q_d"]
+    assert b["q_a"] - 16 * nc / n == pytest.approx(64 / (n * F))
+    sb = g["models"]["Samba"]
+    b = O.bpvf(sb["n"], sb["k"], sb["n_c"], [(sb["k"], sb["k"])], bits=12)
+    assert round(b["q_d"], 4) == sb["pca_qp"]["q_d"]
+
+
+def test_bpvf_counts_the_bits_of_each_part():
+    """Brute-force count of the bits a small sequence's records carry, summed
+    part by part, against bpvf()'s per-vertex-frame figures."""
+    n, F, nc = 1000, 20, 10
+    shapes = [(8, 4), (8, 4), (4, 4)]
+    bits = {"q": 0, "q_r": 0, "q_a": 0, "q_d": 0}
+    for tw, kw in shapes:
+        for _c in range(1):  # one coordinate
+            for _r in range(kw):
+                bits["q"] += sum(12 for _ in range(n))
+                bits["q_r"] += 2 * 32
+            bits["q_a"] += sum(16 for _ in range(tw * nc)) + 2 * 32
+            bits["q_d"] += sum(16 for _ in range(tw * kw))
+    b = O.bpvf(n, F, nc, shapes, bits=12)
+    for key, v in bits.items():
+        assert b[key] == pytest.approx(v / (n * F))
+    assert b["q_s"] == pytest.approx(sum(bits.values()) / (n * F))
+    # raw parts: float32 values, no ranges
+    raw = O.bpvf(n, F, nc, shapes, bits=0, anchor_bits=0, dict_bits=0, raw_bits=32)
+    assert raw["q"] == pytest.approx(32 * 12 * n / (n * F)) and raw["q_r"] == 0.0
+    assert raw["q_a"] == pytest.approx(32 * nc * F / (n * F))
 
 
 def test_nmse_definition():
