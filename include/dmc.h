@@ -256,6 +256,28 @@ dmc_status dmc_encode_window(dmc_ctx ctx, dmc_mesh mesh, const void* frames_dev,
                              void* u_out_dev, void* coef_out_dev,
                              dmc_window_stats* stats);
 
+/* ---- encode one window without allocating --------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * operation, arguments, outputs and errors as dmc_encode_window, bit for bit
+ * the same results, but its scratch (delta coordinates, autocorrelation
+ * partials, covariance, dictionary, coefficients and the window's stats)
+ * lives in a fixed device array of the library of DMC_NOALLOC_SCRATCH_BYTES
+ * per GPU, held from the first dmc_create on that GPU until the process
+ * ends.  A window that needs more returns DMC_ERR_BUFFER_TOO_SMALL before
+ * launching (its need is about T n (3 x frame bytes + 3 k x frame bytes) plus
+ * the autocorrelation partials; e.g. 16,384 vertices x 32 frames fits).
+ * Nothing is allocated by the call; it synchronises the stream at its end
+ * like dmc_encode_window.  Every call on one GPU shares that GPU's array and
+ * each call writes all of it that it reads: calls that overlap in time on
+ * one GPU (two streams, two threads) race and must be serialised by the
+ * caller. */
+#define DMC_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+dmc_status dmc_encode_window_noalloc(dmc_ctx ctx, dmc_mesh mesh, const void* frames_dev,
+                                     int32_t T, const dmc_params* params,
+                                     const void* q_start_dev, void* code_dev, void* u_out_dev,
+                                     void* coef_out_dev, dmc_window_stats* stats);
+
 /* ---- decode one window (Eq. 12) ------------------------------------------
  * code_dev: a record written by dmc_encode_window for this mesh and T;
  * frames_out_dev [T][n][3].  The record's header is read back first: a

@@ -6,12 +6,28 @@
 #include <array>
 #include <chrono>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
 #include "chol_host.h"
 #include "dmc_internal.h"
 #include "mesh_host.h"
+
+// Scratch of dmc_encode_window_noalloc: a fixed device array instead of
+// allocated memory (the delta coordinates, the chain's pieces and the
+// window's stats of one encode).  Every GPU the library runs on holds its own
+// copy, at its own address, until the process ends.  In host code the name is
+// only a stand-in: kernels and copies take the address hipGetSymbolAddress
+// returned for the device (noalloc_scratch below), never the name itself.
+constexpr size_t kNoAllocScratchBytes = DMC_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) uint8_t scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+void* g_noalloc_scratch[kMaxDevices] = {};  // per device, set by dmc_create
+}  // namespace
 
 struct dmc_ctx_s {
   int device = 0;
@@ -737,6 +753,20 @@ dmc_status dmc_create(int32_t device, void* hip_stream, dmc_ctx* out) {
   HIP_TRY(hipGetDeviceProperties(&prop, device));
   if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
     return fail(DMC_ERR_DEVICE, std::string("built for gfx950, device is ") + prop.gcnArchName);
+  if (device >= kMaxDevices) return fail(DMC_ERR_UNSUPPORTED, "device index above 63");
+  {
+    // the device's address of the fixed scratch array, once per device,
+    // with the device current
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (!g_noalloc_scratch[device]) {
+      void* ptr = nullptr;
+      const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !ptr)
+        return fail(DMC_ERR_DEVICE,
+                    std::string("hipGetSymbolAddress of the fixed scratch: ") + hipGetErrorString(e));
+      g_noalloc_scratch[device] = ptr;
+    }
+  }
   dmc_ctx c = new dmc_ctx_s();
   c->device = device;
   c->stream = (hipStream_t)hip_stream;
@@ -1038,6 +1068,28 @@ dmc_status dmc_encode_window(dmc_ctx ctx, dmc_mesh mesh, const void* frames, int
   if (st != DMC_OK) return st;
   return encode_window_on(ctx, mesh->dev, frames, T, *params, q_start, code, u_out, coef_out,
                           stats, (uint8_t*)ctx->scratch, wl, (dmc::StatsDev*)ctx->stats);
+}
+
+dmc_status dmc_encode_window_noalloc(dmc_ctx ctx, dmc_mesh mesh, const void* frames, int32_t T,
+                                     const dmc_params* params, const void* q_start, void* code,
+                                     void* u_out, void* coef_out, dmc_window_stats* stats) {
+  dmc_status st = check_encode_window(ctx, mesh, frames, T, params, code);
+  if (st != DMC_OK) return st;
+  const WindowScratch wl = window_scratch(mesh->dev, T, *params, true);
+  if (wl.total > kNoAllocScratchBytes)
+    return fail(DMC_ERR_BUFFER_TOO_SMALL,
+                "this window needs " + std::to_string(wl.total) +
+                    " bytes of scratch; the fixed array of dmc_encode_window_noalloc holds " +
+                    std::to_string(kNoAllocScratchBytes));
+  HIP_TRY(hipSetDevice(ctx->device));
+  uint8_t* ws = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    ws = (uint8_t*)g_noalloc_scratch[ctx->device];
+  }
+  if (!ws) return fail(DMC_ERR_DEVICE, "no address of the fixed scratch for this device");
+  return encode_window_on(ctx, mesh->dev, frames, T, *params, q_start, code, u_out, coef_out,
+                          stats, ws, wl, (dmc::StatsDev*)(ws + wl.o_stats));
 }
 
 static dmc::SeqLayout seq_layout(int32_t n, int32_t F, int32_t T, int32_t nc, const dmc_params& p) {

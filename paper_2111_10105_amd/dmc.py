@@ -17,6 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdmc.so")
 
 DMC_OK = 0
+NOALLOC_SCRATCH_BYTES = 64 << 20  # DMC_NOALLOC_SCRATCH_BYTES of include/dmc.h
 STATUS = {0: "OK", 1: "INVALID_ARG", 2: "OUT_OF_MEMORY", 3: "DEVICE", 4: "NOT_CONVERGED",
           5: "SINGULAR", 6: "BUFFER_TOO_SMALL", 7: "UNSUPPORTED"}
 FP64, FP32, BF16 = 0, 1, 2
@@ -29,6 +30,7 @@ EXPORTS = ["dmc_create", "dmc_destroy", "dmc_set_stream", "dmc_last_error", "dmc
            "dmc_mesh_create", "dmc_mesh_destroy", "dmc_mesh_nnz", "dmc_mesh_normal_nnz",
            "dmc_mesh_factor_info", "dmc_mesh_anchor_response", "dmc_host_normal_solve",
            "dmc_window_code_bytes", "dmc_sequence_code_bytes", "dmc_encode_window",
+           "dmc_encode_window_noalloc",
            "dmc_decode_window", "dmc_compress_sequence", "dmc_decode_sequence", "dmc_delta",
            "dmc_autocorrelation", "dmc_profile_start", "dmc_profile_stop", "dmc_oi_blocks",
            "dmc_mlp_param_count", "dmc_learned_start", "dmc_mlp_sketch", "dmc_mlp_forward",
@@ -122,6 +124,7 @@ def lib():
         "dmc_window_code_bytes": (sz, [i32, i32, i32, P]),
         "dmc_sequence_code_bytes": (sz, [i32, i32, i32, i32, P]),
         "dmc_encode_window": (i32, [vp, vp, vp, i32, P, vp, vp, vp, vp, S]),
+        "dmc_encode_window_noalloc": (i32, [vp, vp, vp, i32, P, vp, vp, vp, vp, S]),
         "dmc_decode_window": (i32, [vp, vp, vp, i32, P, vp, S]),
         "dmc_compress_sequence": (i32, [vp, vp, vp, i32, i32, P, vp, vp, sz, vp, S]),
         "dmc_decode_sequence": (i32, [vp, vp, vp, i32, i32, P, vp, S]),
