@@ -74,9 +74,11 @@ def parse():
     ap.add_argument("--profile-kernel", default=None,
                     help="kernel family timed live (default: the dominant one)")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="MB")
-    ap.add_argument("--workload", default="icosphere7", choices=["torus", "icosphere7", "batched"],
+    ap.add_argument("--workload", default="icosphere7",
+                    choices=["torus", "icosphere7", "batched", "rd"],
                     help="icosphere7: the headline workload (level 7, 512 frames); torus: the "
-                         "128 x 128 torus alone; batched: 64 sequences in one graph")
+                         "128 x 128 torus alone; batched: 64 sequences in one graph; rd: the "
+                         "rate-distortion sweep over k")
     ap.add_argument("--no-second-workload", action="store_true",
                     help="skip the torus workload that runs beside the headline")
     return ap.parse_args()
@@ -253,6 +255,51 @@ def bench_batched(args):
     ctx.close()
 
 
+def bench_rd_sweep(args):
+    """Rate-distortion sweep in the manner of the paper's Fig. 3 (only the
+    first k of the eigen-trajectory rows kept, k in {2, 5, 10, 20, 30}) on a
+    synthetic stand-in of its Handstand workload's shape: a 100 x 100 torus
+    (10,000 vertices), 175 frames in 5 windows of 35 (the "blocks"
+    variant), 6-bone RBF skinning, 12-bit codes, 1% anchors, float32.  Per k:
+    bits per vertex per frame and coordinate of the stream (Eq. 13), the
+    reconstruction's NMSE against the input and the relative error of its
+    delta coordinates (the Laplacian-domain part of a visual error; the
+    paper's NMSVE is not defined in its text), and the step time."""
+    import numpy as np
+    import torch
+    from paper_2111_10105_amd import dmc
+    from synth import animate, configs, meshes
+    v, t = meshes.torus(100, 100)
+    F, T = 175, 35
+    fr = animate.rbf_skinning(v, F, 6, seed=808, dtype=np.float32)
+    anchors = animate.choose_anchors(v.shape[0], 100, seed=809)
+    n = v.shape[0]
+    ctx = dmc.Context(0)
+    mesh = dmc.Mesh(ctx, n, t, anchors)
+    frames = torch.from_numpy(fr).cuda()
+    delta_in = dmc.delta(ctx, mesh, frames, dmc.FP32).cpu().numpy()
+    flush = Flusher()
+    rows = []
+    for k in (2, 5, 10, 20, 30):
+        p = dmc.make_params(k, coef_bits=12, precision=dmc.FP32, init=dmc.INIT_EXACT)
+        codes = torch.empty(dmc.sequence_code_bytes(n, F, T, mesh.nc, p), dtype=torch.uint8,
+                            device="cuda:0")
+        times, st, status, out = run_form(dmc, ctx, mesh, frames, T, p, None, 5, flush, codes)
+        got = out.cpu().numpy()
+        d_out = dmc.delta(ctx, mesh, out, dmc.FP32).cpu().numpy()
+        rows.append({"k": k, "status": status,
+                     "bpvf": {key: round(sum(x[key] * x["T"] for x in st) / F, 5)
+                              for key in ("q", "q_a", "q_d", "q_s")},
+                     "nmse_vs_input": nmse(got, fr),
+                     "delta_rel_error": float(np.sqrt(np.sum((d_out - delta_in) ** 2) /
+                                                      np.sum(delta_in.astype(np.float64) ** 2))),
+                     "ms_per_step": round(sum(times) / len(times) * 1e3, 3)})
+    print(json.dumps({"workload": f"torus100x100-{n}v-{F}f-T{T}-b12-rd-sweep",
+                      "data": "synthetic (seeded RBF skinning in the shape of Handstand)",
+                      "sweep": rows}))
+    ctx.close()
+
+
 def nmse(x, y) -> float:
     """sum (x - y)^2 / sum y^2 over every vertex, frame and coordinate."""
     import numpy as np
@@ -362,6 +409,9 @@ def main():
         return
     if args.workload == "batched":
         bench_batched(args)
+        return
+    if args.workload == "rd":
+        bench_rd_sweep(args)
         return
     import numpy as np
     import torch

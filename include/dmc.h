@@ -399,8 +399,8 @@ dmc_status dmc_mlp_adam(dmc_ctx ctx, float* theta_dev, const float* grad_dev, fl
  * or <= 32), the bandwidth-bound kernels per sequence, and each decode with
  * exactly params[i].cg_max_iters conjugate-gradient iterations and no host
  * synchronisation.  At creation a small autotuner times candidate vertex
- * splits of the covariance kernel and frames per workgroup of the delta
- * kernel on each sequence's own frames and keeps the fastest.  The batch owns
+ * splits of the covariance kernel on each sequence's own frames and keeps
+ * the fastest.  The batch owns
  * its device scratch (allocated at creation); meshes and caller buffers must
  * outlive it.
  * dmc_batch_run: ordered on the context's stream, does not synchronise.
@@ -409,8 +409,8 @@ dmc_status dmc_mlp_adam(dmc_ctx ctx, float* theta_dev, const float* grad_dev, fl
  * cg_resid = largest relative residual) and returns DMC_ERR_NOT_CONVERGED if
  * some column of the sequence did not reach cg_tol.
  * dmc_batch_tuning: the autotuner's choices for sequence seq:
- * tuning[0] = covariance vertex blocks per window, tuning[1] = delta frames
- * per workgroup. */
+ * tuning[0] = covariance vertex blocks per window, tuning[1] = 0 (reserved;
+ * the delta coordinates are formed inside the projection kernel). */
 typedef struct dmc_batch_s* dmc_batch;
 dmc_status dmc_batch_create(dmc_ctx ctx, int32_t nseq, const dmc_mesh* meshes,
                             const void* const* frames_dev, const int32_t* F, const int32_t* T,

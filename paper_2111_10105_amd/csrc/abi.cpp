@@ -241,7 +241,7 @@ float elapsed_ms(hipEvent_t a, hipEvent_t b) {
 dmc_status encode_chain(dmc_ctx ctx, const dmc::MeshDev& m, const void* frames, int32_t T,
                         int32_t nw, int32_t k, const dmc_params& p, const void* q_start,
                         uint8_t* records, const dmc::RecordLayout& lay, void* u_out,
-                        void* coef_out, const void* delta, uint8_t* ws,
+                        void* coef_out, uint8_t* ws,
                         dmc::StatsDev* stats_dev) {
   hipStream_t s = ctx->stream;
   // scratch pieces (carved by the caller in this order)
@@ -298,7 +298,7 @@ dmc_status encode_chain(dmc_ctx ctx, const dmc::MeshDev& m, const void* frames, 
   oa.ritz_qh = ritz_qh;
   oa.ritz_flag = ritz_flag;
   dmc::launch_oi(s, oa);
-  dmc::launch_project_quantise(s, delta, m.n, T, k, nw, p.precision, p.coef_bits, u_tilde, records,
+  dmc::launch_project_quantise(s, m, frames, T, k, nw, p.precision, p.coef_bits, u_tilde, records,
                                lay.bytes, lay, proj, coef_out);
   dmc::launch_anchors(s, m, frames, T, nw, p.precision, p.anchor_bits, records, lay.bytes, lay);
   return check_launch("encode kernels");
@@ -438,7 +438,10 @@ void decode_enqueue_setup(hipStream_t s, const dmc::MeshDev& m, const uint8_t* r
     dmc::launch_back_project(s, m, records, sl, nullptr, cb.q);
     dmc::launch_rhs(s, m, records, sl, cb.q, cb.r, bb);
   }
-  dmc::launch_cg_init(s, m, d.ncols, cb.r, cb, p.precond, zero_x, bb != nullptr);
+  if (p.precond == DMC_PRECOND_CHOLESKY)
+    dmc::launch_cg_norms(s, m, d.ncols, cb);  // the solve starts from the factor's solution
+  else
+    dmc::launch_cg_init(s, m, d.ncols, cb.r, cb, p.precond, zero_x, bb != nullptr);
   // the test on the reduced columns bounds every frame's full-system residual
   // (r still holds b here)
   if (d.reduced)
@@ -462,9 +465,22 @@ void decode_enqueue_fixed(hipStream_t s, const dmc::MeshDev& m, const uint8_t* r
   const dmc::CgBuffers cb = decode_buffers(ws, d.lay, d.ncols, chol);
   double* Ah = (double*)(ws + d.lay.o_Ah);
   decode_enqueue_setup(s, m, records, sl, p, d, cb, ws, iters < 1);
-  for (int it = 1; it <= iters; ++it) {
-    dmc::launch_cg_step_a(s, m, d.ncols, cb, p.precond, p.cg_tol, it == 1);
-    if (it < iters) dmc::launch_cg_step_b(s, m, d.ncols, cb, p.precond);
+  if (p.precond == DMC_PRECOND_CHOLESKY) {
+    // iteration 1 is the start from the factor's solution; the later ones
+    // continue the preconditioned iterations from it (converged columns stay)
+    dmc::launch_cg_warm_start(s, m, d.ncols, cb, p.cg_tol);
+    for (int it = 2; it <= iters; ++it) {
+      if (it == 2)
+        dmc::launch_cg_restart(s, m, d.ncols, cb);
+      else
+        dmc::launch_cg_step_b(s, m, d.ncols, cb, p.precond);
+      dmc::launch_cg_step_a(s, m, d.ncols, cb, p.precond, p.cg_tol, false);
+    }
+  } else {
+    for (int it = 1; it <= iters; ++it) {
+      dmc::launch_cg_step_a(s, m, d.ncols, cb, p.precond, p.cg_tol, it == 1);
+      if (it < iters) dmc::launch_cg_step_b(s, m, d.ncols, cb, p.precond);
+    }
   }
   dmc::launch_cg_summary(s, cb, d.ncols, summary);
   decode_enqueue_finish(s, m, records, sl, p, d, cb, Ah, frames_out);
@@ -526,10 +542,13 @@ dmc_status decode_all(dmc_ctx ctx, const dmc::MeshDev& m, const uint8_t* records
   int32_t it = 0;
   bool all_done = false;
   if (chol && p.cg_max_iters >= 1) {
-    // The Cholesky preconditioner converges in one iteration, so the frames
-    // are formed right after it and the host reads the convergence flags
-    // once, at the end; columns that have not converged get more iterations
-    // and the frames are formed again.
+    // The solve starts from the Cholesky factor's own solution x = (L L^T)^-1
+    // b, whose residual is checked without being stored (the factor is exact
+    // up to rounding, so that start nearly always meets the tolerance).  The
+    // frames are formed right after that check and the host reads the
+    // convergence flags once, at the end; columns that have not converged
+    // continue with preconditioned iterations from the start and the frames
+    // are formed again.
     auto read_flags = [&]() -> dmc_status {
       HIP_TRY(hipMemcpyAsync(h_done, cb.done, (size_t)ncols * 4, hipMemcpyDeviceToHost, s));
       HIP_TRY(hipMemcpyAsync(h_res, cb.resid, (size_t)ncols * 8, hipMemcpyDeviceToHost, s));
@@ -538,7 +557,7 @@ dmc_status decode_all(dmc_ctx ctx, const dmc::MeshDev& m, const uint8_t* records
       for (int j = 0; j < ncols; ++j) all_done = all_done && h_done[j];
       return DMC_OK;
     };
-    dmc::launch_cg_step_a(s, m, ncols, cb, p.precond, p.cg_tol, true);
+    dmc::launch_cg_warm_start(s, m, ncols, cb, p.cg_tol);
     it = 1;
     decode_enqueue_finish(s, m, records, sl, p, d, cb, Ah, frames_out);
     st = check_launch("cg kernels and frames");
@@ -546,8 +565,9 @@ dmc_status decode_all(dmc_ctx ctx, const dmc::MeshDev& m, const uint8_t* records
     st = read_flags();
     if (st != DMC_OK) return st;
     if (!all_done && it < p.cg_max_iters) {
+      dmc::launch_cg_restart(s, m, ncols, cb);
       while (!all_done && it < p.cg_max_iters) {
-        dmc::launch_cg_step_b(s, m, ncols, cb, p.precond);
+        if (it > 1) dmc::launch_cg_step_b(s, m, ncols, cb, p.precond);
         dmc::launch_cg_step_a(s, m, ncols, cb, p.precond, p.cg_tol, false);
         ++it;
         st = check_launch("cg kernels");
@@ -998,18 +1018,17 @@ size_t dmc_sequence_code_bytes(int32_t n, int32_t F, int32_t T, int32_t n_anchor
   return b;
 }
 
-// Scratch of one window's encode: the delta coordinates, then the chain's
-// pieces (autocorrelation partials, R, dictionary, projection), and the
-// window's stats when the caller's array holds them too (stats_off).
+// Scratch of one window's encode: the chain's pieces (autocorrelation
+// partials, R, dictionary, coefficients), and the window's stats when the
+// caller's array holds them too (o_stats).
 struct WindowScratch {
-  size_t o_delta = 0, o_chain = 0, o_stats = 0, total = 0;
+  size_t o_chain = 0, o_stats = 0, total = 0;
 };
 
 WindowScratch window_scratch(const dmc::MeshDev& m, int32_t T, const dmc_params& p,
                              bool with_stats) {
   Carve cv;
   WindowScratch w;
-  w.o_delta = cv.add((size_t)T * 3 * m.n * real_size(p.precision));
   w.o_chain = cv.add(chain_scratch_bytes(m.n, T, 1, std::min(p.k, T), p.precision, p.init));
   if (with_stats) w.o_stats = cv.add(sizeof(dmc::StatsDev));
   w.total = cv.total();
@@ -1023,11 +1042,9 @@ dmc_status encode_window_on(dmc_ctx ctx, const dmc::MeshDev& m, const void* fram
                             void* coef_out, dmc_window_stats* stats, uint8_t* ws,
                             const WindowScratch& wl, dmc::StatsDev* sd) {
   const dmc::RecordLayout lay = dmc::record_layout(m.n, T, p.k, m.nc, p);
-  void* delta = ws + wl.o_delta;
   if (stats) HIP_TRY(hipEventRecord(ctx->ev[0], ctx->stream));
-  dmc::launch_delta(ctx->stream, m, frames, delta, T, p.precision);
   dmc_status st = encode_chain(ctx, m, frames, T, 1, p.k, p, q_start, (uint8_t*)code, lay, u_out,
-                               coef_out, delta, ws + wl.o_chain, sd);
+                               coef_out, ws + wl.o_chain, sd);
   if (st != DMC_OK) return st;
   if (stats) HIP_TRY(hipEventRecord(ctx->ev[1], ctx->stream));
   // the convergence of the orthogonal iterations is read back at this one
@@ -1211,14 +1228,14 @@ dmc_status dmc_decode_sequence(dmc_ctx ctx, dmc_mesh mesh, const void* codes, in
   return st;
 }
 
-// Scratch bytes of the encoder (delta coordinates of every frame, then the
-// chains of full windows and the short last window) and of the decoder (the
-// solve's vectors), for an F-frame sequence; the two never live together.
+// Scratch bytes of the encoder (the chains of full windows and of the short
+// last window) and of the decoder (the solve's vectors), for an F-frame
+// sequence; the two never live together.
 size_t encode_scratch_bytes(const dmc::MeshDev& m, const dmc::SeqLayout& sl, const dmc_params& p,
                             size_t* o_full = nullptr, size_t* o_tail = nullptr) {
   const int32_t F = sl.nw_full * sl.T + sl.T_tail;
   Carve cv;
-  cv.add((size_t)F * 3 * m.n * real_size(p.precision));
+  (void)F;
   const size_t of = cv.add(sl.nw_full ? chain_scratch_bytes(m.n, sl.T, sl.nw_full, sl.full.k,
                                                               p.precision, p.init)
                                       : 0);
@@ -1269,21 +1286,19 @@ dmc_status dmc_compress_sequence(dmc_ctx ctx, dmc_mesh mesh, const void* frames,
   st = ensure_pinned(ctx, stats_at + sizeof(dmc::StatsDev) * nw);
   if (st != DMC_OK) return st;
   uint8_t* ws = (uint8_t*)ctx->scratch;
-  void* delta = ws;
   dmc::StatsDev* sd = (dmc::StatsDev*)ctx->stats;
   if (per_window) HIP_TRY(hipEventRecord(ctx->ev[0], ctx->stream));
-  dmc::launch_delta(ctx->stream, m, frames, delta, F, p.precision);
   const size_t rs = real_size(p.precision);
   if (sl.nw_full) {
     st = encode_chain(ctx, m, frames, T, sl.nw_full, k_full, p, q_start, (uint8_t*)codes, sl.full,
-                      nullptr, nullptr, delta, ws + o_full, sd);
+                      nullptr, nullptr, ws + o_full, sd);
     if (st != DMC_OK) return st;
   }
   if (sl.T_tail) {
     const size_t f0 = (size_t)sl.nw_full * T;
     st = encode_chain(ctx, m, (const uint8_t*)frames + f0 * 3 * m.n * rs, sl.T_tail, 1, sl.tail.k,
                       p_tail, nullptr, (uint8_t*)codes + (size_t)sl.nw_full * sl.full.bytes, sl.tail,
-                      nullptr, nullptr, (const uint8_t*)delta + f0 * 3 * m.n * rs, ws + o_tail,
+                      nullptr, nullptr, ws + o_tail,
                       sd + sl.nw_full);
     if (st != DMC_OK) return st;
   }
@@ -1520,9 +1535,9 @@ struct BatchSeq {
   uint8_t* codes = nullptr;
   void* out = nullptr;
   dmc::SeqLayout sl{};
-  size_t o_delta = 0, o_R = 0, o_Rt = 0, o_ut = 0, o_utt = 0;
+  size_t o_R = 0, o_Rt = 0, o_ut = 0, o_utt = 0;
   int32_t stats_off = 0;  // first window in the batch's stats array
-  int P = 0, fpb = 8;     // tuned launch shapes
+  int P = 0;              // tuned launch shape
 };
 
 struct dmc_batch_s {
@@ -1544,8 +1559,6 @@ namespace {
 void batch_enqueue(dmc_batch b, hipStream_t s) {
   uint8_t* shared = b->buf + b->o_shared;
   const size_t rs = real_size(b->precision);
-  for (BatchSeq& q : b->seq)
-    dmc::launch_delta(s, q.mesh->dev, q.frames, b->buf + q.o_delta, q.F, b->precision, q.fpb);
   for (BatchSeq& q : b->seq) {
     const dmc::MeshDev& m = q.mesh->dev;
     for (int32_t w = 0; w < q.sl.nw_full; ++w)
@@ -1565,9 +1578,8 @@ void batch_enqueue(dmc_batch b, hipStream_t s) {
                          (const int4*)(b->buf + b->o_jobs) + b->cls_off[c], b->cls_n[c]);
   for (BatchSeq& q : b->seq) {
     const dmc::MeshDev& m = q.mesh->dev;
-    const uint8_t* delta = b->buf + q.o_delta;
     if (q.sl.nw_full) {
-      dmc::launch_project_quantise(s, delta, m.n, q.T, q.k_full, q.sl.nw_full, b->precision,
+      dmc::launch_project_quantise(s, m, q.frames, q.T, q.k_full, q.sl.nw_full, b->precision,
                                    q.p.coef_bits, (const double*)(b->buf + q.o_ut), q.codes,
                                    q.sl.full.bytes, q.sl.full, shared, nullptr);
       dmc::launch_anchors(s, m, q.frames, q.T, q.sl.nw_full, b->precision, q.p.anchor_bits,
@@ -1576,7 +1588,7 @@ void batch_enqueue(dmc_batch b, hipStream_t s) {
     if (q.sl.T_tail) {
       const size_t f0 = (size_t)q.sl.nw_full * q.T;
       uint8_t* rec = q.codes + (size_t)q.sl.nw_full * q.sl.full.bytes;
-      dmc::launch_project_quantise(s, delta + f0 * 3 * m.n * rs, m.n, q.sl.T_tail, q.k_tail, 1,
+      dmc::launch_project_quantise(s, m, q.frames + f0 * 3 * m.n * rs, q.sl.T_tail, q.k_tail, 1,
                                    b->precision, q.p.coef_bits, (const double*)(b->buf + q.o_utt),
                                    rec, q.sl.tail.bytes, q.sl.tail, shared, nullptr);
       dmc::launch_anchors(s, m, q.frames + f0 * 3 * m.n * rs, q.sl.T_tail, 1, b->precision,
@@ -1662,7 +1674,6 @@ dmc_status dmc_batch_create(dmc_ctx ctx, int32_t nseq, const dmc_mesh* meshes,
     q.k_full = std::min(p.k, q.T);
     q.k_tail = q.sl.T_tail ? std::min(p.k, q.sl.T_tail) : 0;
     const size_t rs = real_size(b->precision);
-    q.o_delta = cv.add((size_t)q.F * 3 * m.n * rs);
     q.o_R = cv.add((size_t)q.sl.nw_full * 3 * q.T * q.T * 8);
     q.o_ut = cv.add((size_t)q.sl.nw_full * 3 * q.T * q.k_full * 8);
     q.o_Rt = cv.add((size_t)3 * q.sl.T_tail * q.sl.T_tail * 8);
@@ -1758,25 +1769,15 @@ dmc_status dmc_batch_create(dmc_ctx ctx, int32_t nseq, const dmc_mesh* meshes,
     (void)hipFree(b->buf);
     return bail(fail(DMC_ERR_DEVICE, "cannot upload the batch's job table"));
   }
-  // autotuner: vertex split of the covariance kernel, frames per workgroup of
-  // the delta kernel, timed on each sequence's own frames
+  // autotuner: vertex split of the covariance kernel, timed on each
+  // sequence's own frames
   hipStream_t s = ctx->stream;
   uint8_t* sh = b->buf + b->o_shared;
   for (BatchSeq& q : b->seq) {
     const dmc::MeshDev& m = q.mesh->dev;
-    float best = 1e30f;
-    for (int fpb : {4, 8, 16}) {
-      const float t = time_launch(s, [&] {
-        dmc::launch_delta(s, m, q.frames, b->buf + q.o_delta, q.F, b->precision, fpb);
-      });
-      if (t < best) {
-        best = t;
-        q.fpb = fpb;
-      }
-    }
     if (!q.sl.nw_full) continue;
     const int P0 = dmc::autocorr_blocks(m.n, q.sl.nw_full);
-    best = 1e30f;
+    float best = 1e30f;
     for (int P : {P0 / 4, P0 / 2, P0, 2 * P0, 4 * P0}) {
       if (P < 1 || P > std::max(1, m.n)) continue;
       const float t = time_launch(s, [&] {
@@ -1866,7 +1867,7 @@ dmc_status dmc_batch_tuning(dmc_batch b, int32_t i, int32_t tuning[2]) {
   if (!b || !tuning) return fail(DMC_ERR_INVALID_ARG, "NULL argument");
   if (i < 0 || i >= (int32_t)b->seq.size()) return fail(DMC_ERR_INVALID_ARG, "bad sequence index");
   tuning[0] = b->seq[i].P;
-  tuning[1] = b->seq[i].fpb;
+  tuning[1] = 0;
   return DMC_OK;
 }
 

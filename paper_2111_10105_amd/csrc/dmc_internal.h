@@ -155,10 +155,12 @@ void launch_mlp_backward(hipStream_t s, const float* theta, int k, const float* 
 void launch_mlp_adam(hipStream_t s, float* theta, const float* grad, float* m, float* v, int count,
                      int step, double lr, double b1, double b2, double eps);
 
-// Projection (Eq. 9) + per-row ranges + quantisation (Eq. 10) for nw windows.
+// Projection (Eq. 9) of the delta coordinates (Eq. 3-4, formed on the fly
+// from the frames [nw*T][n][3], never stored) + per-row ranges +
+// quantisation (Eq. 10) for nw windows.
 size_t project_scratch_bytes(int32_t n, int32_t T, int32_t k, int32_t nw, int32_t precision);
-void launch_project_quantise(hipStream_t s, const void* delta, int32_t n, int32_t T, int32_t k,
-                             int32_t nw, int32_t precision, int32_t coef_bits,
+void launch_project_quantise(hipStream_t s, const MeshDev& m, const void* frames, int32_t T,
+                             int32_t k, int32_t nw, int32_t precision, int32_t coef_bits,
                              const double* u_tilde, uint8_t* records, size_t rec_bytes,
                              const RecordLayout& lay, void* scratch, void* coef_out);
 
@@ -230,6 +232,18 @@ void launch_cg_step_a(hipStream_t s, const MeshDev& m, int32_t ncols, const CgBu
                       int32_t precond, double tol, bool first);
 void launch_cg_step_b(hipStream_t s, const MeshDev& m, int32_t ncols, const CgBuffers& cb,
                       int32_t precond);
+// Cholesky-preconditioned solve started from the preconditioner's own
+// solution: launch_cg_norms reduces the b.b partials the right-hand side
+// left in cb.part (bnorm2, done = 0, resid = 1); launch_cg_warm_start sets
+// x = (L L^T)^-1 b (r still holds b), forms the residual norms of
+// b - M x without storing it and marks the columns within tol;
+// launch_cg_restart then (for columns still open) writes r = b - M x, the
+// first search direction p = (L L^T)^-1 r and rz, after which
+// launch_cg_step_a (first = false) and launch_cg_step_b continue.
+void launch_cg_norms(hipStream_t s, const MeshDev& m, int32_t ncols, const CgBuffers& cb);
+void launch_cg_warm_start(hipStream_t s, const MeshDev& m, int32_t ncols, const CgBuffers& cb,
+                          double tol);
+void launch_cg_restart(hipStream_t s, const MeshDev& m, int32_t ncols, const CgBuffers& cb);
 // summary of a solve on the device: out[0] = max relative residual, out[1] =
 // 1.0 if every column converged
 void launch_cg_summary(hipStream_t s, const CgBuffers& cb, int32_t ncols, double* out);

@@ -328,6 +328,61 @@ k_cg_spmm(const int32_t* __restrict__ mrow, const int32_t* __restrict__ mcol,
   }
 }
 
+// Residual of a start x0: partial (b - M x0).(b - M x0) per column into the
+// first half of `part`, tiled as k_cg_spmm; with write_r, r = b - M x0 is also
+// written in place of b (each element is read and written by one thread).
+__global__ void __launch_bounds__(kBlock)
+k_cg_residual(const int32_t* __restrict__ mrow, const int32_t* __restrict__ mcol,
+              const double* __restrict__ mval, int n, int ncols, const double* __restrict__ x,
+              double* b, int write_r, double* __restrict__ part) {
+  constexpr int NW = kBlock / 64;
+  __shared__ double sh[NW][SP_COLS];
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int j = blockIdx.y * SP_COLS + lane;
+  const bool jv = j < ncols;
+  const double* xj = x + (jv ? j : 0);
+  const int r0 = blockIdx.x * CG_RB, r1 = min(n, r0 + CG_RB);
+  double rr = 0.0;
+  for (int i = r0 + wv; i < r1; i += NW) {
+    const int e1 = mrow[i + 1];
+    int e = mrow[i];
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    for (; e + 4 <= e1; e += 4) {
+      a0 = fma(mval[e], xj[(size_t)mcol[e] * ncols], a0);
+      a1 = fma(mval[e + 1], xj[(size_t)mcol[e + 1] * ncols], a1);
+      a2 = fma(mval[e + 2], xj[(size_t)mcol[e + 2] * ncols], a2);
+      a3 = fma(mval[e + 3], xj[(size_t)mcol[e + 3] * ncols], a3);
+    }
+    for (; e < e1; ++e) a0 = fma(mval[e], xj[(size_t)mcol[e] * ncols], a0);
+    const double mx = (a0 + a1) + (a2 + a3);
+    if (jv) {
+      const size_t at = (size_t)i * ncols + j;
+      const double rv = b[at] - mx;
+      if (write_r) b[at] = rv;
+      rr = fma(rv, rv, rr);
+    }
+  }
+  sh[wv][lane] = rr;
+  __syncthreads();
+  if (threadIdx.x < SP_COLS && jv) {
+    double v = sh[0][lane];
+#pragma unroll
+    for (int u = 1; u < NW; ++u) v += sh[u][lane];
+    part[(size_t)blockIdx.x * ncols + j] = v;
+  }
+}
+
+// rz[j] = column sum of the second half of the partials (r.z)
+__global__ void __launch_bounds__(kBlock)
+k_cg_rz_reduce(const double* __restrict__ part, int nrb, int ncols, double* __restrict__ rz) {
+  __shared__ double sh[kBlock];
+  const int j = blockIdx.x * RED_COLS + threadIdx.x % RED_COLS;
+  const double v = column_sum(part, nrb, ncols, 1, j, sh);
+  if (j >= ncols || threadIdx.x >= RED_COLS) return;
+  rz[j] = v;
+}
+
 __global__ void __launch_bounds__(kBlock)
 k_cg_alpha(const double* __restrict__ part, int nrb, int ncols,
            const double* __restrict__ rz, const int32_t* __restrict__ done,
@@ -914,6 +969,38 @@ void launch_cg_init(hipStream_t s, const MeshDev& m, int32_t ncols, const double
   if (precond == DMC_PRECOND_CHOLESKY) launch_precond_apply(s, m, ncols, cb, cb.p);
   hipLaunchKernelGGL(k_cg_init_reduce, dim3((ncols + RED_COLS - 1) / RED_COLS, 2), dim3(kBlock), 0, s,
                      cb.part, nrb, ncols, cb.bnorm2, cb.rz, cb.done, cb.resid);
+}
+
+void launch_cg_norms(hipStream_t s, const MeshDev& m, int32_t ncols, const CgBuffers& cb) {
+  const int nrb = (int)cg_part_rows(m.n);
+  hipLaunchKernelGGL(k_cg_init_reduce, dim3((ncols + RED_COLS - 1) / RED_COLS, 1), dim3(kBlock), 0,
+                     s, cb.part, nrb, ncols, cb.bnorm2, cb.rz, cb.done, cb.resid);
+}
+
+void launch_cg_warm_start(hipStream_t s, const MeshDev& m, int32_t ncols, const CgBuffers& cb,
+                          double tol) {
+  const int nrb = (int)cg_part_rows(m.n);
+  dim3 sgrid(nrb, (ncols + SP_COLS - 1) / SP_COLS);
+  dim3 cgrid((ncols + RED_COLS - 1) / RED_COLS);
+  launch_chol_solve(s, m.chol, ncols, cb.r, cb.x, cb.W, cb.Y, cb.X, cb.U, cb.S);
+  prof::begin(s, DMC_KERNEL_CG_SPMM);
+  hipLaunchKernelGGL(k_cg_residual, sgrid, dim3(kBlock), 0, s, m.m_rowptr, m.m_col, m.m_val, m.n,
+                     ncols, cb.x, cb.r, 0, cb.part);
+  prof::end(s, DMC_KERNEL_CG_SPMM);
+  hipLaunchKernelGGL(k_cg_resid, cgrid, dim3(kBlock), 0, s, cb.part, nrb, ncols, cb.bnorm2,
+                     cb.done, cb.resid, tol);
+}
+
+void launch_cg_restart(hipStream_t s, const MeshDev& m, int32_t ncols, const CgBuffers& cb) {
+  const int nrb = (int)cg_part_rows(m.n);
+  dim3 sgrid(nrb, (ncols + SP_COLS - 1) / SP_COLS);
+  prof::begin(s, DMC_KERNEL_CG_SPMM);
+  hipLaunchKernelGGL(k_cg_residual, sgrid, dim3(kBlock), 0, s, m.m_rowptr, m.m_col, m.m_val, m.n,
+                     ncols, cb.x, cb.r, 1, cb.part);
+  prof::end(s, DMC_KERNEL_CG_SPMM);
+  launch_precond_apply(s, m, ncols, cb, cb.p);
+  hipLaunchKernelGGL(k_cg_rz_reduce, dim3((ncols + RED_COLS - 1) / RED_COLS), dim3(kBlock), 0, s,
+                     cb.part, nrb, ncols, cb.rz);
 }
 
 void launch_cg_step_a(hipStream_t s, const MeshDev& m, int32_t ncols, const CgBuffers& cb,

@@ -292,39 +292,110 @@ k_autocorr_bf16(const float* __restrict__ frames, int n, int T, int nw, int P,
 int pad_T(int T) { return T <= 32 ? 32 : 64; }
 
 
+constexpr int PJ_V = 64;  // vertices per projection block
+
 // ---------------------------------------------------------------------------
-// Projection (Eq. 9): Y_c[r][i] = sum_t U~_c[t][r] delta[t][i][c] for the k
-// kept rows.  Block = 3 waves over 64 vertices; wave c handles coordinate c, so
-// every U~ read is a wave-uniform LDS broadcast and the Y stores are
-// contiguous.  Each wave also reduces the min and max of its rows.
+// Fused encode: the projection of Eq. (9) computed straight from the frames,
+// with the delta coordinates of Eq. (3-4) formed on the fly in LDS and never
+// written to memory (the products are linear, so U~^T (L A^T)^T is the same
+// operation; each delta is still formed by its ring sum first).  Block = 64
+// vertices of one window; the window's frames go by tiles of PF_TT.  All
+// four waves form a tile's delta coordinates (lane = vertex, one 12- or
+// 24-byte xyz gather per ring member and frame, as k_delta), then waves 0-2
+// project it (wave c = coordinate c, as k_project) while the next tile is
+// being formed into the other LDS buffer.  Every delta is evaluated exactly
+// as k_delta does and rounded to the frames' type, and the sums run over the
+// frames in order as in k_project, so the coefficients are bit for bit those
+// of the two-kernel path.
 // ---------------------------------------------------------------------------
-constexpr int PJ_V = 64;
+constexpr int PF_TT = 8;  // frames per delta tile
 
 template <typename Real, int KMAX>
-__global__ void __launch_bounds__(192)
-k_project(const Real* __restrict__ delta, int n, int T, int k, const double* __restrict__ u_tilde,
-          Real* __restrict__ Y, double* __restrict__ mm) {
+__global__ void __launch_bounds__(kBlock)
+k_project_frames(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                 const double* __restrict__ wdeg, int uniform, int n, int T, int k,
+                 const Real* __restrict__ frames, const double* __restrict__ u_tilde,
+                 Real* __restrict__ Y, double* __restrict__ mm) {
   __shared__ Real Ut[3 * 64 * KMAX];
+  __shared__ Real D[2][PF_TT][3][PJ_V];
   const int w = blockIdx.y, blk = blockIdx.x;
-  const int c = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
   const double* ug = u_tilde + (size_t)w * 3 * T * k;
-  for (int e = threadIdx.x; e < 3 * T * k; e += 192) Ut[e] = (Real)ug[e];
-  __syncthreads();
+  for (int e = tid; e < 3 * T * k; e += kBlock) Ut[e] = (Real)ug[e];
   const int i = blk * PJ_V + lane;
   const bool valid = i < n;
+  int e0 = 0, e1 = 0;
+  double wi = 0.0;
+  if (valid) {
+    e0 = rowptr[i];
+    e1 = rowptr[i + 1];
+    wi = wdeg[i];
+  }
+  const int deg = e1 - e0;
+  int nb[DMAX];
+#pragma unroll
+  for (int d = 0; d < DMAX; ++d) nb[d] = d < deg ? col[e0 + d] : (valid ? i : 0);
+  const Real* fw = frames + (size_t)w * T * 3 * n;
+  const size_t fs = (size_t)3 * n;
+  // delta coordinates of tile `tile` into buffer `buf` (frames wave, wave + 4)
+  auto delta_tile = [&](int tile, int buf) {
+#pragma unroll
+    for (int q = 0; q < PF_TT / 4; ++q) {
+      const int tt = wave + 4 * q, t = tile * PF_TT + tt;
+      Xyz<Real> o{(Real)0, (Real)0, (Real)0};
+      if (valid && t < T) {
+        const Xyz<Real>* fr = (const Xyz<Real>*)(fw + (size_t)t * fs);
+        Xyz<Real> v[DMAX];
+#pragma unroll
+        for (int d = 0; d < DMAX; ++d) v[d] = fr[nb[d]];
+        double sx = 0.0, sy = 0.0, sz = 0.0;
+#pragma unroll
+        for (int d = 0; d < DMAX; ++d)
+          if (d < deg) {
+            sx += (double)v[d].x;
+            sy += (double)v[d].y;
+            sz += (double)v[d].z;
+          }
+        for (int e = e0 + DMAX; e < e1; ++e) {
+          const Xyz<Real> u = fr[col[e]];
+          sx += (double)u.x;
+          sy += (double)u.y;
+          sz += (double)u.z;
+        }
+        const Xyz<Real> own = fr[i];
+        o.x = (Real)(uniform ? (double)own.x - wi * sx : wi * (double)own.x - sx);
+        o.y = (Real)(uniform ? (double)own.y - wi * sy : wi * (double)own.y - sy);
+        o.z = (Real)(uniform ? (double)own.z - wi * sz : wi * (double)own.z - sz);
+      }
+      D[buf][tt][0][lane] = o.x;
+      D[buf][tt][1][lane] = o.y;
+      D[buf][tt][2][lane] = o.z;
+    }
+  };
   Real acc[KMAX];
 #pragma unroll
   for (int r = 0; r < KMAX; ++r) acc[r] = 0;
-  const Real* dw = delta + (size_t)w * T * 3 * n;
-  const Real* uc = Ut + c * T * k;
-  // eight frames' loads in flight at a time
-#pragma unroll 8
-  for (int t = 0; t < T; ++t) {
-    const Real d = valid ? dw[(size_t)t * 3 * n + 3 * (size_t)i + c] : (Real)0;
+  const int ntile = (T + PF_TT - 1) / PF_TT;
+  delta_tile(0, 0);
+  __syncthreads();
+  const int c = wave;  // coordinate of waves 0-2 in the projection
+  for (int tile = 0; tile < ntile; ++tile) {
+    const int buf = tile & 1;
+    if (tile + 1 < ntile) delta_tile(tile + 1, buf ^ 1);
+    if (c < 3) {
+      const Real* uc = Ut + c * T * k;
+      for (int tt = 0; tt < PF_TT; ++tt) {
+        const int t = tile * PF_TT + tt;
+        if (t >= T) break;
+        const Real d = D[buf][tt][c][lane];
 #pragma unroll
-    for (int r = 0; r < KMAX; ++r)
-      if (r < k) acc[r] += uc[t * k + r] * d;
+        for (int r = 0; r < KMAX; ++r)
+          if (r < k) acc[r] += uc[t * k + r] * d;
+      }
+    }
+    __syncthreads();
   }
+  if (c >= 3) return;
   Real* yw = Y + ((size_t)w * 3 + c) * k * n;
   const int nblk = gridDim.x;
   for (int r = 0; r < k; ++r) {
@@ -583,25 +654,28 @@ size_t project_scratch_bytes(int32_t n, int32_t T, int32_t k, int32_t nw, int32_
 }
 
 template <typename Real>
-static void project_impl(hipStream_t s, const void* delta, int32_t n, int32_t T, int32_t k,
-                         int32_t nw, int32_t coef_bits, const double* u_tilde, uint8_t* records,
-                         size_t rec_bytes, const RecordLayout& lay, void* scratch,
-                         void* coef_out) {
+static void project_impl(hipStream_t s, const MeshDev& m, const void* frames, int32_t T,
+                         int32_t k, int32_t nw, int32_t coef_bits, const double* u_tilde,
+                         uint8_t* records, size_t rec_bytes, const RecordLayout& lay,
+                         void* scratch, void* coef_out) {
+  const int n = m.n;
   const int nblk = (n + PJ_V - 1) / PJ_V;
   Real* Y = coef_out ? (Real*)coef_out : (Real*)scratch;
   double* mm = (double*)((uint8_t*)scratch +
                          align_up((size_t)nw * 3 * k * n * sizeof(Real)));
   dim3 grid(nblk, nw);
+  const int uni = m.laplacian == DMC_LAP_UNIFORM;
+  const Real* fr = (const Real*)frames;
   prof::begin(s, DMC_KERNEL_PROJECT);
   if (k <= 8)
-    hipLaunchKernelGGL((k_project<Real, 8>), grid, dim3(192), 0, s, (const Real*)delta, n, T, k,
-                       u_tilde, Y, mm);
+    hipLaunchKernelGGL((k_project_frames<Real, 8>), grid, dim3(kBlock), 0, s, m.rowptr, m.col,
+                       m.w64, uni, n, T, k, fr, u_tilde, Y, mm);
   else if (k <= 16)
-    hipLaunchKernelGGL((k_project<Real, 16>), grid, dim3(192), 0, s, (const Real*)delta, n, T,
-                       k, u_tilde, Y, mm);
+    hipLaunchKernelGGL((k_project_frames<Real, 16>), grid, dim3(kBlock), 0, s, m.rowptr, m.col,
+                       m.w64, uni, n, T, k, fr, u_tilde, Y, mm);
   else
-    hipLaunchKernelGGL((k_project<Real, 32>), grid, dim3(192), 0, s, (const Real*)delta, n, T,
-                       k, u_tilde, Y, mm);
+    hipLaunchKernelGGL((k_project_frames<Real, 32>), grid, dim3(kBlock), 0, s, m.rowptr, m.col,
+                       m.w64, uni, n, T, k, fr, u_tilde, Y, mm);
   prof::end(s, DMC_KERNEL_PROJECT);
   const int chunks = std::max(1, std::min(64, (n + 4 * kBlock - 1) / (4 * kBlock)));
   dim3 qgrid(chunks, 3 * k, nw);
@@ -612,15 +686,15 @@ static void project_impl(hipStream_t s, const void* delta, int32_t n, int32_t T,
   prof::end(s, DMC_KERNEL_QUANTISE);
 }
 
-void launch_project_quantise(hipStream_t s, const void* delta, int32_t n, int32_t T, int32_t k,
-                             int32_t nw, int32_t precision, int32_t coef_bits,
+void launch_project_quantise(hipStream_t s, const MeshDev& m, const void* frames, int32_t T,
+                             int32_t k, int32_t nw, int32_t precision, int32_t coef_bits,
                              const double* u_tilde, uint8_t* records, size_t rec_bytes,
                              const RecordLayout& lay, void* scratch, void* coef_out) {
   if (precision == DMC_FP64)
-    project_impl<double>(s, delta, n, T, k, nw, coef_bits, u_tilde, records, rec_bytes, lay,
+    project_impl<double>(s, m, frames, T, k, nw, coef_bits, u_tilde, records, rec_bytes, lay,
                          scratch, coef_out);
   else
-    project_impl<float>(s, delta, n, T, k, nw, coef_bits, u_tilde, records, rec_bytes, lay,
+    project_impl<float>(s, m, frames, T, k, nw, coef_bits, u_tilde, records, rec_bytes, lay,
                         scratch, coef_out);
 }
 
