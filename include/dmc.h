@@ -114,7 +114,22 @@ typedef struct {
   int32_t precond;       /* DMC_PRECOND_*                                      */
   double cg_tol;         /* stop a column when ||r|| <= tol ||b||              */
   int32_t init;          /* DMC_INIT_* (0 = DMC_INIT_PREV, Algorithm 1)        */
+  int32_t dict_mode;     /* DMC_DICT_PLAIN (0) or DMC_DICT_ADAPTIVE (1)        */
+  double coef_step;      /* 0: coef_bits for every kept row (Eq. 10); > 0: each
+                            row takes the fewest bits <= coef_bits whose step
+                            (hi - lo) / (2^b - 1) is at most coef_step        */
 } dmc_params;
+
+/* Dictionary coding (Sec. IV).  DMC_DICT_PLAIN: every entry of U_k coded with
+ * dict_bits over [-1, 1].  DMC_DICT_ADAPTIVE: each column of a window's U_k
+ * coded over its own range (float32, rounded outwards), either as its values
+ * or as its difference from the same column of the previous window's
+ * dequantised dictionary in the same sequence (the block-to-block coding the
+ * paper describes with Fig. 6), whichever needs fewer bits, with the fewest
+ * bits whose step is at most 2 / (2^dict_bits - 1), the plain code's; so no
+ * entry is coded less precisely than in the plain form.  A sequence's first
+ * window, and any window after one of another length, uses values only. */
+enum { DMC_DICT_PLAIN = 0, DMC_DICT_ADAPTIVE = 1 };
 
 /* Per-window statistics.  The bit rates follow Eq. (13) read per coordinate:
  * bits of the window's record part divided by 3 n T (vertices x frames x

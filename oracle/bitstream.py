@@ -108,10 +108,11 @@ def quantise_row(y, lo, hi, bits: int):
     return codes, dequantise_uniform(codes, lo, hi, bits)
 
 
-def quantise_rows_step(Y, step: float, fp32_data: bool):
+def quantise_rows_step(Y, step: float, fp32_data: bool, max_bits: int = 16):
     """Rows of Y (k x n) with the bits per row of a common step: per row the
-    stored range (as Eq. 10's), then bits_for_step, then quantise_row.
-    Returns (codes [k][n] uint16, ranges [k][2] float32, bits [k], deq)."""
+    stored range (as Eq. 10's), then bits_for_step (at most max_bits), then
+    quantise_row.  Returns (codes [k][n] uint16, ranges [k][2] float32,
+    bits [k], deq)."""
     k = Y.shape[0]
     codes = np.empty(Y.shape, dtype=np.uint16)
     ranges = np.empty((k, 2), dtype=np.float32)
@@ -121,7 +122,7 @@ def quantise_rows_step(Y, step: float, fp32_data: bool):
         row = Y[r].astype(np.float32) if fp32_data else Y[r]
         lo, hi = stored_range(row)
         ranges[r] = (lo, hi)
-        bits[r] = bits_for_step(lo, hi, step)
+        bits[r] = bits_for_step(lo, hi, step, max_bits)
         codes[r], deq[r] = quantise_row(row, lo, hi, int(bits[r]))
     return codes, ranges, bits, deq
 
@@ -182,3 +183,43 @@ def decode_dictionary(cols, prev_tilde, T: int, dict_bits: int):
         vals = np.full(T, np.float64(lo)) if b == 0 else dequantise_uniform(codes, lo, hi, b)
         Ut[:, j] = prev_tilde[:, j] + vals if mode == DICT_DIFFERENCE else vals
     return Ut
+
+
+# ---------------------------------------------------------------------------
+# the record's bits (Eq. 13 per coordinate, for the stream as laid out)
+# ---------------------------------------------------------------------------
+
+def _align256(x: int) -> int:
+    return (x + 255) // 256 * 256
+
+
+def _seg_words(count: int, bits: int, raw_bytes: int) -> int:
+    """Words of a segment of packed codes, or of raw values when bits is 0."""
+    if bits:
+        return words_for(count, bits)
+    w = (count * raw_bytes + 3) // 4
+    return w + (w & 1)
+
+
+def record_bits(n: int, T: int, k: int, n_anchors: int, coef_bits: int, anchor_bits: int,
+                dict_bits: int, raw_bytes: int, row_bits=None, dict_col_bits=None) -> dict:
+    """Bits of one window's record by part, per vertex, frame and coordinate
+    (divided by 3 n T), for the record layout: a 128-byte header; 16-byte
+    table entries for the 3 k dictionary columns and the 3 k coefficient rows;
+    three anchor ranges (8 bytes each); then, on 256-byte boundaries, the three
+    anchor segments and the variable part (dictionary columns, then rows).
+    Parts: q = row segments + row table, q_d = column segments + column
+    table, q_a = anchor segments + ranges, q_s = all used bytes (header and
+    alignment included).  row_bits / dict_col_bits: [3 k] bit widths (default:
+    coef_bits / dict_bits for all)."""
+    nq = 3 * k
+    rb = [coef_bits] * nq if row_bits is None else [int(b) for b in row_bits]
+    db = [dict_bits] * nq if dict_col_bits is None else [int(b) for b in dict_col_bits]
+    rows = sum(32 * _seg_words(n, b if coef_bits else 0, raw_bytes) for b in rb)
+    cols = sum(32 * _seg_words(T, b if dict_bits else 0, raw_bytes) for b in db)
+    aseg = 4 * _seg_words(T * n_anchors, anchor_bits, raw_bytes)
+    off_var = _align256(_align256(128 + 2 * nq * 16 + 24) + 3 * aseg)
+    used = off_var + (rows + cols) // 8
+    vf = 3.0 * n * T
+    return {"q": (rows + nq * 128) / vf, "q_d": (cols + nq * 128) / vf,
+            "q_a": 3 * (8 * aseg + 64) / vf, "q_s": 8.0 * used / vf}

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <array>
 #include <chrono>
 #include <cstring>
@@ -167,6 +168,14 @@ dmc_status check_params(const dmc_params* p, int32_t T, bool for_decode = false)
     return fail(DMC_ERR_INVALID_ARG, "precision must be DMC_FP64, DMC_FP32 or DMC_BF16");
   for (int32_t b : {p->coef_bits, p->anchor_bits, p->dict_bits})
     if (b < 0 || b > 16) return fail(DMC_ERR_INVALID_ARG, "bits must be in 0..16");
+  if (p->dict_mode != DMC_DICT_PLAIN && p->dict_mode != DMC_DICT_ADAPTIVE)
+    return fail(DMC_ERR_INVALID_ARG, "dict_mode must be DMC_DICT_PLAIN or DMC_DICT_ADAPTIVE");
+  if (p->dict_mode == DMC_DICT_ADAPTIVE && p->dict_bits < 1)
+    return fail(DMC_ERR_INVALID_ARG, "DMC_DICT_ADAPTIVE needs dict_bits >= 1");
+  if (!(p->coef_step >= 0.0) || !std::isfinite(p->coef_step))
+    return fail(DMC_ERR_INVALID_ARG, "coef_step must be finite and >= 0");
+  if (p->coef_step > 0.0 && p->coef_bits < 1)
+    return fail(DMC_ERR_INVALID_ARG, "coef_step needs coef_bits >= 1 (the widest row)");
   if (!for_decode) {
     if (p->init < DMC_INIT_PREV || p->init > DMC_INIT_LEARNED)
       return fail(DMC_ERR_INVALID_ARG, "unknown init");
@@ -187,24 +196,64 @@ dmc_status check_params(const dmc_params* p, int32_t T, bool for_decode = false)
 size_t real_size(int32_t precision) { return precision == DMC_FP64 ? 8 : 4; }
 
 // Bits per vertex per frame and coordinate of one window's record (Eq. 13
-// read per coordinate): q counts the coefficient codes and their row ranges,
-// q_a the anchor codes and their range, q_d the dictionary.
-void record_bpvf(const dmc::RecordLayout& l, double out[4]) {
+// read per coordinate), from a host copy of its header and tables: q counts
+// the coefficient rows' segments and their table entries, q_a the anchor
+// segments and ranges, q_d the dictionary columns' segments and table
+// entries, q_s the record's used bytes (header and alignment included).
+void record_bpvf(const dmc::RecordLayout& l, const uint8_t* head, double out[4]) {
   const double vf = 3.0 * l.n * l.T;
-  const double real_bits = 8.0 * l.real;
-  double q = 0.0, qa = 0.0, qd = 0.0;
-  for (int c = 0; c < 3; ++c) {
-    q += l.coef_bits > 0 ? (double)l.coef_bits * l.k * l.n + 64.0 * l.k : real_bits * l.k * l.n;
-    qa += l.anchor_bits > 0 ? (double)l.anchor_bits * l.T * l.nc + 64.0 : real_bits * l.T * l.nc;
-    qd += (l.dict_bits > 0 ? (double)l.dict_bits : real_bits) * l.T * l.k;
+  const uint32_t rl = (uint32_t)l.real;
+  const dmc::SegEntry* dt = (const dmc::SegEntry*)(head + l.off_dtab);
+  const dmc::SegEntry* rt = (const dmc::SegEntry*)(head + l.off_rtab);
+  double q = 0.0, qd = 0.0;
+  for (int e = 0; e < 3 * l.k; ++e) {
+    q += 32.0 * dmc::seg_words((uint32_t)l.n, rt[e].bits_mode & 0xffu, rl) + 8.0 * sizeof(dmc::SegEntry);
+    qd += 32.0 * dmc::seg_words((uint32_t)l.T, dt[e].bits_mode & 0xffu, rl) + 8.0 * sizeof(dmc::SegEntry);
   }
+  const double qa = 3.0 * (8.0 * l.anchor_seg + 64.0);
+  const int32_t* h = (const int32_t*)head;
+  const uint64_t used = (uint64_t)(uint32_t)h[dmc::kHdrUsedLo] |
+                        ((uint64_t)(uint32_t)h[dmc::kHdrUsedHi] << 32);
   out[0] = q / vf;
   out[1] = qa / vf;
   out[2] = qd / vf;
-  out[3] = out[0] + out[1] + out[2];
+  out[3] = 8.0 * (double)used / vf;
 }
 
-void fill_stats(dmc_window_stats* st, const dmc::StatsDev& s, const dmc::RecordLayout& l) {
+// Host copies of the header and tables (the first off_arange + 24 bytes) of
+// nw_full records of layout `full` at records + w * full.bytes and, if
+// `tail` is given, of one more record after them; synchronises the stream.
+dmc_status read_record_heads(dmc_ctx ctx, const uint8_t* records, int32_t nw_full,
+                             const dmc::RecordLayout& full, const dmc::RecordLayout* tail,
+                             std::vector<std::vector<uint8_t>>& heads) {
+  const size_t hf = full.off_arange + 24, ht = tail ? tail->off_arange + 24 : 0;
+  dmc_status st = ensure_pinned(ctx, (size_t)nw_full * hf + ht);
+  if (st != DMC_OK) return st;
+  uint8_t* h = (uint8_t*)ctx->pinned;
+  if (nw_full)
+    HIP_TRY(hipMemcpy2DAsync(h, hf, records, full.bytes, hf, nw_full, hipMemcpyDeviceToHost,
+                             ctx->stream));
+  if (tail)
+    HIP_TRY(hipMemcpyAsync(h + (size_t)nw_full * hf, records + (size_t)nw_full * full.bytes, ht,
+                           hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  heads.clear();
+  for (int32_t w = 0; w < nw_full; ++w) heads.emplace_back(h + w * hf, h + (w + 1) * hf);
+  if (tail) heads.emplace_back(h + (size_t)nw_full * hf, h + (size_t)nw_full * hf + ht);
+  return DMC_OK;
+}
+
+void fill_bits(dmc_window_stats* st, const dmc::RecordLayout& l, const uint8_t* head) {
+  double b[4];
+  record_bpvf(l, head, b);
+  st->q = b[0];
+  st->q_a = b[1];
+  st->q_d = b[2];
+  st->q_s = b[3];
+}
+
+void fill_stats(dmc_window_stats* st, const dmc::StatsDev& s, const dmc::RecordLayout& l,
+                const uint8_t* head) {
   st->T = l.T;
   st->k = l.k;
   for (int c = 0; c < 3; ++c) {
@@ -212,12 +261,7 @@ void fill_stats(dmc_window_stats* st, const dmc::StatsDev& s, const dmc::RecordL
     st->oi_resid[c] = s.resid[c];
     st->chol_shifts[c] = s.shifts[c];
   }
-  double b[4];
-  record_bpvf(l, b);
-  st->q = b[0];
-  st->q_a = b[1];
-  st->q_d = b[2];
-  st->q_s = b[3];
+  fill_bits(st, l, head);
 }
 
 // Algorithm 1 did not reach oi_tol for some coordinate of some window (its
@@ -244,14 +288,18 @@ dmc_status encode_chain(dmc_ctx ctx, const dmc::MeshDev& m, const void* frames, 
                         void* coef_out, uint8_t* ws,
                         dmc::StatsDev* stats_dev) {
   hipStream_t s = ctx->stream;
-  // scratch pieces (carved by the caller in this order)
+  // scratch pieces (chain_scratch_bytes counts them in this order)
   uint8_t* cur = ws;
   double* R = (double*)cur;
   cur += dmc::align_up((size_t)nw * 3 * T * T * 8);
   void* part = cur;
   cur += dmc::align_up(dmc::autocorr_scratch_bytes(m.n, T, nw, p.precision));
+  double* u_canon = (double*)cur;
+  cur += dmc::align_up((size_t)nw * 3 * T * k * 8);
   double* u_tilde = (double*)cur;
   cur += dmc::align_up((size_t)nw * 3 * T * k * 8);
+  double* apart = (double*)cur;
+  cur += dmc::anchors_scratch_bytes(nw);
   float* sk = nullptr;
   float* ql = nullptr;
   if (p.init == DMC_INIT_LEARNED) {
@@ -282,25 +330,23 @@ dmc_status encode_chain(dmc_ctx ctx, const dmc::MeshDev& m, const void* frames, 
   oa.T = T;
   oa.k = k;
   oa.precision = p.precision;
-  oa.dict_bits = p.dict_bits;
   oa.init = p.init;
   oa.ncoord = 3;
   oa.q_start = p.init == DMC_INIT_EXACT ? nullptr : q_start;
   oa.q_learned = ql;
   oa.u_out = u_out;
-  oa.u_tilde = u_tilde;
-  oa.records = records;
-  oa.rec_bytes = lay.bytes;
-  oa.off_dict = lay.off_dict;
+  oa.u_canon = u_canon;
   oa.max_sweeps = p.oi_max_sweeps;
   oa.tol = p.oi_tol;
   oa.stats = stats_dev;
   oa.ritz_qh = ritz_qh;
   oa.ritz_flag = ritz_flag;
   dmc::launch_oi(s, oa);
-  dmc::launch_project_quantise(s, m, frames, T, k, nw, p.precision, p.coef_bits, u_tilde, records,
-                               lay.bytes, lay, proj, coef_out);
-  dmc::launch_anchors(s, m, frames, T, nw, p.precision, p.anchor_bits, records, lay.bytes, lay);
+  dmc::launch_dict_code(s, u_canon, nw, lay, records, lay.bytes, u_tilde);
+  dmc::launch_project_quantise(s, m, frames, T, k, nw, p.precision, u_tilde, records, lay.bytes,
+                               lay, proj, coef_out);
+  dmc::launch_anchors(s, m, frames, T, nw, p.precision, records, lay.bytes, lay, apart);
+  dmc::launch_zero_tail(s, records, nw, lay.bytes);
   return check_launch("encode kernels");
 }
 
@@ -316,8 +362,8 @@ size_t chain_scratch_bytes(int32_t n, int32_t T, int32_t nw, int32_t k, int32_t 
                           : 0;
   return dmc::align_up((size_t)nw * 3 * T * T * 8) +
          dmc::align_up(dmc::autocorr_scratch_bytes(n, T, nw, precision)) +
-         dmc::align_up((size_t)nw * 3 * T * k * 8) + learned + ritz +
-         dmc::align_up(dmc::project_scratch_bytes(n, T, k, nw, precision));
+         2 * dmc::align_up((size_t)nw * 3 * T * k * 8) + dmc::anchors_scratch_bytes(nw) +
+         learned + ritz + dmc::align_up(dmc::project_scratch_bytes(n, T, k, nw, precision));
 }
 
 // The learned start needs a network registered for this window length and k.
@@ -332,14 +378,16 @@ dmc_status check_learned(dmc_ctx ctx, const dmc_params& p, int32_t T) {
 
 // Decoder buffers for ncols right-hand sides, carved from one region.
 struct DecodeLayout {
-  size_t o_x, o_r, o_p, o_q, o_part, o_small, o_z, o_W, o_Y, o_X, o_U, o_S, o_Ah, o_gram, total;
+  size_t o_x, o_r, o_p, o_q, o_part, o_small, o_z, o_W, o_Y, o_X, o_U, o_S, o_Ah, o_gram, o_ut,
+      total;
 };
 
 // ah_values, gram_values: doubles of the dense anchor values [nc][3F] and of
 // the partial Gram matrices of the reduced decode (0 for the full decode,
 // whose anchor values follow b)
+// ut_values: doubles of the decoded dictionaries
 DecodeLayout decode_layout(const dmc::MeshDev& m, int32_t ncols, bool chol,
-                           size_t ah_values = 0, size_t gram_values = 0) {
+                           size_t ah_values = 0, size_t gram_values = 0, size_t ut_values = 0) {
   const size_t vec = (size_t)m.n * ncols * 8;
   const size_t nrb = dmc::cg_part_rows(m.n);
   Carve cv;
@@ -360,6 +408,7 @@ DecodeLayout decode_layout(const dmc::MeshDev& m, int32_t ncols, bool chol,
   }
   d.o_Ah = cv.add(ah_values * 8);
   d.o_gram = cv.add(gram_values * 8);
+  d.o_ut = cv.add(ut_values * 8);
   d.total = cv.total();
   return d;
 }
@@ -392,7 +441,8 @@ DecodePlan decode_plan(const dmc::MeshDev& m, const dmc::SeqLayout& sl, const dm
   d.ncols = d.reduced ? nz : 3 * d.F;
   d.lay = decode_layout(m, d.ncols, p.precond == DMC_PRECOND_CHOLESKY,
                         d.reduced ? (size_t)m.nc * 3 * d.F : 0,
-                        d.reduced ? dmc::group_gram_doubles(m.n, sl) : 0);
+                        d.reduced ? dmc::group_gram_doubles(m.n, sl) : 0,
+                        dmc::dict_decode_doubles(sl));
   return d;
 }
 
@@ -427,6 +477,10 @@ void decode_enqueue_setup(hipStream_t s, const dmc::MeshDev& m, const uint8_t* r
                           const dmc::SeqLayout& sl, const dmc_params& p, const DecodePlan& d,
                           const dmc::CgBuffers& cb, uint8_t* ws, bool zero_x) {
   double* Ah = (double*)(ws + d.lay.o_Ah);
+  double* ut = (double*)(ws + d.lay.o_ut);
+  // the windows' dictionaries (in order: a column may be coded as the
+  // difference from the previous window's)
+  dmc::launch_dict_decode(s, records, sl, ut);
   // the right-hand side kernel also forms the b.b partials the Cholesky
   // start needs (the init kernel then has nothing left to do)
   double* bb = p.precond == DMC_PRECOND_CHOLESKY ? cb.part : nullptr;
@@ -435,7 +489,7 @@ void decode_enqueue_setup(hipStream_t s, const dmc::MeshDev& m, const uint8_t* r
     dmc::launch_rhs_reduced(s, m, d.ncols, cb.q, cb.r, bb);
     dmc::launch_anchor_values(s, m, records, sl, Ah);
   } else {
-    dmc::launch_back_project(s, m, records, sl, nullptr, cb.q);
+    dmc::launch_back_project(s, m, records, sl, ut, cb.q);
     dmc::launch_rhs(s, m, records, sl, cb.q, cb.r, bb);
   }
   if (p.precond == DMC_PRECOND_CHOLESKY)
@@ -445,15 +499,16 @@ void decode_enqueue_setup(hipStream_t s, const dmc::MeshDev& m, const uint8_t* r
   // the test on the reduced columns bounds every frame's full-system residual
   // (r still holds b here)
   if (d.reduced)
-    dmc::launch_group_ref(s, m, records, sl, cb.r, Ah, p.cg_tol, (double*)(ws + d.lay.o_gram),
-                          cb.bnorm2);
+    dmc::launch_group_ref(s, m, records, sl, ut, cb.r, Ah, p.cg_tol,
+                          (double*)(ws + d.lay.o_gram), cb.bnorm2);
 }
 
 void decode_enqueue_finish(hipStream_t s, const dmc::MeshDev& m, const uint8_t* records,
                            const dmc::SeqLayout& sl, const dmc_params& p, const DecodePlan& d,
-                           const dmc::CgBuffers& cb, const double* Ah, void* frames_out) {
+                           const dmc::CgBuffers& cb, const uint8_t* ws, void* frames_out) {
   if (d.reduced)
-    dmc::launch_compose(s, m, records, sl, cb.x, Ah, p.precision, frames_out);
+    dmc::launch_compose(s, m, records, sl, (const double*)(ws + d.lay.o_ut), cb.x,
+                        (const double*)(ws + d.lay.o_Ah), p.precision, frames_out);
   else
     dmc::launch_to_frames(s, cb.x, m.n, d.F, p.precision, frames_out);
 }
@@ -463,7 +518,6 @@ void decode_enqueue_fixed(hipStream_t s, const dmc::MeshDev& m, const uint8_t* r
                           uint8_t* ws, void* frames_out, int iters, double* summary) {
   const bool chol = p.precond == DMC_PRECOND_CHOLESKY;
   const dmc::CgBuffers cb = decode_buffers(ws, d.lay, d.ncols, chol);
-  double* Ah = (double*)(ws + d.lay.o_Ah);
   decode_enqueue_setup(s, m, records, sl, p, d, cb, ws, iters < 1);
   if (p.precond == DMC_PRECOND_CHOLESKY) {
     // iteration 1 is the start from the factor's solution; the later ones
@@ -483,7 +537,7 @@ void decode_enqueue_fixed(hipStream_t s, const dmc::MeshDev& m, const uint8_t* r
     }
   }
   dmc::launch_cg_summary(s, cb, d.ncols, summary);
-  decode_enqueue_finish(s, m, records, sl, p, d, cb, Ah, frames_out);
+  decode_enqueue_finish(s, m, records, sl, p, d, cb, ws, frames_out);
 }
 
 // Conjugate-gradient iterations on the system launch_cg_init set up, with a
@@ -532,7 +586,6 @@ dmc_status decode_all(dmc_ctx ctx, const dmc::MeshDev& m, const uint8_t* records
   if (st != DMC_OK) return st;
   uint8_t* ws = (uint8_t*)ctx->scratch;
   const dmc::CgBuffers cb = decode_buffers(ws, d.lay, ncols, chol);
-  double* Ah = (double*)(ws + d.lay.o_Ah);
 
   decode_enqueue_setup(s, m, records, sl, p, d, cb, ws, p.cg_max_iters < 1);
   st = check_launch("decode setup kernels");
@@ -559,7 +612,7 @@ dmc_status decode_all(dmc_ctx ctx, const dmc::MeshDev& m, const uint8_t* records
     };
     dmc::launch_cg_warm_start(s, m, ncols, cb, p.cg_tol);
     it = 1;
-    decode_enqueue_finish(s, m, records, sl, p, d, cb, Ah, frames_out);
+    decode_enqueue_finish(s, m, records, sl, p, d, cb, ws, frames_out);
     st = check_launch("cg kernels and frames");
     if (st != DMC_OK) return st;
     st = read_flags();
@@ -575,7 +628,7 @@ dmc_status decode_all(dmc_ctx ctx, const dmc::MeshDev& m, const uint8_t* records
         st = read_flags();
         if (st != DMC_OK) return st;
       }
-      decode_enqueue_finish(s, m, records, sl, p, d, cb, Ah, frames_out);
+      decode_enqueue_finish(s, m, records, sl, p, d, cb, ws, frames_out);
       st = check_launch("frames");
       if (st != DMC_OK) return st;
       HIP_TRY(hipStreamSynchronize(s));
@@ -583,7 +636,7 @@ dmc_status decode_all(dmc_ctx ctx, const dmc::MeshDev& m, const uint8_t* records
   } else {
     st = cg_iterate(ctx, m, ncols, cb, p.precond, p.cg_tol, p.cg_max_iters, &it, &all_done);
     if (st != DMC_OK) return st;
-    decode_enqueue_finish(s, m, records, sl, p, d, cb, Ah, frames_out);
+    decode_enqueue_finish(s, m, records, sl, p, d, cb, ws, frames_out);
     st = check_launch("frames");
     if (st != DMC_OK) return st;
     HIP_TRY(hipMemcpyAsync(h_res, cb.resid, (size_t)ncols * 8, hipMemcpyDeviceToHost, s));
@@ -671,19 +724,20 @@ RecordLayout record_layout(int32_t n, int32_t T, int32_t k, int32_t nc, const dm
   l.anchor_bits = p.anchor_bits;
   l.dict_bits = p.dict_bits;
   l.precision = p.precision;
+  l.dict_mode = p.dict_mode;
+  l.coef_step = p.coef_bits > 0 ? p.coef_step : 0.0;
   l.real = real_size(p.precision);
-  size_t off = align_up(64);
-  l.off_dict = off;
-  off += align_up((size_t)3 * T * k * (p.dict_bits > 0 ? 2 : l.real));
-  l.off_ranges = off;
-  off += align_up((size_t)3 * k * 2 * 4);
-  l.off_codes = off;
-  off += align_up((size_t)3 * k * n * (p.coef_bits > 0 ? 2 : l.real));
-  l.off_arange = off;
-  off += align_up((size_t)3 * 2 * 4);
-  l.off_anchors = off;
-  off += align_up((size_t)3 * T * nc * (p.anchor_bits > 0 ? 2 : l.real));
-  l.bytes = off;
+  const uint32_t rl = (uint32_t)l.real;
+  l.off_dtab = kHeaderBytes;
+  l.off_rtab = l.off_dtab + (size_t)3 * k * sizeof(SegEntry);
+  l.off_arange = l.off_rtab + (size_t)3 * k * sizeof(SegEntry);
+  l.off_anchors = align_up(l.off_arange + 3 * 8);
+  l.anchor_seg = 4 * (size_t)seg_words((uint32_t)(T * nc), (uint32_t)p.anchor_bits, rl);
+  l.off_var = align_up(l.off_anchors + 3 * l.anchor_seg);
+  // every segment at its widest
+  l.bytes = align_up(l.off_var + 4 * (size_t)3 * k *
+                                     (seg_words((uint32_t)T, (uint32_t)p.dict_bits, rl) +
+                                      seg_words((uint32_t)n, (uint32_t)p.coef_bits, rl)));
   return l;
 }
 
@@ -1018,6 +1072,10 @@ size_t dmc_sequence_code_bytes(int32_t n, int32_t F, int32_t T, int32_t n_anchor
   return b;
 }
 
+}  // extern "C"
+
+namespace {
+
 // Scratch of one window's encode: the chain's pieces (autocorrelation
 // partials, R, dictionary, coefficients), and the window's stats when the
 // caller's array holds them too (o_stats).
@@ -1052,13 +1110,16 @@ dmc_status encode_window_on(dmc_ctx ctx, const dmc::MeshDev& m, const void* fram
   HIP_TRY(hipMemcpyAsync(ctx->pinned, sd, sizeof(dmc::StatsDev), hipMemcpyDeviceToHost,
                          ctx->stream));
   HIP_TRY(hipStreamSynchronize(ctx->stream));
-  const dmc::StatsDev* hs = (const dmc::StatsDev*)ctx->pinned;
+  const dmc::StatsDev hs = *(const dmc::StatsDev*)ctx->pinned;
   if (stats) {
+    std::vector<std::vector<uint8_t>> heads;
+    st = read_record_heads(ctx, (const uint8_t*)code, 1, lay, nullptr, heads);
+    if (st != DMC_OK) return st;
     std::memset(stats, 0, sizeof(*stats));
-    fill_stats(stats, *hs, lay);
+    fill_stats(stats, hs, lay, heads[0].data());
     stats->ms_encode = elapsed_ms(ctx->ev[0], ctx->ev[1]);
   }
-  if (oi_not_converged(hs, 1, p.oi_tol))
+  if (oi_not_converged(&hs, 1, p.oi_tol))
     return fail(DMC_ERR_NOT_CONVERGED, "orthogonal iterations ended above oi_tol");
   return DMC_OK;
 }
@@ -1071,6 +1132,10 @@ dmc_status check_encode_window(dmc_ctx ctx, dmc_mesh mesh, const void* frames, i
   if (params->k > T) return fail(DMC_ERR_INVALID_ARG, "k must not exceed T");
   return check_learned(ctx, *params, T);
 }
+
+}  // namespace
+
+extern "C" {
 
 dmc_status dmc_encode_window(dmc_ctx ctx, dmc_mesh mesh, const void* frames, int32_t T,
                              const dmc_params* params, const void* q_start, void* code,
@@ -1125,7 +1190,7 @@ static dmc::SeqLayout seq_layout(int32_t n, int32_t F, int32_t T, int32_t nc, co
 // window's header (written by k_header) is read back and compared with them
 // before any decode kernel runs.
 dmc_status check_headers(dmc_ctx ctx, const dmc::MeshDev& m, const uint8_t* records,
-                         const dmc::SeqLayout& sl) {
+                         const dmc::SeqLayout& sl, bool standalone = false) {
   const int32_t nw = sl.nw_full + (sl.T_tail ? 1 : 0);
   dmc_status st = ensure_pinned(ctx, (size_t)nw * 64);
   if (st != DMC_OK) return st;
@@ -1140,17 +1205,28 @@ dmc_status check_headers(dmc_ctx ctx, const dmc::MeshDev& m, const uint8_t* reco
   HIP_TRY(hipStreamSynchronize(ctx->stream));
   for (int32_t w = 0; w < nw; ++w) {
     const dmc::RecordLayout& l = w < sl.nw_full ? sl.full : sl.tail;
-    int32_t hd[9];
+    int32_t hd[16];
     std::memcpy(hd, h + (size_t)w * 64, sizeof(hd));
-    const int32_t want[9] = {dmc::kRecordMagic, l.T,         l.k,        m.n,        m.nc,
-                             l.coef_bits,       l.anchor_bits, l.dict_bits, l.precision};
-    static const char* what[9] = {"magic", "T", "k", "n", "n_c", "coef_bits", "anchor_bits",
-                                  "dict_bits", "precision"};
-    for (int f = 0; f < 9; ++f)
+    const int32_t want[10] = {dmc::kRecordMagic, l.T,          l.k,         m.n,         m.nc,
+                              l.coef_bits,       l.anchor_bits, l.dict_bits, l.precision, l.dict_mode};
+    static const char* what[10] = {"magic",       "T",         "k",         "n",
+                                   "n_c",         "coef_bits", "anchor_bits", "dict_bits",
+                                   "precision",   "dict_mode"};
+    for (int f = 0; f < 10; ++f)
       if (hd[f] != want[f])
         return fail(DMC_ERR_INVALID_ARG, "record of window " + std::to_string(w) + ": header " +
                                              what[f] + " = " + std::to_string(hd[f]) +
                                              ", the call expects " + std::to_string(want[f]));
+    uint64_t step_bits;
+    std::memcpy(&step_bits, &hd[dmc::kHdrStepLo], 8);
+    double step;
+    std::memcpy(&step, &step_bits, 8);
+    if (step != l.coef_step)
+      return fail(DMC_ERR_INVALID_ARG, "record of window " + std::to_string(w) +
+                                           ": coef_step differs from the call's");
+    if (standalone && hd[dmc::kHdrHasDiff])
+      return fail(DMC_ERR_INVALID_ARG, "the record codes its dictionary as differences from "
+                                       "the previous window's: decode it with its sequence");
   }
   return DMC_OK;
 }
@@ -1162,7 +1238,7 @@ dmc_status dmc_decode_window(dmc_ctx ctx, dmc_mesh mesh, const void* code, int32
   if (st != DMC_OK) return st;
   HIP_TRY(hipSetDevice(ctx->device));
   const dmc::SeqLayout sl = seq_layout(mesh->dev.n, T, T, mesh->dev.nc, *params);
-  st = check_headers(ctx, mesh->dev, (const uint8_t*)code, sl);
+  st = check_headers(ctx, mesh->dev, (const uint8_t*)code, sl, true);
   if (st != DMC_OK) return st;
   int32_t iters = 0;
   double res = 0.0;
@@ -1172,15 +1248,13 @@ dmc_status dmc_decode_window(dmc_ctx ctx, dmc_mesh mesh, const void* code, int32
   if (stats) {
     HIP_TRY(hipEventRecord(ctx->ev[2], ctx->stream));
     HIP_TRY(hipEventSynchronize(ctx->ev[2]));
+    std::vector<std::vector<uint8_t>> heads;
+    dmc_status hst = read_record_heads(ctx, (const uint8_t*)code, 1, sl.full, nullptr, heads);
+    if (hst != DMC_OK) return hst;
     std::memset(stats, 0, sizeof(*stats));
     stats->T = T;
     stats->k = std::min(params->k, T);
-    double b[4];
-    record_bpvf(sl.full, b);
-    stats->q = b[0];
-    stats->q_a = b[1];
-    stats->q_d = b[2];
-    stats->q_s = b[3];
+    fill_bits(stats, sl.full, heads[0].data());
     stats->cg_iters = iters;
     stats->cg_resid = res;
     stats->ms_decode = elapsed_ms(ctx->ev[1], ctx->ev[2]);
@@ -1209,17 +1283,16 @@ dmc_status dmc_decode_sequence(dmc_ctx ctx, dmc_mesh mesh, const void* codes, in
     HIP_TRY(hipEventSynchronize(ctx->ev[2]));
     const float ms = elapsed_ms(ctx->ev[1], ctx->ev[2]);
     const int nw = sl.nw_full + (sl.T_tail ? 1 : 0);
+    std::vector<std::vector<uint8_t>> heads;
+    dmc_status hst = read_record_heads(ctx, (const uint8_t*)codes, sl.nw_full, sl.full,
+                                       sl.T_tail ? &sl.tail : nullptr, heads);
+    if (hst != DMC_OK) return hst;
     for (int w = 0; w < nw; ++w) {
       const dmc::RecordLayout& l = w < sl.nw_full ? sl.full : sl.tail;
       std::memset(&per_window[w], 0, sizeof(dmc_window_stats));
       per_window[w].T = l.T;
       per_window[w].k = l.k;
-      double b[4];
-      record_bpvf(l, b);
-      per_window[w].q = b[0];
-      per_window[w].q_a = b[1];
-      per_window[w].q_d = b[2];
-      per_window[w].q_s = b[3];
+      fill_bits(&per_window[w], l, heads[w].data());
       per_window[w].cg_iters = iters;
       per_window[w].cg_resid = res;
       per_window[w].ms_decode = ms;
@@ -1322,10 +1395,14 @@ dmc_status dmc_compress_sequence(dmc_ctx ctx, dmc_mesh mesh, const void* frames,
   if (per_window) {
     const float ms_enc = elapsed_ms(ctx->ev[0], ctx->ev[1]);
     const float ms_dec = frames_out ? elapsed_ms(ctx->ev[1], ctx->ev[2]) : 0.f;
+    std::vector<std::vector<uint8_t>> heads;
+    st = read_record_heads(ctx, (const uint8_t*)codes, sl.nw_full, sl.full,
+                           sl.T_tail ? &sl.tail : nullptr, heads);
+    if (st != DMC_OK) return st;
     for (int w = 0; w < nw; ++w) {
       std::memset(&per_window[w], 0, sizeof(dmc_window_stats));
       const bool tail = w >= sl.nw_full;
-      fill_stats(&per_window[w], hs[w], tail ? sl.tail : sl.full);
+      fill_stats(&per_window[w], hs[w], tail ? sl.tail : sl.full, heads[w].data());
       per_window[w].cg_iters = iters;
       per_window[w].cg_resid = res;
       per_window[w].ms_encode = ms_enc;
@@ -1495,14 +1572,12 @@ dmc_status dmc_oi_blocks(dmc_ctx ctx, const double* R, int32_t nb, int32_t T,
   oa.T = T;
   oa.k = p.k;
   oa.precision = DMC_FP64;  // blocks and outputs are float64
-  oa.dict_bits = 0;
   oa.init = p.init;
   oa.ncoord = 1;
   oa.q_start = p.init == DMC_INIT_EXACT ? nullptr : q_start;
   oa.q_learned = learned ? (const float*)(ws + o_q) : nullptr;
   oa.u_out = U_out;
-  oa.u_tilde = nullptr;
-  oa.records = nullptr;
+  oa.u_canon = nullptr;
   oa.max_sweeps = p.oi_max_sweeps;
   oa.tol = p.oi_tol;
   oa.stats = (dmc::StatsDev*)ctx->stats;
@@ -1535,7 +1610,8 @@ struct BatchSeq {
   uint8_t* codes = nullptr;
   void* out = nullptr;
   dmc::SeqLayout sl{};
-  size_t o_R = 0, o_Rt = 0, o_ut = 0, o_utt = 0;
+  size_t o_R = 0, o_Rt = 0, o_ut = 0, o_utt = 0;  // covariances, canonical U (full, tail)
+  size_t o_ud = 0, o_udt = 0, o_ap = 0, o_apt = 0;  // dequantised dictionaries, anchor partials
   int32_t stats_off = 0;  // first window in the batch's stats array
   int P = 0;              // tuned launch shape
 };
@@ -1579,20 +1655,27 @@ void batch_enqueue(dmc_batch b, hipStream_t s) {
   for (BatchSeq& q : b->seq) {
     const dmc::MeshDev& m = q.mesh->dev;
     if (q.sl.nw_full) {
-      dmc::launch_project_quantise(s, m, q.frames, q.T, q.k_full, q.sl.nw_full, b->precision,
-                                   q.p.coef_bits, (const double*)(b->buf + q.o_ut), q.codes,
-                                   q.sl.full.bytes, q.sl.full, shared, nullptr);
-      dmc::launch_anchors(s, m, q.frames, q.T, q.sl.nw_full, b->precision, q.p.anchor_bits,
-                          q.codes, q.sl.full.bytes, q.sl.full);
+      double* ud = (double*)(b->buf + q.o_ud);
+      dmc::launch_dict_code(s, (const double*)(b->buf + q.o_ut), q.sl.nw_full, q.sl.full, q.codes,
+                            q.sl.full.bytes, ud);
+      dmc::launch_project_quantise(s, m, q.frames, q.T, q.k_full, q.sl.nw_full, b->precision, ud,
+                                   q.codes, q.sl.full.bytes, q.sl.full, shared, nullptr);
+      dmc::launch_anchors(s, m, q.frames, q.T, q.sl.nw_full, b->precision, q.codes,
+                          q.sl.full.bytes, q.sl.full, (double*)(b->buf + q.o_ap));
+      dmc::launch_zero_tail(s, q.codes, q.sl.nw_full, q.sl.full.bytes);
     }
     if (q.sl.T_tail) {
       const size_t f0 = (size_t)q.sl.nw_full * q.T;
       uint8_t* rec = q.codes + (size_t)q.sl.nw_full * q.sl.full.bytes;
+      double* ud = (double*)(b->buf + q.o_udt);
+      dmc::launch_dict_code(s, (const double*)(b->buf + q.o_utt), 1, q.sl.tail, rec,
+                            q.sl.tail.bytes, ud);
       dmc::launch_project_quantise(s, m, q.frames + f0 * 3 * m.n * rs, q.sl.T_tail, q.k_tail, 1,
-                                   b->precision, q.p.coef_bits, (const double*)(b->buf + q.o_utt),
-                                   rec, q.sl.tail.bytes, q.sl.tail, shared, nullptr);
-      dmc::launch_anchors(s, m, q.frames + f0 * 3 * m.n * rs, q.sl.T_tail, 1, b->precision,
-                          q.p.anchor_bits, rec, q.sl.tail.bytes, q.sl.tail);
+                                   b->precision, ud, rec, q.sl.tail.bytes, q.sl.tail, shared,
+                                   nullptr);
+      dmc::launch_anchors(s, m, q.frames + f0 * 3 * m.n * rs, q.sl.T_tail, 1, b->precision, rec,
+                          q.sl.tail.bytes, q.sl.tail, (double*)(b->buf + q.o_apt));
+      dmc::launch_zero_tail(s, rec, 1, q.sl.tail.bytes);
     }
   }
   double* summary = (double*)(b->buf + b->o_summary);
@@ -1673,11 +1756,14 @@ dmc_status dmc_batch_create(dmc_ctx ctx, int32_t nseq, const dmc_mesh* meshes,
     q.sl = seq_layout(m.n, q.F, q.T, m.nc, p);
     q.k_full = std::min(p.k, q.T);
     q.k_tail = q.sl.T_tail ? std::min(p.k, q.sl.T_tail) : 0;
-    const size_t rs = real_size(b->precision);
     q.o_R = cv.add((size_t)q.sl.nw_full * 3 * q.T * q.T * 8);
     q.o_ut = cv.add((size_t)q.sl.nw_full * 3 * q.T * q.k_full * 8);
     q.o_Rt = cv.add((size_t)3 * q.sl.T_tail * q.sl.T_tail * 8);
     q.o_utt = cv.add((size_t)3 * q.sl.T_tail * q.k_tail * 8);
+    q.o_ud = cv.add((size_t)q.sl.nw_full * 3 * q.T * q.k_full * 8);
+    q.o_udt = cv.add((size_t)3 * q.sl.T_tail * q.k_tail * 8);
+    q.o_ap = cv.add(dmc::anchors_scratch_bytes(std::max(1, q.sl.nw_full)));
+    q.o_apt = cv.add(dmc::anchors_scratch_bytes(1));
     q.stats_off = (int32_t)nwin;
     nwin += q.sl.nw_full + (q.sl.T_tail ? 1 : 0);
     // shared region: the largest autocorrelation partials (any tuned split),
@@ -1722,16 +1808,12 @@ dmc_status dmc_batch_create(dmc_ctx ctx, int32_t nseq, const dmc_mesh* meshes,
       a.T = tail ? q.sl.T_tail : q.T;
       a.k = tail ? q.k_tail : q.k_full;
       a.precision = b->precision;
-      a.dict_bits = q.p.dict_bits;
       a.init = tail ? DMC_INIT_EXACT : q.p.init;
       a.ncoord = 3;
       a.q_start = (tail || q.p.init == DMC_INIT_EXACT) ? nullptr : q.q_start;
       a.q_learned = nullptr;
       a.u_out = nullptr;
-      a.u_tilde = (double*)(b->buf + (tail ? q.o_utt : q.o_ut));
-      a.records = q.codes + (tail ? (size_t)q.sl.nw_full * q.sl.full.bytes : 0);
-      a.rec_bytes = tail ? q.sl.tail.bytes : q.sl.full.bytes;
-      a.off_dict = tail ? q.sl.tail.off_dict : q.sl.full.off_dict;
+      a.u_canon = (double*)(b->buf + (tail ? q.o_utt : q.o_ut));
       a.max_sweeps = q.p.oi_max_sweeps;
       a.tol = q.p.oi_tol;
       a.stats = stats + q.stats_off + (tail ? q.sl.nw_full : 0);
@@ -1845,19 +1927,24 @@ dmc_status dmc_batch_stats(dmc_batch b, int32_t i, dmc_window_stats* per_window)
   HIP_TRY(hipMemcpyAsync(h + sizeof(dmc::StatsDev) * nw, b->buf + b->o_summary + 16 * i, 16,
                          hipMemcpyDeviceToHost, b->ctx->stream));
   HIP_TRY(hipStreamSynchronize(b->ctx->stream));
-  const dmc::StatsDev* hs = (const dmc::StatsDev*)h;
-  const double* sum = (const double*)(h + sizeof(dmc::StatsDev) * nw);
+  std::vector<dmc::StatsDev> hs((const dmc::StatsDev*)h, (const dmc::StatsDev*)h + nw);
+  double sum[2];
+  std::memcpy(sum, h + sizeof(dmc::StatsDev) * nw, sizeof(sum));
+  std::vector<std::vector<uint8_t>> heads;
+  st = read_record_heads(b->ctx, q.codes, q.sl.nw_full, q.sl.full,
+                         q.sl.T_tail ? &q.sl.tail : nullptr, heads);
+  if (st != DMC_OK) return st;
   for (int32_t w = 0; w < nw; ++w) {
     std::memset(&per_window[w], 0, sizeof(dmc_window_stats));
     const bool tail = w >= q.sl.nw_full;
-    fill_stats(&per_window[w], hs[w], tail ? q.sl.tail : q.sl.full);
+    fill_stats(&per_window[w], hs[w], tail ? q.sl.tail : q.sl.full, heads[w].data());
     per_window[w].cg_iters = q.out ? q.p.cg_max_iters : 0;
     per_window[w].cg_resid = q.out ? sum[0] : 0.0;
   }
   if (q.out && sum[1] == 0.0)
     return fail(DMC_ERR_NOT_CONVERGED, "sequence " + std::to_string(i) +
                                            ": some column did not reach cg_tol");
-  if (oi_not_converged(hs, nw, q.p.oi_tol))
+  if (oi_not_converged(hs.data(), nw, q.p.oi_tol))
     return fail(DMC_ERR_NOT_CONVERGED, "sequence " + std::to_string(i) +
                                            ": orthogonal iterations ended above oi_tol");
   return DMC_OK;

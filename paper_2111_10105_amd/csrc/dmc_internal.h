@@ -18,15 +18,59 @@ constexpr size_t kAlign = 256;
 
 inline size_t align_up(size_t x, size_t a = kAlign) { return (x + a - 1) / a * a; }
 
-// First word of every window record ("DMC1" in memory order).
-constexpr int32_t kRecordMagic = 0x31434d44;
+// First word of every window record ("DMC2" in memory order).
+constexpr int32_t kRecordMagic = 0x32434d44;
 
-// Byte layout of one window record (see dmc.h).
+// Header words of a record (int32 each, 128 bytes in all; see dmc.h).
+enum RecordHeader {
+  kHdrMagic = 0, kHdrT, kHdrK, kHdrN, kHdrNc, kHdrCoefBits, kHdrAnchorBits, kHdrDictBits,
+  kHdrPrecision, kHdrDictMode, kHdrHasDiff, kHdrUsedLo, kHdrUsedHi, kHdrDictWords,
+  kHdrStepLo, kHdrStepHi, kHeaderBytes = 128
+};
+
+// One entry of a record's dictionary-column or coefficient-row table: the
+// range of the coded values (float32), the bit width (low byte) and, for a
+// dictionary column, its mode (second byte: 0 values, 1 difference from the
+// previous window's column), and the first 32-bit word of its segment in the
+// record's variable part.
+struct SegEntry {
+  float lo, hi;
+  uint32_t bits_mode;
+  uint32_t word_off;
+};
+
+// 32-bit words of a segment of `count` codes of `bits` bits (bits = 0: raw
+// values of `real` bytes), rounded up to an even count (8-byte boundary).
+__host__ __device__ inline uint32_t seg_words(uint32_t count, uint32_t bits, uint32_t real) {
+  const uint64_t w = bits ? ((uint64_t)count * bits + 31) / 32 : ((uint64_t)count * real + 3) / 4;
+  return (uint32_t)(w + (w & 1));
+}
+
+// code j of a packed segment (bit j b of the segment's bit string, least
+// significant bit first; b <= 16); the second word is read only when the
+// code reaches into it
+__device__ inline uint32_t get_code(const uint32_t* __restrict__ seg, uint32_t j, uint32_t bits) {
+  const uint64_t pos = (uint64_t)j * bits;
+  const uint32_t w = (uint32_t)(pos >> 5), sh = (uint32_t)(pos & 31);
+  uint64_t v = seg[w];
+  if (sh + bits > 32) v |= (uint64_t)seg[w + 1] << 32;
+  return (uint32_t)(v >> sh) & ((1u << bits) - 1u);
+}
+
+// Byte layout of one window record (see dmc.h).  The fixed part holds the
+// header, the dictionary-column table [3][k], the coefficient-row table
+// [3][k], the anchor ranges [3] and the anchor segments [3]; the variable
+// part (from off_var) holds the dictionary segments and then the coefficient
+// rows, packed back to back at the offsets the tables give.  `bytes` is the
+// capacity: every segment at its widest (dict_bits, coef_bits).
 struct RecordLayout {
   int32_t T = 0, k = 0, n = 0, nc = 0;
   int32_t coef_bits = 0, anchor_bits = 0, dict_bits = 0, precision = 0;
+  int32_t dict_mode = 0;
+  double coef_step = 0.0;
   size_t real = 8;            // bytes per raw value
-  size_t off_dict = 0, off_ranges = 0, off_codes = 0, off_arange = 0, off_anchors = 0;
+  size_t off_dtab = 0, off_rtab = 0, off_arange = 0, off_anchors = 0, anchor_seg = 0;
+  size_t off_var = 0;
   size_t bytes = 0;
 };
 
@@ -108,16 +152,12 @@ struct OiArgs {
   const double* R;       // [nw][3][T][T]
   int32_t nw, T, k;
   int32_t precision;
-  int32_t dict_bits;
   int32_t init;          // DMC_INIT_*
   int32_t ncoord;        // blocks per window: 3 (x, y, z), or 1 for independent blocks
   const void* q_start;   // per init: [3][T][k], [nw][3][T][k] or Omega [T][k] (real)
   const float* q_learned;  // DMC_INIT_LEARNED: [nw][ncoord][T][k] predicted starts
   void* u_out;           // [nw][ncoord][T][k] real (may be nullptr)
-  double* u_tilde;       // [nw][ncoord][T][k] float64 dequantised dictionary (or nullptr)
-  uint8_t* records;      // record of window w at records + w*rec_bytes (or nullptr)
-  size_t rec_bytes;
-  size_t off_dict;
+  double* u_canon;       // [nw][ncoord][T][k] float64 canonical U (or nullptr)
   int32_t max_sweeps;
   double tol;
   StatsDev* stats;       // [nw]
@@ -158,16 +198,28 @@ void launch_mlp_adam(hipStream_t s, float* theta, const float* grad, float* m, f
 // Projection (Eq. 9) of the delta coordinates (Eq. 3-4, formed on the fly
 // from the frames [nw*T][n][3], never stored) + per-row ranges +
 // quantisation (Eq. 10) for nw windows.
+// The coefficient rows go into the records packed at the bits of their
+// row table (k_row_table, after the dictionary segments).
 size_t project_scratch_bytes(int32_t n, int32_t T, int32_t k, int32_t nw, int32_t precision);
 void launch_project_quantise(hipStream_t s, const MeshDev& m, const void* frames, int32_t T,
-                             int32_t k, int32_t nw, int32_t precision, int32_t coef_bits,
-                             const double* u_tilde, uint8_t* records, size_t rec_bytes,
-                             const RecordLayout& lay, void* scratch, void* coef_out);
+                             int32_t k, int32_t nw, int32_t precision, const double* u_tilde,
+                             uint8_t* records, size_t rec_bytes, const RecordLayout& lay,
+                             void* scratch, void* coef_out);
 
-// Anchor values of nw windows (Eq. 12): gather + quantisation into records.
+// Anchor values of nw windows (Eq. 12): gather + quantisation into records;
+// part: anchors_scratch_bytes(nw) bytes.
+size_t anchors_scratch_bytes(int32_t nw);
 void launch_anchors(hipStream_t s, const MeshDev& m, const void* frames, int32_t T, int32_t nw,
-                    int32_t precision, int32_t anchor_bits, uint8_t* records, size_t rec_bytes,
-                    const RecordLayout& lay);
+                    int32_t precision, uint8_t* records, size_t rec_bytes, const RecordLayout& lay,
+                    double* part);
+
+// Dictionary of nw windows from their canonical U (u_canon [nw][3][T][k]
+// float64): column table, packed segments and header words of each record,
+// and the dequantised dictionary u_tilde [nw][3][T][k] the projection uses.
+void launch_dict_code(hipStream_t s, const double* u_canon, int32_t nw, const RecordLayout& lay,
+                      uint8_t* records, size_t rec_bytes, double* u_tilde);
+// zeros after each record's used bytes (run last)
+void launch_zero_tail(hipStream_t s, uint8_t* records, int32_t nw, size_t rec_bytes);
 
 void launch_write_header(hipStream_t s, uint8_t* rec, const RecordLayout& lay);
 
@@ -181,8 +233,12 @@ struct SeqLayout {
   RecordLayout full, tail;
   size_t rec_bytes_full;
 };
+// The dequantised dictionaries of every window, ut [window][3][T][k]
+// (dict_decode_doubles(sl) doubles), which the decode kernels below read.
+size_t dict_decode_doubles(const SeqLayout& sl);
+void launch_dict_decode(hipStream_t s, const uint8_t* records, const SeqLayout& sl, double* ut);
 void launch_back_project(hipStream_t s, const MeshDev& m, const uint8_t* records,
-                         const SeqLayout& sl, const double* u_tilde_or_null, double* B0);
+                         const SeqLayout& sl, const double* ut, double* B0);
 // bb (optional): per-block partial b.b per column (the first half of the CG
 // partials, [cg_part_rows(n)][ncols])
 void launch_rhs(hipStream_t s, const MeshDev& m, const uint8_t* records, const SeqLayout& sl,
@@ -205,10 +261,11 @@ void launch_anchor_unit_rhs(hipStream_t s, const MeshDev& m, double* b);
 // relative residual by tol.  gram_part: group_gram_doubles(n, sl) doubles.
 size_t group_gram_doubles(int32_t n, const SeqLayout& sl);
 void launch_group_ref(hipStream_t s, const MeshDev& m, const uint8_t* records, const SeqLayout& sl,
-                      const double* b, const double* Ah, double tol, double* gram_part,
-                      double* bnorm2);
+                      const double* ut, const double* b, const double* Ah, double tol,
+                      double* gram_part, double* bnorm2);
 void launch_compose(hipStream_t s, const MeshDev& m, const uint8_t* records, const SeqLayout& sl,
-                    const double* Z, const double* Ah, int32_t precision, void* frames_out);
+                    const double* ut, const double* Z, const double* Ah, int32_t precision,
+                    void* frames_out);
 
 struct CgBuffers {
   double *x, *r, *p, *q;

@@ -47,6 +47,59 @@ __device__ inline void window_of(const SeqLayout& sl, const uint8_t* records, in
   }
 }
 
+// The dequantised dictionary of window w in the decoder's u_tilde
+// [window][3][T][k] (the short last window after the full ones).
+__device__ inline const double* dict_of(const SeqLayout& sl, const double* ut, int w) {
+  return ut + (size_t)(w < sl.nw_full ? w : sl.nw_full) * 3 * sl.T * sl.full.k;
+}
+
+// Coefficient cr = c k + r of vertex i, dequantised from its packed row.
+template <typename Real>
+__device__ inline double coef_value(const uint8_t* rec, const RecordLayout& lay, int cr, int i) {
+  const SegEntry e = ((const SegEntry*)(rec + lay.off_rtab))[cr];
+  const uint32_t* seg = (const uint32_t*)(rec + lay.off_var) + e.word_off;
+  if (lay.coef_bits == 0) return (double)((const Real*)seg)[i];
+  const uint32_t bits = e.bits_mode & 0xffu;
+  if (bits == 0) return (double)e.lo;
+  return dequant(get_code(seg, (uint32_t)i, bits), (double)e.lo, (double)e.hi, (int)bits);
+}
+
+// Dictionary decoder: for windows [w0, w1) of one group in order (block =
+// group; wave v takes columns q = v, v + 4, ... of a window, lane = frame),
+// the dequantised dictionary from the column table and packed segments:
+// values, or the difference from the previous window's column.
+template <typename Real>
+__global__ void __launch_bounds__(kBlock)
+k_dict_decode(const uint8_t* __restrict__ records, size_t rec_bytes, RecordLayout l, int nw,
+              int per_block, double* __restrict__ ut) {
+  const int T = l.T, k = l.k, nq = 3 * k;
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int w0 = blockIdx.x * per_block, w1 = min(nw, w0 + per_block);
+  for (int w = w0; w < w1; ++w) {
+    const uint8_t* rec = records + (size_t)w * rec_bytes;
+    const SegEntry* tab = (const SegEntry*)(rec + l.off_dtab);
+    const uint32_t* var = (const uint32_t*)(rec + l.off_var);
+    double* Ut = ut + (size_t)w * 3 * T * k;
+    const double* Up = Ut - (size_t)3 * T * k;  // previous window (difference columns only)
+    for (int q = wave; q < nq; q += kBlock / 64) {
+      const int c = q / k, j = q % k, t = lane;
+      if (t >= T) continue;
+      const SegEntry e = tab[q];
+      const uint32_t* seg = var + e.word_off;
+      const uint32_t bits = e.bits_mode & 0xffu, mode = (e.bits_mode >> 8) & 0xffu;
+      const size_t at = ((size_t)c * T + t) * k + j;
+      double v;
+      if (l.dict_bits == 0)
+        v = (double)((const Real*)seg)[t];
+      else
+        v = bits ? dequant(get_code(seg, (uint32_t)t, bits), (double)e.lo, (double)e.hi, (int)bits)
+                 : (double)e.lo;
+      Ut[at] = mode ? Up[at] + v : v;
+    }
+    __syncthreads();
+  }
+}
+
 // B0[i][3(t0+t)+c] = sum_r U~_c[t][r] Y^_c[r][i]  (Eq. 11/12 right-hand side)
 // Thread (j, g) owns column j = 3 t + c of the window: its dictionary row
 // U~_c[t][.] stays in registers while it runs over the block's vertices
@@ -56,7 +109,7 @@ __device__ inline void window_of(const SeqLayout& sl, const uint8_t* records, in
 template <typename Real>
 __global__ void __launch_bounds__(kBlock)
 k_back_project(const uint8_t* __restrict__ records, SeqLayout sl, int n, int ncols,
-               double* __restrict__ B0) {
+               const double* __restrict__ ut, double* __restrict__ B0) {
   // padded stride 33 keeps the coordinates of a vertex on different LDS banks
   __shared__ double Yh[BP_V * 3 * 33];
   const int w = blockIdx.y;
@@ -67,19 +120,10 @@ k_back_project(const uint8_t* __restrict__ records, SeqLayout sl, int n, int nco
   const int i0 = blockIdx.x * BP_V;
   const int nv = min(BP_V, n - i0);
   // coefficients of this block's vertices: Yh[v][c][r]
-  const int cb = lay.coef_bits;
   for (int e = threadIdx.x; e < 3 * k * nv; e += kBlock) {
     const int v = e % nv, cr = e / nv;  // consecutive threads -> consecutive vertices
     const int c = cr / k, r = cr % k;
-    const size_t idx = ((size_t)c * k + r) * n + i0 + v;
-    double y;
-    if (cb > 0) {
-      const float* rg = (const float*)(rec + lay.off_ranges) + ((size_t)c * k + r) * 2;
-      y = dequant(((const uint16_t*)(rec + lay.off_codes))[idx], (double)rg[0], (double)rg[1], cb);
-    } else {
-      y = (double)((const Real*)(rec + lay.off_codes))[idx];
-    }
-    Yh[(v * 3 + c) * 33 + r] = y;
+    Yh[(v * 3 + c) * 33 + r] = coef_value<Real>(rec, lay, cr, i0 + v);
   }
   __syncthreads();
   const int wcols = 3 * T;  // <= 192
@@ -88,15 +132,10 @@ k_back_project(const uint8_t* __restrict__ records, SeqLayout sl, int n, int nco
   if (g >= groups) return;
   const int t = j / 3, c = j % 3;
   // dictionary row (k <= 32)
-  const int db = lay.dict_bits;
+  const double* ud = dict_of(sl, ut, w);
   double u[32];
 #pragma unroll
-  for (int r = 0; r < 32; ++r) {
-    const int e = (c * T + t) * k + r;
-    u[r] = r >= k ? 0.0
-           : db > 0 ? dequant(((const uint16_t*)(rec + lay.off_dict))[e], -1.0, 1.0, db)
-                    : (double)((const Real*)(rec + lay.off_dict))[e];
-  }
+  for (int r = 0; r < 32; ++r) u[r] = r >= k ? 0.0 : ud[(c * T + t) * k + r];
   for (int v = g; v < nv; v += groups) {
     const double* y = Yh + (v * 3 + c) * 33;
     double s = 0.0;
@@ -122,14 +161,15 @@ __global__ void k_anchor_values(const uint8_t* __restrict__ records, SeqLayout s
   RecordLayout lay;
   window_of(sl, records, w, rec, T, k, t0, lay);
   const int t = tg - t0;
-  const size_t idx = ((size_t)c * T + t) * nc + s;
+  const uint32_t idx = (uint32_t)t * nc + s;
+  const uint32_t* seg = (const uint32_t*)(rec + lay.off_anchors + (size_t)c * lay.anchor_seg);
   double v;
   if (lay.anchor_bits > 0) {
     const float* rg = (const float*)(rec + lay.off_arange) + 2 * c;
-    v = dequant(((const uint16_t*)(rec + lay.off_anchors))[idx], (double)rg[0], (double)rg[1],
+    v = dequant(get_code(seg, idx, (uint32_t)lay.anchor_bits), (double)rg[0], (double)rg[1],
                 lay.anchor_bits);
   } else {
-    v = (double)((const Real*)(rec + lay.off_anchors))[idx];
+    v = (double)((const Real*)seg)[idx];
   }
   Ah[e] = v;
 }
@@ -564,19 +604,10 @@ k_coef_rows(const uint8_t* __restrict__ records, SeqLayout sl, int n, int nz,
   const int i0 = blockIdx.x * CR_V;
   const int nv = min(CR_V, n - i0);
   const int ck = 3 * k;
-  const int cb = lay.coef_bits;
   for (int e = threadIdx.x; e < ck * CR_V; e += kBlock) {
     const int cr = e / CR_V, v = e % CR_V;  // consecutive threads -> consecutive vertices
     if (v >= nv) continue;
-    const size_t idx = (size_t)cr * n + i0 + v;
-    double y;
-    if (cb > 0) {
-      const float* rg = (const float*)(rec + lay.off_ranges) + (size_t)cr * 2;
-      y = dequant(((const uint16_t*)(rec + lay.off_codes))[idx], (double)rg[0], (double)rg[1], cb);
-    } else {
-      y = (double)((const Real*)(rec + lay.off_codes))[idx];
-    }
-    tile[v * 97 + cr] = y;
+    tile[v * 97 + cr] = coef_value<Real>(rec, lay, cr, i0 + v);
   }
   __syncthreads();
   const int z0 = zoff(sl, w);
@@ -665,7 +696,8 @@ k_group_gram(SeqLayout sl, int n, int nz, int kk2, const double* __restrict__ b,
 __global__ void __launch_bounds__(kBlock)
 k_group_ref(const uint8_t* __restrict__ records, SeqLayout sl, int nc, int nz, int ncols,
             int nchunks, int kk2, const int32_t* __restrict__ anchors,
-            const double* __restrict__ b, const double* __restrict__ Ah,
+            const double* __restrict__ ut, const double* __restrict__ b,
+            const double* __restrict__ Ah,
             const double* __restrict__ part, double g_resid, double tol,
             double* __restrict__ bnorm2) {
   __shared__ double gram[1024];
@@ -736,17 +768,10 @@ k_group_ref(const uint8_t* __restrict__ records, SeqLayout sl, int nc, int nz, i
   const int t = tid;
   double allow2 = -1.0;  // < 0: frame without content
   if (t < T) {
-    const int db = lay.dict_bits;
-    const bool raw64 = lay.precision == DMC_FP64;
+    const double* ud = dict_of(sl, ut, w);
     double u[32];
 #pragma unroll
-    for (int r = 0; r < 32; ++r) {
-      const int d = (c * T + t) * k + r;
-      u[r] = r >= k    ? 0.0
-             : db > 0  ? dequant(((const uint16_t*)(rec + lay.off_dict))[d], -1.0, 1.0, db)
-             : raw64   ? ((const double*)(rec + lay.off_dict))[d]
-                       : (double)((const float*)(rec + lay.off_dict))[d];
-    }
+    for (int r = 0; r < 32; ++r) u[r] = r >= k ? 0.0 : ud[(c * T + t) * k + r];
     double q = an2;
 #pragma unroll
     for (int r = 0; r < 32; ++r) {
@@ -811,7 +836,7 @@ template <typename Real, int TTM, int NV>
 __global__ void __launch_bounds__(kBlock)
 k_compose(const uint8_t* __restrict__ records, SeqLayout sl, int n, int nc, int nz, int ncols,
           const double* __restrict__ G, const double* __restrict__ Z,
-          const double* __restrict__ Ah, Real* __restrict__ out) {
+          const double* __restrict__ Ah, const double* __restrict__ ut, Real* __restrict__ out) {
   const int w = blockIdx.y;
   const uint8_t* rec;
   int T, k, t0;
@@ -830,8 +855,7 @@ k_compose(const uint8_t* __restrict__ records, SeqLayout sl, int n, int nc, int 
   const int tl = lane % 16;  // frame within a 16-frame tile (A row)
   const int tt_n = (T + 15) / 16;
   const int z0 = zoff(sl, w);
-  const int db = lay.dict_bits;
-  const bool raw64 = lay.precision == DMC_FP64;
+  const double* ud = dict_of(sl, ut, w);
   using Acc = typename ComposeMfma<Real>::Acc;
   Acc acc[3][TTM][NV];
 #pragma unroll
@@ -876,12 +900,7 @@ k_compose(const uint8_t* __restrict__ records, SeqLayout sl, int n, int nc, int 
         if (tt >= tt_n) continue;
         const int t = 16 * tt + tl;
         double va = 0.0;
-        if (rv && t < T) {
-          const int d = (c * T + t) * k + r;
-          va = db > 0 ? dequant(((const uint16_t*)(rec + lay.off_dict))[d], -1.0, 1.0, db)
-               : raw64 ? ((const double*)(rec + lay.off_dict))[d]
-                       : (double)((const float*)(rec + lay.off_dict))[d];
-        }
+        if (rv && t < T) va = ud[(c * T + t) * k + r];
 #pragma unroll
         for (int v = 0; v < NV; ++v)
           acc[c][tt][v] = ComposeMfma<Real>::step(va, vb[v], acc[c][tt][v]);
@@ -907,18 +926,45 @@ k_compose(const uint8_t* __restrict__ records, SeqLayout sl, int n, int nc, int 
 
 size_t cg_part_rows(int32_t n) { return (size_t)(n + CG_RB - 1) / CG_RB; }
 
+void launch_dict_decode(hipStream_t s, const uint8_t* records, const SeqLayout& sl, double* ut) {
+  // full windows (in order in one block when a column may refer to its
+  // predecessor), then the short last window (values only)
+  const RecordLayout& f = sl.full;
+  const bool chained = f.dict_mode == DMC_DICT_ADAPTIVE;
+  auto launch = [&](const uint8_t* rec, size_t rec_bytes, const RecordLayout& l, int nw,
+                    double* out) {
+    if (nw < 1) return;
+    const int per = chained ? nw : 1;
+    const dim3 grid(chained ? 1 : nw);
+    if (l.precision == DMC_FP64)
+      hipLaunchKernelGGL(k_dict_decode<double>, grid, dim3(kBlock), 0, s, rec, rec_bytes, l, nw,
+                         per, out);
+    else
+      hipLaunchKernelGGL(k_dict_decode<float>, grid, dim3(kBlock), 0, s, rec, rec_bytes, l, nw,
+                         per, out);
+  };
+  launch(records, sl.rec_bytes_full, f, sl.nw_full, ut);
+  if (sl.T_tail)
+    launch(records + (size_t)sl.nw_full * sl.rec_bytes_full, sl.tail.bytes, sl.tail, 1,
+           ut + (size_t)sl.nw_full * 3 * sl.T * f.k);
+}
+
+size_t dict_decode_doubles(const SeqLayout& sl) {
+  return (size_t)(sl.nw_full + (sl.T_tail > 0 ? 1 : 0)) * 3 * sl.T * sl.full.k;
+}
+
 void launch_back_project(hipStream_t s, const MeshDev& m, const uint8_t* records,
-                         const SeqLayout& sl, const double* /*u_tilde*/, double* B0) {
+                         const SeqLayout& sl, const double* ut, double* B0) {
   const int nw = sl.nw_full + (sl.T_tail > 0 ? 1 : 0);
   const int F = sl.nw_full * sl.T + sl.T_tail;
   dim3 grid((m.n + BP_V - 1) / BP_V, nw);
   prof::begin(s, DMC_KERNEL_BACK_PROJECT);
   if (sl.full.precision == DMC_FP64)
     hipLaunchKernelGGL(k_back_project<double>, grid, dim3(kBlock), 0, s, records, sl, m.n, 3 * F,
-                       B0);
+                       ut, B0);
   else
     hipLaunchKernelGGL(k_back_project<float>, grid, dim3(kBlock), 0, s, records, sl, m.n, 3 * F,
-                       B0);
+                       ut, B0);
   prof::end(s, DMC_KERNEL_BACK_PROJECT);
 }
 
@@ -1130,8 +1176,8 @@ size_t group_gram_doubles(int32_t n, const SeqLayout& sl) {
 }
 
 void launch_group_ref(hipStream_t s, const MeshDev& m, const uint8_t* records, const SeqLayout& sl,
-                      const double* b, const double* Ah, double tol, double* gram_part,
-                      double* bnorm2) {
+                      const double* ut, const double* b, const double* Ah, double tol,
+                      double* gram_part, double* bnorm2) {
   if (!(tol > 0.0)) return;
   const int nw = sl.nw_full + (sl.T_tail > 0 ? 1 : 0);
   const int nchunks = (m.n + GR_ROWS - 1) / GR_ROWS;
@@ -1141,7 +1187,7 @@ void launch_group_ref(hipStream_t s, const MeshDev& m, const uint8_t* records, c
   hipLaunchKernelGGL(k_group_gram, dim3(3 * nw, nchunks), dim3(kBlock), 0, s, sl, m.n, nz, kk2, b,
                      gram_part);
   hipLaunchKernelGGL(k_group_ref, dim3(3 * nw), dim3(kBlock), 0, s, records, sl, m.nc, nz, 3 * F,
-                     nchunks, kk2, m.anchors, b, Ah, (const double*)gram_part, m.G_resid, tol,
+                     nchunks, kk2, m.anchors, ut, b, Ah, (const double*)gram_part, m.G_resid, tol,
                      bnorm2);
 }
 
@@ -1152,7 +1198,8 @@ void launch_anchor_unit_rhs(hipStream_t s, const MeshDev& m, double* b) {
 }
 
 void launch_compose(hipStream_t s, const MeshDev& m, const uint8_t* records, const SeqLayout& sl,
-                    const double* Z, const double* Ah, int32_t precision, void* frames_out) {
+                    const double* ut, const double* Z, const double* Ah, int32_t precision,
+                    void* frames_out) {
   const int nw = sl.nw_full + (sl.T_tail > 0 ? 1 : 0);
   const int F = sl.nw_full * sl.T + sl.T_tail;
   const int nz = reduced_cols(sl);
@@ -1166,11 +1213,11 @@ void launch_compose(hipStream_t s, const MeshDev& m, const uint8_t* records, con
   if (precision == DMC_FP64) {
     auto kern = t32 ? k_compose<double, 2, 2> : k_compose<double, 4, 1>;
     hipLaunchKernelGGL(kern, grid, dim3(kBlock), 0, s, records, sl, m.n, m.nc, nz, 3 * F, m.G, Z,
-                       Ah, (double*)frames_out);
+                       Ah, ut, (double*)frames_out);
   } else {
     auto kern = t32 ? k_compose<float, 2, 2> : k_compose<float, 4, 1>;
     hipLaunchKernelGGL(kern, grid, dim3(kBlock), 0, s, records, sl, m.n, m.nc, nz, 3 * F, m.G, Z,
-                       Ah, (float*)frames_out);
+                       Ah, ut, (float*)frames_out);
   }
   prof::end(s, DMC_KERNEL_TO_FRAMES);
 }

@@ -421,137 +421,373 @@ __device__ inline uint16_t quant_code(double y, double lo, double hi, int bits) 
   return (uint16_t)q;
 }
 
-// Range of one row from the per-block partials, stored as float32 (rounded
-// outwards for float64 data), then the row's codes (or raw values).
+// ---------------------------------------------------------------------------
+// The record (layout in dmc.h): packed segments of codes, their tables, the
+// header.  Codes are Eq. (10)'s, with per-segment bit widths: the dictionary
+// at dict_bits over [-1, 1] (plain) or per column over its own range as
+// values or as the difference from the previous window's column, whichever
+// needs fewer bits at a step no coarser than the plain code's (Sec. IV,
+// Fig. 6); the coefficient rows at coef_bits, or with the fewest bits that
+// keep a caller-given step (Fig. 5); the anchors at anchor_bits.
+// ---------------------------------------------------------------------------
+
+// fewest bits b in 1..cap with (hi - lo) <= step (2^b - 1), cap if none; 0
+// for an empty range
+__device__ inline uint32_t bits_for_step(double lo, double hi, double step, uint32_t cap) {
+#pragma clang fp contract(off)
+  const double width = hi - lo;
+  if (width == 0.0) return 0;
+  const double ratio = width / step;
+  for (uint32_t b = 1; b < cap; ++b)
+    if ((double)((1u << b) - 1u) >= ratio) return b;
+  return cap;
+}
+
+__device__ inline double dequant_code(uint32_t code, double lo, double hi, int bits) {
+#pragma clang fp contract(off)
+  const double levels = (double)((1u << bits) - 1u);
+  const double step = (hi - lo) / levels;
+  return lo + (double)code * step;
+}
+
+// OR of the codes of a packed segment that fall in its 32-bit word wi; code(j)
+// gives code j (j < count)
+template <typename CodeOf>
+__device__ inline uint32_t pack_word(uint32_t wi, uint32_t count, uint32_t bits, CodeOf code) {
+  const uint64_t b0 = (uint64_t)wi * 32;
+  uint32_t j = (uint32_t)(b0 / bits);
+  uint64_t word = 0;
+  for (; j < count && (uint64_t)j * bits < b0 + 32; ++j) {
+    const int64_t pos = (int64_t)j * bits - (int64_t)b0;
+    const uint64_t c = code(j);
+    word |= pos >= 0 ? c << pos : c >> (-pos);
+  }
+  return (uint32_t)word;
+}
+
+// Header words: sizes and formats; the words filled later (has_diff,
+// used bytes, dictionary words) start at zero.  Zeros in the alignment
+// gaps of the fixed part, so every byte of a record's stream is defined.
+__global__ void k_header(uint8_t* rec, RecordLayout l) {
+  int32_t* h = (int32_t*)rec;
+  if (threadIdx.x < kHeaderBytes / 4) {
+    const int i = threadIdx.x;
+    int32_t v = 0;
+    switch (i) {
+      case kHdrMagic: v = kRecordMagic; break;
+      case kHdrT: v = l.T; break;
+      case kHdrK: v = l.k; break;
+      case kHdrN: v = l.n; break;
+      case kHdrNc: v = l.nc; break;
+      case kHdrCoefBits: v = l.coef_bits; break;
+      case kHdrAnchorBits: v = l.anchor_bits; break;
+      case kHdrDictBits: v = l.dict_bits; break;
+      case kHdrPrecision: v = l.precision; break;
+      case kHdrDictMode: v = l.dict_mode; break;
+      case kHdrStepLo: v = (int32_t)(uint32_t)__double_as_longlong(l.coef_step); break;
+      case kHdrStepHi: v = (int32_t)(uint32_t)((uint64_t)__double_as_longlong(l.coef_step) >> 32); break;
+      default: v = 0;
+    }
+    h[i] = v;
+  }
+  const size_t gap[2][2] = {{l.off_arange + 3 * 8, l.off_anchors},
+                            {l.off_anchors + 3 * l.anchor_seg, l.off_var}};
+  for (int g = 0; g < 2; ++g)
+    for (size_t b = gap[g][0] + threadIdx.x; b < gap[g][1]; b += blockDim.x) rec[b] = 0;
+}
+
+// Dictionary coder: one block (4 waves) per group of windows; wave v codes
+// the columns q = v, v + 4, ... (q = c k + j) of each window, one lane per
+// frame.  With differences allowed the windows run in order in one block
+// (each column may refer to the previous window's dequantised column);
+// otherwise every window has a block of its own.  Writes the dequantised
+// dictionary u_tilde [nw][3][T][k], the column table and the packed
+// segments (or raw values) of each record, and the header's dictionary words
+// and difference flag.
+constexpr int DC_COLS = 96;  // 3 k, k <= 32
+
 template <typename Real>
 __global__ void __launch_bounds__(kBlock)
-k_quantise_rows(const Real* __restrict__ Y, int n, int k, int nblk, const double* __restrict__ mm,
-                int bits, uint8_t* records, size_t rec_bytes, size_t off_ranges, size_t off_codes) {
-  __shared__ double slo[kBlock], shi[kBlock];
-  const int row = blockIdx.y;  // (c, r) within the window
-  const int w = blockIdx.z;
-  const int c = row / k, r = row % k;
-  uint8_t* rec = records + (size_t)w * rec_bytes;
-  const Real* y = Y + (((size_t)w * 3 + c) * k + r) * n;
-  const size_t code_base = ((size_t)c * k + r) * n;
-  if (bits == 0) {
-    Real* raw = (Real*)(rec + off_codes) + code_base;
-    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) raw[i] = y[i];
-    return;
-  }
-  const double* m = mm + ((((size_t)w * 3 + c) * k + r) * nblk) * 2;
-  double lo = 1e300, hi = -1e300;
-  for (int b = threadIdx.x; b < nblk; b += kBlock) {
-    lo = fmin(lo, m[2 * b]);
-    hi = fmax(hi, m[2 * b + 1]);
-  }
-  slo[threadIdx.x] = lo;
-  shi[threadIdx.x] = hi;
-  __syncthreads();
-  for (int s = kBlock / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) {
-      slo[threadIdx.x] = fmin(slo[threadIdx.x], slo[threadIdx.x + s]);
-      shi[threadIdx.x] = fmax(shi[threadIdx.x], shi[threadIdx.x + s]);
+k_dict_code(const double* __restrict__ u_canon, int nw, int per_block, RecordLayout l,
+            uint8_t* records, size_t rec_bytes, double* __restrict__ u_tilde) {
+  __shared__ uint16_t sc[DC_COLS][64];
+  __shared__ uint32_t sbits[DC_COLS], smode[DC_COLS];
+  const int T = l.T, k = l.k, nq = 3 * k;
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int db = l.dict_bits;
+  const double step = db > 0 ? 2.0 / (double)((1u << db) - 1u) : 0.0;
+  const int w0 = blockIdx.x * per_block, w1 = min(nw, w0 + per_block);
+  for (int w = w0; w < w1; ++w) {
+    uint8_t* rec = records + (size_t)w * rec_bytes;
+    SegEntry* tab = (SegEntry*)(rec + l.off_dtab);
+    const double* U = u_canon + (size_t)w * 3 * T * k;
+    double* Ut = u_tilde + (size_t)w * 3 * T * k;
+    const double* Up = w > w0 ? u_tilde + (size_t)(w - 1) * 3 * T * k : nullptr;
+    for (int q = wave; q < nq; q += kBlock / 64) {
+      const int c = q / k, j = q % k, t = lane;
+      const bool valid = t < T;
+      const size_t at = ((size_t)c * T + t) * k + j;
+      const double u = valid ? U[at] : 0.0;
+      double lo = -1.0, hi = 1.0, ut = u;
+      uint32_t bits = db, mode = 0, code = 0;
+      if (db == 0) {
+        ut = (double)(Real)u;  // raw values in the frames' type
+        lo = hi = 0.0;
+      } else if (l.dict_mode == 0) {
+        code = quant_code(u, -1.0, 1.0, db);
+        ut = dequant_code(code, -1.0, 1.0, db);
+      } else {
+        // values: their own range, the fewest bits at the plain code's step
+        const double la = (double)__double2float_rd(wave_min(valid ? u : 1e300));
+        const double ha = (double)__double2float_ru(wave_max(valid ? u : -1e300));
+        const uint32_t ba = bits_for_step(la, ha, step, 16);
+        lo = la;
+        hi = ha;
+        bits = ba;
+        double val = u;
+        if (Up) {
+          const double pu = valid ? Up[at] : 0.0;
+          const double d = u - pu;
+          const double ld = (double)__double2float_rd(wave_min(valid ? d : 1e300));
+          const double hd = (double)__double2float_ru(wave_max(valid ? d : -1e300));
+          const uint32_t bd = bits_for_step(ld, hd, step, 16);
+          if (bd < ba) {
+            lo = ld;
+            hi = hd;
+            bits = bd;
+            mode = 1;
+            val = d;
+          }
+        }
+        code = bits ? quant_code(val, lo, hi, bits) : 0u;
+        const double deq = bits ? dequant_code(code, lo, hi, bits) : lo;
+        ut = mode ? Up[at] + deq : deq;
+      }
+      if (valid) {
+        Ut[at] = ut;
+        sc[q][t] = (uint16_t)code;
+      }
+      if (lane == 0) {
+        tab[q].lo = (float)lo;
+        tab[q].hi = (float)hi;
+        tab[q].bits_mode = bits | (mode << 8);
+        sbits[q] = bits;
+        smode[q] = mode;
+      }
+      // raw values go straight into the segment below, once offsets are known
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint32_t off = 0, diff = 0;
+      for (int q = 0; q < nq; ++q) {
+        tab[q].word_off = off;
+        off += seg_words(T, sbits[q], (uint32_t)l.real);
+        diff |= smode[q];
+      }
+      int32_t* h = (int32_t*)rec;
+      h[kHdrDictWords] = (int32_t)off;
+      h[kHdrHasDiff] = (int32_t)diff;
+    }
+    __syncthreads();
+    uint32_t* var = (uint32_t*)(rec + l.off_var);
+    for (int q = wave; q < nq; q += kBlock / 64) {
+      const uint32_t bits = sbits[q];
+      uint32_t* seg = var + tab[q].word_off;
+      const uint32_t nwd = seg_words(T, bits, (uint32_t)l.real);
+      if (db == 0) {
+        const int c = q / k, j = q % k;
+        Real* raw = (Real*)seg;
+        if (lane < T) raw[lane] = (Real)U[((size_t)c * T + lane) * k + j];
+        // the padding of the segment: bytes after T raw values up to nwd words
+        for (uint32_t b = (uint32_t)(T * sizeof(Real)) + lane; b < 4 * nwd; b += 64)
+          ((uint8_t*)seg)[b] = 0;
+      } else {
+        for (uint32_t wi = lane; wi < nwd; wi += 64)
+          seg[wi] = pack_word(wi, (uint32_t)T, bits, [&](uint32_t j) { return (uint32_t)sc[q][j]; });
+      }
     }
     __syncthreads();
   }
-  const float flo = __double2float_rd(slo[0]);
-  const float fhi = __double2float_ru(shi[0]);
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    float* rg = (float*)(rec + off_ranges) + ((size_t)c * k + r) * 2;
-    rg[0] = flo;
-    rg[1] = fhi;
+}
+
+// Coefficient-row table of each window (block = window): the row ranges from
+// the projection's per-block partials (float32, rounded outwards), the bits
+// of every row (coef_bits, or the fewest for coef_step), and the rows' word
+// offsets after the dictionary segments; then the header's used bytes.
+__global__ void __launch_bounds__(kBlock)
+k_row_table(int nblk, const double* __restrict__ mm, RecordLayout l, uint8_t* records,
+            size_t rec_bytes) {
+  __shared__ uint32_t sbits[DC_COLS];
+  const int w = blockIdx.x, nq = 3 * l.k;
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  uint8_t* rec = records + (size_t)w * rec_bytes;
+  SegEntry* tab = (SegEntry*)(rec + l.off_rtab);
+  for (int q = wave; q < nq; q += kBlock / 64) {
+    const double* m = mm + ((size_t)w * nq + q) * nblk * 2;
+    double lo = 1e300, hi = -1e300;
+    for (int b = lane; b < nblk; b += 64) {
+      lo = fmin(lo, m[2 * b]);
+      hi = fmax(hi, m[2 * b + 1]);
+    }
+    lo = wave_min(lo);
+    hi = wave_max(hi);
+    const float flo = __double2float_rd(lo), fhi = __double2float_ru(hi);
+    uint32_t bits = (uint32_t)l.coef_bits;
+    if (l.coef_bits > 0 && l.coef_step > 0.0)
+      bits = bits_for_step((double)flo, (double)fhi, l.coef_step, (uint32_t)l.coef_bits);
+    if (lane == 0) {
+      tab[q].lo = l.coef_bits > 0 ? flo : 0.f;
+      tab[q].hi = l.coef_bits > 0 ? fhi : 0.f;
+      tab[q].bits_mode = bits;
+      sbits[q] = bits;
+    }
   }
-  uint16_t* codes = (uint16_t*)(rec + off_codes) + code_base;
-  const double dlo = (double)flo, dhi = (double)fhi;
-  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock)
-    codes[i] = quant_code((double)y[i], dlo, dhi, bits);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int32_t* h = (const int32_t*)rec;
+    uint32_t off = (uint32_t)h[kHdrDictWords];
+    for (int q = 0; q < nq; ++q) {
+      tab[q].word_off = off;
+      off += seg_words((uint32_t)l.n, sbits[q], (uint32_t)l.real);
+    }
+    const uint64_t used = l.off_var + 4ull * off;
+    int32_t* hw = (int32_t*)rec;
+    hw[kHdrUsedLo] = (int32_t)(uint32_t)used;
+    hw[kHdrUsedHi] = (int32_t)(uint32_t)(used >> 32);
+  }
+}
+
+// Codes of the coefficient rows (Eq. 10) packed into their segments: block
+// (x, q, w) writes words x*256 + tid, x*256 + tid + gridDim.x*256, ... of row
+// q of window w, each word from the codes that fall in it (a code across a
+// word boundary is computed by both words' threads); raw rows are copied.
+template <typename Real>
+__global__ void __launch_bounds__(kBlock)
+k_quantise_pack(const Real* __restrict__ Y, int n, int k, RecordLayout l, uint8_t* records,
+                size_t rec_bytes) {
+  const int q = blockIdx.y, w = blockIdx.z;
+  uint8_t* rec = records + (size_t)w * rec_bytes;
+  const SegEntry e = ((const SegEntry*)(rec + l.off_rtab))[q];
+  const Real* y = Y + ((size_t)w * 3 * k + q) * n;
+  uint32_t* seg = (uint32_t*)(rec + l.off_var) + e.word_off;
+  const uint32_t bits = e.bits_mode & 0xff;
+  const uint32_t stride = gridDim.x * kBlock;
+  if (l.coef_bits == 0) {
+    Real* raw = (Real*)seg;
+    for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < (uint32_t)n; i += stride) raw[i] = y[i];
+    const uint32_t nwd = seg_words((uint32_t)n, 0, sizeof(Real));
+    for (uint32_t b = (uint32_t)n * sizeof(Real) + blockIdx.x * kBlock + threadIdx.x; b < 4 * nwd;
+         b += stride)
+      ((uint8_t*)seg)[b] = 0;
+    return;
+  }
+  const uint32_t nwd = seg_words((uint32_t)n, bits, 4);
+  const double lo = (double)e.lo, hi = (double)e.hi;
+  for (uint32_t wi = blockIdx.x * kBlock + threadIdx.x; wi < nwd; wi += stride)
+    seg[wi] = pack_word(wi, (uint32_t)n, bits,
+                        [&](uint32_t j) { return (uint32_t)quant_code((double)y[j], lo, hi, bits); });
+}
+
+// zeros from the record's used bytes to its capacity (a record's stream is
+// its first used bytes; the rest of its slot is defined too)
+__global__ void __launch_bounds__(kBlock)
+k_zero_tail(uint8_t* records, size_t rec_bytes) {
+  uint8_t* rec = records + (size_t)blockIdx.y * rec_bytes;
+  const int32_t* h = (const int32_t*)rec;
+  const uint64_t used = (uint64_t)(uint32_t)h[kHdrUsedLo] | ((uint64_t)(uint32_t)h[kHdrUsedHi] << 32);
+  uint2* p = (uint2*)(rec + used);
+  const size_t count = (rec_bytes - used) / 8;
+  for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < count; i += (size_t)gridDim.x * kBlock)
+    p[i] = make_uint2(0u, 0u);
 }
 
 // ---------------------------------------------------------------------------
-// Anchors (Eq. 12): values A_c[t][N_j] of one window and coordinate, range
-// over all of them (float32, outward for float64 data), 16-bit (or `bits`)
-// codes [c][t][j].
+// Anchors (Eq. 12): values A_c[t][N_a] of one window and coordinate, range
+// over all of them (float32, rounded outwards), codes of anchor_bits packed
+// in order j = t n_c + a (or raw values).  Two launches: partial extrema per
+// chunk of values, then every block takes the range from the partials (the
+// same bits in all of them) and packs its share of the segment's words.
 // ---------------------------------------------------------------------------
+constexpr int AN_CHUNKS = 32;
+
+template <typename Real>
+__device__ inline Real anchor_value(const Real* __restrict__ fw, int n, int nc,
+                                    const int32_t* __restrict__ anchors, int c, int e) {
+  const int t = e / nc, j = e % nc;
+  return fw[(size_t)t * 3 * n + 3 * (size_t)anchors[j] + c];
+}
+
 template <typename Real>
 __global__ void __launch_bounds__(kBlock)
-k_anchors(const Real* __restrict__ frames, int n, int T, const int32_t* __restrict__ anchors,
-          int nc, int bits, uint8_t* records, size_t rec_bytes, size_t off_arange,
-          size_t off_anchors) {
+k_anchor_minmax(const Real* __restrict__ frames, int n, int T, const int32_t* __restrict__ anchors,
+                int nc, double* __restrict__ part) {
   __shared__ double slo[kBlock], shi[kBlock];
-  const int w = blockIdx.x, c = blockIdx.y;
+  const int ch = blockIdx.x, c = blockIdx.y, w = blockIdx.z;
   const Real* fw = frames + (size_t)w * T * 3 * n;
-  uint8_t* rec = records + (size_t)w * rec_bytes;
-  const int m = T * nc;
-  if (bits == 0) {
-    Real* raw = (Real*)(rec + off_anchors) + (size_t)c * m;
-    for (int e = threadIdx.x; e < m; e += kBlock) {
-      const int t = e / nc, j = e % nc;
-      raw[e] = fw[(size_t)t * 3 * n + 3 * (size_t)anchors[j] + c];
-    }
-    return;
-  }
+  const int m = T * nc, per = (m + AN_CHUNKS - 1) / AN_CHUNKS;
+  const int e0 = ch * per, e1 = min(m, e0 + per);
   double lo = 1e300, hi = -1e300;
-  for (int e = threadIdx.x; e < m; e += kBlock) {
-    const int t = e / nc, j = e % nc;
-    const double v = (double)fw[(size_t)t * 3 * n + 3 * (size_t)anchors[j] + c];
+  for (int e = e0 + threadIdx.x; e < e1; e += kBlock) {
+    const double v = (double)anchor_value(fw, n, nc, anchors, c, e);
     lo = fmin(lo, v);
     hi = fmax(hi, v);
   }
   slo[threadIdx.x] = lo;
   shi[threadIdx.x] = hi;
   __syncthreads();
-  for (int s = kBlock / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) {
-      slo[threadIdx.x] = fmin(slo[threadIdx.x], slo[threadIdx.x + s]);
-      shi[threadIdx.x] = fmax(shi[threadIdx.x], shi[threadIdx.x + s]);
+  for (int st = kBlock / 2; st > 0; st >>= 1) {
+    if (threadIdx.x < st) {
+      slo[threadIdx.x] = fmin(slo[threadIdx.x], slo[threadIdx.x + st]);
+      shi[threadIdx.x] = fmax(shi[threadIdx.x], shi[threadIdx.x + st]);
     }
     __syncthreads();
   }
-  const float flo = __double2float_rd(slo[0]);
-  const float fhi = __double2float_ru(shi[0]);
   if (threadIdx.x == 0) {
-    float* rg = (float*)(rec + off_arange) + 2 * c;
-    rg[0] = flo;
-    rg[1] = fhi;
-  }
-  uint16_t* codes = (uint16_t*)(rec + off_anchors) + (size_t)c * m;
-  for (int e = threadIdx.x; e < m; e += kBlock) {
-    const int t = e / nc, j = e % nc;
-    const double v = (double)fw[(size_t)t * 3 * n + 3 * (size_t)anchors[j] + c];
-    codes[e] = quant_code(v, (double)flo, (double)fhi, bits);
+    double* o = part + (((size_t)w * 3 + c) * AN_CHUNKS + ch) * 2;
+    o[0] = slo[0];
+    o[1] = shi[0];
   }
 }
 
-// The record header (the problem sizes and formats), and zeros in the
-// alignment gaps after the header and after each section, so that every byte
-// of a record is defined.
-__global__ void k_header(uint8_t* rec, RecordLayout l) {
-  int32_t* h = (int32_t*)rec;
-  if (threadIdx.x == 0) {
-    h[0] = kRecordMagic;
-    h[1] = l.T;
-    h[2] = l.k;
-    h[3] = l.n;
-    h[4] = l.nc;
-    h[5] = l.coef_bits;
-    h[6] = l.anchor_bits;
-    h[7] = l.dict_bits;
-    h[8] = l.precision;
-    for (int i = 9; i < 16; ++i) h[i] = 0;
+template <typename Real>
+__global__ void __launch_bounds__(kBlock)
+k_anchor_pack(const Real* __restrict__ frames, int n, int T, const int32_t* __restrict__ anchors,
+              int nc, int bits, const double* __restrict__ part, uint8_t* records,
+              size_t rec_bytes, RecordLayout l) {
+  const int c = blockIdx.y, w = blockIdx.z;
+  const Real* fw = frames + (size_t)w * T * 3 * n;
+  uint8_t* rec = records + (size_t)w * rec_bytes;
+  const int m = T * nc;
+  uint32_t* seg = (uint32_t*)(rec + l.off_anchors + (size_t)c * l.anchor_seg);
+  float* rg = (float*)(rec + l.off_arange) + 2 * c;
+  const uint32_t stride = gridDim.x * kBlock, first = blockIdx.x * kBlock + threadIdx.x;
+  if (bits == 0) {
+    Real* raw = (Real*)seg;
+    for (uint32_t e = first; e < (uint32_t)m; e += stride)
+      raw[e] = anchor_value(fw, n, nc, anchors, c, (int)e);
+    for (size_t b = (size_t)m * sizeof(Real) + first; b < l.anchor_seg; b += stride)
+      ((uint8_t*)seg)[b] = 0;
+    if (first == 0) rg[0] = rg[1] = 0.f;
+    return;
   }
-  const size_t dict = (size_t)3 * l.T * l.k * (l.dict_bits > 0 ? 2 : l.real);
-  const size_t codes = (size_t)3 * l.k * l.n * (l.coef_bits > 0 ? 2 : l.real);
-  const size_t anchors = (size_t)3 * l.T * l.nc * (l.anchor_bits > 0 ? 2 : l.real);
-  // (end of a section's data, start of the next section)
-  const size_t gap[6][2] = {{64, l.off_dict},
-                            {l.off_dict + dict, l.off_ranges},
-                            {l.off_ranges + (size_t)3 * l.k * 2 * 4, l.off_codes},
-                            {l.off_codes + codes, l.off_arange},
-                            {l.off_arange + (size_t)3 * 2 * 4, l.off_anchors},
-                            {l.off_anchors + anchors, l.bytes}};
-  for (int g = 0; g < 6; ++g)
-    for (size_t b = gap[g][0] + threadIdx.x; b < gap[g][1]; b += blockDim.x) rec[b] = 0;
+  // the range: every lane adds the partials in the same order
+  const double* pp = part + ((size_t)w * 3 + c) * AN_CHUNKS * 2;
+  double lo = 1e300, hi = -1e300;
+  for (int q = 0; q < AN_CHUNKS; ++q) {
+    lo = fmin(lo, pp[2 * q]);
+    hi = fmax(hi, pp[2 * q + 1]);
+  }
+  const float flo = __double2float_rd(lo), fhi = __double2float_ru(hi);
+  if (first == 0) {
+    rg[0] = flo;
+    rg[1] = fhi;
+  }
+  const uint32_t nwd = (uint32_t)(l.anchor_seg / 4);
+  for (uint32_t wi = first; wi < nwd; wi += stride)
+    seg[wi] = pack_word(wi, (uint32_t)m, (uint32_t)bits, [&](uint32_t j) {
+      return (uint32_t)quant_code((double)anchor_value(fw, n, nc, anchors, c, (int)j), (double)flo,
+                                  (double)fhi, bits);
+    });
 }
 
 }  // namespace
@@ -645,19 +881,12 @@ void launch_autocorr(hipStream_t s, const void* frames, int32_t n, int32_t T, in
     autocorr_impl(s, (const float*)frames, n, T, nw, (double*)part, R, P);
 }
 
-size_t project_scratch_bytes(int32_t n, int32_t T, int32_t k, int32_t nw, int32_t precision) {
-  (void)T;
-  const size_t nblk = (n + PJ_V - 1) / PJ_V;
-  const size_t y = align_up((size_t)nw * 3 * k * n * (precision == DMC_FP64 ? 8 : 4));
-  const size_t mm = align_up((size_t)nw * 3 * k * nblk * 2 * 8);
-  return y + mm;
-}
 
 template <typename Real>
 static void project_impl(hipStream_t s, const MeshDev& m, const void* frames, int32_t T,
-                         int32_t k, int32_t nw, int32_t coef_bits, const double* u_tilde,
-                         uint8_t* records, size_t rec_bytes, const RecordLayout& lay,
-                         void* scratch, void* coef_out) {
+                         int32_t k, int32_t nw, const double* u_tilde, uint8_t* records,
+                         size_t rec_bytes, const RecordLayout& lay, void* scratch,
+                         void* coef_out) {
   const int n = m.n;
   const int nblk = (n + PJ_V - 1) / PJ_V;
   Real* Y = coef_out ? (Real*)coef_out : (Real*)scratch;
@@ -677,41 +906,82 @@ static void project_impl(hipStream_t s, const MeshDev& m, const void* frames, in
     hipLaunchKernelGGL((k_project_frames<Real, 32>), grid, dim3(kBlock), 0, s, m.rowptr, m.col,
                        m.w64, uni, n, T, k, fr, u_tilde, Y, mm);
   prof::end(s, DMC_KERNEL_PROJECT);
-  const int chunks = std::max(1, std::min(64, (n + 4 * kBlock - 1) / (4 * kBlock)));
-  dim3 qgrid(chunks, 3 * k, nw);
   prof::begin(s, DMC_KERNEL_QUANTISE);
-  hipLaunchKernelGGL(k_quantise_rows<Real>, qgrid, dim3(kBlock), 0, s, (const Real*)Y, n, k,
-                     nblk, (const double*)mm, coef_bits, records, rec_bytes, lay.off_ranges,
-                     lay.off_codes);
+  hipLaunchKernelGGL(k_row_table, dim3(nw), dim3(kBlock), 0, s, nblk, (const double*)mm, lay,
+                     records, rec_bytes);
+  // words of a row at its widest, spread so that a block writes a few per thread
+  const uint32_t wmax = seg_words((uint32_t)n, lay.coef_bits > 0 ? lay.coef_bits : 0,
+                                  (uint32_t)sizeof(Real));
+  const int chunks = std::max(1, std::min(64, (int)((wmax + 4 * kBlock - 1) / (4 * kBlock))));
+  hipLaunchKernelGGL(k_quantise_pack<Real>, dim3(chunks, 3 * k, nw), dim3(kBlock), 0, s,
+                     (const Real*)Y, n, k, lay, records, rec_bytes);
   prof::end(s, DMC_KERNEL_QUANTISE);
 }
 
-void launch_project_quantise(hipStream_t s, const MeshDev& m, const void* frames, int32_t T,
-                             int32_t k, int32_t nw, int32_t precision, int32_t coef_bits,
-                             const double* u_tilde, uint8_t* records, size_t rec_bytes,
-                             const RecordLayout& lay, void* scratch, void* coef_out) {
-  if (precision == DMC_FP64)
-    project_impl<double>(s, m, frames, T, k, nw, coef_bits, u_tilde, records, rec_bytes, lay,
-                         scratch, coef_out);
-  else
-    project_impl<float>(s, m, frames, T, k, nw, coef_bits, u_tilde, records, rec_bytes, lay,
-                        scratch, coef_out);
+size_t project_scratch_bytes(int32_t n, int32_t T, int32_t k, int32_t nw, int32_t precision) {
+  (void)T;
+  const size_t nblk = (n + PJ_V - 1) / PJ_V;
+  const size_t y = align_up((size_t)nw * 3 * k * n * (precision == DMC_FP64 ? 8 : 4));
+  const size_t mm = align_up((size_t)nw * 3 * k * nblk * 2 * 8);
+  return y + mm;
 }
 
-void launch_anchors(hipStream_t s, const MeshDev& m, const void* frames, int32_t T, int32_t nw,
-                    int32_t precision, int32_t anchor_bits, uint8_t* records, size_t rec_bytes,
-                    const RecordLayout& lay) {
-  dim3 grid(nw, 3);
-  prof::begin(s, DMC_KERNEL_ANCHORS);
+void launch_project_quantise(hipStream_t s, const MeshDev& m, const void* frames, int32_t T,
+                             int32_t k, int32_t nw, int32_t precision, const double* u_tilde,
+                             uint8_t* records, size_t rec_bytes, const RecordLayout& lay,
+                             void* scratch, void* coef_out) {
   if (precision == DMC_FP64)
-    hipLaunchKernelGGL(k_anchors<double>, grid, dim3(kBlock), 0, s, (const double*)frames, m.n,
-                       T, m.anchors, m.nc, anchor_bits, records, rec_bytes, lay.off_arange,
-                       lay.off_anchors);
+    project_impl<double>(s, m, frames, T, k, nw, u_tilde, records, rec_bytes, lay, scratch,
+                         coef_out);
   else
-    hipLaunchKernelGGL(k_anchors<float>, grid, dim3(kBlock), 0, s, (const float*)frames, m.n, T,
-                       m.anchors, m.nc, anchor_bits, records, rec_bytes, lay.off_arange,
-                       lay.off_anchors);
+    project_impl<float>(s, m, frames, T, k, nw, u_tilde, records, rec_bytes, lay, scratch,
+                        coef_out);
+}
+
+size_t anchors_scratch_bytes(int32_t nw) { return align_up((size_t)nw * 3 * AN_CHUNKS * 2 * 8); }
+
+void launch_anchors(hipStream_t s, const MeshDev& m, const void* frames, int32_t T, int32_t nw,
+                    int32_t precision, uint8_t* records, size_t rec_bytes, const RecordLayout& lay,
+                    double* part) {
+  const int mvals = T * m.nc;
+  const uint32_t nwd = (uint32_t)(lay.anchor_seg / 4);
+  const int pk = std::max(1, std::min(64, (int)((std::max<uint32_t>(nwd, mvals) + 4 * kBlock - 1) /
+                                                (4 * kBlock))));
+  prof::begin(s, DMC_KERNEL_ANCHORS);
+  if (precision == DMC_FP64) {
+    if (lay.anchor_bits > 0)
+      hipLaunchKernelGGL(k_anchor_minmax<double>, dim3(AN_CHUNKS, 3, nw), dim3(kBlock), 0, s,
+                         (const double*)frames, m.n, T, m.anchors, m.nc, part);
+    hipLaunchKernelGGL(k_anchor_pack<double>, dim3(pk, 3, nw), dim3(kBlock), 0, s,
+                       (const double*)frames, m.n, T, m.anchors, m.nc, lay.anchor_bits, part,
+                       records, rec_bytes, lay);
+  } else {
+    if (lay.anchor_bits > 0)
+      hipLaunchKernelGGL(k_anchor_minmax<float>, dim3(AN_CHUNKS, 3, nw), dim3(kBlock), 0, s,
+                         (const float*)frames, m.n, T, m.anchors, m.nc, part);
+    hipLaunchKernelGGL(k_anchor_pack<float>, dim3(pk, 3, nw), dim3(kBlock), 0, s,
+                       (const float*)frames, m.n, T, m.anchors, m.nc, lay.anchor_bits, part,
+                       records, rec_bytes, lay);
+  }
   prof::end(s, DMC_KERNEL_ANCHORS);
+}
+
+void launch_dict_code(hipStream_t s, const double* u_canon, int32_t nw, const RecordLayout& lay,
+                      uint8_t* records, size_t rec_bytes, double* u_tilde) {
+  // differences chain the windows in one block; otherwise one block each
+  const int per = lay.dict_mode == 1 ? nw : 1;
+  const dim3 grid(lay.dict_mode == 1 ? 1 : nw);
+  if (lay.precision == DMC_FP64)
+    hipLaunchKernelGGL(k_dict_code<double>, grid, dim3(kBlock), 0, s, u_canon, nw, per, lay,
+                       records, rec_bytes, u_tilde);
+  else
+    hipLaunchKernelGGL(k_dict_code<float>, grid, dim3(kBlock), 0, s, u_canon, nw, per, lay,
+                       records, rec_bytes, u_tilde);
+}
+
+void launch_zero_tail(hipStream_t s, uint8_t* records, int32_t nw, size_t rec_bytes) {
+  const int chunks = std::max(1, std::min(256, (int)((rec_bytes / 8 + 4 * kBlock - 1) / (4 * kBlock))));
+  hipLaunchKernelGGL(k_zero_tail, dim3(chunks, nw), dim3(kBlock), 0, s, records, rec_bytes);
 }
 
 void launch_write_header(hipStream_t s, uint8_t* rec, const RecordLayout& l) {

@@ -965,25 +965,6 @@ __device__ __forceinline__ void ritz_vectors(OiSmem<TMAX, KMAX>& s, int k) {
   __syncthreads();
 }
 
-template <typename Real>
-__device__ __forceinline__ uint16_t quant(double y, double lo, double hi, int bits) {
-#pragma clang fp contract(off)
-  const double levels = (double)((1 << bits) - 1);
-  if (hi == lo) return 0;
-  const double sc = levels / (hi - lo);
-  const double t = (y - lo) * sc;
-  double q = floor(t + 0.5);
-  q = fmin(levels, fmax(0.0, q));
-  return (uint16_t)q;
-}
-
-__device__ __forceinline__ double dequant(uint16_t code, double lo, double hi, int bits) {
-#pragma clang fp contract(off)
-  const double levels = (double)((1 << bits) - 1);
-  const double step = (hi - lo) / levels;
-  return lo + (double)code * step;
-}
-
 // Algorithm 1's iterations and the Ritz step: start block in Q (the previous
 // window's U, or a caller-given block), sweeps Y = R Q, Q = QR(Y) until the
 // residual test passes or the sweep cap, then U = Q V from H = Q^T R Q = V
@@ -1036,27 +1017,18 @@ __device__ __forceinline__ void oi_sweeps(OiSmem<TMAX, KMAX>& s, int T, int k, i
   }
 }
 
-// Outputs of window w, coordinate c from the canonical U in s.Y: U, the
-// dictionary codes (Sec. IV: 16-bit uniform over [-1, 1]) and the dequantised
-// dictionary.
+// Outputs of window w, coordinate c from the canonical U in s.Y: U in the
+// frames' type (u_out) and in float64 (u_canon, which the dictionary coder
+// reads).
 template <int TMAX, int KMAX, typename Real>
 __device__ __forceinline__ void oi_outputs(OiSmem<TMAX, KMAX>& s, const OiArgs& a, int w, int c) {
   const int T = a.T, k = a.k;
   Real* uo = a.u_out ? (Real*)a.u_out + ((size_t)w * a.ncoord + c) * T * k : nullptr;
-  double* ut = a.u_tilde ? a.u_tilde + ((size_t)w * a.ncoord + c) * T * k : nullptr;
-  uint8_t* rec = a.records ? a.records + (size_t)w * a.rec_bytes + a.off_dict : nullptr;
+  double* uc = a.u_canon ? a.u_canon + ((size_t)w * a.ncoord + c) * T * k : nullptr;
   for (int e = threadIdx.x; e < T * k; e += NT) {
     const double u = s.Y[(e / k) * s.LQ + e % k];
     if (uo) uo[e] = (Real)u;
-    if (!rec) continue;  // subspace only (no record)
-    if (a.dict_bits > 0) {
-      const uint16_t code = quant<Real>(u, -1.0, 1.0, a.dict_bits);
-      ((uint16_t*)rec)[(size_t)c * T * k + e] = code;
-      ut[e] = dequant(code, -1.0, 1.0, a.dict_bits);
-    } else {
-      ((Real*)rec)[(size_t)c * T * k + e] = (Real)u;
-      ut[e] = (double)(Real)u;
-    }
+    if (uc) uc[e] = u;
   }
 }
 

@@ -24,6 +24,7 @@ FP64, FP32, BF16 = 0, 1, 2
 LAP_UNIFORM, LAP_COMBINATORIAL = 0, 1
 PRECOND_NONE, PRECOND_JACOBI, PRECOND_CHOLESKY = 0, 1, 2
 INIT_PREV, INIT_RANDOM, INIT_SKETCH, INIT_EXACT, INIT_LEARNED = 0, 1, 2, 3, 4
+DICT_PLAIN, DICT_ADAPTIVE = 0, 1
 
 EXPORTS = ["dmc_create", "dmc_destroy", "dmc_set_stream", "dmc_last_error", "dmc_scratch_bytes",
            "dmc_workspace_bytes", "dmc_set_workspace",
@@ -54,7 +55,8 @@ class Params(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("oi_max_sweeps", ctypes.c_int32),
                 ("oi_tol", ctypes.c_double), ("cg_max_iters", ctypes.c_int32),
                 ("precond", ctypes.c_int32), ("cg_tol", ctypes.c_double),
-                ("init", ctypes.c_int32)]
+                ("init", ctypes.c_int32), ("dict_mode", ctypes.c_int32),
+                ("coef_step", ctypes.c_double)]
 
 
 class WindowStats(ctypes.Structure):
@@ -75,7 +77,7 @@ class WindowStats(ctypes.Structure):
 
 def make_params(k, coef_bits=12, anchor_bits=16, dict_bits=16, precision=FP32,
                 oi_max_sweeps=200, oi_tol=None, cg_max_iters=None, precond=PRECOND_CHOLESKY,
-                cg_tol=None, init=INIT_PREV) -> Params:
+                cg_tol=None, init=INIT_PREV, dict_mode=0, coef_step=0.0) -> Params:
     if oi_tol is None:
         # the precision form's bfloat16 covariance fixes the trailing
         # eigen-directions only to its rounding: without a gap there the
@@ -86,7 +88,7 @@ def make_params(k, coef_bits=12, anchor_bits=16, dict_bits=16, precision=FP32,
     if cg_max_iters is None:
         cg_max_iters = 50 if precond == PRECOND_CHOLESKY else 20000
     return Params(k, coef_bits, anchor_bits, dict_bits, precision, oi_max_sweeps, float(oi_tol),
-                  cg_max_iters, precond, float(cg_tol), init)
+                  cg_max_iters, precond, float(cg_tol), init, dict_mode, float(coef_step))
 
 
 _lib = None
@@ -410,41 +412,103 @@ def _align(x, a=256):
     return (x + a - 1) // a * a
 
 
+def _seg_words(count, bits, real):
+    w = (count * bits + 31) // 32 if bits else (count * real + 3) // 4
+    return w + (w & 1)
+
+
+def _unpack(words, count, bits):
+    """Codes of a packed segment (LSB first within 32-bit words)."""
+    if bits == 0 or count == 0:
+        return np.zeros(count, dtype=np.uint32)
+    w = np.asarray(words, dtype=np.uint64)
+    pos = np.arange(count, dtype=np.uint64) * np.uint64(bits)
+    wi = (pos >> np.uint64(5)).astype(np.int64)
+    sh = pos & np.uint64(31)
+    hi = np.where(wi + 1 < w.size, w[np.minimum(wi + 1, w.size - 1)], 0).astype(np.uint64)
+    both = w[wi] | (hi << np.uint64(32))
+    return ((both >> sh) & np.uint64((1 << bits) - 1)).astype(np.uint32)
+
+
+HEADER_WORDS = 32
+SEG_DTYPE = np.dtype([("lo", "<f4"), ("hi", "<f4"), ("bits_mode", "<u4"), ("word_off", "<u4")])
+
+
 @dataclass
 class RecordView:
-    header: np.ndarray
-    dict_codes: np.ndarray      # [3][T][k] uint16 or raw
-    ranges: np.ndarray | None   # [3][k][2] float32
-    codes: np.ndarray           # [3][k][n] uint16 or raw
+    header: np.ndarray          # int32 [32]
+    dict_table: np.ndarray      # [3][k] (lo, hi, bits_mode, word_off)
+    dict_codes: np.ndarray      # [3][T][k] codes (uint32) or raw values
+    ranges: np.ndarray | None   # [3][k][2] float32 (None for raw rows)
+    row_bits: np.ndarray        # [3][k]
+    codes: np.ndarray           # [3][k][n] codes (uint32) or raw values
     anchor_range: np.ndarray | None  # [3][2] float32
-    anchor_codes: np.ndarray    # [3][T][nc] uint16 or raw
+    anchor_codes: np.ndarray    # [3][T][nc] codes (uint32) or raw values
+    used_bytes: int
+    var_words: np.ndarray       # the variable part's 32-bit words (dictionary, then rows)
+    anchor_words: list          # [3] words of the anchor segments
+
+    @property
+    def dict_bits(self):
+        return self.dict_table["bits_mode"] & 0xFF
+
+    @property
+    def dict_modes(self):
+        return (self.dict_table["bits_mode"] >> 8) & 0xFF
 
 
 def parse_record(buf: np.ndarray, n: int, T: int, nc: int, params: Params) -> RecordView:
-    """Split one record (bytes copied to the host) into its sections; mirrors
-    the layout documented in dmc.h."""
+    """Split one record (bytes copied to the host) into its header, tables and
+    unpacked codes; mirrors the layout documented in dmc.h."""
     buf = np.asarray(buf, dtype=np.uint8)
     k = min(params.k, T)
     real = np.float64 if params.precision == FP64 else np.float32
     rs = np.dtype(real).itemsize
-    off = _align(64)
-    hdr = buf[:64].view(np.int32)
-
-    def take(count, dt):
-        nonlocal off
-        nbytes = count * np.dtype(dt).itemsize
-        arr = buf[off:off + nbytes].view(dt)
-        off += _align(nbytes)
-        return arr
-
-    dct = take(3 * T * k, np.uint16 if params.dict_bits > 0 else real).reshape(3, T, k)
-    rng = take(3 * k * 2, np.float32).reshape(3, k, 2)
-    cod = take(3 * k * n, np.uint16 if params.coef_bits > 0 else real).reshape(3, k, n)
-    arg = take(3 * 2, np.float32).reshape(3, 2)
-    anc = take(3 * T * nc, np.uint16 if params.anchor_bits > 0 else real).reshape(3, T, nc)
-    del rs
-    return RecordView(hdr, dct, rng if params.coef_bits > 0 else None, cod,
-                      arg if params.anchor_bits > 0 else None, anc)
+    hdr = buf[:128].view(np.int32).copy()
+    off_dtab = 128
+    off_rtab = off_dtab + 3 * k * 16
+    off_arange = off_rtab + 3 * k * 16
+    off_anchors = _align(off_arange + 24)
+    aseg = 4 * _seg_words(T * nc, params.anchor_bits, rs)
+    off_var = _align(off_anchors + 3 * aseg)
+    dtab = buf[off_dtab:off_rtab].view(SEG_DTYPE).reshape(3, k).copy()
+    rtab = buf[off_rtab:off_arange].view(SEG_DTYPE).reshape(3, k).copy()
+    arng = buf[off_arange:off_arange + 24].view(np.float32).reshape(3, 2).copy()
+    used = int(np.uint32(hdr[11])) | (int(np.uint32(hdr[12])) << 32)
+    var = buf[off_var:used].view(np.uint32)
+    dict_codes = np.zeros((3, T, k), dtype=real if params.dict_bits == 0 else np.uint32)
+    for c in range(3):
+        for j in range(k):
+            e = dtab[c, j]
+            b = int(e["bits_mode"]) & 0xFF
+            o = int(e["word_off"])
+            nwd = _seg_words(T, b if params.dict_bits else 0, rs)
+            words = var[o:o + nwd]
+            if params.dict_bits == 0:
+                dict_codes[c, :, j] = words.view(real)[:T]
+            else:
+                dict_codes[c, :, j] = _unpack(words, T, b)
+    codes = np.zeros((3, k, n), dtype=real if params.coef_bits == 0 else np.uint32)
+    row_bits = (rtab["bits_mode"] & 0xFF).astype(np.int64)
+    for c in range(3):
+        for r in range(k):
+            b = int(row_bits[c, r])
+            o = int(rtab[c, r]["word_off"])
+            nwd = _seg_words(n, b if params.coef_bits else 0, rs)
+            words = var[o:o + nwd]
+            codes[c, r] = words.view(real)[:n] if params.coef_bits == 0 else _unpack(words, n, b)
+    ranges = np.stack([rtab["lo"], rtab["hi"]], axis=-1).astype(np.float32)
+    anc = np.zeros((3, T, nc), dtype=real if params.anchor_bits == 0 else np.uint32)
+    aw = []
+    for c in range(3):
+        words = buf[off_anchors + c * aseg:off_anchors + (c + 1) * aseg].view(np.uint32)
+        aw.append(words)
+        if params.anchor_bits == 0:
+            anc[c] = words.view(real)[:T * nc].reshape(T, nc)
+        else:
+            anc[c] = _unpack(words, T * nc, params.anchor_bits).reshape(T, nc)
+    return RecordView(hdr, dtab, dict_codes, ranges if params.coef_bits > 0 else None, row_bits,
+                      codes, arng if params.anchor_bits > 0 else None, anc, used, var, aw)
 
 
 # ---- orthogonal iterations on independent blocks, learned start ------------

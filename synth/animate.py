@@ -136,7 +136,7 @@ def gaussian_subspace(T: int, k: int, seed: int) -> np.ndarray:
 
 
 def gapped_windows(rest, n_frames: int, T: int, k: int, seed: int, gap: float = 4.0,
-                   decay: float = 0.1, scale: float = 0.1, dtype=np.float64):
+                   decay: float = 0.1, scale: float = 0.1, drift=None, dtype=np.float64):
     """Frames whose every window of T frames has, per coordinate, an
     autocorrelation with a clean eigenvalue gap after its k-th eigenvalue.
 
@@ -149,10 +149,14 @@ def gapped_windows(rest, n_frames: int, T: int, k: int, seed: int, gap: float = 
     U diag(s_0^2 + T |r_c|^2, s_1^2, ...) U^T exactly: frame t is the rest
     pose plus a deformation, lambda_k / lambda_(k+1) is about gap^2, and the
     trailing eigenvalues stay far above round-off.  A shorter last window uses
-    its own length T_w and k_w = min(k, T_w)."""
+    its own length T_w and k_w = min(k, T_w).  With `drift`, the full windows
+    share one seeded U per coordinate, perturbed per window by drift times a
+    Gaussian block before orthonormalisation, so consecutive windows have
+    nearby eigenvectors."""
     rng = np.random.default_rng(seed)
     n = rest.shape[0]
     out = np.empty((n_frames, n, 3), dtype=np.float64)
+    base = [rng.standard_normal((T, T)) for _ in range(3)] if drift is not None else None
     for s0 in range(0, n_frames, T):
         tw = min(T, n_frames - s0)
         kw = min(k, tw)
@@ -161,7 +165,10 @@ def gapped_windows(rest, n_frames: int, T: int, k: int, seed: int, gap: float = 
                      2.0 ** (-decay * (kw - 1)) * 2.0 ** (-decay * (j - kw + 1)) / gap)
         s = s * scale * np.sqrt(n)
         for c in range(3):
-            G = rng.standard_normal((tw, tw))
+            if base is not None and tw == T:
+                G = base[c] + drift * rng.standard_normal((tw, tw))
+            else:
+                G = rng.standard_normal((tw, tw))
             G[:, 0] = 1.0
             U, _ = np.linalg.qr(G)
             U[:, 0] = np.abs(U[:, 0])  # the constant column, positive

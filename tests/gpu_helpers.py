@@ -12,20 +12,32 @@ def to_dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
 
 
-def record_to_oracle(view: dmc.RecordView, p: dmc.Params, T: int) -> dict:
-    """The oracle's view of one GPU record: dequantised dictionary, coefficients
-    and anchors, computed by the oracle's own dequantiser from the record's
-    codes."""
+def record_to_oracle(view: dmc.RecordView, p: dmc.Params, T: int, prev_tilde=None) -> dict:
+    """The oracle's view of one GPU record: dequantised dictionary (per
+    column, values or differences from prev_tilde, the previous window's
+    [3][T][k] dequantised dictionary), coefficients and anchors, computed by
+    the oracle's own dequantiser from the record's codes and tables."""
     k = min(p.k, T)
     rec = {"T": T, "k": k, "U_tilde": [], "Y_hat": [], "A_hat": []}
     for c in range(3):
-        if p.dict_bits:
-            rec["U_tilde"].append(O.dequantise_uniform(view.dict_codes[c], -1.0, 1.0, p.dict_bits))
+        if p.dict_bits == 0:
+            ut = view.dict_codes[c].astype(np.float64)
         else:
-            rec["U_tilde"].append(view.dict_codes[c].astype(np.float64))
+            ut = np.empty((T, k))
+            for j in range(k):
+                e = view.dict_table[c, j]
+                b, mode = int(e["bits_mode"]) & 0xFF, (int(e["bits_mode"]) >> 8) & 0xFF
+                vals = (np.full(T, np.float64(e["lo"])) if b == 0 else
+                        O.dequantise_uniform(view.dict_codes[c, :, j], e["lo"], e["hi"], b))
+                ut[:, j] = prev_tilde[c][:, j] + vals if mode else vals
+        rec["U_tilde"].append(ut)
         if p.coef_bits:
-            rows = [O.dequantise_uniform(view.codes[c, r], view.ranges[c, r, 0],
-                                         view.ranges[c, r, 1], p.coef_bits) for r in range(k)]
+            rows = []
+            for r in range(k):
+                b = int(view.row_bits[c, r])
+                lo, hi = view.ranges[c, r, 0], view.ranges[c, r, 1]
+                rows.append(np.full(view.codes.shape[2], np.float64(lo)) if b == 0 else
+                            O.dequantise_uniform(view.codes[c, r], lo, hi, b))
             rec["Y_hat"].append(np.stack(rows))
         else:
             rec["Y_hat"].append(view.codes[c].astype(np.float64))

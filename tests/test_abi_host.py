@@ -37,9 +37,16 @@ def test_record_size_matches_layout(prec, cb, ab, db):
     n, T, nc = 1000, 32, 10
     real = 8 if prec == dmc.FP64 else 4
     k = 16
-    expect = (_align(64) + _align(3 * T * k * (2 if db else real)) + _align(3 * k * 2 * 4)
-              + _align(3 * k * n * (2 if cb else real)) + _align(24)
-              + _align(3 * T * nc * (2 if ab else real)))
+
+    def words(count, bits):  # 32-bit words of a segment, even count; raw values if bits == 0
+        w = (count * bits + 31) // 32 if bits else (count * real + 3) // 4
+        return w + w % 2
+
+    # header 128 B, column and row tables (16 B entries), anchor ranges; the
+    # anchor segments; then the dictionary columns and the rows at their widest
+    fixed = _align(128 + 2 * 3 * k * 16 + 24)
+    anchors = _align(fixed + 3 * 4 * words(T * nc, ab))
+    expect = _align(anchors + 4 * 3 * k * (words(T, db) + words(n, cb)))
     assert dmc.window_code_bytes(n, T, nc, p) == expect
     # a short window keeps k_w = min(k, T_w)
     assert dmc.window_code_bytes(n, 5, nc, p) < expect

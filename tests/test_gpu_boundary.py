@@ -155,22 +155,29 @@ def test_workspace_no_library_scratch(ctx, precond):
 
 @pytest.mark.parametrize("bits", [(12, 16, 16), (8, 12, 10), (0, 0, 0)])
 def test_stats_bit_rates_match_oracle_accounting(ctx, bits):
-    """The bits per vertex per frame and coordinate that each window's stats
-    report (Eq. 13) add up to the oracle's accounting of the same sequence,
-    ragged last window included; the stage timers are filled."""
+    """The bits per vertex per frame and coordinate each window's stats report
+    (Eq. 13) are the stream oracle's count of the record's parts, ragged last
+    window included; Eq. 13's own count (oracle.bpvf) is what they exceed only
+    by word padding and the 16-byte table entries; the stage timers are
+    filled."""
+    from oracle import bitstream as B
     cb, ab, db = bits
     w = configs.small_torus(frames=40, T=16, k=6, precision="fp32")
     m = dmc.Mesh(ctx, w.n, w.tris, w.anchors)
     p = dmc.make_params(w.k, coef_bits=cb, anchor_bits=ab, dict_bits=db, precision=dmc.FP32)
     _, _, stats, status = dmc.compress_sequence(ctx, m, to_dev(w.frames), w.T, p)
     assert status == 0
+    for s, (s0, s1) in zip(stats, O.windows(w.F, w.T)):
+        Tw = s1 - s0
+        ref = B.record_bits(w.n, Tw, min(w.k, Tw), w.anchors.size, cb, ab, db, 4)
+        for key in ("q", "q_a", "q_d", "q_s"):
+            assert s[key] == pytest.approx(ref[key], rel=1e-12), (key, s[key], ref[key])
     shapes = [(e - s, min(w.k, e - s)) for s, e in O.windows(w.F, w.T)]
-    ref = O.bpvf(w.n, w.F, w.anchors.size, shapes, cb, anchor_bits=ab, dict_bits=db,
-                 raw_bits=32)
+    eq13 = O.bpvf(w.n, w.F, w.anchors.size, shapes, cb, anchor_bits=ab, dict_bits=db,
+                  raw_bits=32)
     agg = {key: sum(s[key] * s["T"] for s in stats) / w.F for key in ("q", "q_a", "q_d", "q_s")}
-    print(bits, agg, ref)
-    assert agg["q"] == pytest.approx(ref["q"] + ref["q_r"], rel=1e-12)
-    assert agg["q_a"] == pytest.approx(ref["q_a"], rel=1e-12)
-    assert agg["q_d"] == pytest.approx(ref["q_d"], rel=1e-12)
-    assert agg["q_s"] == pytest.approx(ref["q_s"], rel=1e-12)
+    print(bits, agg, eq13)
+    lo = 1 - 1e-12  # the aggregates are sums of ratios: rounding
+    assert lo * (eq13["q"] + eq13["q_r"]) <= agg["q"] <= 1.02 * (eq13["q"] + eq13["q_r"]) + 0.02
+    assert lo * eq13["q_a"] <= agg["q_a"] <= eq13["q_a"] * 1.1 + 0.01
     assert all(s["ms_encode"] > 0 and s["ms_decode"] > 0 for s in stats)

@@ -96,7 +96,7 @@ def test_encode_window_codes_bit_exact(ctx, prec, bits):
     U = _np(r["u"]).astype(np.float64)
     Y = _np(r["coef"])
     # header
-    assert list(view.header[:9]) == [0x31434D44, T, k, n, anchors.size, bits, 16, 16, prec]
+    assert list(view.header[:10]) == [0x32434D44, T, k, n, anchors.size, bits, 16, 16, prec, 0]
     # dictionary codes: oracle quantiser on the GPU's U
     for c in range(3):
         assert np.array_equal(view.dict_codes[c], O.quantise_uniform(U[c], -1.0, 1.0, 16))

@@ -9,6 +9,7 @@ import numpy as np
 import pytest
 
 import oracle as O
+from oracle import bitstream as B
 from paper_2111_10105_amd import dmc
 from synth import animate, meshes
 
@@ -33,10 +34,10 @@ def test_rate_distortion_sweep_against_oracle(gpu):
             _, ref = O.compress_sequence(n, t, fr, anchors, T, k, 12, init="exact",
                                          fp32_data=True)
             got = out.cpu().numpy()
-            shapes = [(e - s, min(k, e - s)) for s, e in O.windows(F, T)]
-            b = O.bpvf(n, F, anchors.size, shapes, 12)
             q = sum(s["q"] * s["T"] for s in stats) / F
-            assert q == pytest.approx(b["q"] + b["q_r"], rel=1e-12)
+            qref = sum(B.record_bits(n, e - s, min(k, e - s), anchors.size, 12, 16, 16, 4)["q"] *
+                       (e - s) for s, e in O.windows(F, T)) / F
+            assert q == pytest.approx(qref, rel=1e-12)
             e_or, e_in, r_in = O.nmse(got, ref), O.nmse(got, fr), O.nmse(ref, fr)
             print(f"k={k}: q={q:.4f} NMSE(gpu,oracle)={e_or:.3e} NMSE(gpu,input)={e_in:.4e} "
                   f"NMSE(oracle,input)={r_in:.4e}")
