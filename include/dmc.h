@@ -224,20 +224,36 @@ dmc_status dmc_host_normal_solve(int32_t n_verts, int32_t n_tris, const int32_t*
                                  double* X_host, double info[8]);
 
 /* ---- encoded window record -----------------------------------------------
- * One window's record is a byte buffer (device memory), 256-byte aligned
- * sections:
- *   header      64 B  (magic "DMC1", T, k, n, n_c, coef/anchor/dict bits,
- *                      precision)
- *   dictionary  [3][T][k]  uint16 codes over [-1, 1], or raw values
- *   row ranges  [3][k][2]  float32 (lo, hi) per kept row       (coef_bits > 0)
- *   codes       [3][k][n]  uint16 codes of Eq. (10), or raw values
- *   anchor rng  [3][2]     float32 (lo, hi) per coordinate     (anchor_bits > 0)
- *   anchors     [3][T][n_c] uint16 codes, or raw values
- * Raw values are float64 (DMC_FP64) or float32.  The bytes between a
- * section's data and the next 256-byte boundary are written as zeros, so
- * every byte of a record is defined.  A record is self-contained given the
- * mesh (connectivity and N are side information shared with the
- * decoder, as in Sec. III). */
+ * One window's record is a byte buffer (device memory) of
+ * dmc_window_code_bytes bytes (its capacity); its stream is its first
+ * "used" bytes (header words 11-12), all defined, the rest of the slot zero.
+ *   header   128 B: int32 words 0 magic "DMC2", 1 T, 2 k, 3 n, 4 n_c,
+ *            5 coef_bits, 6 anchor_bits, 7 dict_bits, 8 precision,
+ *            9 dict_mode, 10 1 if some dictionary column is a difference
+ *            from the previous window's, 11-12 used bytes (low, high),
+ *            13 words of the dictionary segments, 14-15 coef_step (double);
+ *            the rest zero.
+ *   tables   [3][k] dictionary columns, then [3][k] coefficient rows (row
+ *            r of coordinate c at index c k + r), 16 B each: float32 lo, hi;
+ *            uint32 bits (low byte) | mode << 8 (columns: 0 values, 1
+ *            difference); uint32 first 32-bit word of the segment in the
+ *            variable part.  Then the anchor ranges [3][2] float32.
+ *   anchors  from the next 256-byte boundary: [3] segments of T n_c codes
+ *            (index t n_c + a) at anchor_bits.
+ *   variable from the next 256-byte boundary: every dictionary column's
+ *            segment (T codes), then every coefficient row's (n codes), back
+ *            to back at the offsets of the tables.
+ * A segment holds codes of b bits packed least significant bit first (code
+ * j in bits [j b, (j + 1) b) of the segment's bit string, bit i of which is
+ * bit i mod 32 of 32-bit word i / 32), zero-padded to a multiple of 8 bytes;
+ * with bits = 0 (coef_bits, anchor_bits or dict_bits 0) it holds raw values
+ * (float64 for DMC_FP64, else float32).  A code c over [lo, hi] with b bits
+ * stands for lo + c (hi - lo) / (2^b - 1); a row or column of 0 bits stands
+ * for lo everywhere (hi = lo).  The plain dictionary code has lo = -1, hi =
+ * 1 and dict_bits bits.  A record is self-contained given the mesh
+ * (connectivity and N are side information shared with the decoder, as in
+ * Sec. III), except that a difference column needs the previous window's
+ * record of the same sequence. */
 size_t dmc_window_code_bytes(int32_t n, int32_t T, int32_t n_anchors,
                              const dmc_params* params);
 /* sum of dmc_window_code_bytes over the windows of an F-frame sequence */
