@@ -24,21 +24,41 @@ namespace dmc {
 namespace {
 
 constexpr int CTG = 64;  // columns per gather / reduce block (one per lane)
+
+// Block order of every solve kernel: column tiles fastest, block b = ct +
+// cbp (u + nu v), with cbp (the column-tile count padded to a multiple of
+// the 8 XCDs) so that the dispatcher, which deals consecutive blocks to the
+// XCDs in turn, runs every block of column tile ct on XCD ct mod 8.  A
+// tile's right-hand and solution rows then stay in that XCD's L2 from row
+// tile to row tile and level to level, and the blocks of one operator tile
+// run together, one read of it per XCD.  Blocks of padding tiles (ct >= the
+// tile count) return at once.
+constexpr int kXcds = 8;
+inline int pad_xcd(int tiles) { return (tiles + kXcds - 1) / kXcds * kXcds; }
+
+struct ColBlock {
+  int ct, u, v;
+};
+__device__ inline ColBlock col_block(int cbp, int nu) {
+  const int b = blockIdx.x, q = b / cbp;
+  return {b % cbp, q % nu, q / nu};
+}
 constexpr int RTK = 64;  // rows per task of the task lists
 constexpr int GQ = 16;   // gather: blocks per task (4 rows each, one per wave)
 constexpr int RPW = RTK / GQ / (kBlock / 64);  // gather rows per wave
 
 __global__ void __launch_bounds__(kBlock)
-k_fwd_gather(CholDev f, int t0, int ncols, const double* __restrict__ rhs,
+k_fwd_gather(CholDev f, int t0, int ncols, int cbp, const double* __restrict__ rhs,
              const double* __restrict__ U, double* __restrict__ W) {
-  const int task = t0 + blockIdx.x;
+  const ColBlock cbk = col_block(cbp, GQ);  // u = quarter, v = task
+  const int task = t0 + cbk.v;
   const int s = f.task_w_sn[task], r0 = f.task_w_r0[task];
-  const int c = blockIdx.y * CTG + threadIdx.x % CTG;
+  const int c = cbk.ct * CTG + threadIdx.x % CTG;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
   if (c >= ncols) return;
   const int a = f.sn_start[s], w = f.sn_start[s + 1] - a;
   for (int k = 0; k < RPW; ++k) {
-    const int t = r0 + blockIdx.z * (RTK / GQ) + wv * RPW + k;
+    const int t = r0 + cbk.u * (RTK / GQ) + wv * RPW + k;
     if (t >= w) break;
     const int j = a + t;
     double acc = rhs[(size_t)f.perm[j] * ncols + c];
@@ -102,13 +122,13 @@ struct MfmaTile {
 // The task of a block: the 64-row task lists are shared by both tile sizes;
 // with RT = 32 block x takes half x % 2 of task x / 2 (rows r0 + 32 (x % 2)).
 template <int RT>
-__device__ inline int tile_task(int t0, int& half) {
+__device__ inline int tile_task(int t0, int tidx, int& half) {
   if (RT == 64) {
     half = 0;
-    return t0 + blockIdx.x;
+    return t0 + tidx;
   }
-  half = blockIdx.x & 1;
-  return t0 + (blockIdx.x >> 1);
+  half = tidx & 1;
+  return t0 + (tidx >> 1);
 }
 
 // forward: [Y_s; U_s] rows r0..r0+RT-1 = B_s W_s (K = columns of B_s; rows of the
@@ -117,20 +137,22 @@ __device__ inline int tile_task(int t0, int& half) {
 // out of the LDS stage (kStages).
 template <int RT>
 __global__ void __launch_bounds__(kBlock)
-k_fwd_gemm(CholDev f, int t0, int ncols, const double* __restrict__ W, double* __restrict__ Y,
-           double* __restrict__ U) {
+k_fwd_gemm(CholDev f, int t0, int ncols, int cbp, int ntile, const double* __restrict__ W,
+           double* __restrict__ Y, double* __restrict__ U) {
   constexpr int CT = RT, LDB = MfmaTile<RT>::LDB;
   constexpr int KC = MfmaTile<RT>::KC, LDA = MfmaTile<RT>::LDA;
   constexpr int PER_T = RT * KC / kBlock;  // elements of a chunk staged per thread
   __shared__ double As[kStages][RT * LDA];
   __shared__ double Bs[kStages][KC * LDB];
+  const ColBlock cbk = col_block(cbp, ntile);  // u = row tile
+  if (cbk.ct * CT >= ncols) return;           // padding tile: whole block
   int half;
-  const int task = tile_task<RT>(t0, half);
+  const int task = tile_task<RT>(t0, cbk.u, half);
   const int s = f.task_m_sn[task], r0 = f.task_m_r0[task] + RT * half;
   const int a = f.sn_start[s], w = f.sn_start[s + 1] - a;
   const int m = f.sn_rowptr[s + 1] - f.sn_rowptr[s];
   if (r0 >= m) return;  // whole block
-  const int c0 = blockIdx.y * CT;
+  const int c0 = cbk.ct * CT;
   const double* Br = f.brow + f.sn_valptr[s];
   const int tid = threadIdx.x, lane = tid % 64, wv = tid / 64;
   const int wr = wv / 2, wc = wv % 2;
@@ -201,20 +223,22 @@ k_fwd_gemm(CholDev f, int t0, int ncols, const double* __restrict__ W, double* _
 // partial tile to `part` (summed by k_bwd_reduce); launched with RT = 64.
 template <int RT>
 __global__ void __launch_bounds__(kBlock)
-k_bwd_gemm(CholDev f, int t0, int ncols, const double* __restrict__ Y, double* __restrict__ X,
-           double* __restrict__ z, int nsplit, double* __restrict__ part) {
+k_bwd_gemm(CholDev f, int t0, int ncols, int cbp, int ntile, const double* __restrict__ Y,
+           double* __restrict__ X, double* __restrict__ z, int nsplit, double* __restrict__ part) {
   constexpr int CT = RT, LDB = MfmaTile<RT>::LDB;
   constexpr int KC = MfmaTile<RT>::KC, LDA = MfmaTile<RT>::LDA;
   constexpr int PER_T = RT * KC / kBlock;
   __shared__ double As[kStages][RT * LDA];
   __shared__ double Bs[kStages][KC * LDB];
   __shared__ int rows[RIDX];  // ancestor row indices of this block's K range
+  const ColBlock cbk = col_block(cbp, ntile);  // u = row tile, v = split
+  if (cbk.ct * CT >= ncols) return;           // padding tile: whole block
   int half;
-  const int task = tile_task<RT>(t0, half);
+  const int task = tile_task<RT>(t0, cbk.u, half);
   const int s = f.task_w_sn[task], r0 = f.task_w_r0[task] + RT * half;
   const int a = f.sn_start[s], w = f.sn_start[s + 1] - a;
   if (r0 >= w) return;  // whole block
-  const int c0 = blockIdx.y * CT;
+  const int c0 = cbk.ct * CT;
   const int rb0 = f.sn_rowptr[s], m = f.sn_rowptr[s + 1] - rb0;
   const double* Br = f.brow + f.sn_valptr[s];
   const int tid = threadIdx.x, lane = tid % 64, wv = tid / 64;
@@ -223,7 +247,7 @@ k_bwd_gemm(CholDev f, int t0, int ncols, const double* __restrict__ Y, double* _
   // split-K: this block's share of the K chunks (all of them when nsplit == 1)
   const int nch = (m - r0 + KC - 1) / KC;
   const int per = (nch + nsplit - 1) / nsplit;
-  const int kb = r0 + blockIdx.z * per * KC;
+  const int kb = r0 + cbk.v * per * KC;
   const int ke = min(m, kb + per * KC);
   auto load = [&](int i0) {
 #pragma unroll
@@ -292,7 +316,7 @@ k_bwd_gemm(CholDev f, int t0, int ncols, const double* __restrict__ Y, double* _
           X[(size_t)(a + tr) * ncols + c] = v;
           z[(size_t)f.perm[a + tr] * ncols + c] = v;
         } else {
-          part[(((size_t)blockIdx.z * gridDim.x + blockIdx.x) * RT + lr) * ncols + c] = v;
+          part[(((size_t)cbk.v * ntile + cbk.u) * RT + lr) * ncols + c] = v;
         }
       }
 }
@@ -301,17 +325,19 @@ constexpr int kMaxSplit = 16;  // split-K blocks per backward tile at most
 
 // sums the split-K partials of one level in split order (deterministic)
 __global__ void __launch_bounds__(kBlock)
-k_bwd_reduce(CholDev f, int t0, int ntasks, int ncols, int nsplit, const double* __restrict__ part,
-             double* __restrict__ X, double* __restrict__ z) {
-  const int task = t0 + blockIdx.x;
+k_bwd_reduce(CholDev f, int t0, int ntasks, int ncols, int cbp, int nsplit,
+             const double* __restrict__ part, double* __restrict__ X, double* __restrict__ z) {
+  const ColBlock cbk = col_block(cbp, 4);  // u = quarter, v = task
+  const int tidx = cbk.v;
+  const int task = t0 + tidx;
   const int s = f.task_w_sn[task], r0 = f.task_w_r0[task];
   const int a = f.sn_start[s], w = f.sn_start[s + 1] - a;
-  const int c0 = blockIdx.y * CTG;
-  constexpr int RQ = RTK / 4;  // rows per block (blockIdx.z picks the quarter)
+  const int c0 = cbk.ct * CTG;
+  constexpr int RQ = RTK / 4;  // rows per block (the block order picks the quarter)
 #pragma unroll
   for (int u = 0; u < RQ * CTG / kBlock; ++u) {
     const int e = threadIdx.x + u * kBlock;
-    const int lr = blockIdx.z * RQ + e / CTG, c = c0 + e % CTG;
+    const int lr = cbk.u * RQ + e / CTG, c = c0 + e % CTG;
     const int tr = r0 + lr;
     if (tr >= w || c >= ncols) continue;
     // every partial in flight at once, then added in split order (the
@@ -319,7 +345,7 @@ k_bwd_reduce(CholDev f, int t0, int ntasks, int ncols, int nsplit, const double*
     double pv[kMaxSplit];
 #pragma unroll
     for (int q = 0; q < kMaxSplit; ++q)
-      pv[q] = q < nsplit ? part[(((size_t)q * ntasks + blockIdx.x) * RTK + lr) * ncols + c] : 0.0;
+      pv[q] = q < nsplit ? part[(((size_t)q * ntasks + tidx) * RTK + lr) * ncols + c] : 0.0;
     double v = 0.0;
 #pragma unroll
     for (int q = 0; q < kMaxSplit; ++q) v += pv[q];
@@ -360,19 +386,21 @@ constexpr int kSmallLevelBlocks = 512;
 void launch_chol_solve(hipStream_t s, const CholDev& f, int32_t ncols, const double* r, double* z,
                        double* W, double* Y, double* X, double* U, double* part) {
   dim3 blk(kBlock);
-  const int cb = (ncols + CTG - 1) / CTG;
-  const int cb32 = (ncols + 31) / 32;
+  const int cb = (ncols + CTG - 1) / CTG, cbp = pad_xcd(cb);
+  const int cb32 = (ncols + 31) / 32, cbp32 = pad_xcd(cb32);
   for (int lv = 0; lv < f.nlevels; ++lv) {
     const int tw0 = f.level_w_host[lv], ntw = f.level_w_host[lv + 1] - tw0;
     const int tm0 = f.level_m_host[lv], ntm = f.level_m_host[lv + 1] - tm0;
     prof::begin(s, DMC_KERNEL_CHOL_FWD_GATHER);
-    hipLaunchKernelGGL(k_fwd_gather, dim3(ntw, cb, GQ), blk, 0, s, f, tw0, ncols, r, U, W);
+    hipLaunchKernelGGL(k_fwd_gather, dim3(cbp * GQ * ntw), blk, 0, s, f, tw0, ncols, cbp, r, U, W);
     prof::end(s, DMC_KERNEL_CHOL_FWD_GATHER);
     prof::begin(s, DMC_KERNEL_CHOL_FWD_SOLVE);
     if (ntm * cb < kSmallLevelBlocks)
-      hipLaunchKernelGGL(k_fwd_gemm<32>, dim3(2 * ntm, cb32), blk, 0, s, f, tm0, ncols, W, Y, U);
+      hipLaunchKernelGGL(k_fwd_gemm<32>, dim3(cbp32 * 2 * ntm), blk, 0, s, f, tm0, ncols, cbp32,
+                         2 * ntm, W, Y, U);
     else
-      hipLaunchKernelGGL(k_fwd_gemm<64>, dim3(ntm, cb), blk, 0, s, f, tm0, ncols, W, Y, U);
+      hipLaunchKernelGGL(k_fwd_gemm<64>, dim3(cbp * ntm), blk, 0, s, f, tm0, ncols, cbp, ntm, W,
+                         Y, U);
     prof::end(s, DMC_KERNEL_CHOL_FWD_SOLVE);
   }
   for (int lv = f.nlevels - 1; lv >= 0; --lv) {
@@ -381,15 +409,15 @@ void launch_chol_solve(hipStream_t s, const CholDev& f, int32_t ncols, const dou
     if (f.level_maxw_host[lv] <= 32) {
       // every supernode of the level is at most 32 wide (the dissection's
       // leaves and the lowest separators): 64-row tiles would be half padding
-      hipLaunchKernelGGL(k_bwd_gemm<32>, dim3(2 * ntw, cb32, 1), blk, 0, s, f, tw0, ncols, Y, X,
-                         z, 1, (double*)nullptr);
+      hipLaunchKernelGGL(k_bwd_gemm<32>, dim3(cbp32 * 2 * ntw), blk, 0, s, f, tw0, ncols, cbp32,
+                         2 * ntw, Y, X, z, 1, (double*)nullptr);
     } else {
       const int ns = part ? bwd_split(ntw, cb) : 1;
-      hipLaunchKernelGGL(k_bwd_gemm<64>, dim3(ntw, cb, ns), blk, 0, s, f, tw0, ncols, Y, X, z, ns,
-                         part);
+      hipLaunchKernelGGL(k_bwd_gemm<64>, dim3(cbp * ntw * ns), blk, 0, s, f, tw0, ncols, cbp, ntw,
+                         Y, X, z, ns, part);
       if (ns > 1)
-        hipLaunchKernelGGL(k_bwd_reduce, dim3(ntw, cb, 4), blk, 0, s, f, tw0, ntw, ncols, ns, part,
-                           X, z);
+        hipLaunchKernelGGL(k_bwd_reduce, dim3(cbp * 4 * ntw), blk, 0, s, f, tw0, ntw, ncols, cbp,
+                           ns, part, X, z);
     }
     prof::end(s, DMC_KERNEL_CHOL_BWD_SOLVE);
   }
