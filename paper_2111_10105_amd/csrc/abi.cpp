@@ -378,7 +378,7 @@ dmc_status check_learned(dmc_ctx ctx, const dmc_params& p, int32_t T) {
 
 // Decoder buffers for ncols right-hand sides, carved from one region.
 struct DecodeLayout {
-  size_t o_x, o_r, o_p, o_q, o_part, o_small, o_z, o_W, o_Y, o_X, o_U, o_S, o_Ah, o_gram, o_ut,
+  size_t o_x, o_r, o_p, o_q, o_part, o_small, o_z, o_W, o_Y, o_U, o_S, o_Ah, o_gram, o_ut,
       total;
 };
 
@@ -402,7 +402,6 @@ DecodeLayout decode_layout(const dmc::MeshDev& m, int32_t ncols, bool chol,
     d.o_z = cv.add(vec);
     d.o_W = cv.add(vec);
     d.o_Y = cv.add(vec);
-    d.o_X = cv.add(vec);
     d.o_U = cv.add((size_t)m.chol.nslots * ncols * 8);
     d.o_S = cv.add(dmc::chol_split_bytes(m.chol, ncols));
   }
@@ -456,7 +455,6 @@ dmc::CgBuffers decode_buffers(uint8_t* ws, const DecodeLayout& d, int32_t ncols,
   cb.z = chol ? (double*)(ws + d.o_z) : nullptr;
   cb.W = chol ? (double*)(ws + d.o_W) : nullptr;
   cb.Y = chol ? (double*)(ws + d.o_Y) : nullptr;
-  cb.X = chol ? (double*)(ws + d.o_X) : nullptr;
   cb.U = chol ? (double*)(ws + d.o_U) : nullptr;
   cb.S = chol ? (double*)(ws + d.o_S) : nullptr;
   double* small = (double*)(ws + d.o_small);
@@ -510,7 +508,7 @@ void decode_enqueue_finish(hipStream_t s, const dmc::MeshDev& m, const uint8_t* 
     dmc::launch_compose(s, m, records, sl, (const double*)(ws + d.lay.o_ut), cb.x,
                         (const double*)(ws + d.lay.o_Ah), p.precision, frames_out);
   else
-    dmc::launch_to_frames(s, cb.x, m.n, d.F, p.precision, frames_out);
+    dmc::launch_to_frames(s, m, cb.x, d.F, p.precision, frames_out);
 }
 
 void decode_enqueue_fixed(hipStream_t s, const dmc::MeshDev& m, const uint8_t* records,
@@ -922,6 +920,29 @@ dmc_status dmc_mesh_create(dmc_ctx ctx, int32_t n, int32_t n_tris, const int32_t
       if (M.col[e] == i) dinv[i] = 1.0 / M.val[e];
   }
   for (int32_t a = 0; a < n_anchors; ++a) slot[anchors[a]] = a;
+  // the decoder's row order: the factor's elimination order (position p holds
+  // vertex perm[p]); its operators re-indexed by position, each row's entries
+  // kept in the vertex's own order (the sums run as in vertex order)
+  const std::vector<int32_t>& perm = F.perm;
+  std::vector<int32_t> dpos(n), d_rowptr(n + 1, 0), d_col(C.col.size()), d_slot(n),
+      d_anchors(n_anchors), pm_rowptr(n + 1, 0), pm_col(M.col.size());
+  std::vector<double> d_w64(n), pm_val(M.val.size()), pm_dinv(n);
+  for (int32_t q = 0; q < n; ++q) dpos[perm[q]] = q;
+  for (int32_t q = 0; q < n; ++q) {
+    const int32_t i = perm[q];
+    d_w64[q] = w64[i];
+    d_slot[q] = slot[i];
+    pm_dinv[q] = dinv[i];
+    d_rowptr[q + 1] = d_rowptr[q] + (C.rowptr[i + 1] - C.rowptr[i]);
+    for (int32_t e = C.rowptr[i], o = d_rowptr[q]; e < C.rowptr[i + 1]; ++e, ++o)
+      d_col[o] = dpos[C.col[e]];
+    pm_rowptr[q + 1] = pm_rowptr[q] + (M.rowptr[i + 1] - M.rowptr[i]);
+    for (int32_t e = M.rowptr[i], o = pm_rowptr[q]; e < M.rowptr[i + 1]; ++e, ++o) {
+      pm_col[o] = dpos[M.col[e]];
+      pm_val[o] = M.val[e];
+    }
+  }
+  for (int32_t a = 0; a < n_anchors; ++a) d_anchors[a] = dpos[anchors[a]];
   // factor work items: (supernode, first row of a 64-row tile), by level, over
   // the supernode's w columns and over its m rows
   std::vector<int32_t> tw_sn, tw_r0, tm_sn, tm_r0, level_w(F.nlevels + 1, 0),
@@ -970,11 +991,16 @@ dmc_status dmc_mesh_create(dmc_ctx ctx, int32_t n, int32_t n_tris, const int32_t
   dv.w64 = (const double*)up(w64.data(), n * 8);
   dv.w32 = (const float*)up(w32.data(), n * 4);
   dv.anchors = (const int32_t*)up(anchors, (size_t)n_anchors * 4);
-  dv.slot = (const int32_t*)up(slot.data(), n * 4);
-  dv.m_rowptr = (const int32_t*)up(M.rowptr.data(), M.rowptr.size() * 4);
-  dv.m_col = (const int32_t*)up(M.col.data(), M.col.size() * 4);
-  dv.m_val = (const double*)up(M.val.data(), M.val.size() * 8);
-  dv.m_dinv = (const double*)up(dinv.data(), n * 8);
+  dv.dpos = (const int32_t*)up(dpos.data(), n * 4);
+  dv.d_rowptr = (const int32_t*)up(d_rowptr.data(), d_rowptr.size() * 4);
+  dv.d_col = (const int32_t*)up(d_col.data(), d_col.size() * 4);
+  dv.d_w64 = (const double*)up(d_w64.data(), n * 8);
+  dv.d_slot = (const int32_t*)up(d_slot.data(), n * 4);
+  dv.d_anchors = (const int32_t*)up(d_anchors.data(), (size_t)n_anchors * 4);
+  dv.m_rowptr = (const int32_t*)up(pm_rowptr.data(), pm_rowptr.size() * 4);
+  dv.m_col = (const int32_t*)up(pm_col.data(), pm_col.size() * 4);
+  dv.m_val = (const double*)up(pm_val.data(), pm_val.size() * 8);
+  dv.m_dinv = (const double*)up(pm_dinv.data(), n * 8);
   dmc::CholDev& cd = dv.chol;
   dv.solve_entries = info[6];
   cd.n = n;

@@ -80,7 +80,8 @@ RecordLayout record_layout(int32_t n, int32_t T, int32_t k, int32_t nc, const dm
 // host by build_cholesky, see chol_host.h).
 struct CholDev {
   int32_t n = 0, ns = 0, nlevels = 0;
-  const int32_t* perm = nullptr;        // elimination position -> vertex
+  const int32_t* perm = nullptr;        // elimination position -> vertex (host solve only:
+                                        // the device solves work in positions)
   const int32_t* sn_start = nullptr;    // [ns+1]
   const int32_t* sn_rowptr = nullptr;   // [ns+1]
   const int32_t* rowidx = nullptr;
@@ -111,14 +112,26 @@ struct MeshDev {
   const double* w64 = nullptr;       // [n] 1/d_i (uniform) or d_i (combinatorial)
   const float* w32 = nullptr;
   const int32_t* anchors = nullptr;  // [nc]
-  const int32_t* slot = nullptr;     // [n] anchor slot of a vertex, or -1
-  const int32_t* m_rowptr = nullptr; // [n+1] CSR of L^T L + I_N^T I_N
+  // The decoder's n-row blocks (right-hand sides, CG vectors, solutions, the
+  // anchor response) hold vertex perm[p] in row p, perm the factor's
+  // elimination order: ring members sit a few rows apart (nested dissection
+  // keeps each subdomain contiguous), so the sparse products find their
+  // neighbour rows in the L2, and the supernodal solves read and write their
+  // rows in place.  The operators below are indexed by that row position.
+  const int32_t* dpos = nullptr;     // [n] vertex -> row position
+  const int32_t* d_rowptr = nullptr; // [n+1] C by position (entries in each vertex's ring order)
+  const int32_t* d_col = nullptr;    // [nnz] positions of the ring members
+  const double* d_w64 = nullptr;     // [n] w64 by position
+  const int32_t* d_slot = nullptr;   // [n] anchor slot of a position, or -1
+  const int32_t* d_anchors = nullptr;// [nc] row position of each anchor
+  const int32_t* m_rowptr = nullptr; // [n+1] CSR of L^T L + I_N^T I_N, by position
   const int32_t* m_col = nullptr;
   const double* m_val = nullptr;
-  const double* m_dinv = nullptr;    // [n] 1 / diagonal
+  const double* m_dinv = nullptr;    // [n] 1 / diagonal, by position
   CholDev chol;
-  // anchor response G = (L^T L + I_N^T I_N)^{-1} I_N^T, [n][nc] vertex-major
-  // (nullptr when not built: the decoder then solves 3T columns per window)
+  // anchor response G = (L^T L + I_N^T I_N)^{-1} I_N^T, [n][nc], row p for
+  // vertex perm[p] (nullptr when not built: the decoder then solves 3T
+  // columns per window)
   const double* G = nullptr;
   double G_resid = 0.0;  // largest relative residual of G's columns
   double solve_entries = 0.0;  // entries of the solve operators (one triangular solve)
@@ -269,7 +282,7 @@ void launch_compose(hipStream_t s, const MeshDev& m, const uint8_t* records, con
 
 struct CgBuffers {
   double *x, *r, *p, *q;
-  double *z, *W, *Y, *X, *U;  // preconditioned residual and triangular-solve work
+  double *z, *W, *Y, *U;  // preconditioned residual and triangular-solve work
   double* S;                    // split-K partials of the backward solve
   double* part;      // [nblk_rows][ncols] x 2
   double *rz, *rr, *bnorm2, *alpha, *beta;
@@ -306,11 +319,14 @@ void launch_cg_restart(hipStream_t s, const MeshDev& m, int32_t ncols, const CgB
 void launch_cg_summary(hipStream_t s, const CgBuffers& cb, int32_t ncols, double* out);
 // part: split-K scratch of chol_split_bytes(f, ncols) bytes (nullptr: no split)
 size_t chol_split_bytes(const CholDev& f, int32_t ncols);
+// z = (L L^T)^-1 r for ncols columns (rows by position; z also serves the
+// backward solve as its solution block)
 void launch_chol_solve(hipStream_t s, const CholDev& f, int32_t ncols, const double* r, double* z,
-                       double* W, double* Y, double* X, double* U, double* part);
+                       double* W, double* Y, double* U, double* part);
 void launch_precond_apply(hipStream_t s, const MeshDev& m, int32_t ncols, const CgBuffers& cb,
                           double* p_out);
-void launch_to_frames(hipStream_t s, const double* X, int32_t n, int32_t F, int32_t precision,
-                      void* frames_out);
+// X [n][3F] (rows by position) -> frames [F][n][3] (vertex order)
+void launch_to_frames(hipStream_t s, const MeshDev& m, const double* X, int32_t F,
+                      int32_t precision, void* frames_out);
 
 }  // namespace dmc

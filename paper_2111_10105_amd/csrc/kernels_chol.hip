@@ -1,17 +1,18 @@
 // Supernodal triangular solves with the Cholesky factor of the normal matrix
 // (the decoder's preconditioner): z = (L L^T)^{-1} r for every column at once.
+// r and z hold their rows in elimination order (the decoder keeps all its
+// n-row blocks in that order), so the solves read and write them in place.
 //
 // Each supernode s (columns a..a+w-1, rows R_s of size m) carries the solve
 // operator B_s = [inv(L_ss); L_os inv(L_ss)] (m x w), precomputed on the host.
 // Level scheduling over the supernodal tree (supernodes of one level are
 // independent):
 //   forward, level 0 upwards
-//     gather : W_s = r[perm rows of s] - sum of the update rows aimed at s
+//     gather : W_s = r[rows of s] - sum of the update rows aimed at s
 //     gemm   : [Y_s; U_s] = B_s W_s   (Y_s = solution rows, U_s = update rows
 //              for the ancestors, one slot per row of s below its diagonal block)
 //   backward, top level downwards
-//     gemm   : X_s = B_s^T [Y_s; -X_(R_s below the diagonal block)],
-//              z[perm rows of s] = X_s
+//     gemm   : z_s = B_s^T [Y_s; -z_(R_s below the diagonal block)]
 // Work items are (supernode, 64-row tile) x 64-column tiles (the gather splits
 // each tile into four blocks of 16 rows; the backward GEMM splits its K range
 // over several blocks on levels with few tiles, and a second kernel adds the
@@ -61,7 +62,7 @@ k_fwd_gather(CholDev f, int t0, int ncols, int cbp, const double* __restrict__ r
     const int t = r0 + cbk.u * (RTK / GQ) + wv * RPW + k;
     if (t >= w) break;
     const int j = a + t;
-    double acc = rhs[(size_t)f.perm[j] * ncols + c];
+    double acc = rhs[(size_t)j * ncols + c];
     const int e1 = f.contrib_ptr[j + 1];
     int e = f.contrib_ptr[j];
     // eight independent partial sums keep several loads in flight
@@ -224,7 +225,7 @@ k_fwd_gemm(CholDev f, int t0, int ncols, int cbp, int ntile, const double* __res
 template <int RT>
 __global__ void __launch_bounds__(kBlock)
 k_bwd_gemm(CholDev f, int t0, int ncols, int cbp, int ntile, const double* __restrict__ Y,
-           double* __restrict__ X, double* __restrict__ z, int nsplit, double* __restrict__ part) {
+           double* __restrict__ X, int nsplit, double* __restrict__ part) {
   constexpr int CT = RT, LDB = MfmaTile<RT>::LDB;
   constexpr int KC = MfmaTile<RT>::KC, LDA = MfmaTile<RT>::LDA;
   constexpr int PER_T = RT * KC / kBlock;
@@ -314,7 +315,6 @@ k_bwd_gemm(CholDev f, int t0, int ncols, int cbp, int ntile, const double* __res
         const double v = t.acc[ta][tb][r];
         if (nsplit == 1) {
           X[(size_t)(a + tr) * ncols + c] = v;
-          z[(size_t)f.perm[a + tr] * ncols + c] = v;
         } else {
           part[(((size_t)cbk.v * ntile + cbk.u) * RT + lr) * ncols + c] = v;
         }
@@ -326,7 +326,7 @@ constexpr int kMaxSplit = 16;  // split-K blocks per backward tile at most
 // sums the split-K partials of one level in split order (deterministic)
 __global__ void __launch_bounds__(kBlock)
 k_bwd_reduce(CholDev f, int t0, int ntasks, int ncols, int cbp, int nsplit,
-             const double* __restrict__ part, double* __restrict__ X, double* __restrict__ z) {
+             const double* __restrict__ part, double* __restrict__ X) {
   const ColBlock cbk = col_block(cbp, 4);  // u = quarter, v = task
   const int tidx = cbk.v;
   const int task = t0 + tidx;
@@ -350,7 +350,6 @@ k_bwd_reduce(CholDev f, int t0, int ntasks, int ncols, int cbp, int nsplit,
 #pragma unroll
     for (int q = 0; q < kMaxSplit; ++q) v += pv[q];
     X[(size_t)(a + tr) * ncols + c] = v;
-    z[(size_t)f.perm[a + tr] * ncols + c] = v;
   }
 }
 
@@ -384,7 +383,8 @@ size_t chol_split_bytes(const CholDev& f, int32_t ncols) {
 constexpr int kSmallLevelBlocks = 512;
 
 void launch_chol_solve(hipStream_t s, const CholDev& f, int32_t ncols, const double* r, double* z,
-                       double* W, double* Y, double* X, double* U, double* part) {
+                       double* W, double* Y, double* U, double* part) {
+  double* X = z;  // rows by position: the solution block is the output
   dim3 blk(kBlock);
   const int cb = (ncols + CTG - 1) / CTG, cbp = pad_xcd(cb);
   const int cb32 = (ncols + 31) / 32, cbp32 = pad_xcd(cb32);
@@ -410,14 +410,14 @@ void launch_chol_solve(hipStream_t s, const CholDev& f, int32_t ncols, const dou
       // every supernode of the level is at most 32 wide (the dissection's
       // leaves and the lowest separators): 64-row tiles would be half padding
       hipLaunchKernelGGL(k_bwd_gemm<32>, dim3(cbp32 * 2 * ntw), blk, 0, s, f, tw0, ncols, cbp32,
-                         2 * ntw, Y, X, z, 1, (double*)nullptr);
+                         2 * ntw, Y, X, 1, (double*)nullptr);
     } else {
       const int ns = part ? bwd_split(ntw, cb) : 1;
       hipLaunchKernelGGL(k_bwd_gemm<64>, dim3(cbp * ntw * ns), blk, 0, s, f, tw0, ncols, cbp, ntw,
-                         Y, X, z, ns, part);
+                         Y, X, ns, part);
       if (ns > 1)
         hipLaunchKernelGGL(k_bwd_reduce, dim3(cbp * 4 * ntw), blk, 0, s, f, tw0, ntw, ncols, cbp,
-                           ns, part, X, z);
+                           ns, part, X);
     }
     prof::end(s, DMC_KERNEL_CHOL_BWD_SOLVE);
   }

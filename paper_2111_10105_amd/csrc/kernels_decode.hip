@@ -100,7 +100,8 @@ k_dict_decode(const uint8_t* __restrict__ records, size_t rec_bytes, RecordLayou
   }
 }
 
-// B0[i][3(t0+t)+c] = sum_r U~_c[t][r] Y^_c[r][i]  (Eq. 11/12 right-hand side)
+// B0[pos(i)][3(t0+t)+c] = sum_r U~_c[t][r] Y^_c[r][i]  (Eq. 11/12 right-hand
+// side; row by the vertex's position in the decoder's row order)
 // Thread (j, g) owns column j = 3 t + c of the window: its dictionary row
 // U~_c[t][.] stays in registers while it runs over the block's vertices
 // g, g + G, ... (G = 256 / 3T groups), reading each vertex's coefficients from
@@ -109,7 +110,8 @@ k_dict_decode(const uint8_t* __restrict__ records, size_t rec_bytes, RecordLayou
 template <typename Real>
 __global__ void __launch_bounds__(kBlock)
 k_back_project(const uint8_t* __restrict__ records, SeqLayout sl, int n, int ncols,
-               const double* __restrict__ ut, double* __restrict__ B0) {
+               const int32_t* __restrict__ pos, const double* __restrict__ ut,
+               double* __restrict__ B0) {
   // padded stride 33 keeps the coordinates of a vertex on different LDS banks
   __shared__ double Yh[BP_V * 3 * 33];
   const int w = blockIdx.y;
@@ -142,7 +144,7 @@ k_back_project(const uint8_t* __restrict__ records, SeqLayout sl, int n, int nco
 #pragma unroll
     for (int r = 0; r < 32; ++r)
       if (r < k) s = fma(u[r], y[r], s);
-    B0[(size_t)(i0 + v) * ncols + 3 * t0 + j] = s;
+    B0[(size_t)pos[i0 + v] * ncols + 3 * t0 + j] = s;
   }
 }
 
@@ -555,17 +557,18 @@ k_cg_pupdate(int n, int ncols, const double* __restrict__ beta, const double* __
   }
 }
 
-// X [n][3F] -> frames [F][n][3]
+// X [n][3F] (row pos(i) for vertex i) -> frames [F][n][3]
 template <typename Real>
 __global__ void __launch_bounds__(kBlock)
-k_to_frames(const double* __restrict__ X, int n, int F, Real* __restrict__ out) {
+k_to_frames(const double* __restrict__ X, const int32_t* __restrict__ pos, int n, int F,
+            Real* __restrict__ out) {
   __shared__ double tile[32][97];
   const int i0 = blockIdx.x * 32, t0 = blockIdx.y * 32;
   const int ncols = 3 * F;
   const int nv = min(32, n - i0), nt = min(32, F - t0);
   for (int e = threadIdx.x; e < 32 * 96; e += kBlock) {
     const int v = e / 96, j = e % 96;
-    if (v < nv && j < 3 * nt) tile[v][j] = X[(size_t)(i0 + v) * ncols + 3 * t0 + j];
+    if (v < nv && j < 3 * nt) tile[v][j] = X[(size_t)pos[i0 + v] * ncols + 3 * t0 + j];
   }
   __syncthreads();
   for (int e = threadIdx.x; e < 32 * 96; e += kBlock) {
@@ -590,11 +593,12 @@ __device__ inline int zoff(const SeqLayout& sl, int w) {
 
 constexpr int CR_V = 32;  // vertices per block of k_coef_rows
 
-// Yd[i][zoff(w) + c k + r] = Y^_wc[r][i] (dequantised coefficients, vertex-major)
+// Yd[pos(i)][zoff(w) + c k + r] = Y^_wc[r][i] (dequantised coefficients, one
+// row per vertex in the decoder's row order)
 template <typename Real>
 __global__ void __launch_bounds__(kBlock)
 k_coef_rows(const uint8_t* __restrict__ records, SeqLayout sl, int n, int nz,
-            double* __restrict__ Yd) {
+            const int32_t* __restrict__ pos, double* __restrict__ Yd) {
   __shared__ double tile[CR_V * 97];  // [v][c k + r], 3k <= 96
   const int w = blockIdx.y;
   const uint8_t* rec;
@@ -613,11 +617,12 @@ k_coef_rows(const uint8_t* __restrict__ records, SeqLayout sl, int n, int nz,
   const int z0 = zoff(sl, w);
   for (int e = threadIdx.x; e < nv * ck; e += kBlock) {
     const int v = e / ck, cr = e % ck;
-    Yd[(size_t)(i0 + v) * nz + z0 + cr] = tile[v * 97 + cr];
+    Yd[(size_t)pos[i0 + v] * nz + z0 + cr] = tile[v * 97 + cr];
   }
 }
 
-// right-hand sides of the anchor response: b[i][a] = 1 if vertex i is anchor a
+// right-hand sides of the anchor response: b[p][a] = 1 if the vertex at row
+// position p is anchor a (slot by position)
 __global__ void __launch_bounds__(kBlock)
 k_anchor_unit_rhs(const int32_t* __restrict__ slot, int n, int nc, double* __restrict__ b) {
   const size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x;
@@ -835,8 +840,9 @@ struct ComposeMfma<float> {
 template <typename Real, int TTM, int NV>
 __global__ void __launch_bounds__(kBlock)
 k_compose(const uint8_t* __restrict__ records, SeqLayout sl, int n, int nc, int nz, int ncols,
-          const double* __restrict__ G, const double* __restrict__ Z,
-          const double* __restrict__ Ah, const double* __restrict__ ut, Real* __restrict__ out) {
+          const int32_t* __restrict__ pos, const double* __restrict__ G,
+          const double* __restrict__ Z, const double* __restrict__ Ah,
+          const double* __restrict__ ut, Real* __restrict__ out) {
   const int w = blockIdx.y;
   const uint8_t* rec;
   int T, k, t0;
@@ -844,12 +850,13 @@ k_compose(const uint8_t* __restrict__ records, SeqLayout sl, int n, int nc, int 
   window_of(sl, records, w, rec, T, k, t0, lay);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   // this lane's vertices (B columns), one per 16-vertex tile of the wavefront
-  int iv_[NV];
+  int iv_[NV], ip_[NV];  // vertex, and its row in G and Z
   bool ok_[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
     iv_[v] = (blockIdx.x * 4 + wv) * 16 * NV + 16 * v + lane % 16;
     ok_[v] = iv_[v] < n;
+    ip_[v] = ok_[v] ? pos[iv_[v]] : 0;
   }
   const int kq = lane / 16;  // K index within a step of four
   const int tl = lane % 16;  // frame within a 16-frame tile (A row)
@@ -871,7 +878,7 @@ k_compose(const uint8_t* __restrict__ records, SeqLayout sl, int n, int nc, int 
     const bool av = a < nc;
     double vb[NV];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) vb[v] = (ok_[v] && av) ? G[(size_t)iv_[v] * nc + a] : 0.0;
+    for (int v = 0; v < NV; ++v) vb[v] = (ok_[v] && av) ? G[(size_t)ip_[v] * nc + a] : 0.0;
     const double* ar = Ah + (size_t)(av ? a : 0) * ncols + 3 * t0;
 #pragma unroll
     for (int c = 0; c < 3; ++c)
@@ -894,7 +901,7 @@ k_compose(const uint8_t* __restrict__ records, SeqLayout sl, int n, int nc, int 
       double vb[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v)
-        vb[v] = (ok_[v] && rv) ? Z[(size_t)iv_[v] * nz + z0 + c * k + r] : 0.0;
+        vb[v] = (ok_[v] && rv) ? Z[(size_t)ip_[v] * nz + z0 + c * k + r] : 0.0;
 #pragma unroll
       for (int tt = 0; tt < TTM; ++tt) {
         if (tt >= tt_n) continue;
@@ -961,10 +968,10 @@ void launch_back_project(hipStream_t s, const MeshDev& m, const uint8_t* records
   prof::begin(s, DMC_KERNEL_BACK_PROJECT);
   if (sl.full.precision == DMC_FP64)
     hipLaunchKernelGGL(k_back_project<double>, grid, dim3(kBlock), 0, s, records, sl, m.n, 3 * F,
-                       ut, B0);
+                       m.dpos, ut, B0);
   else
     hipLaunchKernelGGL(k_back_project<float>, grid, dim3(kBlock), 0, s, records, sl, m.n, 3 * F,
-                       ut, B0);
+                       m.dpos, ut, B0);
   prof::end(s, DMC_KERNEL_BACK_PROJECT);
 }
 
@@ -983,8 +990,8 @@ void launch_rhs(hipStream_t s, const MeshDev& m, const uint8_t* records, const S
                        s, records, sl, m.nc, ncols, Ah);
   dim3 grid(cg_part_rows(m.n), (ncols + RHS_COLS - 1) / RHS_COLS);
   prof::begin(s, DMC_KERNEL_RHS);
-  hipLaunchKernelGGL(k_rhs, grid, dim3(kBlock), 0, s, m.rowptr, m.col, m.w64,
-                     m.laplacian == DMC_LAP_UNIFORM ? 1 : 0, m.slot, m.n, ncols, B0, Ah, b, bb);
+  hipLaunchKernelGGL(k_rhs, grid, dim3(kBlock), 0, s, m.d_rowptr, m.d_col, m.d_w64,
+                     m.laplacian == DMC_LAP_UNIFORM ? 1 : 0, m.d_slot, m.n, ncols, B0, Ah, b, bb);
   prof::end(s, DMC_KERNEL_RHS);
 }
 
@@ -996,7 +1003,7 @@ void launch_precond_apply(hipStream_t s, const MeshDev& m, int32_t ncols, const 
   const int nrb = (int)cg_part_rows(m.n);
   dim3 grid(nrb, (ncols + SP_COLS - 1) / SP_COLS);
   double* z = p_out ? p_out : cb.z;
-  launch_chol_solve(s, m.chol, ncols, cb.r, z, cb.W, cb.Y, cb.X, cb.U, cb.S);
+  launch_chol_solve(s, m.chol, ncols, cb.r, z, cb.W, cb.Y, cb.U, cb.S);
   hipLaunchKernelGGL(k_cg_dot, grid, dim3(kBlock), 0, s, m.n, ncols, cb.r, z, (double*)nullptr,
                      cb.part);
 }
@@ -1028,7 +1035,7 @@ void launch_cg_warm_start(hipStream_t s, const MeshDev& m, int32_t ncols, const 
   const int nrb = (int)cg_part_rows(m.n);
   dim3 sgrid(nrb, (ncols + SP_COLS - 1) / SP_COLS);
   dim3 cgrid((ncols + RED_COLS - 1) / RED_COLS);
-  launch_chol_solve(s, m.chol, ncols, cb.r, cb.x, cb.W, cb.Y, cb.X, cb.U, cb.S);
+  launch_chol_solve(s, m.chol, ncols, cb.r, cb.x, cb.W, cb.Y, cb.U, cb.S);
   prof::begin(s, DMC_KERNEL_CG_SPMM);
   hipLaunchKernelGGL(k_cg_residual, sgrid, dim3(kBlock), 0, s, m.m_rowptr, m.m_col, m.m_val, m.n,
                      ncols, cb.x, cb.r, 0, cb.part);
@@ -1115,15 +1122,17 @@ void launch_cg_step_b(hipStream_t s, const MeshDev& m, int32_t ncols, const CgBu
                      precond, cb.r, cb.z, cb.p);
 }
 
-void launch_to_frames(hipStream_t s, const double* X, int32_t n, int32_t F, int32_t precision,
-                      void* frames_out) {
+void launch_to_frames(hipStream_t s, const MeshDev& m, const double* X, int32_t F,
+                      int32_t precision, void* frames_out) {
+  const int n = m.n;
   dim3 grid((n + 31) / 32, (F + 31) / 32);
   prof::begin(s, DMC_KERNEL_TO_FRAMES);
   if (precision == DMC_FP64)
-    hipLaunchKernelGGL(k_to_frames<double>, grid, dim3(kBlock), 0, s, X, n, F,
+    hipLaunchKernelGGL(k_to_frames<double>, grid, dim3(kBlock), 0, s, X, m.dpos, n, F,
                        (double*)frames_out);
   else
-    hipLaunchKernelGGL(k_to_frames<float>, grid, dim3(kBlock), 0, s, X, n, F, (float*)frames_out);
+    hipLaunchKernelGGL(k_to_frames<float>, grid, dim3(kBlock), 0, s, X, m.dpos, n, F,
+                       (float*)frames_out);
   prof::end(s, DMC_KERNEL_TO_FRAMES);
 }
 
@@ -1139,9 +1148,11 @@ void launch_coef_rows(hipStream_t s, const MeshDev& m, const uint8_t* records,
   const int nz = reduced_cols(sl);
   prof::begin(s, DMC_KERNEL_BACK_PROJECT);
   if (sl.full.precision == DMC_FP64)
-    hipLaunchKernelGGL(k_coef_rows<double>, grid, dim3(kBlock), 0, s, records, sl, m.n, nz, Yd);
+    hipLaunchKernelGGL(k_coef_rows<double>, grid, dim3(kBlock), 0, s, records, sl, m.n, nz,
+                       m.dpos, Yd);
   else
-    hipLaunchKernelGGL(k_coef_rows<float>, grid, dim3(kBlock), 0, s, records, sl, m.n, nz, Yd);
+    hipLaunchKernelGGL(k_coef_rows<float>, grid, dim3(kBlock), 0, s, records, sl, m.n, nz,
+                       m.dpos, Yd);
   prof::end(s, DMC_KERNEL_BACK_PROJECT);
 }
 
@@ -1149,8 +1160,8 @@ void launch_rhs_reduced(hipStream_t s, const MeshDev& m, int32_t nz, const doubl
                         double* bb) {
   dim3 grid(cg_part_rows(m.n), (nz + RHS_COLS - 1) / RHS_COLS);
   prof::begin(s, DMC_KERNEL_RHS);
-  hipLaunchKernelGGL(k_rhs, grid, dim3(kBlock), 0, s, m.rowptr, m.col, m.w64,
-                     m.laplacian == DMC_LAP_UNIFORM ? 1 : 0, m.slot, m.n, nz, Yd,
+  hipLaunchKernelGGL(k_rhs, grid, dim3(kBlock), 0, s, m.d_rowptr, m.d_col, m.d_w64,
+                     m.laplacian == DMC_LAP_UNIFORM ? 1 : 0, m.d_slot, m.n, nz, Yd,
                      (const double*)nullptr, b, bb);
   prof::end(s, DMC_KERNEL_RHS);
 }
@@ -1187,14 +1198,14 @@ void launch_group_ref(hipStream_t s, const MeshDev& m, const uint8_t* records, c
   hipLaunchKernelGGL(k_group_gram, dim3(3 * nw, nchunks), dim3(kBlock), 0, s, sl, m.n, nz, kk2, b,
                      gram_part);
   hipLaunchKernelGGL(k_group_ref, dim3(3 * nw), dim3(kBlock), 0, s, records, sl, m.nc, nz, 3 * F,
-                     nchunks, kk2, m.anchors, ut, b, Ah, (const double*)gram_part, m.G_resid, tol,
+                     nchunks, kk2, m.d_anchors, ut, b, Ah, (const double*)gram_part, m.G_resid, tol,
                      bnorm2);
 }
 
 void launch_anchor_unit_rhs(hipStream_t s, const MeshDev& m, double* b) {
   const size_t tot = (size_t)m.n * m.nc;
   hipLaunchKernelGGL(k_anchor_unit_rhs, dim3((tot + kBlock - 1) / kBlock), dim3(kBlock), 0, s,
-                     m.slot, m.n, m.nc, b);
+                     m.d_slot, m.n, m.nc, b);
 }
 
 void launch_compose(hipStream_t s, const MeshDev& m, const uint8_t* records, const SeqLayout& sl,
@@ -1212,12 +1223,12 @@ void launch_compose(hipStream_t s, const MeshDev& m, const uint8_t* records, con
   dim3 grid((m.n + CP_V * nv - 1) / (CP_V * nv), nw);
   if (precision == DMC_FP64) {
     auto kern = t32 ? k_compose<double, 2, 2> : k_compose<double, 4, 1>;
-    hipLaunchKernelGGL(kern, grid, dim3(kBlock), 0, s, records, sl, m.n, m.nc, nz, 3 * F, m.G, Z,
-                       Ah, ut, (double*)frames_out);
+    hipLaunchKernelGGL(kern, grid, dim3(kBlock), 0, s, records, sl, m.n, m.nc, nz, 3 * F, m.dpos,
+                       m.G, Z, Ah, ut, (double*)frames_out);
   } else {
     auto kern = t32 ? k_compose<float, 2, 2> : k_compose<float, 4, 1>;
-    hipLaunchKernelGGL(kern, grid, dim3(kBlock), 0, s, records, sl, m.n, m.nc, nz, 3 * F, m.G, Z,
-                       Ah, ut, (float*)frames_out);
+    hipLaunchKernelGGL(kern, grid, dim3(kBlock), 0, s, records, sl, m.n, m.nc, nz, 3 * F, m.dpos,
+                       m.G, Z, Ah, ut, (float*)frames_out);
   }
   prof::end(s, DMC_KERNEL_TO_FRAMES);
 }

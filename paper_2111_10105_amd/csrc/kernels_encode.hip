@@ -610,50 +610,30 @@ k_dict_code(const double* __restrict__ u_canon, int nw, int per_block, RecordLay
   }
 }
 
-// Coefficient-row table of each window (block = window): the row ranges from
-// the projection's per-block partials (float32, rounded outwards), the bits
-// of every row (coef_bits, or the fewest for coef_step), and the rows' word
-// offsets after the dictionary segments; then the header's used bytes.
-__global__ void __launch_bounds__(kBlock)
-k_row_table(int nblk, const double* __restrict__ mm, RecordLayout l, uint8_t* records,
+// Coefficient-row ranges (block = one row q of one window w): the row's
+// per-block partials from the projection reduced, rounded outwards to
+// float32, and the row's bits (coef_bits, or the fewest for coef_step).
+__global__ void __launch_bounds__(64)
+k_row_range(int nblk, const double* __restrict__ mm, RecordLayout l, uint8_t* records,
             size_t rec_bytes) {
-  __shared__ uint32_t sbits[DC_COLS];
-  const int w = blockIdx.x, nq = 3 * l.k;
-  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-  uint8_t* rec = records + (size_t)w * rec_bytes;
-  SegEntry* tab = (SegEntry*)(rec + l.off_rtab);
-  for (int q = wave; q < nq; q += kBlock / 64) {
-    const double* m = mm + ((size_t)w * nq + q) * nblk * 2;
-    double lo = 1e300, hi = -1e300;
-    for (int b = lane; b < nblk; b += 64) {
-      lo = fmin(lo, m[2 * b]);
-      hi = fmax(hi, m[2 * b + 1]);
-    }
-    lo = wave_min(lo);
-    hi = wave_max(hi);
-    const float flo = __double2float_rd(lo), fhi = __double2float_ru(hi);
-    uint32_t bits = (uint32_t)l.coef_bits;
-    if (l.coef_bits > 0 && l.coef_step > 0.0)
-      bits = bits_for_step((double)flo, (double)fhi, l.coef_step, (uint32_t)l.coef_bits);
-    if (lane == 0) {
-      tab[q].lo = l.coef_bits > 0 ? flo : 0.f;
-      tab[q].hi = l.coef_bits > 0 ? fhi : 0.f;
-      tab[q].bits_mode = bits;
-      sbits[q] = bits;
-    }
+  const int q = blockIdx.x, w = blockIdx.y, nq = 3 * l.k, lane = threadIdx.x;
+  SegEntry* tab = (SegEntry*)(records + (size_t)w * rec_bytes + l.off_rtab);
+  const double* m = mm + ((size_t)w * nq + q) * nblk * 2;
+  double lo = 1e300, hi = -1e300;
+  for (int b = lane; b < nblk; b += 64) {
+    lo = fmin(lo, m[2 * b]);
+    hi = fmax(hi, m[2 * b + 1]);
   }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const int32_t* h = (const int32_t*)rec;
-    uint32_t off = (uint32_t)h[kHdrDictWords];
-    for (int q = 0; q < nq; ++q) {
-      tab[q].word_off = off;
-      off += seg_words((uint32_t)l.n, sbits[q], (uint32_t)l.real);
-    }
-    const uint64_t used = l.off_var + 4ull * off;
-    int32_t* hw = (int32_t*)rec;
-    hw[kHdrUsedLo] = (int32_t)(uint32_t)used;
-    hw[kHdrUsedHi] = (int32_t)(uint32_t)(used >> 32);
+  lo = wave_min(lo);
+  hi = wave_max(hi);
+  const float flo = __double2float_rd(lo), fhi = __double2float_ru(hi);
+  uint32_t bits = (uint32_t)l.coef_bits;
+  if (l.coef_bits > 0 && l.coef_step > 0.0)
+    bits = bits_for_step((double)flo, (double)fhi, l.coef_step, (uint32_t)l.coef_bits);
+  if (lane == 0) {
+    tab[q].lo = l.coef_bits > 0 ? flo : 0.f;
+    tab[q].hi = l.coef_bits > 0 ? fhi : 0.f;
+    tab[q].bits_mode = bits;
   }
 }
 
@@ -661,16 +641,35 @@ k_row_table(int nblk, const double* __restrict__ mm, RecordLayout l, uint8_t* re
 // (x, q, w) writes words x*256 + tid, x*256 + tid + gridDim.x*256, ... of row
 // q of window w, each word from the codes that fall in it (a code across a
 // word boundary is computed by both words' threads); raw rows are copied.
+// Each wave finds the row's word offset (after the dictionary segments) from
+// the bits of the rows before it, lane r taking rows r and r + 64; block
+// (0, q, w) stores it in the table and block (0, last row, w) the record's
+// used bytes in the header.
 template <typename Real>
 __global__ void __launch_bounds__(kBlock)
 k_quantise_pack(const Real* __restrict__ Y, int n, int k, RecordLayout l, uint8_t* records,
                 size_t rec_bytes) {
-  const int q = blockIdx.y, w = blockIdx.z;
+  const int q = blockIdx.y, w = blockIdx.z, nq = 3 * k, lane = threadIdx.x % 64;
   uint8_t* rec = records + (size_t)w * rec_bytes;
-  const SegEntry e = ((const SegEntry*)(rec + l.off_rtab))[q];
-  const Real* y = Y + ((size_t)w * 3 * k + q) * n;
-  uint32_t* seg = (uint32_t*)(rec + l.off_var) + e.word_off;
+  SegEntry* tab = (SegEntry*)(rec + l.off_rtab);
+  uint32_t part = 0;
+  for (int r = lane; r < q; r += 64)
+    part += seg_words((uint32_t)n, tab[r].bits_mode & 0xff, (uint32_t)l.real);
+  // (a sum of word counts, exact in float64)
+  const uint32_t off = (uint32_t)((const int32_t*)rec)[kHdrDictWords] + (uint32_t)wave_sum((double)part);
+  const SegEntry e = tab[q];
   const uint32_t bits = e.bits_mode & 0xff;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    tab[q].word_off = off;
+    if (q == nq - 1) {
+      const uint64_t used = l.off_var + 4ull * (off + seg_words((uint32_t)n, bits, (uint32_t)l.real));
+      int32_t* hw = (int32_t*)rec;
+      hw[kHdrUsedLo] = (int32_t)(uint32_t)used;
+      hw[kHdrUsedHi] = (int32_t)(uint32_t)(used >> 32);
+    }
+  }
+  const Real* y = Y + ((size_t)w * 3 * k + q) * n;
+  uint32_t* seg = (uint32_t*)(rec + l.off_var) + off;
   const uint32_t stride = gridDim.x * kBlock;
   if (l.coef_bits == 0) {
     Real* raw = (Real*)seg;
@@ -907,7 +906,7 @@ static void project_impl(hipStream_t s, const MeshDev& m, const void* frames, in
                        m.w64, uni, n, T, k, fr, u_tilde, Y, mm);
   prof::end(s, DMC_KERNEL_PROJECT);
   prof::begin(s, DMC_KERNEL_QUANTISE);
-  hipLaunchKernelGGL(k_row_table, dim3(nw), dim3(kBlock), 0, s, nblk, (const double*)mm, lay,
+  hipLaunchKernelGGL(k_row_range, dim3(3 * k, nw), dim3(64), 0, s, nblk, (const double*)mm, lay,
                      records, rec_bytes);
   // words of a row at its widest, spread so that a block writes a few per thread
   const uint32_t wmax = seg_words((uint32_t)n, lay.coef_bits > 0 ? lay.coef_bits : 0,
