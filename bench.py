@@ -144,7 +144,9 @@ def work_model(fam, *, n, F, T, k, nw, rs, ncols, nnz, m_nnz, finfo, sweeps_tota
     if fam == "cg_update":
         return "hbm", (5 if cg_first else 6) * vec, "B", hbm
     if fam == "chol_fwd_gather":
-        return "hbm", 2 * vec + 8.0 * finfo["update_rows"] * ncols, "B", hbm
+        # rows above the leaves: read r, write W; plus the update rows read
+        gathered = float(n) - finfo["leaf_rows"]
+        return "hbm", 8.0 * (2 * gathered + finfo["update_rows"]) * ncols, "B", hbm
     if fam in ("chol_fwd_solve", "chol_bwd_solve"):
         return "mfma", 2.0 * finfo["solve_entries"] * ncols, "flop", f64
     if fam == "to_frames":

@@ -188,13 +188,16 @@ dmc_status dmc_mesh_create(dmc_ctx ctx, int32_t n_verts, int32_t n_tris,
 void dmc_mesh_destroy(dmc_mesh mesh);
 int32_t dmc_mesh_nnz(dmc_mesh mesh);          /* nonzeros of C (= 2 |E|)       */
 int32_t dmc_mesh_normal_nnz(dmc_mesh mesh);   /* nonzeros of L^T L + I_N^T I_N */
-/* sizes of the normal matrix's Cholesky factor: [0] stored entries,
- * [1] nonzeros of the exact factor, [2] supernodes, [3] tree levels,
- * [4] factorisation flops, [5] host seconds to build it, [6] entries of the
- * solve operators one triangular solve reads (per right-hand side: 2 flops
- * each), [7] update rows (entries of the factor left of a diagonal block,
- * counted by row of the supernode that produces them) */
-void dmc_mesh_factor_info(dmc_mesh mesh, double info[8]);
+/* sizes of the normal matrix's Cholesky factor, DMC_FACTOR_INFO_LEN values:
+ * [0] stored entries, [1] nonzeros of the exact factor, [2] supernodes,
+ * [3] tree levels, [4] factorisation flops, [5] host seconds to build it,
+ * [6] entries of the solve operators one triangular solve reads (per
+ * right-hand side: 2 flops each), [7] update rows (entries of the factor left
+ * of a diagonal block, counted by row of the supernode that produces them),
+ * [8] columns of the leaf supernodes (rows the forward solve takes straight
+ * from the right-hand side: no update reaches them) */
+#define DMC_FACTOR_INFO_LEN 9
+void dmc_mesh_factor_info(dmc_mesh mesh, double info[DMC_FACTOR_INFO_LEN]);
 /* Whether the mesh holds its anchor response G = (L^T L + I_N^T I_N)^{-1}
  * I_N^T (n x n_c, float64 on the device).  The right-hand side of Eq. (12) is
  * linear in the decoded delta coordinates and anchor values, so with G the
@@ -221,7 +224,7 @@ int32_t dmc_mesh_anchor_response(dmc_mesh mesh, int32_t* cg_iters, double* resid
 dmc_status dmc_host_normal_solve(int32_t n_verts, int32_t n_tris, const int32_t* tris_host,
                                  int32_t n_anchors, const int32_t* anchors_host,
                                  int32_t laplacian, int32_t ncols, const double* B_host,
-                                 double* X_host, double info[8]);
+                                 double* X_host, double info[DMC_FACTOR_INFO_LEN]);
 
 /* ---- encoded window record -----------------------------------------------
  * One window's record is a byte buffer (device memory) of

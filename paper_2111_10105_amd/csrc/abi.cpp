@@ -54,7 +54,7 @@ struct dmc_mesh_s {
   std::vector<void*> allocations;
   std::vector<int32_t> level_w, level_m;  // host copies of the factor's level -> task ranges
   std::vector<int32_t> level_maxw;        // widest supernode of each level
-  double factor_info[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  double factor_info[DMC_FACTOR_INFO_LEN] = {};
   int32_t g_iters = 0;  // CG iterations of the anchor response (0: not built)
 };
 
@@ -659,7 +659,7 @@ constexpr int32_t kNdLeaf = 128;
 
 dmc_status build_mesh_host(int32_t n, int32_t n_tris, const int32_t* tris, int32_t n_anchors,
                            const int32_t* anchors, int32_t laplacian, dmc::HostCsr& C,
-                           dmc::HostCsr& M, dmc::CholFactor& F, double info[8]) {
+                           dmc::HostCsr& M, dmc::CholFactor& F, double info[DMC_FACTOR_INFO_LEN]) {
   if (n < 1 || n_tris < 1 || !tris) return fail(DMC_ERR_INVALID_ARG, "need n >= 1 and triangles");
   if (laplacian != DMC_LAP_UNIFORM && laplacian != DMC_LAP_COMBINATORIAL)
     return fail(DMC_ERR_INVALID_ARG, "unknown Laplacian");
@@ -696,15 +696,17 @@ dmc_status build_mesh_host(int32_t n, int32_t n_tris, const int32_t* tris, int32
   info[5] = secs;
   // entries of the solve operators one triangular solve reads (lower
   // triangle of inv(L_ss) plus the dense L_os inv(L_ss)), and update rows
-  double entries = 0.0, updates = 0.0;
+  double entries = 0.0, updates = 0.0, leaf_rows = 0.0;
   for (int32_t s = 0; s < F.nsuper; ++s) {
     const double w = F.sn_start[s + 1] - F.sn_start[s];
     const double m = F.sn_rowptr[s + 1] - F.sn_rowptr[s];
     entries += w * (w + 1) / 2 + (m - w) * w;
     updates += m - w;
+    if (F.sn_level[s] == 0) leaf_rows += w;
   }
   info[6] = entries;
   info[7] = updates;
+  info[8] = leaf_rows;
   return DMC_OK;
 }
 
@@ -906,7 +908,7 @@ dmc_status dmc_mesh_create(dmc_ctx ctx, int32_t n, int32_t n_tris, const int32_t
   *out = nullptr;
   dmc::HostCsr C, M;
   dmc::CholFactor F;
-  double info[8];
+  double info[DMC_FACTOR_INFO_LEN];
   dmc_status st = build_mesh_host(n, n_tris, tris, n_anchors, anchors, laplacian, C, M, F, info);
   if (st != DMC_OK) return st;
   std::vector<double> w64(n), dinv(n, 0.0);
@@ -1053,18 +1055,18 @@ int32_t dmc_mesh_anchor_response(dmc_mesh mesh, int32_t* cg_iters, double* resid
   return mesh->dev.G ? 1 : 0;
 }
 
-void dmc_mesh_factor_info(dmc_mesh mesh, double info[8]) {
+void dmc_mesh_factor_info(dmc_mesh mesh, double info[DMC_FACTOR_INFO_LEN]) {
   if (!mesh || !info) return;
   std::memcpy(info, mesh->factor_info, sizeof(mesh->factor_info));
 }
 
 dmc_status dmc_host_normal_solve(int32_t n, int32_t n_tris, const int32_t* tris, int32_t n_anchors,
                                  const int32_t* anchors, int32_t laplacian, int32_t ncols,
-                                 const double* B, double* X, double info[8]) {
+                                 const double* B, double* X, double info[DMC_FACTOR_INFO_LEN]) {
   if (ncols < 1 || !B || !X) return fail(DMC_ERR_INVALID_ARG, "bad right-hand side");
   dmc::HostCsr C, M;
   dmc::CholFactor F;
-  double inf[8];
+  double inf[DMC_FACTOR_INFO_LEN];
   dmc_status st = build_mesh_host(n, n_tris, tris, n_anchors, anchors, laplacian, C, M, F, inf);
   if (st != DMC_OK) return st;
   dmc::chol_solve_host(F, ncols, B, X);

@@ -14,6 +14,10 @@
 namespace dmc {
 
 constexpr int kBlock = 256;
+// XCDs of an MI355X: the dispatcher deals consecutive workgroups of a launch
+// to them in turn (workgroup b runs on XCD b mod 8), each with its own L2.
+constexpr int kXcds = 8;
+inline int pad_xcd(int blocks) { return (blocks + kXcds - 1) / kXcds * kXcds; }
 constexpr size_t kAlign = 256;
 
 inline size_t align_up(size_t x, size_t a = kAlign) { return (x + a - 1) / a * a; }

@@ -34,8 +34,6 @@ constexpr int CTG = 64;  // columns per gather / reduce block (one per lane)
 // tile to row tile and level to level, and the blocks of one operator tile
 // run together, one read of it per XCD.  Blocks of padding tiles (ct >= the
 // tile count) return at once.
-constexpr int kXcds = 8;
-inline int pad_xcd(int tiles) { return (tiles + kXcds - 1) / kXcds * kXcds; }
 
 struct ColBlock {
   int ct, u, v;
@@ -391,15 +389,21 @@ void launch_chol_solve(hipStream_t s, const CholDev& f, int32_t ncols, const dou
   for (int lv = 0; lv < f.nlevels; ++lv) {
     const int tw0 = f.level_w_host[lv], ntw = f.level_w_host[lv + 1] - tw0;
     const int tm0 = f.level_m_host[lv], ntm = f.level_m_host[lv + 1] - tm0;
-    prof::begin(s, DMC_KERNEL_CHOL_FWD_GATHER);
-    hipLaunchKernelGGL(k_fwd_gather, dim3(cbp * GQ * ntw), blk, 0, s, f, tw0, ncols, cbp, r, U, W);
-    prof::end(s, DMC_KERNEL_CHOL_FWD_GATHER);
+    // the leaves (level 0) receive no updates: their rows of W are those of r
+    const double* Wl = r;
+    if (lv > 0) {
+      prof::begin(s, DMC_KERNEL_CHOL_FWD_GATHER);
+      hipLaunchKernelGGL(k_fwd_gather, dim3(cbp * GQ * ntw), blk, 0, s, f, tw0, ncols, cbp, r, U,
+                         W);
+      prof::end(s, DMC_KERNEL_CHOL_FWD_GATHER);
+      Wl = W;
+    }
     prof::begin(s, DMC_KERNEL_CHOL_FWD_SOLVE);
     if (ntm * cb < kSmallLevelBlocks)
       hipLaunchKernelGGL(k_fwd_gemm<32>, dim3(cbp32 * 2 * ntm), blk, 0, s, f, tm0, ncols, cbp32,
-                         2 * ntm, W, Y, U);
+                         2 * ntm, Wl, Y, U);
     else
-      hipLaunchKernelGGL(k_fwd_gemm<64>, dim3(cbp * ntm), blk, 0, s, f, tm0, ncols, cbp, ntm, W,
+      hipLaunchKernelGGL(k_fwd_gemm<64>, dim3(cbp * ntm), blk, 0, s, f, tm0, ncols, cbp, ntm, Wl,
                          Y, U);
     prof::end(s, DMC_KERNEL_CHOL_FWD_SOLVE);
   }

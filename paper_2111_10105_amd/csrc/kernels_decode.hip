@@ -176,66 +176,154 @@ __global__ void k_anchor_values(const uint8_t* __restrict__ records, SeqLayout s
   Ah[e] = v;
 }
 
-// b = L^T B0 + I_N^T Ahat (the anchor term only when Ah is given)
+// ---- right-hand side ------------------------------------------------------------
+// k_rhs: a block takes CG_RB consecutive rows and SP_CW columns (SP_CPL per
+// lane, 64 apart).  Row blocks go to the XCDs
+// in contiguous runs: the x extent is padded to a multiple of the XCD count
+// and block x takes row block (x mod 8) per + x / 8, so each XCD walks its
+// own stretch of rows in order and finds the ring members' rows (a few
+// positions away in the elimination order) in its L2.  The block's pattern
+// (row offsets, column positions, values or weights) is staged in LDS first,
+// so a wavefront's row loads wait on no index load of their own; each row's
+// products go to four partial sums by entry index mod 4, added as
+// (s0 + s1) + (s2 + s3).
+constexpr int SP_CPL = 4, SP_CW = 64 * SP_CPL;
+constexpr int SP_PAT = 1024;  // pattern entries staged per block (beyond: read from memory)
+
+__device__ inline int xcd_row_block(int nrbp) {
+  const int per = nrbp / kXcds;
+  return (int)(blockIdx.x % kXcds) * per + (int)(blockIdx.x / kXcds);
+}
+
+// rows r0..r0+nr of the pattern into spr / scol / sval (sval[e] = wt(e))
+template <typename Wt>
+__device__ inline void stage_pattern(const int32_t* __restrict__ rowptr,
+                                     const int32_t* __restrict__ col, int r0, int nr, int* spr,
+                                     int* scol, double* sval, int& base, Wt wt) {
+  for (int e = threadIdx.x; e <= nr; e += kBlock) spr[e] = rowptr[r0 + e];
+  __syncthreads();
+  base = spr[0];
+  const int cnt = min(spr[nr] - base, SP_PAT);
+  for (int e = threadIdx.x; e < cnt; e += kBlock) {
+    const int c = col[base + e];
+    scol[e] = c;
+    sval[e] = wt(base + e, c);
+  }
+  __syncthreads();
+}
+
+// sum over row entries e0..e1 of wt(e) v[col(e)] for the lane's SP_CPL columns
+template <typename Col, typename Wt>
+__device__ inline void row_products(int e0, int e1, int ncols, const double* const (&vj)[SP_CPL],
+                                    Col colof, Wt wtof, double (&out)[SP_CPL]) {
+  double a[4][SP_CPL];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int u = 0; u < SP_CPL; ++u) a[q][u] = 0.0;
+  int e = e0;
+  for (; e + 4 <= e1; e += 4) {
+    int c[4];
+    double wq[4], xv[4][SP_CPL];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      c[q] = colof(e + q);
+      wq[q] = wtof(e + q);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int u = 0; u < SP_CPL; ++u) xv[q][u] = vj[u][(size_t)c[q] * ncols];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int u = 0; u < SP_CPL; ++u) a[q][u] = fma(wq[q], xv[q][u], a[q][u]);
+  }
+  for (; e < e1; ++e) {
+    const int c = colof(e);
+    const double wv = wtof(e);
+#pragma unroll
+    for (int u = 0; u < SP_CPL; ++u) a[0][u] = fma(wv, vj[u][(size_t)c * ncols], a[0][u]);
+  }
+#pragma unroll
+  for (int u = 0; u < SP_CPL; ++u) out[u] = (a[0][u] + a[1][u]) + (a[2][u] + a[3][u]);
+}
+
+// the block's per-column partial sums (wavefront order) into part[rb][j]
+__device__ inline void block_column_partials(double (&v)[SP_CPL], double (*sh)[SP_CW], int ncols,
+                                             int rb, double* __restrict__ part) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int u = 0; u < SP_CPL; ++u) sh[wv][lane + 64 * u] = v[u];
+  __syncthreads();
+  const int j = blockIdx.y * SP_CW + threadIdx.x;
+  if (threadIdx.x < SP_CW && j < ncols) {
+    double t = sh[0][threadIdx.x];
+#pragma unroll
+    for (int w = 1; w < kBlock / 64; ++w) t += sh[w][threadIdx.x];
+    part[(size_t)rb * ncols + j] = t;
+  }
+}
+
+// b = L^T B0 + I_N^T Ahat (the anchor term only when Ah is given), rows by
+// position:
 //   uniform:       (L^T u)_i = u_i - sum_{j in ring(i)} u_j / d_j
 //   combinatorial: (L^T u)_i = d_i u_i - sum_{j in ring(i)} u_j
-// A block takes CG_RB rows and 64 columns (one per lane); its four
-// wavefronts take every fourth row, with the row's pattern in scalar loads.
-// With bb given, also the block's partial b.b per column (the four
-// wavefronts' sums added in wavefront order), the first half of the CG
-// partials.
-constexpr int RHS_COLS = 64;
-
+// (the ring weight is staged as 1 / d_j, or as 1 for the combinatorial
+// form).  With bb given, also the block's partial b.b per column, the first
+// half of the CG partials.
 __global__ void __launch_bounds__(kBlock)
 k_rhs(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
       const double* __restrict__ w, int uniform, const int32_t* __restrict__ slot, int n,
-      int ncols, const double* __restrict__ B0, const double* __restrict__ Ah,
+      int ncols, int nrbp, const double* __restrict__ B0, const double* __restrict__ Ah,
       double* __restrict__ b, double* __restrict__ bb) {
   constexpr int NW = kBlock / 64;
-  __shared__ double sh[NW][RHS_COLS];
+  __shared__ double sh[NW][SP_CW];
+  __shared__ int spr[CG_RB + 1];
+  __shared__ int scol[SP_PAT];
+  __shared__ double sval[SP_PAT];
+  const int rb = xcd_row_block(nrbp);
+  const int r0 = rb * CG_RB;
+  if (r0 >= n) return;  // padding block
+  const int r1 = min(n, r0 + CG_RB);
+  int base;
+  stage_pattern(rowptr, col, r0, r1 - r0, spr, scol, sval, base,
+                [&](int, int c) { return uniform ? w[c] : 1.0; });
   const int lane = threadIdx.x & 63;
-  const int j = blockIdx.y * RHS_COLS + lane;
-  const bool jv = j < ncols;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int r0 = blockIdx.x * CG_RB, r1 = min(n, r0 + CG_RB);
-  const double* Bj = B0 + (jv ? j : 0);
-  double b2 = 0.0;
+  int j[SP_CPL];
+  bool jv[SP_CPL];
+  const double* Bj[SP_CPL];
+#pragma unroll
+  for (int u = 0; u < SP_CPL; ++u) {
+    j[u] = blockIdx.y * SP_CW + lane + 64 * u;
+    jv[u] = j[u] < ncols;
+    Bj[u] = B0 + (jv[u] ? j[u] : 0);
+  }
+  auto colof = [&](int e) { return e - base < SP_PAT ? scol[e - base] : col[e]; };
+  auto wtof = [&](int e) {
+    return e - base < SP_PAT ? sval[e - base] : (uniform ? w[col[e]] : 1.0);
+  };
+  double b2[SP_CPL];
+#pragma unroll
+  for (int u = 0; u < SP_CPL; ++u) b2[u] = 0.0;
   for (int i = r0 + wv; i < r1; i += NW) {
-    const double ui = Bj[(size_t)i * ncols];
-    const int e1 = rowptr[i + 1];
-    int e = rowptr[i];
-    // four independent partial sums keep several row loads in flight
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    for (; e + 4 <= e1; e += 4) {
-      const int n0 = col[e], n1 = col[e + 1], n2 = col[e + 2], n3 = col[e + 3];
-      const double v0 = Bj[(size_t)n0 * ncols], v1 = Bj[(size_t)n1 * ncols];
-      const double v2 = Bj[(size_t)n2 * ncols], v3 = Bj[(size_t)n3 * ncols];
-      s0 += uniform ? v0 * w[n0] : v0;
-      s1 += uniform ? v1 * w[n1] : v1;
-      s2 += uniform ? v2 * w[n2] : v2;
-      s3 += uniform ? v3 * w[n3] : v3;
-    }
-    for (; e < e1; ++e) {
-      const int nb = col[e];
-      const double v = Bj[(size_t)nb * ncols];
-      s0 += uniform ? v * w[nb] : v;
-    }
-    const double s = (s0 + s1) + (s2 + s3);
-    double out = uniform ? ui - s : w[i] * ui - s;
+    double s[SP_CPL], ui[SP_CPL];
+#pragma unroll
+    for (int u = 0; u < SP_CPL; ++u) ui[u] = Bj[u][(size_t)i * ncols];
+    row_products(spr[i - r0], spr[i - r0 + 1], ncols, Bj, colof, wtof, s);
+    const double wi = w[i];
     const int sl = slot[i];
-    if (Ah && sl >= 0 && jv) out += Ah[(size_t)sl * ncols + j];
-    if (jv) b[(size_t)i * ncols + j] = out;
-    b2 = fma(out, out, b2);
+#pragma unroll
+    for (int u = 0; u < SP_CPL; ++u) {
+      double out = uniform ? ui[u] - s[u] : wi * ui[u] - s[u];
+      if (Ah && sl >= 0 && jv[u]) out += Ah[(size_t)sl * ncols + j[u]];
+      if (jv[u]) b[(size_t)i * ncols + j[u]] = out;
+      b2[u] = fma(out, out, b2[u]);
+    }
   }
   if (!bb) return;  // uniform over the block
-  sh[wv][lane] = b2;
-  __syncthreads();
-  if (threadIdx.x < RHS_COLS && jv) {
-    double v = sh[0][lane];
-#pragma unroll
-    for (int u = 1; u < NW; ++u) v += sh[u][lane];
-    bb[(size_t)blockIdx.x * ncols + j] = v;
-  }
+  block_column_partials(b2, sh, ncols, rb, bb);
 }
 
 // ---- conjugate gradients ----------------------------------------------------
@@ -324,7 +412,7 @@ k_cg_init_reduce(const double* __restrict__ part, int nrb, int ncols,
   resid[j] = v == 0.0 ? 0.0 : 1.0;
 }
 
-// q = M p (CSR of L^T L + I_N^T I_N), partial p.q per column.  A block
+// q = M p (CSR of L^T L + I_N^T I_N, by position), partial p.q per column.  A block
 // takes CG_RB rows and 64 columns (one per lane); its four wavefronts take
 // every fourth row, so each lane has a short chain of rows, and their p.q
 // partials are added in wavefront order (deterministic).  The row's pattern
@@ -931,6 +1019,11 @@ k_compose(const uint8_t* __restrict__ records, SeqLayout sl, int n, int nc, int 
 
 }  // namespace
 
+// grid of k_rhs: row blocks padded to the XCD count, 256-column tiles
+static dim3 rhs_grid(int n, int ncols) {
+  return dim3(pad_xcd((n + CG_RB - 1) / CG_RB), (ncols + SP_CW - 1) / SP_CW);
+}
+
 size_t cg_part_rows(int32_t n) { return (size_t)(n + CG_RB - 1) / CG_RB; }
 
 void launch_dict_decode(hipStream_t s, const uint8_t* records, const SeqLayout& sl, double* ut) {
@@ -988,10 +1081,11 @@ void launch_rhs(hipStream_t s, const MeshDev& m, const uint8_t* records, const S
   else
     hipLaunchKernelGGL(k_anchor_values<float>, dim3((tot + kBlock - 1) / kBlock), dim3(kBlock), 0,
                        s, records, sl, m.nc, ncols, Ah);
-  dim3 grid(cg_part_rows(m.n), (ncols + RHS_COLS - 1) / RHS_COLS);
+  const dim3 grid = rhs_grid(m.n, ncols);
   prof::begin(s, DMC_KERNEL_RHS);
   hipLaunchKernelGGL(k_rhs, grid, dim3(kBlock), 0, s, m.d_rowptr, m.d_col, m.d_w64,
-                     m.laplacian == DMC_LAP_UNIFORM ? 1 : 0, m.d_slot, m.n, ncols, B0, Ah, b, bb);
+                     m.laplacian == DMC_LAP_UNIFORM ? 1 : 0, m.d_slot, m.n, ncols, (int)grid.x, B0,
+                     Ah, b, bb);
   prof::end(s, DMC_KERNEL_RHS);
 }
 
@@ -1158,10 +1252,10 @@ void launch_coef_rows(hipStream_t s, const MeshDev& m, const uint8_t* records,
 
 void launch_rhs_reduced(hipStream_t s, const MeshDev& m, int32_t nz, const double* Yd, double* b,
                         double* bb) {
-  dim3 grid(cg_part_rows(m.n), (nz + RHS_COLS - 1) / RHS_COLS);
+  const dim3 grid = rhs_grid(m.n, nz);
   prof::begin(s, DMC_KERNEL_RHS);
   hipLaunchKernelGGL(k_rhs, grid, dim3(kBlock), 0, s, m.d_rowptr, m.d_col, m.d_w64,
-                     m.laplacian == DMC_LAP_UNIFORM ? 1 : 0, m.d_slot, m.n, nz, Yd,
+                     m.laplacian == DMC_LAP_UNIFORM ? 1 : 0, m.d_slot, m.n, nz, (int)grid.x, Yd,
                      (const double*)nullptr, b, bb);
   prof::end(s, DMC_KERNEL_RHS);
 }

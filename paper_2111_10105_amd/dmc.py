@@ -260,7 +260,7 @@ class Mesh:
         return lib().dmc_mesh_normal_nnz(self.h)
 
     def factor_info(self) -> dict:
-        a = (ctypes.c_double * 8)()
+        a = (ctypes.c_double * len(FACTOR_INFO_KEYS))()
         lib().dmc_mesh_factor_info(self.h, a)
         return dict(zip(FACTOR_INFO_KEYS, list(a)))
 
@@ -275,7 +275,7 @@ class Mesh:
 
 
 FACTOR_INFO_KEYS = ("stored", "nnz_exact", "supernodes", "levels", "flops", "seconds",
-                    "solve_entries", "update_rows")
+                    "solve_entries", "update_rows", "leaf_rows")
 
 
 def host_normal_solve(n, tris, anchors, B, laplacian: int = LAP_UNIFORM):
@@ -287,7 +287,7 @@ def host_normal_solve(n, tris, anchors, B, laplacian: int = LAP_UNIFORM):
     if B.ndim == 1:
         B = B[:, None]
     X = np.empty_like(B)
-    info = (ctypes.c_double * 8)()
+    info = (ctypes.c_double * len(FACTOR_INFO_KEYS))()
     _check(lib().dmc_host_normal_solve(int(n), int(tris.shape[0]), tris.ctypes.data_as(ctypes.c_void_p),
                                        int(anchors.size), anchors.ctypes.data_as(ctypes.c_void_p),
                                        int(laplacian), int(B.shape[1]),

@@ -103,6 +103,9 @@ def test_host_factor_solve_matches_direct_solve(mesh, nc, lap):
     assert np.max(np.abs(M @ X - B)) / np.max(np.abs(B)) < 1e-9
     assert info["stored"] >= info["nnz_exact"] - n  # every factor entry is stored
     assert info["levels"] >= 1 and info["supernodes"] >= 1
+    # the leaves' columns: some, and all of them when the tree is one level
+    assert 0 < info["leaf_rows"] <= n
+    assert (info["leaf_rows"] == n) == (info["levels"] == 1)
 
 
 def test_host_factor_rejects_unanchored_component():
