@@ -81,6 +81,10 @@ def parse():
                          "rate-distortion sweep over k")
     ap.add_argument("--no-second-workload", action="store_true",
                     help="skip the torus workload that runs beside the headline")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="time the headline steps and kernel families only (no start or "
+                         "precision variants, no second workload, no CPU baseline): the run "
+                         "profiled under rocprofv3")
     return ap.parse_args()
 
 
@@ -459,6 +463,9 @@ def main():
     launches, kernel_ms = dmc.profile_stop()
     elapsed = sum(times)
 
+    if args.headline_only:
+        args.no_second_workload = True
+        args.no_cpu_baseline = True
     # encode-only and decode-only split (outside the timed region)
     enc = timed_steps(lambda: dmc.compress_sequence(ctx, mesh, frames, T, p, q_start=q0,
                                                     codes=codes, decode=False, stats=False),
@@ -485,6 +492,8 @@ def main():
     }
     nrep = max(3, args.steps // 4)
     by_init = {}
+    if args.headline_only:
+        variants = {}
     for name, (mode, qs) in variants.items():
         pv = dmc.make_params(w.k, coef_bits=w.bits, precision=dmc.FP32, init=mode)
         tv, stv, stt, outv = run_form(dmc, ctx, mesh, frames, T, pv, qs, nrep, flush, codes)
@@ -493,7 +502,8 @@ def main():
                          "oi_sweeps_total": int(sum(sum(x["oi_sweeps"]) for x in stv)),
                          "status": stt, "nmse_vs_input": nmse(outv.cpu().numpy(), w.frames)}
     pb = dmc.make_params(w.k, coef_bits=w.bits, precision=dmc.BF16)
-    tb, stb, stt, outb = run_form(dmc, ctx, mesh, frames, T, pb, q0, nrep, flush, codes)
+    tb, stb, stt, outb = run_form(dmc, ctx, mesh, frames, T, pb, q0,
+                                  1 if args.headline_only else nrep, flush, codes)
     msb = sum(tb) / len(tb) * 1e3
     got_bf16 = outb.cpu().numpy()
     by_precision = {"bf16": {"ms_per_step": round(msb, 4), "value": round(vf / (msb * 1e-3), 1),

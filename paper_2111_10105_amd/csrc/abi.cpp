@@ -318,7 +318,7 @@ dmc_status encode_chain(dmc_ctx ctx, const dmc::MeshDev& m, const void* frames, 
     cur += dmc::align_up((size_t)nw * 3 * 4);
   }
   void* proj = cur;
-  for (int32_t w = 0; w < nw; ++w) dmc::launch_write_header(s, records + (size_t)w * lay.bytes, lay);
+  dmc::launch_write_headers(s, records, nw, lay.bytes, lay);
   dmc::launch_autocorr(s, frames, m.n, T, nw, p.precision, part, R);
   if (p.init == DMC_INIT_LEARNED) {
     dmc::launch_mlp_sketch(s, R, nw * 3, T, ctx->learned_omega, sk);
@@ -1665,10 +1665,10 @@ void batch_enqueue(dmc_batch b, hipStream_t s) {
   const size_t rs = real_size(b->precision);
   for (BatchSeq& q : b->seq) {
     const dmc::MeshDev& m = q.mesh->dev;
-    for (int32_t w = 0; w < q.sl.nw_full; ++w)
-      dmc::launch_write_header(s, q.codes + (size_t)w * q.sl.full.bytes, q.sl.full);
+    dmc::launch_write_headers(s, q.codes, q.sl.nw_full, q.sl.full.bytes, q.sl.full);
     if (q.sl.T_tail)
-      dmc::launch_write_header(s, q.codes + (size_t)q.sl.nw_full * q.sl.full.bytes, q.sl.tail);
+      dmc::launch_write_headers(s, q.codes + (size_t)q.sl.nw_full * q.sl.full.bytes, 1,
+                                q.sl.tail.bytes, q.sl.tail);
     if (q.sl.nw_full)
       dmc::launch_autocorr(s, q.frames, m.n, q.T, q.sl.nw_full, b->precision, shared,
                            (double*)(b->buf + q.o_R), q.P);

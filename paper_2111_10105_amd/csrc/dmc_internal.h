@@ -238,7 +238,9 @@ void launch_dict_code(hipStream_t s, const double* u_canon, int32_t nw, const Re
 // zeros after each record's used bytes (run last)
 void launch_zero_tail(hipStream_t s, uint8_t* records, int32_t nw, size_t rec_bytes);
 
-void launch_write_header(hipStream_t s, uint8_t* rec, const RecordLayout& lay);
+// headers of nw records rec_bytes apart (and the zeros of their alignment gaps)
+void launch_write_headers(hipStream_t s, uint8_t* records, int32_t nw, size_t rec_bytes,
+                          const RecordLayout& lay);
 
 // ---- decode ----------------------------------------------------------------
 

@@ -468,7 +468,9 @@ __device__ inline uint32_t pack_word(uint32_t wi, uint32_t count, uint32_t bits,
 // Header words: sizes and formats; the words filled later (has_diff,
 // used bytes, dictionary words) start at zero.  Zeros in the alignment
 // gaps of the fixed part, so every byte of a record's stream is defined.
-__global__ void k_header(uint8_t* rec, RecordLayout l) {
+// block w: the header of record w (records rec_bytes apart) and its alignment gaps
+__global__ void k_header(uint8_t* records, size_t rec_bytes, RecordLayout l) {
+  uint8_t* rec = records + (size_t)blockIdx.x * rec_bytes;
   int32_t* h = (int32_t*)rec;
   if (threadIdx.x < kHeaderBytes / 4) {
     const int i = threadIdx.x;
@@ -983,8 +985,9 @@ void launch_zero_tail(hipStream_t s, uint8_t* records, int32_t nw, size_t rec_by
   hipLaunchKernelGGL(k_zero_tail, dim3(chunks, nw), dim3(kBlock), 0, s, records, rec_bytes);
 }
 
-void launch_write_header(hipStream_t s, uint8_t* rec, const RecordLayout& l) {
-  hipLaunchKernelGGL(k_header, dim3(1), dim3(64), 0, s, rec, l);
+void launch_write_headers(hipStream_t s, uint8_t* records, int32_t nw, size_t rec_bytes,
+                          const RecordLayout& l) {
+  if (nw > 0) hipLaunchKernelGGL(k_header, dim3(nw), dim3(64), 0, s, records, rec_bytes, l);
 }
 
 }  // namespace dmc
