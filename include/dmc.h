@@ -180,7 +180,11 @@ dmc_status dmc_set_workspace(dmc_ctx ctx, void* dev_ptr, size_t bytes);
  * [n_anchors], distinct vertex indices (the set N of Eq. 12; anchor values are
  * stored in this order).  Errors: DMC_ERR_INVALID_ARG for an index out of
  * range, a repeated anchor, or a vertex with no neighbour (Eq. 3 undefined);
- * DMC_ERR_SINGULAR when a connected component holds no anchor. */
+ * DMC_ERR_SINGULAR when a connected component holds no anchor.  The sparse
+ * Cholesky factor of the normal matrix (the decoder's preconditioner) is
+ * ordered and analysed on the host (nested dissection, supernodes) and
+ * factorised on the device, level by level of the supernodal tree.
+ * Synchronises the context's stream. */
 dmc_status dmc_mesh_create(dmc_ctx ctx, int32_t n_verts, int32_t n_tris,
                            const int32_t* tris_host, int32_t n_anchors,
                            const int32_t* anchors_host, int32_t laplacian,
@@ -190,7 +194,10 @@ int32_t dmc_mesh_nnz(dmc_mesh mesh);          /* nonzeros of C (= 2 |E|)       *
 int32_t dmc_mesh_normal_nnz(dmc_mesh mesh);   /* nonzeros of L^T L + I_N^T I_N */
 /* sizes of the normal matrix's Cholesky factor, DMC_FACTOR_INFO_LEN values:
  * [0] stored entries, [1] nonzeros of the exact factor, [2] supernodes,
- * [3] tree levels, [4] factorisation flops, [5] host seconds to build it,
+ * [3] tree levels, [4] factorisation flops, [5] seconds to build the factor
+ * (host ordering and symbolic analysis, then the numeric factorisation and
+ * the solve operators on the device; all on the host for
+ * dmc_host_normal_solve),
  * [6] entries of the solve operators one triangular solve reads (per
  * right-hand side: 2 flops each), [7] update rows (entries of the factor left
  * of a diagonal block, counted by row of the supernode that produces them),
@@ -214,6 +221,17 @@ void dmc_mesh_factor_info(dmc_mesh mesh, double info[DMC_FACTOR_INFO_LEN]);
  * 0 if not built (the decoder then solves 3T columns per window) or for a
  * NULL mesh. */
 int32_t dmc_mesh_anchor_response(dmc_mesh mesh, int32_t* cg_iters, double* resid);
+
+/* Solves (L^T L + I_N^T I_N) X = B, the normal matrix of Eq. (12), for
+ * ncols right-hand sides with the mesh's sparse Cholesky factor (the
+ * decoder's preconditioner, factorised on the device by dmc_mesh_create):
+ * one forward and one backward supernodal solve, no iteration.  B_dev and
+ * X_dev are float64 [n][ncols] row-major device arrays in vertex order and
+ * may not alias.  Uses the context's scratch, or its workspace
+ * (DMC_ERR_BUFFER_TOO_SMALL when that is short).  Synchronises the context's
+ * stream at the end. */
+dmc_status dmc_mesh_normal_solve(dmc_ctx ctx, dmc_mesh mesh, int32_t ncols, const double* B_dev,
+                                 double* X_dev);
 
 /* Host-only check of the ordering and factorisation (no device needed):
  * builds L^T L + I_N^T I_N and its supernodal Cholesky factor exactly as

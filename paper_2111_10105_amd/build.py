@@ -16,7 +16,7 @@ OBJ = os.path.join(HERE, "_build")
 # the longest units first, so that they start at once on the parallel build
 SOURCES = ["kernels_oi_t64k32.hip", "kernels_oi_t64k16.hip", "kernels_oi_t32k32.hip",
            "kernels_oi_t32k16.hip", "kernels_mlp.hip", "kernels_encode.hip", "kernels_chol.hip",
-           "kernels_decode.hip", "kernels_oi.hip", "abi.cpp", "mesh_host.cpp", "chol_host.cpp",
+           "kernels_decode.hip", "kernels_factor.hip", "kernels_oi.hip", "abi.cpp", "mesh_host.cpp", "chol_host.cpp",
            "profile.cpp"]
 
 # packed FP32 instructions are disabled (the compiler would otherwise form them

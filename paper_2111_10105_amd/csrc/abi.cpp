@@ -657,9 +657,12 @@ dmc_status decode_all(dmc_ctx ctx, const dmc::MeshDev& m, const uint8_t* records
 // for somewhat more operator entries in the dense leaf blocks.
 constexpr int32_t kNdLeaf = 128;
 
+// numeric: also factorise on the host (else only the ordering and symbolic
+// analysis run here, and dmc_mesh_create factorises on the device)
 dmc_status build_mesh_host(int32_t n, int32_t n_tris, const int32_t* tris, int32_t n_anchors,
                            const int32_t* anchors, int32_t laplacian, dmc::HostCsr& C,
-                           dmc::HostCsr& M, dmc::CholFactor& F, double info[DMC_FACTOR_INFO_LEN]) {
+                           dmc::HostCsr& M, dmc::CholFactor& F, double info[DMC_FACTOR_INFO_LEN],
+                           bool numeric) {
   if (n < 1 || n_tris < 1 || !tris) return fail(DMC_ERR_INVALID_ARG, "need n >= 1 and triangles");
   if (laplacian != DMC_LAP_UNIFORM && laplacian != DMC_LAP_COMBINATORIAL)
     return fail(DMC_ERR_INVALID_ARG, "unknown Laplacian");
@@ -685,10 +688,11 @@ dmc_status build_mesh_host(int32_t n, int32_t n_tris, const int32_t* tris, int32
                                       "anchored system is singular");
   dmc::build_normal_matrix(C, laplacian, anchors, n_anchors, M);
   const auto t0 = std::chrono::steady_clock::now();
-  if (!dmc::build_cholesky(M, kNdLeaf, F, msg)) return fail(DMC_ERR_SINGULAR, msg);
+  if (!dmc::build_cholesky_symbolic(M, kNdLeaf, F, msg)) return fail(DMC_ERR_SINGULAR, msg);
+  if (numeric && !dmc::factor_numeric_host(F, msg)) return fail(DMC_ERR_SINGULAR, msg);
   const double secs =
       std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-  info[0] = (double)F.val.size();
+  info[0] = (double)F.sn_valptr[F.nsuper];
   info[1] = (double)F.nnz_exact;
   info[2] = F.nsuper;
   info[3] = F.nlevels;
@@ -901,6 +905,109 @@ dmc_status dmc_set_workspace(dmc_ctx ctx, void* dev_ptr, size_t bytes) {
   return DMC_OK;
 }
 
+// Numeric factorisation of the mesh's normal matrix on the device from the
+// host's symbolic analysis F (kernels_factor.hip): uploads the structure and
+// the work lists, runs the levels, keeps the solve operators B_s (the solve
+// kernels' brow) and frees the rest.  DMC_ERR_SINGULAR if a pivot is not
+// positive.
+static dmc_status factor_on_device(dmc_ctx ctx, dmc_mesh m, const dmc::CholFactor& F) {
+  hipStream_t s = ctx->stream;
+  const int32_t n = F.n, ns = F.nsuper, nl = F.nlevels;
+  // work lists: supernodes by level, update tiles (lower-triangle tiles of the
+  // levels above the leaves), operator tasks
+  std::vector<int32_t> sn_off(nl + 1, 0), lv_sn, tile_off(nl + 1, 0), tile_sn, tile_rc, maxm(nl, 0),
+      maxw(nl, 0), op_sn, op_row, sn_of(n);
+  std::vector<std::vector<int32_t>> by_level(nl);
+  for (int32_t q = 0; q < ns; ++q) by_level[F.sn_level[q]].push_back(q);
+  for (int32_t lv = 0; lv < nl; ++lv) {
+    for (int32_t q : by_level[lv]) {
+      const int32_t w = F.sn_start[q + 1] - F.sn_start[q];
+      const int32_t mm = F.sn_rowptr[q + 1] - F.sn_rowptr[q];
+      lv_sn.push_back(q);
+      maxm[lv] = std::max(maxm[lv], mm);
+      maxw[lv] = std::max(maxw[lv], w);
+      if (F.seg_ptr[q + 1] > F.seg_ptr[q])
+        for (int32_t cb = 0; cb * 64 < w; ++cb)
+          for (int32_t rb = cb; rb * 64 < mm; ++rb) {
+            tile_sn.push_back(q);
+            tile_rc.push_back(rb << 16 | cb);
+          }
+    }
+    sn_off[lv + 1] = (int32_t)lv_sn.size();
+    tile_off[lv + 1] = (int32_t)tile_sn.size();
+  }
+  for (int32_t q = 0; q < ns; ++q) {
+    for (int32_t j = F.sn_start[q]; j < F.sn_start[q + 1]; ++j) sn_of[j] = q;
+    const int32_t mm = F.sn_rowptr[q + 1] - F.sn_rowptr[q];
+    for (int32_t r0 = 0; r0 < mm; r0 += 64) {
+      op_sn.push_back(q);
+      op_row.push_back(r0);
+    }
+  }
+  std::vector<void*> tmp;
+  bool ok = true;
+  auto dev = [&](const void* src, size_t bytes, bool keep) -> void* {
+    void* d = nullptr;
+    if (hipMalloc(&d, std::max<size_t>(bytes, 8)) != hipSuccess) {
+      ok = false;
+      return nullptr;
+    }
+    (keep ? m->allocations : tmp).push_back(d);
+    if (src && bytes && hipMemcpy(d, src, bytes, hipMemcpyHostToDevice) != hipSuccess) ok = false;
+    return d;
+  };
+  const dmc::CholDev& cd = m->dev.chol;
+  const size_t vals = (size_t)F.sn_valptr[ns];
+  dmc::FactorDev fd;
+  fd.n = n;
+  fd.sn_start = cd.sn_start;
+  fd.sn_rowptr = cd.sn_rowptr;
+  fd.rowidx = cd.rowidx;
+  fd.sn_valptr = cd.sn_valptr;
+  fd.sn_of = (const int32_t*)dev(sn_of.data(), sn_of.size() * 4, false);
+  fd.acol_ptr = (const int32_t*)dev(F.acol_ptr.data(), F.acol_ptr.size() * 4, false);
+  fd.acol_row = (const int32_t*)dev(F.acol_row.data(), F.acol_row.size() * 4, false);
+  fd.acol_val = (const double*)dev(F.acol_val.data(), F.acol_val.size() * 8, false);
+  fd.seg_ptr = (const int32_t*)dev(F.seg_ptr.data(), F.seg_ptr.size() * 4, false);
+  fd.seg_d = (const int32_t*)dev(F.seg_d.data(), F.seg_d.size() * 4, false);
+  fd.seg_p1 = (const int32_t*)dev(F.seg_p1.data(), F.seg_p1.size() * 4, false);
+  fd.seg_p2 = (const int32_t*)dev(F.seg_p2.data(), F.seg_p2.size() * 4, false);
+  fd.L = (double*)dev(nullptr, vals * 8, false);
+  fd.B = (double*)dev(nullptr, vals * 8, true);
+  const int32_t fail_init = INT32_MAX;
+  fd.fail = (int32_t*)dev(&fail_init, 4, false);
+  dmc::FactorPlan fp;
+  fp.nlevels = nl;
+  fp.tile_off = tile_off.data();
+  fp.tile_sn = (const int32_t*)dev(tile_sn.data(), tile_sn.size() * 4, false);
+  fp.tile_rc = (const int32_t*)dev(tile_rc.data(), tile_rc.size() * 4, false);
+  fp.sn_off = sn_off.data();
+  fp.lv_sn = (const int32_t*)dev(lv_sn.data(), lv_sn.size() * 4, false);
+  fp.maxm = maxm.data();
+  fp.maxw = maxw.data();
+  fp.op_sn = (const int32_t*)dev(op_sn.data(), op_sn.size() * 4, false);
+  fp.op_row = (const int32_t*)dev(op_row.data(), op_row.size() * 4, false);
+  fp.op_off_total = (int32_t)op_sn.size();
+  int32_t failed = INT32_MAX;
+  if (ok && hipMemsetAsync(fd.L, 0, vals * 8, s) != hipSuccess) ok = false;
+  if (ok) {
+    dmc::launch_factor_numeric(s, fd, fp);
+    if (hipGetLastError() != hipSuccess) ok = false;
+  }
+  if (ok && hipMemcpyAsync(&failed, fd.fail, 4, hipMemcpyDeviceToHost, s) != hipSuccess) ok = false;
+  if (hipStreamSynchronize(s) != hipSuccess) ok = false;
+  for (void* p : tmp) (void)hipFree(p);
+  if (!ok) {
+    (void)hipGetLastError();
+    return fail(DMC_ERR_DEVICE, "device factorisation of the normal matrix failed");
+  }
+  if (failed != INT32_MAX)
+    return fail(DMC_ERR_SINGULAR, "normal matrix is not numerically positive definite (supernode " +
+                                      std::to_string(failed - 1) + ")");
+  m->dev.chol.brow = fd.B;
+  return DMC_OK;
+}
+
 dmc_status dmc_mesh_create(dmc_ctx ctx, int32_t n, int32_t n_tris, const int32_t* tris,
                            int32_t n_anchors, const int32_t* anchors, int32_t laplacian,
                            dmc_mesh* out) {
@@ -909,8 +1016,11 @@ dmc_status dmc_mesh_create(dmc_ctx ctx, int32_t n, int32_t n_tris, const int32_t
   dmc::HostCsr C, M;
   dmc::CholFactor F;
   double info[DMC_FACTOR_INFO_LEN];
-  dmc_status st = build_mesh_host(n, n_tris, tris, n_anchors, anchors, laplacian, C, M, F, info);
+  const auto t_setup = std::chrono::steady_clock::now();
+  dmc_status st =
+      build_mesh_host(n, n_tris, tris, n_anchors, anchors, laplacian, C, M, F, info, false);
   if (st != DMC_OK) return st;
+
   std::vector<double> w64(n), dinv(n, 0.0);
   std::vector<float> w32(n);
   std::vector<int32_t> slot(n, -1);
@@ -1014,8 +1124,6 @@ dmc_status dmc_mesh_create(dmc_ctx ctx, int32_t n, int32_t n_tris, const int32_t
   cd.sn_rowptr = (const int32_t*)up(F.sn_rowptr.data(), F.sn_rowptr.size() * 4);
   cd.rowidx = (const int32_t*)up(F.rowidx.data(), F.rowidx.size() * 4);
   cd.sn_valptr = (const int64_t*)up(F.sn_valptr.data(), F.sn_valptr.size() * 8);
-  cd.bcol = (const double*)up(F.bcol.data(), F.bcol.size() * 8);
-  cd.brow = (const double*)up(F.brow.data(), F.brow.size() * 8);
   cd.slot_base = (const int64_t*)up(F.slot_base.data(), F.slot_base.size() * 8);
   cd.contrib_ptr = (const int32_t*)up(F.contrib_ptr.data(), F.contrib_ptr.size() * 4);
   cd.contrib_slot = (const int32_t*)up(F.contrib_slot.data(), F.contrib_slot.size() * 4);
@@ -1029,13 +1137,21 @@ dmc_status dmc_mesh_create(dmc_ctx ctx, int32_t n, int32_t n_tris, const int32_t
   cd.level_w_host = m->level_w.data();
   cd.level_m_host = m->level_m.data();
   cd.level_maxw_host = m->level_maxw.data();
-  std::memcpy(m->factor_info, info, sizeof(info));
   if (!ok) {
     for (void* p : m->allocations) (void)hipFree(p);
     delete m;
     (void)hipGetLastError();
     return fail(DMC_ERR_OUT_OF_MEMORY, "cannot upload mesh");
   }
+  st = factor_on_device(ctx, m, F);
+  if (st != DMC_OK) {
+    (void)hipStreamSynchronize(ctx->stream);
+    for (void* p : m->allocations) (void)hipFree(p);
+    delete m;
+    return st;
+  }
+  info[5] = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_setup).count();
+  std::memcpy(m->factor_info, info, sizeof(info));
   st = build_anchor_response(ctx, m);
   if (st != DMC_OK) {
     (void)hipStreamSynchronize(ctx->stream);
@@ -1067,7 +1183,8 @@ dmc_status dmc_host_normal_solve(int32_t n, int32_t n_tris, const int32_t* tris,
   dmc::HostCsr C, M;
   dmc::CholFactor F;
   double inf[DMC_FACTOR_INFO_LEN];
-  dmc_status st = build_mesh_host(n, n_tris, tris, n_anchors, anchors, laplacian, C, M, F, inf);
+  dmc_status st =
+      build_mesh_host(n, n_tris, tris, n_anchors, anchors, laplacian, C, M, F, inf, true);
   if (st != DMC_OK) return st;
   dmc::chol_solve_host(F, ncols, B, X);
   if (info) std::memcpy(info, inf, sizeof(inf));
@@ -1475,6 +1592,36 @@ dmc_status dmc_autocorrelation(dmc_ctx ctx, dmc_mesh mesh, const void* frames, i
   dmc::launch_autocorr(ctx->stream, frames, mesh->dev.n, T, 1, precision, ctx->scratch,
                        (double*)R_out);
   return check_launch("autocorrelation");
+}
+
+dmc_status dmc_mesh_normal_solve(dmc_ctx ctx, dmc_mesh mesh, int32_t ncols, const double* B,
+                                 double* X) {
+  if (!ctx || !mesh || !B || !X) return fail(DMC_ERR_INVALID_ARG, "NULL argument");
+  if (ncols < 1) return fail(DMC_ERR_INVALID_ARG, "ncols must be >= 1");
+  if (B == X) return fail(DMC_ERR_INVALID_ARG, "B and X may not alias");
+  HIP_TRY(hipSetDevice(ctx->device));
+  const dmc::MeshDev& m = mesh->dev;
+  const size_t vec = (size_t)m.n * ncols * 8;
+  Carve cv;
+  const size_t o_b = cv.add(vec), o_z = cv.add(vec), o_w = cv.add(vec), o_y = cv.add(vec);
+  const size_t o_u = cv.add((size_t)m.chol.nslots * ncols * 8);
+  const size_t o_s = cv.add(dmc::chol_split_bytes(m.chol, ncols));
+  dmc_status st = ensure_scratch(ctx, cv.total());
+  if (st != DMC_OK) return st;
+  uint8_t* ws = (uint8_t*)ctx->scratch;
+  hipStream_t s = ctx->stream;
+  double* bp = (double*)(ws + o_b);
+  double* zp = (double*)(ws + o_z);
+  const size_t split = dmc::chol_split_bytes(m.chol, ncols);
+  // rows into the factor's order, the two supernodal solves, rows back
+  dmc::launch_permute_rows(s, B, m.chol.perm, m.n, ncols, bp);
+  dmc::launch_chol_solve(s, m.chol, ncols, bp, zp, (double*)(ws + o_w), (double*)(ws + o_y),
+                         (double*)(ws + o_u), split ? (double*)(ws + o_s) : nullptr);
+  dmc::launch_permute_rows(s, zp, m.dpos, m.n, ncols, X);
+  st = check_launch("normal solve");
+  if (st != DMC_OK) return st;
+  HIP_TRY(hipStreamSynchronize(s));
+  return DMC_OK;
 }
 
 }  // extern "C"

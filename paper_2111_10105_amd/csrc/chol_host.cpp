@@ -138,7 +138,7 @@ struct Segment {
 
 }  // namespace
 
-bool build_cholesky(const HostCsr& M, int32_t leaf, CholFactor& f, std::string& msg) {
+bool build_cholesky_symbolic(const HostCsr& M, int32_t leaf, CholFactor& f, std::string& msg) {
   const int32_t n = M.n;
   f = CholFactor();
   f.n = n;
@@ -153,7 +153,9 @@ bool build_cholesky(const HostCsr& M, int32_t leaf, CholFactor& f, std::string& 
             [](const NdNode& x, const NdNode& y) { return x.begin < y.begin; });
 
   // lower triangle of P M P^T: by column (rows >= j, with values) and by row
-  std::vector<int32_t> acol_ptr(n + 1, 0), arow_ptr(n + 1, 0);
+  std::vector<int32_t>& acol_ptr = f.acol_ptr;
+  acol_ptr.assign(n + 1, 0);
+  std::vector<int32_t> arow_ptr(n + 1, 0);
   for (int32_t u = 0; u < n; ++u)
     for (int32_t e = M.rowptr[u]; e < M.rowptr[u + 1]; ++e) {
       const int32_t i = iperm[u], j = iperm[M.col[e]];
@@ -166,8 +168,11 @@ bool build_cholesky(const HostCsr& M, int32_t leaf, CholFactor& f, std::string& 
     acol_ptr[j + 1] += acol_ptr[j];
     arow_ptr[j + 1] += arow_ptr[j];
   }
-  std::vector<int32_t> acol_row(acol_ptr[n]), arow_col(arow_ptr[n]);
-  std::vector<double> acol_val(acol_ptr[n]);
+  std::vector<int32_t>& acol_row = f.acol_row;
+  std::vector<double>& acol_val = f.acol_val;
+  acol_row.assign(acol_ptr[n], 0);
+  acol_val.assign(acol_ptr[n], 0.0);
+  std::vector<int32_t> arow_col(arow_ptr[n]);
   {
     std::vector<int32_t> cf(acol_ptr.begin(), acol_ptr.end() - 1), rf(arow_ptr.begin(), arow_ptr.end() - 1);
     for (int32_t u = 0; u < n; ++u)
@@ -298,8 +303,20 @@ bool build_cholesky(const HostCsr& M, int32_t leaf, CholFactor& f, std::string& 
     }
   }
 
-  // numeric factorisation, level by level (supernodes of one level are
-  // independent: their updates come from lower levels only)
+  // update segments by target, flattened (targets in order, segments in
+  // increasing source supernode)
+  f.seg_ptr.assign(ns + 1, 0);
+  for (int32_t t = 0; t < ns; ++t) f.seg_ptr[t + 1] = f.seg_ptr[t] + (int32_t)updates[t].size();
+  f.seg_d.resize(f.seg_ptr[ns]);
+  f.seg_p1.resize(f.seg_ptr[ns]);
+  f.seg_p2.resize(f.seg_ptr[ns]);
+  for (int32_t t = 0; t < ns; ++t)
+    for (size_t g = 0; g < updates[t].size(); ++g) {
+      f.seg_d[f.seg_ptr[t] + g] = updates[t][g].d;
+      f.seg_p1[f.seg_ptr[t] + g] = updates[t][g].p1;
+      f.seg_p2[f.seg_ptr[t] + g] = updates[t][g].p2;
+    }
+  // block offsets, update slots, and the flops of the numeric factorisation
   f.sn_valptr.assign(ns + 1, 0);
   f.sn_invptr.assign(ns + 1, 0);
   for (int32_t s = 0; s < ns; ++s) {
@@ -308,12 +325,45 @@ bool build_cholesky(const HostCsr& M, int32_t leaf, CholFactor& f, std::string& 
     f.sn_valptr[s + 1] = f.sn_valptr[s] + m * w;
     f.sn_invptr[s + 1] = f.sn_invptr[s] + w * w;
   }
+  f.slot_base.assign(ns + 1, 0);
+  for (int32_t s = 0; s < ns; ++s) {
+    const int64_t w = f.sn_start[s + 1] - f.sn_start[s];
+    const int64_t m = f.sn_rowptr[s + 1] - f.sn_rowptr[s];
+    f.slot_base[s + 1] = f.slot_base[s] + (m - w);
+  }
+  f.contrib_slot.resize(f.contrib_sn.size());
+  for (size_t e = 0; e < f.contrib_sn.size(); ++e) {
+    const int32_t d = f.contrib_sn[e];
+    const int32_t wd = f.sn_start[d + 1] - f.sn_start[d];
+    f.contrib_slot[e] = (int32_t)(f.slot_base[d] + f.contrib_pos[e] - wd);
+  }
+  double flops = 0.0;
+  for (int32_t t = 0; t < ns; ++t) {
+    for (int32_t g = f.seg_ptr[t]; g < f.seg_ptr[t + 1]; ++g) {
+      const int32_t d = f.seg_d[g];
+      const double wd = f.sn_start[d + 1] - f.sn_start[d];
+      const double md = f.sn_rowptr[d + 1] - f.sn_rowptr[d];
+      for (int32_t qi = f.seg_p1[g]; qi < f.seg_p2[g]; ++qi) flops += 2.0 * (md - qi) * wd;
+    }
+    const double w = f.sn_start[t + 1] - f.sn_start[t];
+    const double m = f.sn_rowptr[t + 1] - f.sn_rowptr[t];
+    flops += m * w * (w - 1) - 2.0 * w * (w - 1) * (2 * w - 1) / 6.0 + w * w * w / 3.0;
+  }
+  f.flops = flops;
+  return true;
+}
+
+bool factor_numeric_host(CholFactor& f, std::string& msg) {
+  const int32_t n = f.n, ns = f.nsuper;
+  const std::vector<int32_t>& acol_ptr = f.acol_ptr;
+  const std::vector<int32_t>& acol_row = f.acol_row;
+  const std::vector<double>& acol_val = f.acol_val;
   f.val.assign(f.sn_valptr[ns], 0.0);
   f.inv.assign(f.sn_invptr[ns], 0.0);
   std::vector<std::vector<int32_t>> by_level(f.nlevels);
   for (int32_t s = 0; s < ns; ++s) by_level[f.sn_level[s]].push_back(s);
   int failed = -1;
-  double flops = 0.0;
+  double flops = 0.0;  // counted as the loops run (f.flops holds the symbolic count)
   for (int32_t lv = 0; lv < f.nlevels && failed < 0; ++lv) {
     const std::vector<int32_t>& list = by_level[lv];
 #pragma omp parallel reduction(+ : flops)
@@ -330,7 +380,8 @@ bool build_cholesky(const HostCsr& M, int32_t leaf, CholFactor& f, std::string& 
         for (int32_t j = a; j < b; ++j)
           for (int32_t e = acol_ptr[j]; e < acol_ptr[j + 1]; ++e)
             Ls[(size_t)pos[acol_row[e]] * w + (j - a)] = acol_val[e];
-        for (const Segment& sg : updates[s]) {
+        for (int32_t g = f.seg_ptr[s]; g < f.seg_ptr[s + 1]; ++g) {
+          const Segment sg{f.seg_d[g], f.seg_p1[g], f.seg_p2[g]};
           const int32_t d = sg.d;
           const int32_t wd = f.sn_start[d + 1] - f.sn_start[d];
           const int32_t rd0 = f.sn_rowptr[d], md = f.sn_rowptr[d + 1] - rd0;
@@ -393,7 +444,7 @@ bool build_cholesky(const HostCsr& M, int32_t leaf, CholFactor& f, std::string& 
       }
     }
   }
-  f.flops = flops;
+  (void)flops;
   if (failed >= 0) {
     msg = "normal matrix is not numerically positive definite (supernode " +
           std::to_string(failed) + ")";
@@ -402,12 +453,6 @@ bool build_cholesky(const HostCsr& M, int32_t leaf, CholFactor& f, std::string& 
   // solve operators B_s = [inv(L_ss); L_os inv(L_ss)] and update slots
   f.bcol.assign(f.sn_valptr[ns], 0.0);
   f.brow.assign(f.sn_valptr[ns], 0.0);
-  f.slot_base.assign(ns + 1, 0);
-  for (int32_t s = 0; s < ns; ++s) {
-    const int64_t w = f.sn_start[s + 1] - f.sn_start[s];
-    const int64_t m = f.sn_rowptr[s + 1] - f.sn_rowptr[s];
-    f.slot_base[s + 1] = f.slot_base[s] + (m - w);
-  }
 #pragma omp parallel for schedule(dynamic, 1)
   for (int32_t s = 0; s < ns; ++s) {
     const int32_t w = f.sn_start[s + 1] - f.sn_start[s];
@@ -430,13 +475,11 @@ bool build_cholesky(const HostCsr& M, int32_t leaf, CholFactor& f, std::string& 
     for (int32_t i = 0; i < m; ++i)
       for (int32_t q = 0; q < w; ++q) Bc[(size_t)q * m + i] = Br[(size_t)i * w + q];
   }
-  f.contrib_slot.resize(f.contrib_sn.size());
-  for (size_t e = 0; e < f.contrib_sn.size(); ++e) {
-    const int32_t d = f.contrib_sn[e];
-    const int32_t wd = f.sn_start[d + 1] - f.sn_start[d];
-    f.contrib_slot[e] = (int32_t)(f.slot_base[d] + f.contrib_pos[e] - wd);
-  }
   return true;
+}
+
+bool build_cholesky(const HostCsr& M, int32_t leaf, CholFactor& f, std::string& msg) {
+  return build_cholesky_symbolic(M, leaf, f, msg) && factor_numeric_host(f, msg);
 }
 
 void chol_solve_host(const CholFactor& f, int32_t ncols, const double* r, double* z) {

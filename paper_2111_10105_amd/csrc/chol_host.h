@@ -39,8 +39,16 @@ struct CholFactor {
   std::vector<int32_t> contrib_ptr;  // [n+1]
   std::vector<int32_t> contrib_sn;
   std::vector<int32_t> contrib_pos;
+  // lower triangle of P M P^T by column (rows >= the column, with values):
+  // the entries the numeric factorisation starts from
+  std::vector<int32_t> acol_ptr, acol_row;
+  std::vector<double> acol_val;
+  // updates of each target supernode t: segments seg_ptr[t] .. seg_ptr[t+1]-1,
+  // each the rows [p1, p2) of a descendant d whose row indices are columns of t
+  // (so rows p1 .. m_d - 1 of d update t), in increasing d
+  std::vector<int32_t> seg_ptr, seg_d, seg_p1, seg_p2;
   int64_t nnz_exact = 0;             // nonzeros of the exact factor
-  double flops = 0.0;                // numeric factorisation flops
+  double flops = 0.0;                // numeric factorisation flops (updates, Cholesky, inverses)
 };
 
 // Nested-dissection ordering (recursive bisection by breadth-first level
@@ -49,6 +57,13 @@ struct CholFactor {
 // dissection node.  Returns false with a message if M is not numerically
 // positive definite.
 bool build_cholesky(const HostCsr& M, int32_t leaf, CholFactor& f, std::string& msg);
+
+// The ordering and symbolic part alone (everything but val, inv, bcol and
+// brow): what the device factorisation starts from.
+bool build_cholesky_symbolic(const HostCsr& M, int32_t leaf, CholFactor& f, std::string& msg);
+
+// The numeric part on the host (val, inv, bcol, brow) after the symbolic one.
+bool factor_numeric_host(CholFactor& f, std::string& msg);
 
 // z = (L L^T)^{-1} r on the host, by the same blocked algorithm as the device
 // solve (gather of updates, multiplication by the inverse diagonal blocks).

@@ -90,7 +90,6 @@ struct CholDev {
   const int32_t* sn_rowptr = nullptr;   // [ns+1]
   const int32_t* rowidx = nullptr;
   const int64_t* sn_valptr = nullptr;   // offsets of B_s (m_s x w_s)
-  const double* bcol = nullptr;         // B_s column-major
   const double* brow = nullptr;         // B_s row-major
   const int64_t* slot_base = nullptr;   // [ns+1] update slots of each supernode
   const int32_t* contrib_ptr = nullptr; // [n+1] per column: update slots aimed at it
@@ -106,6 +105,51 @@ struct CholDev {
   const int32_t* level_maxw_host = nullptr;  // host [nlevels]: widest supernode of a level
   int64_t nslots = 0;
 };
+
+// Symbolic structure of the factor on the device, for the numeric
+// factorisation at mesh creation (kernels_factor.hip): supernode blocks L_s
+// (m_s x w_s row-major at sn_valptr[s]), their row indices, the supernode of
+// every column, the lower triangle of P M P^T by column, and each target's
+// update segments (chol_host.h).
+struct FactorDev {
+  int32_t n = 0;
+  const int32_t* sn_start = nullptr;
+  const int32_t* sn_rowptr = nullptr;
+  const int32_t* rowidx = nullptr;
+  const int32_t* sn_of = nullptr;
+  const int64_t* sn_valptr = nullptr;
+  const int32_t* acol_ptr = nullptr;
+  const int32_t* acol_row = nullptr;
+  const double* acol_val = nullptr;
+  const int32_t* seg_ptr = nullptr;
+  const int32_t* seg_d = nullptr;
+  const int32_t* seg_p1 = nullptr;
+  const int32_t* seg_p2 = nullptr;
+  double* L = nullptr;     // the factor's blocks (work, zeroed before the launch)
+  double* B = nullptr;     // the solve operators B_s, row-major (output)
+  int32_t* fail = nullptr; // smallest supernode with a non-positive pivot + 1 (init INT_MAX)
+};
+// Work lists of the numeric factorisation, by level (offsets on the host,
+// lists on the device): update tiles (target, row tile << 16 | column tile),
+// the level's supernodes and their largest block, operator tasks (supernode,
+// first of 64 rows) for all supernodes.
+struct FactorPlan {
+  int32_t nlevels = 0;
+  const int32_t* tile_off = nullptr;  // host [nlevels + 1]
+  const int32_t* tile_sn = nullptr;   // device
+  const int32_t* tile_rc = nullptr;   // device
+  const int32_t* sn_off = nullptr;    // host [nlevels + 1]
+  const int32_t* lv_sn = nullptr;     // device
+  const int32_t* maxm = nullptr;      // host [nlevels]: tallest block of the level
+  const int32_t* maxw = nullptr;      // host [nlevels]: widest block of the level
+  const int32_t* op_sn = nullptr;     // device
+  const int32_t* op_row = nullptr;    // device
+  int32_t op_off_total = 0;
+};
+void launch_factor_numeric(hipStream_t s, const FactorDev& f, const FactorPlan& p);
+// out[r] = in[map[r]] for n rows of ncols doubles
+void launch_permute_rows(hipStream_t s, const double* in, const int32_t* map, int32_t n,
+                         int32_t ncols, double* out);
 
 // Device-side mesh data.
 struct MeshDev {

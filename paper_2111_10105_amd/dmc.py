@@ -30,6 +30,7 @@ EXPORTS = ["dmc_create", "dmc_destroy", "dmc_set_stream", "dmc_last_error", "dmc
            "dmc_workspace_bytes", "dmc_set_workspace",
            "dmc_mesh_create", "dmc_mesh_destroy", "dmc_mesh_nnz", "dmc_mesh_normal_nnz",
            "dmc_mesh_factor_info", "dmc_mesh_anchor_response", "dmc_host_normal_solve",
+           "dmc_mesh_normal_solve",
            "dmc_window_code_bytes", "dmc_sequence_code_bytes", "dmc_encode_window",
            "dmc_encode_window_noalloc",
            "dmc_decode_window", "dmc_compress_sequence", "dmc_decode_sequence", "dmc_delta",
@@ -131,6 +132,7 @@ def lib():
         "dmc_compress_sequence": (i32, [vp, vp, vp, i32, i32, P, vp, vp, sz, vp, S]),
         "dmc_decode_sequence": (i32, [vp, vp, vp, i32, i32, P, vp, S]),
         "dmc_delta": (i32, [vp, vp, vp, i32, i32, vp]),
+        "dmc_mesh_normal_solve": (i32, [vp, vp, i32, vp, vp]),
         "dmc_autocorrelation": (i32, [vp, vp, vp, i32, i32, vp]),
         "dmc_profile_start": (i32, [i32]),
         "dmc_profile_stop": (i32, [ctypes.POINTER(i32), ctypes.POINTER(dbl)]),
@@ -374,6 +376,18 @@ def decode_sequence(ctx: Context, mesh: Mesh, codes, F: int, T: int, params: Par
                                        _ptr(out), sts)
     _check(status, allow=(4,))
     return out, [s.as_dict() for s in sts], status
+
+
+def normal_solve(ctx: Context, mesh: Mesh, B):
+    """X with (L^T L + I_N^T I_N) X = B by the mesh's device Cholesky factor
+    (dmc_mesh_normal_solve); B float64 [n][ncols] on the device."""
+    import torch
+    assert B.dtype == torch.float64 and B.dim() == 2 and B.shape[0] == mesh.n
+    B = B.contiguous()
+    ctx.sync_stream()
+    X = torch.empty_like(B)
+    _check(lib().dmc_mesh_normal_solve(ctx.h, mesh.h, int(B.shape[1]), _ptr(B), _ptr(X)))
+    return X
 
 
 def delta(ctx: Context, mesh: Mesh, frames, precision: int):
