@@ -688,7 +688,7 @@ dmc_status build_mesh_host(int32_t n, int32_t n_tris, const int32_t* tris, int32
                                       "anchored system is singular");
   dmc::build_normal_matrix(C, laplacian, anchors, n_anchors, M);
   const auto t0 = std::chrono::steady_clock::now();
-  if (!dmc::build_cholesky_symbolic(M, kNdLeaf, F, msg)) return fail(DMC_ERR_SINGULAR, msg);
+  if (!dmc::build_cholesky_symbolic(M, kNdLeaf, F, msg, &C)) return fail(DMC_ERR_SINGULAR, msg);
   if (numeric && !dmc::factor_numeric_host(F, msg)) return fail(DMC_ERR_SINGULAR, msg);
   const double secs =
       std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

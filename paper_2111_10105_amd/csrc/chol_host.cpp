@@ -16,13 +16,17 @@ struct NdNode {
   int32_t begin = -1, end = -1, parent = -1;
 };
 
-// Recursive bisection of the graph of M by breadth-first level sets: the
-// level that splits the vertices in half (counted from a pseudo-peripheral
-// vertex) is the separator; it is numbered after both halves.
+// Recursive bisection of a graph by breadth-first level sets: the `thick`
+// consecutive levels around the one that splits the vertices in half
+// (counted from a pseudo-peripheral vertex) are the separator; it is
+// numbered after both halves.  On the graph of M itself one level separates;
+// on the mesh adjacency C, whose square is M's pattern, two do (vertices
+// three or more levels apart are not coupled in M).
 class Dissector {
  public:
-  Dissector(const HostCsr& G, int32_t leaf)
-      : G_(G), leaf_(std::max(leaf, 2)), tag_(G.n, 0), seen_(G.n, 0), lev_(G.n, 0) {}
+  Dissector(const HostCsr& G, int32_t leaf, int32_t thick)
+      : G_(G), leaf_(std::max(leaf, 2)), thick_(thick), tag_(G.n, 0), seen_(G.n, 0),
+        lev_(G.n, 0) {}
 
   void run(std::vector<int32_t>& order, std::vector<NdNode>& nodes) {
     std::vector<int32_t> all(G_.n);
@@ -91,7 +95,7 @@ class Dissector {
     }
     bfs(u, member, vis);
     const int32_t maxl = lev_[vis.back()];
-    if (maxl < 2) {
+    if (maxl < thick_ + 1) {
       make_leaf(S, parent);
       return;
     }
@@ -103,12 +107,12 @@ class Dissector {
       acc += cnt[l];
       if (acc >= half) break;
     }
-    l = std::min(std::max(l, 1), maxl - 1);
+    l = std::min(std::max(l, 1), maxl - thick_);
     std::vector<int32_t> A, B, Sep;
     for (int32_t v : vis) {
       if (lev_[v] < l)
         A.push_back(v);
-      else if (lev_[v] > l)
+      else if (lev_[v] >= l + thick_)
         B.push_back(v);
       else
         Sep.push_back(v);
@@ -125,7 +129,7 @@ class Dissector {
   }
 
   const HostCsr& G_;
-  int32_t leaf_;
+  int32_t leaf_, thick_;
   std::vector<int32_t> tag_, seen_, lev_;
   int32_t stamp_ = 0, bfs_id_ = 0;
   std::vector<int32_t> order_;
@@ -138,13 +142,14 @@ struct Segment {
 
 }  // namespace
 
-bool build_cholesky_symbolic(const HostCsr& M, int32_t leaf, CholFactor& f, std::string& msg) {
+bool build_cholesky_symbolic(const HostCsr& M, int32_t leaf, CholFactor& f, std::string& msg,
+                             const HostCsr* adjacency) {
   const int32_t n = M.n;
   f = CholFactor();
   f.n = n;
   std::vector<NdNode> nodes;
   {
-    Dissector dis(M, leaf);
+    Dissector dis(adjacency ? *adjacency : M, leaf, adjacency ? 2 : 1);
     dis.run(f.perm, nodes);
   }
   std::vector<int32_t> iperm(n);
@@ -201,33 +206,24 @@ bool build_cholesky_symbolic(const HostCsr& M, int32_t leaf, CholFactor& f, std:
         parent[r] = i;
       }
     }
-  // column structures of L below the diagonal, by row subtrees
-  std::vector<int32_t> lptr(n + 1, 0), mark(n, -1);
+  // nonzeros of the exact factor: column counts by row subtrees (each row i
+  // of L is the union of the etree paths from the columns of row i of A)
+  std::vector<int32_t> mark(n, -1);
+  int64_t below = 0;
   for (int32_t i = 0; i < n; ++i) {
     mark[i] = i;
     for (int32_t e = arow_ptr[i]; e < arow_ptr[i + 1]; ++e)
       for (int32_t r = arow_col[e]; mark[r] != i; r = parent[r]) {
-        lptr[r + 1]++;
+        ++below;
         mark[r] = i;
       }
   }
-  for (int32_t j = 0; j < n; ++j) lptr[j + 1] += lptr[j];
-  std::vector<int32_t> lrow(lptr[n]);
-  {
-    std::vector<int32_t> fill(lptr.begin(), lptr.end() - 1);
-    std::fill(mark.begin(), mark.end(), -1);
-    for (int32_t i = 0; i < n; ++i) {
-      mark[i] = i;
-      for (int32_t e = arow_ptr[i]; e < arow_ptr[i + 1]; ++e)
-        for (int32_t r = arow_col[e]; mark[r] != i; r = parent[r]) {
-          lrow[fill[r]++] = i;
-          mark[r] = i;
-        }
-    }
-  }
-  f.nnz_exact = (int64_t)n + lptr[n];
+  f.nnz_exact = (int64_t)n + below;
 
-  // supernodes = dissection nodes; their row structures
+  // supernodes = dissection nodes; their row structures, bottom up: the rows
+  // of s below its columns are those of A in its columns and those of its
+  // children in the supernodal tree below their own columns (the structure of
+  // a supernode is the union of its columns' structures in L)
   const int32_t ns = (int32_t)nodes.size();
   f.nsuper = ns;
   f.sn_start.resize(ns + 1);
@@ -238,25 +234,35 @@ bool build_cholesky_symbolic(const HostCsr& M, int32_t leaf, CholFactor& f, std:
     for (int32_t j = f.sn_start[s]; j < f.sn_start[s + 1]; ++j) sn_of[j] = s;
   f.sn_rowptr.assign(ns + 1, 0);
   std::fill(mark.begin(), mark.end(), -1);
+  std::vector<std::vector<int32_t>> kids(ns);
   std::vector<int32_t> extra;
   for (int32_t s = 0; s < ns; ++s) {
     const int32_t a = f.sn_start[s], b = f.sn_start[s + 1];
     extra.clear();
     for (int32_t j = a; j < b; ++j)
-      for (int32_t e = lptr[j]; e < lptr[j + 1]; ++e) {
-        const int32_t r = lrow[e];
+      for (int32_t e = acol_ptr[j]; e < acol_ptr[j + 1]; ++e) {
+        const int32_t r = acol_row[e];
         if (r >= b && mark[r] != s) {
           mark[r] = s;
           extra.push_back(r);
         }
       }
+    for (int32_t c : kids[s]) {
+      const int32_t wc = f.sn_start[c + 1] - f.sn_start[c];
+      for (int32_t t = f.sn_rowptr[c] + wc; t < f.sn_rowptr[c + 1]; ++t) {
+        const int32_t r = f.rowidx[t];
+        if (r >= b && mark[r] != s) {
+          mark[r] = s;
+          extra.push_back(r);
+        }
+      }
+    }
     std::sort(extra.begin(), extra.end());
     for (int32_t j = a; j < b; ++j) f.rowidx.push_back(j);
     f.rowidx.insert(f.rowidx.end(), extra.begin(), extra.end());
     f.sn_rowptr[s + 1] = (int32_t)f.rowidx.size();
+    if (!extra.empty()) kids[sn_of[extra[0]]].push_back(s);
   }
-  lrow.clear();
-  lrow.shrink_to_fit();
   // supernodal tree and levels
   f.sn_parent.assign(ns, -1);
   f.sn_level.assign(ns, 0);
@@ -478,8 +484,9 @@ bool factor_numeric_host(CholFactor& f, std::string& msg) {
   return true;
 }
 
-bool build_cholesky(const HostCsr& M, int32_t leaf, CholFactor& f, std::string& msg) {
-  return build_cholesky_symbolic(M, leaf, f, msg) && factor_numeric_host(f, msg);
+bool build_cholesky(const HostCsr& M, int32_t leaf, CholFactor& f, std::string& msg,
+                    const HostCsr* adjacency) {
+  return build_cholesky_symbolic(M, leaf, f, msg, adjacency) && factor_numeric_host(f, msg);
 }
 
 void chol_solve_host(const CholFactor& f, int32_t ncols, const double* r, double* z) {

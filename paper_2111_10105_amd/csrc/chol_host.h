@@ -56,11 +56,16 @@ struct CholFactor {
 // followed by symbolic and numeric supernodal factorisation, one supernode per
 // dissection node.  Returns false with a message if M is not numerically
 // positive definite.
-bool build_cholesky(const HostCsr& M, int32_t leaf, CholFactor& f, std::string& msg);
+// With `adjacency` (the mesh's C, whose square has M's pattern) the
+// dissection runs on C with two-level separators (a third of the edges to
+// visit); the factor is of M either way.
+bool build_cholesky(const HostCsr& M, int32_t leaf, CholFactor& f, std::string& msg,
+                    const HostCsr* adjacency = nullptr);
 
 // The ordering and symbolic part alone (everything but val, inv, bcol and
 // brow): what the device factorisation starts from.
-bool build_cholesky_symbolic(const HostCsr& M, int32_t leaf, CholFactor& f, std::string& msg);
+bool build_cholesky_symbolic(const HostCsr& M, int32_t leaf, CholFactor& f, std::string& msg,
+                             const HostCsr* adjacency = nullptr);
 
 // The numeric part on the host (val, inv, bcol, brow) after the symbolic one.
 bool factor_numeric_host(CholFactor& f, std::string& msg);

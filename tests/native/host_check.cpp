@@ -2,7 +2,8 @@
 // chol_host.cpp) for a build with the address and undefined-behaviour
 // sanitizers: it reads one mesh, builds the adjacency of Eq. (2), checks the
 // anchored components, forms the normal matrix of Eq. (12), factorises it
-// with the given leaf size and solves three right-hand sides on the host,
+// (dissection on the mesh graph, as the library does) with the given leaf
+// size and solves three right-hand sides on the host,
 // then prints the relative residual.
 // Input file: int32 n, n_tris, n_anchors, laplacian, leaf, then the
 // triangles [3 n_tris] and the anchors [n_anchors].
@@ -47,7 +48,7 @@ int main(int argc, char** argv) {
   }
   dmc::build_normal_matrix(C, lap, anchors.data(), nc, M);
   dmc::CholFactor F;
-  if (!dmc::build_cholesky(M, leaf, F, msg)) {
+  if (!dmc::build_cholesky(M, leaf, F, msg, &C)) {
     std::printf("not factorised: %s\n", msg.c_str());
     return 4;
   }
