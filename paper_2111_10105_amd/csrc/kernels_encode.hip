@@ -197,19 +197,30 @@ k_autocorr(const In* __restrict__ frames, int n, int T, int nw, int P, Real* __r
   }
 }
 
+// R entry e = sum over the P partials: block = 64 consecutive entries (lane
+// = entry, so every load is coalesced), wave g adding the partials p = g,
+// g + 4, ... in order, the four wave sums added as (s0 + s1) + (s2 + s3)
+// (deterministic; four times the parallelism of one thread per entry).
 template <typename Real, int TP>
-__global__ void k_autocorr_reduce(const Real* __restrict__ part, int T, int nw, int P,
-                                  double* __restrict__ R) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(kBlock)
+k_autocorr_reduce(const Real* __restrict__ part, int T, int nw, int P, double* __restrict__ R) {
+  constexpr int NW = kBlock / 64;
+  __shared__ double sh[NW][64];
+  const int lane = threadIdx.x % 64, g = threadIdx.x / 64;
+  const int e = blockIdx.x * 64 + lane;
   const int per_w = 3 * T * T;
-  if (e >= nw * per_w) return;
-  const int w = e / per_w, rem = e % per_w;
-  const int c = rem / (T * T), ij = rem % (T * T);
-  const int i = ij / T, j = ij % T;
   double s = 0.0;
-  for (int p = 0; p < P; ++p)
-    s += (double)part[(((size_t)w * P + p) * 3 + c) * TP * TP + i * TP + j];
-  R[e] = s;
+  if (e < nw * per_w) {
+    const int w = e / per_w, rem = e % per_w;
+    const int c = rem / (T * T), ij = rem % (T * T);
+    const int i = ij / T, j = ij % T;
+    const Real* pe = part + (((size_t)w * P) * 3 + c) * TP * TP + i * TP + j;
+    const size_t stride = (size_t)3 * TP * TP;
+    for (int p = g; p < P; p += NW) s += (double)pe[(size_t)p * stride];
+  }
+  sh[g][lane] = s;
+  __syncthreads();
+  if (g == 0 && e < nw * per_w) R[e] = (sh[0][lane] + sh[1][lane]) + (sh[2][lane] + sh[3][lane]);
 }
 
 // Precision form: bfloat16 operands, float32 accumulation
@@ -831,7 +842,7 @@ static void autocorr_bf16(hipStream_t s, const float* frames, int32_t n, int32_t
                           float* part, double* R, int P) {
   dim3 grid(P, nw);
   const int tot = nw * 3 * T * T;
-  dim3 rgrid((tot + kBlock - 1) / kBlock);
+  dim3 rgrid((tot + 63) / 64);
   prof::begin(s, DMC_KERNEL_AUTOCORR);
   if (T <= 32)
     hipLaunchKernelGGL((k_autocorr_bf16<32>), grid, dim3(AC_WAVES * 64), 0, s, frames, n, T, nw, P,
@@ -853,7 +864,7 @@ static void autocorr_impl(hipStream_t s, const In* frames, int32_t n, int32_t T,
                           double* part, double* R, int P) {
   dim3 grid(P, nw);
   const int tot = nw * 3 * T * T;
-  dim3 rgrid((tot + kBlock - 1) / kBlock);
+  dim3 rgrid((tot + 63) / 64);
   prof::begin(s, DMC_KERNEL_AUTOCORR);
   if (T <= 32)
     hipLaunchKernelGGL((k_autocorr<In, double, 32>), grid, dim3(AC_WAVES * 64), 0, s, frames, n,
