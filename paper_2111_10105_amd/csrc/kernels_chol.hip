@@ -17,7 +17,8 @@
 // each tile into four blocks of 16 rows; the backward GEMM splits its K range
 // over several blocks on levels with few tiles, and a second kernel adds the
 // partial sums in a fixed order).  The two GEMMs
-// stage 32-deep K slices of B_s and of the right-hand rows in LDS and run on
+// stage shallow K slices (16 deep forward, 4 backward) of B_s and of the
+// right-hand rows in LDS and run on
 // the FP64 matrix cores; the gather is one load per update row.
 #include "dmc_internal.h"
 
@@ -81,17 +82,25 @@ constexpr int RIDX = 2048;   // ancestor row indices cached per block
 // halves the LDS of a block, so twice the blocks share a CU and cover each
 // other's load latency.
 constexpr int kStages = 1;
+// K chunk depth of the forward and backward GEMMs (the backward one at least
+// kBlock / RT, one element per thread)
+constexpr int kKcFwd = 16;
+constexpr int kKcBwd = 4;
+constexpr int bwd_kc(int rt) { return rt * kKcBwd >= kBlock ? kKcBwd : kBlock / rt; }
 
 // One RT x RT output tile per block on the FP64 matrix cores (RT = 64 or 32):
 // wave v owns the quadrant (v / 2, v % 2) as NQ x NQ tiles of
 // v_mfma_f64_16x16x4f64 (NQ = RT / 32; lane l supplies A[l%16][l/16] and
 // B[l/16][l%16]; component r of lane l is D[4r + l/16][l%16]).  The 32 x 32
 // tiles serve forward levels with few tasks: four times the blocks, a quarter
-// of the matrix-core work on each block's critical path.  K chunks are 32 deep.
-template <int RT>
+// of the matrix-core work on each block's critical path.  K chunks are KC_
+// deep: shallow chunks keep a block's LDS small (more blocks per CU to cover
+// each other's loads) and pad the short K ranges of the leaves less.
+template <int RT, int KC_>
 struct MfmaTile {
   static constexpr int NQ = RT / 32, LDB = RT + 1;
-  static constexpr int KC = 32, LDA = KC + 1;
+  static constexpr int KC = KC_, LDA = KC + 1;
+  static_assert(KC % 4 == 0 && RT * KC % kBlock == 0, "a chunk is whole MFMA steps, whole per thread");
   d4 acc[NQ][NQ];
   __device__ void zero() {
 #pragma unroll
@@ -138,8 +147,9 @@ template <int RT>
 __global__ void __launch_bounds__(kBlock)
 k_fwd_gemm(CholDev f, int t0, int ncols, int cbp, int ntile, const double* __restrict__ W,
            double* __restrict__ Y, double* __restrict__ U) {
-  constexpr int CT = RT, LDB = MfmaTile<RT>::LDB;
-  constexpr int KC = MfmaTile<RT>::KC, LDA = MfmaTile<RT>::LDA;
+  using Tile = MfmaTile<RT, kKcFwd>;
+  constexpr int CT = RT, LDB = Tile::LDB;
+  constexpr int KC = Tile::KC, LDA = Tile::LDA;
   constexpr int PER_T = RT * KC / kBlock;  // elements of a chunk staged per thread
   __shared__ double As[kStages][RT * LDA];
   __shared__ double Bs[kStages][KC * LDB];
@@ -177,7 +187,7 @@ k_fwd_gemm(CholDev f, int t0, int ncols, int cbp, int ntile, const double* __res
       Bs[st][(e / CT) * LDB + e % CT] = rb[u];
     }
   };
-  MfmaTile<RT> t;
+  Tile t;
   t.zero();
   int st = 0;
   if (qend > 0) {
@@ -196,7 +206,7 @@ k_fwd_gemm(CholDev f, int t0, int ncols, int cbp, int ntile, const double* __res
     __syncthreads();
     if (kStages == 2) st ^= 1;
   }
-  constexpr int NQ = MfmaTile<RT>::NQ;
+  constexpr int NQ = Tile::NQ;
   const int64_t sb = f.slot_base[s];
 #pragma unroll
   for (int ta = 0; ta < NQ; ++ta)
@@ -224,8 +234,9 @@ template <int RT>
 __global__ void __launch_bounds__(kBlock)
 k_bwd_gemm(CholDev f, int t0, int ncols, int cbp, int ntile, const double* __restrict__ Y,
            double* __restrict__ X, int nsplit, double* __restrict__ part) {
-  constexpr int CT = RT, LDB = MfmaTile<RT>::LDB;
-  constexpr int KC = MfmaTile<RT>::KC, LDA = MfmaTile<RT>::LDA;
+  using Tile = MfmaTile<RT, bwd_kc(RT)>;
+  constexpr int CT = RT, LDB = Tile::LDB;
+  constexpr int KC = Tile::KC, LDA = Tile::LDA;
   constexpr int PER_T = RT * KC / kBlock;
   __shared__ double As[kStages][RT * LDA];
   __shared__ double Bs[kStages][KC * LDB];
@@ -278,7 +289,7 @@ k_bwd_gemm(CholDev f, int t0, int ncols, int cbp, int ntile, const double* __res
       Bs[st][(e / CT) * LDB + e % CT] = rb[u];
     }
   };
-  MfmaTile<RT> t;
+  Tile t;
   t.zero();
   for (int i = kb + threadIdx.x; i < min(ke, kb + RIDX); i += kBlock) rows[i - kb] = f.rowidx[rb0 + i];
   __syncthreads();
@@ -299,7 +310,7 @@ k_bwd_gemm(CholDev f, int t0, int ncols, int cbp, int ntile, const double* __res
     __syncthreads();
     if (kStages == 2) st ^= 1;
   }
-  constexpr int NQ = MfmaTile<RT>::NQ;
+  constexpr int NQ = Tile::NQ;
 #pragma unroll
   for (int ta = 0; ta < NQ; ++ta)
 #pragma unroll
