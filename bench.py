@@ -75,10 +75,12 @@ def parse():
                     help="kernel family timed live (default: the dominant one)")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="MB")
     ap.add_argument("--workload", default="icosphere7",
-                    choices=["torus", "icosphere7", "batched", "rd"],
+                    choices=["torus", "icosphere7", "batched", "rd", "learned"],
                     help="icosphere7: the headline workload (level 7, 512 frames); torus: the "
                          "128 x 128 torus alone; batched: 64 sequences in one graph; rd: the "
-                         "rate-distortion sweep over k")
+                         "rate-distortion sweep over k; learned: the learned start trained on "
+                         "2,000 windows of 8-16-bone animations of 10k-160k-vertex meshes and "
+                         "compared with the plain starts on held-out seeds")
     ap.add_argument("--no-second-workload", action="store_true",
                     help="skip the torus workload that runs beside the headline")
     ap.add_argument("--headline-only", action="store_true",
@@ -261,6 +263,126 @@ def bench_batched(args):
     ctx.close()
 
 
+def bench_learned(args):
+    """The learned start at its training configuration: 2,000 windows of 64
+    frames of seeded 8-16-bone RBF animations of six meshes of 10k-160k
+    vertices (250 animations of 512 frames, skinned on the GPU), covariances
+    by the library, targets the exact eigenvectors (k = 32); trained on the
+    GPU; then on held-out seeds, sweeps of Algorithm 1 to its tolerance from
+    the learned start, a seeded Gaussian block and the previous window's
+    subspace, over all blocks and over those whose numerical rank exceeds k."""
+    import numpy as np
+    import torch
+    from paper_2111_10105_amd import dmc
+    from paper_2111_10105_amd import learned as L
+    from synth import animate, learned, meshes
+    T, k, nwin = 64, 32, 8
+    t_all = time.perf_counter()
+    ctx = dmc.Context(0)
+    dev = torch.device("cuda:0")
+    shapes = [("icosphere5", meshes.icosphere(5)), ("torus160x128", meshes.torus(160, 128)),
+              ("icosphere6", meshes.icosphere(6)), ("torus256x256", meshes.torus(256, 256)),
+              ("torus400x250", meshes.torus(400, 250)), ("icosphere7", meshes.icosphere(7))]
+    mlist = []
+    for name, (v, t) in shapes:
+        n = v.shape[0]
+        mlist.append((name, v, dmc.Mesh(ctx, n, t, animate.choose_anchors(n, 8, seed=1))))
+
+    def windows(seeds):
+        """[nb][T][T] covariances (coordinate blocks of each window in order),
+        numerical ranks, and (animation, window, coordinate) of each block."""
+        R, meta = [], []
+        for a, seed in enumerate(seeds):
+            name, v, mesh = mlist[a % len(mlist)]
+            bones = 8 + seed % 9
+            fr = animate.rbf_skinning_torch(v, T * nwin, bones, seed, dev)
+            for w in range(nwin):
+                Rw = dmc.autocorrelation(ctx, mesh, fr[w * T:(w + 1) * T].contiguous(), dmc.FP32)
+                R.append(Rw.cpu().numpy())
+                meta += [(a, w, c, bones, name) for c in range(3)]
+            del fr
+        R = np.concatenate(R)
+        ev = np.linalg.eigvalsh(R)
+        rank = (ev > 1e-13 * ev[:, -1:]).sum(axis=1)
+        return R, rank, meta
+
+    t0 = time.perf_counter()
+    R_train, rank_train, _ = windows(list(range(20000, 20250)))
+    gen_s = time.perf_counter() - t0
+    omega = learned.sketch_omega(T, 7001)
+    R_test, rank_test, meta = windows(list(range(90000, 90024)))
+    nb = R_test.shape[0]
+
+    def summ(x, mask=None):
+        x = np.asarray(x, dtype=np.float64)
+        if mask is not None:
+            x = x[mask]
+        if x.size == 0:
+            return None
+        return {"mean": round(float(x.mean()), 3), "median": float(np.median(x)),
+                "max": float(x.max()), "blocks": int(x.size)}
+
+    def train_and_compare(k):
+        t0 = time.perf_counter()
+        perm = np.random.default_rng(0).permutation(R_train.shape[0])
+        data = L.Dataset(ctx, R_train[perm], omega, k)
+        steps = max(200, 15 * args.steps * 10)
+        theta, hist = L.train(ctx, data, learned.mlp_init(k, 7002), steps=steps, batch=64,
+                              lr=2e-3)
+        train_s = time.perf_counter() - t0
+        gauss = animate.gaussian_subspace(T, k, 7003)
+        starts = np.stack([gauss[i % 3] for i in range(nb)])
+        ev = L.evaluate(ctx, R_test, theta, omega, k, random_starts=starts, oi_tol=1e-12,
+                        max_sweeps=200)
+        # previous window's subspace (same animation and coordinate); window 0
+        # of an animation has none and is left out of that column
+        exact = dmc.make_params(k, precision=dmc.FP64, init=dmc.INIT_EXACT)
+        U, _, _ = dmc.oi_blocks(ctx, torch.from_numpy(R_test).to(dev), exact)
+        Uh = U.cpu().numpy()
+        prev_idx = [i for i in range(nb) if meta[i][1] > 0]
+        prev_start = np.stack([Uh[i - 3] for i in prev_idx])
+        pr = dmc.make_params(k, precision=dmc.FP64, init=dmc.INIT_RANDOM, oi_tol=1e-12,
+                             oi_max_sweeps=200)
+        _, sw_prev, res_prev = dmc.oi_blocks(ctx, torch.from_numpy(R_test[prev_idx]).to(dev), pr,
+                                             q_start=torch.from_numpy(prev_start).to(dev))
+        above = rank_test > k
+        prev_mask = np.zeros(nb, dtype=bool)
+        prev_mask[prev_idx] = True
+        sw_prev_full = np.full(nb, np.nan)
+        sw_prev_full[prev_idx] = sw_prev
+        return {
+            "k": k,
+            "train": {"windows": int(R_train.shape[0] // 3), "blocks": int(R_train.shape[0]),
+                      "steps": steps, "batch": 64, "loss_first": round(hist[0][1], 4),
+                      "loss_last": round(hist[-1][1], 4), "seconds": round(train_s, 1),
+                      "blocks_rank_above_k": int((rank_train > k).sum())},
+            "test_blocks_rank_above_k": int(above.sum()),
+            "sweeps_all": {"learned": summ(ev["sweeps_learned"]),
+                           "gaussian": summ(ev["sweeps_random"]),
+                           "previous_window": summ(sw_prev_full, prev_mask)},
+            "sweeps_rank_above_k": {"learned": summ(ev["sweeps_learned"], above),
+                                    "gaussian": summ(ev["sweeps_random"], above),
+                                    "previous_window": summ(sw_prev_full, above & prev_mask)},
+            "not_converged": {"learned": int((ev["resid_learned"] > 1e-12).sum()),
+                              "gaussian": int((ev["resid_random"] > 1e-12).sum()),
+                              "previous_window": int((res_prev > 1e-12).sum())},
+            "start_resid_median": {"learned": float(np.median(ev["start_resid_learned"])),
+                                   "gaussian": float(np.median(ev["start_resid_random"]))},
+        }
+
+    result = {
+        "workload": "learned-start-T64", "data": "synthetic (seeded RBF animations, 8-16 bones)",
+        "meshes": [(name, int(v.shape[0])) for name, v, _ in mlist],
+        "generate_seconds": round(gen_s, 1),
+        "test": {"windows": nb // 3, "blocks": nb, "seeds": "90000-90023 (held out)"},
+        "oi_tol": 1e-12,
+        "by_k": [train_and_compare(32), train_and_compare(16)],
+        "seconds": round(time.perf_counter() - t_all, 1),
+    }
+    print(json.dumps(result))
+    ctx.close()
+
+
 def bench_rd_sweep(args):
     """Rate-distortion sweep in the manner of the paper's Fig. 3 (only the
     first k of the eigen-trajectory rows kept, k in {2, 5, 10, 20, 30}) on a
@@ -418,6 +540,9 @@ def main():
         return
     if args.workload == "rd":
         bench_rd_sweep(args)
+        return
+    if args.workload == "learned":
+        bench_learned(args)
         return
     import numpy as np
     import torch

@@ -365,8 +365,8 @@ k_bwd_reduce(CholDev f, int t0, int ntasks, int ncols, int cbp, int nsplit,
 // split factor of a backward level: enough blocks to occupy the chip
 int bwd_split(int ntw, int cb) {
   const int blocks = ntw * cb;
-  if (blocks >= 1024) return 1;
-  return std::min(kMaxSplit, (1024 + blocks - 1) / blocks);
+  if (blocks >= 2048) return 1;
+  return std::min(kMaxSplit, (2048 + blocks - 1) / blocks);
 }
 
 }  // namespace

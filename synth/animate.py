@@ -67,19 +67,10 @@ def bend_twist(rest, n_frames: int, seed: int, amplitude: float = 0.2,
     return (P + noise).astype(dtype)
 
 
-def rbf_skinning(rest, n_frames: int, n_bones: int, seed: int,
-                 max_angle_deg: float = 30.0, period_range=(16.0, 128.0),
-                 root_weight: float = 0.1, sigma_frac: float = 0.25,
-                 t0: int = 0, dtype=np.float32):
-    """Gaussian-RBF skinning with `n_bones` bones rotating sinusoidally.
-
-    Bone b: centre c_b = a random rest vertex, axis uniform on the sphere,
-    angle theta_b(t) = theta_max_b * sin(2 pi t / P_b + phi_b) with
-    theta_max_b ~ U(0, max_angle], P_b ~ U[period_range], phi_b ~ U[0, 2pi).
-    Weights w_b(p) = exp(-|p - c_b|^2 / (2 sigma^2)), sigma = sigma_frac times
-    the bounding-box diagonal, plus a static root weight, normalised per vertex.
-    p(t) = sum_b w_b (R_b(t)(p - c_b) + c_b) + w_root p, t = t0 + frame index.
-    """
+def _rbf_rig(rest, n_bones: int, seed: int, max_angle_deg: float, period_range,
+             root_weight: float, sigma_frac: float):
+    """The seeded bones (centre, axis, theta_max, period, phase) and the
+    normalised weights [n][n_bones + 1] of rbf_skinning."""
     rng = np.random.default_rng(seed)
     n = rest.shape[0]
     bones = []
@@ -98,6 +89,52 @@ def rbf_skinning(rest, n_frames: int, n_bones: int, seed: int,
         W[:, b] = np.exp(-d2 / (2.0 * sigma * sigma))
     W[:, n_bones] = root_weight
     W /= W.sum(axis=1, keepdims=True)
+    return bones, W
+
+
+def rbf_skinning_torch(rest, n_frames: int, n_bones: int, seed: int, device,
+                       max_angle_deg: float = 30.0, period_range=(16.0, 128.0),
+                       root_weight: float = 0.1, sigma_frac: float = 0.25, t0: int = 0,
+                       frames_per_chunk: int = 32):
+    """rbf_skinning with the same seeded rig, evaluated with torch (float64)
+    on `device` and returned there as float32 [n_frames][n][3]: for the large
+    training sets of the learned start (input synthesis only)."""
+    import torch
+    bones, W = _rbf_rig(rest, n_bones, seed, max_angle_deg, period_range, root_weight, sigma_frac)
+    n = rest.shape[0]
+    P = torch.from_numpy(np.asarray(rest, dtype=np.float64)).to(device)
+    Wt = torch.from_numpy(W).to(device)
+    t = t0 + np.arange(n_frames, dtype=np.float64)
+    rots = [torch.from_numpy(_rodrigues(axis, theta_max * np.sin(2.0 * np.pi * t / period + phase)))
+            .to(device) for (c, axis, theta_max, period, phase) in bones]
+    centres = [torch.from_numpy(np.asarray(c, dtype=np.float64)).to(device) for (c, *_r) in bones]
+    out = torch.empty((n_frames, n, 3), dtype=torch.float32, device=device)
+    for f0 in range(0, n_frames, frames_per_chunk):
+        f1 = min(n_frames, f0 + frames_per_chunk)
+        acc = (Wt[:, n_bones:n_bones + 1] * P).unsqueeze(0).repeat(f1 - f0, 1, 1)
+        for b in range(n_bones):
+            rel = P - centres[b]
+            moved = torch.matmul(rel.unsqueeze(0), rots[b][f0:f1].transpose(1, 2).contiguous())
+            acc += Wt[:, b:b + 1].unsqueeze(0) * (moved + centres[b])
+        out[f0:f1] = acc.to(torch.float32)
+    return out
+
+
+def rbf_skinning(rest, n_frames: int, n_bones: int, seed: int,
+                 max_angle_deg: float = 30.0, period_range=(16.0, 128.0),
+                 root_weight: float = 0.1, sigma_frac: float = 0.25,
+                 t0: int = 0, dtype=np.float32):
+    """Gaussian-RBF skinning with `n_bones` bones rotating sinusoidally.
+
+    Bone b: centre c_b = a random rest vertex, axis uniform on the sphere,
+    angle theta_b(t) = theta_max_b * sin(2 pi t / P_b + phi_b) with
+    theta_max_b ~ U(0, max_angle], P_b ~ U[period_range], phi_b ~ U[0, 2pi).
+    Weights w_b(p) = exp(-|p - c_b|^2 / (2 sigma^2)), sigma = sigma_frac times
+    the bounding-box diagonal, plus a static root weight, normalised per vertex.
+    p(t) = sum_b w_b (R_b(t)(p - c_b) + c_b) + w_root p, t = t0 + frame index.
+    """
+    n = rest.shape[0]
+    bones, W = _rbf_rig(rest, n_bones, seed, max_angle_deg, period_range, root_weight, sigma_frac)
     out = np.empty((n_frames, n, 3), dtype=dtype)
     t = t0 + np.arange(n_frames, dtype=np.float64)
     rots = []
