@@ -452,7 +452,10 @@ dmc_status dmc_mlp_adam(dmc_ctx ctx, float* theta_dev, const float* grad_dev, fl
  * exactly params[i].cg_max_iters conjugate-gradient iterations and no host
  * synchronisation.  At creation a small autotuner times candidate vertex
  * splits of the covariance kernel on each sequence's own frames and keeps
- * the fastest.  The batch owns
+ * the fastest.  Sequences are spread over four branches of the graph
+ * (largest first onto the least loaded, by vertex-frames), each with its own
+ * scratch: their kernels overlap on the GPU, those of one sequence run in
+ * order.  The batch owns
  * its device scratch (allocated at creation); meshes and caller buffers must
  * outlive it.
  * dmc_batch_run: ordered on the context's stream, does not synchronise.
@@ -461,8 +464,8 @@ dmc_status dmc_mlp_adam(dmc_ctx ctx, float* theta_dev, const float* grad_dev, fl
  * cg_resid = largest relative residual) and returns DMC_ERR_NOT_CONVERGED if
  * some column of the sequence did not reach cg_tol.
  * dmc_batch_tuning: the autotuner's choices for sequence seq:
- * tuning[0] = covariance vertex blocks per window, tuning[1] = 0 (reserved;
- * the delta coordinates are formed inside the projection kernel). */
+ * tuning[0] = covariance vertex blocks per window, tuning[1] = the graph
+ * branch the sequence runs on (0-3). */
 typedef struct dmc_batch_s* dmc_batch;
 dmc_status dmc_batch_create(dmc_ctx ctx, int32_t nseq, const dmc_mesh* meshes,
                             const void* const* frames_dev, const int32_t* F, const int32_t* T,

@@ -1789,6 +1789,7 @@ struct BatchSeq {
   size_t o_ud = 0, o_udt = 0, o_ap = 0, o_apt = 0;  // dequantised dictionaries, anchor partials
   int32_t stats_off = 0;  // first window in the batch's stats array
   int P = 0;              // tuned launch shape
+  int branch = 0;         // graph branch the sequence's kernels run on
 };
 
 struct dmc_batch_s {
@@ -1796,72 +1797,115 @@ struct dmc_batch_s {
   int32_t precision = DMC_FP32;
   std::vector<BatchSeq> seq;
   uint8_t* buf = nullptr;
-  size_t o_shared = 0, o_args = 0, o_jobs = 0, o_summary = 0, o_stats = 0;
+  size_t o_args = 0, o_jobs = 0, o_summary = 0, o_stats = 0;
+  std::vector<size_t> o_shared;  // per branch: covariance, projection and decoder scratch
   std::vector<int> cls_tmax, cls_kr, cls_off, cls_n;  // OI launch classes
   hipStream_t stream = nullptr;  // private stream the graph is captured on and replayed on
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  // capture only: one stream per branch, fork and join events of the two
+  // per-sequence phases (before and after the orthogonal iterations)
+  std::vector<hipStream_t> br;
+  std::vector<hipEvent_t> ev_fork, ev_join;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
 
 namespace {
 
-// The whole batch on stream s, with no host synchronisation.
-void batch_enqueue(dmc_batch b, hipStream_t s) {
-  uint8_t* shared = b->buf + b->o_shared;
+// Branch streams wait for what stream s has recorded so far (phase ph).
+hipError_t batch_fork(dmc_batch b, hipStream_t s, int ph) {
+  if (b->br.empty()) return hipSuccess;
+  hipError_t e = hipEventRecord(b->ev_fork[ph], s);
+  for (size_t j = 0; j < b->br.size() && e == hipSuccess; ++j)
+    e = hipStreamWaitEvent(b->br[j], b->ev_fork[ph], 0);
+  return e;
+}
+
+// Stream s waits for every branch's work of phase ph.
+hipError_t batch_join(dmc_batch b, hipStream_t s, int ph) {
+  hipError_t e = hipSuccess;
+  const size_t nb = b->br.size();
+  for (size_t j = 0; j < nb && e == hipSuccess; ++j) {
+    e = hipEventRecord(b->ev_join[ph * nb + j], b->br[j]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, b->ev_join[ph * nb + j], 0);
+  }
+  return e;
+}
+
+// The whole batch on stream s, with no host synchronisation.  The kernels of
+// one sequence run in order on its branch; the branches share nothing but
+// the orthogonal-iteration launches between the two phases.
+hipError_t batch_enqueue(dmc_batch b, hipStream_t s) {
   const size_t rs = real_size(b->precision);
+  auto on = [&](const BatchSeq& q) { return b->br.empty() ? s : b->br[q.branch]; };
+  auto shared_of = [&](const BatchSeq& q) { return b->buf + b->o_shared[q.branch]; };
+  hipError_t e = batch_fork(b, s, 0);
+  if (e != hipSuccess) return e;
   for (BatchSeq& q : b->seq) {
     const dmc::MeshDev& m = q.mesh->dev;
-    dmc::launch_write_headers(s, q.codes, q.sl.nw_full, q.sl.full.bytes, q.sl.full);
+    hipStream_t sq = on(q);
+    uint8_t* shared = shared_of(q);
+    dmc::launch_write_headers(sq, q.codes, q.sl.nw_full, q.sl.full.bytes, q.sl.full);
     if (q.sl.T_tail)
-      dmc::launch_write_headers(s, q.codes + (size_t)q.sl.nw_full * q.sl.full.bytes, 1,
+      dmc::launch_write_headers(sq, q.codes + (size_t)q.sl.nw_full * q.sl.full.bytes, 1,
                                 q.sl.tail.bytes, q.sl.tail);
     if (q.sl.nw_full)
-      dmc::launch_autocorr(s, q.frames, m.n, q.T, q.sl.nw_full, b->precision, shared,
+      dmc::launch_autocorr(sq, q.frames, m.n, q.T, q.sl.nw_full, b->precision, shared,
                            (double*)(b->buf + q.o_R), q.P);
     if (q.sl.T_tail)
-      dmc::launch_autocorr(s, q.frames + (size_t)q.sl.nw_full * q.T * 3 * m.n * rs, m.n,
+      dmc::launch_autocorr(sq, q.frames + (size_t)q.sl.nw_full * q.T * 3 * m.n * rs, m.n,
                            q.sl.T_tail, 1, b->precision, shared, (double*)(b->buf + q.o_Rt));
   }
+  if ((e = batch_join(b, s, 0)) != hipSuccess) return e;
   for (size_t c = 0; c < b->cls_n.size(); ++c)
     dmc::launch_oi_batch(s, b->cls_tmax[c], b->cls_kr[c], b->precision,
                          (const dmc::OiArgs*)(b->buf + b->o_args),
                          (const int4*)(b->buf + b->o_jobs) + b->cls_off[c], b->cls_n[c]);
-  for (BatchSeq& q : b->seq) {
+  if ((e = batch_fork(b, s, 1)) != hipSuccess) return e;
+  double* summary = (double*)(b->buf + b->o_summary);
+  for (size_t i = 0; i < b->seq.size(); ++i) {
+    BatchSeq& q = b->seq[i];
     const dmc::MeshDev& m = q.mesh->dev;
+    hipStream_t sq = on(q);
+    uint8_t* shared = shared_of(q);
     if (q.sl.nw_full) {
       double* ud = (double*)(b->buf + q.o_ud);
-      dmc::launch_dict_code(s, (const double*)(b->buf + q.o_ut), q.sl.nw_full, q.sl.full, q.codes,
-                            q.sl.full.bytes, ud);
-      dmc::launch_project_quantise(s, m, q.frames, q.T, q.k_full, q.sl.nw_full, b->precision, ud,
-                                   q.codes, q.sl.full.bytes, q.sl.full, shared, nullptr);
-      dmc::launch_anchors(s, m, q.frames, q.T, q.sl.nw_full, b->precision, q.codes,
+      dmc::launch_dict_code(sq, (const double*)(b->buf + q.o_ut), q.sl.nw_full, q.sl.full,
+                            q.codes, q.sl.full.bytes, ud);
+      dmc::launch_project_quantise(sq, m, q.frames, q.T, q.k_full, q.sl.nw_full, b->precision,
+                                   ud, q.codes, q.sl.full.bytes, q.sl.full, shared, nullptr);
+      dmc::launch_anchors(sq, m, q.frames, q.T, q.sl.nw_full, b->precision, q.codes,
                           q.sl.full.bytes, q.sl.full, (double*)(b->buf + q.o_ap));
-      dmc::launch_zero_tail(s, q.codes, q.sl.nw_full, q.sl.full.bytes);
+      dmc::launch_zero_tail(sq, q.codes, q.sl.nw_full, q.sl.full.bytes);
     }
     if (q.sl.T_tail) {
       const size_t f0 = (size_t)q.sl.nw_full * q.T;
       uint8_t* rec = q.codes + (size_t)q.sl.nw_full * q.sl.full.bytes;
       double* ud = (double*)(b->buf + q.o_udt);
-      dmc::launch_dict_code(s, (const double*)(b->buf + q.o_utt), 1, q.sl.tail, rec,
+      dmc::launch_dict_code(sq, (const double*)(b->buf + q.o_utt), 1, q.sl.tail, rec,
                             q.sl.tail.bytes, ud);
-      dmc::launch_project_quantise(s, m, q.frames + f0 * 3 * m.n * rs, q.sl.T_tail, q.k_tail, 1,
-                                   b->precision, ud, rec, q.sl.tail.bytes, q.sl.tail, shared,
+      dmc::launch_project_quantise(sq, m, q.frames + f0 * 3 * m.n * rs, q.sl.T_tail, q.k_tail,
+                                   1, b->precision, ud, rec, q.sl.tail.bytes, q.sl.tail, shared,
                                    nullptr);
-      dmc::launch_anchors(s, m, q.frames + f0 * 3 * m.n * rs, q.sl.T_tail, 1, b->precision, rec,
-                          q.sl.tail.bytes, q.sl.tail, (double*)(b->buf + q.o_apt));
-      dmc::launch_zero_tail(s, rec, 1, q.sl.tail.bytes);
+      dmc::launch_anchors(sq, m, q.frames + f0 * 3 * m.n * rs, q.sl.T_tail, 1, b->precision,
+                          rec, q.sl.tail.bytes, q.sl.tail, (double*)(b->buf + q.o_apt));
+      dmc::launch_zero_tail(sq, rec, 1, q.sl.tail.bytes);
+    }
+    if (q.out) {
+      const DecodePlan d = decode_plan(m, q.sl, q.p);
+      decode_enqueue_fixed(sq, m, q.codes, q.sl, q.p, d, shared, q.out, q.p.cg_max_iters,
+                           summary + 2 * i);
     }
   }
-  double* summary = (double*)(b->buf + b->o_summary);
-  for (size_t i = 0; i < b->seq.size(); ++i) {
-    BatchSeq& q = b->seq[i];
-    if (!q.out) continue;
-    const DecodePlan d = decode_plan(q.mesh->dev, q.sl, q.p);
-    decode_enqueue_fixed(s, q.mesh->dev, q.codes, q.sl, q.p, d, shared, q.out, q.p.cg_max_iters,
-                         summary + 2 * i);
-  }
+  return batch_join(b, s, 1);
 }
+
+// Branches of the batch's graph: independent sequences overlap on the GPU.
+// Four, the HIP runtime's default number of hardware queues per process (on
+// 64 sequences of 2k-60k vertices: 110 ms per run on one branch, 75 on two,
+// 60 on four; eight branches ran no faster, and eight or sixteen hardware
+// queues made the run slower).
+int batch_branches(int32_t nseq) { return std::max(1, std::min<int>(4, nseq)); }
 
 // Times `launch` (three runs after one warm-up) with events on stream s.
 template <typename F>
@@ -1903,7 +1947,8 @@ dmc_status dmc_batch_create(dmc_ctx ctx, int32_t nseq, const dmc_mesh* meshes,
     return st;
   };
   Carve cv;
-  size_t shared = 0, nargs = 0, njobs = 0, nwin = 0;
+  size_t nargs = 0, njobs = 0, nwin = 0;
+  std::vector<size_t> need(nseq);  // per sequence: bytes of its share of the branch scratch
   b->seq.resize(nseq);
   for (int32_t i = 0; i < nseq; ++i) {
     BatchSeq& q = b->seq[i];
@@ -1941,15 +1986,15 @@ dmc_status dmc_batch_create(dmc_ctx ctx, int32_t nseq, const dmc_mesh* meshes,
     q.o_apt = cv.add(dmc::anchors_scratch_bytes(1));
     q.stats_off = (int32_t)nwin;
     nwin += q.sl.nw_full + (q.sl.T_tail ? 1 : 0);
-    // shared region: the largest autocorrelation partials (any tuned split),
-    // projection scratch and decoder buffers of any one sequence
+    // branch scratch: autocorrelation partials (any tuned split), projection
+    // scratch and decoder buffers, used by one sequence at a time
     const int P0 = dmc::autocorr_blocks(m.n, std::max(1, q.sl.nw_full));
     const int Pmax = std::max(1, std::min(4 * P0, std::max(1, m.n)));
-    shared = std::max(shared, dmc::autocorr_scratch_bytes(m.n, q.T, std::max(1, q.sl.nw_full),
-                                                          b->precision, Pmax));
-    shared = std::max(shared, dmc::project_scratch_bytes(m.n, q.T, q.k_full,
-                                                         std::max(1, q.sl.nw_full), b->precision));
-    if (q.out) shared = std::max(shared, decode_plan(m, q.sl, p).lay.total);
+    need[i] = std::max(dmc::autocorr_scratch_bytes(m.n, q.T, std::max(1, q.sl.nw_full),
+                                                   b->precision, Pmax),
+                       dmc::project_scratch_bytes(m.n, q.T, q.k_full, std::max(1, q.sl.nw_full),
+                                                  b->precision));
+    if (q.out) need[i] = std::max(need[i], decode_plan(m, q.sl, p).lay.total);
     if (q.sl.nw_full) {
       ++nargs;
       njobs += p.init == DMC_INIT_PREV ? 3 : 3 * (size_t)q.sl.nw_full;
@@ -1959,7 +2004,23 @@ dmc_status dmc_batch_create(dmc_ctx ctx, int32_t nseq, const dmc_mesh* meshes,
       njobs += 3;
     }
   }
-  b->o_shared = cv.add(shared);
+  // sequences to branches, largest first onto the least loaded (vertex-frames)
+  const int nbranch = batch_branches(nseq);
+  {
+    std::vector<int> order(nseq);
+    for (int32_t i = 0; i < nseq; ++i) order[i] = i;
+    auto work = [&](int i) { return (double)b->seq[i].mesh->dev.n * b->seq[i].F; };
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return work(x) > work(y); });
+    std::vector<double> load(nbranch, 0.0);
+    std::vector<size_t> bytes(nbranch, 0);
+    for (int i : order) {
+      const int j = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      b->seq[i].branch = j;
+      load[j] += work(i);
+      bytes[j] = std::max(bytes[j], need[i]);
+    }
+    for (int j = 0; j < nbranch; ++j) b->o_shared.push_back(cv.add(bytes[j]));
+  }
   b->o_args = cv.add(nargs * sizeof(dmc::OiArgs));
   b->o_jobs = cv.add(njobs * sizeof(int4));
   b->o_summary = cv.add((size_t)nseq * 2 * sizeof(double));
@@ -2029,10 +2090,10 @@ dmc_status dmc_batch_create(dmc_ctx ctx, int32_t nseq, const dmc_mesh* meshes,
   // autotuner: vertex split of the covariance kernel, timed on each
   // sequence's own frames
   hipStream_t s = ctx->stream;
-  uint8_t* sh = b->buf + b->o_shared;
   for (BatchSeq& q : b->seq) {
     const dmc::MeshDev& m = q.mesh->dev;
     if (!q.sl.nw_full) continue;
+    uint8_t* sh = b->buf + b->o_shared[q.branch];
     const int P0 = dmc::autocorr_blocks(m.n, q.sl.nw_full);
     float best = 1e30f;
     for (int P : {P0 / 4, P0 / 2, P0, 2 * P0, 4 * P0}) {
@@ -2048,12 +2109,24 @@ dmc_status dmc_batch_create(dmc_ctx ctx, int32_t nseq, const dmc_mesh* meshes,
     }
   }
   dmc_status st = check_launch("batch autotuner");
-  if (st == DMC_OK &&
-      (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess ||
-       hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) != hipSuccess ||
-       hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) != hipSuccess)) {
+  bool ok = st == DMC_OK &&
+            hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) == hipSuccess &&
+            hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) == hipSuccess &&
+            hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) == hipSuccess;
+  if (ok && nbranch > 1) {
+    b->br.assign(nbranch, nullptr);
+    b->ev_fork.assign(2, nullptr);
+    b->ev_join.assign(2 * nbranch, nullptr);
+    for (hipStream_t& x : b->br)
+      ok = ok && hipStreamCreateWithFlags(&x, hipStreamNonBlocking) == hipSuccess;
+    for (hipEvent_t& x : b->ev_fork)
+      ok = ok && hipEventCreateWithFlags(&x, hipEventDisableTiming) == hipSuccess;
+    for (hipEvent_t& x : b->ev_join)
+      ok = ok && hipEventCreateWithFlags(&x, hipEventDisableTiming) == hipSuccess;
+  }
+  if (st == DMC_OK && !ok) {
     (void)hipGetLastError();
-    st = fail(DMC_ERR_DEVICE, "cannot create the batch's stream");
+    st = fail(DMC_ERR_DEVICE, "cannot create the batch's streams");
   }
   if (st != DMC_OK) {
     dmc_batch_destroy(b);
@@ -2071,12 +2144,19 @@ dmc_status dmc_batch_run(dmc_batch b) {
     dmc::prof::pause(true);
     hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-      batch_enqueue(b, s);
+      const hipError_t e1 = batch_enqueue(b, s);
       e = hipStreamEndCapture(s, &b->graph);
+      if (e1 != hipSuccess) {
+        if (e == hipSuccess) (void)hipGraphDestroy(b->graph);
+        b->graph = nullptr;
+        e = e1;
+      }
     }
     dmc::prof::pause(false);
-    if (e != hipSuccess)
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
       return fail(DMC_ERR_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    }
     HIP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
   }
   // ordered after earlier work on the context's stream, and before later work
@@ -2129,7 +2209,7 @@ dmc_status dmc_batch_tuning(dmc_batch b, int32_t i, int32_t tuning[2]) {
   if (!b || !tuning) return fail(DMC_ERR_INVALID_ARG, "NULL argument");
   if (i < 0 || i >= (int32_t)b->seq.size()) return fail(DMC_ERR_INVALID_ARG, "bad sequence index");
   tuning[0] = b->seq[i].P;
-  tuning[1] = 0;
+  tuning[1] = b->seq[i].branch;
   return DMC_OK;
 }
 
@@ -2142,6 +2222,12 @@ void dmc_batch_destroy(dmc_batch b) {
   if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->ev_in) (void)hipEventDestroy(b->ev_in);
   if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+  for (hipEvent_t x : b->ev_fork)
+    if (x) (void)hipEventDestroy(x);
+  for (hipEvent_t x : b->ev_join)
+    if (x) (void)hipEventDestroy(x);
+  for (hipStream_t x : b->br)
+    if (x) (void)hipStreamDestroy(x);
   if (b->stream) (void)hipStreamDestroy(b->stream);
   if (b->buf) (void)hipFree(b->buf);
   delete b;

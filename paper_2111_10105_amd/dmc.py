@@ -689,7 +689,7 @@ class Batch:
     def tuning(self, i: int):
         t = (ctypes.c_int32 * 2)()
         _check(lib().dmc_batch_tuning(self.h, int(i), t))
-        return {"autocorr_blocks": t[0]}
+        return {"autocorr_blocks": t[0], "branch": t[1]}
 
     def close(self):
         if self.h:

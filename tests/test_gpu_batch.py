@@ -61,6 +61,7 @@ def test_batch_matches_single_sequences_and_oracle(ctx, init):
             stats, status = b.stats(i)
             assert status == 0, (i, stats)
             tun = b.tuning(i)
+            assert 0 <= tun["branch"] < min(4, len(ws))
             # the same sequence through the single-sequence path
             p1 = dmc.make_params(w.k, coef_bits=w.bits, precision=dmc.FP32, init=init)
             _, single, st1, _ = dmc.compress_sequence(ctx, meshes[i], frames[i], w.T, p1,
