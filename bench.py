@@ -62,7 +62,7 @@ FAMILY_SOURCE = {
 }
 FAMILY_KERNEL = {"chol_bwd_solve": "k_bwd_gemm", "chol_fwd_solve": "k_fwd_gemm",
                  "chol_fwd_gather": "k_fwd_gather", "oi": "k_oi", "cg_spmm": "k_cg_spmm",
-                 "delta": "k_delta", "back_project": "k_back_project"}
+                 "delta": "k_delta", "back_project": "k_coef_rows", "rhs": "k_rhs_expand"}
 
 
 def parse():
@@ -141,10 +141,10 @@ def work_model(fam, *, n, F, T, k, nw, rs, ncols, nnz, m_nnz, finfo, sweeps_tota
         return "hbm", rs * coef + 2.0 * coef, "B", hbm
     if fam == "anchors":
         return "hbm", 2.0 * rs * 3 * nc * F, "B", hbm
-    if fam == "back_project":  # reduced: the dequantised coefficient rows
-        return "hbm", 2.0 * coef + vec, "B", hbm
-    if fam == "rhs":
-        return "hbm", 2 * vec, "B", hbm
+    if fam == "back_project":  # the dequantised coefficient rows (float64)
+        return "hbm", 2.0 * coef + 8.0 * coef, "B", hbm
+    if fam == "rhs":  # L^T on the coefficient rows (and, direct form, their expansion)
+        return "hbm", 8.0 * coef + vec, "B", hbm
     if fam == "cg_spmm":
         return "hbm", 2 * vec + 12.0 * m_nnz, "B", hbm
     if fam == "cg_update":

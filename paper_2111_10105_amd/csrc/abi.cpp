@@ -487,8 +487,12 @@ void decode_enqueue_setup(hipStream_t s, const dmc::MeshDev& m, const uint8_t* r
     dmc::launch_rhs_reduced(s, m, d.ncols, cb.q, cb.r, bb);
     dmc::launch_anchor_values(s, m, records, sl, Ah);
   } else {
-    dmc::launch_back_project(s, m, records, sl, ut, cb.q);
-    dmc::launch_rhs(s, m, records, sl, cb.q, cb.r, bb);
+    // b = L^T (Y^ U~^T) formed as (L^T Y^) U~^T: the dequantised coefficient
+    // rows (in q), the anchor values after b, then the expansion
+    double* Ah = cb.r + (size_t)m.n * d.ncols;
+    dmc::launch_coef_rows(s, m, records, sl, cb.q);
+    dmc::launch_anchor_values(s, m, records, sl, Ah);
+    dmc::launch_rhs_from_coefs(s, m, sl, cb.q, ut, m.nc ? Ah : nullptr, cb.r, bb);
   }
   if (p.precond == DMC_PRECOND_CHOLESKY)
     dmc::launch_cg_norms(s, m, d.ncols, cb);  // the solve starts from the factor's solution

@@ -300,12 +300,6 @@ struct SeqLayout {
 // (dict_decode_doubles(sl) doubles), which the decode kernels below read.
 size_t dict_decode_doubles(const SeqLayout& sl);
 void launch_dict_decode(hipStream_t s, const uint8_t* records, const SeqLayout& sl, double* ut);
-void launch_back_project(hipStream_t s, const MeshDev& m, const uint8_t* records,
-                         const SeqLayout& sl, const double* ut, double* B0);
-// bb (optional): per-block partial b.b per column (the first half of the CG
-// partials, [cg_part_rows(n)][ncols])
-void launch_rhs(hipStream_t s, const MeshDev& m, const uint8_t* records, const SeqLayout& sl,
-                const double* B0, double* b, double* bb);
 // Temporal-subspace decode (X_wc = Z_wc U~_wc^T + G A^_wc, Eq. 12 by linearity):
 // columns of the reduced system (3k per window), dequantised coefficients
 // Yd [n][nz], its right-hand side L^T Yd (no anchor term), the dense anchor
@@ -318,6 +312,14 @@ void launch_rhs_reduced(hipStream_t s, const MeshDev& m, int32_t nz, const doubl
                         double* bb);
 void launch_anchor_values(hipStream_t s, const MeshDev& m, const uint8_t* records,
                           const SeqLayout& sl, double* Ah);
+// Direct decode's right-hand side b [n][3F] = L^T (Y^ U~^T) + I_N^T A^ from
+// the coefficient rows Yd [n][nz] (launch_coef_rows), the dictionaries ut and
+// the dense anchor values Ah [nc][3F] (NULL: no anchor term); bb
+// (optional): per-block partial b.b per column (the first half of the CG
+// partials, [cg_part_rows(n)][3F]).
+void launch_rhs_from_coefs(hipStream_t s, const MeshDev& m, const SeqLayout& sl,
+                           const double* Yd, const double* ut, const double* Ah, double* b,
+                           double* bb);
 void launch_anchor_unit_rhs(hipStream_t s, const MeshDev& m, double* b);
 // Reference norms of the reduced columns (after launch_cg_init, with b the
 // reduced right-hand side): the test on them bounds every frame's full-system

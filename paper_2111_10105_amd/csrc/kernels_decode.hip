@@ -16,7 +16,6 @@ namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-constexpr int BP_V = 32;   // vertices per back-projection block
 constexpr int CG_RB = 32;  // rows per CG block
 
 __device__ inline double dequant(uint32_t code, double lo, double hi, int bits) {
@@ -97,54 +96,6 @@ k_dict_decode(const uint8_t* __restrict__ records, size_t rec_bytes, RecordLayou
       Ut[at] = mode ? Up[at] + v : v;
     }
     __syncthreads();
-  }
-}
-
-// B0[pos(i)][3(t0+t)+c] = sum_r U~_c[t][r] Y^_c[r][i]  (Eq. 11/12 right-hand
-// side; row by the vertex's position in the decoder's row order)
-// Thread (j, g) owns column j = 3 t + c of the window: its dictionary row
-// U~_c[t][.] stays in registers while it runs over the block's vertices
-// g, g + G, ... (G = 256 / 3T groups), reading each vertex's coefficients from
-// LDS (one address per coordinate across the wave); consecutive lanes write
-// consecutive columns of a vertex row.
-template <typename Real>
-__global__ void __launch_bounds__(kBlock)
-k_back_project(const uint8_t* __restrict__ records, SeqLayout sl, int n, int ncols,
-               const int32_t* __restrict__ pos, const double* __restrict__ ut,
-               double* __restrict__ B0) {
-  // padded stride 33 keeps the coordinates of a vertex on different LDS banks
-  __shared__ double Yh[BP_V * 3 * 33];
-  const int w = blockIdx.y;
-  const uint8_t* rec;
-  int T, k, t0;
-  RecordLayout lay;
-  window_of(sl, records, w, rec, T, k, t0, lay);
-  const int i0 = blockIdx.x * BP_V;
-  const int nv = min(BP_V, n - i0);
-  // coefficients of this block's vertices: Yh[v][c][r]
-  for (int e = threadIdx.x; e < 3 * k * nv; e += kBlock) {
-    const int v = e % nv, cr = e / nv;  // consecutive threads -> consecutive vertices
-    const int c = cr / k, r = cr % k;
-    Yh[(v * 3 + c) * 33 + r] = coef_value<Real>(rec, lay, cr, i0 + v);
-  }
-  __syncthreads();
-  const int wcols = 3 * T;  // <= 192
-  const int groups = kBlock / wcols;
-  const int j = threadIdx.x % wcols, g = threadIdx.x / wcols;
-  if (g >= groups) return;
-  const int t = j / 3, c = j % 3;
-  // dictionary row (k <= 32)
-  const double* ud = dict_of(sl, ut, w);
-  double u[32];
-#pragma unroll
-  for (int r = 0; r < 32; ++r) u[r] = r >= k ? 0.0 : ud[(c * T + t) * k + r];
-  for (int v = g; v < nv; v += groups) {
-    const double* y = Yh + (v * 3 + c) * 33;
-    double s = 0.0;
-#pragma unroll
-    for (int r = 0; r < 32; ++r)
-      if (r < k) s = fma(u[r], y[r], s);
-    B0[(size_t)pos[i0 + v] * ncols + 3 * t0 + j] = s;
   }
 }
 
@@ -709,6 +660,192 @@ k_coef_rows(const uint8_t* __restrict__ records, SeqLayout sl, int n, int nz,
   }
 }
 
+// Right-hand side of the direct decode from the coefficient rows: Eq. (12)'s
+// L^T B0 with B0 = Y^_wc^T U~_wc^T per window and coordinate equals
+// (L^T Y^_wc^T) U~_wc^T, so the Laplacian runs on the 3k coefficient columns
+// of a window instead of its 3T frame columns and the back-projected
+// deltas are never stored:
+//   b[pos(i)][3(t0+t)+c] = sum_r U~_c[t][r] (L^T Yd)[i][zoff(w) + c k + r]
+//                          (+ A^[slot][j] at anchor rows)
+// Block (CG row block of CG_RB rows, window w):
+//  1. the block's rings in LDS, padded to RX_RING entries (weight 0 on the
+//     row itself), so a thread issues the loads of two (row, column) items
+//     at once without waiting on a loop bound; longer rings finish from
+//     memory;
+//  2. z = L^T Yd for the window's 3k columns into LDS (ring weights as in
+//     k_rhs);
+//  3. the expansion on the FP64 matrix cores: a wavefront takes a 16-frame
+//     tile and a run of 16-row tiles (the dictionary operands of its frames
+//     stay in registers), puts the three coordinates' results of 8 rows at
+//     a time into its own LDS stage in b's column order, and writes them
+//     out as contiguous runs.
+// With bb given, the block's b.b partial per column (k_rhs's row blocks),
+// summed in a fixed order.  KM: the largest k of the sequence (16 or 32).
+constexpr int RX_RING = 8;
+
+template <int KM>
+__global__ void __launch_bounds__(kBlock)
+k_rhs_expand(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+             const double* __restrict__ w, int uniform, const int32_t* __restrict__ slot, int n,
+             int ncols, int nz, int nrbp, SeqLayout sl, const double* __restrict__ Yd,
+             const double* __restrict__ ut, const double* __restrict__ Ah,
+             double* __restrict__ b, double* __restrict__ bb) {
+  constexpr int ZST = 3 * KM + 1;  // row stride of zs (odd: rows on different banks)
+  constexpr int NW = kBlock / 64;
+  __shared__ double zs[CG_RB * ZST];           // [v][c k + r]
+  __shared__ double stage[NW][8 * 48];         // per wave: 8 rows x (16 frames x 3)
+  __shared__ int rcol[CG_RB][RX_RING];
+  __shared__ double rwt[CG_RB][RX_RING];
+  __shared__ int rlen[CG_RB + 1];
+  __shared__ int sslot[CG_RB];
+  __shared__ double sq[CG_RB / 16][3][64];     // per row tile: column sums of b^2
+  const int rb = xcd_row_block(nrbp);
+  const int r0 = rb * CG_RB;
+  if (r0 >= n) return;  // padding block
+  const int nr = min(CG_RB, n - r0);
+  const int win = blockIdx.y;
+  const bool full = win < sl.nw_full;
+  const int T = full ? sl.T : sl.T_tail, k = full ? sl.full.k : sl.tail.k;
+  const int t0 = (full ? win : sl.nw_full) * sl.T;
+  const int ck = 3 * k, z0 = zoff(sl, win);
+  // 1. rings (rlen[v] = start of row v's entries; rows past n empty)
+  for (int v = threadIdx.x; v <= CG_RB; v += kBlock) rlen[v] = rowptr[r0 + min(v, nr)];
+  for (int v = threadIdx.x; v < CG_RB; v += kBlock) sslot[v] = v < nr ? slot[r0 + v] : -1;
+  __syncthreads();
+  for (int e = threadIdx.x; e < CG_RB * RX_RING; e += kBlock) {
+    const int v = e / RX_RING, h = e % RX_RING;
+    const int q = rlen[v] + h;
+    const bool on = v < nr && q < rlen[v + 1];
+    const int cj = on ? col[q] : min(r0 + v, n - 1);
+    rcol[v][h] = cj;
+    rwt[v][h] = on ? (uniform ? w[cj] : 1.0) : 0.0;
+  }
+  __syncthreads();
+  // 2. z rows: item e = (row e / ck, column e % ck), two items per pass
+  auto zitem = [&](int v, int cr, double (&x)[RX_RING + 1]) {
+    const double* yc = Yd + z0 + cr;
+#pragma unroll
+    for (int h = 0; h < RX_RING; ++h) x[h] = yc[(size_t)rcol[v][h] * nz];
+    x[RX_RING] = yc[(size_t)min(r0 + v, n - 1) * nz];
+  };
+  auto zfinish = [&](int v, int cr, const double (&x)[RX_RING + 1]) {
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int h = 0; h < RX_RING; ++h) a[h % 4] = fma(rwt[v][h], x[h], a[h % 4]);
+    const double* yc = Yd + z0 + cr;
+    for (int q = rlen[v] + RX_RING; q < rlen[v + 1]; ++q) {  // rings longer than RX_RING
+      const int cj = col[q];
+      a[0] = fma(uniform ? w[cj] : 1.0, yc[(size_t)cj * nz], a[0]);
+    }
+    const double s4 = (a[0] + a[1]) + (a[2] + a[3]);
+    const double ui = x[RX_RING];
+    return v < nr ? (uniform ? ui - s4 : w[r0 + v] * ui - s4) : 0.0;
+  };
+  const int nitem = CG_RB * ck;
+  for (int e = threadIdx.x; e < nitem; e += 2 * kBlock) {
+    const int e2 = e + kBlock;
+    const int v1 = e / ck, c1 = e % ck;
+    const int v2 = e2 < nitem ? e2 / ck : v1, c2 = e2 < nitem ? e2 % ck : c1;
+    double x1[RX_RING + 1], x2[RX_RING + 1];
+    zitem(v1, c1, x1);
+    zitem(v2, c2, x2);
+    zs[v1 * ZST + c1] = zfinish(v1, c1, x1);
+    if (e2 < nitem) zs[v2 * ZST + c2] = zfinish(v2, c2, x2);
+  }
+  __syncthreads();
+  // 3. expansion.  Item (tt, g): frames 16 tt.. and row tiles g rts ..; lane l
+  // supplies A[l%16][l/16] = z[row][c k + 4 s + l/16] and B[l/16][l%16] =
+  // U~_c[t][4 s + l/16]; component q of lane l is row 4 q + l/16, frame l%16
+  const double* U = ut + (size_t)(full ? win : sl.nw_full) * 3 * sl.T * sl.full.k;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int l16 = lane & 15, lg = lane >> 4;
+  const int nT16 = (T + 15) >> 4;
+  constexpr int NRT = CG_RB / 16;
+  const int groups = max(1, min(NW / nT16, NRT)), rts = NRT / groups;
+  double* st = stage[wv];
+  for (int it = wv; it < nT16 * groups; it += NW) {
+    const int tt = it % nT16, g = it / nT16;
+    const int t = 16 * tt + l16;
+    const int nt = min(16, T - 16 * tt);  // frames of this tile
+    double bu[3][KM / 4];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int s = 0; s < KM / 4; ++s) {
+        const int r = 4 * s + lg;
+        bu[c][s] = (t < T && r < k) ? U[((size_t)c * T + t) * k + r] : 0.0;
+      }
+    for (int rt = g * rts; rt < (g + 1) * rts; ++rt) {
+      const double* zrow = zs + (16 * rt + l16) * ZST;
+      d4 acc[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        acc[c] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < KM / 4; ++s) {
+          const int r = 4 * s + lg;
+          if (4 * s < k) {
+            const double az = r < k ? zrow[c * k + r] : 0.0;
+            acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(az, bu[c][s], acc[c], 0, 0, 0);
+          }
+        }
+      }
+      // anchor term and column sums of squares (lane: frame t, rows 4 q + lg)
+      double sqs[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int v = 16 * rt + 4 * q + lg;
+        const int sv = v < nr ? sslot[v] : -1;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          double val = acc[c][q];
+          if (Ah && sv >= 0 && t < T) val += Ah[(size_t)sv * ncols + 3 * (t0 + t) + c];
+          acc[c][q] = val;
+          if (v < nr && t < T) sqs[c] = fma(val, val, sqs[c]);
+        }
+      }
+      if (bb) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          // the tile's column sum over lanes l16, l16 + 16, l16 + 32, l16 + 48
+          double x = sqs[c] + swap16_f64(sqs[c]);
+          x += shfl_f64(x, lane ^ 32);
+          if (lg == 0) sq[rt][c][t] = x;
+        }
+      }
+      // rows 4 q + lg in two halves of eight rows: stage in b's column order
+      // (3 t + c), then contiguous runs of 3 nt values per row
+#pragma unroll
+      for (int half = 0; half < 2; ++half) {
+#pragma unroll
+        for (int qq = 0; qq < 2; ++qq)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) st[(4 * qq + lg) * 48 + 3 * l16 + c] = acc[c][2 * half + qq];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (int e = lane; e < 8 * 48; e += 64) {
+          const int vr = e / 48, cc = e % 48;
+          // staged row vr is tile row 8 half + vr: lanes with q = 2 half +
+          // vr / 4 and l/16 = vr % 4 wrote it
+          const int v = 16 * rt + 4 * (2 * half + vr / 4) + vr % 4;
+          if (v < nr && cc < 3 * nt)
+            b[(size_t)(r0 + v) * ncols + 3 * (t0 + 16 * tt) + cc] = st[e];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      }
+    }
+  }
+  if (!bb) return;  // uniform over the block
+  __syncthreads();
+  for (int e = threadIdx.x; e < 3 * T; e += kBlock) {
+    const int t = e / 3, c = e % 3;
+    bb[(size_t)rb * ncols + 3 * (t0 + t) + c] = sq[0][c][t] + sq[1][c][t];
+  }
+}
+
 // right-hand sides of the anchor response: b[p][a] = 1 if the vertex at row
 // position p is anchor a (slot by position)
 __global__ void __launch_bounds__(kBlock)
@@ -1053,42 +1190,6 @@ size_t dict_decode_doubles(const SeqLayout& sl) {
   return (size_t)(sl.nw_full + (sl.T_tail > 0 ? 1 : 0)) * 3 * sl.T * sl.full.k;
 }
 
-void launch_back_project(hipStream_t s, const MeshDev& m, const uint8_t* records,
-                         const SeqLayout& sl, const double* ut, double* B0) {
-  const int nw = sl.nw_full + (sl.T_tail > 0 ? 1 : 0);
-  const int F = sl.nw_full * sl.T + sl.T_tail;
-  dim3 grid((m.n + BP_V - 1) / BP_V, nw);
-  prof::begin(s, DMC_KERNEL_BACK_PROJECT);
-  if (sl.full.precision == DMC_FP64)
-    hipLaunchKernelGGL(k_back_project<double>, grid, dim3(kBlock), 0, s, records, sl, m.n, 3 * F,
-                       m.dpos, ut, B0);
-  else
-    hipLaunchKernelGGL(k_back_project<float>, grid, dim3(kBlock), 0, s, records, sl, m.n, 3 * F,
-                       m.dpos, ut, B0);
-  prof::end(s, DMC_KERNEL_BACK_PROJECT);
-}
-
-void launch_rhs(hipStream_t s, const MeshDev& m, const uint8_t* records, const SeqLayout& sl,
-                const double* B0, double* b, double* bb) {
-  const int F = sl.nw_full * sl.T + sl.T_tail;
-  const int ncols = 3 * F;
-  // dense anchor values live right after b (the caller sizes b for both)
-  double* Ah = b + (size_t)m.n * ncols;
-  const size_t tot = (size_t)m.nc * ncols;
-  if (sl.full.precision == DMC_FP64)
-    hipLaunchKernelGGL(k_anchor_values<double>, dim3((tot + kBlock - 1) / kBlock), dim3(kBlock),
-                       0, s, records, sl, m.nc, ncols, Ah);
-  else
-    hipLaunchKernelGGL(k_anchor_values<float>, dim3((tot + kBlock - 1) / kBlock), dim3(kBlock), 0,
-                       s, records, sl, m.nc, ncols, Ah);
-  const dim3 grid = rhs_grid(m.n, ncols);
-  prof::begin(s, DMC_KERNEL_RHS);
-  hipLaunchKernelGGL(k_rhs, grid, dim3(kBlock), 0, s, m.d_rowptr, m.d_col, m.d_w64,
-                     m.laplacian == DMC_LAP_UNIFORM ? 1 : 0, m.d_slot, m.n, ncols, (int)grid.x, B0,
-                     Ah, b, bb);
-  prof::end(s, DMC_KERNEL_RHS);
-}
-
 // z = M^-1 r by the Cholesky factor and the r.z partials; with p_out the
 // solve writes straight into p_out (the first search direction p = z; z
 // itself is rewritten by every later application before it is read)
@@ -1257,6 +1358,20 @@ void launch_rhs_reduced(hipStream_t s, const MeshDev& m, int32_t nz, const doubl
   hipLaunchKernelGGL(k_rhs, grid, dim3(kBlock), 0, s, m.d_rowptr, m.d_col, m.d_w64,
                      m.laplacian == DMC_LAP_UNIFORM ? 1 : 0, m.d_slot, m.n, nz, (int)grid.x, Yd,
                      (const double*)nullptr, b, bb);
+  prof::end(s, DMC_KERNEL_RHS);
+}
+
+void launch_rhs_from_coefs(hipStream_t s, const MeshDev& m, const SeqLayout& sl,
+                           const double* Yd, const double* ut, const double* Ah, double* b,
+                           double* bb) {
+  const int nw = sl.nw_full + (sl.T_tail > 0 ? 1 : 0);
+  const int F = sl.nw_full * sl.T + sl.T_tail;
+  const dim3 grid(pad_xcd((m.n + CG_RB - 1) / CG_RB), nw);
+  auto kern = sl.full.k > 16 ? k_rhs_expand<32> : k_rhs_expand<16>;
+  prof::begin(s, DMC_KERNEL_RHS);
+  hipLaunchKernelGGL(kern, grid, dim3(kBlock), 0, s, m.d_rowptr, m.d_col, m.d_w64,
+                     m.laplacian == DMC_LAP_UNIFORM ? 1 : 0, m.d_slot, m.n, 3 * F,
+                     reduced_cols(sl), (int)grid.x, sl, Yd, ut, Ah, b, bb);
   prof::end(s, DMC_KERNEL_RHS);
 }
 
