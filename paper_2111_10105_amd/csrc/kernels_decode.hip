@@ -364,7 +364,9 @@ k_cg_init_reduce(const double* __restrict__ part, int nrb, int ncols,
 }
 
 // q = M p (CSR of L^T L + I_N^T I_N, by position), partial p.q per column.  A block
-// takes CG_RB rows and 64 columns (one per lane); its four wavefronts take
+// takes CG_RB rows and 64 columns (one per lane), row blocks in XCD runs as
+// in k_rhs (the rows of a row's two rings stay in its XCD's L2); its four
+// wavefronts take
 // every fourth row, so each lane has a short chain of rows, and their p.q
 // partials are added in wavefront order (deterministic).  The row's pattern
 // and values are the same for the whole wavefront (scalar loads).
@@ -381,7 +383,9 @@ k_cg_spmm(const int32_t* __restrict__ mrow, const int32_t* __restrict__ mcol,
   const int j = blockIdx.y * SP_COLS + lane;
   const bool jv = j < ncols;
   const double* pj = p + (jv ? j : 0);
-  const int r0 = blockIdx.x * CG_RB, r1 = min(n, r0 + CG_RB);
+  const int rb = xcd_row_block(gridDim.x);
+  const int r0 = rb * CG_RB, r1 = min(n, r0 + CG_RB);
+  if (r0 >= n) return;  // padding block
   double pq = 0.0;
   for (int i = r0 + wv; i < r1; i += NW) {
     const int e1 = mrow[i + 1];
@@ -405,52 +409,75 @@ k_cg_spmm(const int32_t* __restrict__ mrow, const int32_t* __restrict__ mcol,
     double v = sh[0][lane];
 #pragma unroll
     for (int u = 1; u < NW; ++u) v += sh[u][lane];
-    part[(size_t)blockIdx.x * ncols + j] = v;
+    part[(size_t)rb * ncols + j] = v;
   }
 }
 
 // Residual of a start x0: partial (b - M x0).(b - M x0) per column into the
-// first half of `part`, tiled as k_cg_spmm; with write_r, r = b - M x0 is also
-// written in place of b (each element is read and written by one thread).
+// first half of `part`; with write_r, r = b - M x0 is also written in place of
+// b (each element is read and written by one thread).  Tiled as k_cg_spmm
+// (row blocks in XCD runs, a wavefront's rows in a chain, the row's pattern
+// in scalar registers), with CPL adjacent columns per lane: CPL = 2 (an even
+// column count) reads each ring member's pair with one 16-byte load, which
+// halves the load instructions per byte and the pattern loads per column.
+// Each element's products are summed by entry index mod 4 as in k_cg_spmm.
+template <int CPL>
 __global__ void __launch_bounds__(kBlock)
 k_cg_residual(const int32_t* __restrict__ mrow, const int32_t* __restrict__ mcol,
               const double* __restrict__ mval, int n, int ncols, const double* __restrict__ x,
               double* b, int write_r, double* __restrict__ part) {
-  constexpr int NW = kBlock / 64;
-  __shared__ double sh[NW][SP_COLS];
+  typedef double dv __attribute__((ext_vector_type(CPL)));
+  constexpr int NW = kBlock / 64, BW = 64 * CPL;
+  __shared__ double sh[NW][BW];
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int j = blockIdx.y * SP_COLS + lane;
-  const bool jv = j < ncols;
+  const int j = blockIdx.y * BW + CPL * lane;
+  const bool jv = j < ncols;  // CPL divides ncols
   const double* xj = x + (jv ? j : 0);
-  const int r0 = blockIdx.x * CG_RB, r1 = min(n, r0 + CG_RB);
-  double rr = 0.0;
+  const int rb = xcd_row_block(gridDim.x);
+  const int r0 = rb * CG_RB, r1 = min(n, r0 + CG_RB);
+  if (r0 >= n) return;  // padding block
+  auto ld = [&](int c) { return *(const dv*)(xj + (size_t)c * ncols); };
+  dv rr = {};
   for (int i = r0 + wv; i < r1; i += NW) {
     const int e1 = mrow[i + 1];
     int e = mrow[i];
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    dv a0 = {}, a1 = {}, a2 = {}, a3 = {};
     for (; e + 4 <= e1; e += 4) {
-      a0 = fma(mval[e], xj[(size_t)mcol[e] * ncols], a0);
-      a1 = fma(mval[e + 1], xj[(size_t)mcol[e + 1] * ncols], a1);
-      a2 = fma(mval[e + 2], xj[(size_t)mcol[e + 2] * ncols], a2);
-      a3 = fma(mval[e + 3], xj[(size_t)mcol[e + 3] * ncols], a3);
+      const dv x0 = ld(mcol[e]), x1 = ld(mcol[e + 1]), x2 = ld(mcol[e + 2]), x3 = ld(mcol[e + 3]);
+#pragma unroll
+      for (int u = 0; u < CPL; ++u) {
+        a0[u] = fma(mval[e], x0[u], a0[u]);
+        a1[u] = fma(mval[e + 1], x1[u], a1[u]);
+        a2[u] = fma(mval[e + 2], x2[u], a2[u]);
+        a3[u] = fma(mval[e + 3], x3[u], a3[u]);
+      }
     }
-    for (; e < e1; ++e) a0 = fma(mval[e], xj[(size_t)mcol[e] * ncols], a0);
-    const double mx = (a0 + a1) + (a2 + a3);
+    for (; e < e1; ++e) {
+      const dv x0 = ld(mcol[e]);
+#pragma unroll
+      for (int u = 0; u < CPL; ++u) a0[u] = fma(mval[e], x0[u], a0[u]);
+    }
     if (jv) {
       const size_t at = (size_t)i * ncols + j;
-      const double rv = b[at] - mx;
-      if (write_r) b[at] = rv;
-      rr = fma(rv, rv, rr);
+      dv rv = *(const dv*)(b + at);
+#pragma unroll
+      for (int u = 0; u < CPL; ++u) {
+        rv[u] -= (a0[u] + a1[u]) + (a2[u] + a3[u]);
+        rr[u] = fma(rv[u], rv[u], rr[u]);
+      }
+      if (write_r) *(dv*)(b + at) = rv;
     }
   }
-  sh[wv][lane] = rr;
-  __syncthreads();
-  if (threadIdx.x < SP_COLS && jv) {
-    double v = sh[0][lane];
 #pragma unroll
-    for (int u = 1; u < NW; ++u) v += sh[u][lane];
-    part[(size_t)blockIdx.x * ncols + j] = v;
+  for (int u = 0; u < CPL; ++u) sh[wv][CPL * lane + u] = rr[u];
+  __syncthreads();
+  const int jj = blockIdx.y * BW + threadIdx.x;
+  if (threadIdx.x < BW && jj < ncols) {
+    double v = sh[0][threadIdx.x];
+#pragma unroll
+    for (int u = 1; u < NW; ++u) v += sh[u][threadIdx.x];
+    part[(size_t)rb * ncols + jj] = v;
   }
 }
 
@@ -1225,15 +1252,26 @@ void launch_cg_norms(hipStream_t s, const MeshDev& m, int32_t ncols, const CgBuf
                      s, cb.part, nrb, ncols, cb.bnorm2, cb.rz, cb.done, cb.resid);
 }
 
+// k_cg_residual with two columns per lane when the column count is even
+// (the vectors' rows then start at 16-byte boundaries), else one
+static void launch_residual(hipStream_t s, const MeshDev& m, int32_t ncols, const double* x,
+                            double* b, int write_r, double* part) {
+  const int nrbp = pad_xcd((int)cg_part_rows(m.n));
+  if (ncols % 2 == 0)
+    hipLaunchKernelGGL(k_cg_residual<2>, dim3(nrbp, (ncols + 127) / 128), dim3(kBlock), 0, s,
+                       m.m_rowptr, m.m_col, m.m_val, m.n, ncols, x, b, write_r, part);
+  else
+    hipLaunchKernelGGL(k_cg_residual<1>, dim3(nrbp, (ncols + 63) / 64), dim3(kBlock), 0, s,
+                       m.m_rowptr, m.m_col, m.m_val, m.n, ncols, x, b, write_r, part);
+}
+
 void launch_cg_warm_start(hipStream_t s, const MeshDev& m, int32_t ncols, const CgBuffers& cb,
                           double tol) {
   const int nrb = (int)cg_part_rows(m.n);
-  dim3 sgrid(nrb, (ncols + SP_COLS - 1) / SP_COLS);
   dim3 cgrid((ncols + RED_COLS - 1) / RED_COLS);
   launch_chol_solve(s, m.chol, ncols, cb.r, cb.x, cb.W, cb.Y, cb.U, cb.S);
   prof::begin(s, DMC_KERNEL_CG_SPMM);
-  hipLaunchKernelGGL(k_cg_residual, sgrid, dim3(kBlock), 0, s, m.m_rowptr, m.m_col, m.m_val, m.n,
-                     ncols, cb.x, cb.r, 0, cb.part);
+  launch_residual(s, m, ncols, cb.x, cb.r, 0, cb.part);
   prof::end(s, DMC_KERNEL_CG_SPMM);
   hipLaunchKernelGGL(k_cg_resid, cgrid, dim3(kBlock), 0, s, cb.part, nrb, ncols, cb.bnorm2,
                      cb.done, cb.resid, tol);
@@ -1241,10 +1279,8 @@ void launch_cg_warm_start(hipStream_t s, const MeshDev& m, int32_t ncols, const 
 
 void launch_cg_restart(hipStream_t s, const MeshDev& m, int32_t ncols, const CgBuffers& cb) {
   const int nrb = (int)cg_part_rows(m.n);
-  dim3 sgrid(nrb, (ncols + SP_COLS - 1) / SP_COLS);
   prof::begin(s, DMC_KERNEL_CG_SPMM);
-  hipLaunchKernelGGL(k_cg_residual, sgrid, dim3(kBlock), 0, s, m.m_rowptr, m.m_col, m.m_val, m.n,
-                     ncols, cb.x, cb.r, 1, cb.part);
+  launch_residual(s, m, ncols, cb.x, cb.r, 1, cb.part);
   prof::end(s, DMC_KERNEL_CG_SPMM);
   launch_precond_apply(s, m, ncols, cb, cb.p);
   hipLaunchKernelGGL(k_cg_rz_reduce, dim3((ncols + RED_COLS - 1) / RED_COLS), dim3(kBlock), 0, s,
@@ -1255,9 +1291,10 @@ void launch_cg_step_a(hipStream_t s, const MeshDev& m, int32_t ncols, const CgBu
                       int32_t precond, double tol, bool first) {
   const int nrb = (int)cg_part_rows(m.n);
   dim3 sgrid(nrb, (ncols + SP_COLS - 1) / SP_COLS);
+  const dim3 xgrid(pad_xcd(nrb), sgrid.y);  // k_cg_spmm
   dim3 cgrid((ncols + RED_COLS - 1) / RED_COLS);
   prof::begin(s, DMC_KERNEL_CG_SPMM);
-  hipLaunchKernelGGL(k_cg_spmm, sgrid, dim3(kBlock), 0, s, m.m_rowptr, m.m_col, m.m_val, m.n,
+  hipLaunchKernelGGL(k_cg_spmm, xgrid, dim3(kBlock), 0, s, m.m_rowptr, m.m_col, m.m_val, m.n,
                      ncols, cb.p, cb.q, cb.part);
   prof::end(s, DMC_KERNEL_CG_SPMM);
   hipLaunchKernelGGL(k_cg_alpha, cgrid, dim3(kBlock), 0, s, cb.part, nrb, ncols, cb.rz, cb.done,
