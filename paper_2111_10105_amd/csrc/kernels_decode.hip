@@ -52,17 +52,6 @@ __device__ inline const double* dict_of(const SeqLayout& sl, const double* ut, i
   return ut + (size_t)(w < sl.nw_full ? w : sl.nw_full) * 3 * sl.T * sl.full.k;
 }
 
-// Coefficient cr = c k + r of vertex i, dequantised from its packed row.
-template <typename Real>
-__device__ inline double coef_value(const uint8_t* rec, const RecordLayout& lay, int cr, int i) {
-  const SegEntry e = ((const SegEntry*)(rec + lay.off_rtab))[cr];
-  const uint32_t* seg = (const uint32_t*)(rec + lay.off_var) + e.word_off;
-  if (lay.coef_bits == 0) return (double)((const Real*)seg)[i];
-  const uint32_t bits = e.bits_mode & 0xffu;
-  if (bits == 0) return (double)e.lo;
-  return dequant(get_code(seg, (uint32_t)i, bits), (double)e.lo, (double)e.hi, (int)bits);
-}
-
 // Dictionary decoder: for windows [w0, w1) of one group in order (block =
 // group; wave v takes columns q = v, v + 4, ... of a window, lane = frame),
 // the dequantised dictionary from the column table and packed segments:
@@ -623,24 +612,44 @@ k_cg_pupdate(int n, int ncols, const double* __restrict__ beta, const double* __
   }
 }
 
-// X [n][3F] (row pos(i) for vertex i) -> frames [F][n][3]
+// X [n][3F] (row pos(i) for vertex i) -> frames [F][n][3].  Block = TF_V
+// vertices x TF_T frames: each vertex's 3 TF_T values are one contiguous run
+// of X (read with TF_U loads in flight per thread), held in LDS in the frames'
+// type, and written frame by frame as runs of 3 TF_V values.
+constexpr int TF_V = 32, TF_T = 64, TF_U = 8;
+
 template <typename Real>
 __global__ void __launch_bounds__(kBlock)
 k_to_frames(const double* __restrict__ X, const int32_t* __restrict__ pos, int n, int F,
             Real* __restrict__ out) {
-  __shared__ double tile[32][97];
-  const int i0 = blockIdx.x * 32, t0 = blockIdx.y * 32;
+  constexpr int RW = 3 * TF_T, LD = RW + 1;
+  __shared__ Real tile[TF_V * LD];
+  __shared__ int prow[TF_V];
+  const int i0 = blockIdx.x * TF_V, t0 = blockIdx.y * TF_T;
   const int ncols = 3 * F;
-  const int nv = min(32, n - i0), nt = min(32, F - t0);
-  for (int e = threadIdx.x; e < 32 * 96; e += kBlock) {
-    const int v = e / 96, j = e % 96;
-    if (v < nv && j < 3 * nt) tile[v][j] = X[(size_t)pos[i0 + v] * ncols + 3 * t0 + j];
+  const int nv = min(TF_V, n - i0), nt = min(TF_T, F - t0);
+  if (threadIdx.x < TF_V) prow[threadIdx.x] = threadIdx.x < nv ? pos[i0 + threadIdx.x] : 0;
+  __syncthreads();
+  for (int e0 = threadIdx.x; e0 < TF_V * RW; e0 += TF_U * kBlock) {
+    double v[TF_U];
+#pragma unroll
+    for (int u = 0; u < TF_U; ++u) {
+      const int e = e0 + u * kBlock, vv = e / RW, j = e % RW;
+      v[u] = e < TF_V * RW && vv < nv && j < 3 * nt
+                 ? X[(size_t)prow[vv] * ncols + 3 * t0 + j]
+                 : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < TF_U; ++u) {
+      const int e = e0 + u * kBlock;
+      if (e < TF_V * RW) tile[(e / RW) * LD + e % RW] = (Real)v[u];
+    }
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < 32 * 96; e += kBlock) {
-    const int t = e / 96, vc = e % 96;
-    const int v = vc / 3, c = vc % 3;
-    if (t < nt && v < nv) out[((size_t)(t0 + t) * n + i0 + v) * 3 + c] = (Real)tile[v][3 * t + c];
+  for (int e = threadIdx.x; e < TF_T * 3 * TF_V; e += kBlock) {
+    const int t = e / (3 * TF_V), vc = e % (3 * TF_V);
+    const int vv = vc / 3, c = vc % 3;
+    if (t < nt && vv < nv) out[((size_t)(t0 + t) * n + i0 + vv) * 3 + c] = tile[vv * LD + 3 * t + c];
   }
 }
 
@@ -657,15 +666,20 @@ __device__ inline int zoff(const SeqLayout& sl, int w) {
   return 3 * sl.full.k * (w < sl.nw_full ? w : sl.nw_full);
 }
 
-constexpr int CR_V = 32;  // vertices per block of k_coef_rows
+constexpr int CR_V = 64;  // vertices per block of k_coef_rows
+constexpr int CR_U = 4;   // codes in flight per thread
 
 // Yd[pos(i)][zoff(w) + c k + r] = Y^_wc[r][i] (dequantised coefficients, one
-// row per vertex in the decoder's row order)
+// row per vertex in the decoder's row order).  The window's row table is
+// staged in LDS first, so each code's load depends on no table load of its
+// own; consecutive threads read consecutive vertices of a row.
 template <typename Real>
 __global__ void __launch_bounds__(kBlock)
 k_coef_rows(const uint8_t* __restrict__ records, SeqLayout sl, int n, int nz,
             const int32_t* __restrict__ pos, double* __restrict__ Yd) {
   __shared__ double tile[CR_V * 97];  // [v][c k + r], 3k <= 96
+  __shared__ SegEntry tab[96];
+  __shared__ int prow[CR_V];
   const int w = blockIdx.y;
   const uint8_t* rec;
   int T, k, t0;
@@ -674,16 +688,41 @@ k_coef_rows(const uint8_t* __restrict__ records, SeqLayout sl, int n, int nz,
   const int i0 = blockIdx.x * CR_V;
   const int nv = min(CR_V, n - i0);
   const int ck = 3 * k;
-  for (int e = threadIdx.x; e < ck * CR_V; e += kBlock) {
-    const int cr = e / CR_V, v = e % CR_V;  // consecutive threads -> consecutive vertices
-    if (v >= nv) continue;
-    tile[v * 97 + cr] = coef_value<Real>(rec, lay, cr, i0 + v);
+  if (threadIdx.x < ck) tab[threadIdx.x] = ((const SegEntry*)(rec + lay.off_rtab))[threadIdx.x];
+  if (threadIdx.x < CR_V) prow[threadIdx.x] = threadIdx.x < nv ? pos[i0 + threadIdx.x] : 0;
+  __syncthreads();
+  const uint32_t* var = (const uint32_t*)(rec + lay.off_var);
+  const int tot = ck * CR_V;
+  for (int e0 = threadIdx.x; e0 < tot; e0 += CR_U * kBlock) {
+    double y[CR_U];
+#pragma unroll
+    for (int u = 0; u < CR_U; ++u) {
+      const int e = e0 + u * kBlock;
+      const int cr = e / CR_V, v = e % CR_V;  // consecutive threads -> consecutive vertices
+      y[u] = 0.0;
+      if (e < tot && v < nv) {
+        const SegEntry se = tab[cr];
+        const uint32_t* seg = var + se.word_off;
+        const uint32_t bits = se.bits_mode & 0xffu;
+        if (lay.coef_bits == 0)
+          y[u] = (double)((const Real*)seg)[i0 + v];
+        else
+          y[u] = bits ? dequant(get_code(seg, (uint32_t)(i0 + v), bits), (double)se.lo,
+                                (double)se.hi, (int)bits)
+                      : (double)se.lo;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < CR_U; ++u) {
+      const int e = e0 + u * kBlock;
+      if (e < tot) tile[(e % CR_V) * 97 + e / CR_V] = y[u];
+    }
   }
   __syncthreads();
   const int z0 = zoff(sl, w);
   for (int e = threadIdx.x; e < nv * ck; e += kBlock) {
     const int v = e / ck, cr = e % ck;
-    Yd[(size_t)pos[i0 + v] * nz + z0 + cr] = tile[v * 97 + cr];
+    Yd[(size_t)prow[v] * nz + z0 + cr] = tile[v * 97 + cr];
   }
 }
 
@@ -1357,7 +1396,7 @@ void launch_cg_step_b(hipStream_t s, const MeshDev& m, int32_t ncols, const CgBu
 void launch_to_frames(hipStream_t s, const MeshDev& m, const double* X, int32_t F,
                       int32_t precision, void* frames_out) {
   const int n = m.n;
-  dim3 grid((n + 31) / 32, (F + 31) / 32);
+  dim3 grid((n + TF_V - 1) / TF_V, (F + TF_T - 1) / TF_T);
   prof::begin(s, DMC_KERNEL_TO_FRAMES);
   if (precision == DMC_FP64)
     hipLaunchKernelGGL(k_to_frames<double>, grid, dim3(kBlock), 0, s, X, m.dpos, n, F,
