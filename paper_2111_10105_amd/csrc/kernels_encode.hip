@@ -151,18 +151,34 @@ k_autocorr(const In* __restrict__ frames, int n, int T, int nw, int P, Real* __r
       jj[q] = bi + rem;
     }
   }
-  for (int v0 = v_begin; v0 < v_end; v0 += AC_VT) {
+  // element (t, v, c) of a vertex tile -> tile[c][v][t] (zero padding); the
+  // next tile's loads are in flight in registers while the current one is
+  // multiplied
+  constexpr int PER = TP * 3 * AC_VT / (AC_WAVES * 64);
+  static_assert(TP * 3 * AC_VT % (AC_WAVES * 64) == 0, "whole elements per thread");
+  In nxt[PER];
+  auto load = [&](int v0) {
     const int nv = min(AC_VT, v_end - v0);
-    __syncthreads();
-    // stage: element (t, v, c) of the window -> tile[c][v][t]; zero padding
-    for (int e = threadIdx.x; e < TP * 3 * AC_VT; e += AC_WAVES * 64) {
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = threadIdx.x + u * AC_WAVES * 64;
       const int t = e / (3 * AC_VT), rem = e % (3 * AC_VT);
       const int v = rem / 3, c = rem % 3;
-      Real val = 0;
-      if (t < T && v < nv) val = (Real)base[(size_t)t * 3 * n + (size_t)(v0 + v) * 3 + c];
-      tile[(c * AC_VT + v) * LD + t] = val;
+      nxt[u] = (t < T && v < nv) ? base[(size_t)t * 3 * n + (size_t)(v0 + v) * 3 + c] : (In)0;
+    }
+  };
+  if (v_begin < v_end) load(v_begin);
+  for (int v0 = v_begin; v0 < v_end; v0 += AC_VT) {
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = threadIdx.x + u * AC_WAVES * 64;
+      const int t = e / (3 * AC_VT), rem = e % (3 * AC_VT);
+      const int v = rem / 3, c = rem % 3;
+      tile[(c * AC_VT + v) * LD + t] = (Real)nxt[u];
     }
     __syncthreads();
+    if (v0 + AC_VT < v_end) load(v0 + AC_VT);
     for (int q = 0; q < Tr::JPW; ++q) {
       if (jc[q] < 0) continue;
       const Real* tc = tile + jc[q] * AC_VT * LD;
@@ -265,17 +281,33 @@ k_autocorr_bf16(const float* __restrict__ frames, int n, int T, int nw, int P,
       jj[q] = bi + rem;
     }
   }
-  for (int v0 = v_begin; v0 < v_end; v0 += BF_VT) {
+  // the next tile's loads are in flight in registers while the current one
+  // is multiplied
+  constexpr int PER = TP * 3 * BF_VT / (AC_WAVES * 64);
+  static_assert(TP * 3 * BF_VT % (AC_WAVES * 64) == 0, "whole elements per thread");
+  float nxt[PER];
+  auto load = [&](int v0) {
     const int nv = min(BF_VT, v_end - v0);
-    __syncthreads();
-    for (int e = threadIdx.x; e < TP * 3 * BF_VT; e += AC_WAVES * 64) {
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = threadIdx.x + u * AC_WAVES * 64;
       const int t = e / (3 * BF_VT), rem = e % (3 * BF_VT);
       const int v = rem / 3, c = rem % 3;
-      float val = 0.f;
-      if (t < T && v < nv) val = base[(size_t)t * 3 * n + (size_t)(v0 + v) * 3 + c];
-      tile[(c * TP + t) * BF_LD + v] = (__bf16)val;
+      nxt[u] = (t < T && v < nv) ? base[(size_t)t * 3 * n + (size_t)(v0 + v) * 3 + c] : 0.f;
+    }
+  };
+  if (v_begin < v_end) load(v_begin);
+  for (int v0 = v_begin; v0 < v_end; v0 += BF_VT) {
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = threadIdx.x + u * AC_WAVES * 64;
+      const int t = e / (3 * BF_VT), rem = e % (3 * BF_VT);
+      const int v = rem / 3, c = rem % 3;
+      tile[(c * TP + t) * BF_LD + v] = (__bf16)nxt[u];
     }
     __syncthreads();
+    if (v0 + BF_VT < v_end) load(v0 + BF_VT);
     for (int q = 0; q < JPW; ++q) {
       if (jc[q] < 0) continue;
       const __bf16* tc = tile + jc[q] * TP * BF_LD;
