@@ -352,6 +352,10 @@ constexpr int PJ_V = 64;  // vertices per projection block
 // of the two-kernel path.
 // ---------------------------------------------------------------------------
 constexpr int PF_TT = 8;  // frames per delta tile
+// ring members held in registers (valence 6 is the rule on these meshes: a
+// larger pad would add gathers of the vertex itself; longer rings finish
+// from memory)
+constexpr int PF_DMAX = 6;
 
 template <typename Real, int KMAX>
 __global__ void __launch_bounds__(kBlock)
@@ -375,9 +379,9 @@ k_project_frames(const int32_t* __restrict__ rowptr, const int32_t* __restrict__
     wi = wdeg[i];
   }
   const int deg = e1 - e0;
-  int nb[DMAX];
+  int nb[PF_DMAX];
 #pragma unroll
-  for (int d = 0; d < DMAX; ++d) nb[d] = d < deg ? col[e0 + d] : (valid ? i : 0);
+  for (int d = 0; d < PF_DMAX; ++d) nb[d] = d < deg ? col[e0 + d] : (valid ? i : 0);
   const Real* fw = frames + (size_t)w * T * 3 * n;
   const size_t fs = (size_t)3 * n;
   // delta coordinates of tile `tile` into buffer `buf` (frames wave, wave + 4)
@@ -388,18 +392,18 @@ k_project_frames(const int32_t* __restrict__ rowptr, const int32_t* __restrict__
       Xyz<Real> o{(Real)0, (Real)0, (Real)0};
       if (valid && t < T) {
         const Xyz<Real>* fr = (const Xyz<Real>*)(fw + (size_t)t * fs);
-        Xyz<Real> v[DMAX];
+        Xyz<Real> v[PF_DMAX];
 #pragma unroll
-        for (int d = 0; d < DMAX; ++d) v[d] = fr[nb[d]];
+        for (int d = 0; d < PF_DMAX; ++d) v[d] = fr[nb[d]];
         double sx = 0.0, sy = 0.0, sz = 0.0;
 #pragma unroll
-        for (int d = 0; d < DMAX; ++d)
+        for (int d = 0; d < PF_DMAX; ++d)
           if (d < deg) {
             sx += (double)v[d].x;
             sy += (double)v[d].y;
             sz += (double)v[d].z;
           }
-        for (int e = e0 + DMAX; e < e1; ++e) {
+        for (int e = e0 + PF_DMAX; e < e1; ++e) {
           const Xyz<Real> u = fr[col[e]];
           sx += (double)u.x;
           sy += (double)u.y;
