@@ -1114,6 +1114,8 @@ dmc_status dmc_mesh_create(dmc_ctx ctx, int32_t n, int32_t n_tris, const int32_t
   dv.d_slot = (const int32_t*)up(d_slot.data(), n * 4);
   dv.d_anchors = (const int32_t*)up(d_anchors.data(), (size_t)n_anchors * 4);
   dv.m_rowptr = (const int32_t*)up(pm_rowptr.data(), pm_rowptr.size() * 4);
+  pm_col.resize(pm_col.size() + dmc::kMatPad, 0);
+  pm_val.resize(pm_val.size() + dmc::kMatPad, 0.0);
   dv.m_col = (const int32_t*)up(pm_col.data(), pm_col.size() * 4);
   dv.m_val = (const double*)up(pm_val.data(), pm_val.size() * 8);
   dv.m_dinv = (const double*)up(pm_dinv.data(), n * 8);

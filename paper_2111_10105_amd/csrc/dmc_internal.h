@@ -17,6 +17,10 @@ constexpr int kBlock = 256;
 // XCDs of an MI355X: the dispatcher deals consecutive workgroups of a launch
 // to them in turn (workgroup b runs on XCD b mod 8), each with its own L2.
 constexpr int kXcds = 8;
+// Entries past the end of the device copies of M's column and value arrays
+// (column 0, value 0), so a kernel may read the first entries of a row's
+// pattern without testing them against the row's end.
+constexpr int kMatPad = 32;
 inline int pad_xcd(int blocks) { return (blocks + kXcds - 1) / kXcds * kXcds; }
 constexpr size_t kAlign = 256;
 

@@ -360,6 +360,8 @@ k_cg_init_reduce(const double* __restrict__ part, int nrb, int ncols,
 // partials are added in wavefront order (deterministic).  The row's pattern
 // and values are the same for the whole wavefront (scalar loads).
 constexpr int SP_COLS = 64;
+constexpr int SP_ROW = 20;  // gathers of a row issued together (M's rows: 19 at valence 6)
+static_assert(SP_ROW <= kMatPad, "a row's first SP_ROW entries lie inside the padded arrays");
 
 __global__ void __launch_bounds__(kBlock)
 k_cg_spmm(const int32_t* __restrict__ mrow, const int32_t* __restrict__ mcol,
@@ -377,18 +379,29 @@ k_cg_spmm(const int32_t* __restrict__ mrow, const int32_t* __restrict__ mcol,
   if (r0 >= n) return;  // padding block
   double pq = 0.0;
   for (int i = r0 + wv; i < r1; i += NW) {
-    const int e1 = mrow[i + 1];
-    int e = mrow[i];
-    // four independent partial sums keep several row loads in flight
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    for (; e + 4 <= e1; e += 4) {
-      a0 = fma(mval[e], pj[(size_t)mcol[e] * ncols], a0);
-      a1 = fma(mval[e + 1], pj[(size_t)mcol[e + 1] * ncols], a1);
-      a2 = fma(mval[e + 2], pj[(size_t)mcol[e + 2] * ncols], a2);
-      a3 = fma(mval[e + 3], pj[(size_t)mcol[e + 3] * ncols], a3);
+    const int e0 = mrow[i], e1 = mrow[i + 1], len = e1 - e0, full = len & ~3;
+    // the row's first SP_ROW gathers are issued before any product; entries
+    // in groups of four go to a[e mod 4], the remainder to a[0] (a chained
+    // four-way sum); indices and weights are read without bounds tests (the
+    // arrays carry kMatPad entries past their end)
+    int cx[SP_ROW];
+    double wx[SP_ROW], x[SP_ROW];
+#pragma unroll
+    for (int h = 0; h < SP_ROW; ++h) {
+      cx[h] = mcol[e0 + h];
+      wx[h] = mval[e0 + h];
     }
-    for (; e < e1; ++e) a0 = fma(mval[e], pj[(size_t)mcol[e] * ncols], a0);
-    const double acc = (a0 + a1) + (a2 + a3);
+#pragma unroll
+    for (int h = 0; h < SP_ROW; ++h) x[h] = h < len ? pj[(size_t)cx[h] * ncols] : 0.0;
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int h = 0; h < SP_ROW; ++h)
+      if (h < len) a[h < full ? (h & 3) : 0] = fma(wx[h], x[h], a[h < full ? (h & 3) : 0]);
+    for (int h = SP_ROW; h < len; ++h) {  // rows longer than SP_ROW
+      const int q = h < full ? (h & 3) : 0;
+      a[q] = fma(mval[e0 + h], pj[(size_t)mcol[e0 + h] * ncols], a[q]);
+    }
+    const double acc = (a[0] + a[1]) + (a[2] + a[3]);
     if (jv) q[(size_t)i * ncols + j] = acc;
     pq = fma(pj[(size_t)i * ncols], acc, pq);
   }
@@ -410,6 +423,9 @@ k_cg_spmm(const int32_t* __restrict__ mrow, const int32_t* __restrict__ mcol,
 // column count) reads each ring member's pair with one 16-byte load, which
 // halves the load instructions per byte and the pattern loads per column.
 // Each element's products are summed by entry index mod 4 as in k_cg_spmm.
+constexpr int RS_ROW = 20;  // gathers of a row issued together (M's rows: 19 at valence 6)
+static_assert(RS_ROW <= kMatPad, "a row's first RS_ROW entries lie inside the padded arrays");
+
 template <int CPL>
 __global__ void __launch_bounds__(kBlock)
 k_cg_residual(const int32_t* __restrict__ mrow, const int32_t* __restrict__ mcol,
@@ -429,27 +445,43 @@ k_cg_residual(const int32_t* __restrict__ mrow, const int32_t* __restrict__ mcol
   auto ld = [&](int c) { return *(const dv*)(xj + (size_t)c * ncols); };
   dv rr = {};
   for (int i = r0 + wv; i < r1; i += NW) {
-    const int e1 = mrow[i + 1];
-    int e = mrow[i];
-    dv a0 = {}, a1 = {}, a2 = {}, a3 = {};
-    for (; e + 4 <= e1; e += 4) {
-      const dv x0 = ld(mcol[e]), x1 = ld(mcol[e + 1]), x2 = ld(mcol[e + 2]), x3 = ld(mcol[e + 3]);
+    const int e0 = mrow[i], e1 = mrow[i + 1], len = e1 - e0, full = len & ~3;
+    // the row's first RS_ROW gathers and its b value are all issued before
+    // any product (the entries in groups of four go to a[e mod 4], the
+    // remainder to a[0], the order of a chained four-way sum)
+    const size_t at = (size_t)i * ncols + (jv ? j : 0);
+    const dv bv = *(const dv*)(b + at);
+    // indices and weights read without bounds tests (the arrays carry
+    // kMatPad entries past their end)
+    int cx[RS_ROW];
+    double wx[RS_ROW];
 #pragma unroll
-      for (int u = 0; u < CPL; ++u) {
-        a0[u] = fma(mval[e], x0[u], a0[u]);
-        a1[u] = fma(mval[e + 1], x1[u], a1[u]);
-        a2[u] = fma(mval[e + 2], x2[u], a2[u]);
-        a3[u] = fma(mval[e + 3], x3[u], a3[u]);
+    for (int h = 0; h < RS_ROW; ++h) {
+      cx[h] = mcol[e0 + h];
+      wx[h] = mval[e0 + h];
+    }
+    dv x[RS_ROW];
+#pragma unroll
+    for (int h = 0; h < RS_ROW; ++h) x[h] = h < len ? ld(cx[h]) : dv{};
+    dv a[4] = {{}, {}, {}, {}};
+#pragma unroll
+    for (int h = 0; h < RS_ROW; ++h) {
+      if (h < len) {
+        const int q = h < full ? (h & 3) : 0;
+        const double wt = wx[h];
+#pragma unroll
+        for (int u = 0; u < CPL; ++u) a[q][u] = fma(wt, x[h][u], a[q][u]);
       }
     }
-    for (; e < e1; ++e) {
-      const dv x0 = ld(mcol[e]);
+    for (int h = RS_ROW; h < len; ++h) {  // rows longer than RS_ROW
+      const int q = h < full ? (h & 3) : 0;
+      const dv x0 = ld(mcol[e0 + h]);
 #pragma unroll
-      for (int u = 0; u < CPL; ++u) a0[u] = fma(mval[e], x0[u], a0[u]);
+      for (int u = 0; u < CPL; ++u) a[q][u] = fma(mval[e0 + h], x0[u], a[q][u]);
     }
+    const dv a0 = a[0], a1 = a[1], a2 = a[2], a3 = a[3];
     if (jv) {
-      const size_t at = (size_t)i * ncols + j;
-      dv rv = *(const dv*)(b + at);
+      dv rv = bv;
 #pragma unroll
       for (int u = 0; u < CPL; ++u) {
         rv[u] -= (a0[u] + a1[u]) + (a2[u] + a3[u]);
