@@ -6,40 +6,56 @@
 #include <omp.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
+#include <memory>
 #include <numeric>
 
 namespace dmc {
 namespace {
-
-struct NdNode {
-  int32_t begin = -1, end = -1, parent = -1;
-};
 
 // Recursive bisection of a graph by breadth-first level sets: the `thick`
 // consecutive levels around the one that splits the vertices in half
 // (counted from a pseudo-peripheral vertex) are the separator; it is
 // numbered after both halves.  On the graph of M itself one level separates;
 // on the mesh adjacency C, whose square is M's pattern, two do (vertices
-// three or more levels apart are not coupled in M).
+// three or more levels apart are not coupled in M).  The two halves of the
+// top kTaskDepth levels are ordered by parallel tasks, each into its own
+// segment of the ordering (left half, right half, separator, as in the serial
+// order); a task touches the marks of its own vertices only, and reads the
+// tags of other vertices, which never carry its own tag.
+struct NdOut {
+  std::vector<int32_t> order;                      // this subtree's vertices in order
+  std::vector<std::pair<int32_t, int32_t>> nodes;  // its dissection nodes, ranges in `order`
+};
+
 class Dissector {
  public:
-  Dissector(const HostCsr& G, int32_t leaf, int32_t thick)
-      : G_(G), leaf_(std::max(leaf, 2)), thick_(thick), tag_(G.n, 0), seen_(G.n, 0),
-        lev_(G.n, 0) {}
+  static constexpr int kTaskDepth = 6;
 
-  void run(std::vector<int32_t>& order, std::vector<NdNode>& nodes) {
+  Dissector(const HostCsr& G, int32_t leaf, int32_t thick)
+      : G_(G), leaf_(std::max(leaf, 2)), thick_(thick), tag_(new std::atomic<int32_t>[G.n]),
+        seen_(G.n, 0), lev_(G.n, 0) {
+    for (int32_t v = 0; v < G.n; ++v) tag_[v].store(0, std::memory_order_relaxed);
+  }
+
+  // the ordering and the (begin, end) ranges of the dissection nodes in it
+  void run(std::vector<int32_t>& order, std::vector<std::pair<int32_t, int32_t>>& nodes) {
     std::vector<int32_t> all(G_.n);
     std::iota(all.begin(), all.end(), 0);
-    order_.reserve(G_.n);
-    rec(all, -1);
-    order.swap(order_);
-    nodes.swap(nodes_);
+    NdOut out;
+#pragma omp parallel
+#pragma omp single
+    rec(all, out, 0);
+    order.swap(out.order);
+    nodes.swap(out.nodes);
   }
 
  private:
-  void bfs(int32_t s, int32_t member, std::vector<int32_t>& vis) {
-    const int32_t id = ++bfs_id_;
+  int32_t tag(int32_t v) const { return tag_[v].load(std::memory_order_relaxed); }
+
+  void bfs(int32_t s, int32_t member, std::vector<int32_t>& vis, int32_t& id) {
+    id = bfs_id_.fetch_add(1, std::memory_order_relaxed) + 1;
     vis.clear();
     vis.push_back(s);
     seen_[s] = id;
@@ -48,7 +64,7 @@ class Dissector {
       const int32_t u = vis[h];
       for (int32_t e = G_.rowptr[u]; e < G_.rowptr[u + 1]; ++e) {
         const int32_t v = G_.col[e];
-        if (v == u || tag_[v] != member || seen_[v] == id) continue;
+        if (v == u || tag(v) != member || seen_[v] == id) continue;
         seen_[v] = id;
         lev_[v] = lev_[u] + 1;
         vis.push_back(v);
@@ -56,26 +72,41 @@ class Dissector {
     }
   }
 
-  void make_leaf(const std::vector<int32_t>& S, int32_t parent) {
-    NdNode nd;
-    nd.begin = (int32_t)order_.size();
-    order_.insert(order_.end(), S.begin(), S.end());
-    nd.end = (int32_t)order_.size();
-    nd.parent = parent;
-    nodes_.push_back(nd);
+  static void leaf_of(const std::vector<int32_t>& S, NdOut& out) {
+    out.nodes.emplace_back((int32_t)out.order.size(), (int32_t)(out.order.size() + S.size()));
+    out.order.insert(out.order.end(), S.begin(), S.end());
   }
 
-  void rec(std::vector<int32_t>& S, int32_t parent) {
+  // the orderings of two independent vertex sets, X's before Y's, appended
+  void pair(std::vector<int32_t>& X, std::vector<int32_t>& Y, NdOut& out, int depth) {
+    NdOut ox, oy;
+    if (depth < kTaskDepth) {
+#pragma omp task shared(X, ox)
+      rec(X, ox, depth + 1);
+      rec(Y, oy, depth + 1);
+#pragma omp taskwait
+    } else {
+      rec(X, ox, depth + 1);
+      rec(Y, oy, depth + 1);
+    }
+    for (NdOut* o : {&ox, &oy}) {
+      const int32_t base = (int32_t)out.order.size();
+      for (const auto& nd : o->nodes) out.nodes.emplace_back(base + nd.first, base + nd.second);
+      out.order.insert(out.order.end(), o->order.begin(), o->order.end());
+    }
+  }
+
+  void rec(std::vector<int32_t>& S, NdOut& out, int depth) {
     if ((int32_t)S.size() <= leaf_) {
-      make_leaf(S, parent);
+      leaf_of(S, out);
       return;
     }
-    const int32_t member = ++stamp_;
-    for (int32_t v : S) tag_[v] = member;
+    const int32_t member = stamp_.fetch_add(1, std::memory_order_relaxed) + 1;
+    for (int32_t v : S) tag_[v].store(member, std::memory_order_relaxed);
     std::vector<int32_t> vis;
-    bfs(S[0], member, vis);
+    int32_t id = 0;
+    bfs(S[0], member, vis, id);
     if (vis.size() < S.size()) {  // not connected: recurse per component
-      const int32_t id = bfs_id_;
       std::vector<int32_t> rest;
       rest.reserve(S.size() - vis.size());
       for (int32_t v : S)
@@ -83,20 +114,19 @@ class Dissector {
       std::vector<int32_t> comp(vis);
       S.clear();
       S.shrink_to_fit();
-      rec(comp, parent);
-      rec(rest, parent);
+      pair(comp, rest, out, depth);
       return;
     }
     int32_t u = vis.back();
     for (int it = 0; it < 2; ++it) {
-      bfs(u, member, vis);
+      bfs(u, member, vis, id);
       if (vis.back() == u) break;
       u = vis.back();
     }
-    bfs(u, member, vis);
+    bfs(u, member, vis, id);
     const int32_t maxl = lev_[vis.back()];
     if (maxl < thick_ + 1) {
-      make_leaf(S, parent);
+      leaf_of(S, out);
       return;
     }
     std::vector<int32_t> cnt(maxl + 1, 0);
@@ -119,21 +149,16 @@ class Dissector {
     }
     S.clear();
     S.shrink_to_fit();
-    const int32_t me = (int32_t)nodes_.size();
-    nodes_.push_back(NdNode{-1, -1, parent});
-    rec(A, me);
-    rec(B, me);
-    nodes_[me].begin = (int32_t)order_.size();
-    order_.insert(order_.end(), Sep.begin(), Sep.end());
-    nodes_[me].end = (int32_t)order_.size();
+    pair(A, B, out, depth);
+    out.nodes.emplace_back((int32_t)out.order.size(), (int32_t)(out.order.size() + Sep.size()));
+    out.order.insert(out.order.end(), Sep.begin(), Sep.end());
   }
 
   const HostCsr& G_;
   int32_t leaf_, thick_;
-  std::vector<int32_t> tag_, seen_, lev_;
-  int32_t stamp_ = 0, bfs_id_ = 0;
-  std::vector<int32_t> order_;
-  std::vector<NdNode> nodes_;
+  std::unique_ptr<std::atomic<int32_t>[]> tag_;
+  std::vector<int32_t> seen_, lev_;
+  std::atomic<int32_t> stamp_{0}, bfs_id_{0};
 };
 
 struct Segment {
@@ -147,48 +172,61 @@ bool build_cholesky_symbolic(const HostCsr& M, int32_t leaf, CholFactor& f, std:
   const int32_t n = M.n;
   f = CholFactor();
   f.n = n;
-  std::vector<NdNode> nodes;
+  std::vector<std::pair<int32_t, int32_t>> nodes;  // (begin, end) in the ordering
   {
     Dissector dis(adjacency ? *adjacency : M, leaf, adjacency ? 2 : 1);
     dis.run(f.perm, nodes);
   }
   std::vector<int32_t> iperm(n);
   for (int32_t p = 0; p < n; ++p) iperm[f.perm[p]] = p;
-  std::sort(nodes.begin(), nodes.end(),
-            [](const NdNode& x, const NdNode& y) { return x.begin < y.begin; });
+  std::sort(nodes.begin(), nodes.end());
 
-  // lower triangle of P M P^T: by column (rows >= j, with values) and by row
+  // lower triangle of P M P^T: by column (rows >= j, with values) and by row.
+  // M's pattern is symmetric, so column j's rows are the neighbours u of
+  // vertex perm[j] with iperm[u] >= j, taken in increasing u (the order a
+  // scan of M's rows gives), each with its value from row u; row i's columns
+  // are the entries of vertex perm[i]'s row with iperm <= i, in row order.
+  // Counts, then entries, both by rows and columns in parallel.
   std::vector<int32_t>& acol_ptr = f.acol_ptr;
   acol_ptr.assign(n + 1, 0);
   std::vector<int32_t> arow_ptr(n + 1, 0);
-  for (int32_t u = 0; u < n; ++u)
-    for (int32_t e = M.rowptr[u]; e < M.rowptr[u + 1]; ++e) {
-      const int32_t i = iperm[u], j = iperm[M.col[e]];
-      if (i >= j) {
-        acol_ptr[j + 1]++;
-        arow_ptr[i + 1]++;
-      }
+#pragma omp parallel for schedule(static, 1024)
+  for (int32_t j = 0; j < n; ++j) {
+    const int32_t v = f.perm[j];
+    int32_t nc = 0, nr = 0;
+    for (int32_t e = M.rowptr[v]; e < M.rowptr[v + 1]; ++e) {
+      const int32_t q = iperm[M.col[e]];
+      nc += q >= j;
+      nr += q <= j;
     }
+    acol_ptr[j + 1] = nc;
+    arow_ptr[j + 1] = nr;
+  }
   for (int32_t j = 0; j < n; ++j) {
     acol_ptr[j + 1] += acol_ptr[j];
     arow_ptr[j + 1] += arow_ptr[j];
   }
   std::vector<int32_t>& acol_row = f.acol_row;
   std::vector<double>& acol_val = f.acol_val;
-  acol_row.assign(acol_ptr[n], 0);
-  acol_val.assign(acol_ptr[n], 0.0);
+  acol_row.resize(acol_ptr[n]);
+  acol_val.resize(acol_ptr[n]);
   std::vector<int32_t> arow_col(arow_ptr[n]);
-  {
-    std::vector<int32_t> cf(acol_ptr.begin(), acol_ptr.end() - 1), rf(arow_ptr.begin(), arow_ptr.end() - 1);
-    for (int32_t u = 0; u < n; ++u)
-      for (int32_t e = M.rowptr[u]; e < M.rowptr[u + 1]; ++e) {
-        const int32_t i = iperm[u], j = iperm[M.col[e]];
-        if (i >= j) {
-          acol_row[cf[j]] = i;
-          acol_val[cf[j]++] = M.val[e];
-          arow_col[rf[i]++] = j;
-        }
+#pragma omp parallel for schedule(static, 1024)
+  for (int32_t j = 0; j < n; ++j) {
+    const int32_t v = f.perm[j];
+    int32_t oc = acol_ptr[j], orr = arow_ptr[j];
+    for (int32_t e = M.rowptr[v]; e < M.rowptr[v + 1]; ++e) {
+      const int32_t u = M.col[e], q = iperm[u];
+      if (q <= j) arow_col[orr++] = q;
+      if (q >= j) {
+        // M[u][v] from row u (sorted columns)
+        const int32_t* c0 = M.col.data() + M.rowptr[u];
+        const int32_t* c1 = M.col.data() + M.rowptr[u + 1];
+        const int32_t* at = std::lower_bound(c0, c1, v);
+        acol_row[oc] = q;
+        acol_val[oc++] = M.val[at - M.col.data()];
       }
+    }
   }
   // elimination tree (Liu, with path compression)
   std::vector<int32_t> parent(n, -1), anc(n, -1);
@@ -208,17 +246,23 @@ bool build_cholesky_symbolic(const HostCsr& M, int32_t leaf, CholFactor& f, std:
     }
   // nonzeros of the exact factor: column counts by row subtrees (each row i
   // of L is the union of the etree paths from the columns of row i of A)
-  std::vector<int32_t> mark(n, -1);
+  // (rows in parallel, each thread with its own marks)
   int64_t below = 0;
-  for (int32_t i = 0; i < n; ++i) {
-    mark[i] = i;
-    for (int32_t e = arow_ptr[i]; e < arow_ptr[i + 1]; ++e)
-      for (int32_t r = arow_col[e]; mark[r] != i; r = parent[r]) {
-        ++below;
-        mark[r] = i;
-      }
+#pragma omp parallel reduction(+ : below)
+  {
+    std::vector<int32_t> mk(n, -1);
+#pragma omp for schedule(static, 1024)
+    for (int32_t i = 0; i < n; ++i) {
+      mk[i] = i;
+      for (int32_t e = arow_ptr[i]; e < arow_ptr[i + 1]; ++e)
+        for (int32_t r = arow_col[e]; mk[r] != i; r = parent[r]) {
+          ++below;
+          mk[r] = i;
+        }
+    }
   }
   f.nnz_exact = (int64_t)n + below;
+  std::vector<int32_t> mark(n, -1);
 
   // supernodes = dissection nodes; their row structures, bottom up: the rows
   // of s below its columns are those of A in its columns and those of its
@@ -227,7 +271,7 @@ bool build_cholesky_symbolic(const HostCsr& M, int32_t leaf, CholFactor& f, std:
   const int32_t ns = (int32_t)nodes.size();
   f.nsuper = ns;
   f.sn_start.resize(ns + 1);
-  for (int32_t s = 0; s < ns; ++s) f.sn_start[s] = nodes[s].begin;
+  for (int32_t s = 0; s < ns; ++s) f.sn_start[s] = nodes[s].first;
   f.sn_start[ns] = n;
   std::vector<int32_t> sn_of(n);
   for (int32_t s = 0; s < ns; ++s)
