@@ -774,7 +774,7 @@ k_coef_rows(const uint8_t* __restrict__ records, SeqLayout sl, int n, int nz,
 //     k_rhs);
 //  3. the expansion on the FP64 matrix cores: a wavefront takes a 16-frame
 //     tile and a run of 16-row tiles (the dictionary operands of its frames
-//     stay in registers), puts the three coordinates' results of 8 rows at
+//     stay in registers), puts the three coordinates' results of 4 rows at
 //     a time into its own LDS stage in b's column order, and writes them
 //     out as contiguous runs.
 // With bb given, the block's b.b partial per column (k_rhs's row blocks),
@@ -791,7 +791,7 @@ k_rhs_expand(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col
   constexpr int ZST = 3 * KM + 1;  // row stride of zs (odd: rows on different banks)
   constexpr int NW = kBlock / 64;
   __shared__ double zs[CG_RB * ZST];           // [v][c k + r]
-  __shared__ double stage[NW][8 * 48];         // per wave: 8 rows x (16 frames x 3)
+  __shared__ double stage[NW][4 * 48];         // per wave: 4 rows x (16 frames x 3)
   __shared__ int rcol[CG_RB][RX_RING];
   __shared__ double rwt[CG_RB][RX_RING];
   __shared__ int rlen[CG_RB + 1];
@@ -911,22 +911,19 @@ k_rhs_expand(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col
           if (lg == 0) sq[rt][c][t] = x;
         }
       }
-      // rows 4 q + lg in two halves of eight rows: stage in b's column order
+      // rows 4 q + lg, four at a time (one q): stage in b's column order
       // (3 t + c), then contiguous runs of 3 nt values per row
 #pragma unroll
-      for (int half = 0; half < 2; ++half) {
+      for (int q = 0; q < 4; ++q) {
 #pragma unroll
-        for (int qq = 0; qq < 2; ++qq)
-#pragma unroll
-          for (int c = 0; c < 3; ++c) st[(4 * qq + lg) * 48 + 3 * l16 + c] = acc[c][2 * half + qq];
+        for (int c = 0; c < 3; ++c) st[lg * 48 + 3 * l16 + c] = acc[c][q];
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        for (int e = lane; e < 8 * 48; e += 64) {
+        for (int e = lane; e < 4 * 48; e += 64) {
           const int vr = e / 48, cc = e % 48;
-          // staged row vr is tile row 8 half + vr: lanes with q = 2 half +
-          // vr / 4 and l/16 = vr % 4 wrote it
-          const int v = 16 * rt + 4 * (2 * half + vr / 4) + vr % 4;
+          // staged row vr is tile row 4 q + vr (lanes with l/16 = vr wrote it)
+          const int v = 16 * rt + 4 * q + vr;
           if (v < nr && cc < 3 * nt)
             b[(size_t)(r0 + v) * ncols + 3 * (t0 + 16 * tt) + cc] = st[e];
         }

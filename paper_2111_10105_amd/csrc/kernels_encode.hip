@@ -960,7 +960,7 @@ static void project_impl(hipStream_t s, const MeshDev& m, const void* frames, in
   // words of a row at its widest, spread so that a block writes a few per thread
   const uint32_t wmax = seg_words((uint32_t)n, lay.coef_bits > 0 ? lay.coef_bits : 0,
                                   (uint32_t)sizeof(Real));
-  const int chunks = std::max(1, std::min(64, (int)((wmax + 4 * kBlock - 1) / (4 * kBlock))));
+  const int chunks = std::max(1, std::min(64, (int)((wmax + 16 * kBlock - 1) / (16 * kBlock))));
   hipLaunchKernelGGL(k_quantise_pack<Real>, dim3(chunks, 3 * k, nw), dim3(kBlock), 0, s,
                      (const Real*)Y, n, k, lay, records, rec_bytes);
   prof::end(s, DMC_KERNEL_QUANTISE);
