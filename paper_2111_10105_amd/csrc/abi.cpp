@@ -1796,6 +1796,7 @@ struct BatchSeq {
   int32_t stats_off = 0;  // first window in the batch's stats array
   int P = 0;              // tuned launch shape
   int branch = 0;         // graph branch the sequence's kernels run on
+  int cls[2] = {-1, -1};  // orthogonal-iteration classes of its full windows and tail
 };
 
 struct dmc_batch_s {
@@ -1809,9 +1810,11 @@ struct dmc_batch_s {
   hipStream_t stream = nullptr;  // private stream the graph is captured on and replayed on
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   // capture only: one stream per branch, fork and join events of the two
-  // per-sequence phases (before and after the orthogonal iterations)
-  std::vector<hipStream_t> br;
-  std::vector<hipEvent_t> ev_fork, ev_join;
+  // per-sequence phases (before and after the orthogonal iterations); one
+  // stream and end event per orthogonal-iteration class
+  std::vector<hipStream_t> br, cs;
+  std::vector<hipEvent_t> ev_fork, ev_join, ev_cls;
+  std::vector<int> order2;  // sequences in the order of the second phase
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
@@ -1863,17 +1866,27 @@ hipError_t batch_enqueue(dmc_batch b, hipStream_t s) {
                            q.sl.T_tail, 1, b->precision, shared, (double*)(b->buf + q.o_Rt));
   }
   if ((e = batch_join(b, s, 0)) != hipSuccess) return e;
-  for (size_t c = 0; c < b->cls_n.size(); ++c)
-    dmc::launch_oi_batch(s, b->cls_tmax[c], b->cls_kr[c], b->precision,
+  if (!b->cs.empty() && (e = hipEventRecord(b->ev_fork[2], s)) != hipSuccess) return e;
+  // the classes run side by side (each on its own stream when there are
+  // branches); a sequence's second phase waits for its own classes only
+  for (size_t c = 0; c < b->cls_n.size(); ++c) {
+    hipStream_t sc = b->cs.empty() ? s : b->cs[c];
+    if (!b->cs.empty() && (e = hipStreamWaitEvent(sc, b->ev_fork[2], 0)) != hipSuccess) return e;
+    dmc::launch_oi_batch(sc, b->cls_tmax[c], b->cls_kr[c], b->precision,
                          (const dmc::OiArgs*)(b->buf + b->o_args),
                          (const int4*)(b->buf + b->o_jobs) + b->cls_off[c], b->cls_n[c]);
+    if (!b->cs.empty() && (e = hipEventRecord(b->ev_cls[c], sc)) != hipSuccess) return e;
+  }
   if ((e = batch_fork(b, s, 1)) != hipSuccess) return e;
   double* summary = (double*)(b->buf + b->o_summary);
-  for (size_t i = 0; i < b->seq.size(); ++i) {
+  for (int i : b->order2) {
     BatchSeq& q = b->seq[i];
     const dmc::MeshDev& m = q.mesh->dev;
     hipStream_t sq = on(q);
     uint8_t* shared = shared_of(q);
+    if (!b->cs.empty())
+      for (int c : q.cls)
+        if (c >= 0 && (e = hipStreamWaitEvent(sq, b->ev_cls[c], 0)) != hipSuccess) return e;
     if (q.sl.nw_full) {
       double* ud = (double*)(b->buf + q.o_ud);
       dmc::launch_dict_code(sq, (const double*)(b->buf + q.o_ut), q.sl.nw_full, q.sl.full,
@@ -2085,6 +2098,26 @@ dmc_status dmc_batch_create(dmc_ctx ctx, int32_t nseq, const dmc_mesh* meshes,
     }
     ++b->cls_n.back();
   }
+  // each sequence's classes, and the second phase's order: sequences whose
+  // slowest class is the cheapest first (its windows' T and k bound a class's
+  // time), so a branch works on them while the larger classes still run
+  auto class_of = [&](int T, int k) {
+    const int tmax = T <= 32 ? 32 : 64, kr = k <= 16 ? 16 : 32;
+    for (size_t c = 0; c < b->cls_n.size(); ++c)
+      if (b->cls_tmax[c] == tmax && b->cls_kr[c] == kr) return (int)c;
+    return -1;
+  };
+  std::vector<int> slowest(nseq, 0);
+  for (int32_t i = 0; i < nseq; ++i) {
+    BatchSeq& q = b->seq[i];
+    if (q.sl.nw_full) q.cls[0] = class_of(q.T, q.k_full);
+    if (q.sl.T_tail) q.cls[1] = class_of(q.sl.T_tail, q.k_tail);
+    for (int c : q.cls)
+      if (c >= 0) slowest[i] = std::max(slowest[i], b->cls_tmax[c] * b->cls_kr[c]);
+    b->order2.push_back(i);
+  }
+  std::stable_sort(b->order2.begin(), b->order2.end(),
+                   [&](int x, int y) { return slowest[x] < slowest[y]; });
   if (hipMemcpy(b->buf + b->o_args, args.data(), args.size() * sizeof(dmc::OiArgs),
                 hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(b->buf + b->o_jobs, dj.data(), dj.size() * sizeof(int4),
@@ -2121,10 +2154,16 @@ dmc_status dmc_batch_create(dmc_ctx ctx, int32_t nseq, const dmc_mesh* meshes,
             hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) == hipSuccess;
   if (ok && nbranch > 1) {
     b->br.assign(nbranch, nullptr);
-    b->ev_fork.assign(2, nullptr);
+    b->cs.assign(b->cls_n.size(), nullptr);
+    b->ev_fork.assign(3, nullptr);
     b->ev_join.assign(2 * nbranch, nullptr);
+    b->ev_cls.assign(b->cls_n.size(), nullptr);
     for (hipStream_t& x : b->br)
       ok = ok && hipStreamCreateWithFlags(&x, hipStreamNonBlocking) == hipSuccess;
+    for (hipStream_t& x : b->cs)
+      ok = ok && hipStreamCreateWithFlags(&x, hipStreamNonBlocking) == hipSuccess;
+    for (hipEvent_t& x : b->ev_cls)
+      ok = ok && hipEventCreateWithFlags(&x, hipEventDisableTiming) == hipSuccess;
     for (hipEvent_t& x : b->ev_fork)
       ok = ok && hipEventCreateWithFlags(&x, hipEventDisableTiming) == hipSuccess;
     for (hipEvent_t& x : b->ev_join)
@@ -2232,7 +2271,11 @@ void dmc_batch_destroy(dmc_batch b) {
     if (x) (void)hipEventDestroy(x);
   for (hipEvent_t x : b->ev_join)
     if (x) (void)hipEventDestroy(x);
+  for (hipEvent_t x : b->ev_cls)
+    if (x) (void)hipEventDestroy(x);
   for (hipStream_t x : b->br)
+    if (x) (void)hipStreamDestroy(x);
+  for (hipStream_t x : b->cs)
     if (x) (void)hipStreamDestroy(x);
   if (b->stream) (void)hipStreamDestroy(b->stream);
   if (b->buf) (void)hipFree(b->buf);
