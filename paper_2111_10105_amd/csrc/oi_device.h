@@ -411,10 +411,12 @@ __device__ __forceinline__ int orthonormalise(OiSmem<TMAX, KMAX>& s, const doubl
 // A pair is skipped when |A_pq| <= max(eps sqrt(|A_pp A_qq|), eps ||A||_F)
 // (below one ulp of the matrix a rotation changes nothing the matrix
 // determines); stops after a sweep with no rotation.  General-size version,
-// with the matrices in LDS (used for m > 32).  In each round the rotations are disjoint, so A J and V J
-// are done by rows (a thread owns row x and updates its entries in columns p, q
-// of every pair) and J^T (A J) by columns; each thread issues all loads of a
-// batch before its stores, so the LDS latency is paid once per batch.
+// with the matrices in LDS (used for m > 32).  In each round the rotations
+// are disjoint, so A J and V J are done by rows (thread x owns row x and
+// updates its entries in columns p, q of every pair) and J^T (A J) by columns
+// (thread y owns column y); the pairs go in batches of eight, each thread
+// issuing all loads of a batch before its stores, so the LDS latency is paid
+// once per batch.
 template <int TMAX, int KMAX>
 __device__ __forceinline__ void jacobi(OiSmem<TMAX, KMAX>& s, int m) {
   const int LR = s.LR;
@@ -468,31 +470,63 @@ __device__ __forceinline__ void jacobi(OiSmem<TMAX, KMAX>& s, int m) {
         s.rot_s[i] = sn;
       }
       __syncthreads();
-      // A <- A J and V <- V J
-      for (int e = threadIdx.x; e < m * np; e += NT) {
-        const int x = e / np, i = e % np;
-        const double sn = s.rot_s[i];
-        if (sn == 0.0) continue;
-        const int p = s.rot_p[i], q = s.rot_q[i];
-        const double c = s.rot_c[i];
-        const double ap = s.A[x * LR + p], aq = s.A[x * LR + q];
-        s.A[x * LR + p] = c * ap - sn * aq;
-        s.A[x * LR + q] = sn * ap + c * aq;
-        const double vp = s.V[x * LR + p], vq = s.V[x * LR + q];
-        s.V[x * LR + p] = c * vp - sn * vq;
-        s.V[x * LR + q] = sn * vp + c * vq;
+      // A <- A J and V <- V J: thread x owns row x; the pairs go in batches
+      // of JB, every load of a batch issued before its stores
+      constexpr int JB = 8;
+      const int x = threadIdx.x;
+      if (x < m) {
+        for (int i0 = 0; i0 < np; i0 += JB) {
+          double ap[JB], aq[JB], vp[JB], vq[JB], cc[JB], ss[JB];
+          int pp[JB], qq[JB];
+#pragma unroll
+          for (int u = 0; u < JB; ++u) {
+            const int i = i0 + u < np ? i0 + u : np - 1;
+            pp[u] = s.rot_p[i];
+            qq[u] = s.rot_q[i];
+            cc[u] = s.rot_c[i];
+            ss[u] = i0 + u < np ? s.rot_s[i] : 0.0;
+            ap[u] = s.A[x * LR + pp[u]];
+            aq[u] = s.A[x * LR + qq[u]];
+            vp[u] = s.V[x * LR + pp[u]];
+            vq[u] = s.V[x * LR + qq[u]];
+          }
+#pragma unroll
+          for (int u = 0; u < JB; ++u) {
+            if (ss[u] == 0.0) continue;
+            const double c = cc[u], sn = ss[u];
+            s.A[x * LR + pp[u]] = c * ap[u] - sn * aq[u];
+            s.A[x * LR + qq[u]] = sn * ap[u] + c * aq[u];
+            s.V[x * LR + pp[u]] = c * vp[u] - sn * vq[u];
+            s.V[x * LR + qq[u]] = sn * vp[u] + c * vq[u];
+          }
+        }
       }
       __syncthreads();
-      // A <- J^T A; the rotated pair's own off-diagonal entries become zero
-      for (int e = threadIdx.x; e < np * m; e += NT) {
-        const int i = e / m, y = e % m;
-        const double sn = s.rot_s[i];
-        if (sn == 0.0) continue;
-        const int p = s.rot_p[i], q = s.rot_q[i];
-        const double c = s.rot_c[i];
-        const double rp = s.A[p * LR + y], rq = s.A[q * LR + y];
-        s.A[p * LR + y] = (y == q) ? 0.0 : c * rp - sn * rq;
-        s.A[q * LR + y] = (y == p) ? 0.0 : sn * rp + c * rq;
+      // A <- J^T A: thread y owns column y; the rotated pair's own
+      // off-diagonal entries become zero
+      const int y = threadIdx.x;
+      if (y < m) {
+        for (int i0 = 0; i0 < np; i0 += JB) {
+          double rp[JB], rq[JB], cc[JB], ss[JB];
+          int pp[JB], qq[JB];
+#pragma unroll
+          for (int u = 0; u < JB; ++u) {
+            const int i = i0 + u < np ? i0 + u : np - 1;
+            pp[u] = s.rot_p[i];
+            qq[u] = s.rot_q[i];
+            cc[u] = s.rot_c[i];
+            ss[u] = i0 + u < np ? s.rot_s[i] : 0.0;
+            rp[u] = s.A[pp[u] * LR + y];
+            rq[u] = s.A[qq[u] * LR + y];
+          }
+#pragma unroll
+          for (int u = 0; u < JB; ++u) {
+            if (ss[u] == 0.0) continue;
+            const double c = cc[u], sn = ss[u];
+            s.A[pp[u] * LR + y] = (y == qq[u]) ? 0.0 : c * rp[u] - sn * rq[u];
+            s.A[qq[u] * LR + y] = (y == pp[u]) ? 0.0 : sn * rp[u] + c * rq[u];
+          }
+        }
       }
       __syncthreads();
     }
