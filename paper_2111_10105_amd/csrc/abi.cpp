@@ -517,9 +517,11 @@ void decode_enqueue_finish(hipStream_t s, const dmc::MeshDev& m, const uint8_t* 
 
 void decode_enqueue_fixed(hipStream_t s, const dmc::MeshDev& m, const uint8_t* records,
                           const dmc::SeqLayout& sl, const dmc_params& p, const DecodePlan& d,
-                          uint8_t* ws, void* frames_out, int iters, double* summary) {
+                          uint8_t* ws, void* frames_out, int iters, double* summary,
+                          int32_t split_target = 2048) {
   const bool chol = p.precond == DMC_PRECOND_CHOLESKY;
-  const dmc::CgBuffers cb = decode_buffers(ws, d.lay, d.ncols, chol);
+  dmc::CgBuffers cb = decode_buffers(ws, d.lay, d.ncols, chol);
+  cb.split_target = split_target;
   decode_enqueue_setup(s, m, records, sl, p, d, cb, ws, iters < 1);
   if (p.precond == DMC_PRECOND_CHOLESKY) {
     // iteration 1 is the start from the factor's solution; the later ones
@@ -1912,8 +1914,9 @@ hipError_t batch_enqueue(dmc_batch b, hipStream_t s) {
     }
     if (q.out) {
       const DecodePlan d = decode_plan(m, q.sl, q.p);
+      // the branches share the chip: a backward level needs a share of it
       decode_enqueue_fixed(sq, m, q.codes, q.sl, q.p, d, shared, q.out, q.p.cg_max_iters,
-                           summary + 2 * i);
+                           summary + 2 * i, b->br.empty() ? 2048 : 2048 / (int)b->br.size());
     }
   }
   return batch_join(b, s, 1);

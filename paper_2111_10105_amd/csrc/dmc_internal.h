@@ -340,6 +340,9 @@ struct CgBuffers {
   double *x, *r, *p, *q;
   double *z, *W, *Y, *U;  // preconditioned residual and triangular-solve work
   double* S;                    // split-K partials of the backward solve
+  // blocks a backward level is split up to (fewer where other work runs
+  // beside the solve, as in the batched form's graph branches)
+  int32_t split_target = 2048;
   double* part;      // [nblk_rows][ncols] x 2
   double *rz, *rr, *bnorm2, *alpha, *beta;
   int32_t* done;     // [ncols]
@@ -376,9 +379,11 @@ void launch_cg_summary(hipStream_t s, const CgBuffers& cb, int32_t ncols, double
 // part: split-K scratch of chol_split_bytes(f, ncols) bytes (nullptr: no split)
 size_t chol_split_bytes(const CholDev& f, int32_t ncols);
 // z = (L L^T)^-1 r for ncols columns (rows by position; z also serves the
-// backward solve as its solution block)
+// backward solve as its solution block); split_target: blocks a backward
+// level is split up to (at most 2048)
 void launch_chol_solve(hipStream_t s, const CholDev& f, int32_t ncols, const double* r, double* z,
-                       double* W, double* Y, double* U, double* part);
+                       double* W, double* Y, double* U, double* part,
+                       int32_t split_target = 2048);
 void launch_precond_apply(hipStream_t s, const MeshDev& m, int32_t ncols, const CgBuffers& cb,
                           double* p_out);
 // X [n][3F] (rows by position) -> frames [F][n][3] (vertex order)

@@ -362,11 +362,12 @@ k_bwd_reduce(CholDev f, int t0, int ntasks, int ncols, int cbp, int nsplit,
   }
 }
 
-// split factor of a backward level: enough blocks to occupy the chip
-int bwd_split(int ntw, int cb) {
+// split factor of a backward level: enough blocks to occupy the chip (or
+// the share of it the caller names)
+int bwd_split(int ntw, int cb, int target = 2048) {
   const int blocks = ntw * cb;
-  if (blocks >= 2048) return 1;
-  return std::min(kMaxSplit, (2048 + blocks - 1) / blocks);
+  if (blocks >= target) return 1;
+  return std::min(kMaxSplit, (target + blocks - 1) / blocks);
 }
 
 }  // namespace
@@ -392,7 +393,7 @@ size_t chol_split_bytes(const CholDev& f, int32_t ncols) {
 constexpr int kSmallLevelBlocks = 512;
 
 void launch_chol_solve(hipStream_t s, const CholDev& f, int32_t ncols, const double* r, double* z,
-                       double* W, double* Y, double* U, double* part) {
+                       double* W, double* Y, double* U, double* part, int32_t split_target) {
   double* X = z;  // rows by position: the solution block is the output
   dim3 blk(kBlock);
   const int cb = (ncols + CTG - 1) / CTG, cbp = pad_xcd(cb);
@@ -427,7 +428,7 @@ void launch_chol_solve(hipStream_t s, const CholDev& f, int32_t ncols, const dou
       hipLaunchKernelGGL(k_bwd_gemm<32>, dim3(cbp32 * 2 * ntw), blk, 0, s, f, tw0, ncols, cbp32,
                          2 * ntw, Y, X, 1, (double*)nullptr);
     } else {
-      const int ns = part ? bwd_split(ntw, cb) : 1;
+      const int ns = part ? bwd_split(ntw, cb, std::min<int>(split_target, 2048)) : 1;
       hipLaunchKernelGGL(k_bwd_gemm<64>, dim3(cbp * ntw * ns), blk, 0, s, f, tw0, ncols, cbp, ntw,
                          Y, X, ns, part);
       if (ns > 1)

@@ -1293,7 +1293,7 @@ void launch_precond_apply(hipStream_t s, const MeshDev& m, int32_t ncols, const 
   const int nrb = (int)cg_part_rows(m.n);
   dim3 grid(nrb, (ncols + SP_COLS - 1) / SP_COLS);
   double* z = p_out ? p_out : cb.z;
-  launch_chol_solve(s, m.chol, ncols, cb.r, z, cb.W, cb.Y, cb.U, cb.S);
+  launch_chol_solve(s, m.chol, ncols, cb.r, z, cb.W, cb.Y, cb.U, cb.S, cb.split_target);
   hipLaunchKernelGGL(k_cg_dot, grid, dim3(kBlock), 0, s, m.n, ncols, cb.r, z, (double*)nullptr,
                      cb.part);
 }
@@ -1337,7 +1337,7 @@ void launch_cg_warm_start(hipStream_t s, const MeshDev& m, int32_t ncols, const 
                           double tol) {
   const int nrb = (int)cg_part_rows(m.n);
   dim3 cgrid((ncols + RED_COLS - 1) / RED_COLS);
-  launch_chol_solve(s, m.chol, ncols, cb.r, cb.x, cb.W, cb.Y, cb.U, cb.S);
+  launch_chol_solve(s, m.chol, ncols, cb.r, cb.x, cb.W, cb.Y, cb.U, cb.S, cb.split_target);
   prof::begin(s, DMC_KERNEL_CG_SPMM);
   launch_residual(s, m, ncols, cb.x, cb.r, 0, cb.part);
   prof::end(s, DMC_KERNEL_CG_SPMM);
