@@ -345,13 +345,16 @@ constexpr int PJ_V = 64;  // vertices per projection block
 // vertices of one window; the window's frames go by tiles of PF_TT.  All
 // four waves form a tile's delta coordinates (lane = vertex, one 12- or
 // 24-byte xyz gather per ring member and frame, as k_delta), then waves 0-2
-// project it (wave c = coordinate c, as k_project) while the next tile is
-// being formed into the other LDS buffer.  Every delta is evaluated exactly
-// as k_delta does and rounded to the frames' type, and the sums run over the
-// frames in order as in k_project, so the coefficients are bit for bit those
-// of the two-kernel path.
+// project it (wave c = coordinate c, as k_project).  The gathers of the next
+// tile (every ring member and the vertex itself, both of a wave's frames)
+// are issued together before the current tile is projected, so their
+// latency hides behind the products instead of following one another.
+// Every delta is evaluated exactly as k_delta does and rounded to the
+// frames' type, and the sums run over the frames in order as in k_project,
+// so the coefficients are bit for bit those of the two-kernel path.
 // ---------------------------------------------------------------------------
 constexpr int PF_TT = 8;  // frames per delta tile
+constexpr int PF_FQ = PF_TT / (kBlock / 64);  // frames per wave and tile
 // ring members held in registers (valence 6 is the rule on these meshes: a
 // larger pad would add gathers of the vertex itself; longer rings finish
 // from memory)
@@ -363,12 +366,17 @@ k_project_frames(const int32_t* __restrict__ rowptr, const int32_t* __restrict__
                  const double* __restrict__ wdeg, int uniform, int n, int T, int k,
                  const Real* __restrict__ frames, const double* __restrict__ u_tilde,
                  Real* __restrict__ Y, double* __restrict__ mm) {
-  __shared__ Real Ut[3 * 64 * KMAX];
+  // the dictionary with rows padded to KMAX by zeros: a frame's row is read
+  // as whole 16-byte words
+  __shared__ __align__(16) Real Ut[3 * 64 * KMAX];
   __shared__ Real D[2][PF_TT][3][PJ_V];
   const int w = blockIdx.y, blk = blockIdx.x;
   const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
   const double* ug = u_tilde + (size_t)w * 3 * T * k;
-  for (int e = tid; e < 3 * T * k; e += kBlock) Ut[e] = (Real)ug[e];
+  for (int e = tid; e < 3 * T * KMAX; e += kBlock) {
+    const int r = e % KMAX, ct = e / KMAX;
+    Ut[e] = r < k ? (Real)ug[(size_t)ct * k + r] : (Real)0;
+  }
   const int i = blk * PJ_V + lane;
   const bool valid = i < n;
   int e0 = 0, e1 = 0;
@@ -379,37 +387,51 @@ k_project_frames(const int32_t* __restrict__ rowptr, const int32_t* __restrict__
     wi = wdeg[i];
   }
   const int deg = e1 - e0;
+  const int iv = valid ? i : 0;
   int nb[PF_DMAX];
 #pragma unroll
-  for (int d = 0; d < PF_DMAX; ++d) nb[d] = d < deg ? col[e0 + d] : (valid ? i : 0);
+  for (int d = 0; d < PF_DMAX; ++d) nb[d] = d < deg ? col[e0 + d] : iv;
   const Real* fw = frames + (size_t)w * T * 3 * n;
   const size_t fs = (size_t)3 * n;
-  // delta coordinates of tile `tile` into buffer `buf` (frames wave, wave + 4)
-  auto delta_tile = [&](int tile, int buf) {
+  // the wave's gathers of tile `tile`: ring members, then the vertex itself
+  Xyz<Real> g[PF_FQ][PF_DMAX + 1];
+  auto gather = [&](int tile) {
 #pragma unroll
-    for (int q = 0; q < PF_TT / 4; ++q) {
+    for (int q = 0; q < PF_FQ; ++q) {
+      const int t = min(tile * PF_TT + wave + 4 * q, T - 1);
+      const Xyz<Real>* fr = (const Xyz<Real>*)(fw + (size_t)t * fs);
+#pragma unroll
+      for (int d = 0; d < PF_DMAX; ++d) g[q][d] = fr[nb[d]];
+      g[q][PF_DMAX] = fr[iv];
+    }
+  };
+  // delta coordinates of tile `tile` from the gathers into buffer `buf`
+  // (pads beyond the ring add exact zeros: a sum that starts at +0 is never
+  // -0, so the sums are those of the ring alone)
+  auto delta_store = [&](int tile, int buf) {
+#pragma unroll
+    for (int q = 0; q < PF_FQ; ++q) {
       const int tt = wave + 4 * q, t = tile * PF_TT + tt;
-      Xyz<Real> o{(Real)0, (Real)0, (Real)0};
-      if (valid && t < T) {
-        const Xyz<Real>* fr = (const Xyz<Real>*)(fw + (size_t)t * fs);
-        Xyz<Real> v[PF_DMAX];
+      double sx = 0.0, sy = 0.0, sz = 0.0;
 #pragma unroll
-        for (int d = 0; d < PF_DMAX; ++d) v[d] = fr[nb[d]];
-        double sx = 0.0, sy = 0.0, sz = 0.0;
-#pragma unroll
-        for (int d = 0; d < PF_DMAX; ++d)
-          if (d < deg) {
-            sx += (double)v[d].x;
-            sy += (double)v[d].y;
-            sz += (double)v[d].z;
-          }
+      for (int d = 0; d < PF_DMAX; ++d) {
+        const bool in = d < deg;
+        sx += in ? (double)g[q][d].x : 0.0;
+        sy += in ? (double)g[q][d].y : 0.0;
+        sz += in ? (double)g[q][d].z : 0.0;
+      }
+      if (deg > PF_DMAX) {
+        const Xyz<Real>* fr = (const Xyz<Real>*)(fw + (size_t)min(t, T - 1) * fs);
         for (int e = e0 + PF_DMAX; e < e1; ++e) {
           const Xyz<Real> u = fr[col[e]];
           sx += (double)u.x;
           sy += (double)u.y;
           sz += (double)u.z;
         }
-        const Xyz<Real> own = fr[i];
+      }
+      const Xyz<Real> own = g[q][PF_DMAX];
+      Xyz<Real> o{(Real)0, (Real)0, (Real)0};
+      if (valid && t < T) {
         o.x = (Real)(uniform ? (double)own.x - wi * sx : wi * (double)own.x - sx);
         o.y = (Real)(uniform ? (double)own.y - wi * sy : wi * (double)own.y - sy);
         o.z = (Real)(uniform ? (double)own.z - wi * sz : wi * (double)own.z - sz);
@@ -423,32 +445,44 @@ k_project_frames(const int32_t* __restrict__ rowptr, const int32_t* __restrict__
 #pragma unroll
   for (int r = 0; r < KMAX; ++r) acc[r] = 0;
   const int ntile = (T + PF_TT - 1) / PF_TT;
-  delta_tile(0, 0);
+  gather(0);
+  delta_store(0, 0);
   __syncthreads();
   const int c = wave;  // coordinate of waves 0-2 in the projection
   for (int tile = 0; tile < ntile; ++tile) {
     const int buf = tile & 1;
-    if (tile + 1 < ntile) delta_tile(tile + 1, buf ^ 1);
+    const bool more = tile + 1 < ntile;
+    if (more) gather(tile + 1);
     if (c < 3) {
-      const Real* uc = Ut + c * T * k;
+      const Real* uc = Ut + c * T * KMAX;
+#pragma unroll
       for (int tt = 0; tt < PF_TT; ++tt) {
         const int t = tile * PF_TT + tt;
         if (t >= T) break;
         const Real d = D[buf][tt][c][lane];
 #pragma unroll
-        for (int r = 0; r < KMAX; ++r)
-          if (r < k) acc[r] += uc[t * k + r] * d;
+        for (int r = 0; r < KMAX; ++r) acc[r] += uc[t * KMAX + r] * d;
       }
     }
+    if (more) delta_store(tile + 1, buf ^ 1);
     __syncthreads();
   }
   if (c >= 3) return;
   Real* yw = Y + ((size_t)w * 3 + c) * k * n;
   const int nblk = gridDim.x;
+  // the coefficients pass through the dictionary's LDS (idle after the last
+  // barrier), each lane reading back only its own: the loop over the k rows
+  // then indexes LDS, and acc keeps static indices (a runtime index would
+  // move it to scratch memory)
+  static_assert(3 * KMAX * PJ_V <= 3 * 64 * KMAX, "coefficients fit the dictionary's LDS");
+  Real* keep = Ut + (size_t)c * KMAX * PJ_V;
+#pragma unroll
+  for (int r = 0; r < KMAX; ++r) keep[r * PJ_V + lane] = acc[r];
   for (int r = 0; r < k; ++r) {
-    if (valid) yw[(size_t)r * n + i] = acc[r];
-    const double lo = wave_min(valid ? (double)acc[r] : 1e300);
-    const double hi = wave_max(valid ? (double)acc[r] : -1e300);
+    const Real a = keep[r * PJ_V + lane];
+    if (valid) yw[(size_t)r * n + i] = a;
+    const double lo = wave_min(valid ? (double)a : 1e300);
+    const double hi = wave_max(valid ? (double)a : -1e300);
     if (lane == 0) {
       double* o = mm + ((((size_t)w * 3 + c) * k + r) * nblk + blk) * 2;
       o[0] = lo;
