@@ -662,19 +662,22 @@ k_to_frames(const double* __restrict__ X, const int32_t* __restrict__ pos, int n
   const int nv = min(TF_V, n - i0), nt = min(TF_T, F - t0);
   if (threadIdx.x < TF_V) prow[threadIdx.x] = threadIdx.x < nv ? pos[i0 + threadIdx.x] : 0;
   __syncthreads();
+  // the tile is whole rounds of TF_U loads per thread, and items beyond the
+  // block's vertices or frames read an in-range value that is never written
+  // out: no load sits behind a branch, so all TF_U are in flight at once
+  static_assert(TF_V * RW % (TF_U * kBlock) == 0, "whole rounds");
   for (int e0 = threadIdx.x; e0 < TF_V * RW; e0 += TF_U * kBlock) {
     double v[TF_U];
 #pragma unroll
     for (int u = 0; u < TF_U; ++u) {
-      const int e = e0 + u * kBlock, vv = e / RW, j = e % RW;
-      v[u] = e < TF_V * RW && vv < nv && j < 3 * nt
-                 ? X[(size_t)prow[vv] * ncols + 3 * t0 + j]
-                 : 0.0;
+      const int e = e0 + u * kBlock;
+      const int vv = min(e / RW, nv - 1), j = min(e % RW, 3 * nt - 1);
+      v[u] = X[(size_t)prow[vv] * ncols + 3 * t0 + j];
     }
 #pragma unroll
     for (int u = 0; u < TF_U; ++u) {
       const int e = e0 + u * kBlock;
-      if (e < TF_V * RW) tile[(e / RW) * LD + e % RW] = (Real)v[u];
+      tile[(e / RW) * LD + e % RW] = (Real)v[u];
     }
   }
   __syncthreads();
@@ -699,12 +702,16 @@ __device__ inline int zoff(const SeqLayout& sl, int w) {
 }
 
 constexpr int CR_V = 64;  // vertices per block of k_coef_rows
-constexpr int CR_U = 4;   // codes in flight per thread
+constexpr int CR_U = 8;   // codes in flight per thread
 
 // Yd[pos(i)][zoff(w) + c k + r] = Y^_wc[r][i] (dequantised coefficients, one
 // row per vertex in the decoder's row order).  The window's row table is
 // staged in LDS first, so each code's load depends on no table load of its
-// own; consecutive threads read consecutive vertices of a row.
+// own; consecutive threads read consecutive vertices of a row.  A code is
+// read as two words without a branch (the second is the first again when
+// the code does not cross a word boundary; a constant row reads the record's
+// first word and uses none of it), so all 2 CR_U words of a thread's codes
+// are in flight at once; the value is that of get_code.
 template <typename Real>
 __global__ void __launch_bounds__(kBlock)
 k_coef_rows(const uint8_t* __restrict__ records, SeqLayout sl, int n, int nz,
@@ -724,24 +731,45 @@ k_coef_rows(const uint8_t* __restrict__ records, SeqLayout sl, int n, int nz,
   if (threadIdx.x < CR_V) prow[threadIdx.x] = threadIdx.x < nv ? pos[i0 + threadIdx.x] : 0;
   __syncthreads();
   const uint32_t* var = (const uint32_t*)(rec + lay.off_var);
+  const uint32_t* first = (const uint32_t*)rec;
   const int tot = ck * CR_V;
   for (int e0 = threadIdx.x; e0 < tot; e0 += CR_U * kBlock) {
     double y[CR_U];
+    if (lay.coef_bits == 0) {
 #pragma unroll
-    for (int u = 0; u < CR_U; ++u) {
-      const int e = e0 + u * kBlock;
-      const int cr = e / CR_V, v = e % CR_V;  // consecutive threads -> consecutive vertices
-      y[u] = 0.0;
-      if (e < tot && v < nv) {
+      for (int u = 0; u < CR_U; ++u) {
+        const int e = e0 + u * kBlock;
+        const int cr = e / CR_V, v = e % CR_V;
+        y[u] = (e < tot && v < nv) ? (double)((const Real*)(var + tab[cr].word_off))[i0 + v] : 0.0;
+      }
+    } else {
+      uint32_t wlo[CR_U], whi[CR_U];
+#pragma unroll
+      for (int u = 0; u < CR_U; ++u) {
+        // out-of-range items read an in-range code and are dropped below
+        const int e = e0 + u * kBlock;
+        const int cr = min(e / CR_V, ck - 1), v = min(e % CR_V, nv - 1);
         const SegEntry se = tab[cr];
-        const uint32_t* seg = var + se.word_off;
         const uint32_t bits = se.bits_mode & 0xffu;
-        if (lay.coef_bits == 0)
-          y[u] = (double)((const Real*)seg)[i0 + v];
-        else
-          y[u] = bits ? dequant(get_code(seg, (uint32_t)(i0 + v), bits), (double)se.lo,
-                                (double)se.hi, (int)bits)
-                      : (double)se.lo;
+        const uint64_t at = (uint64_t)(uint32_t)(i0 + v) * bits;
+        const uint32_t sh = (uint32_t)(at & 31);
+        const uint32_t* p = bits ? var + se.word_off + (uint32_t)(at >> 5) : first;
+        wlo[u] = p[0];
+        whi[u] = p[sh + bits > 32 ? 1 : 0];
+      }
+#pragma unroll
+      for (int u = 0; u < CR_U; ++u) {
+        const int e = e0 + u * kBlock;
+        const int cr = e / CR_V, v = e % CR_V;
+        y[u] = 0.0;
+        if (e < tot && v < nv) {
+          const SegEntry se = tab[cr];
+          const uint32_t bits = se.bits_mode & 0xffu;
+          const uint32_t sh = (uint32_t)(((uint64_t)(uint32_t)(i0 + v) * bits) & 31);
+          const uint64_t word = (uint64_t)wlo[u] | ((uint64_t)whi[u] << 32);
+          const uint32_t code = (uint32_t)(word >> sh) & ((1u << bits) - 1u);
+          y[u] = bits ? dequant(code, (double)se.lo, (double)se.hi, (int)bits) : (double)se.lo;
+        }
       }
     }
 #pragma unroll

@@ -721,13 +721,16 @@ k_row_range(int nblk, const double* __restrict__ mm, RecordLayout l, uint8_t* re
 }
 
 // Codes of the coefficient rows (Eq. 10) packed into their segments: block
-// (x, q, w) writes words x*256 + tid, x*256 + tid + gridDim.x*256, ... of row
-// q of window w, each word from the codes that fall in it (a code across a
-// word boundary is computed by both words' threads); raw rows are copied.
-// Each wave finds the row's word offset (after the dictionary segments) from
-// the bits of the rows before it, lane r taking rows r and r + 64; block
-// (0, q, w) stores it in the table and block (0, last row, w) the record's
-// used bytes in the header.
+// (x, q, w) packs a contiguous share of the words of row q of window w in
+// rounds of kBlock words.  A round's codes are formed once each into LDS
+// from coalesced loads (QP_U per thread, none behind a branch, so all are
+// in flight at once), then thread t assembles word t of the round from the
+// codes that fall in it.  A single-valued row (0 bits) keeps its raw-sized
+// segment of zeros; raw rows are copied.  Each wave finds the row's word
+// offset (after the dictionary segments) from the bits of the rows before
+// it, lane r taking rows r and r + 64; block (0, q, w) stores it in the
+// table and block (0, last row, w) the record's used bytes in the header.
+constexpr int QP_U = 4;  // code loads per thread and pass of a round
 template <typename Real>
 __global__ void __launch_bounds__(kBlock)
 k_quantise_pack(const Real* __restrict__ Y, int n, int k, RecordLayout l, uint8_t* records,
@@ -764,10 +767,36 @@ k_quantise_pack(const Real* __restrict__ Y, int n, int k, RecordLayout l, uint8_
     return;
   }
   const uint32_t nwd = seg_words((uint32_t)n, bits, 4);
+  if (bits == 0) {
+    for (uint32_t wi = blockIdx.x * kBlock + threadIdx.x; wi < nwd; wi += stride) seg[wi] = 0u;
+    return;
+  }
+  // a round holds at most 32 kBlock / bits + 1 codes; the passes store whole
+  // QP_U kBlock slices (the entries beyond the round's codes are never read)
+  __shared__ uint16_t cs[32 * kBlock + QP_U * kBlock];
   const double lo = (double)e.lo, hi = (double)e.hi;
-  for (uint32_t wi = blockIdx.x * kBlock + threadIdx.x; wi < nwd; wi += stride)
-    seg[wi] = pack_word(wi, (uint32_t)n, bits,
-                        [&](uint32_t j) { return (uint32_t)quant_code((double)y[j], lo, hi, bits); });
+  const uint32_t per = (nwd + gridDim.x - 1) / gridDim.x;
+  const uint32_t wb = blockIdx.x * per, we = min(nwd, wb + per);
+  for (uint32_t r0 = wb; r0 < we; r0 += kBlock) {
+    const uint32_t rw = min((uint32_t)kBlock, we - r0);
+    const uint32_t jlo = (uint32_t)((32ull * r0) / bits);
+    const uint64_t jend = (32ull * (r0 + rw) + bits - 1) / bits;  // codes starting in the round
+    const uint32_t jhi = (uint32_t)min((uint64_t)n, jend);
+    const uint32_t nc = jhi > jlo ? jhi - jlo : 0u;
+    for (uint32_t b = threadIdx.x; b < nc; b += QP_U * kBlock) {
+      Real v[QP_U];
+#pragma unroll
+      for (int u = 0; u < QP_U; ++u) v[u] = y[min(jlo + b + u * kBlock, jhi - 1)];
+#pragma unroll
+      for (int u = 0; u < QP_U; ++u)
+        cs[b + u * kBlock] = (uint16_t)quant_code((double)v[u], lo, hi, (int)bits);
+    }
+    __syncthreads();
+    if (threadIdx.x < rw)
+      seg[r0 + threadIdx.x] = pack_word(r0 + threadIdx.x, (uint32_t)n, bits,
+                                        [&](uint32_t j) { return (uint32_t)cs[j - jlo]; });
+    __syncthreads();
+  }
 }
 
 // zeros from the record's used bytes to its capacity (a record's stream is
