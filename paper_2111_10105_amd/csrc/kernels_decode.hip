@@ -647,8 +647,10 @@ k_cg_pupdate(int n, int ncols, const double* __restrict__ beta, const double* __
 // X [n][3F] (row pos(i) for vertex i) -> frames [F][n][3].  Block = TF_V
 // vertices x TF_T frames: each vertex's 3 TF_T values are one contiguous run
 // of X (read with TF_U loads in flight per thread), held in LDS in the frames'
-// type, and written frame by frame as runs of 3 TF_V values.
-constexpr int TF_V = 32, TF_T = 64, TF_U = 8;
+// type, and written frame by frame as runs of 3 TF_V values.  Long write runs
+// pay more than long read runs: at icosphere 7 (F = 512) 128 x 16 took 0.61
+// ms, 64 x 32 0.67, 32 x 64 0.73, 16 x 128 0.85 (256 x 8 as 128 x 16).
+constexpr int TF_V = 128, TF_T = 16, TF_U = 8;
 
 template <typename Real>
 __global__ void __launch_bounds__(kBlock)
