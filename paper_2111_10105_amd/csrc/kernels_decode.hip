@@ -703,7 +703,9 @@ __device__ inline int zoff(const SeqLayout& sl, int w) {
   return 3 * sl.full.k * (w < sl.nw_full ? w : sl.nw_full);
 }
 
-constexpr int CR_V = 64;  // vertices per block of k_coef_rows
+// vertices per block of k_coef_rows (at icosphere 7: 32 -> 0.37 ms, 64 -> 0.40,
+// 16 -> 0.39; the smaller tile lets more blocks share a CU)
+constexpr int CR_V = 32;
 constexpr int CR_U = 8;   // codes in flight per thread
 
 // Yd[pos(i)][zoff(w) + c k + r] = Y^_wc[r][i] (dequantised coefficients, one
