@@ -1166,6 +1166,11 @@ constexpr int CP_V = 64;  // vertices per compose block and vertex tile (16 per 
 // matrix cores; float32 frames on the FP32 ones (v_mfma_f32_16x16x4f32, the
 // same operand layout, twice the rate; the products' rounding, ~1e-7
 // relative, is that of the float32 output itself).
+// An empty asm statement that takes v as an operand: the load that produced
+// v must have been issued before it, so a group of loads followed by their
+// pins stays in flight together (no instruction is emitted).
+__device__ __forceinline__ void pin(double& v) { asm volatile("" : "+v"(v)); }
+
 typedef float cf4 __attribute__((ext_vector_type(4)));
 template <typename Real>
 struct ComposeMfma;
@@ -1223,48 +1228,91 @@ k_compose(const uint8_t* __restrict__ records, SeqLayout sl, int n, int nc, int 
     for (int tt = 0; tt < TTM; ++tt)
 #pragma unroll
       for (int v = 0; v < NV; ++v) acc[c][tt][v] = Acc{0, 0, 0, 0};
+  // Operands are read without branches: indices past an edge are clamped to
+  // an element that exists and the value is replaced by zero afterwards
+  // (frames past T too, whose sums are never stored).  The operands of CS K
+  // steps are loaded, then pinned (pin: the compiler would otherwise move
+  // each load behind its bounds test and wait on them one by one), then
+  // multiplied, so their loads are in flight together.  Every accumulator
+  // still takes its K steps in order.
+  constexpr int CS = 2;
   // anchor part: K = anchors, four per step
-#pragma unroll 2
-  for (int a0 = 0; a0 < nc; a0 += 4) {
-    const int a = a0 + kq;
-    const bool av = a < nc;
-    double vb[NV];
+  for (int a00 = 0; a00 < nc; a00 += 4 * CS) {
+    double vb[CS][NV], va[CS][3][TTM];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) vb[v] = (ok_[v] && av) ? G[(size_t)ip_[v] * nc + a] : 0.0;
-    const double* ar = Ah + (size_t)(av ? a : 0) * ncols + 3 * t0;
+    for (int g = 0; g < CS; ++g) {
+      const int ac = min(a00 + 4 * g + kq, nc - 1);
 #pragma unroll
-    for (int c = 0; c < 3; ++c)
+      for (int v = 0; v < NV; ++v) vb[g][v] = G[(size_t)ip_[v] * nc + ac];
+      const double* ar = Ah + (size_t)ac * ncols + 3 * t0;
 #pragma unroll
-      for (int tt = 0; tt < TTM; ++tt) {
-        if (tt >= tt_n) continue;
-        const int t = 16 * tt + tl;
-        const double va = (av && t < T) ? ar[3 * t + c] : 0.0;
+      for (int c = 0; c < 3; ++c)
 #pragma unroll
-        for (int v = 0; v < NV; ++v)
-          acc[c][tt][v] = ComposeMfma<Real>::step(va, vb[v], acc[c][tt][v]);
+        for (int tt = 0; tt < TTM; ++tt) va[g][c][tt] = ar[3 * min(16 * tt + tl, T - 1) + c];
+    }
+#pragma unroll
+    for (int g = 0; g < CS; ++g) {
+      const bool av = a00 + 4 * g + kq < nc;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        pin(vb[g][v]);
+        vb[g][v] = (ok_[v] && av) ? vb[g][v] : 0.0;
       }
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int tt = 0; tt < TTM; ++tt) {
+          pin(va[g][c][tt]);
+          va[g][c][tt] = (av && 16 * tt + tl < T) ? va[g][c][tt] : 0.0;
+        }
+    }
+#pragma unroll
+    for (int g = 0; g < CS; ++g)
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int tt = 0; tt < TTM; ++tt)
+#pragma unroll
+          for (int v = 0; v < NV; ++v)
+            acc[c][tt][v] = ComposeMfma<Real>::step(va[g][c][tt], vb[g][v], acc[c][tt][v]);
   }
   // subspace part: K = the k coefficients of each coordinate
 #pragma unroll
-  for (int c = 0; c < 3; ++c)
-    for (int r0 = 0; r0 < k; r0 += 4) {
-      const int r = r0 + kq;
-      const bool rv = r < k;
-      double vb[NV];
+  for (int c = 0; c < 3; ++c) {
+    for (int r00 = 0; r00 < k; r00 += 4 * CS) {
+      double vb[CS][NV], va[CS][TTM];
 #pragma unroll
-      for (int v = 0; v < NV; ++v)
-        vb[v] = (ok_[v] && rv) ? Z[(size_t)ip_[v] * nz + z0 + c * k + r] : 0.0;
+      for (int g = 0; g < CS; ++g) {
+        const int rc = min(r00 + 4 * g + kq, k - 1);
 #pragma unroll
-      for (int tt = 0; tt < TTM; ++tt) {
-        if (tt >= tt_n) continue;
-        const int t = 16 * tt + tl;
-        double va = 0.0;
-        if (rv && t < T) va = ud[(c * T + t) * k + r];
+        for (int v = 0; v < NV; ++v) vb[g][v] = Z[(size_t)ip_[v] * nz + z0 + c * k + rc];
 #pragma unroll
-        for (int v = 0; v < NV; ++v)
-          acc[c][tt][v] = ComposeMfma<Real>::step(va, vb[v], acc[c][tt][v]);
+        for (int tt = 0; tt < TTM; ++tt)
+          va[g][tt] = ud[(c * T + min(16 * tt + tl, T - 1)) * k + rc];
       }
+#pragma unroll
+      for (int g = 0; g < CS; ++g) {
+        const bool rv = r00 + 4 * g + kq < k;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          pin(vb[g][v]);
+          vb[g][v] = (ok_[v] && rv) ? vb[g][v] : 0.0;
+        }
+#pragma unroll
+        for (int tt = 0; tt < TTM; ++tt) {
+          pin(va[g][tt]);
+          va[g][tt] = (rv && 16 * tt + tl < T) ? va[g][tt] : 0.0;
+        }
+      }
+#pragma unroll
+      for (int g = 0; g < CS; ++g)
+#pragma unroll
+        for (int tt = 0; tt < TTM; ++tt)
+#pragma unroll
+          for (int v = 0; v < NV; ++v)
+            acc[c][tt][v] = ComposeMfma<Real>::step(va[g][tt], vb[g][v], acc[c][tt][v]);
     }
+  }
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
     if (!ok_[v]) continue;
