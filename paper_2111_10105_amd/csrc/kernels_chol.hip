@@ -259,34 +259,45 @@ k_bwd_gemm(CholDev f, int t0, int ncols, int cbp, int ntile, const double* __res
   const int per = (nch + nsplit - 1) / nsplit;
   const int kb = r0 + cbk.v * per * KC;
   const int ke = min(m, kb + per * KC);
+  // The loads of a chunk are unconditional (indices clamped to elements
+  // that exist) and nothing uses their values until they are staged after
+  // the current chunk's products: the zeros past the edges and the sign of
+  // the ancestor rows are applied then.  (Applied at the load, behind its
+  // bounds test, they made every chunk wait on its loads before multiplying.)
+  // per staged element u, four bits from bit 4u: A in range (1), B in range
+  // (4), B from an ancestor row (8)
+  static_assert(PER_T <= 8, "four flag bits per staged element");
+  uint32_t keep = 0;
   auto load = [&](int i0) {
+    keep = 0;
 #pragma unroll
     for (int u = 0; u < PER_T; ++u) {
       const int e = tid + u * kBlock;
+      // B operand first: its row index (from LDS, or from memory past the
+      // cached range) is waited for before any load of the chunk is issued
+      const int i2 = e / CT, cc = e % CT;
+      const int ib = i0 + i2, c = c0 + cc;
+      const bool bv = ib < m && c < ncols;
+      const int ibc = min(ib, m - 1);
+      const bool anc = ibc >= w;
+      int ri = a + ibc;
+      if (anc) ri = ibc - kb < RIDX ? rows[ibc - kb] : f.rowidx[rb0 + ibc];
+      rb[u] = (anc ? X : Y)[(size_t)ri * ncols + min(c, ncols - 1)];
       // A operand: As[tt][ii] = B_s[i0 + ii][r0 + tt] (transposed while staging)
       const int ii = e / RT, tt = e % RT;
       const int i = i0 + ii, tc = r0 + tt;
-      ra[u] = (i < m && tc < w) ? Br[(size_t)i * w + tc] : 0.0;
-      const int i2 = e / CT, cc = e % CT;
-      const int ib = i0 + i2, c = c0 + cc;
-      double v = 0.0;
-      if (ib < m && c < ncols) {
-        if (ib < w) {
-          v = Y[(size_t)(a + ib) * ncols + c];
-        } else {
-          const int ri = ib - kb < RIDX ? rows[ib - kb] : f.rowidx[rb0 + ib];
-          v = -X[(size_t)ri * ncols + c];
-        }
-      }
-      rb[u] = v;
+      ra[u] = Br[(size_t)min(i, m - 1) * w + min(tc, w - 1)];
+      const bool av = i < m && tc < w;
+      keep |= ((av ? 1u : 0u) | (bv ? 4u : 0u) | (anc ? 8u : 0u)) << (4 * u);
     }
   };
   auto store = [&](int st) {
 #pragma unroll
     for (int u = 0; u < PER_T; ++u) {
       const int e = tid + u * kBlock;
-      As[st][(e % RT) * LDA + e / RT] = ra[u];
-      Bs[st][(e / CT) * LDB + e % CT] = rb[u];
+      const uint32_t kf = keep >> (4 * u);
+      As[st][(e % RT) * LDA + e / RT] = (kf & 1u) ? ra[u] : 0.0;
+      Bs[st][(e / CT) * LDB + e % CT] = (kf & 4u) ? ((kf & 8u) ? -rb[u] : rb[u]) : 0.0;
     }
   };
   Tile t;
