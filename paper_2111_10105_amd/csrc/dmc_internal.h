@@ -21,6 +21,14 @@ constexpr int kXcds = 8;
 // (column 0, value 0), so a kernel may read the first entries of a row's
 // pattern without testing them against the row's end.
 constexpr int kMatPad = 32;
+
+// An empty asm statement that takes v as an operand (no instruction is
+// emitted): the load that produced v must have been issued before it, so a
+// group of loads followed by their pins stays in flight together, where the
+// compiler would otherwise move each load behind the bounds test that
+// selects its value and wait on them one by one.
+__device__ __forceinline__ void pin(double& v) { asm volatile("" : "+v"(v)); }
+
 inline int pad_xcd(int blocks) { return (blocks + kXcds - 1) / kXcds * kXcds; }
 constexpr size_t kAlign = 256;
 

@@ -1166,11 +1166,6 @@ constexpr int CP_V = 64;  // vertices per compose block and vertex tile (16 per 
 // matrix cores; float32 frames on the FP32 ones (v_mfma_f32_16x16x4f32, the
 // same operand layout, twice the rate; the products' rounding, ~1e-7
 // relative, is that of the float32 output itself).
-// An empty asm statement that takes v as an operand: the load that produced
-// v must have been issued before it, so a group of loads followed by their
-// pins stays in flight together (no instruction is emitted).
-__device__ __forceinline__ void pin(double& v) { asm volatile("" : "+v"(v)); }
-
 typedef float cf4 __attribute__((ext_vector_type(4)));
 template <typename Real>
 struct ComposeMfma;
