@@ -165,7 +165,8 @@ def work_model(fam, *, n, F, T, k, nw, rs, ncols, nnz, m_nnz, finfo, sweeps_tota
 
 def host_description():
     """CPU model, logical CPUs and the BLAS libraries numpy uses (with their
-    thread counts) of the machine the benchmark runs on."""
+    default thread counts, outside any limit) of the machine the benchmark
+    runs on."""
     model = None
     try:
         with open("/proc/cpuinfo") as f:
@@ -182,7 +183,7 @@ def host_description():
                 for i in threadpool_info()]
     except Exception:
         pass
-    return {"cpu_model": model, "nproc": os.cpu_count(), "blas": blas}
+    return {"cpu_model": model, "nproc": os.cpu_count(), "blas_default_threads": blas}
 
 
 def train_learned_start(ctx, dmc, w, dev, mesh):
@@ -726,7 +727,7 @@ def main():
                                          first_start=q0_host.astype(np.float64), fp32_data=True)
             cpu_s = time.perf_counter() - tc
         result["cpu_baseline"] = {"value": round(n * Ts / cpu_s, 1), "unit": "vertex-frames/s",
-                                  "cores": 1, "kind": "oracle",
+                                  "cores": 1, "kind": "oracle", "blas_threads_used": 1,
                                   "sample": f"first window of the workload ({n} vertices x {Ts} "
                                             f"frames, encode + decode incl. its sparse LU, "
                                             f"{cpu_s:.1f} s)",
